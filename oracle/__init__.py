@@ -1,0 +1,242 @@
+"""CPU oracle of the parallel one-sided Jacobi SVD hot path (arXiv:2202.08361).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark.  The product path (the HIP library and its
+binding) never imports it, and it imports nothing from the product.
+
+A thin ctypes layer over ``liboracle.so`` (plain C, see ``oracle.h``); every
+array argument is a numpy float64 array, matrices column-major (Fortran
+order), complex data split into real and imaginary arrays.
+"""
+import ctypes as _ct
+import os as _os
+
+import numpy as _np
+
+_HERE = _os.path.dirname(_os.path.abspath(__file__))
+_LIB_PATH = _os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+OK, NOT_CONVERGED, EINVAL, ENONFINITE, EZERO = 0, 1, -1, -2, -3
+EVD_SCALED, EVD_SINFORM = 1, 2
+NO_PERMUTE = 1
+LANES = 1024
+
+_dp = _ct.POINTER(_ct.c_double)
+_ip = _ct.POINTER(_ct.c_int32)
+
+
+def lib():
+    """Load (building on first use if absent) the oracle library."""
+    global _lib
+    if _lib is None:
+        if not _os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = _ct.CDLL(_LIB_PATH)
+        d, i, sz = _ct.c_double, _ct.c_int, _ct.c_size_t
+        L.ora_evd2_cplx.restype = i
+        L.ora_evd2_cplx.argtypes = [d, d, d, d, _dp, _dp, _dp, _dp, _dp, _ct.c_uint]
+        L.ora_evd2_real.restype = i
+        L.ora_evd2_real.argtypes = [d, d, d, _dp, _dp, _dp, _dp, _ct.c_uint]
+        L.ora_evd2_batch.restype = None
+        L.ora_evd2_batch.argtypes = [sz, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ct.c_uint, i]
+        L.ora_omp_max_threads.restype = i
+        L.ora_hypot.restype = d
+        L.ora_hypot.argtypes = [d, d]
+        L.ora_getexp.restype = i
+        L.ora_getexp.argtypes = [d]
+        L.ora_lg_bound_m.restype = i
+        L.ora_lg_bound_m.argtypes = [i, i]
+        L.ora_s_round.restype = i
+        L.ora_s_round.argtypes = [d, i]
+        L.ora_s_square.restype = i
+        L.ora_s_square.argtypes = [d, i, i]
+        L.ora_rr_pair.restype = i
+        L.ora_rr_pair.argtypes = [i, _ct.c_long, i, _ct.POINTER(i), _ct.POINTER(i)]
+        L.ora_rr_steps.restype = i
+        L.ora_rr_steps.argtypes = [i]
+        L.ora_colnorm.restype = None
+        L.ora_colnorm.argtypes = [i, _dp, _dp, _dp, _dp]
+        L.ora_dpscl.restype = None
+        L.ora_dpscl.argtypes = [i, _dp, _dp, _dp, _dp, d, d, d, d, _dp, _dp]
+        L.ora_gram.restype = None
+        L.ora_gram.argtypes = [d, d, d, d, d, d, _dp, _dp, _dp, _dp]
+        L.ora_rot.restype = d
+        L.ora_rot.argtypes = [i, _dp, _dp, _dp, _dp, d, d, d, i]
+        L.ora_init_ext.restype = i
+        L.ora_init_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, _ct.POINTER(i), _dp]
+        L.ora_step_ext.restype = None
+        L.ora_step_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, _ct.POINTER(i), _dp,
+                                   _ct.c_long, _ct.POINTER(_ct.c_long), _ct.POINTER(_ct.c_long),
+                                   _ct.POINTER(i), i]
+        L.ora_finalize_ext.restype = None
+        L.ora_finalize_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, i, _dp, _dp]
+        L.ora_gesvj.restype = i
+        L.ora_gesvj.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, i,
+                                _ct.POINTER(i), _ct.POINTER(_ct.c_long), _ct.c_uint]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == _np.float64 and (a.flags.f_contiguous or a.flags.c_contiguous)
+    return a.ctypes.data_as(_dp)
+
+
+def _pi(a):
+    if a is None:
+        return None
+    assert a.dtype == _np.int32
+    return a.ctypes.data_as(_ip)
+
+
+# ---------------------------------------------------------------- EVD
+def evd2(a11, a22, a21r, a21i=None, flags=0):
+    """Scalar EVD (Listing 1 / Alg. d8jac2).  Returns a dict of the outputs."""
+    L = lib()
+    c, C, S, l1, l2 = (_ct.c_double() for _ in range(5))
+    if a21i is None:
+        z = L.ora_evd2_real(a11, a22, a21r, c, C, l1, l2, flags)
+        S.value = 0.0
+    else:
+        z = L.ora_evd2_cplx(a11, a22, a21r, a21i, c, C, S, l1, l2, flags)
+    return dict(cos=c.value, ctan_re=C.value, ctan_im=S.value, l1=l1.value, l2=l2.value, zp=z)
+
+
+def evd2_batch(a11, a22, a21r, a21i=None, flags=0, nthreads=0):
+    """Batched EVD over numpy SoA arrays; returns (cos, ctan_re, ctan_im|None, l1, l2, zp)."""
+    r = a11.shape[0]
+    out = [_np.empty(r) for _ in range(5)]
+    zp = _np.empty(r, dtype=_np.int32)
+    cti = out[2] if a21i is not None else None
+    lib().ora_evd2_batch(r, _p(a11), _p(a22), _p(a21r), _p(a21i), _p(out[0]), _p(out[1]), _p(cti),
+                         _p(out[3]), _p(out[4]), _pi(zp), flags, nthreads)
+    return out[0], out[1], cti, out[3], out[4], zp
+
+
+def omp_max_threads():
+    return lib().ora_omp_max_threads()
+
+
+# ---------------------------------------------------------------- helpers
+def hypot(x, y):
+    return lib().ora_hypot(x, y)
+
+
+def lg_bound_m(m, cplx):
+    return lib().ora_lg_bound_m(m, int(cplx))
+
+
+def s_round(Mt, cplx):
+    return lib().ora_s_round(Mt, int(cplx))
+
+
+def s_square(Mt, m, cplx):
+    return lib().ora_s_square(Mt, m, int(cplx))
+
+
+def rr_steps(n):
+    return lib().ora_rr_steps(n)
+
+
+def rr_pair(n, k, l):
+    p, q = _ct.c_int(), _ct.c_int()
+    ok = lib().ora_rr_pair(n, k, l, p, q)
+    return bool(ok), p.value, q.value
+
+
+def colnorm(xr, xi=None):
+    e, f = _ct.c_double(), _ct.c_double()
+    xr = _np.ascontiguousarray(xr, dtype=_np.float64)
+    xi = None if xi is None else _np.ascontiguousarray(xi, dtype=_np.float64)
+    lib().ora_colnorm(xr.shape[0], _p(xr), _p(xi), e, f)
+    return e.value, f.value
+
+
+def dpscl(qr, qi, pr, pi, eq, fq, ep, fp):
+    zr, zi = _ct.c_double(), _ct.c_double()
+    qr, pr = (_np.ascontiguousarray(a, dtype=_np.float64) for a in (qr, pr))
+    qi = None if qi is None else _np.ascontiguousarray(qi, dtype=_np.float64)
+    pi = None if pi is None else _np.ascontiguousarray(pi, dtype=_np.float64)
+    lib().ora_dpscl(qr.shape[0], _p(qr), _p(qi), _p(pr), _p(pi), eq, fq, ep, fp, zr, zi)
+    return zr.value, zi.value
+
+
+def gram(zr, zi, e1, f1, e2, f2):
+    o = [_ct.c_double() for _ in range(4)]
+    lib().ora_gram(zr, zi, e1, f1, e2, f2, *o)
+    return tuple(x.value for x in o)
+
+
+def rot(xpr, xpi, xqr, xqi, c, C, S, swap):
+    """In-place rotation of a column pair; returns the max-norm."""
+    return lib().ora_rot(xpr.shape[0], _p(xpr), _p(xpi), _p(xqr), _p(xqi), c, C, S, int(swap))
+
+
+# ---------------------------------------------------------------- SVD
+class State:
+    """Oracle SVD state on host numpy arrays (column-major)."""
+
+    def __init__(self, G_re, G_im=None, nosort=False):
+        self.nosort = bool(nosort)
+        self.m, self.n = G_re.shape
+        self.cplx = G_im is not None
+        self.Gr = _np.array(G_re, dtype=_np.float64, order="F", copy=True)
+        self.Gi = _np.array(G_im, dtype=_np.float64, order="F", copy=True) if self.cplx else None
+        self.Vr = _np.zeros((self.n, self.n), order="F")
+        self.Vi = _np.zeros((self.n, self.n), order="F") if self.cplx else None
+        self.e = _np.full(self.n, -_np.inf)
+        self.f = _np.ones(self.n)
+        self.s = 0
+        self.Mt = 0.0
+        self.k = 0
+        self.last_t = 0
+        self.last_sw = 0
+        self.rescaled = 0
+
+    def _args(self):
+        return (self.m, self.n, _p(self.Gr), _p(self.Gi), self.m, _p(self.Vr), _p(self.Vi), self.n,
+                _p(self.e), _p(self.f))
+
+    def init(self):
+        s, Mt = _ct.c_int(), _ct.c_double()
+        st = lib().ora_init_ext(*self._args(), s, Mt)
+        self.s, self.Mt, self.k = s.value, Mt.value, 0
+        return st
+
+    def step(self):
+        s, Mt = _ct.c_int(self.s), _ct.c_double(self.Mt)
+        t, sw, r = _ct.c_long(), _ct.c_long(), _ct.c_int()
+        lib().ora_step_ext(*self._args(), s, Mt, self.k, t, sw, r, int(self.nosort))
+        self.s, self.Mt, self.last_t, self.last_sw = s.value, Mt.value, t.value, sw.value
+        self.rescaled += r.value
+        self.k += 1
+        return t.value
+
+    def finalize(self):
+        sv_e, sv_f = _np.empty(self.n), _np.empty(self.n)
+        lib().ora_finalize_ext(*self._args(), self.s, _p(sv_e), _p(sv_f))
+        return sv_e, sv_f
+
+
+def gesvj(G_re, G_im=None, max_sweeps=64, flags=0):
+    """The whole SVD.  Returns dict(status, U_re, U_im, V_re, V_im, sv_e, sv_f, sweeps, steps)."""
+    m, n = G_re.shape
+    Gr = _np.array(G_re, dtype=_np.float64, order="F", copy=True)
+    Gi = _np.array(G_im, dtype=_np.float64, order="F", copy=True) if G_im is not None else None
+    Vr = _np.zeros((n, n), order="F")
+    Vi = _np.zeros((n, n), order="F") if G_im is not None else None
+    sv_e, sv_f = _np.empty(n), _np.empty(n)
+    sw, stp = _ct.c_int(), _ct.c_long()
+    st = lib().ora_gesvj(m, n, _p(Gr), _p(Gi), m, _p(Vr), _p(Vi), n, _p(sv_e), _p(sv_f),
+                         max_sweeps, sw, stp, flags)
+    return dict(status=st, U_re=Gr, U_im=Gi, V_re=Vr, V_im=Vi, sv_e=sv_e, sv_f=sv_f,
+                sweeps=sw.value, steps=stp.value)
+
+
+def sv_values(sv_e, sv_f):
+    """sigma_j = 2^e_j f_j as float64 (may overflow or underflow)."""
+    return _np.ldexp(sv_f, _np.where(_np.isinf(sv_e), -2000, sv_e).astype(_np.int64))

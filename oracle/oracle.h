@@ -1,0 +1,144 @@
+/*
+ * oracle.h -- CPU reference ("oracle") of the parallel one-sided Jacobi SVD
+ * hot path of Novakovic, "Vectorization of a thread-parallel Jacobi singular
+ * value decomposition method" (arXiv:2202.08361).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this code; only the test suite, the smoke check and the CPU baseline
+ * leg of the benchmark use it.  It shares no code, header or table with the
+ * HIP library.
+ *
+ * Every routine is plain, sequential (the batch EVD loop may use OpenMP
+ * threads, which does not change any result) and follows the paper's
+ * formulas in the paper's order.  Build with -ffp-contract=off so that every
+ * a*b+c is rounded twice unless fma() is written out, exactly as the paper's
+ * operation lists require.
+ *
+ * Storage: matrices are column-major with a leading dimension (in elements);
+ * complex data is split into separate real and imaginary arrays (Sect. 2.4.1).
+ */
+#ifndef JSVD_ORACLE_H
+#define JSVD_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Number of lanes of the "vector" over which every sum (sum of squares,
+ * scaled dot-product) is accumulated: lane L takes rows i = L, L+S, L+2S, ...
+ * in increasing order, and the lanes are then combined by a pairwise
+ * halving tree (lane j += lane j+h for h = S/2, S/4, ..., 1).  This is the
+ * paper's vector accumulation followed by reduce_add (Alg. zdpscl), with the
+ * vector width s taken as 1024. */
+#define ORA_LANES 1024
+
+/* flags of the stand-alone EVD */
+#define ORA_EVD_SCALED  1u  /* return lambda' (not backscaled) */
+#define ORA_EVD_SINFORM 2u  /* return e^{i alpha} sin(phi) instead of e^{i alpha} tan(phi) */
+
+/* ---- 2x2 Hermitian / symmetric EVD (Sect. 2.1-2.3, Listing 1, Alg. d8jac2) ---- */
+int ora_evd2_cplx(double a11, double a22, double a21r, double a21i,
+                  double *cs, double *ctr, double *cti, double *l1, double *l2,
+                  unsigned flags);
+int ora_evd2_real(double a11, double a22, double a21,
+                  double *cs, double *tn, double *l1, double *l2, unsigned flags);
+/* Batched form (Alg. zbjac2 / dbjac2): a21i == NULL selects real symmetric.
+ * Any output pointer may be NULL.  nthreads <= 0 uses the OpenMP default. */
+void ora_evd2_batch(size_t r, const double *a11, const double *a22,
+                    const double *a21r, const double *a21i,
+                    double *cs, double *ctr, double *cti,
+                    double *l1, double *l2, int32_t *zp,
+                    unsigned flags, int nthreads);
+int ora_omp_max_threads(void);
+
+/* ---- scalar helpers ---- */
+double ora_hypot(double x, double y);            /* Alg. hypot */
+int    ora_getexp(double x);                      /* floor(lg|x|), x finite non-zero */
+/* floor(lg(nu/(varsigma*m))) for the real (varsigma=2) and complex
+ * (varsigma=4*sqrt(2)) cases, eq. (skn); exact integer evaluation. */
+int    ora_lg_bound_m(int m, int cplx);
+int    ora_s_round(double Mt, int cplx);          /* s_(k), eq. (skr) */
+int    ora_s_square(double Mt, int m, int cplx);  /* s_[k], eq. (skn) */
+
+/* ---- round-robin parallel pivot order ----
+ * N = n (even) or n+1 (odd, index n is a phantom); K = N-1 steps per sweep.
+ * Step k' in [0,K): pair 0 is (N-1, k'); pair l = 1..N/2-1 is
+ * ((k'+l) mod K, (k'-l+K) mod K).  Each pair is returned ordered p < q.
+ * Returns 0 if the pair contains the phantom column (skipped), 1 otherwise. */
+int ora_rr_pair(int n, long kk, int l, int *p, int *q);
+int ora_rr_steps(int n);                          /* K */
+
+/* ---- column kernels (Sect. 3) ---- */
+/* Frobenius norm of a real (xi == NULL) or complex column as (e, f), f in [1,2);
+ * zero column -> (-inf, 1). */
+void ora_colnorm(int m, const double *xr, const double *xi, double *e, double *f);
+/* Scaled dot-product a21' = g_q^* g_p / (||g_q|| ||g_p||) (Alg. zdpscl). */
+void ora_dpscl(int m, const double *qr, const double *qi, const double *pr, const double *pi,
+               double eq, double fq, double ep, double fp, double *zr, double *zi);
+/* Scaled Gram matrix A'' (Alg. Gram). */
+void ora_gram(double zr, double zi, double e1, double f1, double e2, double f2,
+              double *a11, double *a22, double *a21r, double *a21i);
+/* Rotation of a column pair (Alg. zjrot, eq. transf); returns the max-norm
+ * of the transformed columns.  xi == NULL for real data (then S is ignored). */
+double ora_rot(int l, double *xpr, double *xpi, double *xqr, double *xqi,
+               double c, double C, double S, int swap);
+void ora_swap(int l, double *xpr, double *xpi, double *xqr, double *xqi);
+
+/* ---- the SVD driver (Sect. 4, Alg. zvjsvd) ---- */
+typedef struct {
+    int m, n, cplx;
+    double *Gr, *Gi; size_t ldg;   /* iteration matrix, overwritten by U */
+    double *Vr, *Vi; size_t ldv;   /* right singular vectors */
+    double *e, *f;                 /* column norms (e,f), n each */
+    int s;                         /* effective scaling exponent of G */
+    double Mt;                     /* M~_k */
+    long k;                        /* global step counter */
+    long T;                        /* transformations in the current sweep */
+    long last_t;                   /* transformations of the last step */
+    long SW;                       /* swaps without transformation in the current sweep */
+    long last_sw;                  /* swaps without transformation in the last step */
+    int  rescaled;                 /* number of step-start downscalings */
+    int  nosort;                   /* apply U instead of U P (ignore the EVD's permutation) */
+} ora_svd;
+
+#define ORA_NO_PERMUTE 1u
+
+#define ORA_OK 0
+#define ORA_NOT_CONVERGED 1
+#define ORA_EINVAL (-1)
+#define ORA_ENONFINITE (-2)
+#define ORA_EZERO (-3)
+
+/* Validate, find M~_0, scale G by 2^{s_0}, set V = I (Alg. zvjsvd, first two lines). */
+int  ora_init(ora_svd *st);
+/* One parallel step with pairs RR(k mod K); updates G, V, e, f, Mt, s, T. */
+void ora_step(ora_svd *st);
+/* U = G diag(2^{-e}) / f, sigma = (e - s, f), then a stable descending sort of
+ * (sigma, u, v).  Writes the sorted U into G and sorted V into V. */
+void ora_finalize(ora_svd *st, double *sv_e, double *sv_f);
+/* The whole method: returns ORA_OK / ORA_NOT_CONVERGED / error; *sweeps = C,
+ * the number of sweeps before the one that found nothing to do.  A sweep
+ * converges when it neither transformed nor swapped a pair: a swap moves
+ * columns, so a sweep that swapped did not meet every column pair. */
+int  ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
+               double *Vr, double *Vi, size_t ldv,
+               double *sv_e, double *sv_f, int max_sweeps, int *sweeps, long *steps,
+               unsigned flags);
+
+/* flat-argument forms of ora_init / ora_step / ora_finalize */
+int  ora_init_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
+                  double *Vr, double *Vi, size_t ldv, double *e, double *f,
+                  int *s, double *Mt);
+void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
+                  double *Vr, double *Vi, size_t ldv, double *e, double *f,
+                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, int nosort);
+void ora_finalize_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
+                      double *Vr, double *Vi, size_t ldv, double *e, double *f,
+                      int s, double *sv_e, double *sv_f);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
