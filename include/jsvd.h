@@ -1,0 +1,249 @@
+/*
+ * jsvd.h -- C ABI of the MI355X (gfx950) implementation of the parallel
+ * one-sided Jacobi SVD hot path of V. Novakovic, "Vectorization of a
+ * thread-parallel Jacobi singular value decomposition method",
+ * arXiv:2202.08361 (SIAM J. Sci. Comput., 2023).
+ *
+ * General conventions
+ * -------------------
+ * - Every matrix and vector argument is a DEVICE pointer owned by the caller
+ *   (the library never frees it).  The library owns only the workspace it
+ *   allocates in *_create and frees in *_destroy.
+ * - Matrices are column-major with a leading dimension in elements.  Complex
+ *   data is split: a complex m x n matrix is two real m x n matrices (real and
+ *   imaginary parts), as in Sect. 2.4.1 of the paper.  A NULL imaginary
+ *   pointer selects the real (symmetric / orthogonal) variant.
+ * - Every floating-point quantity is IEEE-754 binary64; integer exponents
+ *   and counters are int32 / int64.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Calls that only
+ *   launch work return as soon as it is enqueued; calls documented as
+ *   "synchronises" wait for the stream.
+ * - Return value: JSVD_OK (0) on success, > 0 a warning, < 0 an error.  No
+ *   C++ exception crosses the ABI.  Arguments are validated before anything
+ *   is enqueued; on an error nothing is enqueued and no output is touched.
+ */
+#ifndef JSVD_H
+#define JSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define JSVD_VERSION_MAJOR 0
+#define JSVD_VERSION_MINOR 1
+
+enum {
+    JSVD_OK = 0,
+    JSVD_NOT_CONVERGED = 1, /* sweep limit reached (Alg. zvjsvd returns C = S) */
+    JSVD_EINVAL = -1,       /* invalid argument (sizes, strides, NULL pointers, flags) */
+    JSVD_ENONFINITE = -2,   /* the input holds Inf or NaN (M~_0 = inf, Sect. 3.2) */
+    JSVD_EZERO = -3,        /* the input is the zero matrix (M~_0 = 0, Sect. 3.2) */
+    JSVD_ENOMEM = -4,       /* device or host allocation failed */
+    JSVD_EDEVICE = -5,      /* a HIP runtime call failed */
+    JSVD_EAGAIN = -6,       /* serving: the request cannot be admitted now */
+    JSVD_ENOTFOUND = -7     /* serving: unknown ticket */
+};
+
+/* flags of jsvd_gesvj / jsvd_gesvj_batched */
+#define JSVD_NO_PERMUTE 1u  /* apply U instead of U P during the iteration (no column
+                               sorting by the EVD's permutation, Sect. 2); the final
+                               sort still orders the output */
+
+/* flags of jsvd_evd2_batched */
+#define JSVD_EVD_SCALED  1u /* return lambda' = 2^zeta lambda (not backscaled), Sect. 2.3 */
+#define JSVD_EVD_SINFORM 2u /* return e^{i alpha} sin(phi) instead of e^{i alpha} tan(phi), eq. (jacsec) */
+
+/* Library version as (major << 16) | minor. */
+int jsvd_version(void);
+/* Static text of a status code. */
+const char *jsvd_strerror(int status);
+
+/* ----------------------------------------------------------------------
+ * Stand-alone batched EVD of Hermitian / real symmetric 2x2 matrices
+ * (Sect. 2, Listing 1, Alg. zbjac2 and dbjac2).
+ *
+ * Input: r matrices [[a11, conj(a21)], [a21, a22]] in structure-of-arrays
+ * form: a11[i], a22[i], a21_re[i] and (complex) a21_im[i], all finite.
+ * a21_im == NULL selects the real symmetric variant; then ctan_im must be
+ * NULL too.
+ * Output (each r elements, any of lambda1, lambda2, zp may be NULL):
+ *   cos_phi[i]              cos(phi)
+ *   ctan_re[i], ctan_im[i]  e^{i alpha} tan(phi) (real: sign(a21) tan(phi)),
+ *                           or e^{i alpha} sin(phi) with JSVD_EVD_SINFORM
+ *   lambda1[i], lambda2[i]  eigenvalues 2^-zeta lambda'_1,2 (or lambda' with
+ *                           JSVD_EVD_SCALED); U = [[c, -conj(e) s], [e s, c]]
+ *                           with A = U diag(lambda1, lambda2) U^*
+ *   zp[i]                   (zeta' << 1) | p, zeta' = -zeta the exponent of
+ *                           the backscaling, p = [lambda'_1 < lambda'_2]
+ * Results are bit-for-bit those of the serial algorithm of Listing 1 in
+ * IEEE double arithmetic with round-to-nearest-even and gradual underflow.
+ * Input and output arrays must not overlap.  Asynchronous on `stream`.
+ * ---------------------------------------------------------------------- */
+int jsvd_evd2_batched(size_t r, const double *a11, const double *a22,
+                      const double *a21_re, const double *a21_im,
+                      double *cos_phi, double *ctan_re, double *ctan_im,
+                      double *lambda1, double *lambda2, int32_t *zp,
+                      unsigned flags, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Device-resident SVD state: the hot path one parallel step at a time
+ * (Sect. 4, Alg. zvjsvd).
+ *
+ * The state owns a working copy of the iteration matrix G (m x n, m >= n >= 1),
+ * the accumulated right transformations V (n x n), the column norms (e, f)
+ * (sigma-like pairs 2^e f, f in [1, 2), Sect. 3.2), the scaling exponent s,
+ * the max-norm estimate M~ and the step / sweep / transformation counters.
+ * The pivot pairs of step k are the round-robin pairs of k mod K,
+ * K = n - 1 (n even) or n (n odd).
+ * ---------------------------------------------------------------------- */
+typedef struct jsvd_state_s *jsvd_state;
+
+typedef struct {
+    int64_t steps;        /* steps taken since the last load */
+    int64_t sweeps;       /* completed sweeps (jsvd_sweep) */
+    int64_t T;            /* transformations in the current sweep so far */
+    int64_t last_t;       /* transformations in the last step */
+    int64_t swaps;        /* column swaps without transformation in the current sweep */
+    int32_t s;            /* effective scaling exponent: G_k = 2^s (G_0 V_k) */
+    int32_t rescaled;     /* step-start downscalings performed (Sect. 3.2) */
+    double Mt;            /* M~_k, the max-norm estimate of G_k */
+    int32_t converged;    /* a full sweep with neither transformation nor swap */
+    int32_t status;       /* JSVD_OK or the load error */
+} jsvd_info;
+
+/* Allocate a state for an m x n real (is_complex = 0) or complex problem.
+ * Returns JSVD_EINVAL for m < n, n < 1, JSVD_ENOMEM when out of memory. */
+int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out);
+void jsvd_state_destroy(jsvd_state st);
+
+/* Load G (device, column-major, leading dimension ldg >= m) into the state,
+ * then initialise as in Alg. zvjsvd: M~_0 = max|component| (NaN counted as
+ * Inf), s_0 = s_[0] of eq. (skn), G_1 = 2^{s_0} G, V_1 = I.  Synchronises.
+ * Returns JSVD_ENONFINITE / JSVD_EZERO for a non-finite / zero G. */
+int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_t ldg,
+                    void *stream);
+
+/* One parallel Jacobi step on the state (the hot path): for every pivot pair
+ * of the step, the Frobenius norms of both columns, the scaled dot-product
+ * (Alg. zdpscl), the convergence test (Alg. cvg) and scaled Gram matrix
+ * (Alg. Gram), the 2x2 EVD (Listing 1), and the rotation or swap of the G
+ * and V column pairs (Alg. zjrot), with the step-start rescaling check of
+ * Sect. 3.2.  Step index, M~ and the counters stay on the device; launches
+ * only. */
+int jsvd_step(jsvd_state st, void *stream);
+
+/* K steps followed by the end-of-sweep bookkeeping; launches only. */
+int jsvd_sweep(jsvd_state st, void *stream);
+
+/* Read the scalars of the state.  Synchronises. */
+int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream);
+
+/* Copy the working G (scaled iteration matrix), V and the column norms of
+ * the last step out of the state (any pointer may be NULL).  Synchronises. */
+int jsvd_state_save(jsvd_state st, double *G_re, double *G_im, size_t ldg,
+                    double *V_re, double *V_im, size_t ldv,
+                    double *e, double *f, int32_t *s, double *Mt, int64_t *step,
+                    void *stream);
+/* Overwrite the working G and V and the scalars (resume a saved state).
+ * Synchronises. */
+int jsvd_state_restore(jsvd_state st, const double *G_re, const double *G_im, size_t ldg,
+                       const double *V_re, const double *V_im, size_t ldv,
+                       int32_t s, double Mt, int64_t step, void *stream);
+
+/* Finalisation (Sect. 4.2.1): u_j = (g_j 2^{-e_j}) / f_j, sigma_j =
+ * (e_j - s, f_j), then a stable sort of (sigma, u, v) into descending order.
+ * U (m x n) and V (n x n) are caller buffers; sv_e/sv_f receive the pairs and
+ * sv (may be NULL) the values 2^e f as doubles.  Launches only. */
+int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu,
+                        double *V_re, double *V_im, size_t ldv,
+                        double *sv_e, double *sv_f, double *sv, void *stream);
+
+/* Force the workgroup size (threads per pivot pair: 64, 128, 256, 512 or
+ * 1024; 0 = automatic).  Results do not depend on it (bit-identical). */
+int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
+
+/* ----------------------------------------------------------------------
+ * The whole SVD (Alg. zvjsvd with round-robin pairs): G = U Sigma V^*.
+ * G (m x n, ldg >= m) is overwritten by U; V (n x n, ldv >= n) receives V;
+ * sv_e/sv_f (n) receive sigma_j = 2^{sv_e[j]} sv_f[j] in descending order;
+ * sv (n, may be NULL) the same as doubles.  *sweeps receives the number of
+ * sweeps that transformed something (C in Alg. zvjsvd).  max_sweeps <= 0
+ * selects 64.  Synchronises.  On JSVD_NOT_CONVERGED G holds the scaled
+ * iteration matrix and sv_e/sv_f its current (unsorted) column norms.
+ * ---------------------------------------------------------------------- */
+int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg,
+               double *V_re, double *V_im, size_t ldv,
+               double *sv_e, double *sv_f, double *sv, int max_sweeps, int *sweeps,
+               unsigned flags, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Many independent SVDs of uneven sizes in one persistent launch.  Arrays
+ * of `count` host pointers / sizes describe the problems; every matrix
+ * pointer is a device pointer.  Matrix i follows jsvd_gesvj exactly (same
+ * results, bit for bit).  status[i] and sweeps[i] (host arrays) receive the
+ * per-matrix outcome.  Synchronises.
+ * ---------------------------------------------------------------------- */
+int jsvd_gesvj_batched(int count, const int *m, const int *n, const int *is_complex,
+                       double *const *G_re, double *const *G_im, const size_t *ldg,
+                       double *const *V_re, double *const *V_im, const size_t *ldv,
+                       double *const *sv_e, double *const *sv_f,
+                       int max_sweeps, int *sweeps, int *status, unsigned flags, void *stream);
+
+/* ----------------------------------------------------------------------
+ * Serving: continuous batching of SVD requests under an HBM budget.
+ * Requests are admitted as slots and device memory free up; admitted
+ * requests advance concurrently on the device, sweep by sweep, with their
+ * iteration state device-resident.  Buffers stay caller-owned and must stay
+ * valid until the ticket completes.
+ * ---------------------------------------------------------------------- */
+typedef struct jsvd_server_s *jsvd_server;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* device bytes the server may allocate for work state */
+    int max_slots;           /* requests on the device at once */
+    int max_sweeps;          /* per request (<= 0: 64) */
+    int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
+} jsvd_serve_config;
+
+typedef struct {
+    int m, n, is_complex;
+    double *G_re, *G_im; size_t ldg;   /* in: A; out: U */
+    double *V_re, *V_im; size_t ldv;   /* out: V */
+    double *sv_e, *sv_f;               /* out: sigma (device, n each) */
+    uint64_t tag;
+} jsvd_request;
+
+typedef struct {
+    uint64_t submitted, completed, rejected;
+    double p50_ns, p99_ns;       /* submit-to-completion latency */
+    double p50_queue_ns, p99_queue_ns; /* submit-to-admission */
+    double svds_per_s;           /* completions per second since creation */
+    int queue_depth, active;
+    size_t hbm_in_use;
+} jsvd_serve_stats;
+
+int jsvd_serve_create(const jsvd_serve_config *cfg, jsvd_server *out);
+/* Non-blocking; *ticket identifies the request. */
+int jsvd_serve_submit(jsvd_server sv, const jsvd_request *req, uint64_t *ticket);
+/* *done = 1 once finished; *status is its jsvd_gesvj status, *sweeps its C. */
+int jsvd_serve_poll(jsvd_server sv, uint64_t ticket, int *done, int *status, int *sweeps);
+int jsvd_serve_wait(jsvd_server sv, uint64_t ticket, int *status, int *sweeps);
+int jsvd_serve_stats_get(jsvd_server sv, jsvd_serve_stats *out);
+/* Waits for every admitted request, then frees the server. */
+int jsvd_serve_destroy(jsvd_server sv);
+
+/* ----------------------------------------------------------------------
+ * Layout helpers (Sect. SM5): interleaved complex (re, im pairs) <-> split.
+ * ---------------------------------------------------------------------- */
+int jsvd_split(int m, int n, const double *Z, size_t ldz, double *X_re, double *X_im, size_t ldx,
+               void *stream);
+int jsvd_merge(int m, int n, const double *X_re, const double *X_im, size_t ldx, double *Z, size_t ldz,
+               void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* JSVD_H */

@@ -1,0 +1,459 @@
+// capi.cpp -- the C ABI (include/jsvd.h) over the gfx950 kernels: argument
+// validation, device workspace, the sweep loop of Alg. zvjsvd
+// (arXiv:2202.08361, Sect. 4.3) with hipGraph-captured sweeps, and the
+// finalisation.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <new>
+
+#include "../../include/jsvd.h"
+#include "kernels.hpp"
+
+using namespace jsvd;
+
+#define HIPCHK(x)                                 \
+    do {                                          \
+        if ((x) != hipSuccess) return JSVD_EDEVICE; \
+    } while (0)
+
+// floor(lg(nu / (varsigma m))) of eq. (skn) by integer arithmetic:
+// real (varsigma = 2): 1022 - floor(lg m);
+// complex (varsigma = 4 sqrt 2): 1021 - floor(lg m) - [m^2 > 2^(2 floor(lg m) + 1)].
+static int lg_bound(int m, int cplx)
+{
+    int a = 0;
+    while ((2LL << a) <= (long long)m) ++a;
+    if (!cplx) return 1022 - a;
+    const unsigned long long mm = (unsigned long long)m * (unsigned long long)m;
+    return 1021 - a - (mm > (1ULL << (2 * a + 1)) ? 1 : 0);
+}
+
+static long long round_up(long long x, long long a) { return (x + a - 1) / a * a; }
+
+struct jsvd_state_s {
+    int m, n, cplx;
+    int threads;       // forced workgroup size (0 = auto)
+    int nosort;
+    int max_sweeps;
+    int device;
+    void *mem;         // the single device allocation
+    SvdDesc d;
+    int *rank;
+    unsigned long long *maxbits;
+    DevScalars *host;  // pinned staging for the scalars
+    unsigned long long *host_bits;
+    hipGraphExec_t graph;
+    hipGraph_t graph_def;
+    int graph_threads;
+};
+
+extern "C" int jsvd_version(void) { return (JSVD_VERSION_MAJOR << 16) | JSVD_VERSION_MINOR; }
+
+extern "C" const char *jsvd_strerror(int status)
+{
+    switch (status) {
+    case JSVD_OK: return "ok";
+    case JSVD_NOT_CONVERGED: return "not converged within the sweep limit";
+    case JSVD_EINVAL: return "invalid argument";
+    case JSVD_ENONFINITE: return "input holds Inf or NaN";
+    case JSVD_EZERO: return "input is the zero matrix";
+    case JSVD_ENOMEM: return "out of memory";
+    case JSVD_EDEVICE: return "HIP runtime error";
+    case JSVD_EAGAIN: return "request not admitted now";
+    case JSVD_ENOTFOUND: return "unknown ticket";
+    }
+    return "unknown status";
+}
+
+// ---------------------------------------------------------------------------
+// batched EVD
+extern "C" int jsvd_evd2_batched(size_t r, const double *a11, const double *a22, const double *a21_re,
+                                 const double *a21_im, double *cos_phi, double *ctan_re, double *ctan_im,
+                                 double *lambda1, double *lambda2, int32_t *zp, unsigned flags, void *stream)
+{
+    if (flags & ~3u) return JSVD_EINVAL;
+    if (r == 0) return JSVD_OK;
+    if (!a11 || !a22 || !a21_re || !cos_phi || !ctan_re) return JSVD_EINVAL;
+    if ((a21_im == nullptr) != (ctan_im == nullptr)) return JSVD_EINVAL;
+    if (r > (size_t)1 << 40) return JSVD_EINVAL;
+    const int force_scalar = getenv("JSVD_EVD_SCALAR") != nullptr;
+    if (launch_evd2(r, a11, a22, a21_re, a21_im, cos_phi, ctan_re, ctan_im, lambda1, lambda2, zp, flags,
+                    force_scalar, (hipStream_t)stream) != hipSuccess)
+        return JSVD_EDEVICE;
+    return JSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// state
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
+{
+    if (!out) return JSVD_EINVAL;
+    *out = nullptr;
+    if (n < 1 || m < n) return JSVD_EINVAL;
+    if (m > step_max_rows(is_complex != 0, 1024)) return JSVD_EINVAL;
+    jsvd_state st = new (std::nothrow) jsvd_state_s;
+    if (!st) return JSVD_ENOMEM;
+    memset(st, 0, sizeof(*st));
+    st->m = m;
+    st->n = n;
+    st->cplx = is_complex != 0;
+    st->max_sweeps = 64;
+    if (hipGetDevice(&st->device) != hipSuccess) {
+        delete st;
+        return JSVD_EDEVICE;
+    }
+    const long long ldg = round_up(m, 64), ldv = round_up(n, 64);
+    const int c = st->cplx ? 2 : 1;
+    size_t off = 0;
+    const size_t oG = off; off = align_up(off + sizeof(double) * (size_t)ldg * n * c);
+    const size_t oV = off; off = align_up(off + sizeof(double) * (size_t)ldv * n * c);
+    const size_t oE = off; off = align_up(off + sizeof(double) * (size_t)n);
+    const size_t oF = off; off = align_up(off + sizeof(double) * (size_t)n);
+    const size_t oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
+    const size_t oS = off; off = align_up(off + sizeof(DevScalars));
+    const size_t oM = off; off = align_up(off + sizeof(unsigned long long));
+    if (hipMalloc(&st->mem, off) != hipSuccess) {
+        delete st;
+        return JSVD_ENOMEM;
+    }
+    if (hipHostMalloc((void **)&st->host, 512, hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(st->mem);
+        delete st;
+        return JSVD_ENOMEM;
+    }
+    static_assert(sizeof(DevScalars) <= 256, "staging layout");
+    st->host_bits = (unsigned long long *)((char *)st->host + 256);
+    char *b = (char *)st->mem;
+    SvdDesc &d = st->d;
+    d.m = m;
+    d.n = n;
+    d.cplx = st->cplx;
+    d.nosort = 0;
+    d.Gr = (double *)(b + oG);
+    d.Gi = st->cplx ? d.Gr + (size_t)ldg * n : nullptr;
+    d.ldg = ldg;
+    d.Vr = (double *)(b + oV);
+    d.Vi = st->cplx ? d.Vr + (size_t)ldv * n : nullptr;
+    d.ldv = ldv;
+    d.e = (double *)(b + oE);
+    d.f = (double *)(b + oF);
+    d.sc = (DevScalars *)(b + oS);
+    d.lgbound = lg_bound(m, st->cplx);
+    d.ups = ldexp(sqrt((double)m), -53);
+    st->rank = (int *)(b + oR);
+    st->maxbits = (unsigned long long *)(b + oM);
+    *out = st;
+    return JSVD_OK;
+}
+
+extern "C" void jsvd_state_destroy(jsvd_state st)
+{
+    if (!st) return;
+    if (st->graph) (void)hipGraphExecDestroy(st->graph);
+    if (st->graph_def) (void)hipGraphDestroy(st->graph_def);
+    if (st->mem) (void)hipFree(st->mem);
+    if (st->host) (void)hipHostFree(st->host);
+    delete st;
+}
+
+static int push_scalars(jsvd_state st, const DevScalars &h, hipStream_t s)
+{
+    *st->host = h;
+    HIPCHK(hipMemcpyAsync(st->d.sc, st->host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return JSVD_OK;
+}
+
+static int pull_scalars(jsvd_state st, hipStream_t s)
+{
+    HIPCHK(hipMemcpyAsync(st->host, st->d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return JSVD_OK;
+}
+
+static unsigned long long dbits(double x)
+{
+    unsigned long long b;
+    memcpy(&b, &x, 8);
+    return b;
+}
+
+static double bitsd(unsigned long long b)
+{
+    double x;
+    memcpy(&x, &b, 8);
+    return x;
+}
+
+extern "C" int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, void *stream)
+{
+    if (!st || !G_re || ldg < (size_t)st->m) return JSVD_EINVAL;
+    if ((G_im != nullptr) != (st->cplx != 0)) return JSVD_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(hipMemsetAsync(st->maxbits, 0, sizeof(unsigned long long), s));
+    HIPCHK(launch_maxabs(st->d, G_re, G_im, (long long)ldg, st->maxbits, s));
+    HIPCHK(hipMemcpyAsync(st->host_bits, st->maxbits, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double M0 = bitsd(*st->host_bits);
+    DevScalars h;
+    memset(&h, 0, sizeof(h));
+    h.max_sweeps = st->max_sweeps;
+    if (!(M0 <= 1.79769313486231570815e308)) {
+        h.status = JSVD_ENONFINITE;
+        h.stop = 1;
+        push_scalars(st, h, s);
+        return JSVD_ENONFINITE;
+    }
+    if (M0 == 0.0) {
+        h.status = JSVD_EZERO;
+        h.stop = 1;
+        push_scalars(st, h, s);
+        return JSVD_EZERO;
+    }
+    // s_0 = s_[0] (eq. skn), G_1 = 2^{s_0} G, M~_1 = 2^{s_0} M~_0, V_1 = I
+    const int s0 = st->d.lgbound - ilogb(M0) - 1;
+    HIPCHK(launch_init_scale(st->d, G_re, G_im, (long long)ldg, s0, s));
+    h.Mt_bits = dbits(ldexp(M0, s0));
+    h.s = s0;
+    return push_scalars(st, h, s);
+}
+
+extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
+{
+    if (!st) return JSVD_EINVAL;
+    const int t = threads_per_pair;
+    if (t != 0 && t != 64 && t != 128 && t != 256 && t != 512 && t != 1024) return JSVD_EINVAL;
+    if (t != 0 && st->m > step_max_rows(st->cplx, t)) return JSVD_EINVAL;
+    st->threads = t;
+    return JSVD_OK;
+}
+
+static int state_threads(jsvd_state st)
+{
+    return st->threads ? st->threads : step_auto_threads(st->m, st->n);
+}
+
+extern "C" int jsvd_step(jsvd_state st, void *stream)
+{
+    if (!st) return JSVD_EINVAL;
+    HIPCHK(launch_step(st->d, state_threads(st), (hipStream_t)stream));
+    return JSVD_OK;
+}
+
+static int sweep_steps(int n) { return n + (n & 1) - 1; }
+
+static int build_graph(jsvd_state st)
+{
+    const int thr = state_threads(st);
+    if (st->graph && st->graph_threads == thr) return JSVD_OK;
+    if (st->graph) {
+        (void)hipGraphExecDestroy(st->graph);
+        st->graph = nullptr;
+    }
+    if (st->graph_def) {
+        (void)hipGraphDestroy(st->graph_def);
+        st->graph_def = nullptr;
+    }
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    int rc = JSVD_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return JSVD_EDEVICE;
+    }
+    const int K = sweep_steps(st->n);
+    for (int k = 0; k < K && rc == JSVD_OK; ++k)
+        if (launch_step(st->d, thr, cs) != hipSuccess) rc = JSVD_EDEVICE;
+    if (rc == JSVD_OK && launch_sweep_end(st->d, cs) != hipSuccess) rc = JSVD_EDEVICE;
+    hipGraph_t g = nullptr;
+    if (hipStreamEndCapture(cs, &g) != hipSuccess) rc = JSVD_EDEVICE;
+    (void)hipStreamDestroy(cs);
+    if (rc != JSVD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (hipGraphInstantiate(&st->graph, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return JSVD_EDEVICE;
+    }
+    st->graph_def = g;
+    st->graph_threads = thr;
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_sweep(jsvd_state st, void *stream)
+{
+    if (!st) return JSVD_EINVAL;
+    const int rc = build_graph(st);
+    if (rc != JSVD_OK) return rc;
+    HIPCHK(hipGraphLaunch(st->graph, (hipStream_t)stream));
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
+{
+    if (!st || !out) return JSVD_EINVAL;
+    const int rc = pull_scalars(st, (hipStream_t)stream);
+    if (rc != JSVD_OK) return rc;
+    const DevScalars &h = *st->host;
+    out->steps = h.k;
+    out->sweeps = h.C;
+    out->T = h.T;
+    out->last_t = h.last_t;
+    out->swaps = h.SW;
+    out->s = h.s;
+    out->rescaled = h.rescaled;
+    out->Mt = bitsd(h.Mt_bits);
+    out->converged = h.converged;
+    out->status = h.status;
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_save(jsvd_state st, double *G_re, double *G_im, size_t ldg, double *V_re,
+                               double *V_im, size_t ldv, double *e, double *f, int32_t *s_out, double *Mt,
+                               int64_t *step, void *stream)
+{
+    if (!st) return JSVD_EINVAL;
+    if (G_re && ldg < (size_t)st->m) return JSVD_EINVAL;
+    if (V_re && ldv < (size_t)st->n) return JSVD_EINVAL;
+    if (st->cplx && ((G_re && !G_im) || (V_re && !V_im))) return JSVD_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const SvdDesc &d = st->d;
+    if (G_re) {
+        HIPCHK(launch_copy2d(d.m, d.n, d.Gr, d.ldg, G_re, (long long)ldg, s));
+        if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, d.Gi, d.ldg, G_im, (long long)ldg, s));
+    }
+    if (V_re) {
+        HIPCHK(launch_copy2d(d.n, d.n, d.Vr, d.ldv, V_re, (long long)ldv, s));
+        if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, d.Vi, d.ldv, V_im, (long long)ldv, s));
+    }
+    if (e) HIPCHK(hipMemcpyAsync(e, d.e, sizeof(double) * d.n, hipMemcpyDeviceToDevice, s));
+    if (f) HIPCHK(hipMemcpyAsync(f, d.f, sizeof(double) * d.n, hipMemcpyDeviceToDevice, s));
+    const int rc = pull_scalars(st, s);
+    if (rc != JSVD_OK) return rc;
+    if (s_out) *s_out = st->host->s;
+    if (Mt) *Mt = bitsd(st->host->Mt_bits);
+    if (step) *step = st->host->k;
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_restore(jsvd_state st, const double *G_re, const double *G_im, size_t ldg,
+                                  const double *V_re, const double *V_im, size_t ldv, int32_t s_in, double Mt,
+                                  int64_t step, void *stream)
+{
+    if (!st || !G_re || !V_re || ldg < (size_t)st->m || ldv < (size_t)st->n) return JSVD_EINVAL;
+    if (st->cplx && (!G_im || !V_im)) return JSVD_EINVAL;
+    if (!(Mt >= 0.0 && Mt <= 1.79769313486231570815e308) || step < 0) return JSVD_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const SvdDesc &d = st->d;
+    HIPCHK(launch_copy2d(d.m, d.n, G_re, (long long)ldg, d.Gr, d.ldg, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, G_im, (long long)ldg, d.Gi, d.ldg, s));
+    HIPCHK(launch_copy2d(d.n, d.n, V_re, (long long)ldv, d.Vr, d.ldv, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, V_im, (long long)ldv, d.Vi, d.ldv, s));
+    DevScalars h;
+    memset(&h, 0, sizeof(h));
+    h.Mt_bits = dbits(Mt);
+    h.s = s_in;
+    h.k = step;
+    h.max_sweeps = st->max_sweeps;
+    return push_scalars(st, h, s);
+}
+
+extern "C" int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu, double *V_re,
+                                   double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv,
+                                   void *stream)
+{
+    if (!st || !U_re || !V_re || !sv_e || !sv_f || ldu < (size_t)st->m || ldv < (size_t)st->n)
+        return JSVD_EINVAL;
+    if (st->cplx && (!U_im || !V_im)) return JSVD_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = pull_scalars(st, s);
+    if (rc != JSVD_OK) return rc;
+    const int sexp = st->host->s;
+    HIPCHK(launch_colnorms_raw(st->d, s));
+    HIPCHK(launch_rank(st->d, st->rank, s));
+    HIPCHK(launch_final_write(st->d, st->rank, U_re, U_im, (long long)ldu, V_re, V_im, (long long)ldv, sv_e,
+                              sv_f, sv, sexp, s));
+    return JSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
+// the whole SVD
+static int gesvj_on_state(jsvd_state st, double *G_re, double *G_im, size_t ldg, double *V_re, double *V_im,
+                          size_t ldv, double *sv_e, double *sv_f, double *sv, int *sweeps, hipStream_t s)
+{
+    int rc = jsvd_state_load(st, G_re, G_im, ldg, s);
+    if (rc != JSVD_OK) {
+        if (sweeps) *sweeps = 0;
+        return rc;
+    }
+    // one graph-launched sweep at a time; the device decides convergence
+    for (;;) {
+        rc = jsvd_sweep(st, s);
+        if (rc != JSVD_OK) return rc;
+        rc = pull_scalars(st, s);
+        if (rc != JSVD_OK) return rc;
+        if (st->host->stop) break;
+    }
+    const DevScalars h = *st->host;
+    if (sweeps) *sweeps = (int)h.C;
+    if (h.converged) {
+        rc = jsvd_state_finalize(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, s);
+        if (rc != JSVD_OK) return rc;
+        HIPCHK(hipStreamSynchronize(s));
+        return JSVD_OK;
+    }
+    // not converged: the scaled iteration matrix, V, and the current norms
+    const SvdDesc &d = st->d;
+    HIPCHK(launch_copy2d(d.m, d.n, d.Gr, d.ldg, G_re, (long long)ldg, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, d.Gi, d.ldg, G_im, (long long)ldg, s));
+    HIPCHK(launch_copy2d(d.n, d.n, d.Vr, d.ldv, V_re, (long long)ldv, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, d.Vi, d.ldv, V_im, (long long)ldv, s));
+    HIPCHK(launch_colnorms_raw(d, s));
+    HIPCHK(launch_colnorm_out(d, h.s, sv_e, sv_f, sv, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return JSVD_NOT_CONVERGED;
+}
+
+extern "C" int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg, double *V_re, double *V_im,
+                          size_t ldv, double *sv_e, double *sv_f, double *sv, int max_sweeps, int *sweeps,
+                          unsigned flags, void *stream)
+{
+    if (n < 1 || m < n || !G_re || !V_re || !sv_e || !sv_f || ldg < (size_t)m || ldv < (size_t)n)
+        return JSVD_EINVAL;
+    if ((G_im == nullptr) != (V_im == nullptr)) return JSVD_EINVAL;
+    if (flags & ~JSVD_NO_PERMUTE) return JSVD_EINVAL;
+    jsvd_state st = nullptr;
+    int rc = jsvd_state_create(m, n, G_im != nullptr, &st);
+    if (rc != JSVD_OK) return rc;
+    st->max_sweeps = max_sweeps > 0 ? max_sweeps : 64;
+    st->d.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+    rc = gesvj_on_state(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, sweeps, (hipStream_t)stream);
+    jsvd_state_destroy(st);
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// layout helpers
+extern "C" int jsvd_split(int m, int n, const double *Z, size_t ldz, double *X_re, double *X_im, size_t ldx,
+                          void *stream)
+{
+    if (m < 0 || n < 0 || !Z || !X_re || !X_im || ldz < 2 * (size_t)m || ldx < (size_t)m) return JSVD_EINVAL;
+    HIPCHK(launch_split(m, n, Z, (long long)ldz, X_re, X_im, (long long)ldx, (hipStream_t)stream));
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_merge(int m, int n, const double *X_re, const double *X_im, size_t ldx, double *Z, size_t ldz,
+                          void *stream)
+{
+    if (m < 0 || n < 0 || !Z || !X_re || !X_im || ldz < 2 * (size_t)m || ldx < (size_t)m) return JSVD_EINVAL;
+    HIPCHK(launch_merge(m, n, X_re, X_im, (long long)ldx, Z, (long long)ldz, (hipStream_t)stream));
+    return JSVD_OK;
+}

@@ -1,0 +1,80 @@
+// kernels.hpp -- internal launch interface between the C ABI (capi.cpp) and
+// the HIP kernels.  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace jsvd {
+
+hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const double *ar,
+                       const double *ai, double *cs, double *cr, double *ci, double *l1,
+                       double *l2, int32_t *zp, unsigned flags, int force_scalar, hipStream_t s);
+
+// Device-resident scalars of one SVD (updated only by kernels).
+struct DevScalars {
+    unsigned long long Mt_bits;   // M~_k as the bit pattern of a non-negative double
+    unsigned long long M_step;    // max-norm of the transformed columns of this step (bits)
+    unsigned long long t_step;    // transformations in this step
+    unsigned long long sw_step;   // swaps without transformation in this step
+    unsigned long long done;      // workgroups finished in this step
+    long long k;                  // global step counter
+    long long T;                  // transformations in the current sweep
+    long long SW;                 // swaps without transformation in the current sweep
+    long long last_t;             // transformations of the last completed step
+    long long sweeps;             // sweeps completed
+    long long C;                  // sweeps that found a transformation or a swap
+    int s;                        // effective scaling exponent
+    int rescaled;                 // step-start downscalings
+    int converged;                // a sweep without transformation and swap was seen
+    int stop;                     // set when converged or the sweep limit is reached
+    int max_sweeps;
+    int status;                   // init status: 0, or -2 (non-finite), -3 (zero)
+};
+
+// Problem description shared by the SVD kernels.
+struct SvdDesc {
+    int m, n;
+    int cplx;
+    int nosort;            // ignore the permutation of the EVD during the iteration
+    double *Gr, *Gi;       // working iteration matrix
+    long long ldg;
+    double *Vr, *Vi;       // accumulated right transformations
+    long long ldv;
+    double *e, *f;         // column norms of the last step (e as double)
+    DevScalars *sc;
+    int lgbound;           // floor(lg(nu/(varsigma m))) of eq. (skn)
+    double ups;            // fl(sqrt(m)) 2^-53
+};
+
+// initialisation: M~_0 into *maxbits (zeroed by the caller), then
+// G <- 2^{s_0} A copied into the workspace and V <- I
+hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
+                         unsigned long long *maxbits, hipStream_t s);
+hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda, int s0,
+                             hipStream_t s);
+// one parallel step; threads = 0 picks automatically
+hipError_t launch_step(const SvdDesc &d, int threads, hipStream_t s);
+int step_max_rows(int cplx, int W);
+int step_auto_threads(int m, int n);
+// end-of-sweep bookkeeping (1 thread)
+hipError_t launch_sweep_end(const SvdDesc &d, hipStream_t s);
+// finalisation: norms of all columns into d.e/d.f, their descending ranks,
+// then U = G diag(2^-e)/f and V permuted into the caller's buffers
+hipError_t launch_colnorms_raw(const SvdDesc &d, hipStream_t s);
+hipError_t launch_rank(const SvdDesc &d, int *rank, hipStream_t s);
+hipError_t launch_final_write(const SvdDesc &d, const int *rank, double *Ur, double *Ui, long long ldu,
+                              double *Vr, double *Vi, long long ldv, double *sv_e, double *sv_f,
+                              double *sv, int s_exp, hipStream_t s);
+// non-converged exit: the current norms, backscaled, in column order
+hipError_t launch_colnorm_out(const SvdDesc &d, int s_exp, double *sv_e, double *sv_f, double *sv,
+                              hipStream_t s);
+// strided 2D copy of doubles (device to device), and 2D scaling by 2^e
+hipError_t launch_copy2d(int m, int n, const double *src, long long lds, double *dst, long long ldd,
+                         hipStream_t s);
+hipError_t launch_split(int m, int n, const double *Z, long long ldz, double *Xr, double *Xi,
+                        long long ldx, hipStream_t s);
+hipError_t launch_merge(int m, int n, const double *Xr, const double *Xi, long long ldx, double *Z,
+                        long long ldz, hipStream_t s);
+
+} // namespace jsvd

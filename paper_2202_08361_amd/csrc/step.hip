@@ -1,0 +1,696 @@
+// step.hip -- one parallel step of the one-sided Jacobi SVD on gfx950
+// (arXiv:2202.08361, Alg. zvjsvd phases: column norms, scaled dot-products
+// (Alg. zdpscl), convergence test (Alg. cvg) and scaled Gram matrices
+// (Alg. Gram), batched 2x2 EVD (Listing 1), rotations (Alg. zjrot), with the
+// step-start rescaling check of Sect. 3.2), plus initialisation, end-of-sweep
+// bookkeeping and finalisation (Sect. 4.2.1).
+//
+// Mapping: one workgroup of W threads per pivot pair; the column pair lives
+// in registers between the phases, so a step reads and writes each column of
+// G and V once (16 c n (m + n) bytes per fully transformed step, c = 1 real,
+// 2 complex).  The step index, M~ and the counters live on the device; the
+// last workgroup to finish a step (an atomic ticket) folds the per-step
+// results into them, so consecutive steps need no host involvement and can
+// be captured in a graph.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "evd2_core.hpp"
+#include "kernels.hpp"
+#include "pair.hpp"
+
+namespace jsvd {
+
+// Alg. Gram (eqs. sGramEF, efpq, F): A'' = 2^{sA} [[|g_p|/|g_q|, .], [a21', |g_q|/|g_p|]]
+__device__ __forceinline__ void gram(double zr, double zi, int e1, double f1, int e2, double f2,
+                                     double *a11, double *a22, double *a21r, double *a21i)
+{
+    double f12 = f1 / f2;
+    double f21 = f2 / f1;
+    int e12 = e1 - e2, e21 = e2 - e1;
+    const int g12 = getexp(f12), g21 = getexp(f21);
+    e12 += g12;
+    f12 = scal2(f12, -g12);
+    e21 += g21;
+    f21 = scal2(f21, -g21);
+    const int sA = min(1023 - max(e12, e21), 0);
+    e12 += sA;
+    e21 += sA;
+    *a11 = scal2(f12, e12);
+    *a22 = scal2(f21, e21);
+    *a21r = scal2(zr, sA);
+    *a21i = scal2(zi, sA);
+}
+
+template <int W>
+struct StepSmem {
+    double norm[4 * W];
+    double dot[2 * W];
+    double mx1[2 * (W / 64)];
+    double mx2[W / 64];
+};
+
+template <bool CPLX, int W, int R>
+__global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
+{
+    __shared__ StepSmem<W> sm;
+    using LS = LaneShape<W, R>;
+    constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
+    DevScalars *sc = d.sc;
+    if (*(volatile int *)&sc->stop) return;
+    const long long k = *(volatile long long *)&sc->k;
+    const double Mt = bits2d(*(volatile unsigned long long *)&sc->Mt_bits);
+    const int m = d.m, n = d.n;
+    const int t = threadIdx.x;
+    int p, q;
+    const bool valid = rr_pair(n, k, (int)blockIdx.x, &p, &q);
+
+    // step-start rescaling check, Sect. 3.2: s_(k) < 0 => scale by 2^{s_[k]}
+    const int sr = (CPLX ? 1020 : 1022) - getexp(Mt);
+    const bool rescale = sr < 0;
+    const int sp = rescale ? (d.lgbound - getexp(Mt) - 1) : 0;
+
+    double *const Gpr = d.Gr + (size_t)p * d.ldg;
+    double *const Gqr = d.Gr + (size_t)q * d.ldg;
+    double *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
+    double *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
+
+    bool transform = false;
+    int pbit = 0;
+    double Mblk = 0.0;
+
+    if (!valid) {
+        // the column sitting out this step (odd n): only the rescaling applies
+        if (rescale) {
+            for (int i = t; i < m; i += W) {
+                Gpr[i] = scal2(Gpr[i], sp);
+                if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
+            }
+        }
+    } else {
+        double xr[2][R], xi[2][R];
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + W * j;
+            const bool in = i < m;
+            xr[0][j] = in ? Gpr[i] : 0.0;
+            xr[1][j] = in ? Gqr[i] : 0.0;
+            if (CPLX) {
+                xi[0][j] = in ? Gpi[i] : 0.0;
+                xi[1][j] = in ? Gqi[i] : 0.0;
+            }
+        }
+        if (rescale) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    xr[c][j] = scal2(xr[c][j], sp);
+                    if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
+                }
+        }
+
+        // ---- column norms (e, f) of both columns
+        double mx[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                mx[c] = fmax(mx[c], fabs(xr[c][j]));
+                if (CPLX) mx[c] = fmax(mx[c], fabs(xi[c][j]));
+            }
+        group_max<W, 2>(mx, sm.mx1);
+        const bool zp_ = mx[0] == 0.0, zq_ = mx[1] == 0.0;
+        const int Ep = zp_ ? 0 : getexp(mx[0]);
+        const int Eq = zq_ ? 0 : getexp(mx[1]);
+
+        constexpr int NQ = CPLX ? 4 : 2;
+        double acc[NQ][NL];
+#pragma unroll
+        for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+            for (int v = 0; v < NL; ++v) acc[qq][v] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int v = 0; v < NL; ++v) {
+                const int j = ch * V + v;
+                if (j < R) {
+                    const double ypr = scal2(xr[0][j], -Ep), yqr = scal2(xr[1][j], -Eq);
+                    acc[0][v] = fma(ypr, ypr, acc[0][v]);
+                    acc[1][v] = fma(yqr, yqr, acc[1][v]);
+                    if (CPLX) {
+                        const double ypi = scal2(xi[0][j], -Ep), yqi = scal2(xi[1][j], -Eq);
+                        acc[2][v] = fma(ypi, ypi, acc[2][v]);
+                        acc[3][v] = fma(yqi, yqi, acc[3][v]);
+                    }
+                }
+            }
+        double s[NQ];
+#pragma unroll
+        for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
+        group_tree_sum<W, NQ>(s, sm.norm);
+        Norm np_ = norm_from_sums(Ep, s[0], CPLX ? s[2] : 0.0, CPLX);
+        Norm nq_ = norm_from_sums(Eq, s[1], CPLX ? s[3] : 0.0, CPLX);
+        np_.zero = zp_;
+        nq_.zero = zq_;
+
+        double c = 1.0, C = 0.0, S = 0.0;
+        if (zp_ || zq_) {
+            // a zero column is never rotated; it goes after the other one
+            pbit = (zp_ && !zq_) ? 1 : 0;
+        } else {
+            // ---- scaled dot-product a21' = g_q^* g_p / (|g_q| |g_p|), Alg. zdpscl
+            double dr[NL], di[NL];
+#pragma unroll
+            for (int v = 0; v < NL; ++v) {
+                dr[v] = 0.0;
+                di[v] = 0.0;
+            }
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+                for (int v = 0; v < NL; ++v) {
+                    const int j = ch * V + v;
+                    if (j < R) {
+                        const double gqr = scal2(xr[1][j], -nq_.e), gpr = scal2(xr[0][j], -np_.e);
+                        if (CPLX) {
+                            const double gqi = scal2(xi[1][j], -nq_.e), gpi = scal2(xi[0][j], -np_.e);
+                            dr[v] = fma(gqr, gpr, dr[v]);
+                            di[v] = fma(gqr, gpi, di[v]);
+                            dr[v] = fma(gqi, gpi, dr[v]);
+                            di[v] = fma(-gqi, gpr, di[v]);
+                        } else {
+                            dr[v] = fma(gqr, gpr, dr[v]);
+                        }
+                    }
+                }
+            constexpr int ND = CPLX ? 2 : 1;
+            double h[ND];
+            h[0] = thread_tree<V>(dr);
+            if (CPLX) h[ND - 1] = thread_tree<V>(di);
+            group_tree_sum<W, ND>(h, sm.dot);
+            const double dd = nq_.f * np_.f;
+            const double zr = h[0] / dd;
+            const double zi = CPLX ? h[ND - 1] / dd : 0.0;
+            // ---- convergence test (Alg. cvg) and the scaled Gram matrix (Alg. Gram)
+            const double az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
+            transform = d.ups <= az;
+            double a11, a22, a21r, a21i;
+            gram(zr, zi, np_.e, np_.f, nq_.e, nq_.f, &a11, &a22, &a21r, &a21i);
+            // ---- the 2x2 EVD (Listing 1); lambda' only decide the permutation
+            const Evd2Out o = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
+            c = o.c;
+            C = o.C;
+            S = o.S;
+            pbit = o.p;
+        }
+        if (d.nosort) pbit = 0;
+
+        // ---- rotation (Alg. zjrot, eq. transf with the complex fma of eq. zfma) or swap
+        double *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
+        double *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
+        double *const Dp_i = pbit ? Gqi : Gpi;
+        double *const Dq_i = pbit ? Gpi : Gqi;
+        if (transform) {
+            double Mx = 0.0;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + W * j;
+                const double pr = xr[0][j], qr = xr[1][j];
+                double npr, nqr, npi = 0.0, nqi = 0.0;
+                if (CPLX) {
+                    const double pi = xi[0][j], qi = xi[1][j];
+                    npr = fma(qr, C, fma(-qi, S, pr)) * c;
+                    npi = fma(qr, S, fma(qi, C, pi)) * c;
+                    nqr = fma(pr, -C, fma(-pi, S, qr)) * c;
+                    nqi = fma(pr, S, fma(pi, -C, qi)) * c;
+                    Mx = fmax(Mx, fmax(fabs(npr), fabs(npi)));
+                    Mx = fmax(Mx, fmax(fabs(nqr), fabs(nqi)));
+                } else {
+                    npr = fma(qr, C, pr) * c;
+                    nqr = fma(pr, -C, qr) * c;
+                    Mx = fmax(Mx, fmax(fabs(npr), fabs(nqr)));
+                }
+                if (i < m) {
+                    Dp_r[i] = npr;
+                    Dq_r[i] = nqr;
+                    if (CPLX) {
+                        Dp_i[i] = npi;
+                        Dq_i[i] = nqi;
+                    }
+                }
+            }
+            // the same transformation of the V column pair (n rows)
+            double *const Vpr = d.Vr + (size_t)p * d.ldv;
+            double *const Vqr = d.Vr + (size_t)q * d.ldv;
+            double *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
+            double *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
+            double *const Ep_r = pbit ? Vqr : Vpr;
+            double *const Eq_r = pbit ? Vpr : Vqr;
+            double *const Ep_i = pbit ? Vqi : Vpi;
+            double *const Eq_i = pbit ? Vpi : Vqi;
+            double vr[2][R], vi[2][R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + W * j;
+                const bool in = i < n;
+                vr[0][j] = in ? Vpr[i] : 0.0;
+                vr[1][j] = in ? Vqr[i] : 0.0;
+                if (CPLX) {
+                    vi[0][j] = in ? Vpi[i] : 0.0;
+                    vi[1][j] = in ? Vqi[i] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + W * j;
+                if (i < n) {
+                    const double pr = vr[0][j], qr = vr[1][j];
+                    if (CPLX) {
+                        const double pi = vi[0][j], qi = vi[1][j];
+                        Ep_r[i] = fma(qr, C, fma(-qi, S, pr)) * c;
+                        Ep_i[i] = fma(qr, S, fma(qi, C, pi)) * c;
+                        Eq_r[i] = fma(pr, -C, fma(-pi, S, qr)) * c;
+                        Eq_i[i] = fma(pr, S, fma(pi, -C, qi)) * c;
+                    } else {
+                        Ep_r[i] = fma(qr, C, pr) * c;
+                        Eq_r[i] = fma(pr, -C, qr) * c;
+                    }
+                }
+            }
+            double mm[1] = {Mx};
+            group_max<W, 1>(mm, sm.mx2);
+            Mblk = mm[0];
+        } else if (pbit || rescale) {
+            // swap (or only store the rescaled columns)
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + W * j;
+                if (i < m) {
+                    Dp_r[i] = xr[0][j];
+                    Dq_r[i] = xr[1][j];
+                    if (CPLX) {
+                        Dp_i[i] = xi[0][j];
+                        Dq_i[i] = xi[1][j];
+                    }
+                }
+            }
+            if (pbit) {
+                double *const Vpr = d.Vr + (size_t)p * d.ldv;
+                double *const Vqr = d.Vr + (size_t)q * d.ldv;
+                for (int i = t; i < n; i += W) {
+                    const double a = Vpr[i], b = Vqr[i];
+                    Vpr[i] = b;
+                    Vqr[i] = a;
+                    if (CPLX) {
+                        double *const Vpi = d.Vi + (size_t)p * d.ldv;
+                        double *const Vqi = d.Vi + (size_t)q * d.ldv;
+                        const double ai = Vpi[i], bi = Vqi[i];
+                        Vpi[i] = bi;
+                        Vqi[i] = ai;
+                    }
+                }
+            }
+        }
+        if (t == 0) {
+            const double ep = np_.zero ? -INFINITY : (double)np_.e;
+            const double eq = nq_.zero ? -INFINITY : (double)nq_.e;
+            const int dp = pbit ? q : p, dq = pbit ? p : q;
+            d.e[dp] = ep;
+            d.f[dp] = np_.zero ? 1.0 : np_.f;
+            d.e[dq] = eq;
+            d.f[dq] = nq_.zero ? 1.0 : nq_.f;
+        }
+    }
+
+    // ---- end of step: the last workgroup folds the step into the scalars
+    if constexpr (W > 64) __syncthreads();
+    if (t == 0) {
+        if (transform) {
+            atomicMax(&sc->M_step, d2bits(Mblk));
+            atomicAdd(&sc->t_step, 1ull);
+        } else if (pbit) {
+            atomicAdd(&sc->sw_step, 1ull);
+        }
+        __threadfence();
+        const unsigned long long prev = atomicAdd(&sc->done, 1ull);
+        if (prev == (unsigned long long)gridDim.x - 1) {
+            __threadfence();
+            const double Mt2 = rescale ? scal2(Mt, sp) : Mt;
+            const double Ms = bits2d(atomicExch(&sc->M_step, 0ull));
+            sc->Mt_bits = d2bits(fmax(Mt2, Ms));
+            const long long tt = (long long)atomicExch(&sc->t_step, 0ull);
+            const long long sw = (long long)atomicExch(&sc->sw_step, 0ull);
+            sc->T += tt;
+            sc->SW += sw;
+            sc->last_t = tt;
+            if (rescale) {
+                sc->s += sp;
+                sc->rescaled += 1;
+            }
+            atomicExch(&sc->done, 0ull);
+            sc->k = k + 1;
+            __threadfence();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dispatch over (complex, W, R)
+template <bool CPLX, int W, int R>
+static hipError_t launch_step_t(const SvdDesc &d, hipStream_t s)
+{
+    const int N = d.n + (d.n & 1);
+    const unsigned blocks = (unsigned)(N / 2);
+    hipLaunchKernelGGL((step_kernel<CPLX, W, R>), dim3(blocks), dim3(W), 0, s, d);
+    return hipGetLastError();
+}
+
+template <bool CPLX, int W>
+static hipError_t launch_step_w(const SvdDesc &d, hipStream_t s)
+{
+    const int R = (d.m + W - 1) / W;
+    if (R <= 1) return launch_step_t<CPLX, W, 1>(d, s);
+    if (R <= 2) return launch_step_t<CPLX, W, 2>(d, s);
+    if (R <= 4) return launch_step_t<CPLX, W, 4>(d, s);
+    if (R <= 8) return launch_step_t<CPLX, W, 8>(d, s);
+    if constexpr (!CPLX && W == 1024)
+        if (R <= 16) return launch_step_t<CPLX, W, 16>(d, s);
+    return hipErrorInvalidValue;
+}
+
+// largest supported m for a workgroup size
+int step_max_rows(int cplx, int W) { return W * ((!cplx && W == 1024) ? 16 : 8); }
+
+int step_auto_threads(int m, int n)
+{
+    (void)n;
+    if (m <= 256) return 64;
+    if (m <= 1024) return 256;
+    if (m <= 2048) return 512;
+    return 1024;
+}
+
+hipError_t launch_step(const SvdDesc &d, int threads, hipStream_t s)
+{
+    if (threads <= 0) threads = step_auto_threads(d.m, d.n);
+    if (d.m > step_max_rows(d.cplx, threads)) return hipErrorInvalidValue;
+    if (d.cplx) {
+        switch (threads) {
+        case 64: return launch_step_w<true, 64>(d, s);
+        case 128: return launch_step_w<true, 128>(d, s);
+        case 256: return launch_step_w<true, 256>(d, s);
+        case 512: return launch_step_w<true, 512>(d, s);
+        case 1024: return launch_step_w<true, 1024>(d, s);
+        }
+    } else {
+        switch (threads) {
+        case 64: return launch_step_w<false, 64>(d, s);
+        case 128: return launch_step_w<false, 128>(d, s);
+        case 256: return launch_step_w<false, 256>(d, s);
+        case 512: return launch_step_w<false, 512>(d, s);
+        case 1024: return launch_step_w<false, 1024>(d, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// end of sweep: convergence when a whole sweep neither transformed nor swapped
+__global__ void sweep_end_kernel(DevScalars *sc)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (sc->stop) return;
+    sc->sweeps += 1;
+    if (sc->T == 0 && sc->SW == 0) {
+        sc->converged = 1;
+        sc->stop = 1;
+    } else {
+        sc->C += 1;
+        if (sc->C >= sc->max_sweeps) sc->stop = 1;
+    }
+    sc->T = 0;
+    sc->SW = 0;
+}
+
+hipError_t launch_sweep_end(const SvdDesc &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(64), 0, s, d.sc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// initialisation
+template <bool CPLX>
+__global__ __launch_bounds__(256) void maxabs_kernel(int m, int n, const double *Ar, const double *Ai,
+                                                     long long lda, unsigned long long *out)
+{
+    // M~_0 = max |component|, NaN turned into Inf (Sect. 3.2)
+    double mx = 0.0;
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+        mx = fmax(mx, fmin(fabs(Ar[(size_t)j * lda + i]), INFINITY));
+        if (CPLX) mx = fmax(mx, fmin(fabs(Ai[(size_t)j * lda + i]), INFINITY));
+    }
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) atomicMax(out, d2bits(mx));
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void init_scale_kernel(SvdDesc d, const double *Ar, const double *Ai,
+                                                         long long lda, int s0)
+{
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < d.m; i += gridDim.x * 256) {
+        d.Gr[(size_t)j * d.ldg + i] = scal2(Ar[(size_t)j * lda + i], s0);
+        if (CPLX) d.Gi[(size_t)j * d.ldg + i] = scal2(Ai[(size_t)j * lda + i], s0);
+    }
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < d.n; i += gridDim.x * 256) {
+        d.Vr[(size_t)j * d.ldv + i] = (i == j) ? 1.0 : 0.0;
+        if (CPLX) d.Vi[(size_t)j * d.ldv + i] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.e[j] = -INFINITY;
+        d.f[j] = 1.0;
+    }
+}
+
+static unsigned row_blocks(int m) { return (unsigned)min(64, (m + 255) / 256); }
+
+hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
+                         unsigned long long *maxbits, hipStream_t s)
+{
+    // reduces M~_0 into *maxbits, which the caller has zeroed
+    dim3 grid(row_blocks(d.m), d.n);
+    if (d.cplx)
+        hipLaunchKernelGGL(maxabs_kernel<true>, grid, dim3(256), 0, s, d.m, d.n, Ar, Ai, lda, maxbits);
+    else
+        hipLaunchKernelGGL(maxabs_kernel<false>, grid, dim3(256), 0, s, d.m, d.n, Ar, Ai, lda, maxbits);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda, int s0,
+                             hipStream_t s)
+{
+    dim3 grid(row_blocks(d.m), d.n);
+    if (d.cplx)
+        hipLaunchKernelGGL(init_scale_kernel<true>, grid, dim3(256), 0, s, d, Ar, Ai, lda, s0);
+    else
+        hipLaunchKernelGGL(init_scale_kernel<false>, grid, dim3(256), 0, s, d, Ar, Ai, lda, s0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// finalisation
+// Column norms of all columns (1024 threads per column, the canonical order:
+// thread t = lane t, rows t, t+1024, ... in order).
+template <bool CPLX>
+__global__ __launch_bounds__(1024) void colnorm_kernel(SvdDesc d, double *e_out, double *f_out)
+{
+    __shared__ double red[2 * 1024];
+    __shared__ double mx1[16];
+    const int j = blockIdx.x, t = threadIdx.x;
+    const double *xr = d.Gr + (size_t)j * d.ldg;
+    const double *xi = CPLX ? d.Gi + (size_t)j * d.ldg : nullptr;
+    double mx[1] = {0.0};
+    for (int i = t; i < d.m; i += 1024) {
+        mx[0] = fmax(mx[0], fabs(xr[i]));
+        if (CPLX) mx[0] = fmax(mx[0], fabs(xi[i]));
+    }
+    group_max<1024, 1>(mx, mx1);
+    if (mx[0] == 0.0) {
+        if (t == 0) {
+            e_out[j] = -INFINITY;
+            f_out[j] = 1.0;
+        }
+        return;
+    }
+    const int E = getexp(mx[0]);
+    double s[2] = {0.0, 0.0};
+    for (int i = t; i < d.m; i += 1024) {
+        const double yr = scal2(xr[i], -E);
+        s[0] = fma(yr, yr, s[0]);
+        if (CPLX) {
+            const double yi = scal2(xi[i], -E);
+            s[1] = fma(yi, yi, s[1]);
+        }
+    }
+    group_tree_sum<1024, 2>(s, red);
+    const Norm nn = norm_from_sums(E, s[0], s[1], CPLX);
+    if (t == 0) {
+        e_out[j] = (double)nn.e;
+        f_out[j] = nn.f;
+    }
+}
+
+// stable descending rank of sigma_j = (e_j, f_j)
+__global__ __launch_bounds__(256) void rank_kernel(int n, const double *e, const double *f, int *rank)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const double ej = e[j], fj = f[j];
+    int r = 0;
+    for (int i = 0; i < n; ++i) {
+        const double ei = e[i], fi = f[i];
+        const bool gt = ei > ej || (ei == ej && fi > fj);
+        const bool eqb = (ei == ej && fi == fj) && i < j;
+        r += (gt || eqb) ? 1 : 0;
+    }
+    rank[j] = r;
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void final_write_kernel(SvdDesc d, const double *e, const double *f,
+                                                          const int *rank, double *Ur, double *Ui,
+                                                          long long ldu, double *Vr, double *Vi,
+                                                          long long ldv, double *sv_e, double *sv_f,
+                                                          double *sv, int s)
+{
+    const int j = blockIdx.x;
+    const int dst = rank[j];
+    const double ej = e[j], fj = f[j];
+    const bool zero = isinf(ej);
+    const int E = zero ? 0 : (int)ej;
+    for (int i = threadIdx.x; i < d.m; i += 256) {
+        const double xr = d.Gr[(size_t)j * d.ldg + i];
+        Ur[(size_t)dst * ldu + i] = zero ? 0.0 : scal2(xr, -E) / fj;
+        if (CPLX) {
+            const double xi = d.Gi[(size_t)j * d.ldg + i];
+            Ui[(size_t)dst * ldu + i] = zero ? 0.0 : scal2(xi, -E) / fj;
+        }
+    }
+    for (int i = threadIdx.x; i < d.n; i += 256) {
+        Vr[(size_t)dst * ldv + i] = d.Vr[(size_t)j * d.ldv + i];
+        if (CPLX) Vi[(size_t)dst * ldv + i] = d.Vi[(size_t)j * d.ldv + i];
+    }
+    if (threadIdx.x == 0) {
+        sv_e[dst] = zero ? -INFINITY : ej - (double)s;
+        sv_f[dst] = fj;
+        if (sv) sv[dst] = zero ? 0.0 : scal2(fj, E - s);
+    }
+}
+
+hipError_t launch_final_write(const SvdDesc &d, const int *rank, double *Ur, double *Ui, long long ldu,
+                              double *Vr, double *Vi, long long ldv, double *sv_e, double *sv_f,
+                              double *sv, int s, hipStream_t st)
+{
+    if (d.cplx)
+        hipLaunchKernelGGL(final_write_kernel<true>, dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur, Ui,
+                           ldu, Vr, Vi, ldv, sv_e, sv_f, sv, s);
+    else
+        hipLaunchKernelGGL(final_write_kernel<false>, dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur,
+                           Ui, ldu, Vr, Vi, ldv, sv_e, sv_f, sv, s);
+    return hipGetLastError();
+}
+
+// non-converged exit: current column norms, backscaled, in column order
+__global__ __launch_bounds__(256) void colnorm_out_kernel(int n, const double *e, const double *f, int s,
+                                                          double *sv_e, double *sv_f, double *sv)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= n) return;
+    const bool zero = isinf(e[j]);
+    sv_e[j] = zero ? -INFINITY : e[j] - (double)s;
+    sv_f[j] = f[j];
+    if (sv) sv[j] = zero ? 0.0 : scal2(f[j], (int)e[j] - s);
+}
+
+hipError_t launch_colnorms_raw(const SvdDesc &d, hipStream_t st)
+{
+    if (d.cplx)
+        hipLaunchKernelGGL(colnorm_kernel<true>, dim3(d.n), dim3(1024), 0, st, d, d.e, d.f);
+    else
+        hipLaunchKernelGGL(colnorm_kernel<false>, dim3(d.n), dim3(1024), 0, st, d, d.e, d.f);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorm_out(const SvdDesc &d, int s, double *sv_e, double *sv_f, double *sv, hipStream_t st)
+{
+    hipLaunchKernelGGL(colnorm_out_kernel, dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, s, sv_e,
+                       sv_f, sv);
+    return hipGetLastError();
+}
+
+hipError_t launch_rank(const SvdDesc &d, int *rank, hipStream_t st)
+{
+    hipLaunchKernelGGL(rank_kernel, dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, rank);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// layout helpers (Sect. SM5)
+__global__ __launch_bounds__(256) void copy2d_kernel(int m, const double *src, long long lds, double *dst,
+                                                     long long ldd)
+{
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256)
+        dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
+}
+
+hipError_t launch_copy2d(int m, int n, const double *src, long long lds, double *dst, long long ldd,
+                         hipStream_t s)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy2d_kernel, dim3(row_blocks(m), n), dim3(256), 0, s, m, src, lds, dst, ldd);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void split_kernel(int m, const double *Z, long long ldz, double *Xr,
+                                                    double *Xi, long long ldx)
+{
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+        Xr[(size_t)j * ldx + i] = Z[(size_t)j * ldz + 2 * (size_t)i];
+        Xi[(size_t)j * ldx + i] = Z[(size_t)j * ldz + 2 * (size_t)i + 1];
+    }
+}
+
+__global__ __launch_bounds__(256) void merge_kernel(int m, const double *Xr, const double *Xi, long long ldx,
+                                                    double *Z, long long ldz)
+{
+    const int j = blockIdx.y;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+        Z[(size_t)j * ldz + 2 * (size_t)i] = Xr[(size_t)j * ldx + i];
+        Z[(size_t)j * ldz + 2 * (size_t)i + 1] = Xi[(size_t)j * ldx + i];
+    }
+}
+
+hipError_t launch_split(int m, int n, const double *Z, long long ldz, double *Xr, double *Xi, long long ldx,
+                        hipStream_t s)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(split_kernel, dim3(row_blocks(m), n), dim3(256), 0, s, m, Z, ldz, Xr, Xi, ldx);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge(int m, int n, const double *Xr, const double *Xi, long long ldx, double *Z,
+                        long long ldz, hipStream_t s)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(merge_kernel, dim3(row_blocks(m), n), dim3(256), 0, s, m, Xr, Xi, ldx, Z, ldz);
+    return hipGetLastError();
+}
+
+} // namespace jsvd

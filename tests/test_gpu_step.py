@@ -1,0 +1,188 @@
+"""GPU parity of the Jacobi step (jsvd_step) and the whole SVD (jsvd_gesvj)
+against the CPU oracle, and run-to-run / launch-shape reproducibility.
+
+The GPU evaluates every sum in the same canonical order as the oracle (the
+paper's lane-wise accumulation with 1024 lanes and a halving-tree reduce),
+and every other operation is a single IEEE-754 operation in the paper's
+order, so the bar is bit-for-bit equality of G, V, the column norms, M~, s
+and the transformation count after every step, and of U, V and sigma at the
+end of the SVD.
+"""
+import numpy as np
+import pytest
+
+from paper_2202_08361_amd import inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def J():
+    import paper_2202_08361_amd as jsvd
+    return jsvd
+
+
+def _bits_equal(a, b):
+    a = np.ascontiguousarray(a)
+    b = np.ascontiguousarray(b)
+    return a.shape == b.shape and np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+def _host(t):
+    return None if t is None else t.cpu().numpy()
+
+
+def _check_state(ost, sv, tag):
+    assert _bits_equal(_host(sv["G_re"]), ost.Gr), tag + " G_re"
+    if ost.cplx:
+        assert _bits_equal(_host(sv["G_im"]), ost.Gi), tag + " G_im"
+    assert _bits_equal(_host(sv["V_re"]), ost.Vr), tag + " V_re"
+    if ost.cplx:
+        assert _bits_equal(_host(sv["V_im"]), ost.Vi), tag + " V_im"
+    assert sv["s"] == ost.s and sv["Mt"] == ost.Mt, tag + " scalars"
+    assert sv["k"] == ost.k, tag + " k"
+
+
+def _pair_run(ora, m, n, cplx, steps, seed, threads=0, check_every=1):
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 300 + seed)
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    ost = ora.State(Ar, Ai)
+    assert ost.init() == ora.OK
+    st = J().State(m, n, cplx)
+    if threads:
+        st.set_launch(threads)
+    dAr = J().to_device_fortran(Ar)
+    dAi = J().to_device_fortran(Ai) if cplx else None
+    assert st.load(dAr, dAi) == 0
+    _check_state(ost, st.save(), f"load m={m} n={n}")
+    for k in range(steps):
+        ost.step()
+        st.step()
+        if (k + 1) % check_every == 0 or k == steps - 1:
+            sv = st.save()
+            _check_state(ost, sv, f"step {k} m={m} n={n} cplx={cplx} W={threads}")
+            q = st.query()
+            assert q["last_t"] == ost.last_t
+            assert _bits_equal(_host(sv["e"]), ost.e) and _bits_equal(_host(sv["f"]), ost.f)
+    return st
+
+
+@pytest.mark.parametrize("m,n,cplx", [
+    (16, 16, False), (70, 24, True), (100, 37, False), (256, 256, False), (97, 33, True),
+    (1500, 64, False), (2100, 20, True), (4096, 8, False), (5000, 12, True), (9000, 6, False),
+])
+def test_step_bitwise(ora, m, n, cplx):
+    """Every step, every bit: G, V, (e, f), M~, s and t against the oracle
+    (chains of the 1024-lane accumulation from m > 1024, ragged tails, odd n)."""
+    K = ora.rr_steps(n)
+    _pair_run(ora, m, n, cplx, steps=min(2 * K + 1, 40), seed=m + n, check_every=1 if n <= 64 else 7)
+
+
+@pytest.mark.parametrize("cplx,m", [(False, 500), (True, 500), (False, 3000), (True, 3000)])
+def test_launch_shapes_identical(ora, cplx, m):
+    """Threads per pair 64 ... 1024 give the same bits (and the oracle's);
+    every workgroup size that can hold m rows in registers is tried."""
+    n = 18
+    ref = None
+    for W in [w for w in (64, 128, 256, 512, 1024) if w * 8 >= m]:
+        st = _pair_run(ora, m, n, cplx, steps=5, seed=7, threads=W, check_every=5)
+        sv = st.save()
+        cur = (_host(sv["G_re"]), _host(sv["V_re"]))
+        if ref is not None:
+            assert _bits_equal(cur[0], ref[0]) and _bits_equal(cur[1], ref[1])
+        ref = cur
+
+
+def test_rescale_path(ora):
+    """Sect. 3.2: a state whose M~ exceeds nu/2 is downscaled at the step start."""
+    m, n = 40, 10
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 400)
+    Ar, _ = inputs.random_columns(m, n, g)
+    ost = ora.State(Ar)
+    ost.init()
+    ost.Mt = np.finfo(np.float64).max * 0.75
+    ost.Vr[:] = np.eye(n)
+    st = J().State(m, n)
+    st.restore(J().to_device_fortran(ost.Gr), None, J().to_device_fortran(ost.Vr), None, ost.s, ost.Mt, 0)
+    ost.step()
+    st.step()
+    q = st.query()
+    assert q["rescaled"] == 1 and ost.rescaled == 1
+    _check_state(ost, st.save(), "rescale")
+
+
+def _gesvj_both(ora, Ar, Ai, flags=0):
+    ro = ora.gesvj(Ar, Ai, flags=flags)
+    dAr = J().to_device_fortran(Ar)
+    dAi = J().to_device_fortran(Ai) if Ai is not None else None
+    rg = J().gesvj(dAr, dAi, flags=flags)
+    torch.cuda.synchronize()
+    return ro, rg
+
+
+def _check_svd(ro, rg):
+    assert rg["status"] == ro["status"] and rg["sweeps"] == ro["sweeps"]
+    assert _bits_equal(_host(rg["sv_e"]), ro["sv_e"]) and _bits_equal(_host(rg["sv_f"]), ro["sv_f"])
+    assert _bits_equal(_host(rg["U_re"]), ro["U_re"]) and _bits_equal(_host(rg["V_re"]), ro["V_re"])
+    if ro["U_im"] is not None:
+        assert _bits_equal(_host(rg["U_im"]), ro["U_im"]) and _bits_equal(_host(rg["V_im"]), ro["V_im"])
+
+
+@pytest.mark.parametrize("flags", [0, 1])
+def test_gesvj_plain_real_256(ora, flags):
+    """The plain real 256 x 256 workload (sigma log-spaced in [1e-6, 1]): the
+    whole SVD bit-for-bit, and max relative sigma error <= 1e-10."""
+    A, sig = inputs.plain_real_256()
+    ro, rg = _gesvj_both(ora, A, None, flags)
+    _check_svd(ro, rg)
+    sv = rg["sv"].cpu().numpy()
+    assert np.max(np.abs(sv - sig) / sig) <= 1e-10
+
+
+@pytest.mark.parametrize("m,n,cplx,kappa", [(60, 33, True, 1e4), (129, 128, False, 1e8), (7, 1, False, 1.0),
+                                              (2, 2, True, 10.0), (1100, 40, False, 1e3)])
+def test_gesvj_bitwise_shapes(ora, m, n, cplx, kappa):
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 500 + m)
+    sig = inputs.sigma_logspace(n, 1.0 / kappa)
+    Ar, Ai = inputs.svd_matrix(m, n, sig, g, cplx=cplx)
+    ro, rg = _gesvj_both(ora, Ar, Ai)
+    _check_svd(ro, rg)
+
+
+def test_gesvj_failures(ora):
+    A = np.ones((5, 3), order="F")
+    B = A.copy(order="F")
+    B[2, 1] = np.nan
+    assert J().gesvj(J().to_device_fortran(B))["status"] == J().ENONFINITE
+    B[2, 1] = np.inf
+    assert J().gesvj(J().to_device_fortran(B))["status"] == J().ENONFINITE
+    assert J().gesvj(J().to_device_fortran(np.zeros((5, 3))))["status"] == J().EZERO
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 600)
+    Ar, _ = inputs.random_columns(30, 20, g)
+    ro = ora.gesvj(Ar, max_sweeps=1)
+    rg = J().gesvj(J().to_device_fortran(Ar), max_sweeps=1)
+    assert rg["status"] == ro["status"] == J().NOT_CONVERGED and rg["sweeps"] == 1
+    assert _bits_equal(_host(rg["U_re"]), ro["U_re"]) and _bits_equal(_host(rg["sv_f"]), ro["sv_f"])
+
+
+def test_run_to_run(ora):
+    """Ten runs of the same SVD give identical bits."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 700)
+    sig = inputs.sigma_logspace(96, 1e-6)
+    Ar, Ai = inputs.svd_matrix(130, 96, sig, g, cplx=True)
+    first = None
+    for _ in range(10):
+        r = J().gesvj(J().to_device_fortran(Ar), J().to_device_fortran(Ai))
+        cur = [_host(r[k]) for k in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f")]
+        if first is None:
+            first = cur
+        else:
+            assert all(_bits_equal(a, b) for a, b in zip(cur, first))
+
+
+@pytest.mark.parametrize("m,n,cplx", [(8192, 2048, False), (4096, 4096, True)])
+def test_step_full_size(ora, m, n, cplx):
+    """One step of the large workloads (real 8192 x 2048, complex 4096 x 4096)
+    on Gaussian columns: G, V, norms and scalars bit-for-bit."""
+    _pair_run(ora, m, n, cplx, steps=1, seed=1)
