@@ -50,6 +50,8 @@ struct jsvd_state_s {
     hipGraphExec_t graph;
     hipGraph_t graph_def;
     int graph_threads;
+    int ncu;           // compute units of the device (persistent grid size)
+    PairParam *prm;    // per-pair rotations of the last step (pipelined path)
 };
 
 extern "C" int jsvd_version(void) { return (JSVD_VERSION_MAJOR << 16) | JSVD_VERSION_MINOR; }
@@ -109,7 +111,8 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
         delete st;
         return JSVD_EDEVICE;
     }
-    const long long ldg = round_up(m, 64), ldv = round_up(n, 64);
+    // columns of the working G are whole 1 KiB chunks (the LDS prefetch moves 128 doubles at a time)
+    const long long ldg = round_up(m, 128), ldv = round_up(n, 64);
     const int c = st->cplx ? 2 : 1;
     size_t off = 0;
     const size_t oG = off; off = align_up(off + sizeof(double) * (size_t)ldg * n * c);
@@ -119,6 +122,10 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     const size_t oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
     const size_t oS = off; off = align_up(off + sizeof(DevScalars));
     const size_t oM = off; off = align_up(off + sizeof(unsigned long long));
+    const size_t oP = off; off = align_up(off + sizeof(PairParam) * (size_t)((n + 1) / 2 + 1));
+    if (hipDeviceGetAttribute(&st->ncu, hipDeviceAttributeMultiprocessorCount, st->device) != hipSuccess ||
+        st->ncu <= 0)
+        st->ncu = 256;
     if (hipMalloc(&st->mem, off) != hipSuccess) {
         delete st;
         return JSVD_ENOMEM;
@@ -149,6 +156,11 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     d.ups = ldexp(sqrt((double)m), -53);
     st->rank = (int *)(b + oR);
     st->maxbits = (unsigned long long *)(b + oM);
+    st->prm = (PairParam *)(b + oP);
+    if (gstep_prepare(m, st->cplx) != hipSuccess) {
+        jsvd_state_destroy(st);
+        return JSVD_EDEVICE;
+    }
     *out = st;
     return JSVD_OK;
 }
@@ -240,10 +252,19 @@ static int state_threads(jsvd_state st)
     return st->threads ? st->threads : step_auto_threads(st->m, st->n);
 }
 
+// one step: the pipelined pair of kernels when the columns fit its tile and no
+// workgroup size is forced, otherwise the one-workgroup-per-pair kernel
+static hipError_t launch_one_step(jsvd_state st, hipStream_t s)
+{
+    if (st->threads == 0 && gstep_rows(st->m, st->cplx) != 0 && st->m > 256)
+        return launch_gstep(st->d, st->prm, st->ncu, s);
+    return launch_step(st->d, state_threads(st), s);
+}
+
 extern "C" int jsvd_step(jsvd_state st, void *stream)
 {
     if (!st) return JSVD_EINVAL;
-    HIPCHK(launch_step(st->d, state_threads(st), (hipStream_t)stream));
+    HIPCHK(launch_one_step(st, (hipStream_t)stream));
     return JSVD_OK;
 }
 
@@ -251,7 +272,7 @@ static int sweep_steps(int n) { return n + (n & 1) - 1; }
 
 static int build_graph(jsvd_state st)
 {
-    const int thr = state_threads(st);
+    const int thr = st->threads;
     if (st->graph && st->graph_threads == thr) return JSVD_OK;
     if (st->graph) {
         (void)hipGraphExecDestroy(st->graph);
@@ -270,7 +291,7 @@ static int build_graph(jsvd_state st)
     }
     const int K = sweep_steps(st->n);
     for (int k = 0; k < K && rc == JSVD_OK; ++k)
-        if (launch_step(st->d, thr, cs) != hipSuccess) rc = JSVD_EDEVICE;
+        if (launch_one_step(st, cs) != hipSuccess) rc = JSVD_EDEVICE;
     if (rc == JSVD_OK && launch_sweep_end(st->d, cs) != hipSuccess) rc = JSVD_EDEVICE;
     hipGraph_t g = nullptr;
     if (hipStreamEndCapture(cs, &g) != hipSuccess) rc = JSVD_EDEVICE;

@@ -47,6 +47,20 @@ struct SvdDesc {
     double ups;            // fl(sqrt(m)) 2^-53
 };
 
+// rotation of one pivot pair, produced by the pipelined G kernel for the V kernel
+struct PairParam {
+    double c, C, S;   // cos phi, e^{i alpha} tan phi
+    int p, q;         // the pair
+    int flag;         // bit 0: rotate, bit 1: swap the columns (permutation P)
+    int pad;
+};
+
+// pipelined step for large columns (gstep.hip): rows per thread for m
+// (0 = not supported) and the launch of the G kernel followed by the V kernel
+int gstep_rows(int m, int cplx);
+hipError_t launch_gstep(const SvdDesc &d, PairParam *prm, int grid, hipStream_t s);
+hipError_t gstep_prepare(int m, int cplx);
+
 // initialisation: M~_0 into *maxbits (zeroed by the caller), then
 // G <- 2^{s_0} A copied into the workspace and V <- I
 hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
