@@ -171,7 +171,7 @@ int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
  * sv_e/sv_f (n) receive sigma_j = 2^{sv_e[j]} sv_f[j] in descending order;
  * sv (n, may be NULL) the same as doubles.  *sweeps receives the number of
  * sweeps that transformed something (C in Alg. zvjsvd).  max_sweeps <= 0
- * selects 64.  Synchronises.  On JSVD_NOT_CONVERGED G holds the scaled
+ * selects 128.  Synchronises.  On JSVD_NOT_CONVERGED G holds the scaled
  * iteration matrix and sv_e/sv_f its current (unsorted) column norms.
  * ---------------------------------------------------------------------- */
 int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg,
@@ -204,7 +204,7 @@ typedef struct jsvd_server_s *jsvd_server;
 typedef struct {
     size_t hbm_budget_bytes; /* device bytes the server may allocate for work state */
     int max_slots;           /* requests on the device at once */
-    int max_sweeps;          /* per request (<= 0: 64) */
+    int max_sweeps;          /* per request (<= 0: 128) */
     int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
 } jsvd_serve_config;
 

@@ -222,7 +222,7 @@ class State:
         return sv_e, sv_f
 
 
-def gesvj(G_re, G_im=None, max_sweeps=64, flags=0):
+def gesvj(G_re, G_im=None, max_sweeps=128, flags=0):
     """The whole SVD.  Returns dict(status, U_re, U_im, V_re, V_im, sv_e, sv_f, sweeps, steps)."""
     m, n = G_re.shape
     Gr = _np.array(G_re, dtype=_np.float64, order="F", copy=True)

@@ -162,8 +162,10 @@ def _mat(t, m, n, name):
         raise ValueError(f"{name}: expected a float64 CUDA tensor")
     if tuple(t.shape) != (m, n):
         raise ValueError(f"{name}: expected shape {(m, n)}, got {tuple(t.shape)}")
-    if n > 1 and t.stride(0) != 1:
+    if m > 1 and t.stride(0) != 1:
         raise ValueError(f"{name}: must be column-major (stride(0) == 1); use fortran_empty")
+    if n > 1 and t.stride(1) < m:
+        raise ValueError(f"{name}: leading dimension {t.stride(1)} < {m}")
     return t.stride(1) if n > 1 else max(m, 1)
 
 
@@ -285,7 +287,7 @@ class State:
         return dict(U_re=U_re, U_im=U_im, V_re=V_re, V_im=V_im, sv_e=sv_e, sv_f=sv_f, sv=sv)
 
 
-def gesvj(G_re, G_im=None, max_sweeps=64, flags=0, overwrite=False, stream=None):
+def gesvj(G_re, G_im=None, max_sweeps=0, flags=0, overwrite=False, stream=None):
     """The whole SVD G = U diag(sigma) V^*.  Returns a dict with U (in place of a
     copy of G unless overwrite), V, sv_e, sv_f, sv, status, sweeps."""
     torch = _torch()
@@ -314,7 +316,7 @@ def gesvj(G_re, G_im=None, max_sweeps=64, flags=0, overwrite=False, stream=None)
                 sv_f=sv_f, sv=sv)
 
 
-def gesvj_batched(mats, max_sweeps=64, flags=0, stream=None):
+def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None):
     """Many SVDs in one call.  ``mats`` is a list of (G_re, G_im|None) column-major
     device tensors, overwritten by U.  Returns a list of dicts like :func:`gesvj`."""
     torch = _torch()
@@ -355,7 +357,7 @@ def gesvj_batched(mats, max_sweeps=64, flags=0, stream=None):
 class Server:
     """Continuous-batching SVD server (jsvd_serve_*)."""
 
-    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_sweeps=64, max_queue=0):
+    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_sweeps=0, max_queue=0):
         cfg = ServeConfig(hbm_budget_bytes, max_slots, max_sweeps, max_queue)
         h = _ct.c_void_p()
         _check(lib().jsvd_serve_create(_ct.byref(cfg), _ct.byref(h)), "jsvd_serve_create")

@@ -1,0 +1,35 @@
+// batch.hpp -- the persistent batched SVD launch (batched.hip) as used by the
+// C ABI and the server.  Internal; not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace jsvd {
+
+// One matrix of a batched launch (device pointers; status/sweeps are outputs).
+struct BatchItem {
+    int m, n, cplx, R;
+    double *Gr, *Gi;
+    long long ldg;
+    double *Vr, *Vi;
+    long long ldv;
+    double *sv_e, *sv_f;
+    int lgbound;
+    double ups;
+    int status, sweeps;
+};
+
+// rows-per-lane class of the batched kernel for an m x n matrix (0: too large)
+int batch_rows(int m, int n, int cplx);
+BatchItem make_batch_item(int m, int n, int cplx, double *Gr, double *Gi, size_t ldg, double *Vr, double *Vi,
+                          size_t ldv, double *sv_e, double *sv_f);
+
+struct BatchLaunch;
+// Enqueue one persistent launch over the items (all batch_rows() != 0) and the
+// copy of their outcomes to pinned host memory; nullptr on failure.
+BatchLaunch *batch_launch(const BatchItem *items, int count, int max_sweeps, unsigned flags, hipStream_t s);
+// The outcomes (valid once the stream has passed the launch), then release.
+const BatchItem *batch_results(const BatchLaunch *bl);
+void batch_release(BatchLaunch *bl);
+
+} // namespace jsvd

@@ -13,6 +13,7 @@
 
 #include "../../include/jsvd.h"
 #include "kernels.hpp"
+#include "state.hpp"
 
 using namespace jsvd;
 
@@ -34,25 +35,6 @@ static int lg_bound(int m, int cplx)
 }
 
 static long long round_up(long long x, long long a) { return (x + a - 1) / a * a; }
-
-struct jsvd_state_s {
-    int m, n, cplx;
-    int threads;       // forced workgroup size (0 = auto)
-    int nosort;
-    int max_sweeps;
-    int device;
-    void *mem;         // the single device allocation
-    SvdDesc d;
-    int *rank;
-    unsigned long long *maxbits;
-    DevScalars *host;  // pinned staging for the scalars
-    unsigned long long *host_bits;
-    hipGraphExec_t graph;
-    hipGraph_t graph_def;
-    int graph_threads;
-    int ncu;           // compute units of the device (persistent grid size)
-    PairParam *prm;    // per-pair rotations of the last step (pipelined path)
-};
 
 extern "C" int jsvd_version(void) { return (JSVD_VERSION_MAJOR << 16) | JSVD_VERSION_MINOR; }
 
@@ -94,6 +76,33 @@ extern "C" int jsvd_evd2_batched(size_t r, const double *a11, const double *a22,
 // state
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+struct StateLayout {
+    long long ldg, ldv;
+    size_t oG, oV, oE, oF, oR, oS, oM, oP, total;
+};
+
+static StateLayout state_layout(int m, int n, int cplx)
+{
+    StateLayout L;
+    // columns of the working G are whole 1 KiB chunks (the LDS prefetch moves 128 doubles at a time)
+    L.ldg = round_up(m, 128);
+    L.ldv = round_up(n, 64);
+    const int c = cplx ? 2 : 1;
+    size_t off = 0;
+    L.oG = off; off = align_up(off + sizeof(double) * (size_t)L.ldg * n * c);
+    L.oV = off; off = align_up(off + sizeof(double) * (size_t)L.ldv * n * c);
+    L.oE = off; off = align_up(off + sizeof(double) * (size_t)n);
+    L.oF = off; off = align_up(off + sizeof(double) * (size_t)n);
+    L.oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
+    L.oS = off; off = align_up(off + sizeof(DevScalars));
+    L.oM = off; off = align_up(off + sizeof(unsigned long long));
+    L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)((n + 1) / 2 + 1));
+    L.total = off;
+    return L;
+}
+
+size_t jsvd::state_bytes(int m, int n, int cplx) { return state_layout(m, n, cplx).total; }
+
 extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
 {
     if (!out) return JSVD_EINVAL;
@@ -106,57 +115,46 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     st->m = m;
     st->n = n;
     st->cplx = is_complex != 0;
-    st->max_sweeps = 64;
+    st->max_sweeps = 128;
     if (hipGetDevice(&st->device) != hipSuccess) {
         delete st;
         return JSVD_EDEVICE;
     }
-    // columns of the working G are whole 1 KiB chunks (the LDS prefetch moves 128 doubles at a time)
-    const long long ldg = round_up(m, 128), ldv = round_up(n, 64);
-    const int c = st->cplx ? 2 : 1;
-    size_t off = 0;
-    const size_t oG = off; off = align_up(off + sizeof(double) * (size_t)ldg * n * c);
-    const size_t oV = off; off = align_up(off + sizeof(double) * (size_t)ldv * n * c);
-    const size_t oE = off; off = align_up(off + sizeof(double) * (size_t)n);
-    const size_t oF = off; off = align_up(off + sizeof(double) * (size_t)n);
-    const size_t oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
-    const size_t oS = off; off = align_up(off + sizeof(DevScalars));
-    const size_t oM = off; off = align_up(off + sizeof(unsigned long long));
-    const size_t oP = off; off = align_up(off + sizeof(PairParam) * (size_t)((n + 1) / 2 + 1));
     if (hipDeviceGetAttribute(&st->ncu, hipDeviceAttributeMultiprocessorCount, st->device) != hipSuccess ||
         st->ncu <= 0)
         st->ncu = 256;
-    if (hipMalloc(&st->mem, off) != hipSuccess) {
+    const StateLayout L = state_layout(m, n, st->cplx);
+    if (hipMalloc(&st->mem, L.total) != hipSuccess) {
         delete st;
         return JSVD_ENOMEM;
     }
+    st->mem_bytes = L.total;
     if (hipHostMalloc((void **)&st->host, 512, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(st->mem);
         delete st;
         return JSVD_ENOMEM;
     }
     static_assert(sizeof(DevScalars) <= 256, "staging layout");
-    st->host_bits = (unsigned long long *)((char *)st->host + 256);
     char *b = (char *)st->mem;
     SvdDesc &d = st->d;
     d.m = m;
     d.n = n;
     d.cplx = st->cplx;
     d.nosort = 0;
-    d.Gr = (double *)(b + oG);
-    d.Gi = st->cplx ? d.Gr + (size_t)ldg * n : nullptr;
-    d.ldg = ldg;
-    d.Vr = (double *)(b + oV);
-    d.Vi = st->cplx ? d.Vr + (size_t)ldv * n : nullptr;
-    d.ldv = ldv;
-    d.e = (double *)(b + oE);
-    d.f = (double *)(b + oF);
-    d.sc = (DevScalars *)(b + oS);
+    d.Gr = (double *)(b + L.oG);
+    d.Gi = st->cplx ? d.Gr + (size_t)L.ldg * n : nullptr;
+    d.ldg = L.ldg;
+    d.Vr = (double *)(b + L.oV);
+    d.Vi = st->cplx ? d.Vr + (size_t)L.ldv * n : nullptr;
+    d.ldv = L.ldv;
+    d.e = (double *)(b + L.oE);
+    d.f = (double *)(b + L.oF);
+    d.sc = (DevScalars *)(b + L.oS);
     d.lgbound = lg_bound(m, st->cplx);
     d.ups = ldexp(sqrt((double)m), -53);
-    st->rank = (int *)(b + oR);
-    st->maxbits = (unsigned long long *)(b + oM);
-    st->prm = (PairParam *)(b + oP);
+    st->rank = (int *)(b + L.oR);
+    st->maxbits = (unsigned long long *)(b + L.oM);
+    st->prm = (PairParam *)(b + L.oP);
     if (gstep_prepare(m, st->cplx) != hipSuccess) {
         jsvd_state_destroy(st);
         return JSVD_EDEVICE;
@@ -204,37 +202,26 @@ static double bitsd(unsigned long long b)
     return x;
 }
 
-extern "C" int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, void *stream)
+// The load is stream-ordered: M~_0 is reduced on the device, s_0 and the
+// status are derived there too, and nothing waits for the host.
+int jsvd::state_load_async(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, hipStream_t s)
 {
     if (!st || !G_re || ldg < (size_t)st->m) return JSVD_EINVAL;
     if ((G_im != nullptr) != (st->cplx != 0)) return JSVD_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    HIPCHK(hipMemsetAsync(st->maxbits, 0, sizeof(unsigned long long), s));
+    HIPCHK(launch_zero_u64(st->maxbits, s));
     HIPCHK(launch_maxabs(st->d, G_re, G_im, (long long)ldg, st->maxbits, s));
-    HIPCHK(hipMemcpyAsync(st->host_bits, st->maxbits, 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    const double M0 = bitsd(*st->host_bits);
-    DevScalars h;
-    memset(&h, 0, sizeof(h));
-    h.max_sweeps = st->max_sweeps;
-    if (!(M0 <= 1.79769313486231570815e308)) {
-        h.status = JSVD_ENONFINITE;
-        h.stop = 1;
-        push_scalars(st, h, s);
-        return JSVD_ENONFINITE;
-    }
-    if (M0 == 0.0) {
-        h.status = JSVD_EZERO;
-        h.stop = 1;
-        push_scalars(st, h, s);
-        return JSVD_EZERO;
-    }
-    // s_0 = s_[0] (eq. skn), G_1 = 2^{s_0} G, M~_1 = 2^{s_0} M~_0, V_1 = I
-    const int s0 = st->d.lgbound - ilogb(M0) - 1;
-    HIPCHK(launch_init_scale(st->d, G_re, G_im, (long long)ldg, s0, s));
-    h.Mt_bits = dbits(ldexp(M0, s0));
-    h.s = s0;
-    return push_scalars(st, h, s);
+    HIPCHK(launch_init_scale(st->d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, void *stream)
+{
+    hipStream_t s = (hipStream_t)stream;
+    int rc = state_load_async(st, G_re, G_im, ldg, s);
+    if (rc != JSVD_OK) return rc;
+    rc = pull_scalars(st, s);
+    if (rc != JSVD_OK) return rc;
+    return st->host->status;
 }
 
 extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
@@ -318,6 +305,37 @@ extern "C" int jsvd_sweep(jsvd_state st, void *stream)
     return JSVD_OK;
 }
 
+int jsvd::state_sweep_async(jsvd_state st, hipStream_t s)
+{
+    const int rc = jsvd_sweep(st, s);
+    if (rc != JSVD_OK) return rc;
+    HIPCHK(hipMemcpyAsync(st->host, st->d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    return JSVD_OK;
+}
+
+const DevScalars &jsvd::state_staged(jsvd_state st) { return *st->host; }
+
+int jsvd::state_finish_async(jsvd_state st, bool converged, double *U_re, double *U_im, size_t ldu,
+                             double *V_re, double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv,
+                             hipStream_t s)
+{
+    const SvdDesc &d = st->d;
+    if (converged) {
+        HIPCHK(launch_colnorms_raw(d, s));
+        HIPCHK(launch_rank(d, st->rank, s));
+        HIPCHK(launch_final_write(d, st->rank, U_re, U_im, (long long)ldu, V_re, V_im, (long long)ldv, sv_e, sv_f,
+                                  sv, s));
+        return JSVD_OK;
+    }
+    HIPCHK(launch_copy2d(d.m, d.n, d.Gr, d.ldg, U_re, (long long)ldu, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, d.Gi, d.ldg, U_im, (long long)ldu, s));
+    HIPCHK(launch_copy2d(d.n, d.n, d.Vr, d.ldv, V_re, (long long)ldv, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, d.Vi, d.ldv, V_im, (long long)ldv, s));
+    HIPCHK(launch_colnorms_raw(d, s));
+    HIPCHK(launch_colnorm_out(d, sv_e, sv_f, sv, s));
+    return JSVD_OK;
+}
+
 extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
 {
     if (!st || !out) return JSVD_EINVAL;
@@ -394,15 +412,7 @@ extern "C" int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, si
     if (!st || !U_re || !V_re || !sv_e || !sv_f || ldu < (size_t)st->m || ldv < (size_t)st->n)
         return JSVD_EINVAL;
     if (st->cplx && (!U_im || !V_im)) return JSVD_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    int rc = pull_scalars(st, s);
-    if (rc != JSVD_OK) return rc;
-    const int sexp = st->host->s;
-    HIPCHK(launch_colnorms_raw(st->d, s));
-    HIPCHK(launch_rank(st->d, st->rank, s));
-    HIPCHK(launch_final_write(st->d, st->rank, U_re, U_im, (long long)ldu, V_re, V_im, (long long)ldv, sv_e,
-                              sv_f, sv, sexp, s));
-    return JSVD_OK;
+    return state_finish_async(st, true, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, (hipStream_t)stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -410,37 +420,22 @@ extern "C" int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, si
 static int gesvj_on_state(jsvd_state st, double *G_re, double *G_im, size_t ldg, double *V_re, double *V_im,
                           size_t ldv, double *sv_e, double *sv_f, double *sv, int *sweeps, hipStream_t s)
 {
-    int rc = jsvd_state_load(st, G_re, G_im, ldg, s);
-    if (rc != JSVD_OK) {
-        if (sweeps) *sweeps = 0;
-        return rc;
-    }
+    int rc = state_load_async(st, G_re, G_im, ldg, s);
+    if (rc != JSVD_OK) return rc;
     // one graph-launched sweep at a time; the device decides convergence
     for (;;) {
-        rc = jsvd_sweep(st, s);
+        rc = state_sweep_async(st, s);
         if (rc != JSVD_OK) return rc;
-        rc = pull_scalars(st, s);
-        if (rc != JSVD_OK) return rc;
+        HIPCHK(hipStreamSynchronize(s));
         if (st->host->stop) break;
     }
     const DevScalars h = *st->host;
     if (sweeps) *sweeps = (int)h.C;
-    if (h.converged) {
-        rc = jsvd_state_finalize(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, s);
-        if (rc != JSVD_OK) return rc;
-        HIPCHK(hipStreamSynchronize(s));
-        return JSVD_OK;
-    }
-    // not converged: the scaled iteration matrix, V, and the current norms
-    const SvdDesc &d = st->d;
-    HIPCHK(launch_copy2d(d.m, d.n, d.Gr, d.ldg, G_re, (long long)ldg, s));
-    if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, d.Gi, d.ldg, G_im, (long long)ldg, s));
-    HIPCHK(launch_copy2d(d.n, d.n, d.Vr, d.ldv, V_re, (long long)ldv, s));
-    if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, d.Vi, d.ldv, V_im, (long long)ldv, s));
-    HIPCHK(launch_colnorms_raw(d, s));
-    HIPCHK(launch_colnorm_out(d, h.s, sv_e, sv_f, sv, s));
+    if (h.status != 0) return h.status;
+    rc = state_finish_async(st, h.converged != 0, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, s);
+    if (rc != JSVD_OK) return rc;
     HIPCHK(hipStreamSynchronize(s));
-    return JSVD_NOT_CONVERGED;
+    return h.converged ? JSVD_OK : JSVD_NOT_CONVERGED;
 }
 
 extern "C" int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg, double *V_re, double *V_im,
@@ -454,7 +449,7 @@ extern "C" int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg, 
     jsvd_state st = nullptr;
     int rc = jsvd_state_create(m, n, G_im != nullptr, &st);
     if (rc != JSVD_OK) return rc;
-    st->max_sweeps = max_sweeps > 0 ? max_sweeps : 64;
+    st->max_sweeps = max_sweeps > 0 ? max_sweeps : 128;
     st->d.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
     rc = gesvj_on_state(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, sweeps, (hipStream_t)stream);
     jsvd_state_destroy(st);

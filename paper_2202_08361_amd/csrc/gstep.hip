@@ -31,27 +31,6 @@ namespace jsvd {
 
 constexpr int kGW = 256;   // threads per workgroup of the pipelined kernel
 
-// Alg. Gram (eqs. sGramEF, efpq, F)
-__device__ __forceinline__ void gram2(double zr, double zi, int e1, double f1, int e2, double f2,
-                                      double *a11, double *a22, double *a21r, double *a21i)
-{
-    double f12 = f1 / f2;
-    double f21 = f2 / f1;
-    int e12 = e1 - e2, e21 = e2 - e1;
-    const int g12 = getexp(f12), g21 = getexp(f21);
-    e12 += g12;
-    f12 = scal2(f12, -g12);
-    e21 += g21;
-    f21 = scal2(f21, -g21);
-    const int sA = min(1023 - max(e12, e21), 0);
-    e12 += sA;
-    e21 += sA;
-    *a11 = scal2(f12, e12);
-    *a22 = scal2(f21, e21);
-    *a21r = scal2(zr, sA);
-    *a21i = scal2(zi, sA);
-}
-
 typedef __attribute__((address_space(3))) void lds_void;
 
 // Issue the asynchronous copy of the column pair (p, q) into the LDS tile.
@@ -75,14 +54,12 @@ template <bool CPLX, int R>
 __global__ __launch_bounds__(kGW, 1) void gstep_kernel(SvdDesc d, PairParam *prm)
 {
     constexpr int W = kGW;
-    using LS = LaneShape<W, R>;
-    constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
     constexpr int NCOL = CPLX ? 4 : 2;
     extern __shared__ double smem[];
     double *const tile = smem;                               // NCOL * ldt doubles
     constexpr int ldt = R * W;
-    double *const red = smem + NCOL * ldt;                   // 4 * W doubles
-    double *const mxs = red + 4 * W;                         // 8 doubles
+    double *const red = smem + NCOL * ldt;                   // 6 * W doubles
+    double *const mxs = red + 6 * W;                         // 12 doubles
 
     DevScalars *sc = d.sc;
     if (*(volatile int *)&sc->stop) return;
@@ -159,101 +136,10 @@ __global__ __launch_bounds__(kGW, 1) void gstep_kernel(SvdDesc d, PairParam *prm
                     if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
                 }
         }
-        // ---- column norms
-        double mx[2] = {0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                mx[c] = fmax(mx[c], fabs(xr[c][j]));
-                if (CPLX) mx[c] = fmax(mx[c], fabs(xi[c][j]));
-            }
-        group_max<W, 2>(mx, mxs);
-        const bool zp_ = mx[0] == 0.0, zq_ = mx[1] == 0.0;
-        const int Ep = zp_ ? 0 : getexp(mx[0]);
-        const int Eq = zq_ ? 0 : getexp(mx[1]);
-        constexpr int NQ = CPLX ? 4 : 2;
-        double acc[NQ][NL];
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq)
-#pragma unroll
-            for (int v = 0; v < NL; ++v) acc[qq][v] = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-#pragma unroll
-            for (int v = 0; v < NL; ++v) {
-                const int j = ch * V + v;
-                if (j < R) {
-                    const double ypr = scal2(xr[0][j], -Ep), yqr = scal2(xr[1][j], -Eq);
-                    acc[0][v] = fma(ypr, ypr, acc[0][v]);
-                    acc[1][v] = fma(yqr, yqr, acc[1][v]);
-                    if (CPLX) {
-                        const double ypi = scal2(xi[0][j], -Ep), yqi = scal2(xi[1][j], -Eq);
-                        acc[2][v] = fma(ypi, ypi, acc[2][v]);
-                        acc[3][v] = fma(yqi, yqi, acc[3][v]);
-                    }
-                }
-            }
-        double s[NQ];
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
-        __syncthreads();   // red[] of the previous pair has been consumed
-        group_tree_sum<W, NQ>(s, red);
-        Norm np_ = norm_from_sums(Ep, s[0], CPLX ? s[2] : 0.0, CPLX);
-        Norm nq_ = norm_from_sums(Eq, s[1], CPLX ? s[3] : 0.0, CPLX);
-        np_.zero = zp_;
-        nq_.zero = zq_;
-
-        bool transform = false;
-        int pbit = 0;
-        double c = 1.0, C = 0.0, S = 0.0;
-        if (zp_ || zq_) {
-            pbit = (zp_ && !zq_) ? 1 : 0;
-        } else {
-            double dr[NL], di[NL];
-#pragma unroll
-            for (int v = 0; v < NL; ++v) {
-                dr[v] = 0.0;
-                di[v] = 0.0;
-            }
-#pragma unroll
-            for (int ch = 0; ch < CH; ++ch)
-#pragma unroll
-                for (int v = 0; v < NL; ++v) {
-                    const int j = ch * V + v;
-                    if (j < R) {
-                        const double gqr = scal2(xr[1][j], -nq_.e), gpr = scal2(xr[0][j], -np_.e);
-                        if (CPLX) {
-                            const double gqi = scal2(xi[1][j], -nq_.e), gpi = scal2(xi[0][j], -np_.e);
-                            dr[v] = fma(gqr, gpr, dr[v]);
-                            di[v] = fma(gqr, gpi, di[v]);
-                            dr[v] = fma(gqi, gpi, dr[v]);
-                            di[v] = fma(-gqi, gpr, di[v]);
-                        } else {
-                            dr[v] = fma(gqr, gpr, dr[v]);
-                        }
-                    }
-                }
-            constexpr int ND = CPLX ? 2 : 1;
-            double h[ND];
-            h[0] = thread_tree<V>(dr);
-            if (CPLX) h[ND - 1] = thread_tree<V>(di);
-            __syncthreads();   // red[] consumed by the norm round
-            group_tree_sum<W, ND>(h, red);
-            const double dd = nq_.f * np_.f;
-            const double zr = h[0] / dd;
-            const double zi = CPLX ? h[ND - 1] / dd : 0.0;
-            const double az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
-            transform = d.ups <= az;
-            double a11, a22, a21r, a21i;
-            gram2(zr, zi, np_.e, np_.f, nq_.e, nq_.f, &a11, &a22, &a21r, &a21i);
-            const Evd2Out o = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
-            c = o.c;
-            C = o.C;
-            S = o.S;
-            pbit = o.p;
-        }
-        if (d.nosort) pbit = 0;
+        const PairDecision dc = pair_core<CPLX, W, R>(xr, xi, d.ups, d.nosort, red, red + 4 * W, mxs);
+        const bool transform = dc.transform;
+        const int pbit = dc.pbit;
+        const Norm np_ = dc.np, nq_ = dc.nq;
 
         double *const Gpr = d.Gr + (size_t)p * d.ldg;
         double *const Gqr = d.Gr + (size_t)q * d.ldg;
@@ -264,40 +150,25 @@ __global__ __launch_bounds__(kGW, 1) void gstep_kernel(SvdDesc d, PairParam *prm
         double *const Dp_i = pbit ? Gqi : Gpi;
         double *const Dq_i = pbit ? Gpi : Gqi;
         if (transform) {
-            double Mx = 0.0;
+            const double Mx = rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
-                const double pr = xr[0][j], qr = xr[1][j];
-                double npr, nqr, npi = 0.0, nqi = 0.0;
-                if (CPLX) {
-                    const double pi = xi[0][j], qi = xi[1][j];
-                    npr = fma(qr, C, fma(-qi, S, pr)) * c;
-                    npi = fma(qr, S, fma(qi, C, pi)) * c;
-                    nqr = fma(pr, -C, fma(-pi, S, qr)) * c;
-                    nqi = fma(pr, S, fma(pi, -C, qi)) * c;
-                    Mx = fmax(Mx, fmax(fabs(npr), fabs(npi)));
-                    Mx = fmax(Mx, fmax(fabs(nqr), fabs(nqi)));
-                } else {
-                    npr = fma(qr, C, pr) * c;
-                    nqr = fma(pr, -C, qr) * c;
-                    Mx = fmax(Mx, fmax(fabs(npr), fabs(nqr)));
-                }
                 if (i < m) {
-                    Dp_r[i] = npr;
-                    Dq_r[i] = nqr;
+                    Dp_r[i] = xr[0][j];
+                    Dq_r[i] = xr[1][j];
                     if (CPLX) {
-                        Dp_i[i] = npi;
-                        Dq_i[i] = nqi;
+                        Dp_i[i] = xi[0][j];
+                        Dq_i[i] = xi[1][j];
                     }
                 }
             }
             Mblk = fmax(Mblk, Mx);   // thread-local; reduced once at the end
             ++tcount;
             pp.flag = 1 | (pbit ? 2 : 0);
-            pp.c = c;
-            pp.C = C;
-            pp.S = S;
+            pp.c = dc.c;
+            pp.C = dc.C;
+            pp.S = dc.S;
         } else if (pbit || rescale) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
@@ -330,7 +201,7 @@ __global__ __launch_bounds__(kGW, 1) void gstep_kernel(SvdDesc d, PairParam *prm
     // workgroup folds the step into the device scalars
     __syncthreads();
     double mm[1] = {Mblk};
-    group_max<W, 1>(mm, mxs + 4);
+    group_max<W, 1>(mm, mxs + 8);
     if (t == 0) {
         if (tcount) {
             atomicMax(&sc->M_step, d2bits(mm[0]));
@@ -421,7 +292,7 @@ template <bool CPLX, int R>
 static size_t gstep_shm()
 {
     constexpr int NCOL = CPLX ? 4 : 2;
-    return sizeof(double) * ((size_t)NCOL * R * kGW + 4 * kGW + 8);
+    return sizeof(double) * ((size_t)NCOL * R * kGW + 6 * kGW + 12);
 }
 
 template <bool CPLX, int R>

@@ -65,8 +65,9 @@ hipError_t gstep_prepare(int m, int cplx);
 // G <- 2^{s_0} A copied into the workspace and V <- I
 hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
                          unsigned long long *maxbits, hipStream_t s);
-hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda, int s0,
-                             hipStream_t s);
+hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
+                             const unsigned long long *maxbits, int max_sweeps, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 // one parallel step; threads = 0 picks automatically
 hipError_t launch_step(const SvdDesc &d, int threads, hipStream_t s);
 int step_max_rows(int cplx, int W);
@@ -79,10 +80,9 @@ hipError_t launch_colnorms_raw(const SvdDesc &d, hipStream_t s);
 hipError_t launch_rank(const SvdDesc &d, int *rank, hipStream_t s);
 hipError_t launch_final_write(const SvdDesc &d, const int *rank, double *Ur, double *Ui, long long ldu,
                               double *Vr, double *Vi, long long ldv, double *sv_e, double *sv_f,
-                              double *sv, int s_exp, hipStream_t s);
+                              double *sv, hipStream_t s);
 // non-converged exit: the current norms, backscaled, in column order
-hipError_t launch_colnorm_out(const SvdDesc &d, int s_exp, double *sv_e, double *sv_f, double *sv,
-                              hipStream_t s);
+hipError_t launch_colnorm_out(const SvdDesc &d, double *sv_e, double *sv_f, double *sv, hipStream_t s);
 // strided 2D copy of doubles (device to device), and 2D scaling by 2^e
 hipError_t launch_copy2d(int m, int n, const double *src, long long lds, double *dst, long long ldd,
                          hipStream_t s);

@@ -183,3 +183,171 @@ __device__ __forceinline__ Norm norm_from_sums(int E, double sr, double si, bool
 }
 
 } // namespace jsvd
+
+namespace jsvd {
+
+// Alg. Gram (eqs. sGramEF, efpq, F): A'' = 2^{sA} [[|g_p|/|g_q|, .], [a21', |g_q|/|g_p|]],
+// sA = min(DBL_MAX_EXP - 1 - max(e12, e21), 0)
+__device__ __forceinline__ void gram_scaled(double zr, double zi, int e1, double f1, int e2, double f2,
+                                            double *a11, double *a22, double *a21r, double *a21i)
+{
+    double f12 = f1 / f2;
+    double f21 = f2 / f1;
+    int e12 = e1 - e2, e21 = e2 - e1;
+    const int g12 = getexp(f12), g21 = getexp(f21);
+    e12 += g12;
+    f12 = scal2(f12, -g12);
+    e21 += g21;
+    f21 = scal2(f21, -g21);
+    const int sA = min(1023 - max(e12, e21), 0);
+    e12 += sA;
+    e21 += sA;
+    *a11 = scal2(f12, e12);
+    *a22 = scal2(f21, e21);
+    *a21r = scal2(zr, sA);
+    *a21i = scal2(zi, sA);
+}
+
+// Decision for one pivot pair held in registers by a group of W threads.
+struct PairDecision {
+    Norm np, nq;   // the column norms (e, f) before the transformation
+    bool transform;
+    int pbit;      // the permutation of the EVD (0 when ignored)
+    double c, C, S;
+};
+
+// Norms (Sect. 3.2), scaled dot-product (Alg. zdpscl), convergence test
+// (Alg. cvg), scaled Gram matrix (Alg. Gram) and 2x2 EVD (Listing 1) of the
+// pair (xr/xi[0] = column p, [1] = column q; rows t + W j, zeros beyond m).
+// Scratch: red_norm (4 W doubles), red_dot (2 W doubles), mxs (2 W/64 doubles);
+// unused for W = 64.  Every thread returns the same decision.
+template <bool CPLX, int W, int R>
+__device__ __forceinline__ PairDecision pair_core(const double (&xr)[2][R], const double (&xi)[2][R], double ups,
+                                                  int nosort, double *red_norm, double *red_dot, double *mxs)
+{
+    using LS = LaneShape<W, R>;
+    constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
+    PairDecision o;
+    double mx[2] = {0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            mx[c] = fmax(mx[c], fabs(xr[c][j]));
+            if (CPLX) mx[c] = fmax(mx[c], fabs(xi[c][j]));
+        }
+    group_max<W, 2>(mx, mxs);
+    const bool zp_ = mx[0] == 0.0, zq_ = mx[1] == 0.0;
+    const int Ep = zp_ ? 0 : getexp(mx[0]);
+    const int Eq = zq_ ? 0 : getexp(mx[1]);
+    constexpr int NQ = CPLX ? 4 : 2;
+    double acc[NQ][NL];
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq)
+#pragma unroll
+        for (int v = 0; v < NL; ++v) acc[qq][v] = 0.0;
+#pragma unroll
+    for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+            const int j = ch * V + v;
+            if (j < R) {
+                const double ypr = scal2(xr[0][j], -Ep), yqr = scal2(xr[1][j], -Eq);
+                acc[0][v] = fma(ypr, ypr, acc[0][v]);
+                acc[1][v] = fma(yqr, yqr, acc[1][v]);
+                if (CPLX) {
+                    const double ypi = scal2(xi[0][j], -Ep), yqi = scal2(xi[1][j], -Eq);
+                    acc[2][v] = fma(ypi, ypi, acc[2][v]);
+                    acc[3][v] = fma(yqi, yqi, acc[3][v]);
+                }
+            }
+        }
+    double s[NQ];
+#pragma unroll
+    for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
+    group_tree_sum<W, NQ>(s, red_norm);
+    o.np = norm_from_sums(Ep, s[0], CPLX ? s[2] : 0.0, CPLX);
+    o.nq = norm_from_sums(Eq, s[1], CPLX ? s[3] : 0.0, CPLX);
+    o.np.zero = zp_;
+    o.nq.zero = zq_;
+    o.transform = false;
+    o.c = 1.0;
+    o.C = 0.0;
+    o.S = 0.0;
+    if (zp_ || zq_) {
+        // a zero column is never rotated; it goes after the other one
+        o.pbit = (zp_ && !zq_) ? 1 : 0;
+    } else {
+        double dr[NL], di[NL];
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+            dr[v] = 0.0;
+            di[v] = 0.0;
+        }
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int v = 0; v < NL; ++v) {
+                const int j = ch * V + v;
+                if (j < R) {
+                    const double gqr = scal2(xr[1][j], -o.nq.e), gpr = scal2(xr[0][j], -o.np.e);
+                    if (CPLX) {
+                        const double gqi = scal2(xi[1][j], -o.nq.e), gpi = scal2(xi[0][j], -o.np.e);
+                        dr[v] = fma(gqr, gpr, dr[v]);
+                        di[v] = fma(gqr, gpi, di[v]);
+                        dr[v] = fma(gqi, gpi, dr[v]);
+                        di[v] = fma(-gqi, gpr, di[v]);
+                    } else {
+                        dr[v] = fma(gqr, gpr, dr[v]);
+                    }
+                }
+            }
+        constexpr int ND = CPLX ? 2 : 1;
+        double h[ND];
+        h[0] = thread_tree<V>(dr);
+        if (CPLX) h[ND - 1] = thread_tree<V>(di);
+        group_tree_sum<W, ND>(h, red_dot);
+        const double dd = o.nq.f * o.np.f;
+        const double zr = h[0] / dd;
+        const double zi = CPLX ? h[ND - 1] / dd : 0.0;
+        const double az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
+        o.transform = ups <= az;
+        double a11, a22, a21r, a21i;
+        gram_scaled(zr, zi, o.np.e, o.np.f, o.nq.e, o.nq.f, &a11, &a22, &a21r, &a21i);
+        const Evd2Out e = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
+        o.c = e.c;
+        o.C = e.C;
+        o.S = e.S;
+        o.pbit = e.p;
+    }
+    if (nosort) o.pbit = 0;
+    return o;
+}
+
+// Rotation of a register pair (Alg. zjrot, eq. transf with the complex fma
+// of eq. zfma): xr/xi[0] <- x_p', [1] <- x_q'; returns the thread's max-norm.
+template <bool CPLX, int R>
+__device__ __forceinline__ double rot_regs(double (&xr)[2][R], double (&xi)[2][R], double c, double C, double S)
+{
+    double Mx = 0.0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const double pr = xr[0][j], qr = xr[1][j];
+        if (CPLX) {
+            const double pi = xi[0][j], qi = xi[1][j];
+            xr[0][j] = fma(qr, C, fma(-qi, S, pr)) * c;
+            xi[0][j] = fma(qr, S, fma(qi, C, pi)) * c;
+            xr[1][j] = fma(pr, -C, fma(-pi, S, qr)) * c;
+            xi[1][j] = fma(pr, S, fma(pi, -C, qi)) * c;
+            Mx = fmax(Mx, fmax(fabs(xr[0][j]), fabs(xi[0][j])));
+            Mx = fmax(Mx, fmax(fabs(xr[1][j]), fabs(xi[1][j])));
+        } else {
+            xr[0][j] = fma(qr, C, pr) * c;
+            xr[1][j] = fma(pr, -C, qr) * c;
+            Mx = fmax(Mx, fmax(fabs(xr[0][j]), fabs(xr[1][j])));
+        }
+    }
+    return Mx;
+}
+
+} // namespace jsvd

@@ -1,0 +1,50 @@
+// state.hpp -- the device-resident SVD state behind jsvd_state and the
+// stream-ordered operations the C ABI and the server are built from.
+// Internal; not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/jsvd.h"
+#include "kernels.hpp"
+
+struct jsvd_state_s {
+    int m, n, cplx;
+    int threads;       // forced workgroup size (0 = automatic)
+    int max_sweeps;
+    int device;
+    int ncu;           // compute units (persistent grid size)
+    void *mem;         // the single device allocation
+    size_t mem_bytes;
+    jsvd::SvdDesc d;
+    int *rank;
+    unsigned long long *maxbits;
+    jsvd::PairParam *prm;
+    jsvd::DevScalars *host;  // pinned staging for the scalars
+    hipGraphExec_t graph;
+    hipGraph_t graph_def;
+    int graph_threads;
+};
+
+namespace jsvd {
+
+// Bytes of device memory a state for this problem allocates.
+size_t state_bytes(int m, int n, int cplx);
+
+// Enqueue the load of G (M~_0, s_0, G_1 = 2^{s_0} G, V_1 = I); a non-finite or
+// zero G leaves the state stopped with that status.
+int state_load_async(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, hipStream_t s);
+// Enqueue one sweep (a graph of K steps and the end-of-sweep bookkeeping)
+// followed by the copy of the scalars into the state's pinned staging area.
+int state_sweep_async(jsvd_state st, hipStream_t s);
+// The scalars staged by the last state_sweep_async (valid once the stream
+// has passed that point).
+const DevScalars &state_staged(jsvd_state st);
+// Enqueue the output: for a converged state U = G diag(2^-e)/f and V sorted
+// by descending sigma, else the scaled iteration matrix, V and the current
+// column norms.
+int state_finish_async(jsvd_state st, bool converged, double *U_re, double *U_im, size_t ldu, double *V_re,
+                       double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv, hipStream_t s);
+
+} // namespace jsvd

@@ -22,27 +22,6 @@
 
 namespace jsvd {
 
-// Alg. Gram (eqs. sGramEF, efpq, F): A'' = 2^{sA} [[|g_p|/|g_q|, .], [a21', |g_q|/|g_p|]]
-__device__ __forceinline__ void gram(double zr, double zi, int e1, double f1, int e2, double f2,
-                                     double *a11, double *a22, double *a21r, double *a21i)
-{
-    double f12 = f1 / f2;
-    double f21 = f2 / f1;
-    int e12 = e1 - e2, e21 = e2 - e1;
-    const int g12 = getexp(f12), g21 = getexp(f21);
-    e12 += g12;
-    f12 = scal2(f12, -g12);
-    e21 += g21;
-    f21 = scal2(f21, -g21);
-    const int sA = min(1023 - max(e12, e21), 0);
-    e12 += sA;
-    e21 += sA;
-    *a11 = scal2(f12, e12);
-    *a22 = scal2(f21, e21);
-    *a21r = scal2(zr, sA);
-    *a21i = scal2(zi, sA);
-}
-
 template <int W>
 struct StepSmem {
     double norm[4 * W];
@@ -55,8 +34,6 @@ template <bool CPLX, int W, int R>
 __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
 {
     __shared__ StepSmem<W> sm;
-    using LS = LaneShape<W, R>;
-    constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
     DevScalars *sc = d.sc;
     if (*(volatile int *)&sc->stop) return;
     const long long k = *(volatile long long *)&sc->k;
@@ -111,138 +88,30 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                 }
         }
 
-        // ---- column norms (e, f) of both columns
-        double mx[2] = {0.0, 0.0};
-#pragma unroll
-        for (int j = 0; j < R; ++j)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-                mx[c] = fmax(mx[c], fabs(xr[c][j]));
-                if (CPLX) mx[c] = fmax(mx[c], fabs(xi[c][j]));
-            }
-        group_max<W, 2>(mx, sm.mx1);
-        const bool zp_ = mx[0] == 0.0, zq_ = mx[1] == 0.0;
-        const int Ep = zp_ ? 0 : getexp(mx[0]);
-        const int Eq = zq_ ? 0 : getexp(mx[1]);
+        const PairDecision dc = pair_core<CPLX, W, R>(xr, xi, d.ups, d.nosort, sm.norm, sm.dot, sm.mx1);
+        transform = dc.transform;
+        pbit = dc.pbit;
+        const Norm np_ = dc.np, nq_ = dc.nq;
 
-        constexpr int NQ = CPLX ? 4 : 2;
-        double acc[NQ][NL];
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq)
-#pragma unroll
-            for (int v = 0; v < NL; ++v) acc[qq][v] = 0.0;
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-#pragma unroll
-            for (int v = 0; v < NL; ++v) {
-                const int j = ch * V + v;
-                if (j < R) {
-                    const double ypr = scal2(xr[0][j], -Ep), yqr = scal2(xr[1][j], -Eq);
-                    acc[0][v] = fma(ypr, ypr, acc[0][v]);
-                    acc[1][v] = fma(yqr, yqr, acc[1][v]);
-                    if (CPLX) {
-                        const double ypi = scal2(xi[0][j], -Ep), yqi = scal2(xi[1][j], -Eq);
-                        acc[2][v] = fma(ypi, ypi, acc[2][v]);
-                        acc[3][v] = fma(yqi, yqi, acc[3][v]);
-                    }
-                }
-            }
-        double s[NQ];
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
-        group_tree_sum<W, NQ>(s, sm.norm);
-        Norm np_ = norm_from_sums(Ep, s[0], CPLX ? s[2] : 0.0, CPLX);
-        Norm nq_ = norm_from_sums(Eq, s[1], CPLX ? s[3] : 0.0, CPLX);
-        np_.zero = zp_;
-        nq_.zero = zq_;
-
-        double c = 1.0, C = 0.0, S = 0.0;
-        if (zp_ || zq_) {
-            // a zero column is never rotated; it goes after the other one
-            pbit = (zp_ && !zq_) ? 1 : 0;
-        } else {
-            // ---- scaled dot-product a21' = g_q^* g_p / (|g_q| |g_p|), Alg. zdpscl
-            double dr[NL], di[NL];
-#pragma unroll
-            for (int v = 0; v < NL; ++v) {
-                dr[v] = 0.0;
-                di[v] = 0.0;
-            }
-#pragma unroll
-            for (int ch = 0; ch < CH; ++ch)
-#pragma unroll
-                for (int v = 0; v < NL; ++v) {
-                    const int j = ch * V + v;
-                    if (j < R) {
-                        const double gqr = scal2(xr[1][j], -nq_.e), gpr = scal2(xr[0][j], -np_.e);
-                        if (CPLX) {
-                            const double gqi = scal2(xi[1][j], -nq_.e), gpi = scal2(xi[0][j], -np_.e);
-                            dr[v] = fma(gqr, gpr, dr[v]);
-                            di[v] = fma(gqr, gpi, di[v]);
-                            dr[v] = fma(gqi, gpi, dr[v]);
-                            di[v] = fma(-gqi, gpr, di[v]);
-                        } else {
-                            dr[v] = fma(gqr, gpr, dr[v]);
-                        }
-                    }
-                }
-            constexpr int ND = CPLX ? 2 : 1;
-            double h[ND];
-            h[0] = thread_tree<V>(dr);
-            if (CPLX) h[ND - 1] = thread_tree<V>(di);
-            group_tree_sum<W, ND>(h, sm.dot);
-            const double dd = nq_.f * np_.f;
-            const double zr = h[0] / dd;
-            const double zi = CPLX ? h[ND - 1] / dd : 0.0;
-            // ---- convergence test (Alg. cvg) and the scaled Gram matrix (Alg. Gram)
-            const double az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
-            transform = d.ups <= az;
-            double a11, a22, a21r, a21i;
-            gram(zr, zi, np_.e, np_.f, nq_.e, nq_.f, &a11, &a22, &a21r, &a21i);
-            // ---- the 2x2 EVD (Listing 1); lambda' only decide the permutation
-            const Evd2Out o = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
-            c = o.c;
-            C = o.C;
-            S = o.S;
-            pbit = o.p;
-        }
-        if (d.nosort) pbit = 0;
-
-        // ---- rotation (Alg. zjrot, eq. transf with the complex fma of eq. zfma) or swap
+        // ---- rotation (Alg. zjrot) or swap of the G pair, then of the V pair
         double *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
         double *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
         double *const Dp_i = pbit ? Gqi : Gpi;
         double *const Dq_i = pbit ? Gpi : Gqi;
         if (transform) {
-            double Mx = 0.0;
+            const double Mx = rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
-                const double pr = xr[0][j], qr = xr[1][j];
-                double npr, nqr, npi = 0.0, nqi = 0.0;
-                if (CPLX) {
-                    const double pi = xi[0][j], qi = xi[1][j];
-                    npr = fma(qr, C, fma(-qi, S, pr)) * c;
-                    npi = fma(qr, S, fma(qi, C, pi)) * c;
-                    nqr = fma(pr, -C, fma(-pi, S, qr)) * c;
-                    nqi = fma(pr, S, fma(pi, -C, qi)) * c;
-                    Mx = fmax(Mx, fmax(fabs(npr), fabs(npi)));
-                    Mx = fmax(Mx, fmax(fabs(nqr), fabs(nqi)));
-                } else {
-                    npr = fma(qr, C, pr) * c;
-                    nqr = fma(pr, -C, qr) * c;
-                    Mx = fmax(Mx, fmax(fabs(npr), fabs(nqr)));
-                }
                 if (i < m) {
-                    Dp_r[i] = npr;
-                    Dq_r[i] = nqr;
+                    Dp_r[i] = xr[0][j];
+                    Dq_r[i] = xr[1][j];
                     if (CPLX) {
-                        Dp_i[i] = npi;
-                        Dq_i[i] = nqi;
+                        Dp_i[i] = xi[0][j];
+                        Dq_i[i] = xi[1][j];
                     }
                 }
             }
-            // the same transformation of the V column pair (n rows)
             double *const Vpr = d.Vr + (size_t)p * d.ldv;
             double *const Vqr = d.Vr + (size_t)q * d.ldv;
             double *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
@@ -263,20 +132,16 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                     vi[1][j] = in ? Vqi[i] : 0.0;
                 }
             }
+            (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
                 if (i < n) {
-                    const double pr = vr[0][j], qr = vr[1][j];
+                    Ep_r[i] = vr[0][j];
+                    Eq_r[i] = vr[1][j];
                     if (CPLX) {
-                        const double pi = vi[0][j], qi = vi[1][j];
-                        Ep_r[i] = fma(qr, C, fma(-qi, S, pr)) * c;
-                        Ep_i[i] = fma(qr, S, fma(qi, C, pi)) * c;
-                        Eq_r[i] = fma(pr, -C, fma(-pi, S, qr)) * c;
-                        Eq_i[i] = fma(pr, S, fma(pi, -C, qi)) * c;
-                    } else {
-                        Ep_r[i] = fma(qr, C, pr) * c;
-                        Eq_r[i] = fma(pr, -C, qr) * c;
+                        Ep_i[i] = vi[0][j];
+                        Eq_i[i] = vi[1][j];
                     }
                 }
             }
@@ -458,10 +323,46 @@ __global__ __launch_bounds__(256) void maxabs_kernel(int m, int n, const double 
     if ((threadIdx.x & 63) == 0) atomicMax(out, d2bits(mx));
 }
 
+// s_0 = s_[0] of eq. (skn) from M~_0 (device side, so the load needs no host round trip);
+// a non-finite or zero M~_0 stops the state with its status
+__global__ void init_scalars_kernel(SvdDesc d, const unsigned long long *maxbits, int max_sweeps)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const double M0 = bits2d(*maxbits);
+    DevScalars *sc = d.sc;
+    sc->Mt_bits = 0;
+    sc->M_step = 0;
+    sc->t_step = 0;
+    sc->sw_step = 0;
+    sc->done = 0;
+    sc->k = 0;
+    sc->T = 0;
+    sc->SW = 0;
+    sc->last_t = 0;
+    sc->sweeps = 0;
+    sc->C = 0;
+    sc->rescaled = 0;
+    sc->converged = 0;
+    sc->max_sweeps = max_sweeps;
+    if (!(M0 <= 1.79769313486231570815e308) || M0 == 0.0) {
+        sc->status = (M0 == 0.0) ? -3 : -2;
+        sc->stop = 1;
+        sc->s = 0;
+        return;
+    }
+    const int s0 = d.lgbound - getexp(M0) - 1;
+    sc->status = 0;
+    sc->stop = 0;
+    sc->s = s0;
+    sc->Mt_bits = d2bits(scal2(M0, s0));
+}
+
 template <bool CPLX>
 __global__ __launch_bounds__(256) void init_scale_kernel(SvdDesc d, const double *Ar, const double *Ai,
-                                                         long long lda, int s0)
+                                                         long long lda)
 {
+    if (d.sc->status != 0) return;
+    const int s0 = d.sc->s;
     const int j = blockIdx.y;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < d.m; i += gridDim.x * 256) {
         d.Gr[(size_t)j * d.ldg + i] = scal2(Ar[(size_t)j * lda + i], s0);
@@ -491,14 +392,25 @@ hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, l
     return hipGetLastError();
 }
 
-hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda, int s0,
-                             hipStream_t s)
+hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
+                             const unsigned long long *maxbits, int max_sweeps, hipStream_t s)
 {
+    hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, d, maxbits, max_sweeps);
     dim3 grid(row_blocks(d.m), d.n);
     if (d.cplx)
-        hipLaunchKernelGGL(init_scale_kernel<true>, grid, dim3(256), 0, s, d, Ar, Ai, lda, s0);
+        hipLaunchKernelGGL(init_scale_kernel<true>, grid, dim3(256), 0, s, d, Ar, Ai, lda);
     else
-        hipLaunchKernelGGL(init_scale_kernel<false>, grid, dim3(256), 0, s, d, Ar, Ai, lda, s0);
+        hipLaunchKernelGGL(init_scale_kernel<false>, grid, dim3(256), 0, s, d, Ar, Ai, lda);
+    return hipGetLastError();
+}
+
+// clear a 64-bit word on the stream (a kernel rather than a memset, so the
+// sequence may be captured in a graph)
+__global__ void zero_u64_kernel(unsigned long long *p) { if (threadIdx.x == 0) *p = 0ull; }
+
+hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, p);
     return hipGetLastError();
 }
 
@@ -566,8 +478,9 @@ __global__ __launch_bounds__(256) void final_write_kernel(SvdDesc d, const doubl
                                                           const int *rank, double *Ur, double *Ui,
                                                           long long ldu, double *Vr, double *Vi,
                                                           long long ldv, double *sv_e, double *sv_f,
-                                                          double *sv, int s)
+                                                          double *sv)
 {
+    const int s = d.sc->s;
     const int j = blockIdx.x;
     const int dst = rank[j];
     const double ej = e[j], fj = f[j];
@@ -594,21 +507,23 @@ __global__ __launch_bounds__(256) void final_write_kernel(SvdDesc d, const doubl
 
 hipError_t launch_final_write(const SvdDesc &d, const int *rank, double *Ur, double *Ui, long long ldu,
                               double *Vr, double *Vi, long long ldv, double *sv_e, double *sv_f,
-                              double *sv, int s, hipStream_t st)
+                              double *sv, hipStream_t st)
 {
     if (d.cplx)
         hipLaunchKernelGGL(final_write_kernel<true>, dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur, Ui,
-                           ldu, Vr, Vi, ldv, sv_e, sv_f, sv, s);
+                           ldu, Vr, Vi, ldv, sv_e, sv_f, sv);
     else
         hipLaunchKernelGGL(final_write_kernel<false>, dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur,
-                           Ui, ldu, Vr, Vi, ldv, sv_e, sv_f, sv, s);
+                           Ui, ldu, Vr, Vi, ldv, sv_e, sv_f, sv);
     return hipGetLastError();
 }
 
 // non-converged exit: current column norms, backscaled, in column order
-__global__ __launch_bounds__(256) void colnorm_out_kernel(int n, const double *e, const double *f, int s,
-                                                          double *sv_e, double *sv_f, double *sv)
+__global__ __launch_bounds__(256) void colnorm_out_kernel(int n, const double *e, const double *f,
+                                                          const DevScalars *sc, double *sv_e, double *sv_f,
+                                                          double *sv)
 {
+    const int s = sc->s;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const bool zero = isinf(e[j]);
@@ -626,9 +541,9 @@ hipError_t launch_colnorms_raw(const SvdDesc &d, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_colnorm_out(const SvdDesc &d, int s, double *sv_e, double *sv_f, double *sv, hipStream_t st)
+hipError_t launch_colnorm_out(const SvdDesc &d, double *sv_e, double *sv_f, double *sv, hipStream_t st)
 {
-    hipLaunchKernelGGL(colnorm_out_kernel, dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, s, sv_e,
+    hipLaunchKernelGGL(colnorm_out_kernel, dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, d.sc, sv_e,
                        sv_f, sv);
     return hipGetLastError();
 }

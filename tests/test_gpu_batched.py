@@ -1,0 +1,100 @@
+"""GPU tests of the batched form (jsvd_gesvj_batched): every matrix of a batch
+of uneven shapes gives, bit for bit, the same U, V, sigma, status and sweep
+count as the plain jsvd_gesvj (and so as the oracle), including matrices
+that fall back to the plain path, failing matrices and the sweep limit."""
+import numpy as np
+import pytest
+
+from paper_2202_08361_amd import inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def J():
+    import paper_2202_08361_amd as jsvd
+    return jsvd
+
+
+def _bits(x):
+    return np.ascontiguousarray(x.cpu().numpy() if hasattr(x, "cpu") else x).view(np.int64)
+
+
+def _same(a, b):
+    return a is None and b is None or np.array_equal(_bits(a), _bits(b))
+
+
+def _mats(shapes, seed):
+    out = []
+    g = inputs.rng(inputs.CFG_BATCHED, 900 + seed)
+    for (m, n, c, kappa) in shapes:
+        sig = inputs.sigma_logspace(n, 1.0 / kappa)
+        Ar, Ai = inputs.svd_matrix(m, n, sig, g, cplx=c)
+        out.append((Ar, Ai))
+    return out
+
+
+def _check_batch(host_mats, max_sweeps=0, flags=0):
+    dev = [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host_mats]
+    res = J().gesvj_batched(dev, max_sweeps=max_sweeps, flags=flags)
+    torch.cuda.synchronize()
+    for (Ar, Ai), rb in zip(host_mats, res):
+        rp = J().gesvj(J().to_device_fortran(Ar), None if Ai is None else J().to_device_fortran(Ai),
+                       max_sweeps=max_sweeps, flags=flags)
+        assert rb["status"] == rp["status"] and rb["sweeps"] == rp["sweeps"], (Ar.shape, rb["status"], rp["status"])
+        if rp["status"] < 0:
+            continue
+        for k in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+            assert _same(rb[k], rp[k]), (Ar.shape, k)
+    return res
+
+
+def test_batched_mixed_shapes():
+    shapes = [(16, 16, False, 1e2), (17, 17, False, 1e3), (40, 33, True, 1e4), (128, 64, False, 1e6),
+              (300, 257, False, 1e5), (512, 512, False, 1e2), (200, 130, True, 1e3), (1, 1, False, 1.0),
+              (9, 2, True, 10.0), (511, 256, True, 1e8), (700, 100, False, 1e4)]   # the last is outside the tile
+    _check_batch(_mats(shapes, 1))
+
+
+def test_batched_vs_oracle():
+    import oracle
+    host = _mats([(60, 33, True, 1e4), (90, 90, False, 1e6)], 2)
+    dev = [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host]
+    res = J().gesvj_batched(dev)
+    for (Ar, Ai), rb in zip(host, res):
+        ro = oracle.gesvj(Ar, Ai)
+        assert rb["status"] == ro["status"] and rb["sweeps"] == ro["sweeps"]
+        for k in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+            assert (rb[k] is None and ro[k] is None) or np.array_equal(_bits(rb[k]), _bits(ro[k])), k
+
+
+def test_batched_failures_and_limits():
+    host = _mats([(20, 10, False, 1e3), (30, 30, True, 1e2), (25, 12, False, 1e2)], 3)
+    Ab = host[2][0].copy(order="F")
+    Ab[3, 4] = np.nan
+    host.append((Ab, None))
+    host.append((np.zeros((8, 5), order="F"), None))
+    res = _check_batch(host)
+    assert res[3]["status"] == J().ENONFINITE and res[4]["status"] == J().EZERO
+    assert res[0]["status"] == J().OK
+    _check_batch(host[:3], max_sweeps=1)
+    _check_batch(host[:3], flags=J().NO_PERMUTE)
+
+
+def test_batched_workload_sample():
+    """A sample of the batched workload (n uniform in [16, 256], m in [n, 2n],
+    kappa log-uniform in [1e2, 1e8]) against the plain path; relative sigma
+    error against the prescribed values for sigma >= 1e-6 sigma_max."""
+    m, n, kappa = inputs.batched_shapes(24, seed_sub=7)
+    host, sigs = [], []
+    for i in range(24):
+        A, sig = inputs.batched_matrix(i, int(m[i]), int(n[i]), float(kappa[i]), seed_sub=7)
+        host.append((A, None))
+        sigs.append(sig)
+    res = _check_batch(host)
+    for r, sig in zip(res, sigs):
+        assert r["status"] == 0
+        sv = np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))
+        big = sig >= 1e-6 * sig[0]
+        assert np.max(np.abs(sv[big] - sig[big]) / sig[big]) < 1e-9
