@@ -32,6 +32,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kind):
+    """HBM bytes per launch of the EVD kernel from the committed hardware-counter
+    record (FETCH_SIZE/WRITE_SIZE scaled by a plain copy), or None when the
+    kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "evd2_traffic.json")))
+        csrc = os.path.join(ROOT, "paper_2202_08361_amd", "csrc")
+        src = open(os.path.join(csrc, "evd2.hip"), "rb").read() + open(os.path.join(csrc, "evd2_core.hpp"), "rb").read()
+        if hashlib.sha256(src).hexdigest() != rec["kernel_sources_sha256"]:
+            return None
+        return rec[kind]["bytes"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def evd_workload(torch, J, inputs, r, K, W):
     dev = {}
     for cplx in (False, True):
@@ -89,6 +105,126 @@ def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2):
                 algorithmic_bytes=byts, achieved_GBs=byts / t / 1e9, frac=byts / t / 1e9 / HBM_PEAK_GBS)
 
 
+def sweep_time(torch, J, inputs, m, n, cplx):
+    """One whole sweep (graph of K steps) of the large plain workloads on a fresh state."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 88 + int(cplx))
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    st = J.State(m, n, cplx)
+    st.load(J.to_device_fortran(Ar), J.to_device_fortran(Ai) if cplx else None)
+    st.sweep()                     # builds the graph; first sweep
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    st.sweep()
+    e.record()
+    torch.cuda.synchronize()
+    q = st.query()
+    st.close()
+    K = n - 1 if n % 2 == 0 else n
+    return dict(m=m, n=n, complex=bool(cplx), ms_per_sweep=s.elapsed_time(e), steps=K,
+                us_per_step=s.elapsed_time(e) * 1e3 / K, transformed_in_last_step=q["last_t"], pairs=n // 2)
+
+
+def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
+    """The first `count` matrices of the batched workload in one call, and the
+    first `plain_count` of them one by one through jsvd_gesvj."""
+    import numpy as np
+    m, n, kappa = inputs.batched_shapes(10000)
+    mats, sigs = [], []
+    for i in range(count):
+        A, sig = inputs.batched_matrix(i, int(m[i]), int(n[i]), float(kappa[i]))
+        mats.append(A)
+        sigs.append(sig)
+    dev = [(J.to_device_fortran(A), None) for A in mats]
+    J.gesvj_batched([(J.to_device_fortran(mats[0]), None)], flags=flags)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = J.gesvj_batched(dev, flags=flags)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    errs, byts, sweeps = [], 0.0, []
+    for i, r in enumerate(res):
+        sv = np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))
+        big = sigs[i] >= 1e-6 * sigs[i][0]
+        errs.append(float(np.max(np.abs(sv[big] - sigs[i][big]) / sigs[i][big])))
+        K = n[i] - 1 if n[i] % 2 == 0 else n[i]
+        byts += 16.0 * n[i] * (m[i] + n[i]) * K * (r["sweeps"] + 1)
+        sweeps.append(r["sweeps"])
+    dev2 = [J.to_device_fortran(A) for A in mats[:plain_count]]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for A in dev2:
+        J.gesvj(A, flags=flags, overwrite=True)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    return dict(count=count, batched_s=tb, batched_svds_per_s=count / tb,
+                plain_count=plain_count, plain_s=tp, plain_svds_per_s=plain_count / tp,
+                speedup=(count / tb) / (plain_count / tp), max_rel_sigma_err=max(errs),
+                mean_sweeps=float(np.mean(sweeps)), max_sweeps=int(max(sweeps)),
+                algorithmic_bytes_upper=byts, algorithmic_GBs_upper=byts / tb / 1e9,
+                bit_identical_to_plain="tested (tests/test_gpu_batched.py)")
+
+
+def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32, budget=64 << 30,
+                slots=16, drain_limit=120.0):
+    """Poisson arrivals replayed from a pre-generated pool of request matrices."""
+    import numpy as np
+    t_arr, cplx, m, n, kappa = inputs.serve_stream(rate, duration)
+    g = inputs.rng(inputs.CFG_SERVE, 12345)
+    pidx = np.arange(len(t_arr)) % pool_size
+    pool = []
+    for k in range(pool_size):
+        Ar, Ai, sig = inputs.serve_matrix(int(m[k]), int(n[k]), float(kappa[k]), bool(cplx[k]), g)
+        pool.append((J.to_device_fortran(Ar), None if Ai is None else J.to_device_fortran(Ai)))
+    torch.cuda.synchronize()
+    srv = J.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=max_queue, flags=flags)
+    outstanding, rejected, submitted = {}, 0, 0
+    t0 = time.perf_counter()
+    for i, ta in enumerate(t_arr):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.0002)
+        st = srv.stats()
+        if st["queue_depth"] >= max_queue:
+            rejected += 1
+            continue
+        Gr, Gi = pool[pidx[i]]
+        gr = J.fortran_empty(*Gr.shape)
+        gr.copy_(Gr)
+        gi = None
+        if Gi is not None:
+            gi = J.fortran_empty(*Gi.shape)
+            gi.copy_(Gi)
+        t = srv.submit(gr, gi)
+        if t is None:
+            rejected += 1
+            continue
+        submitted += 1
+        outstanding[t] = (gr, gi)
+        if i % 64 == 0:
+            for tk in [tk for tk in outstanding if srv.poll(tk)[0]]:
+                srv.wait(tk)
+                outstanding.pop(tk)
+    t_end_arrivals = time.perf_counter() - t0
+    deadline = time.perf_counter() + drain_limit
+    for tk in list(outstanding):
+        while not srv.poll(tk)[0] and time.perf_counter() < deadline:
+            time.sleep(0.001)
+        if srv.poll(tk)[0]:
+            srv.wait(tk)
+            outstanding.pop(tk)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    unfinished = len(outstanding)
+    if unfinished == 0:
+        srv.close()
+    return dict(offered_rate=rate, arrival_window_s=duration, offered=len(t_arr), submitted=submitted,
+                rejected_backpressure=rejected, completed=st["completed"], unfinished_at_limit=unfinished,
+                wall_s=wall, arrivals_s=t_end_arrivals, svds_per_s=st["completed"] / wall,
+                p50_latency_ms=st["p50_ns"] / 1e6, p99_latency_ms=st["p99_ns"] / 1e6,
+                p50_queue_ms=st["p50_queue_ns"] / 1e6, p99_queue_ms=st["p99_queue_ns"] / 1e6,
+                pool=pool_size, max_queue=max_queue, slots=slots, flags=flags)
+
+
 def svd_plain(torch, J, inputs, flags):
     A, sig = inputs.plain_real_256()
     dA = J.to_device_fortran(A)
@@ -112,6 +248,17 @@ def main():
     ap.add_argument("--log2r", type=int, default=26)
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched", type=int, default=500)
+    ap.add_argument("--batched-plain", type=int, default=25)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--calib-copy", type=int, default=0,
+                    help="MiB copied once by a plain device copy before the timed region "
+                         "(a reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the batched EVD and the Jacobi step are single-device "
@@ -128,6 +275,13 @@ def main():
         import __graft_entry__
         __graft_entry__.build()
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        src = torch.ones(args.calib_copy << 17, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     r = 1 << args.log2r
     K, W = args.steps, args.warmup
     log(f"[bench] batched EVD: r = 2^{args.log2r} real + complex, warmup {W}, steps {K}")
@@ -138,26 +292,35 @@ def main():
     ach_r = EVD_BYTES_REAL * r / dur[False] / 1e9
     log(f"[bench] EVD: {value:.4g} EVD/s, {ms_per_step:.3f} ms/step; complex kernel {dur[True]*1e3:.3f} ms "
         f"({ach_c:.0f} GB/s), real kernel {dur[False]*1e3:.3f} ms ({ach_r:.0f} GB/s)")
+    tr_c, tr_r = (measured_traffic("complex"), measured_traffic("real")) if r == 1 << 26 else (None, None)
     roofline = dict(bound="hbm", kernel="evd2_kernel_v2<complex>", achieved=round(ach_c, 1),
-                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach_c / HBM_PEAK_GBS, 4), traffic=None,
+                    peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach_c / HBM_PEAK_GBS, 4),
+                    traffic=None if tr_c is None else round(tr_c / 1e9, 4), traffic_unit="GB per launch",
                     bytes_per_launch=EVD_BYTES_CPLX * r, avg_launch_ms=round(dur[True] * 1e3, 4),
                     real_kernel=dict(achieved=round(ach_r, 1), frac=round(ach_r / HBM_PEAK_GBS, 4),
+                                     traffic=None if tr_r is None else round(tr_r / 1e9, 4),
                                      bytes_per_launch=EVD_BYTES_REAL * r,
                                      avg_launch_ms=round(dur[False] * 1e3, 4)))
     cpu = None
     if not args.no_cpu:
         import oracle
-        ns = 1 << min(args.log2r, 23)
+        ns = 1 << min(args.log2r, 24)
         nth = oracle.omp_max_threads()
         t0 = time.perf_counter()
-        for cplx in (False, True):
-            a11, a22, ar, ai = dev[cplx][2]
-            oracle.evd2_batch(a11[:ns], a22[:ns], ar[:ns], None if ai is None else ai[:ns], nthreads=nth)
+        passes = 0
+        while True:
+            for cplx in (False, True):
+                a11, a22, ar, ai = dev[cplx][2]
+                oracle.evd2_batch(a11[:ns], a22[:ns], ar[:ns], None if ai is None else ai[:ns], nthreads=nth)
+            passes += 1
+            if time.perf_counter() - t0 >= args.cpu_seconds:
+                break
         ct = time.perf_counter() - t0
-        cpu = dict(value=round(2 * ns / ct, 1), unit="EVD/s", cores=nth, kind="oracle",
-                   sample=f"first 2^{ns.bit_length() - 1} real + 2^{ns.bit_length() - 1} complex matrices of the "
-                          f"workload, OpenMP over matrices, {ct:.1f} s")
-        log(f"[bench] cpu oracle: {cpu['value']:.4g} EVD/s on {nth} threads")
+        cpu = dict(value=round(2 * ns * passes / ct, 1), unit="EVD/s", cores=nth, kind="oracle",
+                   sample=f"{passes} passes over the first 2^{ns.bit_length() - 1} real + "
+                          f"2^{ns.bit_length() - 1} complex matrices of the workload, OpenMP over matrices, "
+                          f"{ct:.1f} s")
+        log(f"[bench] cpu oracle: {cpu['value']:.4g} EVD/s on {nth} threads ({ct:.1f} s)")
     del dev
     torch.cuda.empty_cache()
     extra = {}
@@ -170,6 +333,21 @@ def main():
             log(f"[bench] {nm}")
             extra[nm] = svd_plain(torch, J, inputs, fl)
             log(f"[bench]   {extra[nm]}")
+        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
+            nm = f"sweep_{'c' if c else 'r'}{m}x{n}"
+            log(f"[bench] {nm}")
+            extra[nm] = sweep_time(torch, J, inputs, m, n, c)
+            log(f"[bench]   {extra[nm]}")
+        if not args.no_batched:
+            for nm, fl in (("batched_permute", 0), ("batched_nopermute", J.NO_PERMUTE)):
+                log(f"[bench] {nm}: first {args.batched} matrices of the 10,000-matrix workload")
+                extra[nm] = batched_vs_plain(torch, J, inputs, args.batched, args.batched_plain, fl)
+                log(f"[bench]   {extra[nm]}")
+        if not args.no_serve:
+            log(f"[bench] serving: Poisson {args.serve_rate}/s for {args.serve_seconds} s")
+            extra["serving"] = serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
+                                           args.serve_pool, J.NO_PERMUTE)
+            log(f"[bench]   {extra['serving']}")
     line = {
         "metric": "batched 2x2 EVDs/s",
         "value": round(value, 1),

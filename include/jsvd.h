@@ -206,6 +206,7 @@ typedef struct {
     int max_slots;           /* requests on the device at once */
     int max_sweeps;          /* per request (<= 0: 128) */
     int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
+    unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_NO_PERMUTE) */
 } jsvd_serve_config;
 
 typedef struct {

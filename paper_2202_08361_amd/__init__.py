@@ -49,7 +49,7 @@ class _Info(_ct.Structure):
 
 class ServeConfig(_ct.Structure):
     _fields_ = [("hbm_budget_bytes", _ct.c_size_t), ("max_slots", _ct.c_int),
-                ("max_sweeps", _ct.c_int), ("max_queue", _ct.c_int)]
+                ("max_sweeps", _ct.c_int), ("max_queue", _ct.c_int), ("flags", _ct.c_uint)]
 
 
 class Request(_ct.Structure):
@@ -357,8 +357,8 @@ def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None):
 class Server:
     """Continuous-batching SVD server (jsvd_serve_*)."""
 
-    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_sweeps=0, max_queue=0):
-        cfg = ServeConfig(hbm_budget_bytes, max_slots, max_sweeps, max_queue)
+    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_sweeps=0, max_queue=0, flags=0):
+        cfg = ServeConfig(hbm_budget_bytes, max_slots, max_sweeps, max_queue, flags)
         h = _ct.c_void_p()
         _check(lib().jsvd_serve_create(_ct.byref(cfg), _ct.byref(h)), "jsvd_serve_create")
         self._h = h
