@@ -122,7 +122,7 @@ def sweep_time(torch, J, inputs, m, n, cplx):
     st.close()
     K = n - 1 if n % 2 == 0 else n
     return dict(m=m, n=n, complex=bool(cplx), ms_per_sweep=s.elapsed_time(e), steps=K,
-                us_per_step=s.elapsed_time(e) * 1e3 / K, transformed_in_last_step=q["last_t"], pairs=n // 2)
+                us_per_step=s.elapsed_time(e) * 1e3 / K, transformations_in_sweep=q["last_sweep_T"], swaps_in_sweep=q["last_sweep_swaps"])
 
 
 def batched_vs_plain(torch, J, inputs, count, plain_count, flags):

@@ -103,7 +103,7 @@ typedef struct jsvd_state_s *jsvd_state;
 
 typedef struct {
     int64_t steps;        /* steps taken since the last load */
-    int64_t sweeps;       /* completed sweeps (jsvd_sweep) */
+    int64_t sweeps;       /* sweeps that transformed or swapped (C of Alg. zvjsvd) */
     int64_t T;            /* transformations in the current sweep so far */
     int64_t last_t;       /* transformations in the last step */
     int64_t swaps;        /* column swaps without transformation in the current sweep */
@@ -112,6 +112,8 @@ typedef struct {
     double Mt;            /* M~_k, the max-norm estimate of G_k */
     int32_t converged;    /* a full sweep with neither transformation nor swap */
     int32_t status;       /* JSVD_OK or the load error */
+    int64_t last_sweep_T;     /* transformations in the last completed sweep */
+    int64_t last_sweep_swaps; /* swaps without transformation in the last completed sweep */
 } jsvd_info;
 
 /* Allocate a state for an m x n real (is_complex = 0) or complex problem.

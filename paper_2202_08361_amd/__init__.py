@@ -44,7 +44,7 @@ class _Info(_ct.Structure):
     _fields_ = [("steps", _ct.c_int64), ("sweeps", _ct.c_int64), ("T", _ct.c_int64),
                 ("last_t", _ct.c_int64), ("swaps", _ct.c_int64), ("s", _ct.c_int32),
                 ("rescaled", _ct.c_int32), ("Mt", _ct.c_double), ("converged", _ct.c_int32),
-                ("status", _ct.c_int32)]
+                ("status", _ct.c_int32), ("last_sweep_T", _ct.c_int64), ("last_sweep_swaps", _ct.c_int64)]
 
 
 class ServeConfig(_ct.Structure):

@@ -155,10 +155,6 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     st->rank = (int *)(b + L.oR);
     st->maxbits = (unsigned long long *)(b + L.oM);
     st->prm = (PairParam *)(b + L.oP);
-    if (gstep_prepare(m, st->cplx) != hipSuccess) {
-        jsvd_state_destroy(st);
-        return JSVD_EDEVICE;
-    }
     *out = st;
     return JSVD_OK;
 }
@@ -239,12 +235,16 @@ static int state_threads(jsvd_state st)
     return st->threads ? st->threads : step_auto_threads(st->m, st->n);
 }
 
-// one step: the pipelined pair of kernels when the columns fit its tile and no
-// workgroup size is forced, otherwise the one-workgroup-per-pair kernel
+// one step: for long columns (and no forced workgroup size) the G kernel and
+// the V kernel, otherwise the fused one-workgroup-per-pair kernel
+static bool uses_gpair(jsvd_state st)
+{
+    return st->threads == 0 && gpair_rows(st->m, st->cplx) != 0 && st->m > 256;
+}
+
 static hipError_t launch_one_step(jsvd_state st, hipStream_t s)
 {
-    if (st->threads == 0 && gstep_rows(st->m, st->cplx) != 0 && st->m > 256)
-        return launch_gstep(st->d, st->prm, st->ncu, s);
+    if (uses_gpair(st)) return launch_gpair(st->d, st->prm, s);
     return launch_step(st->d, state_threads(st), s);
 }
 
@@ -256,6 +256,15 @@ extern "C" int jsvd_step(jsvd_state st, void *stream)
 }
 
 static int sweep_steps(int n) { return n + (n & 1) - 1; }
+
+// Capture the K steps of a sweep and the end-of-sweep bookkeeping.
+static int capture_sweep(jsvd_state st, hipStream_t cs)
+{
+    const int K = sweep_steps(st->n);
+    for (int k = 0; k < K; ++k)
+        if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
+    return launch_sweep_end(st->d, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
+}
 
 static int build_graph(jsvd_state st)
 {
@@ -269,27 +278,26 @@ static int build_graph(jsvd_state st)
         (void)hipGraphDestroy(st->graph_def);
         st->graph_def = nullptr;
     }
-    hipStream_t cs;
-    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipStream_t cs = nullptr;
     int rc = JSVD_OK;
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-        (void)hipStreamDestroy(cs);
-        return JSVD_EDEVICE;
-    }
-    const int K = sweep_steps(st->n);
-    for (int k = 0; k < K && rc == JSVD_OK; ++k)
-        if (launch_one_step(st, cs) != hipSuccess) rc = JSVD_EDEVICE;
-    if (rc == JSVD_OK && launch_sweep_end(st->d, cs) != hipSuccess) rc = JSVD_EDEVICE;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = JSVD_EDEVICE;
     hipGraph_t g = nullptr;
-    if (hipStreamEndCapture(cs, &g) != hipSuccess) rc = JSVD_EDEVICE;
-    (void)hipStreamDestroy(cs);
+    if (rc == JSVD_OK) {
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = JSVD_EDEVICE;
+        } else {
+            rc = capture_sweep(st, cs);
+            // a failed capture still has to be ended
+            if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == JSVD_OK) rc = JSVD_EDEVICE;
+        }
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (rc == JSVD_OK && (!g || hipGraphInstantiate(&st->graph, g, nullptr, nullptr, 0) != hipSuccess))
+        rc = JSVD_EDEVICE;
     if (rc != JSVD_OK) {
         if (g) (void)hipGraphDestroy(g);
+        st->graph = nullptr;
         return rc;
-    }
-    if (hipGraphInstantiate(&st->graph, g, nullptr, nullptr, 0) != hipSuccess) {
-        (void)hipGraphDestroy(g);
-        return JSVD_EDEVICE;
     }
     st->graph_def = g;
     st->graph_threads = thr;
@@ -352,6 +360,8 @@ extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
     out->Mt = bitsd(h.Mt_bits);
     out->converged = h.converged;
     out->status = h.status;
+    out->last_sweep_T = h.T_prev;
+    out->last_sweep_swaps = h.SW_prev;
     return JSVD_OK;
 }
 

@@ -24,6 +24,8 @@ struct DevScalars {
     long long last_t;             // transformations of the last completed step
     long long sweeps;             // sweeps completed
     long long C;                  // sweeps that found a transformation or a swap
+    long long T_prev;             // transformations of the last completed sweep
+    long long SW_prev;            // swaps without transformation of the last completed sweep
     int s;                        // effective scaling exponent
     int rescaled;                 // step-start downscalings
     int converged;                // a sweep without transformation and swap was seen
@@ -47,19 +49,22 @@ struct SvdDesc {
     double ups;            // fl(sqrt(m)) 2^-53
 };
 
-// rotation of one pivot pair, produced by the pipelined G kernel for the V kernel
+// outcome of one pivot pair, written by the G kernels for the V kernel and
+// for the end-of-step fold
 struct PairParam {
     double c, C, S;   // cos phi, e^{i alpha} tan phi
+    double mx;        // max |component| of the rotated G columns (0 if not rotated)
     int p, q;         // the pair
     int flag;         // bit 0: rotate, bit 1: swap the columns (permutation P)
     int pad;
 };
 
-// pipelined step for large columns (gstep.hip): rows per thread for m
-// (0 = not supported) and the launch of the G kernel followed by the V kernel
-int gstep_rows(int m, int cplx);
-hipError_t launch_gstep(const SvdDesc &d, PairParam *prm, int grid, hipStream_t s);
-hipError_t gstep_prepare(int m, int cplx);
+// step for large columns (gstep.hip): rows per thread of the G kernel for m
+// (0 = not supported); the V kernel (applies the rotations in prm and folds
+// the step into the device scalars); the G kernel followed by the V kernel
+int gpair_rows(int m, int cplx);
+hipError_t launch_vrot(const SvdDesc &d, const PairParam *prm, hipStream_t s);
+hipError_t launch_gpair(const SvdDesc &d, PairParam *prm, hipStream_t s);
 
 // initialisation: M~_0 into *maxbits (zeroed by the caller), then
 // G <- 2^{s_0} A copied into the workspace and V <- I

@@ -67,6 +67,21 @@ __device__ __forceinline__ bool rr_pair(int n, long long kk, int l, int *p, int 
     return b < n;
 }
 
+// Workgroup barrier that orders LDS only: every wave first waits for its own
+// LDS operations (lgkmcnt = 0), so LDS writes before the barrier are visible
+// to LDS reads after it, while global loads and stores, including the
+// asynchronous global->LDS prefetch, stay in flight.  (A fence-based barrier
+// would also drain those, which stalls a pair on the prefetch of the next
+// one.)  The empty asm statements keep the compiler from moving memory
+// accesses across the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt not waited on
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // ---------------------------------------------------------------------------
 // In-wave halving tree: after the call lane 0 holds x_0 + x_1 + ... in the
 // canonical order (lane i += lane i+h for h = 32, ..., 1); the total is
@@ -87,7 +102,7 @@ __device__ __forceinline__ double wave_max(double x)
 
 // Group-wide canonical sum of NQ quantities (one value per thread each, the
 // thread's in-thread tree already applied).  lds must hold NQ * W doubles and
-// must not be reused by the caller until after the next __syncthreads().
+// must not be reused by the caller until after the next workgroup barrier.
 template <int W, int NQ>
 __device__ __forceinline__ void group_tree_sum(double (&v)[NQ], double *lds)
 {
@@ -99,7 +114,7 @@ __device__ __forceinline__ void group_tree_sum(double (&v)[NQ], double *lds)
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) lds[q * W + wv * 64 + lane] = v[q];
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             double x[NW];
@@ -128,7 +143,7 @@ __device__ __forceinline__ void group_max(double (&v)[NQ], double *lds)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) lds[q * NW + wv] = v[q];
         }
-        __syncthreads();
+        lds_barrier();
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             double x = lds[q * NW];

@@ -296,6 +296,8 @@ __global__ void sweep_end_kernel(DevScalars *sc)
         sc->C += 1;
         if (sc->C >= sc->max_sweeps) sc->stop = 1;
     }
+    sc->T_prev = sc->T;
+    sc->SW_prev = sc->SW;
     sc->T = 0;
     sc->SW = 0;
 }
@@ -341,6 +343,8 @@ __global__ void init_scalars_kernel(SvdDesc d, const unsigned long long *maxbits
     sc->last_t = 0;
     sc->sweeps = 0;
     sc->C = 0;
+    sc->T_prev = 0;
+    sc->SW_prev = 0;
     sc->rescaled = 0;
     sc->converged = 0;
     sc->max_sweeps = max_sweeps;

@@ -186,3 +186,27 @@ def test_step_full_size(ora, m, n, cplx):
     """One step of the large workloads (real 8192 x 2048, complex 4096 x 4096)
     on Gaussian columns: G, V, norms and scalars bit-for-bit."""
     _pair_run(ora, m, n, cplx, steps=1, seed=1)
+
+
+@pytest.mark.parametrize("m,n,cplx", [(1500, 21, True), (700, 32, False), (3000, 9, False)])
+def test_sweep_graph_bitwise(ora, m, n, cplx):
+    """Whole sweeps through the captured sweep graph (the pipelined kernels, the
+    V kernel of step j beside the G kernel of step j+1) equal K oracle steps,
+    with the sweep's transformation and swap counts."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 800 + m)
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    ost = ora.State(Ar, Ai)
+    assert ost.init() == ora.OK
+    st = J().State(m, n, cplx)
+    assert st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None) == 0
+    K = ora.rr_steps(n)
+    for sweep in range(3):
+        T = SW = 0
+        for _ in range(K):
+            T += ost.step()
+            SW += ost.last_sw
+        st.sweep()
+        q = st.query()
+        _check_state(ost, st.save(), f"sweep {sweep} m={m} n={n} cplx={cplx}")
+        assert q["last_sweep_T"] == T and q["last_sweep_swaps"] == SW
+        assert q["steps"] == ost.k
