@@ -48,6 +48,63 @@ def measured_traffic(kind):
         return None
 
 
+def evd_kernel_name(r, cplx):
+    """The EVD kernel the library launches for a 16-byte aligned batch of r."""
+    v = "v1" if r >= (1 << 22) else "v2"
+    return f"evd2_kernel_{v}<{'true' if cplx else 'false'}, false, false>"
+
+
+def _rocpd_rows(db, sql):
+    import sqlite3
+    con = sqlite3.connect(db)
+    try:
+        return con.execute(sql).fetchall()
+    finally:
+        con.close()
+
+
+def trace_summary(db):
+    """Markdown table of a rocprofv3 --kernel-trace --stats database."""
+    rows = _rocpd_rows(db, "select name, total_calls, total_duration, average, percentage from top_kernels")
+    out = ["| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for name, calls, total, avg, pct in rows:
+        out.append(f"| `{name[:110]}` | {calls} | {total:.1f} | {avg:.2f} | {pct:.2f} |")
+    return "\n".join(out)
+
+
+def traffic_from(fetch_db, write_db, calib_mib, r=1 << 26):
+    """HBM bytes per launch of the EVD kernels from one FETCH_SIZE and one
+    WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
+    reads for the plain device copy of calib_mib MiB in the same run."""
+    import hashlib
+    q = "select kernel_name, grid_size, value from counters_collection order by dispatch_id"
+    fetch, write = _rocpd_rows(fetch_db, q), _rocpd_rows(write_db, q)
+    moved = calib_mib * 1024.0   # KiB read and written by the copy
+
+    def pick(rows, key):
+        vals = [v for (nm, g, v) in rows if key in nm]
+        if not vals:
+            raise SystemExit(f"no dispatch of {key} in the counter database")
+        return vals[-1]
+    f_scale = moved / pick(fetch, "copyBuffer")
+    w_scale = moved / pick(write, "copyBuffer")
+    csrc = os.path.join(ROOT, "paper_2202_08361_amd", "csrc")
+    src = open(os.path.join(csrc, "evd2.hip"), "rb").read() + open(os.path.join(csrc, "evd2_core.hpp"), "rb").read()
+    rec = dict(kernel_sources_sha256=hashlib.sha256(src).hexdigest(), fetch_scale=f_scale, write_scale=w_scale,
+               r=r, calib_copy_mib=calib_mib)
+    md = ["| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled bytes | algorithmic bytes |", "|---|---|---|---|---|"]
+    for kind, cplx, alg in (("real", False, EVD_BYTES_REAL), ("complex", True, EVD_BYTES_CPLX)):
+        name = evd_kernel_name(r, cplx)
+        fk, wk = pick(fetch, name), pick(write, name)
+        byts = (fk * f_scale + wk * w_scale) * 1024.0
+        rec[kind] = dict(kernel=name, fetch_kib=fk, write_kib=wk, bytes=byts)
+        md.append(f"| `{name}` | {fk:.1f} | {wk:.1f} | {byts:.4g} | {alg * r:.4g} |")
+    md.append(f"\nCalibration: the plain device copy of {calib_mib} MiB reads as FETCH_SIZE "
+              f"{pick(fetch, 'copyBuffer'):.1f} KiB and WRITE_SIZE {pick(write, 'copyBuffer'):.1f} KiB; "
+              f"scale factors {f_scale:.4f} and {w_scale:.4f}.")
+    return rec, "\n".join(md)
+
+
 def evd_workload(torch, J, inputs, r, K, W):
     dev = {}
     for cplx in (False, True):
@@ -259,7 +316,21 @@ def main():
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied once by a plain device copy before the timed region "
                          "(a reference for hardware byte counters)")
+    ap.add_argument("--trace-summary", metavar="DB",
+                    help="print the kernel table of a rocprofv3 --kernel-trace --stats database and exit")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="derive the EVD kernels' HBM bytes per launch from FETCH_SIZE / WRITE_SIZE "
+                         "databases of runs made with --calib-copy, write profiles/evd2_traffic.json, exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary))
+        return
+    if args.traffic_from:
+        rec, md = traffic_from(args.traffic_from[0], args.traffic_from[1], args.calib_copy or 512)
+        with open(os.path.join(ROOT, "profiles", "evd2_traffic.json"), "w") as fh:
+            json.dump(rec, fh, indent=1)
+        print(md)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the batched EVD and the Jacobi step are single-device "
               "kernels here (how the path would shard across GPUs is described in DESIGN.md)",
@@ -293,11 +364,12 @@ def main():
     log(f"[bench] EVD: {value:.4g} EVD/s, {ms_per_step:.3f} ms/step; complex kernel {dur[True]*1e3:.3f} ms "
         f"({ach_c:.0f} GB/s), real kernel {dur[False]*1e3:.3f} ms ({ach_r:.0f} GB/s)")
     tr_c, tr_r = (measured_traffic("complex"), measured_traffic("real")) if r == 1 << 26 else (None, None)
-    roofline = dict(bound="hbm", kernel="evd2_kernel_v2<complex>", achieved=round(ach_c, 1),
+    roofline = dict(bound="hbm", kernel=evd_kernel_name(r, True), achieved=round(ach_c, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach_c / HBM_PEAK_GBS, 4),
                     traffic=None if tr_c is None else round(tr_c / 1e9, 4), traffic_unit="GB per launch",
                     bytes_per_launch=EVD_BYTES_CPLX * r, avg_launch_ms=round(dur[True] * 1e3, 4),
-                    real_kernel=dict(achieved=round(ach_r, 1), frac=round(ach_r / HBM_PEAK_GBS, 4),
+                    real_kernel=dict(kernel=evd_kernel_name(r, False), achieved=round(ach_r, 1),
+                                     frac=round(ach_r / HBM_PEAK_GBS, 4),
                                      traffic=None if tr_r is None else round(tr_r / 1e9, 4),
                                      bytes_per_launch=EVD_BYTES_REAL * r,
                                      avg_launch_ms=round(dur[False] * 1e3, 4)))

@@ -65,9 +65,8 @@ extern "C" int jsvd_evd2_batched(size_t r, const double *a11, const double *a22,
     if (!a11 || !a22 || !a21_re || !cos_phi || !ctan_re) return JSVD_EINVAL;
     if ((a21_im == nullptr) != (ctan_im == nullptr)) return JSVD_EINVAL;
     if (r > (size_t)1 << 40) return JSVD_EINVAL;
-    const int force_scalar = getenv("JSVD_EVD_SCALAR") != nullptr;
     if (launch_evd2(r, a11, a22, a21_re, a21_im, cos_phi, ctan_re, ctan_im, lambda1, lambda2, zp, flags,
-                    force_scalar, (hipStream_t)stream) != hipSuccess)
+                    (hipStream_t)stream) != hipSuccess)
         return JSVD_EDEVICE;
     return JSVD_OK;
 }

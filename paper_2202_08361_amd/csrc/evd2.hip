@@ -4,10 +4,12 @@
 //
 // Structure-of-arrays streams in, structure-of-arrays streams out: the
 // kernel is bound by HBM bandwidth (60 B per real, 76 B per complex matrix).
-// Each lane handles two consecutive matrices with 16-byte loads and stores
-// when every stream is 16-byte aligned, otherwise one matrix.  Streams are
-// read and written once, with non-temporal hints so the batch does not
-// evict other data from the caches.
+// A batch larger than the caches runs one matrix per lane (8-byte accesses,
+// the most lanes in flight: measured 9-10% faster than two per lane on
+// MI355X); a smaller batch with 16-byte aligned streams runs two consecutive
+// matrices per lane with 16-byte accesses (faster out of the caches).
+// Streams are read and written once, with non-temporal hints so the batch
+// does not evict other data from the caches.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -110,13 +112,16 @@ static hipError_t launch_t(const Evd2Args &A, bool vec2, hipStream_t s)
     return hipGetLastError();
 }
 
+// batches from this size on stream from HBM (beyond the 256 MB last-level cache)
+constexpr size_t kLargeBatch = (size_t)1 << 22;
+
 hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const double *ar,
                        const double *ai, double *cs, double *cr, double *ci, double *l1,
-                       double *l2, int32_t *zp, unsigned flags, int force_scalar, hipStream_t s)
+                       double *l2, int32_t *zp, unsigned flags, hipStream_t s)
 {
     if (r == 0) return hipSuccess;
     Evd2Args A{r, a11, a22, ar, ai, cs, cr, ci, l1, l2, zp};
-    const bool vec2 = !force_scalar && aligned16(a11) && aligned16(a22) && aligned16(ar) &&
+    const bool vec2 = r < kLargeBatch && aligned16(a11) && aligned16(a22) && aligned16(ar) &&
                       aligned16(ai) && aligned16(cs) && aligned16(cr) && aligned16(ci) &&
                       aligned16(l1) && aligned16(l2) && ((uintptr_t)zp & 7u) == 0;
     const bool cplx = ai != nullptr;

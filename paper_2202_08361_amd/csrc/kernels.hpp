@@ -9,7 +9,7 @@ namespace jsvd {
 
 hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const double *ar,
                        const double *ai, double *cs, double *cr, double *ci, double *l1,
-                       double *l2, int32_t *zp, unsigned flags, int force_scalar, hipStream_t s);
+                       double *l2, int32_t *zp, unsigned flags, hipStream_t s);
 
 // Device-resident scalars of one SVD (updated only by kernels).
 struct DevScalars {
