@@ -47,10 +47,13 @@ enum {
     JSVD_ENOTFOUND = -7     /* serving: unknown ticket */
 };
 
-/* flags of jsvd_gesvj / jsvd_gesvj_batched */
+/* flags of jsvd_gesvj / jsvd_gesvj_batched / jsvd_state_set_flags / serving */
 #define JSVD_NO_PERMUTE 1u  /* apply U instead of U P during the iteration (no column
                                sorting by the EVD's permutation, Sect. 2); the final
                                sort still orders the output */
+#define JSVD_COMPENSATED 2u /* scaled dot-products with compensated summation
+                               (Sect. SM2.2, Alg. zdpsclcs / ddpsclcs) instead of
+                               Alg. zdpscl */
 
 /* flags of jsvd_evd2_batched */
 #define JSVD_EVD_SCALED  1u /* return lambda' = 2^zeta lambda (not backscaled), Sect. 2.3 */
@@ -168,6 +171,23 @@ int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu,
 int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
 
 /* ----------------------------------------------------------------------
+ * Batched scaled dot-products (Sect. 3.3): for j < npairs,
+ *   z_j = (q_j / 2^{eq_j})^* (p_j / 2^{ep_j}) / (fq_j fp_j)
+ * of the columns q_j = Q[:, j] and p_j = P[:, j] (m rows, column-major,
+ * leading dimension ld >= m; complex columns split, Q_im/P_im NULL for real
+ * data), by Alg. zdpscl, or by Alg. zdpsclcs / ddpsclcs with
+ * JSVD_COMPENSATED.  With (e, f) the column norms this is the a21' of a
+ * pivot pair; with e = 0, f = 1 it is the dot-product itself.  The sums run
+ * in the same lane order as in jsvd_step, so the results are those of the
+ * step.  All arrays are device arrays of the caller; z_im may be NULL for
+ * real data.  m <= 4096 (complex) / 8192 (real).  Launches only.
+ * ---------------------------------------------------------------------- */
+int jsvd_dot_scaled_batched(int npairs, int m, const double *Q_re, const double *Q_im,
+                            const double *P_re, const double *P_im, size_t ld,
+                            const double *eq, const double *fq, const double *ep, const double *fp,
+                            double *z_re, double *z_im, unsigned flags, void *stream);
+
+/* ----------------------------------------------------------------------
  * The whole SVD (Alg. zvjsvd with round-robin pairs): G = U Sigma V^*.
  * G (m x n, ldg >= m) is overwritten by U; V (n x n, ldv >= n) receives V;
  * sv_e/sv_f (n) receive sigma_j = 2^{sv_e[j]} sv_f[j] in descending order;
@@ -208,7 +228,8 @@ typedef struct {
     int max_slots;           /* requests on the device at once */
     int max_sweeps;          /* per request (<= 0: 128) */
     int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
-    unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_NO_PERMUTE) */
+    unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_NO_PERMUTE,
+                                JSVD_COMPENSATED) */
 } jsvd_serve_config;
 
 typedef struct {

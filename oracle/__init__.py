@@ -20,6 +20,7 @@ _lib = None
 OK, NOT_CONVERGED, EINVAL, ENONFINITE, EZERO = 0, 1, -1, -2, -3
 EVD_SCALED, EVD_SINFORM = 1, 2
 NO_PERMUTE = 1
+COMPENSATED = 2
 LANES = 1024
 
 _dp = _ct.POINTER(_ct.c_double)
@@ -60,6 +61,12 @@ def lib():
         L.ora_colnorm.argtypes = [i, _dp, _dp, _dp, _dp]
         L.ora_dpscl.restype = None
         L.ora_dpscl.argtypes = [i, _dp, _dp, _dp, _dp, d, d, d, d, _dp, _dp]
+        L.ora_mul_rd.restype = d
+        L.ora_mul_rd.argtypes = [d, d]
+        L.ora_2sum.restype = None
+        L.ora_2sum.argtypes = [d, d, _dp, _dp]
+        L.ora_dpscl_cs.restype = None
+        L.ora_dpscl_cs.argtypes = [i, _dp, _dp, _dp, _dp, d, d, d, d, _dp, _dp]
         L.ora_gram.restype = None
         L.ora_gram.argtypes = [d, d, d, d, d, d, _dp, _dp, _dp, _dp]
         L.ora_rot.restype = d
@@ -69,7 +76,7 @@ def lib():
         L.ora_step_ext.restype = None
         L.ora_step_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, _ct.POINTER(i), _dp,
                                    _ct.c_long, _ct.POINTER(_ct.c_long), _ct.POINTER(_ct.c_long),
-                                   _ct.POINTER(i), i]
+                                   _ct.POINTER(i), _ct.c_uint]
         L.ora_finalize_ext.restype = None
         L.ora_finalize_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, i, _dp, _dp]
         L.ora_gesvj.restype = i
@@ -165,6 +172,28 @@ def dpscl(qr, qi, pr, pi, eq, fq, ep, fp):
     return zr.value, zi.value
 
 
+def mul_rd(a, b):
+    """RD(a b), the product rounded toward -infinity (Sect. SM2.2, item G.)."""
+    return lib().ora_mul_rd(a, b)
+
+
+def two_sum(a, b):
+    """eq. (d2sum): (s, t) with s = fl(a + b) and a + b = s + t."""
+    s, t = _ct.c_double(), _ct.c_double()
+    lib().ora_2sum(a, b, s, t)
+    return s.value, t.value
+
+
+def dpscl_cs(qr, qi, pr, pi, eq, fq, ep, fp):
+    """Alg. zdpsclcs / ddpsclcs: the compensated scaled dot-product."""
+    zr, zi = _ct.c_double(), _ct.c_double()
+    qr, pr = (_np.ascontiguousarray(a, dtype=_np.float64) for a in (qr, pr))
+    qi = None if qi is None else _np.ascontiguousarray(qi, dtype=_np.float64)
+    pi = None if pi is None else _np.ascontiguousarray(pi, dtype=_np.float64)
+    lib().ora_dpscl_cs(qr.shape[0], _p(qr), _p(qi), _p(pr), _p(pi), eq, fq, ep, fp, zr, zi)
+    return zr.value, zi.value
+
+
 def gram(zr, zi, e1, f1, e2, f2):
     o = [_ct.c_double() for _ in range(4)]
     lib().ora_gram(zr, zi, e1, f1, e2, f2, *o)
@@ -180,8 +209,9 @@ def rot(xpr, xpi, xqr, xqi, c, C, S, swap):
 class State:
     """Oracle SVD state on host numpy arrays (column-major)."""
 
-    def __init__(self, G_re, G_im=None, nosort=False):
+    def __init__(self, G_re, G_im=None, nosort=False, compensated=False):
         self.nosort = bool(nosort)
+        self.compensated = bool(compensated)
         self.m, self.n = G_re.shape
         self.cplx = G_im is not None
         self.Gr = _np.array(G_re, dtype=_np.float64, order="F", copy=True)
@@ -210,7 +240,8 @@ class State:
     def step(self):
         s, Mt = _ct.c_int(self.s), _ct.c_double(self.Mt)
         t, sw, r = _ct.c_long(), _ct.c_long(), _ct.c_int()
-        lib().ora_step_ext(*self._args(), s, Mt, self.k, t, sw, r, int(self.nosort))
+        flags = (NO_PERMUTE if self.nosort else 0) | (COMPENSATED if self.compensated else 0)
+        lib().ora_step_ext(*self._args(), s, Mt, self.k, t, sw, r, flags)
         self.s, self.Mt, self.last_t, self.last_sw = s.value, Mt.value, t.value, sw.value
         self.rescaled += r.value
         self.k += 1

@@ -1,7 +1,9 @@
 """Build the CPU oracle shared library (test infrastructure only).
 
 The oracle is plain C compiled with gcc, contraction of a*b+c into fma
-disabled, no fast-math, round-to-nearest-even, gradual underflow.
+disabled, no fast-math, round-to-nearest-even (switched to rounding toward
+-infinity only around the one product that asks for it, hence
+-frounding-math), gradual underflow.
 """
 import os
 import subprocess
@@ -10,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["ora_evd2.c", "ora_svd.c"]
 LIB = os.path.join(HERE, "liboracle.so")
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only",
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only", "-frounding-math",
           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-D_GNU_SOURCE"]
 
 

@@ -8,6 +8,7 @@
  * out (build with -ffp-contract=off).  Readings where the paper leaves a
  * choice open are stated next to the code that takes them.
  */
+#include <fenv.h>
 #include <float.h>
 #include <math.h>
 #include <stdint.h>
@@ -197,6 +198,94 @@ void ora_dpscl(int m, const double *qr, const double *qi, const double *pr, cons
     *zi = qi ? hi / d : 0.0;
 }
 
+/* ------------------------------------------------------------------ */
+/* compensated scaled dot-product (Sect. SM2.2, Alg. zdpsclcs/ddpsclcs) */
+/* ------------------------------------------------------------------ */
+
+/* RD(a b): the product rounded toward -infinity, computed by the host FPU
+ * switched to that rounding mode (item G. of Sect. SM2.2).  The library is
+ * built with -frounding-math, so the multiplication is not moved across
+ * the mode switches or folded at compile time. */
+double ora_mul_rd(double a, double b)
+{
+    const int old = fegetround();
+    fesetround(FE_DOWNWARD);
+    volatile double c = a * b;
+    fesetround(old);
+    return c;
+}
+
+/* eq. (d2sum), Moller's 2Sum: s = fl(a + b) and a + b = s + t exactly. */
+void ora_2sum(double a, double b, double *s, double *t)
+{
+    const double s0 = a + b;
+    double a1 = s0 - b;
+    double b1 = s0 - a1;
+    a1 = a - a1;
+    b1 = b - b1;
+    *s = s0;
+    *t = a1 + b1;
+}
+
+/* One product term of the compensated sums: c = RD(x y) and c' = x y - c
+ * (one fma), then Kahan's update of the value stream (s, t) with c and of
+ * the error stream (s', t') with c', each by 2Sum (items G., M., K.). */
+static void cs_term(double x, double y, double *s, double *t, double *s2, double *t2)
+{
+    const double c = ora_mul_rd(x, y);
+    const double c2 = fma(x, y, -c);
+    ora_2sum(*s, c + *t, s, t);
+    ora_2sum(*s2, c2 + *t2, s2, t2);
+}
+
+/* Alg. zdpsclcs / ddpsclcs: the scaled dot-product g_q^* g_p / (|g_q| |g_p|)
+ * with compensated summation.  Each lane of the 1024-lane vector keeps four
+ * partial sums per real stream (s, t of the rounded-down products, s', t' of
+ * their errors); the lanes are reduced one sum at a time by the halving
+ * tree, and the four totals are added as ((s' + t') + t) + s (the real
+ * algorithm writes s + (t + (s' + t')), the same value since floating-point
+ * addition commutes).
+ *
+ * Reading: the paper states the result as g_q^* g_p for both routines, as
+ * in Alg. zdpscl, but the imaginary-part updates printed in Alg. zdpsclcs
+ * form Re(g_p) Im(g_q) - Im(g_p) Re(g_q), the imaginary part of g_p^* g_q.
+ * The stated result is taken: the imaginary stream adds Re(g_q) Im(g_p),
+ * then (-Im(g_q)) Re(g_p) (the sign flipped on the operand before the
+ * rounded-down product, as the algorithm flips it). */
+void ora_dpscl_cs(int m, const double *qr, const double *qi, const double *pr, const double *pi,
+                  double eq, double fq, double ep, double fp, double *zr, double *zi)
+{
+    static _Thread_local double acc[8][ORA_LANES];
+    const int Eq = (int)eq, Ep = (int)ep;
+    const int P = lanes_used(m);
+    for (int a = 0; a < 8; ++a) memset(acc[a], 0, sizeof(double) * (size_t)P);
+    double *rs = acc[0], *rt = acc[1], *rs2 = acc[2], *rt2 = acc[3];
+    double *is = acc[4], *it = acc[5], *is2 = acc[6], *it2 = acc[7];
+    for (int i = 0; i < m; ++i) {
+        const int L = i % ORA_LANES;
+        const double gpr = scalbn(pr[i], -Ep), gqr = scalbn(qr[i], -Eq);
+        cs_term(gpr, gqr, &rs[L], &rt[L], &rs2[L], &rt2[L]);
+        if (qi) {
+            const double gpi = scalbn(pi[i], -Ep), gqi = scalbn(qi[i], -Eq);
+            cs_term(gpi, gqi, &rs[L], &rt[L], &rs2[L], &rt2[L]);
+            cs_term(gqr, gpi, &is[L], &it[L], &is2[L], &it2[L]);
+            cs_term(-gqi, gpr, &is[L], &it[L], &is2[L], &it2[L]);
+        }
+    }
+    double hr = lanes_reduce(rs2, P) + lanes_reduce(rt2, P);
+    hr = hr + lanes_reduce(rt, P);
+    hr = hr + lanes_reduce(rs, P);
+    double hi = 0.0;
+    if (qi) {
+        hi = lanes_reduce(is2, P) + lanes_reduce(it2, P);
+        hi = hi + lanes_reduce(it, P);
+        hi = hi + lanes_reduce(is, P);
+    }
+    const double d = fq * fp;
+    *zr = hr / d;
+    *zi = qi ? hi / d : 0.0;
+}
+
 /* Alg. Gram with eqs. (sGramEF), (efpq), (F): the diagonal entries are
  * ||g_p||/||g_q|| and ||g_q||/||g_p|| in normalised (e,f) form, and the
  * whole matrix is scaled by 2^{s_A}, s_A = min(DBL_MAX_EXP-1 - max(e12,e21), 0). */
@@ -362,7 +451,10 @@ void ora_step(ora_svd *st)
             pbit = isinf(ep) && !isinf(eq);
         } else {
             double zr, zi;
-            ora_dpscl(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
+            if (st->comp)
+                ora_dpscl_cs(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
+            else
+                ora_dpscl(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
             const double az = cplx ? ora_hypot(zr, zi) : fabs(zr);
             transform = (ups <= az);
             double a11, a22, a21r, a21i;
@@ -463,6 +555,7 @@ int ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
     st.Gr = Gr; st.Gi = Gi; st.ldg = ldg;
     st.Vr = Vr; st.Vi = Vi; st.ldv = ldv;
     st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.comp = (flags & ORA_COMPENSATED) != 0;
     if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1) return ORA_EINVAL;
     st.e = (double *)malloc(sizeof(double) * (size_t)n);
     st.f = (double *)malloc(sizeof(double) * (size_t)n);
@@ -530,14 +623,15 @@ int ora_init_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
 
 void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                   double *Vr, double *Vi, size_t ldv, double *e, double *f,
-                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, int nosort)
+                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, unsigned flags)
 {
     ora_svd st;
     fill(&st, m, n, Gr, Gi, ldg, Vr, Vi, ldv, e, f);
     st.s = *s;
     st.Mt = *Mt;
     st.k = k;
-    st.nosort = nosort;
+    st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.comp = (flags & ORA_COMPENSATED) != 0;
     ora_step(&st);
     *s = st.s;
     *Mt = st.Mt;

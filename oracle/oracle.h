@@ -77,6 +77,12 @@ void ora_colnorm(int m, const double *xr, const double *xi, double *e, double *f
 /* Scaled dot-product a21' = g_q^* g_p / (||g_q|| ||g_p||) (Alg. zdpscl). */
 void ora_dpscl(int m, const double *qr, const double *qi, const double *pr, const double *pi,
                double eq, double fq, double ep, double fp, double *zr, double *zi);
+/* Sect. SM2.2: RD(a b) (product rounded toward -infinity), eq. (d2sum) 2Sum,
+ * and Alg. zdpsclcs / ddpsclcs (compensated scaled dot-product). */
+double ora_mul_rd(double a, double b);
+void ora_2sum(double a, double b, double *s, double *t);
+void ora_dpscl_cs(int m, const double *qr, const double *qi, const double *pr, const double *pi,
+                  double eq, double fq, double ep, double fp, double *zr, double *zi);
 /* Scaled Gram matrix A'' (Alg. Gram). */
 void ora_gram(double zr, double zi, double e1, double f1, double e2, double f2,
               double *a11, double *a22, double *a21r, double *a21i);
@@ -101,9 +107,11 @@ typedef struct {
     long last_sw;                  /* swaps without transformation in the last step */
     int  rescaled;                 /* number of step-start downscalings */
     int  nosort;                   /* apply U instead of U P (ignore the EVD's permutation) */
+    int  comp;                     /* scaled dot-products with compensated summation */
 } ora_svd;
 
 #define ORA_NO_PERMUTE 1u
+#define ORA_COMPENSATED 2u      /* Alg. zdpsclcs / ddpsclcs instead of zdpscl */
 
 #define ORA_OK 0
 #define ORA_NOT_CONVERGED 1
@@ -133,7 +141,7 @@ int  ora_init_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                   int *s, double *Mt);
 void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                   double *Vr, double *Vi, size_t ldv, double *e, double *f,
-                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, int nosort);
+                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, unsigned flags);
 void ora_finalize_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                       double *Vr, double *Vi, size_t ldv, double *e, double *f,
                       int s, double *sv_e, double *sv_f);

@@ -20,7 +20,8 @@ import os as _os
 
 __all__ = [
     "lib", "JsvdError", "fortran_empty", "to_device_fortran", "evd2_batched", "State", "gesvj",
-    "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE",
+    "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "COMPENSATED",
+    "dot_scaled_batched",
 ]
 
 _HERE = _os.path.dirname(_os.path.abspath(__file__))
@@ -29,6 +30,7 @@ LIB_PATH = _os.path.join(_HERE, "libjsvd.so")
 OK, NOT_CONVERGED, EINVAL, ENONFINITE, EZERO, ENOMEM, EDEVICE, EAGAIN, ENOTFOUND = 0, 1, -1, -2, -3, -4, -5, -6, -7
 EVD_SCALED, EVD_SINFORM = 1, 2
 NO_PERMUTE = 1
+COMPENSATED = 2
 
 _lib = None
 
@@ -101,6 +103,10 @@ def lib():
         L.jsvd_state_finalize.argtypes = [vp, vp, vp, sz, vp, vp, sz, vp, vp, vp, vp]
         L.jsvd_state_set_launch.restype = i
         L.jsvd_state_set_launch.argtypes = [vp, i]
+        L.jsvd_state_set_flags.restype = i
+        L.jsvd_state_set_flags.argtypes = [vp, u]
+        L.jsvd_dot_scaled_batched.restype = i
+        L.jsvd_dot_scaled_batched.argtypes = [i, i, vp, vp, vp, vp, sz, vp, vp, vp, vp, vp, vp, u, vp]
         L.jsvd_gesvj.restype = i
         L.jsvd_gesvj.argtypes = [i, i, vp, vp, sz, vp, vp, sz, vp, vp, vp, i, _ct.POINTER(i), u, vp]
         L.jsvd_gesvj_batched.restype = i
@@ -213,6 +219,26 @@ def evd2_batched(a11, a22, a21_re, a21_im=None, flags=0, out=None, with_lambda=T
     return out
 
 
+def dot_scaled_batched(Q_re, P_re, eq, fq, ep, fp, Q_im=None, P_im=None, flags=0, stream=None):
+    """Batched scaled dot-products (jsvd_dot_scaled_batched): for every column j
+    of the m x npairs column-major tensors, z_j = (q_j 2^-eq_j)^* (p_j 2^-ep_j)
+    / (fq_j fp_j).  Returns (z_re, z_im) (z_im None for real data)."""
+    torch = _torch()
+    m, npairs = Q_re.shape
+    ld = _mat(Q_re, m, npairs, "Q_re")
+    for t, nm in ((P_re, "P_re"), (Q_im, "Q_im"), (P_im, "P_im")):
+        if t is not None and _mat(t, m, npairs, nm) != ld:
+            raise ValueError(f"{nm}: leading dimension differs from Q_re's")
+    for t, nm in ((eq, "eq"), (fq, "fq"), (ep, "ep"), (fp, "fp")):
+        _vec(t, npairs, nm)
+    z_re = torch.empty(npairs, dtype=torch.float64, device=Q_re.device)
+    z_im = torch.empty(npairs, dtype=torch.float64, device=Q_re.device) if Q_im is not None else None
+    _check(lib().jsvd_dot_scaled_batched(npairs, m, _ptr(Q_re), _ptr(Q_im), _ptr(P_re), _ptr(P_im), ld,
+                                         _ptr(eq), _ptr(fq), _ptr(ep), _ptr(fp), _ptr(z_re), _ptr(z_im),
+                                         flags, _stream(stream)), "jsvd_dot_scaled_batched")
+    return z_re, z_im
+
+
 # ---------------------------------------------------------------------------- state
 class State:
     """Device-resident SVD state (jsvd_state_*): the hot path one step at a time."""
@@ -240,6 +266,9 @@ class State:
 
     def set_launch(self, threads):
         _check(lib().jsvd_state_set_launch(self._h, threads), "jsvd_state_set_launch")
+
+    def set_flags(self, flags):
+        _check(lib().jsvd_state_set_flags(self._h, flags), "jsvd_state_set_flags")
 
     def step(self, stream=None):
         _check(lib().jsvd_step(self._h, _stream(stream)), "jsvd_step")

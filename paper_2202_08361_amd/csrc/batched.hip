@@ -117,7 +117,7 @@ __device__ __forceinline__ Norm wave_colnorm(const double *xr, const double *xi,
     return o;
 }
 
-template <bool CPLX, int R>
+template <bool CPLX, int R, bool COMP>
 __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSmem &sm)
 {
     const int m = it.m, n = it.n;
@@ -203,7 +203,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSm
                             if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
                         }
                 }
-                const PairDecision dc = pair_core<CPLX, 64, R>(xr, xi, it.ups, nosort, nullptr, nullptr, nullptr);
+                const PairDecision dc = pair_core<CPLX, 64, R, COMP>(xr, xi, it.ups, nosort, nullptr, nullptr, nullptr);
                 const int pbit = dc.pbit;
                 double *const Dp_r = pbit ? Gqr : Gpr;
                 double *const Dq_r = pbit ? Gpr : Gqr;
@@ -407,6 +407,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSm
     }
 }
 
+template <bool COMP>
 __global__ __launch_bounds__(kBT) void batched_kernel(BatchItem *items, const int *order, BatchCtl *ctl)
 {
     __shared__ BatchSmem sm;
@@ -419,14 +420,14 @@ __global__ __launch_bounds__(kBT) void batched_kernel(BatchItem *items, const in
         if (idx >= count) return;
         BatchItem it = items[order[idx]];
         switch ((it.cplx ? 100 : 0) + it.R) {
-        case 1: svd_workgroup<false, 1>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 2: svd_workgroup<false, 2>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 4: svd_workgroup<false, 4>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 8: svd_workgroup<false, 8>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 101: svd_workgroup<true, 1>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 102: svd_workgroup<true, 2>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 104: svd_workgroup<true, 4>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 108: svd_workgroup<true, 8>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 1: svd_workgroup<false, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 2: svd_workgroup<false, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 4: svd_workgroup<false, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 8: svd_workgroup<false, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 101: svd_workgroup<true, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 102: svd_workgroup<true, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 104: svd_workgroup<true, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 108: svd_workgroup<true, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
         default: break;
         }
         if (threadIdx.x == 0) {
@@ -530,8 +531,12 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     bool ok = hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
     if (ok) {
         const int grid = std::min(cnt, 2 * ncu);
-        hipLaunchKernelGGL(batched_kernel, dim3(grid), dim3(kBT), 0, s, (BatchItem *)(dm + oItems),
-                           (const int *)(dm + oOrder), (BatchCtl *)(dm + oCtl));
+        if (flags & JSVD_COMPENSATED)
+            hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(kBT), 0, s, (BatchItem *)(dm + oItems),
+                               (const int *)(dm + oOrder), (BatchCtl *)(dm + oCtl));
+        else
+            hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(kBT), 0, s, (BatchItem *)(dm + oItems),
+                               (const int *)(dm + oOrder), (BatchCtl *)(dm + oCtl));
         ok = hipGetLastError() == hipSuccess &&
              hipMemcpyAsync(bl->host, dm, sizeof(BatchItem) * cnt, hipMemcpyDeviceToHost, s) == hipSuccess;
     }
@@ -566,7 +571,7 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
     if (count < 0) return JSVD_EINVAL;
     if (count == 0) return JSVD_OK;
     if (!m || !n || !G_re || !ldg || !V_re || !ldv || !sv_e || !sv_f || !status) return JSVD_EINVAL;
-    if (flags & ~JSVD_NO_PERMUTE) return JSVD_EINVAL;
+    if (flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED)) return JSVD_EINVAL;
     for (int i = 0; i < count; ++i) {
         const int c = is_complex ? is_complex[i] : 0;
         if (n[i] < 1 || m[i] < n[i] || !G_re[i] || !V_re[i] || !sv_e[i] || !sv_f[i] || ldg[i] < (size_t)m[i] ||

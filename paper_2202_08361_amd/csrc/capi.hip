@@ -140,6 +140,7 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     d.n = n;
     d.cplx = st->cplx;
     d.nosort = 0;
+    d.comp = 0;
     d.Gr = (double *)(b + L.oG);
     d.Gi = st->cplx ? d.Gr + (size_t)L.ldg * n : nullptr;
     d.ldg = L.ldg;
@@ -229,6 +230,24 @@ extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
     return JSVD_OK;
 }
 
+static constexpr unsigned kIterFlags = JSVD_NO_PERMUTE | JSVD_COMPENSATED;
+
+static void apply_flags(jsvd_state st, unsigned flags)
+{
+    st->flags = flags;
+    st->d.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+    st->d.comp = (flags & JSVD_COMPENSATED) ? 1 : 0;
+}
+
+extern "C" int jsvd_state_set_flags(jsvd_state st, unsigned flags)
+{
+    if (!st || (flags & ~kIterFlags)) return JSVD_EINVAL;
+    apply_flags(st, flags);
+    return JSVD_OK;
+}
+
+int jsvd::state_set_flags(jsvd_state st, unsigned flags) { return jsvd_state_set_flags(st, flags); }
+
 static int state_threads(jsvd_state st)
 {
     return st->threads ? st->threads : step_auto_threads(st->m, st->n);
@@ -268,7 +287,7 @@ static int capture_sweep(jsvd_state st, hipStream_t cs)
 static int build_graph(jsvd_state st)
 {
     const int thr = st->threads;
-    if (st->graph && st->graph_threads == thr) return JSVD_OK;
+    if (st->graph && st->graph_threads == thr && st->graph_flags == st->flags) return JSVD_OK;
     if (st->graph) {
         (void)hipGraphExecDestroy(st->graph);
         st->graph = nullptr;
@@ -300,6 +319,7 @@ static int build_graph(jsvd_state st)
     }
     st->graph_def = g;
     st->graph_threads = thr;
+    st->graph_flags = st->flags;
     return JSVD_OK;
 }
 
@@ -454,15 +474,34 @@ extern "C" int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg, 
     if (n < 1 || m < n || !G_re || !V_re || !sv_e || !sv_f || ldg < (size_t)m || ldv < (size_t)n)
         return JSVD_EINVAL;
     if ((G_im == nullptr) != (V_im == nullptr)) return JSVD_EINVAL;
-    if (flags & ~JSVD_NO_PERMUTE) return JSVD_EINVAL;
+    if (flags & ~kIterFlags) return JSVD_EINVAL;
     jsvd_state st = nullptr;
     int rc = jsvd_state_create(m, n, G_im != nullptr, &st);
     if (rc != JSVD_OK) return rc;
     st->max_sweeps = max_sweeps > 0 ? max_sweeps : 128;
-    st->d.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+    apply_flags(st, flags);
     rc = gesvj_on_state(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, sweeps, (hipStream_t)stream);
     jsvd_state_destroy(st);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// batched scaled dot-products
+extern "C" int jsvd_dot_scaled_batched(int npairs, int m, const double *Q_re, const double *Q_im,
+                                       const double *P_re, const double *P_im, size_t ld, const double *eq,
+                                       const double *fq, const double *ep, const double *fp, double *z_re,
+                                       double *z_im, unsigned flags, void *stream)
+{
+    if (flags & ~JSVD_COMPENSATED) return JSVD_EINVAL;
+    if (npairs < 0 || m < 1 || ld < (size_t)m) return JSVD_EINVAL;
+    const bool cplx = Q_im != nullptr;
+    if ((P_im != nullptr) != cplx || (z_im != nullptr && !cplx) || (cplx && !z_im)) return JSVD_EINVAL;
+    if (npairs == 0) return JSVD_OK;
+    if (!Q_re || !P_re || !eq || !fq || !ep || !fp || !z_re) return JSVD_EINVAL;
+    if (dot_rows(m, cplx) == 0) return JSVD_EINVAL;
+    HIPCHK(launch_dot(npairs, m, Q_re, Q_im, P_re, P_im, (long long)ld, eq, fq, ep, fp, z_re, z_im,
+                      (flags & JSVD_COMPENSATED) != 0, (hipStream_t)stream));
+    return JSVD_OK;
 }
 
 // ---------------------------------------------------------------------------

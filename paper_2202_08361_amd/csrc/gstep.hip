@@ -28,12 +28,13 @@ constexpr int kPW = 256;   // threads per pivot pair of the G kernel
 // G part of the step: one workgroup of W = 256 threads per pivot pair, the
 // pair held in registers from its load to its store.  At most 256 VGPRs, so
 // two workgroups share a compute unit and one computes (reductions, EVD)
-// while the other waits on its loads or stores.  The outcome of the pair
+// while the other waits on its loads or stores (the compensated dot-products
+// need more registers and run one workgroup per compute unit).  The outcome of the pair
 // (rotation, permutation, max-norm of the rotated columns) goes to prm.
-template <bool CPLX, int W, int R>
-__global__ __launch_bounds__(W, W / 128) void gpair_kernel(SvdDesc d, PairParam *prm)
+template <bool CPLX, int W, int R, bool COMP>
+__global__ __launch_bounds__(W, COMP ? 1 : W / 128) void gpair_kernel(SvdDesc d, PairParam *prm)
 {
-    __shared__ double red[6 * W];
+    __shared__ double red[(COMP ? 12 : 6) * W];
     __shared__ double mxs[4 * (W / 64)];
     DevScalars *sc = d.sc;
     if (*(volatile int *)&sc->stop) return;
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(W, W / 128) void gpair_kernel(SvdDesc d, PairParam 
                     if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
                 }
         }
-        const PairDecision dc = pair_core<CPLX, W, R>(xr, xi, d.ups, d.nosort, red, red + 4 * W, mxs);
+        const PairDecision dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, red, red + 4 * W, mxs);
         const int pbit = dc.pbit;
         double *const Dp_r = pbit ? Gqr : Gpr;
         double *const Dq_r = pbit ? Gpr : Gqr;
@@ -277,7 +278,10 @@ static hipError_t launch_gpair_t(const SvdDesc &d, PairParam *prm, int R, hipStr
 #define JSVD_GP(r)                                                                                    \
     case r:                                                                                           \
         if constexpr (r <= RM) {                                                                      \
-            hipLaunchKernelGGL((gpair_kernel<CPLX, kPW, r>), dim3(npairs), dim3(kPW), 0, s, d, prm); \
+            if (d.comp)                                                                               \
+                hipLaunchKernelGGL((gpair_kernel<CPLX, kPW, r, true>), dim3(npairs), dim3(kPW), 0, s, d, prm); \
+            else                                                                                      \
+                hipLaunchKernelGGL((gpair_kernel<CPLX, kPW, r, false>), dim3(npairs), dim3(kPW), 0, s, d, prm); \
             return hipGetLastError();                                                                 \
         }                                                                                             \
         break;

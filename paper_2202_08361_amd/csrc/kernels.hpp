@@ -39,6 +39,7 @@ struct SvdDesc {
     int m, n;
     int cplx;
     int nosort;            // ignore the permutation of the EVD during the iteration
+    int comp;              // compensated scaled dot-products (Alg. zdpsclcs / ddpsclcs)
     double *Gr, *Gi;       // working iteration matrix
     long long ldg;
     double *Vr, *Vi;       // accumulated right transformations
@@ -65,6 +66,13 @@ struct PairParam {
 int gpair_rows(int m, int cplx);
 hipError_t launch_vrot(const SvdDesc &d, const PairParam *prm, hipStream_t s);
 hipError_t launch_gpair(const SvdDesc &d, PairParam *prm, hipStream_t s);
+
+// batched scaled dot-products (dot.hip): rows per thread for m (0 = not
+// supported) and the launch (one workgroup per column pair)
+int dot_rows(int m, int cplx);
+hipError_t launch_dot(int npairs, int m, const double *Qr, const double *Qi, const double *Pr, const double *Pi,
+                      long long ld, const double *eq, const double *fq, const double *ep, const double *fp,
+                      double *zr, double *zi, bool comp, hipStream_t s);
 
 // initialisation: M~_0 into *maxbits (zeroed by the caller), then
 // G <- 2^{s_0} A copied into the workspace and V <- I

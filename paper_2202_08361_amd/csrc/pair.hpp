@@ -177,6 +177,75 @@ __device__ __forceinline__ double thread_tree(double (&acc)[NL])
 }
 
 // ---------------------------------------------------------------------------
+// Compensated summation (Sect. SM2.2): RD(a b), the product rounded toward
+// -infinity (item G.), without touching the rounding mode of the wave.
+// A product of magnitude >= 2^-960 has an exactly representable error
+// a b - fl(a b), which one fma yields; then RD(a b) is fl(a b) when that
+// error is >= 0 and the next double towards -infinity otherwise.  Smaller
+// products, zeros and non-finite values take the exact slow path.
+__device__ __noinline__ double mul_rd_slow(double a, double b, double p)
+{
+    if (p != p || a == 0.0 || b == 0.0 || __builtin_isinf(a) || __builtin_isinf(b)) return p;
+    const bool neg = (a < 0.0) != (b < 0.0);
+    if (__builtin_isinf(p)) return neg ? -INFINITY : 1.79769313486231570815e308;
+    // |a b| < 2^-960: a b = (hi + lo) 2^E exactly, with a', b' in [1, 2)
+    const int ea = getexp(a), eb = getexp(b);
+    const double am = scal2(fabs(a), -ea), bm = scal2(fabs(b), -eb);
+    const double hi = am * bm;
+    const double lo = fma(am, bm, -hi);
+    const int E = ea + eb;
+    if (E + getexp(hi) >= -1022) {
+        // normal result: fl(|a b|) = hi 2^E exactly; step down when the exact
+        // value lies below the rounded one
+        const double r = neg ? -scal2(hi, E) : scal2(hi, E);
+        const bool down = neg ? (lo > 0.0) : (lo < 0.0);
+        return down ? __longlong_as_double(__double_as_longlong(r) + (neg ? 1 : -1)) : r;
+    }
+    // subnormal result: the grid is 2^-1074, |a b| 2^1074 = (hi + lo) 2^S
+    const int S = E + 1074;
+    if (S < -2) return neg ? -4.9406564584124654e-324 : 0.0;   // 0 < |a b| < 2^-1074
+    const double q = scal2(hi, S);    // exact, >= 1/4
+    const double f = floor(q);
+    const double fr = q - f;          // exact; when > 0 it exceeds |lo| 2^S
+    if (!neg) return scal2((fr == 0.0 && lo < 0.0) ? f - 1.0 : f, -1074);
+    return -scal2((fr > 0.0 || lo > 0.0) ? f + 1.0 : f, -1074);
+}
+
+__device__ __forceinline__ double mul_rd(double a, double b)
+{
+    const double p = a * b;
+    const double ap = fabs(p);
+    if (ap >= 0x1p-960 && ap <= 1.79769313486231570815e308) {
+        const double e = fma(a, b, -p);
+        if (e < 0.0) return __longlong_as_double(__double_as_longlong(p) + (p > 0.0 ? -1 : 1));
+        return p;
+    }
+    return mul_rd_slow(a, b, p);
+}
+
+// eq. (d2sum): s = fl(a + b), a + b = s + t exactly
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &t)
+{
+    const double s0 = a + b;
+    double a1 = s0 - b;
+    double b1 = s0 - a1;
+    a1 = a - a1;
+    b1 = b - b1;
+    s = s0;
+    t = a1 + b1;
+}
+
+// Kahan's summation with 2Sum of c = RD(x y) into (s, t) and of c' = x y - c
+// into (s', t') (items G., M., K.)
+__device__ __forceinline__ void cs_term(double x, double y, double &s, double &t, double &s2, double &t2)
+{
+    const double c = mul_rd(x, y);
+    const double c2 = fma(x, y, -c);
+    two_sum(s, c + t, s, t);
+    two_sum(s2, c2 + t2, s2, t2);
+}
+
+// ---------------------------------------------------------------------------
 // Column norm in (e, f) form (Sect. 3.2 and SM6.1): prescale by 2^-E with
 // E = floor(lg max|x|), canonical sum of squares, sqrt, and for complex data
 // the naive hypot of the real and imaginary norms.  Zero column: e = -inf.
@@ -223,6 +292,93 @@ __device__ __forceinline__ void gram_scaled(double zr, double zi, int e1, double
     *a21i = scal2(zi, sA);
 }
 
+// The scaled dot-product of the pair without its final division, \hat z =
+// (g_q 2^-e_q)^* (g_p 2^-e_p), in the canonical lane order (h[0] = Re,
+// h[1] = Im): Alg. zdpscl (fma per lane), or with COMP Alg. zdpsclcs /
+// ddpsclcs (compensated per lane; the four sums of each real stream reduced
+// one by one and added as ((s' + t') + t) + s).  The imaginary stream takes
+// Re(g_q) Im(g_p), then (-Im(g_q)) Re(g_p), which is the stated result
+// g_q^* g_p.  lds: (COMP ? 4 : 1) * (CPLX ? 2 : 1) * W doubles (W > 64).
+template <bool CPLX, int W, int R, bool COMP>
+__device__ __forceinline__ void pair_dot(const double (&xr)[2][R], const double (&xi)[2][R], int ep, int eq,
+                                         double (&h)[2], double *lds)
+{
+    using LS = LaneShape<W, R>;
+    constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
+    if constexpr (!COMP) {
+        double dr[NL], di[NL];
+#pragma unroll
+        for (int v = 0; v < NL; ++v) {
+            dr[v] = 0.0;
+            di[v] = 0.0;
+        }
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int v = 0; v < NL; ++v) {
+                const int j = ch * V + v;
+                if (j < R) {
+                    const double gqr = scal2(xr[1][j], -eq), gpr = scal2(xr[0][j], -ep);
+                    if (CPLX) {
+                        const double gqi = scal2(xi[1][j], -eq), gpi = scal2(xi[0][j], -ep);
+                        dr[v] = fma(gqr, gpr, dr[v]);
+                        di[v] = fma(gqr, gpi, di[v]);
+                        dr[v] = fma(gqi, gpi, dr[v]);
+                        di[v] = fma(-gqi, gpr, di[v]);
+                    } else {
+                        dr[v] = fma(gqr, gpr, dr[v]);
+                    }
+                }
+            }
+        constexpr int ND = CPLX ? 2 : 1;
+        double g[ND];
+        g[0] = thread_tree<V>(dr);
+        if (CPLX) g[ND - 1] = thread_tree<V>(di);
+        group_tree_sum<W, ND>(g, lds);
+        h[0] = g[0];
+        h[1] = CPLX ? g[ND - 1] : 0.0;
+    } else {
+        // [stream][s, t, s', t'][lane]
+        constexpr int NS = CPLX ? 2 : 1;
+        double a[NS][4][NL];
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < NL; ++v) a[st][u][v] = 0.0;
+#pragma unroll
+        for (int ch = 0; ch < CH; ++ch)
+#pragma unroll
+            for (int v = 0; v < NL; ++v) {
+                const int j = ch * V + v;
+                if (j < R) {
+                    const double gpr = scal2(xr[0][j], -ep), gqr = scal2(xr[1][j], -eq);
+                    cs_term(gpr, gqr, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v]);
+                    if (CPLX) {
+                        const double gpi = scal2(xi[0][j], -ep), gqi = scal2(xi[1][j], -eq);
+                        cs_term(gpi, gqi, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v]);
+                        cs_term(gqr, gpi, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v], a[NS - 1][3][v]);
+                        cs_term(-gqi, gpr, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v], a[NS - 1][3][v]);
+                    }
+                }
+            }
+        double g[4 * NS];
+#pragma unroll
+        for (int st = 0; st < NS; ++st)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) g[4 * st + u] = thread_tree<V>(a[st][u]);
+        group_tree_sum<W, 4 * NS>(g, lds);
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            double z = g[4 * st + 2] + g[4 * st + 3];
+            z = z + g[4 * st + 1];
+            h[st] = z + g[4 * st + 0];
+        }
+        if (!CPLX) h[1] = 0.0;
+    }
+}
+
 // Decision for one pivot pair held in registers by a group of W threads.
 struct PairDecision {
     Norm np, nq;   // the column norms (e, f) before the transformation
@@ -231,12 +387,13 @@ struct PairDecision {
     double c, C, S;
 };
 
-// Norms (Sect. 3.2), scaled dot-product (Alg. zdpscl), convergence test
-// (Alg. cvg), scaled Gram matrix (Alg. Gram) and 2x2 EVD (Listing 1) of the
-// pair (xr/xi[0] = column p, [1] = column q; rows t + W j, zeros beyond m).
-// Scratch: red_norm (4 W doubles), red_dot (2 W doubles), mxs (2 W/64 doubles);
+// Norms (Sect. 3.2), scaled dot-product (Alg. zdpscl, or zdpsclcs /
+// ddpsclcs with COMP), convergence test (Alg. cvg), scaled Gram matrix
+// (Alg. Gram) and 2x2 EVD (Listing 1) of the pair (xr/xi[0] = column p,
+// [1] = column q; rows t + W j, zeros beyond m).  Scratch: red_norm (4 W
+// doubles), red_dot (2 W doubles, 8 W with COMP), mxs (2 W/64 doubles);
 // unused for W = 64.  Every thread returns the same decision.
-template <bool CPLX, int W, int R>
+template <bool CPLX, int W, int R, bool COMP = false>
 __device__ __forceinline__ PairDecision pair_core(const double (&xr)[2][R], const double (&xi)[2][R], double ups,
                                                   int nosort, double *red_norm, double *red_dot, double *mxs)
 {
@@ -293,38 +450,11 @@ __device__ __forceinline__ PairDecision pair_core(const double (&xr)[2][R], cons
         // a zero column is never rotated; it goes after the other one
         o.pbit = (zp_ && !zq_) ? 1 : 0;
     } else {
-        double dr[NL], di[NL];
-#pragma unroll
-        for (int v = 0; v < NL; ++v) {
-            dr[v] = 0.0;
-            di[v] = 0.0;
-        }
-#pragma unroll
-        for (int ch = 0; ch < CH; ++ch)
-#pragma unroll
-            for (int v = 0; v < NL; ++v) {
-                const int j = ch * V + v;
-                if (j < R) {
-                    const double gqr = scal2(xr[1][j], -o.nq.e), gpr = scal2(xr[0][j], -o.np.e);
-                    if (CPLX) {
-                        const double gqi = scal2(xi[1][j], -o.nq.e), gpi = scal2(xi[0][j], -o.np.e);
-                        dr[v] = fma(gqr, gpr, dr[v]);
-                        di[v] = fma(gqr, gpi, di[v]);
-                        dr[v] = fma(gqi, gpi, dr[v]);
-                        di[v] = fma(-gqi, gpr, di[v]);
-                    } else {
-                        dr[v] = fma(gqr, gpr, dr[v]);
-                    }
-                }
-            }
-        constexpr int ND = CPLX ? 2 : 1;
-        double h[ND];
-        h[0] = thread_tree<V>(dr);
-        if (CPLX) h[ND - 1] = thread_tree<V>(di);
-        group_tree_sum<W, ND>(h, red_dot);
+        double h[2];
+        pair_dot<CPLX, W, R, COMP>(xr, xi, o.np.e, o.nq.e, h, red_dot);
         const double dd = o.nq.f * o.np.f;
         const double zr = h[0] / dd;
-        const double zi = CPLX ? h[ND - 1] / dd : 0.0;
+        const double zi = CPLX ? h[1] / dd : 0.0;
         const double az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
         o.transform = ups <= az;
         double a11, a22, a21r, a21i;

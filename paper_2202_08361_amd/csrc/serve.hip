@@ -255,7 +255,9 @@ static bool admit(jsvd_server sv)
         rc = jsvd_state_create(r.m, r.n, r.is_complex, &s.st);
         if (rc == JSVD_OK) {
             s.st->max_sweeps = sv->cfg.max_sweeps > 0 ? sv->cfg.max_sweeps : 128;
-            s.st->d.nosort = (sv->cfg.flags & JSVD_NO_PERMUTE) ? 1 : 0;
+            rc = state_set_flags(s.st, sv->cfg.flags);
+        }
+        if (rc == JSVD_OK) {
             rc = state_load_async(s.st, r.G_re, r.is_complex ? r.G_im : nullptr, r.ldg, s.stream);
         }
         if (rc == JSVD_OK) rc = state_sweep_async(s.st, s.stream);
@@ -319,7 +321,7 @@ extern "C" int jsvd_serve_create(const jsvd_serve_config *cfg, jsvd_server *out)
     if (!out) return JSVD_EINVAL;
     *out = nullptr;
     if (!cfg || cfg->max_slots < 1 || cfg->max_slots > 1024 || cfg->hbm_budget_bytes == 0 ||
-        (cfg->flags & ~JSVD_NO_PERMUTE))
+        (cfg->flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED)))
         return JSVD_EINVAL;
     jsvd_server sv = new (std::nothrow) jsvd_server_s;
     if (!sv) return JSVD_ENOMEM;

@@ -25,12 +25,17 @@ struct jsvd_state_s {
     hipGraphExec_t graph;
     hipGraph_t graph_def;
     int graph_threads;
+    unsigned flags;          // JSVD_NO_PERMUTE | JSVD_COMPENSATED of the iteration
+    unsigned graph_flags;    // flags the captured sweep was built with
 };
 
 namespace jsvd {
 
 // Bytes of device memory a state for this problem allocates.
 size_t state_bytes(int m, int n, int cplx);
+
+// Set the iteration flags (JSVD_NO_PERMUTE | JSVD_COMPENSATED) of a state.
+int state_set_flags(jsvd_state st, unsigned flags);
 
 // Enqueue the load of G (M~_0, s_0, G_1 = 2^{s_0} G, V_1 = I); a non-finite or
 // zero G leaves the state stopped with that status.

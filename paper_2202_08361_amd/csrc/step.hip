@@ -22,18 +22,18 @@
 
 namespace jsvd {
 
-template <int W>
+template <int W, bool COMP>
 struct StepSmem {
     double norm[4 * W];
-    double dot[2 * W];
+    double dot[(COMP ? 8 : 2) * W];
     double mx1[2 * (W / 64)];
     double mx2[W / 64];
 };
 
-template <bool CPLX, int W, int R>
+template <bool CPLX, int W, int R, bool COMP>
 __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
 {
-    __shared__ StepSmem<W> sm;
+    __shared__ StepSmem<W, COMP> sm;
     DevScalars *sc = d.sc;
     if (*(volatile int *)&sc->stop) return;
     const long long k = *(volatile long long *)&sc->k;
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                 }
         }
 
-        const PairDecision dc = pair_core<CPLX, W, R>(xr, xi, d.ups, d.nosort, sm.norm, sm.dot, sm.mx1);
+        const PairDecision dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, sm.norm, sm.dot, sm.mx1);
         transform = dc.transform;
         pbit = dc.pbit;
         const Norm np_ = dc.np, nq_ = dc.nq;
@@ -223,13 +223,16 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
 }
 
 // ---------------------------------------------------------------------------
-// dispatch over (complex, W, R)
+// dispatch over (complex, W, R, compensated dot-products)
 template <bool CPLX, int W, int R>
 static hipError_t launch_step_t(const SvdDesc &d, hipStream_t s)
 {
     const int N = d.n + (d.n & 1);
     const unsigned blocks = (unsigned)(N / 2);
-    hipLaunchKernelGGL((step_kernel<CPLX, W, R>), dim3(blocks), dim3(W), 0, s, d);
+    if (d.comp)
+        hipLaunchKernelGGL((step_kernel<CPLX, W, R, true>), dim3(blocks), dim3(W), 0, s, d);
+    else
+        hipLaunchKernelGGL((step_kernel<CPLX, W, R, false>), dim3(blocks), dim3(W), 0, s, d);
     return hipGetLastError();
 }
 

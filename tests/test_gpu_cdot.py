@@ -1,0 +1,204 @@
+"""GPU parity of the scaled dot-products and of the compensated variant
+(Sect. SM2.2, Alg. zdpsclcs / ddpsclcs) against the CPU oracle, bit for bit:
+the batched dot-product entry point on random and adversarial data
+(products that round into and below the subnormal range exercise the exact
+slow path of the rounded-down product), and the Jacobi step, the whole SVD,
+the batched form and the server with JSVD_COMPENSATED."""
+import numpy as np
+import pytest
+
+from paper_2202_08361_amd import inputs
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def J():
+    import paper_2202_08361_amd as jsvd
+    return jsvd
+
+
+def _bits(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64)).view(np.int64)
+
+
+def _dev(a):
+    return torch.from_numpy(np.asfortranarray(a)).cuda()
+
+
+def _dev_cols(a):
+    """m x k column-major device copy."""
+    return J().to_device_fortran(np.asfortranarray(a))
+
+
+def _run_dot(ora, Q, P, Qi, Pi, eq, fq, ep, fp, flags):
+    k = Q.shape[1]
+    zr, zi = J().dot_scaled_batched(_dev_cols(Q), _dev_cols(P), _dev(eq), _dev(fq), _dev(ep), _dev(fp),
+                                    None if Qi is None else _dev_cols(Qi), None if Pi is None else _dev_cols(Pi),
+                                    flags=flags)
+    torch.cuda.synchronize()
+    fn = ora.dpscl_cs if flags & J().COMPENSATED else ora.dpscl
+    want = [fn(Q[:, j], None if Qi is None else Qi[:, j], P[:, j], None if Pi is None else Pi[:, j],
+               eq[j], fq[j], ep[j], fp[j]) for j in range(k)]
+    wr = np.array([w[0] for w in want])
+    assert np.array_equal(_bits(zr.cpu().numpy()), _bits(wr)), (flags, zr.cpu().numpy()[:4], wr[:4])
+    if Qi is not None:
+        wi = np.array([w[1] for w in want])
+        assert np.array_equal(_bits(zi.cpu().numpy()), _bits(wi)), flags
+
+
+def _norms(ora, X, Xi):
+    e, f = zip(*[ora.colnorm(X[:, j], None if Xi is None else Xi[:, j]) for j in range(X.shape[1])])
+    return np.array(e, dtype=np.float64), np.array(f, dtype=np.float64)
+
+
+@pytest.mark.parametrize("flags", [0, 2])
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("m", [1, 100, 1024, 1025, 3000, 4096])
+def test_dot_random_with_norms(ora, m, cplx, flags):
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 900 + m)
+    k = 6
+    Q = g.standard_normal((m, k)) * np.ldexp(1.0, g.integers(-30, 30, k))[None, :]
+    P = g.standard_normal((m, k))
+    Qi = g.standard_normal((m, k)) if cplx else None
+    Pi = g.standard_normal((m, k)) if cplx else None
+    eq, fq = _norms(ora, Q, Qi)
+    ep, fp = _norms(ora, P, Pi)
+    _run_dot(ora, Q, P, Qi, Pi, eq, fq, ep, fp, flags)
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_dot_compensated_adversarial(ora, cplx):
+    """e = 0, f = 1 (the raw sums): columns whose products are all tiny,
+    subnormal or around the 2^-960 / 2^-1022 thresholds of the rounded-down
+    product, both signs, with pairs cancelling in the same lane; plus the
+    sub-ulp and exact-cancellation patterns of the oracle's pins."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 950)
+    m = 2048
+    cols_q, cols_p = [], []
+    for lo, hi in ((-560, -500), (-540, -470), (-490, -470), (-1000, -900), (-600, -300), (-40, 40)):
+        a = g.uniform(1, 2, m) * np.ldexp(1.0, g.integers(lo, hi, m)) * g.choice([-1.0, 1.0], m)
+        b = g.uniform(1, 2, m) * np.ldexp(1.0, g.integers(lo, hi, m)) * g.choice([-1.0, 1.0], m)
+        cols_q.append(a)
+        cols_p.append(b)
+    # cancelling pairs in one lane: row i and row i + 1024
+    a = g.standard_normal(1024) * 2.0 ** -520
+    b = g.standard_normal(1024) * 2.0 ** -520
+    cols_q.append(np.concatenate([a, -a]))
+    cols_p.append(np.concatenate([b, b]))
+    a = g.standard_normal(1024)
+    b = g.standard_normal(1024)
+    cols_q.append(np.concatenate([a, -a]))
+    cols_p.append(np.concatenate([b, b]))
+    # subnormal operands
+    cols_q.append(g.integers(1, 2 ** 40, m) * 5e-324 * g.choice([-1.0, 1.0], m))
+    cols_p.append(g.uniform(0.5, 2.0, m) * np.ldexp(1.0, g.integers(0, 60, m)))
+    Q = np.stack(cols_q, axis=1)
+    P = np.stack(cols_p, axis=1)
+    k = Q.shape[1]
+    Qi = Pi = None
+    if cplx:
+        Qi = np.roll(Q, 1, axis=1) * -1.0
+        Pi = np.roll(P, 2, axis=1)
+    zeros, ones = np.zeros(k), np.ones(k)
+    for flags in (0, 2):
+        _run_dot(ora, Q, P, Qi, Pi, zeros, ones, zeros, ones, flags)
+
+
+def test_dot_invalid():
+    x = _dev_cols(np.ones((8, 2)))
+    v = _dev(np.zeros(2))
+    with pytest.raises(J().JsvdError):
+        J().dot_scaled_batched(x, x, v, v, v, v, flags=4)
+    big = _dev_cols(np.ones((8193, 1)))
+    v1 = _dev(np.zeros(1))
+    with pytest.raises(J().JsvdError):
+        J().dot_scaled_batched(big, big, v1, v1, v1, v1)
+
+
+def _check_state(ost, sv, tag):
+    assert np.array_equal(_bits(sv["G_re"].cpu().numpy()), _bits(ost.Gr)), tag + " G_re"
+    assert np.array_equal(_bits(sv["V_re"].cpu().numpy()), _bits(ost.Vr)), tag + " V_re"
+    if ost.cplx:
+        assert np.array_equal(_bits(sv["G_im"].cpu().numpy()), _bits(ost.Gi)), tag + " G_im"
+        assert np.array_equal(_bits(sv["V_im"].cpu().numpy()), _bits(ost.Vi)), tag + " V_im"
+    assert sv["s"] == ost.s and sv["Mt"] == ost.Mt and sv["k"] == ost.k, tag + " scalars"
+    assert np.array_equal(_bits(sv["e"].cpu().numpy()), _bits(ost.e)), tag + " e"
+    assert np.array_equal(_bits(sv["f"].cpu().numpy()), _bits(ost.f)), tag + " f"
+
+
+@pytest.mark.parametrize("m,n,cplx,threads", [(70, 24, True, 0), (100, 37, False, 0), (300, 40, False, 256),
+                                               (1500, 64, False, 0), (2100, 20, True, 0), (900, 31, True, 512)])
+def test_step_compensated_bitwise(ora, m, n, cplx, threads):
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 960 + m)
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    ost = ora.State(Ar, Ai, compensated=True)
+    assert ost.init() == ora.OK
+    st = J().State(m, n, cplx)
+    st.set_flags(J().COMPENSATED)
+    if threads:
+        st.set_launch(threads)
+    assert st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None) == 0
+    K = ora.rr_steps(n)
+    for k in range(K + 3):
+        ost.step()
+        st.step()
+        _check_state(ost, st.save(), f"step {k} m={m} n={n} cplx={cplx}")
+        assert st.query()["last_t"] == ost.last_t
+    # a sweep through the captured graph after a flag change is rebuilt with the flags
+    st.set_flags(0)
+    for _ in range(K):
+        ost.compensated = False
+        ost.step()
+    st.sweep()
+    _check_state(ost, st.save(), "sweep after set_flags(0)")
+
+
+@pytest.mark.parametrize("m,n,cplx,kappa", [(60, 33, True, 1e4), (129, 128, False, 1e8), (1100, 40, False, 1e3),
+                                              (600, 48, True, 1e6)])
+def test_gesvj_compensated_bitwise(ora, m, n, cplx, kappa):
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 970 + m)
+    sig = inputs.sigma_logspace(n, 1.0 / kappa)
+    Ar, Ai = inputs.svd_matrix(m, n, sig, g, cplx=cplx)
+    for flags in (J().COMPENSATED, J().COMPENSATED | J().NO_PERMUTE):
+        ro = ora.gesvj(Ar, Ai, flags=flags)
+        rg = J().gesvj(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None, flags=flags)
+        assert rg["status"] == ro["status"] and rg["sweeps"] == ro["sweeps"], (flags, rg["sweeps"], ro["sweeps"])
+        for key in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+            if ro[key] is None:
+                continue
+            assert np.array_equal(_bits(rg[key].cpu().numpy()), _bits(ro[key])), (flags, key)
+
+
+def test_batched_and_served_compensated(ora):
+    shapes = [(40, 33, True, 1e4), (128, 64, False, 1e6), (300, 257, False, 1e5), (9, 2, True, 10.0)]
+    g = inputs.rng(inputs.CFG_BATCHED, 980)
+    host = []
+    for (m, n, c, kappa) in shapes:
+        Ar, Ai = inputs.svd_matrix(m, n, inputs.sigma_logspace(n, 1.0 / kappa), g, cplx=c)
+        host.append((Ar, Ai))
+    flags = J().COMPENSATED
+    dev = [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host]
+    res = J().gesvj_batched(dev, flags=flags)
+    torch.cuda.synchronize()
+    for (Ar, Ai), rb in zip(host, res):
+        ro = ora.gesvj(Ar, Ai, flags=flags)
+        assert rb["status"] == ro["status"] and rb["sweeps"] == ro["sweeps"]
+        for key in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+            if ro[key] is None:
+                continue
+            assert np.array_equal(_bits(rb[key].cpu().numpy()), _bits(ro[key])), key
+    srv = J().Server(hbm_budget_bytes=1 << 30, max_slots=4, flags=flags)
+    tickets = [srv.submit(J().to_device_fortran(Ar), None if Ai is None else J().to_device_fortran(Ai))
+               for Ar, Ai in host]
+    assert all(t is not None for t in tickets)
+    results = [srv.wait(t) for t in tickets]
+    srv.close()
+    for (Ar, Ai), r in zip(host, results):
+        ro = ora.gesvj(Ar, Ai, flags=flags)
+        assert r["status"] == ro["status"] and r["sweeps"] == ro["sweeps"]
+        for key in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+            if ro[key] is None:
+                continue
+            assert np.array_equal(_bits(r[key].cpu().numpy()), _bits(ro[key])), key

@@ -431,15 +431,17 @@ def test_no_permute_option(ora):
         assert st.last_sw == 0
 
 
+@pytest.mark.parametrize("flags", [0, 2])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_scaling_invariance_svd(ora, cplx):
+def test_scaling_invariance_svd(ora, cplx, flags):
     """SVD(2^k A): bitwise identical U, V, f and sweeps; e shifted by k (the
-    initial scaling 2^{s_0} absorbs the factor)."""
+    initial scaling 2^{s_0} absorbs the factor); also with the compensated
+    scaled dot-products (flags = 2)."""
     g = inputs.rng(inputs.CFG_PLAIN_REAL_256, 103)
     Ar, Ai = inputs.random_columns(30, 12, g, cplx)
-    r0 = ora.gesvj(Ar, Ai)
+    r0 = ora.gesvj(Ar, Ai, flags=flags)
     for k in (-900, -37, 41, 700):
-        r1 = ora.gesvj(np.ldexp(Ar, k), None if Ai is None else np.ldexp(Ai, k))
+        r1 = ora.gesvj(np.ldexp(Ar, k), None if Ai is None else np.ldexp(Ai, k), flags=flags)
         assert r1["sweeps"] == r0["sweeps"]
         assert np.array_equal(r1["U_re"], r0["U_re"]) and np.array_equal(r1["V_re"], r0["V_re"])
         if cplx:
@@ -475,12 +477,14 @@ def test_tiny_svd_vs_mpmath(ora):
             assert abs(mpmath.mpf(a) / b - 1) < 200 * EPS * float(ex[0] / b)
 
 
-def test_c1_plain_real_256_accuracy(ora):
+@pytest.mark.parametrize("flags", [0, 2])
+def test_c1_plain_real_256_accuracy(ora, flags):
     """Plain real 256 x 256, sigma log-spaced in [1e-6, 1]: max relative sigma
     error <= 1e-10 against the prescribed sigma and against dgejsv of the
-    rounded A; residual <= 64 n eps ||A||_F; U, V orthonormal."""
+    rounded A; residual <= 64 n eps ||A||_F; U, V orthonormal.  The same bars
+    hold with the compensated scaled dot-products (flags = 2)."""
     A, sig = inputs.plain_real_256()
-    res = ora.gesvj(A)
+    res = ora.gesvj(A, flags=flags)
     assert res["status"] == ora.OK
     sv = _sv(res)
     assert np.max(np.abs(sv - sig) / sig) <= 1e-10
@@ -498,13 +502,15 @@ def test_c1_plain_real_256_accuracy(ora):
     assert 3 <= res["sweeps"] < 64
 
 
-def test_complex_svd_accuracy(ora):
-    """Complex Haar factors, kappa = 1e4: sigma relative error ~ eps kappa."""
+@pytest.mark.parametrize("flags", [0, 2])
+def test_complex_svd_accuracy(ora, flags):
+    """Complex Haar factors, kappa = 1e4: sigma relative error ~ eps kappa,
+    with the plain and with the compensated scaled dot-products."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 106)
     n = 48
     sig = inputs.sigma_logspace(n, 1e-4)
     Ar, Ai = inputs.svd_matrix(64, n, sig, g, cplx=True, extended=True)
-    res = ora.gesvj(Ar, Ai)
+    res = ora.gesvj(Ar, Ai, flags=flags)
     assert res["status"] == ora.OK
     sv = _sv(res)
     assert np.max(np.abs(sv - sig) / sig) <= 1e-11
