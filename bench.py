@@ -138,11 +138,12 @@ def evd_workload(torch, J, inputs, r, K, W):
     return wall, dur, dev
 
 
-def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2):
-    """Time the fused Jacobi step on a freshly loaded state (every pair transforms)."""
+def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0):
+    """Time the Jacobi step on a freshly loaded state (every pair transforms)."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 77 + int(cplx))
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
     st = J.State(m, n, cplx)
+    st.set_flags(flags)
     st.load(J.to_device_fortran(Ar), J.to_device_fortran(Ai) if cplx else None)
     for _ in range(warm):
         st.step()
@@ -401,7 +402,14 @@ def main():
             log(f"[bench] Jacobi step {m}x{n} {'complex' if c else 'real'}")
             extra[f"step_{'c' if c else 'r'}{m}x{n}"] = step_roofline(torch, J, inputs, m, n, c)
             log(f"[bench]   {extra[f'step_{chr(99) if c else chr(114)}{m}x{n}']}")
-        for nm, fl in (("svd_real256_permute", 0), ("svd_real256_nopermute", J.NO_PERMUTE)):
+        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
+            nm = f"step_{'c' if c else 'r'}{m}x{n}_compensated"
+            log(f"[bench] {nm}")
+            extra[nm] = step_roofline(torch, J, inputs, m, n, c, flags=J.COMPENSATED)
+            log(f"[bench]   {extra[nm]}")
+        for nm, fl in (("svd_real256_permute", 0), ("svd_real256_nopermute", J.NO_PERMUTE),
+                       ("svd_real256_permute_compensated", J.COMPENSATED),
+                       ("svd_real256_nopermute_compensated", J.NO_PERMUTE | J.COMPENSATED)):
             log(f"[bench] {nm}")
             extra[nm] = svd_plain(torch, J, inputs, fl)
             log(f"[bench]   {extra[nm]}")
