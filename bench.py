@@ -138,6 +138,39 @@ def evd_workload(torch, J, inputs, r, K, W):
     return wall, dur, dev
 
 
+EVD_BYTES_REAL_F32 = 32      # 3 x 4 in, 4 x 4 out, 4 zp
+EVD_BYTES_CPLX_F32 = 40      # 4 x 4 in, 5 x 4 out, 4 zp
+
+
+def evd_f32(torch, J, inputs, r, K, W):
+    """The single precision batched EVD on the same recipe over the float32
+    range: EVDs/s over both kernels and each kernel against the HBM roofline."""
+    dur = {}
+    for cplx in (False, True):
+        a = inputs.evd_batch_f32(r, cplx)
+        ins = [None if x is None else torch.from_numpy(x).cuda() for x in a]
+        out = None
+        for _ in range(W):
+            out = J.evd2_batched_f32(*ins, out=out)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for s, e in evs:
+            s.record()
+            J.evd2_batched_f32(*ins, out=out)
+            e.record()
+        torch.cuda.synchronize()
+        dur[cplx] = sum(s.elapsed_time(e) for s, e in evs) / K * 1e-3
+        del ins, out
+        torch.cuda.empty_cache()
+    tot = dur[False] + dur[True]
+    res = dict(r=r, evd_per_s=2.0 * r / tot)
+    for cplx, nb in ((False, EVD_BYTES_REAL_F32), (True, EVD_BYTES_CPLX_F32)):
+        ach = nb * r / dur[cplx] / 1e9
+        res["complex" if cplx else "real"] = dict(avg_launch_ms=round(dur[cplx] * 1e3, 4), achieved_GBs=round(ach, 1),
+                                                  frac=round(ach / HBM_PEAK_GBS, 4), bytes_per_launch=nb * r)
+    return res
+
+
 def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0):
     """Time the Jacobi step on a freshly loaded state (every pair transforms)."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 77 + int(cplx))
@@ -398,6 +431,9 @@ def main():
     torch.cuda.empty_cache()
     extra = {}
     if not args.no_extra:
+        log(f"[bench] single precision batched EVD, r = 2^{args.log2r}")
+        extra["evd_f32"] = evd_f32(torch, J, inputs, r, K, W)
+        log(f"[bench]   {extra['evd_f32']}")
         for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
             log(f"[bench] Jacobi step {m}x{n} {'complex' if c else 'real'}")
             extra[f"step_{'c' if c else 'r'}{m}x{n}"] = step_roofline(torch, J, inputs, m, n, c)

@@ -91,6 +91,17 @@ int jsvd_evd2_batched(size_t r, const double *a11, const double *a22,
                       double *lambda1, double *lambda2, int32_t *zp,
                       unsigned flags, void *stream);
 
+/* Single precision variant (Sect. 2.4.1: nu = FLT_MAX, fl(sqrt nu) =
+ * 1.844674297E+19, FLT_TRUE_MIN, eta = FLT_MAX_EXP - 4): the same interface
+ * on float arrays.  Results are bit-for-bit those of the serial algorithm
+ * carried out in IEEE single arithmetic (round-to-nearest-even, gradual
+ * underflow).  zeta' fits the same int32 packing. */
+int jsvd_evd2_batched_f32(size_t r, const float *a11, const float *a22,
+                          const float *a21_re, const float *a21_im,
+                          float *cos_phi, float *ctan_re, float *ctan_im,
+                          float *lambda1, float *lambda2, int32_t *zp,
+                          unsigned flags, void *stream);
+
 /* ----------------------------------------------------------------------
  * Device-resident SVD state: the hot path one parallel step at a time
  * (Sect. 4, Alg. zvjsvd).

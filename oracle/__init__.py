@@ -24,6 +24,7 @@ COMPENSATED = 2
 LANES = 1024
 
 _dp = _ct.POINTER(_ct.c_double)
+_fp = _ct.POINTER(_ct.c_float)
 _ip = _ct.POINTER(_ct.c_int32)
 
 
@@ -42,6 +43,13 @@ def lib():
         L.ora_evd2_real.argtypes = [d, d, d, _dp, _dp, _dp, _dp, _ct.c_uint]
         L.ora_evd2_batch.restype = None
         L.ora_evd2_batch.argtypes = [sz, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _ip, _ct.c_uint, i]
+        f = _ct.c_float
+        L.ora_sevd2_cplx.restype = i
+        L.ora_sevd2_cplx.argtypes = [f, f, f, f, _fp, _fp, _fp, _fp, _fp, _ct.c_uint]
+        L.ora_sevd2_real.restype = i
+        L.ora_sevd2_real.argtypes = [f, f, f, _fp, _fp, _fp, _fp, _ct.c_uint]
+        L.ora_sevd2_batch.restype = None
+        L.ora_sevd2_batch.argtypes = [sz, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _ip, _ct.c_uint, i]
         L.ora_omp_max_threads.restype = i
         L.ora_hypot.restype = d
         L.ora_hypot.argtypes = [d, d]
@@ -121,6 +129,42 @@ def evd2_batch(a11, a22, a21r, a21i=None, flags=0, nthreads=0):
     cti = out[2] if a21i is not None else None
     lib().ora_evd2_batch(r, _p(a11), _p(a22), _p(a21r), _p(a21i), _p(out[0]), _p(out[1]), _p(cti),
                          _p(out[3]), _p(out[4]), _pi(zp), flags, nthreads)
+    return out[0], out[1], cti, out[3], out[4], zp
+
+
+def _pf(a):
+    if a is None:
+        return None
+    assert a.dtype == _np.float32 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_fp)
+
+
+def sevd2(a11, a22, a21r, a21i=None, flags=0):
+    """Single precision scalar EVD; inputs are rounded to float32 first.
+    Returns a dict of float32 outputs."""
+    L = lib()
+    c, C, S, l1, l2 = (_ct.c_float() for _ in range(5))
+    a11, a22, a21r = (_np.float32(x) for x in (a11, a22, a21r))
+    if a21i is None:
+        z = L.ora_sevd2_real(a11, a22, a21r, c, C, l1, l2, flags)
+        S.value = 0.0
+    else:
+        z = L.ora_sevd2_cplx(a11, a22, a21r, _np.float32(a21i), c, C, S, l1, l2, flags)
+    f32 = _np.float32
+    return dict(cos=f32(c.value), ctan_re=f32(C.value), ctan_im=f32(S.value), l1=f32(l1.value), l2=f32(l2.value),
+                zp=z)
+
+
+def sevd2_batch(a11, a22, a21r, a21i=None, flags=0, nthreads=0):
+    """Single precision batched EVD over float32 SoA arrays."""
+    a11, a22, a21r = (_np.ascontiguousarray(x, dtype=_np.float32) for x in (a11, a22, a21r))
+    a21i = None if a21i is None else _np.ascontiguousarray(a21i, dtype=_np.float32)
+    r = a11.shape[0]
+    out = [_np.empty(r, dtype=_np.float32) for _ in range(5)]
+    zp = _np.empty(r, dtype=_np.int32)
+    cti = out[2] if a21i is not None else None
+    lib().ora_sevd2_batch(r, _pf(a11), _pf(a22), _pf(a21r), _pf(a21i), _pf(out[0]), _pf(out[1]), _pf(cti),
+                          _pf(out[3]), _pf(out[4]), _pi(zp), flags, nthreads)
     return out[0], out[1], cti, out[3], out[4], zp
 
 

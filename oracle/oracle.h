@@ -53,6 +53,18 @@ void ora_evd2_batch(size_t r, const double *a11, const double *a22,
                     unsigned flags, int nthreads);
 int ora_omp_max_threads(void);
 
+/* ---- single precision variants (Sect. 2.4.1: nu = FLT_MAX, fl(sqrt nu) =
+ * 1.844674297E+19, FLT_TRUE_MIN, eta = FLT_MAX_EXP - 4) ---- */
+int ora_sevd2_cplx(float a11, float a22, float a21r, float a21i,
+                   float *cs, float *ctr, float *cti, float *l1, float *l2, unsigned flags);
+int ora_sevd2_real(float a11, float a22, float a21,
+                   float *cs, float *tn, float *l1, float *l2, unsigned flags);
+void ora_sevd2_batch(size_t r, const float *a11, const float *a22,
+                     const float *a21r, const float *a21i,
+                     float *cs, float *ctr, float *cti,
+                     float *l1, float *l2, int32_t *zp,
+                     unsigned flags, int nthreads);
+
 /* ---- scalar helpers ---- */
 double ora_hypot(double x, double y);            /* Alg. hypot */
 int    ora_getexp(double x);                      /* floor(lg|x|), x finite non-zero */

@@ -21,7 +21,7 @@ import os as _os
 __all__ = [
     "lib", "JsvdError", "fortran_empty", "to_device_fortran", "evd2_batched", "State", "gesvj",
     "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "COMPENSATED",
-    "dot_scaled_batched",
+    "dot_scaled_batched", "evd2_batched_f32",
 ]
 
 _HERE = _os.path.dirname(_os.path.abspath(__file__))
@@ -82,6 +82,8 @@ def lib():
         L.jsvd_strerror.argtypes = [i]
         L.jsvd_evd2_batched.restype = i
         L.jsvd_evd2_batched.argtypes = [sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u, vp]
+        L.jsvd_evd2_batched_f32.restype = i
+        L.jsvd_evd2_batched_f32.argtypes = [sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u, vp]
         L.jsvd_state_create.restype = i
         L.jsvd_state_create.argtypes = [i, i, i, _ct.POINTER(vp)]
         L.jsvd_state_destroy.restype = None
@@ -237,6 +239,33 @@ def dot_scaled_batched(Q_re, P_re, eq, fq, ep, fp, Q_im=None, P_im=None, flags=0
                                          _ptr(eq), _ptr(fq), _ptr(ep), _ptr(fp), _ptr(z_re), _ptr(z_im),
                                          flags, _stream(stream)), "jsvd_dot_scaled_batched")
     return z_re, z_im
+
+
+def evd2_batched_f32(a11, a22, a21_re, a21_im=None, flags=0, out=None, with_lambda=True, with_zp=True,
+                     stream=None):
+    """Single precision batched 2x2 EVD over float32 CUDA vectors (same outputs
+    as evd2_batched, float32)."""
+    torch = _torch()
+    r = a11.numel()
+    for t, nm in ((a11, "a11"), (a22, "a22"), (a21_re, "a21_re"), (a21_im, "a21_im")):
+        if t is not None and not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and t.numel() >= r):
+            raise ValueError(f"{nm}: expected a contiguous float32 CUDA tensor of {r} elements")
+    dev = a11.device
+    if out is None:
+        out = dict(cos=torch.empty(r, dtype=torch.float32, device=dev),
+                   ctan_re=torch.empty(r, dtype=torch.float32, device=dev))
+        if a21_im is not None:
+            out["ctan_im"] = torch.empty(r, dtype=torch.float32, device=dev)
+        if with_lambda:
+            out["lambda1"] = torch.empty(r, dtype=torch.float32, device=dev)
+            out["lambda2"] = torch.empty(r, dtype=torch.float32, device=dev)
+        if with_zp:
+            out["zp"] = torch.empty(r, dtype=torch.int32, device=dev)
+    st = lib().jsvd_evd2_batched_f32(r, _ptr(a11), _ptr(a22), _ptr(a21_re), _ptr(a21_im), _ptr(out["cos"]),
+                                     _ptr(out["ctan_re"]), _ptr(out.get("ctan_im")), _ptr(out.get("lambda1")),
+                                     _ptr(out.get("lambda2")), _ptr(out.get("zp")), flags, _stream(stream))
+    _check(st, "jsvd_evd2_batched_f32")
+    return out
 
 
 # ---------------------------------------------------------------------------- state

@@ -96,6 +96,122 @@ __global__ __launch_bounds__(256) void evd2_kernel_v2(Evd2Args A)
                                     (i2v *)(A.zp + i));
 }
 
+// ---------------------------------------------------------------------------
+// single precision (Sect. 2.4.1): V consecutive matrices per lane with
+// V * 4-byte accesses; a tail shorter than V runs one matrix at a time.
+struct SEvd2Args {
+    size_t r;
+    const float *a11, *a22, *ar, *ai;
+    float *cs, *cr, *ci, *l1, *l2;
+    int32_t *zp;
+};
+
+template <bool CPLX, bool SINFORM, bool SCALED>
+__device__ __forceinline__ void sevd2_one(const SEvd2Args &A, size_t i)
+{
+    const float a11 = __builtin_nontemporal_load(A.a11 + i);
+    const float a22 = __builtin_nontemporal_load(A.a22 + i);
+    const float ar = __builtin_nontemporal_load(A.ar + i);
+    Evd2OutT<float> o;
+    if (CPLX)
+        o = evd2_cplx<SINFORM>(a11, a22, ar, __builtin_nontemporal_load(A.ai + i));
+    else
+        o = evd2_real<SINFORM>(a11, a22, ar);
+    __builtin_nontemporal_store(o.c, A.cs + i);
+    __builtin_nontemporal_store(o.C, A.cr + i);
+    if (CPLX) __builtin_nontemporal_store(o.S, A.ci + i);
+    if (A.l1) __builtin_nontemporal_store(SCALED ? o.l1 : __builtin_amdgcn_ldexpf(o.l1, o.zeta_b), A.l1 + i);
+    if (A.l2) __builtin_nontemporal_store(SCALED ? o.l2 : __builtin_amdgcn_ldexpf(o.l2, o.zeta_b), A.l2 + i);
+    if (A.zp) __builtin_nontemporal_store(pack_zp(o.zeta_b, o.p), A.zp + i);
+}
+
+template <bool CPLX, bool SINFORM, bool SCALED, int V>
+__global__ __launch_bounds__(256) void sevd2_kernel(SEvd2Args A)
+{
+    const size_t i = ((size_t)blockIdx.x * 256 + threadIdx.x) * V;
+    if (i >= A.r) return;
+    if constexpr (V == 1) {
+        sevd2_one<CPLX, SINFORM, SCALED>(A, i);
+    } else {
+        if (i + V > A.r) {
+            for (size_t k = i; k < A.r; ++k) sevd2_one<CPLX, SINFORM, SCALED>(A, k);
+            return;
+        }
+        typedef float fv __attribute__((ext_vector_type(V)));
+        typedef int iv __attribute__((ext_vector_type(V)));
+        const fv a11 = __builtin_nontemporal_load((const fv *)(A.a11 + i));
+        const fv a22 = __builtin_nontemporal_load((const fv *)(A.a22 + i));
+        const fv ar = __builtin_nontemporal_load((const fv *)(A.ar + i));
+        fv ai = {};
+        if (CPLX) ai = __builtin_nontemporal_load((const fv *)(A.ai + i));
+        fv c, C, S, L1, L2;
+        iv z;
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+            const Evd2OutT<float> o = CPLX ? evd2_cplx<SINFORM>(a11[u], a22[u], ar[u], ai[u])
+                                           : evd2_real<SINFORM>(a11[u], a22[u], ar[u]);
+            c[u] = o.c;
+            C[u] = o.C;
+            S[u] = o.S;
+            L1[u] = SCALED ? o.l1 : __builtin_amdgcn_ldexpf(o.l1, o.zeta_b);
+            L2[u] = SCALED ? o.l2 : __builtin_amdgcn_ldexpf(o.l2, o.zeta_b);
+            z[u] = pack_zp(o.zeta_b, o.p);
+        }
+        __builtin_nontemporal_store(c, (fv *)(A.cs + i));
+        __builtin_nontemporal_store(C, (fv *)(A.cr + i));
+        if (CPLX) __builtin_nontemporal_store(S, (fv *)(A.ci + i));
+        if (A.l1) __builtin_nontemporal_store(L1, (fv *)(A.l1 + i));
+        if (A.l2) __builtin_nontemporal_store(L2, (fv *)(A.l2 + i));
+        if (A.zp) __builtin_nontemporal_store(z, (iv *)(A.zp + i));
+    }
+}
+
+template <bool CPLX, bool SINFORM, bool SCALED>
+static hipError_t launch_s_t(const SEvd2Args &A, int V, hipStream_t s)
+{
+    const size_t threads = (A.r + V - 1) / V;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    switch (V) {
+    case 4: hipLaunchKernelGGL((sevd2_kernel<CPLX, SINFORM, SCALED, 4>), dim3(blocks), dim3(256), 0, s, A); break;
+    case 2: hipLaunchKernelGGL((sevd2_kernel<CPLX, SINFORM, SCALED, 2>), dim3(blocks), dim3(256), 0, s, A); break;
+    default: hipLaunchKernelGGL((sevd2_kernel<CPLX, SINFORM, SCALED, 1>), dim3(blocks), dim3(256), 0, s, A); break;
+    }
+    return hipGetLastError();
+}
+
+static bool aligned_to(const void *p, unsigned a) { return p == nullptr || ((uintptr_t)p & (a - 1)) == 0; }
+
+// matrices per lane of the single precision kernel: the widest access that
+// every stream's alignment allows, up to the width measured fastest
+int sevd2_lanes(size_t r, const void *const *ptrs, int nptr, int widest)
+{
+    (void)r;
+    for (int V = widest; V > 1; V /= 2) {
+        bool ok = true;
+        for (int k = 0; k < nptr; ++k) ok = ok && aligned_to(ptrs[k], 4u * (unsigned)V);
+        if (ok) return V;
+    }
+    return 1;
+}
+
+hipError_t launch_sevd2(size_t r, const float *a11, const float *a22, const float *ar, const float *ai, float *cs,
+                        float *cr, float *ci, float *l1, float *l2, int32_t *zp, unsigned flags, int widest,
+                        hipStream_t s)
+{
+    if (r == 0) return hipSuccess;
+    SEvd2Args A{r, a11, a22, ar, ai, cs, cr, ci, l1, l2, zp};
+    const void *ptrs[10] = {a11, a22, ar, ai, cs, cr, ci, l1, l2, zp};
+    const int V = sevd2_lanes(r, ptrs, 10, widest);
+    const bool cplx = ai != nullptr;
+    const bool sinf = (flags & 2u) != 0, scaled = (flags & 1u) != 0;
+    if (cplx) {
+        if (sinf) return scaled ? launch_s_t<true, true, true>(A, V, s) : launch_s_t<true, true, false>(A, V, s);
+        return scaled ? launch_s_t<true, false, true>(A, V, s) : launch_s_t<true, false, false>(A, V, s);
+    }
+    if (sinf) return scaled ? launch_s_t<false, true, true>(A, V, s) : launch_s_t<false, true, false>(A, V, s);
+    return scaled ? launch_s_t<false, false, true>(A, V, s) : launch_s_t<false, false, false>(A, V, s);
+}
+
 static bool aligned16(const void *p) { return p == nullptr || ((uintptr_t)p & 15u) == 0; }
 
 template <bool CPLX, bool SINFORM, bool SCALED>

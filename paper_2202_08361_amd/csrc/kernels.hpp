@@ -11,6 +11,12 @@ hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const dou
                        const double *ai, double *cs, double *cr, double *ci, double *l1,
                        double *l2, int32_t *zp, unsigned flags, hipStream_t s);
 
+// single precision batched EVD: `widest` matrices per lane at most (1, 2 or
+// 4; fewer when a stream's alignment does not allow the wider accesses)
+hipError_t launch_sevd2(size_t r, const float *a11, const float *a22, const float *ar, const float *ai, float *cs,
+                        float *cr, float *ci, float *l1, float *l2, int32_t *zp, unsigned flags, int widest,
+                        hipStream_t s);
+
 // Device-resident scalars of one SVD (updated only by kernels).
 struct DevScalars {
     unsigned long long Mt_bits;   // M~_k as the bit pattern of a non-negative double

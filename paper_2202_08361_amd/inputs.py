@@ -118,6 +118,68 @@ def evd_exponent_sweep(cplx: bool):
     return a11, a22, a21r, a21i
 
 
+# ------------------------------------------------------------------ single precision EVD inputs
+def _wide_components_f32(g: np.random.Generator, r: int) -> np.ndarray:
+    """sign * 2^E * f as float32, E uniform in [-149, 127], f in [1, 2) with 23
+    random fraction bits (E < -126 rounds into the subnormals)."""
+    E = g.integers(-149, 128, size=r)
+    f = 1.0 + g.integers(0, 1 << 23, size=r).astype(np.float64) * 2.0 ** -23
+    s = np.where(g.integers(0, 2, size=r) == 1, -1.0, 1.0)
+    return (s * np.ldexp(f, E)).astype(np.float32)
+
+
+def evd_batch_f32(r: int, cplx: bool, seed_sub: int = 0, zero_frac: float = 0.01,
+                  subn_frac: float = 0.01):
+    """SoA float32 inputs of the single precision batched EVD, the same recipe
+    as evd_batch over the float32 range.  Returns (a11, a22, a21r, a21i|None)."""
+    g = rng(CFG_EVD_BATCH, 1000 + (1 if cplx else 0) + 2 * seed_sub)
+    a11 = _wide_components_f32(g, r)
+    a22 = _wide_components_f32(g, r)
+    a21r = _wide_components_f32(g, r)
+    a21i = _wide_components_f32(g, r) if cplx else None
+    # subnormal off-diagonal, k * 2^-149, k in [1, 2^23 - 1]
+    sel = g.random(r) < subn_frac
+    ns = int(sel.sum())
+    a21r[sel] = (np.ldexp(g.integers(1, 1 << 23, size=ns).astype(np.float64), -149) *
+                 np.where(g.integers(0, 2, size=ns) == 1, -1.0, 1.0)).astype(np.float32)
+    if cplx:
+        a21i[sel] = (np.ldexp(g.integers(1, 1 << 23, size=ns).astype(np.float64), -149) *
+                     np.where(g.integers(0, 2, size=ns) == 1, -1.0, 1.0)).astype(np.float32)
+    for a in (a11, a22, a21r) + ((a21i,) if cplx else ()):
+        a[g.random(r) < zero_frac] = np.float32(0.0)
+    return a11, a22, a21r, a21i
+
+
+def evd_adversarial_f32(cplx: bool):
+    """Special float32 cases: signed zeros, subnormals, values near the overflow
+    threshold, equal diagonals."""
+    f = np.float32
+    nu = np.finfo(np.float32).max
+    mu = np.nextafter(f(0.0), f(1.0))
+    tn = np.finfo(np.float32).tiny
+    vals = [f(0.0), f(-0.0), mu, -mu, f(2) * mu, f(3) * mu, tn, -tn, tn / f(2), f(1.0), f(-1.0), f(0.5), f(3.0),
+            nu, -nu, nu / f(8), nu / f(2), np.sqrt(nu), f(1e-38), f(1e38), f(2.0 ** -126), f(1.0 + 2 ** -23),
+            np.nextafter(nu / f(8), f(0)), f(np.ldexp(1.5, -140)), f(7.0), f(-7.0)]
+    g = rng(CFG_EVD_BATCH, 1099)
+    rows = []
+    for a in vals:
+        for b in vals[::3]:
+            for c in vals[::2]:
+                if cplx:
+                    for d in (f(0.0), f(-0.0), mu, c, -c, tn):
+                        rows.append((a, b, c, d))
+                else:
+                    rows.append((a, b, c, f(0.0)))
+    for a in vals:
+        for c in vals:
+            rows.append((a, a, c, c if cplx else f(0.0)))
+    rows = np.array(rows, dtype=np.float32)
+    g.shuffle(rows, axis=0)
+    a11, a22, a21r = rows[:, 0].copy(), rows[:, 1].copy(), rows[:, 2].copy()
+    a21i = rows[:, 3].copy() if cplx else None
+    return a11, a22, a21r, a21i
+
+
 # ------------------------------------------------------------------ SVD inputs
 def haar(n: int, g: np.random.Generator, cplx: bool = False, m: int | None = None) -> np.ndarray:
     """m x n matrix with Haar-distributed orthonormal columns (QR of a Gaussian,
