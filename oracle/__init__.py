@@ -90,6 +90,30 @@ def lib():
         L.ora_gesvj.restype = i
         L.ora_gesvj.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, i,
                                 _ct.POINTER(i), _ct.POINTER(_ct.c_long), _ct.c_uint]
+        f = _ct.c_float
+        L.ora_s_hypot.restype = f
+        L.ora_s_hypot.argtypes = [f, f]
+        L.ora_s_lg_bound_m.restype = i
+        L.ora_s_lg_bound_m.argtypes = [i, i]
+        L.ora_s_s_round.restype = i
+        L.ora_s_s_round.argtypes = [f, i]
+        L.ora_s_s_square.restype = i
+        L.ora_s_s_square.argtypes = [f, i, i]
+        L.ora_s_colnorm.restype = None
+        L.ora_s_colnorm.argtypes = [i, _fp, _fp, _fp, _fp]
+        L.ora_s_dpscl.restype = None
+        L.ora_s_dpscl.argtypes = [i, _fp, _fp, _fp, _fp, f, f, f, f, _fp, _fp]
+        L.ora_s_rot.restype = f
+        L.ora_s_rot.argtypes = [i, _fp, _fp, _fp, _fp, f, f, f, i]
+        L.ora_sgesvj.restype = i
+        L.ora_sgesvj.argtypes = [i, i, _fp, _fp, sz, _fp, _fp, sz, _fp, _fp, i,
+                                 _ct.POINTER(i), _ct.POINTER(_ct.c_long), _ct.c_uint]
+        L.ora_s_init_ext.restype = i
+        L.ora_s_init_ext.argtypes = [i, i, _fp, _fp, sz, _fp, _fp, sz, _fp, _fp, _ct.POINTER(i), _fp]
+        L.ora_s_step_ext.restype = None
+        L.ora_s_step_ext.argtypes = [i, i, _fp, _fp, sz, _fp, _fp, sz, _fp, _fp, _ct.POINTER(i), _fp,
+                                     _ct.c_long, _ct.POINTER(_ct.c_long), _ct.POINTER(_ct.c_long),
+                                     _ct.POINTER(i), _ct.c_uint]
         _lib = L
     return _lib
 
@@ -135,7 +159,7 @@ def evd2_batch(a11, a22, a21r, a21i=None, flags=0, nthreads=0):
 def _pf(a):
     if a is None:
         return None
-    assert a.dtype == _np.float32 and a.flags["C_CONTIGUOUS"]
+    assert a.dtype == _np.float32 and (a.flags.f_contiguous or a.flags.c_contiguous)
     return a.ctypes.data_as(_fp)
 
 
@@ -308,6 +332,92 @@ def gesvj(G_re, G_im=None, max_sweeps=128, flags=0):
     sw, stp = _ct.c_int(), _ct.c_long()
     st = lib().ora_gesvj(m, n, _p(Gr), _p(Gi), m, _p(Vr), _p(Vi), n, _p(sv_e), _p(sv_f),
                          max_sweeps, sw, stp, flags)
+    return dict(status=st, U_re=Gr, U_im=Gi, V_re=Vr, V_im=Vi, sv_e=sv_e, sv_f=sv_f,
+                sweeps=sw.value, steps=stp.value)
+
+
+# ---- single precision SVD ----
+def s_colnorm(xr, xi=None):
+    e, f = _ct.c_float(), _ct.c_float()
+    xr = _np.ascontiguousarray(xr, dtype=_np.float32)
+    xi = None if xi is None else _np.ascontiguousarray(xi, dtype=_np.float32)
+    lib().ora_s_colnorm(xr.shape[0], _pf(xr), _pf(xi), e, f)
+    return _np.float32(e.value), _np.float32(f.value)
+
+
+def s_dpscl(qr, qi, pr, pi, eq, fq, ep, fp):
+    zr, zi = _ct.c_float(), _ct.c_float()
+    qr, pr = (_np.ascontiguousarray(a, dtype=_np.float32) for a in (qr, pr))
+    qi = None if qi is None else _np.ascontiguousarray(qi, dtype=_np.float32)
+    pi = None if pi is None else _np.ascontiguousarray(pi, dtype=_np.float32)
+    lib().ora_s_dpscl(qr.shape[0], _pf(qr), _pf(qi), _pf(pr), _pf(pi), eq, fq, ep, fp, zr, zi)
+    return _np.float32(zr.value), _np.float32(zi.value)
+
+
+def s_lg_bound_m(m, cplx):
+    return lib().ora_s_lg_bound_m(m, int(cplx))
+
+
+def s_s_round(Mt, cplx):
+    return lib().ora_s_s_round(Mt, int(cplx))
+
+
+def s_s_square(Mt, m, cplx):
+    return lib().ora_s_s_square(Mt, m, int(cplx))
+
+
+class SState:
+    """Single precision oracle SVD state on host float32 arrays (column-major)."""
+
+    def __init__(self, G_re, G_im=None, nosort=False):
+        self.nosort = bool(nosort)
+        self.m, self.n = G_re.shape
+        self.cplx = G_im is not None
+        self.Gr = _np.array(G_re, dtype=_np.float32, order="F", copy=True)
+        self.Gi = _np.array(G_im, dtype=_np.float32, order="F", copy=True) if self.cplx else None
+        self.Vr = _np.zeros((self.n, self.n), dtype=_np.float32, order="F")
+        self.Vi = _np.zeros((self.n, self.n), dtype=_np.float32, order="F") if self.cplx else None
+        self.e = _np.full(self.n, -_np.inf, dtype=_np.float32)
+        self.f = _np.ones(self.n, dtype=_np.float32)
+        self.s = 0
+        self.Mt = _np.float32(0)
+        self.k = 0
+        self.last_t = 0
+        self.last_sw = 0
+        self.rescaled = 0
+
+    def _args(self):
+        return (self.m, self.n, _pf(self.Gr), _pf(self.Gi), self.m, _pf(self.Vr), _pf(self.Vi), self.n,
+                _pf(self.e), _pf(self.f))
+
+    def init(self):
+        s, Mt = _ct.c_int(), _ct.c_float()
+        st = lib().ora_s_init_ext(*self._args(), s, Mt)
+        self.s, self.Mt, self.k = s.value, _np.float32(Mt.value), 0
+        return st
+
+    def step(self):
+        s, Mt = _ct.c_int(self.s), _ct.c_float(self.Mt)
+        t, sw, r = _ct.c_long(), _ct.c_long(), _ct.c_int()
+        lib().ora_s_step_ext(*self._args(), s, Mt, self.k, t, sw, r, NO_PERMUTE if self.nosort else 0)
+        self.s, self.Mt, self.last_t, self.last_sw = s.value, _np.float32(Mt.value), t.value, sw.value
+        self.rescaled += r.value
+        self.k += 1
+        return t.value
+
+
+def sgesvj(G_re, G_im=None, max_sweeps=128, flags=0):
+    """The single precision SVD.  Returns dict(status, U_re, U_im, V_re, V_im, sv_e, sv_f, sweeps, steps)
+    with float32 arrays."""
+    m, n = G_re.shape
+    Gr = _np.array(G_re, dtype=_np.float32, order="F", copy=True)
+    Gi = _np.array(G_im, dtype=_np.float32, order="F", copy=True) if G_im is not None else None
+    Vr = _np.zeros((n, n), dtype=_np.float32, order="F")
+    Vi = _np.zeros((n, n), dtype=_np.float32, order="F") if G_im is not None else None
+    sv_e, sv_f = _np.empty(n, dtype=_np.float32), _np.empty(n, dtype=_np.float32)
+    sw, stp = _ct.c_int(), _ct.c_long()
+    st = lib().ora_sgesvj(m, n, _pf(Gr), _pf(Gi), m, _pf(Vr), _pf(Vi), n, _pf(sv_e), _pf(sv_f),
+                          max_sweeps, sw, stp, flags)
     return dict(status=st, U_re=Gr, U_im=Gi, V_re=Vr, V_im=Vi, sv_e=sv_e, sv_f=sv_f,
                 sweeps=sw.value, steps=stp.value)
 

@@ -125,6 +125,25 @@ typedef struct {
 #define ORA_NO_PERMUTE 1u
 #define ORA_COMPENSATED 2u      /* Alg. zdpsclcs / ddpsclcs instead of zdpscl */
 
+/* ---- single precision SVD (Sect. SM8; constants in ora_ssvd.c) ---- */
+float ora_s_hypot(float x, float y);
+int ora_s_lg_bound_m(int m, int cplx);
+int ora_s_s_round(float Mt, int cplx);
+int ora_s_s_square(float Mt, int m, int cplx);
+void ora_s_colnorm(int m, const float *xr, const float *xi, float *e, float *f);
+void ora_s_dpscl(int m, const float *qr, const float *qi, const float *pr, const float *pi,
+                 float eq, float fq, float ep, float fp, float *zr, float *zi);
+void ora_s_gram(float zr, float zi, float e1, float f1, float e2, float f2,
+                float *a11, float *a22, float *a21r, float *a21i);
+float ora_s_rot(int l, float *xpr, float *xpi, float *xqr, float *xqi, float c, float C, float S, int swap);
+int ora_sgesvj(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
+               float *sv_e, float *sv_f, int max_sweeps, int *sweeps, long *steps, unsigned flags);
+int ora_s_init_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
+                   float *e, float *f, int *s, float *Mt);
+void ora_s_step_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
+                    float *e, float *f, int *s, float *Mt, long k, long *t, long *sw, int *rescaled,
+                    unsigned flags);
+
 #define ORA_OK 0
 #define ORA_NOT_CONVERGED 1
 #define ORA_EINVAL (-1)
