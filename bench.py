@@ -171,13 +171,15 @@ def evd_f32(torch, J, inputs, r, K, W):
     return res
 
 
-def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0):
-    """Time the Jacobi step on a freshly loaded state (every pair transforms)."""
+def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0, fp32=False):
+    """Time the Jacobi step on a freshly loaded state (every pair transforms);
+    fp32: the single precision state on the same columns rounded to float."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 77 + int(cplx))
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
-    st = J.State(m, n, cplx)
+    dt = torch.float32 if fp32 else torch.float64
+    st = J.State(m, n, cplx, fp32=fp32)
     st.set_flags(flags)
-    st.load(J.to_device_fortran(Ar), J.to_device_fortran(Ai) if cplx else None)
+    st.load(J.to_device_fortran(Ar, dtype=dt), J.to_device_fortran(Ai, dtype=dt) if cplx else None)
     for _ in range(warm):
         st.step()
     torch.cuda.synchronize()
@@ -190,18 +192,21 @@ def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0):
     q = st.query()
     t = sum(s.elapsed_time(e) for s, e in evs) / nsteps * 1e-3
     c = 2 if cplx else 1
-    byts = 16.0 * c * n * (m + n) * (q["last_t"] / (n // 2))
+    # each element of the transformed G and V column pairs read once and written once
+    byts = 2.0 * (4 if fp32 else 8) * c * n * (m + n) * (q["last_t"] / (n // 2))
     st.close()
-    return dict(m=m, n=n, complex=bool(cplx), us_per_step=t * 1e6, transformed=q["last_t"], pairs=n // 2,
-                algorithmic_bytes=byts, achieved_GBs=byts / t / 1e9, frac=byts / t / 1e9 / HBM_PEAK_GBS)
+    return dict(m=m, n=n, complex=bool(cplx), dtype="f32" if fp32 else "f64", us_per_step=t * 1e6,
+                transformed=q["last_t"], pairs=n // 2, algorithmic_bytes=byts, achieved_GBs=byts / t / 1e9,
+                frac=byts / t / 1e9 / HBM_PEAK_GBS)
 
 
-def sweep_time(torch, J, inputs, m, n, cplx):
+def sweep_time(torch, J, inputs, m, n, cplx, fp32=False):
     """One whole sweep (graph of K steps) of the large plain workloads on a fresh state."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 88 + int(cplx))
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
-    st = J.State(m, n, cplx)
-    st.load(J.to_device_fortran(Ar), J.to_device_fortran(Ai) if cplx else None)
+    dt = torch.float32 if fp32 else torch.float64
+    st = J.State(m, n, cplx, fp32=fp32)
+    st.load(J.to_device_fortran(Ar, dtype=dt), J.to_device_fortran(Ai, dtype=dt) if cplx else None)
     st.sweep()                     # builds the graph; first sweep
     torch.cuda.synchronize()
     s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -212,7 +217,8 @@ def sweep_time(torch, J, inputs, m, n, cplx):
     q = st.query()
     st.close()
     K = n - 1 if n % 2 == 0 else n
-    return dict(m=m, n=n, complex=bool(cplx), ms_per_sweep=s.elapsed_time(e), steps=K,
+    return dict(m=m, n=n, complex=bool(cplx), dtype="f32" if fp32 else "f64", ms_per_sweep=s.elapsed_time(e),
+                steps=K,
                 us_per_step=s.elapsed_time(e) * 1e3 / K, transformations_in_sweep=q["last_sweep_T"], swaps_in_sweep=q["last_sweep_swaps"])
 
 
@@ -316,9 +322,9 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
                 pool=pool_size, max_queue=max_queue, slots=slots, flags=flags)
 
 
-def svd_plain(torch, J, inputs, flags):
+def svd_plain(torch, J, inputs, flags, fp32=False):
     A, sig = inputs.plain_real_256()
-    dA = J.to_device_fortran(A)
+    dA = J.to_device_fortran(A, dtype=torch.float32 if fp32 else torch.float64)
     J.gesvj(dA, flags=flags)               # warm-up (graph build, caches)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -326,8 +332,8 @@ def svd_plain(torch, J, inputs, flags):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     import numpy as np
-    sv = r["sv"].cpu().numpy()
-    return dict(ms=dt * 1e3, sweeps=r["sweeps"], status=r["status"],
+    sv = r["sv"].cpu().numpy().astype(np.float64)
+    return dict(ms=dt * 1e3, sweeps=r["sweeps"], status=r["status"], dtype="f32" if fp32 else "f64",
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
@@ -443,6 +449,15 @@ def main():
             log(f"[bench] {nm}")
             extra[nm] = step_roofline(torch, J, inputs, m, n, c, flags=J.COMPENSATED)
             log(f"[bench]   {extra[nm]}")
+        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
+            nm = f"step_{'c' if c else 'r'}{m}x{n}_f32"
+            log(f"[bench] {nm}")
+            extra[nm] = step_roofline(torch, J, inputs, m, n, c, fp32=True)
+            log(f"[bench]   {extra[nm]}")
+        for nm, fl in (("svd_real256_permute_f32", 0), ("svd_real256_nopermute_f32", J.NO_PERMUTE)):
+            log(f"[bench] {nm}")
+            extra[nm] = svd_plain(torch, J, inputs, fl, fp32=True)
+            log(f"[bench]   {extra[nm]}")
         for nm, fl in (("svd_real256_permute", 0), ("svd_real256_nopermute", J.NO_PERMUTE),
                        ("svd_real256_permute_compensated", J.COMPENSATED),
                        ("svd_real256_nopermute_compensated", J.NO_PERMUTE | J.COMPENSATED)):
@@ -450,10 +465,11 @@ def main():
             extra[nm] = svd_plain(torch, J, inputs, fl)
             log(f"[bench]   {extra[nm]}")
         for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
-            nm = f"sweep_{'c' if c else 'r'}{m}x{n}"
-            log(f"[bench] {nm}")
-            extra[nm] = sweep_time(torch, J, inputs, m, n, c)
-            log(f"[bench]   {extra[nm]}")
+            for fp32 in (False, True):
+                nm = f"sweep_{'c' if c else 'r'}{m}x{n}" + ("_f32" if fp32 else "")
+                log(f"[bench] {nm}")
+                extra[nm] = sweep_time(torch, J, inputs, m, n, c, fp32=fp32)
+                log(f"[bench]   {extra[nm]}")
         if not args.no_batched:
             for nm, fl in (("batched_permute", 0), ("batched_nopermute", J.NO_PERMUTE)):
                 log(f"[bench] {nm}: first {args.batched} matrices of the 10,000-matrix workload")

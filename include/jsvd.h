@@ -181,6 +181,34 @@ int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu,
  * 1024; 0 = automatic).  Results do not depend on it (bit-identical). */
 int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
 
+/* Single precision state (Sect. SM8: the method in the precision of the
+ * datatype, with that precision's range constants): G, V and the norms are
+ * float arrays and every operation of the step is an IEEE single operation;
+ * nu = FLT_MAX, eps = 2^-24 (upsilon = fl(sqrt m) 2^-24), s_(k) = 126
+ * (real) / 124 (complex) - floor(lg M~), s_[k] from eq. (skn) with nu =
+ * FLT_MAX, the Gram scaling with FLT_MAX_EXP - 1 and the single precision EVD
+ * (Sect. 2.4.1).  The compensated dot-products are not offered.
+ * jsvd_step, jsvd_sweep, jsvd_state_query (M~ as a double holding the float
+ * value), jsvd_state_set_launch, jsvd_state_set_flags (JSVD_NO_PERMUTE only)
+ * and jsvd_state_destroy take either kind of state; the calls below take a
+ * single precision state and the double calls above reject one
+ * (JSVD_EINVAL), and the other way round.  Arguments as for the double
+ * calls, with float arrays. */
+int jsvd_state_create_f32(int m, int n, int is_complex, jsvd_state *out);
+int jsvd_state_load_f32(jsvd_state st, const float *G_re, const float *G_im, size_t ldg,
+                        void *stream);
+int jsvd_state_save_f32(jsvd_state st, float *G_re, float *G_im, size_t ldg,
+                        float *V_re, float *V_im, size_t ldv,
+                        float *e, float *f, int32_t *s, double *Mt, int64_t *step,
+                        void *stream);
+/* Mt must be a finite non-negative float value. */
+int jsvd_state_restore_f32(jsvd_state st, const float *G_re, const float *G_im, size_t ldg,
+                           const float *V_re, const float *V_im, size_t ldv,
+                           int32_t s, double Mt, int64_t step, void *stream);
+int jsvd_state_finalize_f32(jsvd_state st, float *U_re, float *U_im, size_t ldu,
+                            float *V_re, float *V_im, size_t ldv,
+                            float *sv_e, float *sv_f, float *sv, void *stream);
+
 /* ----------------------------------------------------------------------
  * Batched scaled dot-products (Sect. 3.3): for j < npairs,
  *   z_j = (q_j / 2^{eq_j})^* (p_j / 2^{ep_j}) / (fq_j fp_j)
@@ -211,6 +239,14 @@ int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg,
                double *V_re, double *V_im, size_t ldv,
                double *sv_e, double *sv_f, double *sv, int max_sweeps, int *sweeps,
                unsigned flags, void *stream);
+
+/* The whole SVD in single precision (Sect. SM8; the step of
+ * jsvd_state_create_f32): the same interface on float arrays, sv_e holding
+ * the exponents as floats.  flags: JSVD_NO_PERMUTE only. */
+int jsvd_gesvj_f32(int m, int n, float *G_re, float *G_im, size_t ldg,
+                   float *V_re, float *V_im, size_t ldv,
+                   float *sv_e, float *sv_f, float *sv, int max_sweeps, int *sweeps,
+                   unsigned flags, void *stream);
 
 /* ----------------------------------------------------------------------
  * Many independent SVDs of uneven sizes in one persistent launch.  Arrays

@@ -10,8 +10,10 @@ the first call does, and raises if the library is not built (there is no CPU
 fallback).
 
 Matrices are column-major: an ``m x n`` matrix is a float64 CUDA tensor of
-shape ``(m, n)`` with ``stride(0) == 1`` (see :func:`fortran_empty`).
-Complex matrices are split into real and imaginary tensors.
+shape ``(m, n)`` with ``stride(0) == 1`` (see :func:`fortran_empty`), or a
+float32 one for the single precision variant (``State(..., fp32=True)``,
+:func:`gesvj` on float32 input).  Complex matrices are split into real and
+imaginary tensors.
 """
 from __future__ import annotations
 
@@ -86,6 +88,19 @@ def lib():
         L.jsvd_evd2_batched_f32.argtypes = [sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u, vp]
         L.jsvd_state_create.restype = i
         L.jsvd_state_create.argtypes = [i, i, i, _ct.POINTER(vp)]
+        L.jsvd_state_create_f32.restype = i
+        L.jsvd_state_create_f32.argtypes = [i, i, i, _ct.POINTER(vp)]
+        L.jsvd_state_load_f32.restype = i
+        L.jsvd_state_load_f32.argtypes = [vp, vp, vp, sz, vp]
+        L.jsvd_state_save_f32.restype = i
+        L.jsvd_state_save_f32.argtypes = [vp, vp, vp, sz, vp, vp, sz, vp, vp, _ct.POINTER(_ct.c_int32),
+                                          _ct.POINTER(d), _ct.POINTER(_ct.c_int64), vp]
+        L.jsvd_state_restore_f32.restype = i
+        L.jsvd_state_restore_f32.argtypes = [vp, vp, vp, sz, vp, vp, sz, _ct.c_int32, d, _ct.c_int64, vp]
+        L.jsvd_state_finalize_f32.restype = i
+        L.jsvd_state_finalize_f32.argtypes = [vp, vp, vp, sz, vp, vp, sz, vp, vp, vp, vp]
+        L.jsvd_gesvj_f32.restype = i
+        L.jsvd_gesvj_f32.argtypes = [i, i, vp, vp, sz, vp, vp, sz, vp, vp, vp, i, _ct.POINTER(i), u, vp]
         L.jsvd_state_destroy.restype = None
         L.jsvd_state_destroy.argtypes = [vp]
         L.jsvd_state_load.restype = i
@@ -163,11 +178,13 @@ def _vec(t, n, name):
     return t
 
 
-def _mat(t, m, n, name):
-    """Column-major check: shape (m, n), stride(0) == 1; returns the leading dimension."""
+def _mat(t, m, n, name, dtype=None):
+    """Column-major check: shape (m, n), stride(0) == 1, dtype (default
+    float64); returns the leading dimension."""
     torch = _torch()
-    if not (t.is_cuda and t.dtype == torch.float64):
-        raise ValueError(f"{name}: expected a float64 CUDA tensor")
+    dtype = torch.float64 if dtype is None else dtype
+    if not (t.is_cuda and t.dtype == dtype):
+        raise ValueError(f"{name}: expected a {dtype} CUDA tensor")
     if tuple(t.shape) != (m, n):
         raise ValueError(f"{name}: expected shape {(m, n)}, got {tuple(t.shape)}")
     if m > 1 and t.stride(0) != 1:
@@ -177,19 +194,23 @@ def _mat(t, m, n, name):
     return t.stride(1) if n > 1 else max(m, 1)
 
 
-def fortran_empty(m, n, device="cuda", ld=None):
-    """An uninitialised column-major float64 (m, n) tensor with leading dimension ld >= m."""
+def fortran_empty(m, n, device="cuda", ld=None, dtype=None):
+    """An uninitialised column-major (m, n) tensor (float64 unless dtype) with
+    leading dimension ld >= m."""
     torch = _torch()
     ld = m if ld is None else ld
-    return torch.empty((n, ld), dtype=torch.float64, device=device).t()[:m]
+    dtype = torch.float64 if dtype is None else dtype
+    return torch.empty((n, ld), dtype=dtype, device=device).t()[:m]
 
 
-def to_device_fortran(a, device="cuda"):
-    """Copy a host array (numpy / torch, any order) into a column-major device tensor."""
+def to_device_fortran(a, device="cuda", dtype=None):
+    """Copy a host array (numpy / torch, any order) into a column-major device
+    tensor (float64 unless dtype; the values are converted on the host)."""
     torch = _torch()
-    a = torch.as_tensor(a, dtype=torch.float64)
+    dtype = torch.float64 if dtype is None else dtype
+    a = torch.as_tensor(a).to(dtype)
     m, n = a.shape
-    out = fortran_empty(m, n, device)
+    out = fortran_empty(m, n, device, dtype=dtype)
     out.copy_(a)
     return out
 
@@ -270,13 +291,22 @@ def evd2_batched_f32(a11, a22, a21_re, a21_im=None, flags=0, out=None, with_lamb
 
 # ---------------------------------------------------------------------------- state
 class State:
-    """Device-resident SVD state (jsvd_state_*): the hot path one step at a time."""
+    """Device-resident SVD state (jsvd_state_*): the hot path one step at a
+    time; fp32=True makes a single precision state (float32 tensors, the
+    jsvd_state_*_f32 calls)."""
 
-    def __init__(self, m, n, cplx=False):
-        self.m, self.n, self.cplx = m, n, bool(cplx)
+    def __init__(self, m, n, cplx=False, fp32=False):
+        torch = _torch()
+        self.m, self.n, self.cplx, self.fp32 = m, n, bool(cplx), bool(fp32)
+        self.dtype = torch.float32 if fp32 else torch.float64
+        self._sfx = "_f32" if fp32 else ""
         h = _ct.c_void_p()
-        _check(lib().jsvd_state_create(m, n, int(cplx), _ct.byref(h)), "jsvd_state_create")
+        create = lib().jsvd_state_create_f32 if fp32 else lib().jsvd_state_create
+        _check(create(m, n, int(cplx), _ct.byref(h)), "jsvd_state_create" + self._sfx)
         self._h = h
+
+    def _fn(self, name):
+        return getattr(lib(), name + self._sfx)
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -287,11 +317,11 @@ class State:
         self.__del__()
 
     def load(self, G_re, G_im=None, stream=None):
-        ld = _mat(G_re, self.m, self.n, "G_re")
-        if G_im is not None and _mat(G_im, self.m, self.n, "G_im") != ld:
+        ld = _mat(G_re, self.m, self.n, "G_re", self.dtype)
+        if G_im is not None and _mat(G_im, self.m, self.n, "G_im", self.dtype) != ld:
             raise ValueError("G_re and G_im need the same leading dimension")
-        return _check(lib().jsvd_state_load(self._h, _ptr(G_re), _ptr(G_im), ld, _stream(stream)),
-                      "jsvd_state_load", allow=(OK, ENONFINITE, EZERO))
+        return _check(self._fn("jsvd_state_load")(self._h, _ptr(G_re), _ptr(G_im), ld, _stream(stream)),
+                      "jsvd_state_load" + self._sfx, allow=(OK, ENONFINITE, EZERO))
 
     def set_launch(self, threads):
         _check(lib().jsvd_state_set_launch(self._h, threads), "jsvd_state_set_launch")
@@ -312,64 +342,72 @@ class State:
 
     def save(self, stream=None):
         torch = _torch()
-        Gr = fortran_empty(self.m, self.n)
-        Gi = fortran_empty(self.m, self.n) if self.cplx else None
-        Vr = fortran_empty(self.n, self.n)
-        Vi = fortran_empty(self.n, self.n) if self.cplx else None
-        e = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        f = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        dt = self.dtype
+        Gr = fortran_empty(self.m, self.n, dtype=dt)
+        Gi = fortran_empty(self.m, self.n, dtype=dt) if self.cplx else None
+        Vr = fortran_empty(self.n, self.n, dtype=dt)
+        Vi = fortran_empty(self.n, self.n, dtype=dt) if self.cplx else None
+        e = torch.empty(self.n, dtype=dt, device="cuda")
+        f = torch.empty(self.n, dtype=dt, device="cuda")
         s, Mt, k = _ct.c_int32(), _ct.c_double(), _ct.c_int64()
-        _check(lib().jsvd_state_save(self._h, _ptr(Gr), _ptr(Gi), self.m, _ptr(Vr), _ptr(Vi), self.n,
-                                     _ptr(e), _ptr(f), _ct.byref(s), _ct.byref(Mt), _ct.byref(k),
-                                     _stream(stream)), "jsvd_state_save")
+        _check(self._fn("jsvd_state_save")(self._h, _ptr(Gr), _ptr(Gi), self.m, _ptr(Vr), _ptr(Vi), self.n,
+                                           _ptr(e), _ptr(f), _ct.byref(s), _ct.byref(Mt), _ct.byref(k),
+                                           _stream(stream)), "jsvd_state_save" + self._sfx)
         return dict(G_re=Gr, G_im=Gi, V_re=Vr, V_im=Vi, e=e, f=f, s=s.value, Mt=Mt.value, k=k.value)
 
     def restore(self, G_re, G_im, V_re, V_im, s, Mt, k, stream=None):
-        ldg = _mat(G_re, self.m, self.n, "G_re")
-        ldv = _mat(V_re, self.n, self.n, "V_re")
-        _check(lib().jsvd_state_restore(self._h, _ptr(G_re), _ptr(G_im), ldg, _ptr(V_re), _ptr(V_im), ldv,
-                                        int(s), float(Mt), int(k), _stream(stream)), "jsvd_state_restore")
+        ldg = _mat(G_re, self.m, self.n, "G_re", self.dtype)
+        ldv = _mat(V_re, self.n, self.n, "V_re", self.dtype)
+        _check(self._fn("jsvd_state_restore")(self._h, _ptr(G_re), _ptr(G_im), ldg, _ptr(V_re), _ptr(V_im), ldv,
+                                              int(s), float(Mt), int(k), _stream(stream)),
+               "jsvd_state_restore" + self._sfx)
 
     def finalize(self, stream=None):
         torch = _torch()
-        U_re = fortran_empty(self.m, self.n)
-        U_im = fortran_empty(self.m, self.n) if self.cplx else None
-        V_re = fortran_empty(self.n, self.n)
-        V_im = fortran_empty(self.n, self.n) if self.cplx else None
-        sv_e = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        sv_f = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        sv = torch.empty(self.n, dtype=torch.float64, device="cuda")
-        _check(lib().jsvd_state_finalize(self._h, _ptr(U_re), _ptr(U_im), self.m, _ptr(V_re), _ptr(V_im),
-                                         self.n, _ptr(sv_e), _ptr(sv_f), _ptr(sv), _stream(stream)),
-               "jsvd_state_finalize")
+        dt = self.dtype
+        U_re = fortran_empty(self.m, self.n, dtype=dt)
+        U_im = fortran_empty(self.m, self.n, dtype=dt) if self.cplx else None
+        V_re = fortran_empty(self.n, self.n, dtype=dt)
+        V_im = fortran_empty(self.n, self.n, dtype=dt) if self.cplx else None
+        sv_e = torch.empty(self.n, dtype=dt, device="cuda")
+        sv_f = torch.empty(self.n, dtype=dt, device="cuda")
+        sv = torch.empty(self.n, dtype=dt, device="cuda")
+        _check(self._fn("jsvd_state_finalize")(self._h, _ptr(U_re), _ptr(U_im), self.m, _ptr(V_re), _ptr(V_im),
+                                               self.n, _ptr(sv_e), _ptr(sv_f), _ptr(sv), _stream(stream)),
+               "jsvd_state_finalize" + self._sfx)
         return dict(U_re=U_re, U_im=U_im, V_re=V_re, V_im=V_im, sv_e=sv_e, sv_f=sv_f, sv=sv)
 
 
 def gesvj(G_re, G_im=None, max_sweeps=0, flags=0, overwrite=False, stream=None):
     """The whole SVD G = U diag(sigma) V^*.  Returns a dict with U (in place of a
-    copy of G unless overwrite), V, sv_e, sv_f, sv, status, sweeps."""
+    copy of G unless overwrite), V, sv_e, sv_f, sv, status, sweeps.  float32
+    input runs the single precision variant (jsvd_gesvj_f32)."""
     torch = _torch()
     m, n = G_re.shape
+    dt = G_re.dtype
+    if dt not in (torch.float64, torch.float32):
+        raise ValueError("G_re: expected a float64 or float32 CUDA tensor")
+    name = "jsvd_gesvj_f32" if dt == torch.float32 else "jsvd_gesvj"
     if not overwrite:
-        g = fortran_empty(m, n)
+        g = fortran_empty(m, n, dtype=dt)
         g.copy_(G_re)
         G_re = g
         if G_im is not None:
-            g = fortran_empty(m, n)
+            g = fortran_empty(m, n, dtype=dt)
             g.copy_(G_im)
             G_im = g
-    ldg = _mat(G_re, m, n, "G_re")
-    if G_im is not None and _mat(G_im, m, n, "G_im") != ldg:
+    ldg = _mat(G_re, m, n, "G_re", dt)
+    if G_im is not None and _mat(G_im, m, n, "G_im", dt) != ldg:
         raise ValueError("G_re and G_im need the same leading dimension")
-    V_re = fortran_empty(n, n)
-    V_im = fortran_empty(n, n) if G_im is not None else None
-    sv_e = torch.empty(n, dtype=torch.float64, device="cuda")
-    sv_f = torch.empty(n, dtype=torch.float64, device="cuda")
-    sv = torch.empty(n, dtype=torch.float64, device="cuda")
+    V_re = fortran_empty(n, n, dtype=dt)
+    V_im = fortran_empty(n, n, dtype=dt) if G_im is not None else None
+    sv_e = torch.empty(n, dtype=dt, device="cuda")
+    sv_f = torch.empty(n, dtype=dt, device="cuda")
+    sv = torch.empty(n, dtype=dt, device="cuda")
     sw = _ct.c_int()
-    st = lib().jsvd_gesvj(m, n, _ptr(G_re), _ptr(G_im), ldg, _ptr(V_re), _ptr(V_im), n, _ptr(sv_e), _ptr(sv_f),
-                          _ptr(sv), max_sweeps, _ct.byref(sw), flags, _stream(stream))
-    _check(st, "jsvd_gesvj", allow=(OK, NOT_CONVERGED, ENONFINITE, EZERO))
+    st = getattr(lib(), name)(m, n, _ptr(G_re), _ptr(G_im), ldg, _ptr(V_re), _ptr(V_im), n, _ptr(sv_e),
+                              _ptr(sv_f), _ptr(sv), max_sweeps, _ct.byref(sw), flags, _stream(stream))
+    _check(st, name, allow=(OK, NOT_CONVERGED, ENONFINITE, EZERO))
     return dict(status=st, sweeps=sw.value, U_re=G_re, U_im=G_im, V_re=V_re, V_im=V_im, sv_e=sv_e,
                 sv_f=sv_f, sv=sv)
 

@@ -203,7 +203,8 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSm
                             if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
                         }
                 }
-                const PairDecision dc = pair_core<CPLX, 64, R, COMP>(xr, xi, it.ups, nosort, nullptr, nullptr, nullptr);
+                const PairDecision dc = pair_core<CPLX, 64, R, COMP>(xr, xi, it.ups, nosort, (double *)nullptr,
+                                                                     (double *)nullptr, (double *)nullptr);
                 const int pbit = dc.pbit;
                 double *const Dp_r = pbit ? Gqr : Gpr;
                 double *const Dq_r = pbit ? Gpr : Gqr;

@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <limits>
 #include <mutex>
 #include <new>
 
@@ -32,6 +33,21 @@ static int lg_bound(int m, int cplx)
     if (!cplx) return 1022 - a;
     const unsigned long long mm = (unsigned long long)m * (unsigned long long)m;
     return 1021 - a - (mm > (1ULL << (2 * a + 1)) ? 1 : 0);
+}
+
+// The same bound for nu = FLT_MAX = (2^24 - 1) 2^104, evaluated as its
+// definition, the largest k with 2^k varsigma m <= nu: nu lies only 2^-24
+// (relative) below 2^128, so closed forms like those above can be off by one
+// once m approaches that resolution.  The comparisons are exact in double for
+// m < 2^26: real 2 m 2^k <= nu, complex (4 sqrt 2 m 2^k)^2 = 32 m^2 2^2k <= nu^2.
+static int lg_bound_f32(int m, int cplx)
+{
+    const double nu24 = 16777215.0;
+    for (int k = 160;; --k) {
+        const bool fits = cplx ? ldexp(32.0 * (double)m * (double)m, 2 * k) <= ldexp(nu24 * nu24, 208)
+                               : ldexp(2.0 * (double)m, k) <= ldexp(nu24, 104);
+        if (fits) return k;
+    }
 }
 
 static long long round_up(long long x, long long a) { return (x + a - 1) / a * a; }
@@ -100,18 +116,19 @@ struct StateLayout {
     size_t oG, oV, oE, oF, oR, oS, oM, oP, total;
 };
 
-static StateLayout state_layout(int m, int n, int cplx)
+// es: bytes per element of the working precision
+static StateLayout state_layout(int m, int n, int cplx, size_t es)
 {
     StateLayout L;
-    // columns of the working G are whole 1 KiB chunks (the LDS prefetch moves 128 doubles at a time)
-    L.ldg = round_up(m, 128);
+    // columns of the working G start on 1 KiB boundaries
+    L.ldg = round_up(m, (long long)(1024 / es));
     L.ldv = round_up(n, 64);
     const int c = cplx ? 2 : 1;
     size_t off = 0;
-    L.oG = off; off = align_up(off + sizeof(double) * (size_t)L.ldg * n * c);
-    L.oV = off; off = align_up(off + sizeof(double) * (size_t)L.ldv * n * c);
-    L.oE = off; off = align_up(off + sizeof(double) * (size_t)n);
-    L.oF = off; off = align_up(off + sizeof(double) * (size_t)n);
+    L.oG = off; off = align_up(off + es * (size_t)L.ldg * n * c);
+    L.oV = off; off = align_up(off + es * (size_t)L.ldv * n * c);
+    L.oE = off; off = align_up(off + es * (size_t)n);
+    L.oF = off; off = align_up(off + es * (size_t)n);
     L.oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
     L.oS = off; off = align_up(off + sizeof(DevScalars));
     L.oM = off; off = align_up(off + sizeof(unsigned long long));
@@ -120,9 +137,41 @@ static StateLayout state_layout(int m, int n, int cplx)
     return L;
 }
 
-size_t jsvd::state_bytes(int m, int n, int cplx) { return state_layout(m, n, cplx).total; }
+size_t jsvd::state_bytes(int m, int n, int cplx, bool fp32)
+{
+    return state_layout(m, n, cplx, fp32 ? sizeof(float) : sizeof(double)).total;
+}
 
-extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
+// the descriptor of the state's working precision
+template <typename T>
+static SvdDescT<T> &desc_of(jsvd_state st);
+template <>
+SvdDescT<double> &desc_of<double>(jsvd_state st) { return st->d; }
+template <>
+SvdDescT<float> &desc_of<float>(jsvd_state st) { return st->df; }
+
+template <typename T>
+static void fill_desc(SvdDescT<T> &d, int m, int n, int cplx, char *b, const StateLayout &L, int lgbound, T ups)
+{
+    d.m = m;
+    d.n = n;
+    d.cplx = cplx;
+    d.nosort = 0;
+    d.comp = 0;
+    d.Gr = (T *)(b + L.oG);
+    d.Gi = cplx ? d.Gr + (size_t)L.ldg * n : nullptr;
+    d.ldg = L.ldg;
+    d.Vr = (T *)(b + L.oV);
+    d.Vi = cplx ? d.Vr + (size_t)L.ldv * n : nullptr;
+    d.ldv = L.ldv;
+    d.e = (T *)(b + L.oE);
+    d.f = (T *)(b + L.oF);
+    d.sc = (DevScalars *)(b + L.oS);
+    d.lgbound = lgbound;
+    d.ups = ups;
+}
+
+static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out)
 {
     if (!out) return JSVD_EINVAL;
     *out = nullptr;
@@ -134,6 +183,7 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     st->m = m;
     st->n = n;
     st->cplx = is_complex != 0;
+    st->fp32 = fp32 ? 1 : 0;
     st->max_sweeps = 128;
     if (hipGetDevice(&st->device) != hipSuccess) {
         delete st;
@@ -142,7 +192,7 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     if (hipDeviceGetAttribute(&st->ncu, hipDeviceAttributeMultiprocessorCount, st->device) != hipSuccess ||
         st->ncu <= 0)
         st->ncu = 256;
-    const StateLayout L = state_layout(m, n, st->cplx);
+    const StateLayout L = state_layout(m, n, st->cplx, fp32 ? sizeof(float) : sizeof(double));
     if (hipMalloc(&st->mem, L.total) != hipSuccess) {
         delete st;
         return JSVD_ENOMEM;
@@ -155,28 +205,26 @@ extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
     }
     static_assert(sizeof(DevScalars) <= 256, "staging layout");
     char *b = (char *)st->mem;
-    SvdDesc &d = st->d;
-    d.m = m;
-    d.n = n;
-    d.cplx = st->cplx;
-    d.nosort = 0;
-    d.comp = 0;
-    d.Gr = (double *)(b + L.oG);
-    d.Gi = st->cplx ? d.Gr + (size_t)L.ldg * n : nullptr;
-    d.ldg = L.ldg;
-    d.Vr = (double *)(b + L.oV);
-    d.Vi = st->cplx ? d.Vr + (size_t)L.ldv * n : nullptr;
-    d.ldv = L.ldv;
-    d.e = (double *)(b + L.oE);
-    d.f = (double *)(b + L.oF);
-    d.sc = (DevScalars *)(b + L.oS);
-    d.lgbound = lg_bound(m, st->cplx);
-    d.ups = ldexp(sqrt((double)m), -53);
+    if (fp32)
+        fill_desc<float>(st->df, m, n, st->cplx, b, L, lg_bound_f32(m, st->cplx), ldexpf(sqrtf((float)m), -24));
+    else
+        fill_desc<double>(st->d, m, n, st->cplx, b, L, lg_bound(m, st->cplx), ldexp(sqrt((double)m), -53));
+    st->sc = (DevScalars *)(b + L.oS);
     st->rank = (int *)(b + L.oR);
     st->maxbits = (unsigned long long *)(b + L.oM);
     st->prm = (PairParam *)(b + L.oP);
     *out = st;
     return JSVD_OK;
+}
+
+extern "C" int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out)
+{
+    return state_create(m, n, is_complex, false, out);
+}
+
+extern "C" int jsvd_state_create_f32(int m, int n, int is_complex, jsvd_state *out)
+{
+    return state_create(m, n, is_complex, true, out);
 }
 
 extern "C" void jsvd_state_destroy(jsvd_state st)
@@ -192,14 +240,14 @@ extern "C" void jsvd_state_destroy(jsvd_state st)
 static int push_scalars(jsvd_state st, const DevScalars &h, hipStream_t s)
 {
     *st->host = h;
-    HIPCHK(hipMemcpyAsync(st->d.sc, st->host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(st->sc, st->host, sizeof(DevScalars), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));
     return JSVD_OK;
 }
 
 static int pull_scalars(jsvd_state st, hipStream_t s)
 {
-    HIPCHK(hipMemcpyAsync(st->host, st->d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     return JSVD_OK;
 }
@@ -218,26 +266,56 @@ static double bitsd(unsigned long long b)
     return x;
 }
 
+// a state of the precision T
+template <typename T>
+static bool is_prec(jsvd_state st)
+{
+    return st && (st->fp32 != 0) == (sizeof(T) == sizeof(float));
+}
+
 // The load is stream-ordered: M~_0 is reduced on the device, s_0 and the
 // status are derived there too, and nothing waits for the host.
-int jsvd::state_load_async(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, hipStream_t s)
+template <typename T>
+static int load_async_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, hipStream_t s)
 {
-    if (!st || !G_re || ldg < (size_t)st->m) return JSVD_EINVAL;
+    if (!is_prec<T>(st) || !G_re || ldg < (size_t)st->m) return JSVD_EINVAL;
     if ((G_im != nullptr) != (st->cplx != 0)) return JSVD_EINVAL;
+    const SvdDescT<T> &d = desc_of<T>(st);
     HIPCHK(launch_zero_u64(st->maxbits, s));
-    HIPCHK(launch_maxabs(st->d, G_re, G_im, (long long)ldg, st->maxbits, s));
-    HIPCHK(launch_init_scale(st->d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
+    HIPCHK(launch_maxabs(d, G_re, G_im, (long long)ldg, st->maxbits, s));
+    HIPCHK(launch_init_scale(d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
     return JSVD_OK;
 }
 
-extern "C" int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, void *stream)
+int jsvd::state_load_async(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, hipStream_t s)
+{
+    return load_async_t<double>(st, G_re, G_im, ldg, s);
+}
+
+int jsvd::state_load_async(jsvd_state st, const float *G_re, const float *G_im, size_t ldg, hipStream_t s)
+{
+    return load_async_t<float>(st, G_re, G_im, ldg, s);
+}
+
+template <typename T>
+static int load_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, void *stream)
 {
     hipStream_t s = (hipStream_t)stream;
-    int rc = state_load_async(st, G_re, G_im, ldg, s);
+    int rc = load_async_t<T>(st, G_re, G_im, ldg, s);
     if (rc != JSVD_OK) return rc;
     rc = pull_scalars(st, s);
     if (rc != JSVD_OK) return rc;
     return st->host->status;
+}
+
+extern "C" int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, void *stream)
+{
+    return load_t<double>(st, G_re, G_im, ldg, stream);
+}
+
+extern "C" int jsvd_state_load_f32(jsvd_state st, const float *G_re, const float *G_im, size_t ldg, void *stream)
+{
+    return load_t<float>(st, G_re, G_im, ldg, stream);
 }
 
 extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
@@ -252,16 +330,22 @@ extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
 
 static constexpr unsigned kIterFlags = JSVD_NO_PERMUTE | JSVD_COMPENSATED;
 
+// the iteration flags a state accepts (the compensated dot-products are
+// double precision only)
+static unsigned iter_flags_of(jsvd_state st) { return st->fp32 ? JSVD_NO_PERMUTE : kIterFlags; }
+
 static void apply_flags(jsvd_state st, unsigned flags)
 {
     st->flags = flags;
-    st->d.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
-    st->d.comp = (flags & JSVD_COMPENSATED) ? 1 : 0;
+    const int nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+    const int comp = (flags & JSVD_COMPENSATED) ? 1 : 0;
+    st->d.nosort = st->df.nosort = nosort;
+    st->d.comp = st->df.comp = comp;
 }
 
 extern "C" int jsvd_state_set_flags(jsvd_state st, unsigned flags)
 {
-    if (!st || (flags & ~kIterFlags)) return JSVD_EINVAL;
+    if (!st || (flags & ~iter_flags_of(st))) return JSVD_EINVAL;
     apply_flags(st, flags);
     return JSVD_OK;
 }
@@ -277,13 +361,20 @@ static int state_threads(jsvd_state st)
 // the V kernel, otherwise the fused one-workgroup-per-pair kernel
 static bool uses_gpair(jsvd_state st)
 {
-    return st->threads == 0 && gpair_rows(st->m, st->cplx) != 0 && st->m > 256;
+    return st->threads == 0 && gpair_rows(st->m, st->cplx, st->fp32 != 0) != 0 && st->m > 256;
+}
+
+template <typename T>
+static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s)
+{
+    const SvdDescT<T> &d = desc_of<T>(st);
+    if (uses_gpair(st)) return launch_gpair(d, st->prm, s);
+    return launch_step(d, state_threads(st), s);
 }
 
 static hipError_t launch_one_step(jsvd_state st, hipStream_t s)
 {
-    if (uses_gpair(st)) return launch_gpair(st->d, st->prm, s);
-    return launch_step(st->d, state_threads(st), s);
+    return st->fp32 ? launch_one_step_t<float>(st, s) : launch_one_step_t<double>(st, s);
 }
 
 extern "C" int jsvd_step(jsvd_state st, void *stream)
@@ -301,7 +392,7 @@ static int capture_sweep(jsvd_state st, hipStream_t cs)
     const int K = sweep_steps(st->n);
     for (int k = 0; k < K; ++k)
         if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
-    return launch_sweep_end(st->d, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
+    return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
 }
 
 static int build_graph(jsvd_state st)
@@ -356,17 +447,18 @@ int jsvd::state_sweep_async(jsvd_state st, hipStream_t s)
 {
     const int rc = jsvd_sweep(st, s);
     if (rc != JSVD_OK) return rc;
-    HIPCHK(hipMemcpyAsync(st->host, st->d.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     return JSVD_OK;
 }
 
 const DevScalars &jsvd::state_staged(jsvd_state st) { return *st->host; }
 
-int jsvd::state_finish_async(jsvd_state st, bool converged, double *U_re, double *U_im, size_t ldu,
-                             double *V_re, double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv,
-                             hipStream_t s)
+template <typename T>
+static int finish_async_t(jsvd_state st, bool converged, T *U_re, T *U_im, size_t ldu, T *V_re, T *V_im, size_t ldv,
+                          T *sv_e, T *sv_f, T *sv, hipStream_t s)
 {
-    const SvdDesc &d = st->d;
+    if (!is_prec<T>(st)) return JSVD_EINVAL;
+    const SvdDescT<T> &d = desc_of<T>(st);
     if (converged) {
         HIPCHK(launch_colnorms_raw(d, s));
         HIPCHK(launch_rank(d, st->rank, s));
@@ -374,13 +466,25 @@ int jsvd::state_finish_async(jsvd_state st, bool converged, double *U_re, double
                                   sv, s));
         return JSVD_OK;
     }
-    HIPCHK(launch_copy2d(d.m, d.n, d.Gr, d.ldg, U_re, (long long)ldu, s));
-    if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, d.Gi, d.ldg, U_im, (long long)ldu, s));
-    HIPCHK(launch_copy2d(d.n, d.n, d.Vr, d.ldv, V_re, (long long)ldv, s));
-    if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, d.Vi, d.ldv, V_im, (long long)ldv, s));
+    HIPCHK(launch_copy2d(d.m, d.n, (const T *)d.Gr, d.ldg, U_re, (long long)ldu, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, (const T *)d.Gi, d.ldg, U_im, (long long)ldu, s));
+    HIPCHK(launch_copy2d(d.n, d.n, (const T *)d.Vr, d.ldv, V_re, (long long)ldv, s));
+    if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, (const T *)d.Vi, d.ldv, V_im, (long long)ldv, s));
     HIPCHK(launch_colnorms_raw(d, s));
     HIPCHK(launch_colnorm_out(d, sv_e, sv_f, sv, s));
     return JSVD_OK;
+}
+
+int jsvd::state_finish_async(jsvd_state st, bool converged, double *U_re, double *U_im, size_t ldu, double *V_re,
+                             double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv, hipStream_t s)
+{
+    return finish_async_t<double>(st, converged, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, s);
+}
+
+int jsvd::state_finish_async(jsvd_state st, bool converged, float *U_re, float *U_im, size_t ldu, float *V_re,
+                             float *V_im, size_t ldv, float *sv_e, float *sv_f, float *sv, hipStream_t s)
+{
+    return finish_async_t<float>(st, converged, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, s);
 }
 
 extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
@@ -404,26 +508,26 @@ extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
     return JSVD_OK;
 }
 
-extern "C" int jsvd_state_save(jsvd_state st, double *G_re, double *G_im, size_t ldg, double *V_re,
-                               double *V_im, size_t ldv, double *e, double *f, int32_t *s_out, double *Mt,
-                               int64_t *step, void *stream)
+template <typename T>
+static int save_t(jsvd_state st, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im, size_t ldv, T *e, T *f,
+                  int32_t *s_out, double *Mt, int64_t *step, void *stream)
 {
-    if (!st) return JSVD_EINVAL;
+    if (!is_prec<T>(st)) return JSVD_EINVAL;
     if (G_re && ldg < (size_t)st->m) return JSVD_EINVAL;
     if (V_re && ldv < (size_t)st->n) return JSVD_EINVAL;
     if (st->cplx && ((G_re && !G_im) || (V_re && !V_im))) return JSVD_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const SvdDesc &d = st->d;
+    const SvdDescT<T> &d = desc_of<T>(st);
     if (G_re) {
-        HIPCHK(launch_copy2d(d.m, d.n, d.Gr, d.ldg, G_re, (long long)ldg, s));
-        if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, d.Gi, d.ldg, G_im, (long long)ldg, s));
+        HIPCHK(launch_copy2d(d.m, d.n, (const T *)d.Gr, d.ldg, G_re, (long long)ldg, s));
+        if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, (const T *)d.Gi, d.ldg, G_im, (long long)ldg, s));
     }
     if (V_re) {
-        HIPCHK(launch_copy2d(d.n, d.n, d.Vr, d.ldv, V_re, (long long)ldv, s));
-        if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, d.Vi, d.ldv, V_im, (long long)ldv, s));
+        HIPCHK(launch_copy2d(d.n, d.n, (const T *)d.Vr, d.ldv, V_re, (long long)ldv, s));
+        if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, (const T *)d.Vi, d.ldv, V_im, (long long)ldv, s));
     }
-    if (e) HIPCHK(hipMemcpyAsync(e, d.e, sizeof(double) * d.n, hipMemcpyDeviceToDevice, s));
-    if (f) HIPCHK(hipMemcpyAsync(f, d.f, sizeof(double) * d.n, hipMemcpyDeviceToDevice, s));
+    if (e) HIPCHK(hipMemcpyAsync(e, d.e, sizeof(T) * d.n, hipMemcpyDeviceToDevice, s));
+    if (f) HIPCHK(hipMemcpyAsync(f, d.f, sizeof(T) * d.n, hipMemcpyDeviceToDevice, s));
     const int rc = pull_scalars(st, s);
     if (rc != JSVD_OK) return rc;
     if (s_out) *s_out = st->host->s;
@@ -432,15 +536,31 @@ extern "C" int jsvd_state_save(jsvd_state st, double *G_re, double *G_im, size_t
     return JSVD_OK;
 }
 
-extern "C" int jsvd_state_restore(jsvd_state st, const double *G_re, const double *G_im, size_t ldg,
-                                  const double *V_re, const double *V_im, size_t ldv, int32_t s_in, double Mt,
-                                  int64_t step, void *stream)
+extern "C" int jsvd_state_save(jsvd_state st, double *G_re, double *G_im, size_t ldg, double *V_re,
+                               double *V_im, size_t ldv, double *e, double *f, int32_t *s_out, double *Mt,
+                               int64_t *step, void *stream)
 {
-    if (!st || !G_re || !V_re || ldg < (size_t)st->m || ldv < (size_t)st->n) return JSVD_EINVAL;
+    return save_t<double>(st, G_re, G_im, ldg, V_re, V_im, ldv, e, f, s_out, Mt, step, stream);
+}
+
+extern "C" int jsvd_state_save_f32(jsvd_state st, float *G_re, float *G_im, size_t ldg, float *V_re, float *V_im,
+                                   size_t ldv, float *e, float *f, int32_t *s_out, double *Mt, int64_t *step,
+                                   void *stream)
+{
+    return save_t<float>(st, G_re, G_im, ldg, V_re, V_im, ldv, e, f, s_out, Mt, step, stream);
+}
+
+template <typename T>
+static int restore_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, const T *V_re, const T *V_im,
+                     size_t ldv, int32_t s_in, double Mt, int64_t step, void *stream)
+{
+    if (!is_prec<T>(st) || !G_re || !V_re || ldg < (size_t)st->m || ldv < (size_t)st->n) return JSVD_EINVAL;
     if (st->cplx && (!G_im || !V_im)) return JSVD_EINVAL;
-    if (!(Mt >= 0.0 && Mt <= 1.79769313486231570815e308) || step < 0) return JSVD_EINVAL;
+    // M~ must be a finite non-negative value of the working precision
+    if (!(Mt >= 0.0 && Mt <= (double)std::numeric_limits<T>::max()) || (double)(T)Mt != Mt || step < 0)
+        return JSVD_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const SvdDesc &d = st->d;
+    const SvdDescT<T> &d = desc_of<T>(st);
     HIPCHK(launch_copy2d(d.m, d.n, G_re, (long long)ldg, d.Gr, d.ldg, s));
     if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, G_im, (long long)ldg, d.Gi, d.ldg, s));
     HIPCHK(launch_copy2d(d.n, d.n, V_re, (long long)ldv, d.Vr, d.ldv, s));
@@ -454,22 +574,50 @@ extern "C" int jsvd_state_restore(jsvd_state st, const double *G_re, const doubl
     return push_scalars(st, h, s);
 }
 
+extern "C" int jsvd_state_restore(jsvd_state st, const double *G_re, const double *G_im, size_t ldg,
+                                  const double *V_re, const double *V_im, size_t ldv, int32_t s_in, double Mt,
+                                  int64_t step, void *stream)
+{
+    return restore_t<double>(st, G_re, G_im, ldg, V_re, V_im, ldv, s_in, Mt, step, stream);
+}
+
+extern "C" int jsvd_state_restore_f32(jsvd_state st, const float *G_re, const float *G_im, size_t ldg,
+                                      const float *V_re, const float *V_im, size_t ldv, int32_t s_in, double Mt,
+                                      int64_t step, void *stream)
+{
+    return restore_t<float>(st, G_re, G_im, ldg, V_re, V_im, ldv, s_in, Mt, step, stream);
+}
+
+template <typename T>
+static int finalize_t(jsvd_state st, T *U_re, T *U_im, size_t ldu, T *V_re, T *V_im, size_t ldv, T *sv_e, T *sv_f,
+                      T *sv, void *stream)
+{
+    if (!is_prec<T>(st) || !U_re || !V_re || !sv_e || !sv_f || ldu < (size_t)st->m || ldv < (size_t)st->n)
+        return JSVD_EINVAL;
+    if (st->cplx && (!U_im || !V_im)) return JSVD_EINVAL;
+    return finish_async_t<T>(st, true, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, (hipStream_t)stream);
+}
+
 extern "C" int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu, double *V_re,
                                    double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv,
                                    void *stream)
 {
-    if (!st || !U_re || !V_re || !sv_e || !sv_f || ldu < (size_t)st->m || ldv < (size_t)st->n)
-        return JSVD_EINVAL;
-    if (st->cplx && (!U_im || !V_im)) return JSVD_EINVAL;
-    return state_finish_async(st, true, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, (hipStream_t)stream);
+    return finalize_t<double>(st, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, stream);
+}
+
+extern "C" int jsvd_state_finalize_f32(jsvd_state st, float *U_re, float *U_im, size_t ldu, float *V_re,
+                                       float *V_im, size_t ldv, float *sv_e, float *sv_f, float *sv, void *stream)
+{
+    return finalize_t<float>(st, U_re, U_im, ldu, V_re, V_im, ldv, sv_e, sv_f, sv, stream);
 }
 
 // ---------------------------------------------------------------------------
 // the whole SVD
-static int gesvj_on_state(jsvd_state st, double *G_re, double *G_im, size_t ldg, double *V_re, double *V_im,
-                          size_t ldv, double *sv_e, double *sv_f, double *sv, int *sweeps, hipStream_t s)
+template <typename T>
+static int gesvj_on_state(jsvd_state st, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im, size_t ldv, T *sv_e,
+                          T *sv_f, T *sv, int *sweeps, hipStream_t s)
 {
-    int rc = state_load_async(st, G_re, G_im, ldg, s);
+    int rc = load_async_t<T>(st, G_re, G_im, ldg, s);
     if (rc != JSVD_OK) return rc;
     // one graph-launched sweep at a time; the device decides convergence
     for (;;) {
@@ -481,28 +629,45 @@ static int gesvj_on_state(jsvd_state st, double *G_re, double *G_im, size_t ldg,
     const DevScalars h = *st->host;
     if (sweeps) *sweeps = (int)h.C;
     if (h.status != 0) return h.status;
-    rc = state_finish_async(st, h.converged != 0, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, s);
+    rc = finish_async_t<T>(st, h.converged != 0, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, s);
     if (rc != JSVD_OK) return rc;
     HIPCHK(hipStreamSynchronize(s));
     return h.converged ? JSVD_OK : JSVD_NOT_CONVERGED;
+}
+
+template <typename T>
+static int gesvj_t(int m, int n, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im, size_t ldv, T *sv_e, T *sv_f,
+                   T *sv, int max_sweeps, int *sweeps, unsigned flags, void *stream)
+{
+    constexpr bool F32 = sizeof(T) == sizeof(float);
+    if (n < 1 || m < n || !G_re || !V_re || !sv_e || !sv_f || ldg < (size_t)m || ldv < (size_t)n)
+        return JSVD_EINVAL;
+    if ((G_im == nullptr) != (V_im == nullptr)) return JSVD_EINVAL;
+    if (flags & ~(F32 ? (unsigned)JSVD_NO_PERMUTE : kIterFlags)) return JSVD_EINVAL;
+    jsvd_state st = nullptr;
+    int rc = state_create(m, n, G_im != nullptr, F32, &st);
+    if (rc != JSVD_OK) return rc;
+    st->max_sweeps = max_sweeps > 0 ? max_sweeps : 128;
+    apply_flags(st, flags);
+    rc = gesvj_on_state<T>(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, sweeps, (hipStream_t)stream);
+    jsvd_state_destroy(st);
+    return rc;
 }
 
 extern "C" int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg, double *V_re, double *V_im,
                           size_t ldv, double *sv_e, double *sv_f, double *sv, int max_sweeps, int *sweeps,
                           unsigned flags, void *stream)
 {
-    if (n < 1 || m < n || !G_re || !V_re || !sv_e || !sv_f || ldg < (size_t)m || ldv < (size_t)n)
-        return JSVD_EINVAL;
-    if ((G_im == nullptr) != (V_im == nullptr)) return JSVD_EINVAL;
-    if (flags & ~kIterFlags) return JSVD_EINVAL;
-    jsvd_state st = nullptr;
-    int rc = jsvd_state_create(m, n, G_im != nullptr, &st);
-    if (rc != JSVD_OK) return rc;
-    st->max_sweeps = max_sweeps > 0 ? max_sweeps : 128;
-    apply_flags(st, flags);
-    rc = gesvj_on_state(st, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, sweeps, (hipStream_t)stream);
-    jsvd_state_destroy(st);
-    return rc;
+    return gesvj_t<double>(m, n, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, max_sweeps, sweeps, flags,
+                           stream);
+}
+
+extern "C" int jsvd_gesvj_f32(int m, int n, float *G_re, float *G_im, size_t ldg, float *V_re, float *V_im,
+                              size_t ldv, float *sv_e, float *sv_f, float *sv, int max_sweeps, int *sweeps,
+                              unsigned flags, void *stream)
+{
+    return gesvj_t<float>(m, n, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, sv, max_sweeps, sweeps, flags,
+                          stream);
 }
 
 // ---------------------------------------------------------------------------

@@ -40,21 +40,27 @@ struct DevScalars {
     int status;                   // init status: 0, or -2 (non-finite), -3 (zero)
 };
 
-// Problem description shared by the SVD kernels.
-struct SvdDesc {
+// Problem description shared by the SVD kernels, for the working precision T
+// (double, or float for the single precision variant).  Device scalars that
+// hold a value of the working precision (M~, the max-norms) keep it as a
+// double: a float converts to double and back exactly.
+template <typename T>
+struct SvdDescT {
     int m, n;
     int cplx;
     int nosort;            // ignore the permutation of the EVD during the iteration
-    int comp;              // compensated scaled dot-products (Alg. zdpsclcs / ddpsclcs)
-    double *Gr, *Gi;       // working iteration matrix
+    int comp;              // compensated scaled dot-products (Alg. zdpsclcs / ddpsclcs; double only)
+    T *Gr, *Gi;            // working iteration matrix
     long long ldg;
-    double *Vr, *Vi;       // accumulated right transformations
+    T *Vr, *Vi;            // accumulated right transformations
     long long ldv;
-    double *e, *f;         // column norms of the last step (e as double)
+    T *e, *f;              // column norms of the last step (e as a value of type T)
     DevScalars *sc;
-    int lgbound;           // floor(lg(nu/(varsigma m))) of eq. (skn)
-    double ups;            // fl(sqrt(m)) 2^-53
+    int lgbound;           // floor(lg(nu/(varsigma m))) of eq. (skn), nu = DBL_MAX or FLT_MAX
+    T ups;                 // fl(sqrt(m)) eps, eps = 2^-53 or 2^-24
 };
+using SvdDesc = SvdDescT<double>;
+using SvdDescF = SvdDescT<float>;
 
 // outcome of one pivot pair, written by the G kernels for the V kernel and
 // for the end-of-step fold
@@ -69,9 +75,11 @@ struct PairParam {
 // step for large columns (gstep.hip): rows per thread of the G kernel for m
 // (0 = not supported); the V kernel (applies the rotations in prm and folds
 // the step into the device scalars); the G kernel followed by the V kernel
-int gpair_rows(int m, int cplx);
-hipError_t launch_vrot(const SvdDesc &d, const PairParam *prm, hipStream_t s);
-hipError_t launch_gpair(const SvdDesc &d, PairParam *prm, hipStream_t s);
+int gpair_rows(int m, int cplx, bool fp32 = false);
+template <typename T>
+hipError_t launch_vrot(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s);
+template <typename T>
+hipError_t launch_gpair(const SvdDescT<T> &d, PairParam *prm, hipStream_t s);
 
 // batched scaled dot-products (dot.hip): rows per thread for m (0 = not
 // supported) and the launch (one workgroup per column pair)
@@ -82,29 +90,35 @@ hipError_t launch_dot(int npairs, int m, const double *Qr, const double *Qi, con
 
 // initialisation: M~_0 into *maxbits (zeroed by the caller), then
 // G <- 2^{s_0} A copied into the workspace and V <- I
-hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
-                         unsigned long long *maxbits, hipStream_t s);
-hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
+template <typename T>
+hipError_t launch_maxabs(const SvdDescT<T> &d, const T *Ar, const T *Ai, long long lda, unsigned long long *maxbits,
+                         hipStream_t s);
+template <typename T>
+hipError_t launch_init_scale(const SvdDescT<T> &d, const T *Ar, const T *Ai, long long lda,
                              const unsigned long long *maxbits, int max_sweeps, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 // one parallel step; threads = 0 picks automatically
-hipError_t launch_step(const SvdDesc &d, int threads, hipStream_t s);
+template <typename T>
+hipError_t launch_step(const SvdDescT<T> &d, int threads, hipStream_t s);
 int step_max_rows(int cplx, int W);
 int step_auto_threads(int m, int n);
 // end-of-sweep bookkeeping (1 thread)
-hipError_t launch_sweep_end(const SvdDesc &d, hipStream_t s);
+hipError_t launch_sweep_end(DevScalars *sc, hipStream_t s);
 // finalisation: norms of all columns into d.e/d.f, their descending ranks,
 // then U = G diag(2^-e)/f and V permuted into the caller's buffers
-hipError_t launch_colnorms_raw(const SvdDesc &d, hipStream_t s);
-hipError_t launch_rank(const SvdDesc &d, int *rank, hipStream_t s);
-hipError_t launch_final_write(const SvdDesc &d, const int *rank, double *Ur, double *Ui, long long ldu,
-                              double *Vr, double *Vi, long long ldv, double *sv_e, double *sv_f,
-                              double *sv, hipStream_t s);
+template <typename T>
+hipError_t launch_colnorms_raw(const SvdDescT<T> &d, hipStream_t s);
+template <typename T>
+hipError_t launch_rank(const SvdDescT<T> &d, int *rank, hipStream_t s);
+template <typename T>
+hipError_t launch_final_write(const SvdDescT<T> &d, const int *rank, T *Ur, T *Ui, long long ldu, T *Vr, T *Vi,
+                              long long ldv, T *sv_e, T *sv_f, T *sv, hipStream_t s);
 // non-converged exit: the current norms, backscaled, in column order
-hipError_t launch_colnorm_out(const SvdDesc &d, double *sv_e, double *sv_f, double *sv, hipStream_t s);
-// strided 2D copy of doubles (device to device), and 2D scaling by 2^e
-hipError_t launch_copy2d(int m, int n, const double *src, long long lds, double *dst, long long ldd,
-                         hipStream_t s);
+template <typename T>
+hipError_t launch_colnorm_out(const SvdDescT<T> &d, T *sv_e, T *sv_f, T *sv, hipStream_t s);
+// strided 2D copy (device to device), and 2D scaling by 2^e
+template <typename T>
+hipError_t launch_copy2d(int m, int n, const T *src, long long lds, T *dst, long long ldd, hipStream_t s);
 hipError_t launch_split(int m, int n, const double *Z, long long ldz, double *Xr, double *Xi,
                         long long ldx, hipStream_t s);
 hipError_t launch_merge(int m, int n, const double *Xr, const double *Xi, long long ldx, double *Z,

@@ -31,14 +31,37 @@ __device__ __forceinline__ unsigned long long d2bits(double x) { return (unsigne
 
 // floor(lg |x|) for finite non-zero x (subnormals included)
 __device__ __forceinline__ int getexp(double x) { return __builtin_amdgcn_frexp_exp(x) - 1; }
+__device__ __forceinline__ int getexp(float x) { return __builtin_amdgcn_frexp_expf(x) - 1; }
+
+// x * 2^e in single precision, correctly rounded (v_ldexp_f32)
+__device__ __forceinline__ float scal2(float x, int e) { return __builtin_amdgcn_ldexpf(x, e); }
+
+// Range constants of the SVD in the precision T (Sect. 3.2, eq. skr; Alg.
+// Gram), from nu = DBL_MAX or FLT_MAX (the single precision routines redefine
+// nu, Sect. 2.4.1):
+//   round_real / round_cplx: floor(lg(nu/2)) and floor(lg(nu/(4 sqrt 2))) - 1,
+//     so s_(k) = round - floor(lg M~);
+//   gram_emax: the largest finite exponent, DBL_MAX_EXP - 1 or FLT_MAX_EXP - 1;
+//   eps_exp: lg eps of the convergence tolerance upsilon = fl(sqrt m) eps.
+template <typename T>
+struct SvdFp;
+template <>
+struct SvdFp<double> {
+    static constexpr int round_real = 1022, round_cplx = 1020, gram_emax = 1023, eps_exp = -53;
+};
+template <>
+struct SvdFp<float> {
+    static constexpr int round_real = 126, round_cplx = 124, gram_emax = 127, eps_exp = -24;
+};
 
 // Alg. hypot: M sqrt((m/M)^2 + 1), q = max(m/M, 0)
-__device__ __forceinline__ double hypot_naive(double x, double y)
+template <typename T>
+__device__ __forceinline__ T hypot_naive(T x, T y)
 {
-    const double ax = fabs(x), ay = fabs(y);
-    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
-    const double q = fmax(mn / mx, 0.0);
-    return sqrt(fma(q, q, 1.0)) * mx;
+    const T ax = fabs(x), ay = fabs(y);
+    const T mn = fmin(ax, ay), mx = fmax(ax, ay);
+    const T q = fmax(mn / mx, T(0));
+    return sqrt(fma(q, q, T(1))) * mx;
 }
 
 // Round-robin pair l of step kk (circle method): N = n rounded up to even,
@@ -86,14 +109,16 @@ __device__ __forceinline__ void lds_barrier()
 // In-wave halving tree: after the call lane 0 holds x_0 + x_1 + ... in the
 // canonical order (lane i += lane i+h for h = 32, ..., 1); the total is
 // broadcast to every lane.
-__device__ __forceinline__ double wave_tree_sum(double x)
+template <typename T>
+__device__ __forceinline__ T wave_tree_sum(T x)
 {
 #pragma unroll
     for (int h = 32; h >= 1; h >>= 1) x = x + __shfl_down(x, h, 64);
     return __shfl(x, 0, 64);
 }
 
-__device__ __forceinline__ double wave_max(double x)
+template <typename T>
+__device__ __forceinline__ T wave_max(T x)
 {
 #pragma unroll
     for (int h = 32; h >= 1; h >>= 1) x = fmax(x, __shfl_xor(x, h, 64));
@@ -101,10 +126,10 @@ __device__ __forceinline__ double wave_max(double x)
 }
 
 // Group-wide canonical sum of NQ quantities (one value per thread each, the
-// thread's in-thread tree already applied).  lds must hold NQ * W doubles and
+// thread's in-thread tree already applied).  lds must hold NQ * W values and
 // must not be reused by the caller until after the next workgroup barrier.
-template <int W, int NQ>
-__device__ __forceinline__ void group_tree_sum(double (&v)[NQ], double *lds)
+template <int W, int NQ, typename T>
+__device__ __forceinline__ void group_tree_sum(T (&v)[NQ], T *lds)
 {
     constexpr int NW = W / 64;
     if constexpr (NW == 1) {
@@ -117,7 +142,7 @@ __device__ __forceinline__ void group_tree_sum(double (&v)[NQ], double *lds)
         lds_barrier();
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            double x[NW];
+            T x[NW];
 #pragma unroll
             for (int w = 0; w < NW; ++w) x[w] = lds[q * W + w * 64 + lane];
             // thread index t = 64 w + lane: levels h >= 64 combine whole waves
@@ -131,8 +156,8 @@ __device__ __forceinline__ void group_tree_sum(double (&v)[NQ], double *lds)
 }
 
 // Group-wide max of NQ non-negative quantities (exact, order-free).
-template <int W, int NQ>
-__device__ __forceinline__ void group_max(double (&v)[NQ], double *lds)
+template <int W, int NQ, typename T>
+__device__ __forceinline__ void group_max(T (&v)[NQ], T *lds)
 {
     constexpr int NW = W / 64;
 #pragma unroll
@@ -146,7 +171,7 @@ __device__ __forceinline__ void group_max(double (&v)[NQ], double *lds)
         lds_barrier();
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            double x = lds[q * NW];
+            T x = lds[q * NW];
 #pragma unroll
             for (int w = 1; w < NW; ++w) x = fmax(x, lds[q * NW + w]);
             v[q] = x;
@@ -165,8 +190,8 @@ struct LaneShape {
     static constexpr int CH = (R + V - 1) / V;
 };
 
-template <int V, int NL>
-__device__ __forceinline__ double thread_tree(double (&acc)[NL])
+template <int V, int NL, typename T>
+__device__ __forceinline__ T thread_tree(T (&acc)[NL])
 {
 #pragma unroll
     for (int h = V / 2; h >= 1; h >>= 1)
@@ -249,16 +274,19 @@ __device__ __forceinline__ void cs_term(double x, double y, double &s, double &t
 // Column norm in (e, f) form (Sect. 3.2 and SM6.1): prescale by 2^-E with
 // E = floor(lg max|x|), canonical sum of squares, sqrt, and for complex data
 // the naive hypot of the real and imaginary norms.  Zero column: e = -inf.
-struct Norm {
+template <typename T>
+struct NormT {
     int zero;   // the column is zero
     int e;      // exponent (valid when !zero)
-    double f;   // fraction in [1, 2)
+    T f;        // fraction in [1, 2)
 };
+using Norm = NormT<double>;
 
-__device__ __forceinline__ Norm norm_from_sums(int E, double sr, double si, bool cplx)
+template <typename T>
+__device__ __forceinline__ NormT<T> norm_from_sums(int E, T sr, T si, bool cplx)
 {
-    Norm o;
-    const double r = cplx ? hypot_naive(sqrt(sr), sqrt(si)) : sqrt(sr);
+    NormT<T> o;
+    const T r = cplx ? hypot_naive(sqrt(sr), sqrt(si)) : sqrt(sr);
     const int er = getexp(r);
     o.zero = 0;
     o.e = E + er;
@@ -271,19 +299,20 @@ __device__ __forceinline__ Norm norm_from_sums(int E, double sr, double si, bool
 namespace jsvd {
 
 // Alg. Gram (eqs. sGramEF, efpq, F): A'' = 2^{sA} [[|g_p|/|g_q|, .], [a21', |g_q|/|g_p|]],
-// sA = min(DBL_MAX_EXP - 1 - max(e12, e21), 0)
-__device__ __forceinline__ void gram_scaled(double zr, double zi, int e1, double f1, int e2, double f2,
-                                            double *a11, double *a22, double *a21r, double *a21i)
+// sA = min(DBL_MAX_EXP - 1 - max(e12, e21), 0) (FLT_MAX_EXP - 1 in single precision)
+template <typename T>
+__device__ __forceinline__ void gram_scaled(T zr, T zi, int e1, T f1, int e2, T f2, T *a11, T *a22, T *a21r,
+                                            T *a21i)
 {
-    double f12 = f1 / f2;
-    double f21 = f2 / f1;
+    T f12 = f1 / f2;
+    T f21 = f2 / f1;
     int e12 = e1 - e2, e21 = e2 - e1;
     const int g12 = getexp(f12), g21 = getexp(f21);
     e12 += g12;
     f12 = scal2(f12, -g12);
     e21 += g21;
     f21 = scal2(f21, -g21);
-    const int sA = min(1023 - max(e12, e21), 0);
+    const int sA = min(SvdFp<T>::gram_emax - max(e12, e21), 0);
     e12 += sA;
     e21 += sA;
     *a11 = scal2(f12, e12);
@@ -298,19 +327,21 @@ __device__ __forceinline__ void gram_scaled(double zr, double zi, int e1, double
 // ddpsclcs (compensated per lane; the four sums of each real stream reduced
 // one by one and added as ((s' + t') + t) + s).  The imaginary stream takes
 // Re(g_q) Im(g_p), then (-Im(g_q)) Re(g_p), which is the stated result
-// g_q^* g_p.  lds: (COMP ? 4 : 1) * (CPLX ? 2 : 1) * W doubles (W > 64).
-template <bool CPLX, int W, int R, bool COMP>
-__device__ __forceinline__ void pair_dot(const double (&xr)[2][R], const double (&xi)[2][R], int ep, int eq,
-                                         double (&h)[2], double *lds)
+// g_q^* g_p.  lds: (COMP ? 4 : 1) * (CPLX ? 2 : 1) * W values (W > 64).  The
+// compensated variant is defined for double precision only.
+template <bool CPLX, int W, int R, bool COMP, typename T>
+__device__ __forceinline__ void pair_dot(const T (&xr)[2][R], const T (&xi)[2][R], int ep, int eq, T (&h)[2],
+                                         T *lds)
 {
     using LS = LaneShape<W, R>;
     constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
+    static_assert(!COMP || sizeof(T) == sizeof(double), "compensated dot-products are double precision");
     if constexpr (!COMP) {
-        double dr[NL], di[NL];
+        T dr[NL], di[NL];
 #pragma unroll
         for (int v = 0; v < NL; ++v) {
-            dr[v] = 0.0;
-            di[v] = 0.0;
+            dr[v] = T(0);
+            di[v] = T(0);
         }
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch)
@@ -318,9 +349,9 @@ __device__ __forceinline__ void pair_dot(const double (&xr)[2][R], const double 
             for (int v = 0; v < NL; ++v) {
                 const int j = ch * V + v;
                 if (j < R) {
-                    const double gqr = scal2(xr[1][j], -eq), gpr = scal2(xr[0][j], -ep);
+                    const T gqr = scal2(xr[1][j], -eq), gpr = scal2(xr[0][j], -ep);
                     if (CPLX) {
-                        const double gqi = scal2(xi[1][j], -eq), gpi = scal2(xi[0][j], -ep);
+                        const T gqi = scal2(xi[1][j], -eq), gpi = scal2(xi[0][j], -ep);
                         dr[v] = fma(gqr, gpr, dr[v]);
                         di[v] = fma(gqr, gpi, di[v]);
                         dr[v] = fma(gqi, gpi, dr[v]);
@@ -331,12 +362,12 @@ __device__ __forceinline__ void pair_dot(const double (&xr)[2][R], const double 
                 }
             }
         constexpr int ND = CPLX ? 2 : 1;
-        double g[ND];
+        T g[ND];
         g[0] = thread_tree<V>(dr);
         if (CPLX) g[ND - 1] = thread_tree<V>(di);
         group_tree_sum<W, ND>(g, lds);
         h[0] = g[0];
-        h[1] = CPLX ? g[ND - 1] : 0.0;
+        h[1] = CPLX ? g[ND - 1] : T(0);
     } else {
         // [stream][s, t, s', t'][lane]
         constexpr int NS = CPLX ? 2 : 1;
@@ -380,27 +411,30 @@ __device__ __forceinline__ void pair_dot(const double (&xr)[2][R], const double 
 }
 
 // Decision for one pivot pair held in registers by a group of W threads.
-struct PairDecision {
-    Norm np, nq;   // the column norms (e, f) before the transformation
+template <typename T>
+struct PairDecisionT {
+    NormT<T> np, nq;   // the column norms (e, f) before the transformation
     bool transform;
-    int pbit;      // the permutation of the EVD (0 when ignored)
-    double c, C, S;
+    int pbit;          // the permutation of the EVD (0 when ignored)
+    T c, C, S;
 };
+using PairDecision = PairDecisionT<double>;
 
 // Norms (Sect. 3.2), scaled dot-product (Alg. zdpscl, or zdpsclcs /
 // ddpsclcs with COMP), convergence test (Alg. cvg), scaled Gram matrix
 // (Alg. Gram) and 2x2 EVD (Listing 1) of the pair (xr/xi[0] = column p,
 // [1] = column q; rows t + W j, zeros beyond m).  Scratch: red_norm (4 W
-// doubles), red_dot (2 W doubles, 8 W with COMP), mxs (2 W/64 doubles);
-// unused for W = 64.  Every thread returns the same decision.
-template <bool CPLX, int W, int R, bool COMP = false>
-__device__ __forceinline__ PairDecision pair_core(const double (&xr)[2][R], const double (&xi)[2][R], double ups,
-                                                  int nosort, double *red_norm, double *red_dot, double *mxs)
+// values), red_dot (2 W values, 8 W with COMP), mxs (2 W/64 values);
+// unused for W = 64.  Every thread returns the same decision.  All of it in
+// the precision T, with that precision's constants.
+template <bool CPLX, int W, int R, bool COMP = false, typename T>
+__device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const T (&xi)[2][R], T ups, int nosort,
+                                                      T *red_norm, T *red_dot, T *mxs)
 {
     using LS = LaneShape<W, R>;
     constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
-    PairDecision o;
-    double mx[2] = {0.0, 0.0};
+    PairDecisionT<T> o;
+    T mx[2] = {T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < R; ++j)
 #pragma unroll
@@ -409,57 +443,57 @@ __device__ __forceinline__ PairDecision pair_core(const double (&xr)[2][R], cons
             if (CPLX) mx[c] = fmax(mx[c], fabs(xi[c][j]));
         }
     group_max<W, 2>(mx, mxs);
-    const bool zp_ = mx[0] == 0.0, zq_ = mx[1] == 0.0;
+    const bool zp_ = mx[0] == T(0), zq_ = mx[1] == T(0);
     const int Ep = zp_ ? 0 : getexp(mx[0]);
     const int Eq = zq_ ? 0 : getexp(mx[1]);
     constexpr int NQ = CPLX ? 4 : 2;
-    double acc[NQ][NL];
+    T acc[NQ][NL];
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq)
 #pragma unroll
-        for (int v = 0; v < NL; ++v) acc[qq][v] = 0.0;
+        for (int v = 0; v < NL; ++v) acc[qq][v] = T(0);
 #pragma unroll
     for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
         for (int v = 0; v < NL; ++v) {
             const int j = ch * V + v;
             if (j < R) {
-                const double ypr = scal2(xr[0][j], -Ep), yqr = scal2(xr[1][j], -Eq);
+                const T ypr = scal2(xr[0][j], -Ep), yqr = scal2(xr[1][j], -Eq);
                 acc[0][v] = fma(ypr, ypr, acc[0][v]);
                 acc[1][v] = fma(yqr, yqr, acc[1][v]);
                 if (CPLX) {
-                    const double ypi = scal2(xi[0][j], -Ep), yqi = scal2(xi[1][j], -Eq);
+                    const T ypi = scal2(xi[0][j], -Ep), yqi = scal2(xi[1][j], -Eq);
                     acc[2][v] = fma(ypi, ypi, acc[2][v]);
                     acc[3][v] = fma(yqi, yqi, acc[3][v]);
                 }
             }
         }
-    double s[NQ];
+    T s[NQ];
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
     group_tree_sum<W, NQ>(s, red_norm);
-    o.np = norm_from_sums(Ep, s[0], CPLX ? s[2] : 0.0, CPLX);
-    o.nq = norm_from_sums(Eq, s[1], CPLX ? s[3] : 0.0, CPLX);
+    o.np = norm_from_sums(Ep, s[0], CPLX ? s[2] : T(0), CPLX);
+    o.nq = norm_from_sums(Eq, s[1], CPLX ? s[3] : T(0), CPLX);
     o.np.zero = zp_;
     o.nq.zero = zq_;
     o.transform = false;
-    o.c = 1.0;
-    o.C = 0.0;
-    o.S = 0.0;
+    o.c = T(1);
+    o.C = T(0);
+    o.S = T(0);
     if (zp_ || zq_) {
         // a zero column is never rotated; it goes after the other one
         o.pbit = (zp_ && !zq_) ? 1 : 0;
     } else {
-        double h[2];
+        T h[2];
         pair_dot<CPLX, W, R, COMP>(xr, xi, o.np.e, o.nq.e, h, red_dot);
-        const double dd = o.nq.f * o.np.f;
-        const double zr = h[0] / dd;
-        const double zi = CPLX ? h[1] / dd : 0.0;
-        const double az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
+        const T dd = o.nq.f * o.np.f;
+        const T zr = h[0] / dd;
+        const T zi = CPLX ? h[1] / dd : T(0);
+        const T az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
         o.transform = ups <= az;
-        double a11, a22, a21r, a21i;
+        T a11, a22, a21r, a21i;
         gram_scaled(zr, zi, o.np.e, o.np.f, o.nq.e, o.nq.f, &a11, &a22, &a21r, &a21i);
-        const Evd2Out e = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
+        const Evd2OutT<T> e = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
         o.c = e.c;
         o.C = e.C;
         o.S = e.S;
@@ -471,15 +505,15 @@ __device__ __forceinline__ PairDecision pair_core(const double (&xr)[2][R], cons
 
 // Rotation of a register pair (Alg. zjrot, eq. transf with the complex fma
 // of eq. zfma): xr/xi[0] <- x_p', [1] <- x_q'; returns the thread's max-norm.
-template <bool CPLX, int R>
-__device__ __forceinline__ double rot_regs(double (&xr)[2][R], double (&xi)[2][R], double c, double C, double S)
+template <bool CPLX, int R, typename T>
+__device__ __forceinline__ T rot_regs(T (&xr)[2][R], T (&xi)[2][R], T c, T C, T S)
 {
-    double Mx = 0.0;
+    T Mx = T(0);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const double pr = xr[0][j], qr = xr[1][j];
+        const T pr = xr[0][j], qr = xr[1][j];
         if (CPLX) {
-            const double pi = xi[0][j], qi = xi[1][j];
+            const T pi = xi[0][j], qi = xi[1][j];
             xr[0][j] = fma(qr, C, fma(-qi, S, pr)) * c;
             xi[0][j] = fma(qr, S, fma(qi, C, pi)) * c;
             xr[1][j] = fma(pr, -C, fma(-pi, S, qr)) * c;

@@ -11,13 +11,16 @@
 
 struct jsvd_state_s {
     int m, n, cplx;
+    int fp32;          // single precision state: float G, V and norms (descriptor df)
     int threads;       // forced workgroup size (0 = automatic)
     int max_sweeps;
     int device;
     int ncu;           // compute units (persistent grid size)
     void *mem;         // the single device allocation
     size_t mem_bytes;
-    jsvd::SvdDesc d;
+    jsvd::SvdDesc d;     // double precision descriptor (fp32 == 0)
+    jsvd::SvdDescF df;   // single precision descriptor (fp32 != 0)
+    jsvd::DevScalars *sc;  // the device scalars (either descriptor's sc)
     int *rank;
     unsigned long long *maxbits;
     jsvd::PairParam *prm;
@@ -31,15 +34,18 @@ struct jsvd_state_s {
 
 namespace jsvd {
 
-// Bytes of device memory a state for this problem allocates.
-size_t state_bytes(int m, int n, int cplx);
+// Bytes of device memory a state for this problem allocates (fp32: the
+// single precision state).
+size_t state_bytes(int m, int n, int cplx, bool fp32 = false);
 
 // Set the iteration flags (JSVD_NO_PERMUTE | JSVD_COMPENSATED) of a state.
 int state_set_flags(jsvd_state st, unsigned flags);
 
 // Enqueue the load of G (M~_0, s_0, G_1 = 2^{s_0} G, V_1 = I); a non-finite or
-// zero G leaves the state stopped with that status.
+// zero G leaves the state stopped with that status.  The double overloads
+// need a double precision state, the float ones a single precision state.
 int state_load_async(jsvd_state st, const double *G_re, const double *G_im, size_t ldg, hipStream_t s);
+int state_load_async(jsvd_state st, const float *G_re, const float *G_im, size_t ldg, hipStream_t s);
 // Enqueue one sweep (a graph of K steps and the end-of-sweep bookkeeping)
 // followed by the copy of the scalars into the state's pinned staging area.
 int state_sweep_async(jsvd_state st, hipStream_t s);
@@ -51,5 +57,7 @@ const DevScalars &state_staged(jsvd_state st);
 // column norms.
 int state_finish_async(jsvd_state st, bool converged, double *U_re, double *U_im, size_t ldu, double *V_re,
                        double *V_im, size_t ldv, double *sv_e, double *sv_f, double *sv, hipStream_t s);
+int state_finish_async(jsvd_state st, bool converged, float *U_re, float *U_im, size_t ldu, float *V_re,
+                       float *V_im, size_t ldv, float *sv_e, float *sv_f, float *sv, hipStream_t s);
 
 } // namespace jsvd

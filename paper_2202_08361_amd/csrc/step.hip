@@ -22,40 +22,40 @@
 
 namespace jsvd {
 
-template <int W, bool COMP>
+template <int W, bool COMP, typename T>
 struct StepSmem {
-    double norm[4 * W];
-    double dot[(COMP ? 8 : 2) * W];
-    double mx1[2 * (W / 64)];
-    double mx2[W / 64];
+    T norm[4 * W];
+    T dot[(COMP ? 8 : 2) * W];
+    T mx1[2 * (W / 64)];
+    T mx2[W / 64];
 };
 
-template <bool CPLX, int W, int R, bool COMP>
-__global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
+template <bool CPLX, int W, int R, bool COMP, typename T>
+__global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
 {
-    __shared__ StepSmem<W, COMP> sm;
+    __shared__ StepSmem<W, COMP, T> sm;
     DevScalars *sc = d.sc;
     if (*(volatile int *)&sc->stop) return;
     const long long k = *(volatile long long *)&sc->k;
-    const double Mt = bits2d(*(volatile unsigned long long *)&sc->Mt_bits);
+    const T Mt = (T)bits2d(*(volatile unsigned long long *)&sc->Mt_bits);
     const int m = d.m, n = d.n;
     const int t = threadIdx.x;
     int p, q;
     const bool valid = rr_pair(n, k, (int)blockIdx.x, &p, &q);
 
     // step-start rescaling check, Sect. 3.2: s_(k) < 0 => scale by 2^{s_[k]}
-    const int sr = (CPLX ? 1020 : 1022) - getexp(Mt);
+    const int sr = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt);
     const bool rescale = sr < 0;
     const int sp = rescale ? (d.lgbound - getexp(Mt) - 1) : 0;
 
-    double *const Gpr = d.Gr + (size_t)p * d.ldg;
-    double *const Gqr = d.Gr + (size_t)q * d.ldg;
-    double *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
-    double *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
+    T *const Gpr = d.Gr + (size_t)p * d.ldg;
+    T *const Gqr = d.Gr + (size_t)q * d.ldg;
+    T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
+    T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
 
     bool transform = false;
     int pbit = 0;
-    double Mblk = 0.0;
+    T Mblk = T(0);
 
     if (!valid) {
         // the column sitting out this step (odd n): only the rescaling applies
@@ -66,16 +66,16 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
             }
         }
     } else {
-        double xr[2][R], xi[2][R];
+        T xr[2][R], xi[2][R];
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = t + W * j;
             const bool in = i < m;
-            xr[0][j] = in ? Gpr[i] : 0.0;
-            xr[1][j] = in ? Gqr[i] : 0.0;
+            xr[0][j] = in ? Gpr[i] : T(0);
+            xr[1][j] = in ? Gqr[i] : T(0);
             if (CPLX) {
-                xi[0][j] = in ? Gpi[i] : 0.0;
-                xi[1][j] = in ? Gqi[i] : 0.0;
+                xi[0][j] = in ? Gpi[i] : T(0);
+                xi[1][j] = in ? Gqi[i] : T(0);
             }
         }
         if (rescale) {
@@ -88,18 +88,18 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                 }
         }
 
-        const PairDecision dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, sm.norm, sm.dot, sm.mx1);
+        const PairDecisionT<T> dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, sm.norm, sm.dot, sm.mx1);
         transform = dc.transform;
         pbit = dc.pbit;
-        const Norm np_ = dc.np, nq_ = dc.nq;
+        const NormT<T> np_ = dc.np, nq_ = dc.nq;
 
         // ---- rotation (Alg. zjrot) or swap of the G pair, then of the V pair
-        double *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
-        double *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
-        double *const Dp_i = pbit ? Gqi : Gpi;
-        double *const Dq_i = pbit ? Gpi : Gqi;
+        T *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
+        T *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
+        T *const Dp_i = pbit ? Gqi : Gpi;
+        T *const Dq_i = pbit ? Gpi : Gqi;
         if (transform) {
-            const double Mx = rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S);
+            const T Mx = rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
@@ -112,24 +112,24 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                     }
                 }
             }
-            double *const Vpr = d.Vr + (size_t)p * d.ldv;
-            double *const Vqr = d.Vr + (size_t)q * d.ldv;
-            double *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
-            double *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
-            double *const Ep_r = pbit ? Vqr : Vpr;
-            double *const Eq_r = pbit ? Vpr : Vqr;
-            double *const Ep_i = pbit ? Vqi : Vpi;
-            double *const Eq_i = pbit ? Vpi : Vqi;
-            double vr[2][R], vi[2][R];
+            T *const Vpr = d.Vr + (size_t)p * d.ldv;
+            T *const Vqr = d.Vr + (size_t)q * d.ldv;
+            T *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
+            T *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
+            T *const Ep_r = pbit ? Vqr : Vpr;
+            T *const Eq_r = pbit ? Vpr : Vqr;
+            T *const Ep_i = pbit ? Vqi : Vpi;
+            T *const Eq_i = pbit ? Vpi : Vqi;
+            T vr[2][R], vi[2][R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
                 const bool in = i < n;
-                vr[0][j] = in ? Vpr[i] : 0.0;
-                vr[1][j] = in ? Vqr[i] : 0.0;
+                vr[0][j] = in ? Vpr[i] : T(0);
+                vr[1][j] = in ? Vqr[i] : T(0);
                 if (CPLX) {
-                    vi[0][j] = in ? Vpi[i] : 0.0;
-                    vi[1][j] = in ? Vqi[i] : 0.0;
+                    vi[0][j] = in ? Vpi[i] : T(0);
+                    vi[1][j] = in ? Vqi[i] : T(0);
                 }
             }
             (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                     }
                 }
             }
-            double mm[1] = {Mx};
+            T mm[1] = {Mx};
             group_max<W, 1>(mm, sm.mx2);
             Mblk = mm[0];
         } else if (pbit || rescale) {
@@ -163,16 +163,16 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
                 }
             }
             if (pbit) {
-                double *const Vpr = d.Vr + (size_t)p * d.ldv;
-                double *const Vqr = d.Vr + (size_t)q * d.ldv;
+                T *const Vpr = d.Vr + (size_t)p * d.ldv;
+                T *const Vqr = d.Vr + (size_t)q * d.ldv;
                 for (int i = t; i < n; i += W) {
-                    const double a = Vpr[i], b = Vqr[i];
+                    const T a = Vpr[i], b = Vqr[i];
                     Vpr[i] = b;
                     Vqr[i] = a;
                     if (CPLX) {
-                        double *const Vpi = d.Vi + (size_t)p * d.ldv;
-                        double *const Vqi = d.Vi + (size_t)q * d.ldv;
-                        const double ai = Vpi[i], bi = Vqi[i];
+                        T *const Vpi = d.Vi + (size_t)p * d.ldv;
+                        T *const Vqi = d.Vi + (size_t)q * d.ldv;
+                        const T ai = Vpi[i], bi = Vqi[i];
                         Vpi[i] = bi;
                         Vqi[i] = ai;
                     }
@@ -180,13 +180,13 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
             }
         }
         if (t == 0) {
-            const double ep = np_.zero ? -INFINITY : (double)np_.e;
-            const double eq = nq_.zero ? -INFINITY : (double)nq_.e;
+            const T ep = np_.zero ? T(-INFINITY) : (T)np_.e;
+            const T eq = nq_.zero ? T(-INFINITY) : (T)nq_.e;
             const int dp = pbit ? q : p, dq = pbit ? p : q;
             d.e[dp] = ep;
-            d.f[dp] = np_.zero ? 1.0 : np_.f;
+            d.f[dp] = np_.zero ? T(1) : np_.f;
             d.e[dq] = eq;
-            d.f[dq] = nq_.zero ? 1.0 : nq_.f;
+            d.f[dq] = nq_.zero ? T(1) : nq_.f;
         }
     }
 
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
     if constexpr (W > 64) __syncthreads();
     if (t == 0) {
         if (transform) {
-            atomicMax(&sc->M_step, d2bits(Mblk));
+            atomicMax(&sc->M_step, d2bits((double)Mblk));
             atomicAdd(&sc->t_step, 1ull);
         } else if (pbit) {
             atomicAdd(&sc->sw_step, 1ull);
@@ -203,9 +203,9 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
         const unsigned long long prev = atomicAdd(&sc->done, 1ull);
         if (prev == (unsigned long long)gridDim.x - 1) {
             __threadfence();
-            const double Mt2 = rescale ? scal2(Mt, sp) : Mt;
-            const double Ms = bits2d(atomicExch(&sc->M_step, 0ull));
-            sc->Mt_bits = d2bits(fmax(Mt2, Ms));
+            const T Mt2 = rescale ? scal2(Mt, sp) : Mt;
+            const T Ms = (T)bits2d(atomicExch(&sc->M_step, 0ull));
+            sc->Mt_bits = d2bits((double)fmax(Mt2, Ms));
             const long long tt = (long long)atomicExch(&sc->t_step, 0ull);
             const long long sw = (long long)atomicExch(&sc->sw_step, 0ull);
             sc->T += tt;
@@ -223,21 +223,26 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDesc d)
 }
 
 // ---------------------------------------------------------------------------
-// dispatch over (complex, W, R, compensated dot-products)
-template <bool CPLX, int W, int R>
-static hipError_t launch_step_t(const SvdDesc &d, hipStream_t s)
+// dispatch over (complex, W, R, compensated dot-products; these exist in
+// double precision only)
+template <bool CPLX, int W, int R, typename T>
+static hipError_t launch_step_t(const SvdDescT<T> &d, hipStream_t s)
 {
     const int N = d.n + (d.n & 1);
     const unsigned blocks = (unsigned)(N / 2);
-    if (d.comp)
-        hipLaunchKernelGGL((step_kernel<CPLX, W, R, true>), dim3(blocks), dim3(W), 0, s, d);
-    else
-        hipLaunchKernelGGL((step_kernel<CPLX, W, R, false>), dim3(blocks), dim3(W), 0, s, d);
+    if (d.comp) {
+        if constexpr (sizeof(T) == sizeof(double))
+            hipLaunchKernelGGL((step_kernel<CPLX, W, R, true, T>), dim3(blocks), dim3(W), 0, s, d);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((step_kernel<CPLX, W, R, false, T>), dim3(blocks), dim3(W), 0, s, d);
+    }
     return hipGetLastError();
 }
 
-template <bool CPLX, int W>
-static hipError_t launch_step_w(const SvdDesc &d, hipStream_t s)
+template <bool CPLX, int W, typename T>
+static hipError_t launch_step_w(const SvdDescT<T> &d, hipStream_t s)
 {
     const int R = (d.m + W - 1) / W;
     if (R <= 1) return launch_step_t<CPLX, W, 1>(d, s);
@@ -261,7 +266,8 @@ int step_auto_threads(int m, int n)
     return 1024;
 }
 
-hipError_t launch_step(const SvdDesc &d, int threads, hipStream_t s)
+template <typename T>
+hipError_t launch_step(const SvdDescT<T> &d, int threads, hipStream_t s)
 {
     if (threads <= 0) threads = step_auto_threads(d.m, d.n);
     if (d.m > step_max_rows(d.cplx, threads)) return hipErrorInvalidValue;
@@ -305,35 +311,36 @@ __global__ void sweep_end_kernel(DevScalars *sc)
     sc->SW = 0;
 }
 
-hipError_t launch_sweep_end(const SvdDesc &d, hipStream_t s)
+hipError_t launch_sweep_end(DevScalars *sc, hipStream_t s)
 {
-    hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(64), 0, s, d.sc);
+    hipLaunchKernelGGL(sweep_end_kernel, dim3(1), dim3(64), 0, s, sc);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // initialisation
-template <bool CPLX>
-__global__ __launch_bounds__(256) void maxabs_kernel(int m, int n, const double *Ar, const double *Ai,
-                                                     long long lda, unsigned long long *out)
+template <bool CPLX, typename T>
+__global__ __launch_bounds__(256) void maxabs_kernel(int m, int n, const T *Ar, const T *Ai, long long lda,
+                                                     unsigned long long *out)
 {
     // M~_0 = max |component|, NaN turned into Inf (Sect. 3.2)
-    double mx = 0.0;
+    T mx = T(0);
     const int j = blockIdx.y;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
-        mx = fmax(mx, fmin(fabs(Ar[(size_t)j * lda + i]), INFINITY));
-        if (CPLX) mx = fmax(mx, fmin(fabs(Ai[(size_t)j * lda + i]), INFINITY));
+        mx = fmax(mx, fmin(fabs(Ar[(size_t)j * lda + i]), T(INFINITY)));
+        if (CPLX) mx = fmax(mx, fmin(fabs(Ai[(size_t)j * lda + i]), T(INFINITY)));
     }
     mx = wave_max(mx);
-    if ((threadIdx.x & 63) == 0) atomicMax(out, d2bits(mx));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, d2bits((double)mx));
 }
 
 // s_0 = s_[0] of eq. (skn) from M~_0 (device side, so the load needs no host round trip);
 // a non-finite or zero M~_0 stops the state with its status
-__global__ void init_scalars_kernel(SvdDesc d, const unsigned long long *maxbits, int max_sweeps)
+template <typename T>
+__global__ void init_scalars_kernel(SvdDescT<T> d, const unsigned long long *maxbits, int max_sweeps)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const double M0 = bits2d(*maxbits);
+    const T M0 = (T)bits2d(*maxbits);
     DevScalars *sc = d.sc;
     sc->Mt_bits = 0;
     sc->M_step = 0;
@@ -351,8 +358,8 @@ __global__ void init_scalars_kernel(SvdDesc d, const unsigned long long *maxbits
     sc->rescaled = 0;
     sc->converged = 0;
     sc->max_sweeps = max_sweeps;
-    if (!(M0 <= 1.79769313486231570815e308) || M0 == 0.0) {
-        sc->status = (M0 == 0.0) ? -3 : -2;
+    if (!(M0 < T(INFINITY)) || M0 == T(0)) {
+        sc->status = (M0 == T(0)) ? -3 : -2;
         sc->stop = 1;
         sc->s = 0;
         return;
@@ -361,12 +368,11 @@ __global__ void init_scalars_kernel(SvdDesc d, const unsigned long long *maxbits
     sc->status = 0;
     sc->stop = 0;
     sc->s = s0;
-    sc->Mt_bits = d2bits(scal2(M0, s0));
+    sc->Mt_bits = d2bits((double)scal2(M0, s0));
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void init_scale_kernel(SvdDesc d, const double *Ar, const double *Ai,
-                                                         long long lda)
+template <bool CPLX, typename T>
+__global__ __launch_bounds__(256) void init_scale_kernel(SvdDescT<T> d, const T *Ar, const T *Ai, long long lda)
 {
     if (d.sc->status != 0) return;
     const int s0 = d.sc->s;
@@ -376,38 +382,40 @@ __global__ __launch_bounds__(256) void init_scale_kernel(SvdDesc d, const double
         if (CPLX) d.Gi[(size_t)j * d.ldg + i] = scal2(Ai[(size_t)j * lda + i], s0);
     }
     for (int i = blockIdx.x * 256 + threadIdx.x; i < d.n; i += gridDim.x * 256) {
-        d.Vr[(size_t)j * d.ldv + i] = (i == j) ? 1.0 : 0.0;
-        if (CPLX) d.Vi[(size_t)j * d.ldv + i] = 0.0;
+        d.Vr[(size_t)j * d.ldv + i] = (i == j) ? T(1) : T(0);
+        if (CPLX) d.Vi[(size_t)j * d.ldv + i] = T(0);
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        d.e[j] = -INFINITY;
-        d.f[j] = 1.0;
+        d.e[j] = T(-INFINITY);
+        d.f[j] = T(1);
     }
 }
 
 static unsigned row_blocks(int m) { return (unsigned)min(64, (m + 255) / 256); }
 
-hipError_t launch_maxabs(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
-                         unsigned long long *maxbits, hipStream_t s)
+template <typename T>
+hipError_t launch_maxabs(const SvdDescT<T> &d, const T *Ar, const T *Ai, long long lda, unsigned long long *maxbits,
+                         hipStream_t s)
 {
     // reduces M~_0 into *maxbits, which the caller has zeroed
     dim3 grid(row_blocks(d.m), d.n);
     if (d.cplx)
-        hipLaunchKernelGGL(maxabs_kernel<true>, grid, dim3(256), 0, s, d.m, d.n, Ar, Ai, lda, maxbits);
+        hipLaunchKernelGGL((maxabs_kernel<true, T>), grid, dim3(256), 0, s, d.m, d.n, Ar, Ai, lda, maxbits);
     else
-        hipLaunchKernelGGL(maxabs_kernel<false>, grid, dim3(256), 0, s, d.m, d.n, Ar, Ai, lda, maxbits);
+        hipLaunchKernelGGL((maxabs_kernel<false, T>), grid, dim3(256), 0, s, d.m, d.n, Ar, Ai, lda, maxbits);
     return hipGetLastError();
 }
 
-hipError_t launch_init_scale(const SvdDesc &d, const double *Ar, const double *Ai, long long lda,
+template <typename T>
+hipError_t launch_init_scale(const SvdDescT<T> &d, const T *Ar, const T *Ai, long long lda,
                              const unsigned long long *maxbits, int max_sweeps, hipStream_t s)
 {
-    hipLaunchKernelGGL(init_scalars_kernel, dim3(1), dim3(64), 0, s, d, maxbits, max_sweeps);
+    hipLaunchKernelGGL((init_scalars_kernel<T>), dim3(1), dim3(64), 0, s, d, maxbits, max_sweeps);
     dim3 grid(row_blocks(d.m), d.n);
     if (d.cplx)
-        hipLaunchKernelGGL(init_scale_kernel<true>, grid, dim3(256), 0, s, d, Ar, Ai, lda);
+        hipLaunchKernelGGL((init_scale_kernel<true, T>), grid, dim3(256), 0, s, d, Ar, Ai, lda);
     else
-        hipLaunchKernelGGL(init_scale_kernel<false>, grid, dim3(256), 0, s, d, Ar, Ai, lda);
+        hipLaunchKernelGGL((init_scale_kernel<false, T>), grid, dim3(256), 0, s, d, Ar, Ai, lda);
     return hipGetLastError();
 }
 
@@ -425,54 +433,55 @@ hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s)
 // finalisation
 // Column norms of all columns (1024 threads per column, the canonical order:
 // thread t = lane t, rows t, t+1024, ... in order).
-template <bool CPLX>
-__global__ __launch_bounds__(1024) void colnorm_kernel(SvdDesc d, double *e_out, double *f_out)
+template <bool CPLX, typename T>
+__global__ __launch_bounds__(1024) void colnorm_kernel(SvdDescT<T> d, T *e_out, T *f_out)
 {
-    __shared__ double red[2 * 1024];
-    __shared__ double mx1[16];
+    __shared__ T red[2 * 1024];
+    __shared__ T mx1[16];
     const int j = blockIdx.x, t = threadIdx.x;
-    const double *xr = d.Gr + (size_t)j * d.ldg;
-    const double *xi = CPLX ? d.Gi + (size_t)j * d.ldg : nullptr;
-    double mx[1] = {0.0};
+    const T *xr = d.Gr + (size_t)j * d.ldg;
+    const T *xi = CPLX ? d.Gi + (size_t)j * d.ldg : nullptr;
+    T mx[1] = {T(0)};
     for (int i = t; i < d.m; i += 1024) {
         mx[0] = fmax(mx[0], fabs(xr[i]));
         if (CPLX) mx[0] = fmax(mx[0], fabs(xi[i]));
     }
     group_max<1024, 1>(mx, mx1);
-    if (mx[0] == 0.0) {
+    if (mx[0] == T(0)) {
         if (t == 0) {
-            e_out[j] = -INFINITY;
-            f_out[j] = 1.0;
+            e_out[j] = T(-INFINITY);
+            f_out[j] = T(1);
         }
         return;
     }
     const int E = getexp(mx[0]);
-    double s[2] = {0.0, 0.0};
+    T s[2] = {T(0), T(0)};
     for (int i = t; i < d.m; i += 1024) {
-        const double yr = scal2(xr[i], -E);
+        const T yr = scal2(xr[i], -E);
         s[0] = fma(yr, yr, s[0]);
         if (CPLX) {
-            const double yi = scal2(xi[i], -E);
+            const T yi = scal2(xi[i], -E);
             s[1] = fma(yi, yi, s[1]);
         }
     }
     group_tree_sum<1024, 2>(s, red);
-    const Norm nn = norm_from_sums(E, s[0], s[1], CPLX);
+    const NormT<T> nn = norm_from_sums(E, s[0], s[1], CPLX);
     if (t == 0) {
-        e_out[j] = (double)nn.e;
+        e_out[j] = (T)nn.e;
         f_out[j] = nn.f;
     }
 }
 
 // stable descending rank of sigma_j = (e_j, f_j)
-__global__ __launch_bounds__(256) void rank_kernel(int n, const double *e, const double *f, int *rank)
+template <typename T>
+__global__ __launch_bounds__(256) void rank_kernel(int n, const T *e, const T *f, int *rank)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
-    const double ej = e[j], fj = f[j];
+    const T ej = e[j], fj = f[j];
     int r = 0;
     for (int i = 0; i < n; ++i) {
-        const double ei = e[i], fi = f[i];
+        const T ei = e[i], fi = f[i];
         const bool gt = ei > ej || (ei == ej && fi > fj);
         const bool eqb = (ei == ej && fi == fj) && i < j;
         r += (gt || eqb) ? 1 : 0;
@@ -480,25 +489,23 @@ __global__ __launch_bounds__(256) void rank_kernel(int n, const double *e, const
     rank[j] = r;
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(256) void final_write_kernel(SvdDesc d, const double *e, const double *f,
-                                                          const int *rank, double *Ur, double *Ui,
-                                                          long long ldu, double *Vr, double *Vi,
-                                                          long long ldv, double *sv_e, double *sv_f,
-                                                          double *sv)
+template <bool CPLX, typename T>
+__global__ __launch_bounds__(256) void final_write_kernel(SvdDescT<T> d, const T *e, const T *f, const int *rank,
+                                                          T *Ur, T *Ui, long long ldu, T *Vr, T *Vi, long long ldv,
+                                                          T *sv_e, T *sv_f, T *sv)
 {
     const int s = d.sc->s;
     const int j = blockIdx.x;
     const int dst = rank[j];
-    const double ej = e[j], fj = f[j];
+    const T ej = e[j], fj = f[j];
     const bool zero = isinf(ej);
     const int E = zero ? 0 : (int)ej;
     for (int i = threadIdx.x; i < d.m; i += 256) {
-        const double xr = d.Gr[(size_t)j * d.ldg + i];
-        Ur[(size_t)dst * ldu + i] = zero ? 0.0 : scal2(xr, -E) / fj;
+        const T xr = d.Gr[(size_t)j * d.ldg + i];
+        Ur[(size_t)dst * ldu + i] = zero ? T(0) : scal2(xr, -E) / fj;
         if (CPLX) {
-            const double xi = d.Gi[(size_t)j * d.ldg + i];
-            Ui[(size_t)dst * ldu + i] = zero ? 0.0 : scal2(xi, -E) / fj;
+            const T xi = d.Gi[(size_t)j * d.ldg + i];
+            Ui[(size_t)dst * ldu + i] = zero ? T(0) : scal2(xi, -E) / fj;
         }
     }
     for (int i = threadIdx.x; i < d.n; i += 256) {
@@ -506,76 +513,79 @@ __global__ __launch_bounds__(256) void final_write_kernel(SvdDesc d, const doubl
         if (CPLX) Vi[(size_t)dst * ldv + i] = d.Vi[(size_t)j * d.ldv + i];
     }
     if (threadIdx.x == 0) {
-        sv_e[dst] = zero ? -INFINITY : ej - (double)s;
+        sv_e[dst] = zero ? T(-INFINITY) : ej - (T)s;
         sv_f[dst] = fj;
-        if (sv) sv[dst] = zero ? 0.0 : scal2(fj, E - s);
+        if (sv) sv[dst] = zero ? T(0) : scal2(fj, E - s);
     }
 }
 
-hipError_t launch_final_write(const SvdDesc &d, const int *rank, double *Ur, double *Ui, long long ldu,
-                              double *Vr, double *Vi, long long ldv, double *sv_e, double *sv_f,
-                              double *sv, hipStream_t st)
+template <typename T>
+hipError_t launch_final_write(const SvdDescT<T> &d, const int *rank, T *Ur, T *Ui, long long ldu, T *Vr, T *Vi,
+                              long long ldv, T *sv_e, T *sv_f, T *sv, hipStream_t st)
 {
     if (d.cplx)
-        hipLaunchKernelGGL(final_write_kernel<true>, dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur, Ui,
+        hipLaunchKernelGGL((final_write_kernel<true, T>), dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur, Ui,
                            ldu, Vr, Vi, ldv, sv_e, sv_f, sv);
     else
-        hipLaunchKernelGGL(final_write_kernel<false>, dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur,
-                           Ui, ldu, Vr, Vi, ldv, sv_e, sv_f, sv);
+        hipLaunchKernelGGL((final_write_kernel<false, T>), dim3(d.n), dim3(256), 0, st, d, d.e, d.f, rank, Ur, Ui,
+                           ldu, Vr, Vi, ldv, sv_e, sv_f, sv);
     return hipGetLastError();
 }
 
 // non-converged exit: current column norms, backscaled, in column order
-__global__ __launch_bounds__(256) void colnorm_out_kernel(int n, const double *e, const double *f,
-                                                          const DevScalars *sc, double *sv_e, double *sv_f,
-                                                          double *sv)
+template <typename T>
+__global__ __launch_bounds__(256) void colnorm_out_kernel(int n, const T *e, const T *f, const DevScalars *sc,
+                                                          T *sv_e, T *sv_f, T *sv)
 {
     const int s = sc->s;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const bool zero = isinf(e[j]);
-    sv_e[j] = zero ? -INFINITY : e[j] - (double)s;
+    sv_e[j] = zero ? T(-INFINITY) : e[j] - (T)s;
     sv_f[j] = f[j];
-    if (sv) sv[j] = zero ? 0.0 : scal2(f[j], (int)e[j] - s);
+    if (sv) sv[j] = zero ? T(0) : scal2(f[j], (int)e[j] - s);
 }
 
-hipError_t launch_colnorms_raw(const SvdDesc &d, hipStream_t st)
+template <typename T>
+hipError_t launch_colnorms_raw(const SvdDescT<T> &d, hipStream_t st)
 {
     if (d.cplx)
-        hipLaunchKernelGGL(colnorm_kernel<true>, dim3(d.n), dim3(1024), 0, st, d, d.e, d.f);
+        hipLaunchKernelGGL((colnorm_kernel<true, T>), dim3(d.n), dim3(1024), 0, st, d, d.e, d.f);
     else
-        hipLaunchKernelGGL(colnorm_kernel<false>, dim3(d.n), dim3(1024), 0, st, d, d.e, d.f);
+        hipLaunchKernelGGL((colnorm_kernel<false, T>), dim3(d.n), dim3(1024), 0, st, d, d.e, d.f);
     return hipGetLastError();
 }
 
-hipError_t launch_colnorm_out(const SvdDesc &d, double *sv_e, double *sv_f, double *sv, hipStream_t st)
+template <typename T>
+hipError_t launch_colnorm_out(const SvdDescT<T> &d, T *sv_e, T *sv_f, T *sv, hipStream_t st)
 {
-    hipLaunchKernelGGL(colnorm_out_kernel, dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, d.sc, sv_e,
-                       sv_f, sv);
+    hipLaunchKernelGGL((colnorm_out_kernel<T>), dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, d.sc,
+                       sv_e, sv_f, sv);
     return hipGetLastError();
 }
 
-hipError_t launch_rank(const SvdDesc &d, int *rank, hipStream_t st)
+template <typename T>
+hipError_t launch_rank(const SvdDescT<T> &d, int *rank, hipStream_t st)
 {
-    hipLaunchKernelGGL(rank_kernel, dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, rank);
+    hipLaunchKernelGGL((rank_kernel<T>), dim3((d.n + 255) / 256), dim3(256), 0, st, d.n, d.e, d.f, rank);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // layout helpers (Sect. SM5)
-__global__ __launch_bounds__(256) void copy2d_kernel(int m, const double *src, long long lds, double *dst,
-                                                     long long ldd)
+template <typename T>
+__global__ __launch_bounds__(256) void copy2d_kernel(int m, const T *src, long long lds, T *dst, long long ldd)
 {
     const int j = blockIdx.y;
     for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256)
         dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
 }
 
-hipError_t launch_copy2d(int m, int n, const double *src, long long lds, double *dst, long long ldd,
-                         hipStream_t s)
+template <typename T>
+hipError_t launch_copy2d(int m, int n, const T *src, long long lds, T *dst, long long ldd, hipStream_t s)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(copy2d_kernel, dim3(row_blocks(m), n), dim3(256), 0, s, m, src, lds, dst, ldd);
+    hipLaunchKernelGGL((copy2d_kernel<T>), dim3(row_blocks(m), n), dim3(256), 0, s, m, src, lds, dst, ldd);
     return hipGetLastError();
 }
 
@@ -614,5 +624,22 @@ hipError_t launch_merge(int m, int n, const double *Xr, const double *Xi, long l
     hipLaunchKernelGGL(merge_kernel, dim3(row_blocks(m), n), dim3(256), 0, s, m, Xr, Xi, ldx, Z, ldz);
     return hipGetLastError();
 }
+
+// the two working precisions
+#define JSVD_STEP_INST(T)                                                                                         \
+    template hipError_t launch_maxabs<T>(const SvdDescT<T> &, const T *, const T *, long long, unsigned long long *, \
+                                         hipStream_t);                                                            \
+    template hipError_t launch_init_scale<T>(const SvdDescT<T> &, const T *, const T *, long long,                  \
+                                             const unsigned long long *, int, hipStream_t);                       \
+    template hipError_t launch_step<T>(const SvdDescT<T> &, int, hipStream_t);                                     \
+    template hipError_t launch_colnorms_raw<T>(const SvdDescT<T> &, hipStream_t);                                  \
+    template hipError_t launch_rank<T>(const SvdDescT<T> &, int *, hipStream_t);                                   \
+    template hipError_t launch_final_write<T>(const SvdDescT<T> &, const int *, T *, T *, long long, T *, T *,      \
+                                              long long, T *, T *, T *, hipStream_t);                             \
+    template hipError_t launch_colnorm_out<T>(const SvdDescT<T> &, T *, T *, T *, hipStream_t);                    \
+    template hipError_t launch_copy2d<T>(int, int, const T *, long long, T *, long long, hipStream_t);
+JSVD_STEP_INST(double)
+JSVD_STEP_INST(float)
+#undef JSVD_STEP_INST
 
 } // namespace jsvd
