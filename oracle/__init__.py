@@ -21,6 +21,7 @@ OK, NOT_CONVERGED, EINVAL, ENONFINITE, EZERO = 0, 1, -1, -2, -3
 EVD_SCALED, EVD_SINFORM = 1, 2
 NO_PERMUTE = 1
 COMPENSATED = 2
+NO_GS = 4
 LANES = 1024
 
 _dp = _ct.POINTER(_ct.c_double)
@@ -84,7 +85,11 @@ def lib():
         L.ora_step_ext.restype = None
         L.ora_step_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, _ct.POINTER(i), _dp,
                                    _ct.c_long, _ct.POINTER(_ct.c_long), _ct.POINTER(_ct.c_long),
-                                   _ct.POINTER(i), _ct.c_uint]
+                                   _ct.POINTER(_ct.c_long), _ct.POINTER(i), _ct.c_uint]
+        L.ora_gs_case.restype = i
+        L.ora_gs_case.argtypes = [d, d, d, d, d]
+        L.ora_gs.restype = d
+        L.ora_gs.argtypes = [i, _dp, _dp, _dp, _dp, d, d, d, d, d, d]
         L.ora_finalize_ext.restype = None
         L.ora_finalize_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, i, _dp, _dp]
         L.ora_gesvj.restype = i
@@ -113,7 +118,11 @@ def lib():
         L.ora_s_step_ext.restype = None
         L.ora_s_step_ext.argtypes = [i, i, _fp, _fp, sz, _fp, _fp, sz, _fp, _fp, _ct.POINTER(i), _fp,
                                      _ct.c_long, _ct.POINTER(_ct.c_long), _ct.POINTER(_ct.c_long),
-                                     _ct.POINTER(i), _ct.c_uint]
+                                     _ct.POINTER(_ct.c_long), _ct.POINTER(i), _ct.c_uint]
+        L.ora_s_gs_case.restype = i
+        L.ora_s_gs_case.argtypes = [f, f, f, f, f]
+        L.ora_s_gs.restype = f
+        L.ora_s_gs.argtypes = [i, _fp, _fp, _fp, _fp, f, f, f, f, f, f]
         _lib = L
     return _lib
 
@@ -273,13 +282,32 @@ def rot(xpr, xpi, xqr, xqi, c, C, S, swap):
     return lib().ora_rot(xpr.shape[0], _p(xpr), _p(xpi), _p(xqr), _p(xqi), c, C, S, int(swap))
 
 
+def gs_case(e1, f1, e2, f2, ups):
+    """eq. (GScond): 1 if ||g_p|| > 2^eta_hat ups ||g_q||, 2 if the reverse, else 0."""
+    return lib().ora_gs_case(e1, f1, e2, f2, ups)
+
+
+def gs(xr, xi, yr, yi, ex, fx, ey, fy, wr, wi):
+    """eq. (GS) in place on y (x unchanged); returns the max-norm of the new y."""
+    return lib().ora_gs(yr.shape[0], _p(xr), _p(xi), _p(yr), _p(yi), ex, fx, ey, fy, wr, wi)
+
+
+def s_gs_case(e1, f1, e2, f2, ups):
+    return lib().ora_s_gs_case(e1, f1, e2, f2, ups)
+
+
+def s_gs(xr, xi, yr, yi, ex, fx, ey, fy, wr, wi):
+    return lib().ora_s_gs(yr.shape[0], _pf(xr), _pf(xi), _pf(yr), _pf(yi), ex, fx, ey, fy, wr, wi)
+
+
 # ---------------------------------------------------------------- SVD
 class State:
     """Oracle SVD state on host numpy arrays (column-major)."""
 
-    def __init__(self, G_re, G_im=None, nosort=False, compensated=False):
+    def __init__(self, G_re, G_im=None, nosort=False, compensated=False, nogs=False):
         self.nosort = bool(nosort)
         self.compensated = bool(compensated)
+        self.nogs = bool(nogs)
         self.m, self.n = G_re.shape
         self.cplx = G_im is not None
         self.Gr = _np.array(G_re, dtype=_np.float64, order="F", copy=True)
@@ -293,6 +321,7 @@ class State:
         self.k = 0
         self.last_t = 0
         self.last_sw = 0
+        self.last_gs = 0
         self.rescaled = 0
 
     def _args(self):
@@ -307,10 +336,12 @@ class State:
 
     def step(self):
         s, Mt = _ct.c_int(self.s), _ct.c_double(self.Mt)
-        t, sw, r = _ct.c_long(), _ct.c_long(), _ct.c_int()
-        flags = (NO_PERMUTE if self.nosort else 0) | (COMPENSATED if self.compensated else 0)
-        lib().ora_step_ext(*self._args(), s, Mt, self.k, t, sw, r, flags)
+        t, sw, gs_, r = _ct.c_long(), _ct.c_long(), _ct.c_long(), _ct.c_int()
+        flags = ((NO_PERMUTE if self.nosort else 0) | (COMPENSATED if self.compensated else 0) |
+                 (NO_GS if self.nogs else 0))
+        lib().ora_step_ext(*self._args(), s, Mt, self.k, t, sw, gs_, r, flags)
         self.s, self.Mt, self.last_t, self.last_sw = s.value, Mt.value, t.value, sw.value
+        self.last_gs = gs_.value
         self.rescaled += r.value
         self.k += 1
         return t.value
@@ -369,8 +400,9 @@ def s_s_square(Mt, m, cplx):
 class SState:
     """Single precision oracle SVD state on host float32 arrays (column-major)."""
 
-    def __init__(self, G_re, G_im=None, nosort=False):
+    def __init__(self, G_re, G_im=None, nosort=False, nogs=False):
         self.nosort = bool(nosort)
+        self.nogs = bool(nogs)
         self.m, self.n = G_re.shape
         self.cplx = G_im is not None
         self.Gr = _np.array(G_re, dtype=_np.float32, order="F", copy=True)
@@ -384,6 +416,7 @@ class SState:
         self.k = 0
         self.last_t = 0
         self.last_sw = 0
+        self.last_gs = 0
         self.rescaled = 0
 
     def _args(self):
@@ -398,9 +431,11 @@ class SState:
 
     def step(self):
         s, Mt = _ct.c_int(self.s), _ct.c_float(self.Mt)
-        t, sw, r = _ct.c_long(), _ct.c_long(), _ct.c_int()
-        lib().ora_s_step_ext(*self._args(), s, Mt, self.k, t, sw, r, NO_PERMUTE if self.nosort else 0)
+        t, sw, gs_, r = _ct.c_long(), _ct.c_long(), _ct.c_long(), _ct.c_int()
+        flags = (NO_PERMUTE if self.nosort else 0) | (NO_GS if self.nogs else 0)
+        lib().ora_s_step_ext(*self._args(), s, Mt, self.k, t, sw, gs_, r, flags)
         self.s, self.Mt, self.last_t, self.last_sw = s.value, _np.float32(Mt.value), t.value, sw.value
+        self.last_gs = gs_.value
         self.rescaled += r.value
         self.k += 1
         return t.value

@@ -216,6 +216,53 @@ float ora_s_rot(int l, float *xpr, float *xpi, float *xqr, float *xqi, float c, 
     return M;
 }
 
+/* eq. (GScond) on the normalised quotient of the norms (eq. efpq), as
+ * ora_gs_case, with eta_hat = FLT_MAX_EXP - 1 */
+static int s_gs_exceeds(float ea, float fa, float eb, float fb, float ups)
+{
+    float fab = fa / fb;
+    const int g = ilogbf(fab);
+    const long eab = (long)ea - (long)eb + g;
+    fab = scalbnf(fab, -g);
+    const int eu = ilogbf(ups);
+    const float fu = scalbnf(ups, -eu);
+    const long et = (long)(FLT_MAX_EXP - 1) + eu;
+    return eab > et || (eab == et && fab > fu);
+}
+
+int ora_s_gs_case(float e1, float f1, float e2, float f2, float ups)
+{
+    if (s_gs_exceeds(e1, f1, e2, f2, ups)) return 1;
+    if (s_gs_exceeds(e2, f2, e1, f1, ups)) return 2;
+    return 0;
+}
+
+/* eq. (GS) in float, in the order of ora_gs */
+float ora_s_gs(int l, const float *xr, const float *xi, float *yr, float *yi,
+               float ex, float fx, float ey, float fy, float wr, float wi)
+{
+    const float fyx = fy / fx;
+    const float psr = wr * fyx, psi = wi * fyx;
+    const int Ex = (int)ex, Ey = (int)ey;
+    float M = 0.0f;
+    for (int i = 0; i < l; ++i) {
+        const float xpr = scalbnf(xr[i], -Ex), ypr = scalbnf(yr[i], -Ey);
+        if (yi) {
+            const float xpi = scalbnf(xi[i], -Ex), ypi = scalbnf(yi[i], -Ey);
+            const float nr = scalbnf(fmaf(-psr, xpr, fmaf(psi, xpi, ypr)), Ey);
+            const float ni = scalbnf(fmaf(-psr, xpi, fmaf(-psi, xpr, ypi)), Ey);
+            yr[i] = nr;
+            yi[i] = ni;
+            M = fmaxf(M, fmaxf(fabsf(nr), fabsf(ni)));
+        } else {
+            const float nr = scalbnf(fmaf(-psr, xpr, ypr), Ey);
+            yr[i] = nr;
+            M = fmaxf(M, fabsf(nr));
+        }
+    }
+    return M;
+}
+
 static void swap_f(int l, float *xpr, float *xpi, float *xqr, float *xqi)
 {
     for (int i = 0; i < l; ++i) {
@@ -235,8 +282,8 @@ typedef struct {
     float *e, *f;
     int s;
     float Mt;
-    long k, T, last_t, SW, last_sw;
-    int rescaled, nosort;
+    long k, T, last_t, SW, last_sw, GS, last_gs;
+    int rescaled, nosort, nogs;
 } ora_ssvd;
 
 #define SCOLR(st, j) ((st)->Gr + (size_t)(j) * (st)->ldg)
@@ -306,18 +353,17 @@ static void s_step(ora_ssvd *st)
     }
     /* upsilon = fl(eps sqrt m), eps = 2^-24 */
     const float ups = scalbnf(sqrtf((float)m), -24);
-    long t = 0, sw = 0;
+    long t = 0, sw = 0, gs = 0;
     float M = 0.0f;
     for (int l = 0; l < npairs; ++l) {
         int p, q;
         if (!ora_rr_pair(n, kk, l, &p, &q)) continue;
         const float ep = st->e[p], fp = st->f[p], eq = st->e[q], fq = st->f[q];
-        int transform = 0, pbit;
-        float c = 1.0f, C = 0.0f, S = 0.0f;
+        int transform = 0, pbit, gsc = 0;
+        float c = 1.0f, C = 0.0f, S = 0.0f, zr = 0.0f, zi = 0.0f;
         if (isinf(ep) || isinf(eq)) {
             pbit = isinf(ep) && !isinf(eq);
         } else {
-            float zr, zi;
             ora_s_dpscl(m, SCOLR(st, q), SCOLI(st, q), SCOLR(st, p), SCOLI(st, p), eq, fq, ep, fp, &zr, &zi);
             const float az = cplx ? ora_s_hypot(zr, zi) : fabsf(zr);
             transform = (ups <= az);
@@ -329,9 +375,24 @@ static void s_step(ora_ssvd *st)
             else
                 zp = ora_sevd2_real(a11, a22, a21r, &c, &C, &l1, &l2, ORA_EVD_SCALED);
             pbit = zp & 1;
+            if (transform && !st->nogs) {
+                gsc = ora_s_gs_case(ep, fp, eq, fq, ups);
+                if (gsc) pbit = (gsc == 2);
+            }
         }
         if (st->nosort) pbit = 0;
-        if (transform) {
+        if (transform && gsc) {
+            ++t;
+            ++gs;
+            float Mg;
+            if (gsc == 1)
+                Mg = ora_s_gs(m, SCOLR(st, p), SCOLI(st, p), SCOLR(st, q), SCOLI(st, q), ep, fp, eq, fq, zr, -zi);
+            else
+                Mg = ora_s_gs(m, SCOLR(st, q), SCOLI(st, q), SCOLR(st, p), SCOLI(st, p), eq, fq, ep, fp, zr, zi);
+            if (pbit) swap_f(m, SCOLR(st, p), SCOLI(st, p), SCOLR(st, q), SCOLI(st, q));
+            (void)ora_s_rot(n, SVCOLR(st, p), SVCOLI(st, p), SVCOLR(st, q), SVCOLI(st, q), c, C, S, pbit);
+            M = fmaxf(M, Mg);
+        } else if (transform) {
             ++t;
             const float Mg = ora_s_rot(m, SCOLR(st, p), SCOLI(st, p), SCOLR(st, q), SCOLI(st, q), c, C, S, pbit);
             (void)ora_s_rot(n, SVCOLR(st, p), SVCOLI(st, p), SVCOLR(st, q), SVCOLI(st, q), c, C, S, pbit);
@@ -350,6 +411,8 @@ static void s_step(ora_ssvd *st)
     st->last_t = t;
     st->SW += sw;
     st->last_sw = sw;
+    st->GS += gs;
+    st->last_gs = gs;
     st->Mt = fmaxf(st->Mt, M);
     st->k++;
 }
@@ -413,7 +476,9 @@ int ora_sgesvj(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float 
     st.Gr = Gr; st.Gi = Gi; st.ldg = ldg;
     st.Vr = Vr; st.Vi = Vi; st.ldv = ldv;
     st.nosort = (flags & ORA_NO_PERMUTE) != 0;
-    if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1 || (flags & ~ORA_NO_PERMUTE)) return ORA_EINVAL;
+    st.nogs = (flags & ORA_NO_GS) != 0;
+    if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1 || (flags & ~(ORA_NO_PERMUTE | ORA_NO_GS)))
+        return ORA_EINVAL;
     st.e = (float *)malloc(sizeof(float) * (size_t)n);
     st.f = (float *)malloc(sizeof(float) * (size_t)n);
     int status = s_init(&st);
@@ -473,7 +538,8 @@ int ora_s_init_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, fl
 }
 
 void ora_s_step_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
-                    float *e, float *f, int *s, float *Mt, long k, long *t, long *sw, int *rescaled, unsigned flags)
+                    float *e, float *f, int *s, float *Mt, long k, long *t, long *sw, long *gs, int *rescaled,
+                    unsigned flags)
 {
     ora_ssvd st;
     s_fill(&st, m, n, Gr, Gi, ldg, Vr, Vi, ldv, e, f);
@@ -481,10 +547,12 @@ void ora_s_step_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, f
     st.Mt = *Mt;
     st.k = k;
     st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.nogs = (flags & ORA_NO_GS) != 0;
     s_step(&st);
     *s = st.s;
     *Mt = st.Mt;
     *t = st.last_t;
     *sw = st.last_sw;
+    *gs = st.last_gs;
     *rescaled = st.rescaled;
 }

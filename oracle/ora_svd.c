@@ -359,6 +359,60 @@ void ora_swap(int l, double *xpr, double *xpi, double *xqr, double *xqi)
     }
 }
 
+/* eq. (GScond), evaluated on the normalised quotient of the norms that
+ * Alg. Gram forms (eq. efpq): ||g_p|| / ||g_q|| = 2^{e_{p/q}} f_{p/q} with
+ * f_{p/q} = F(fl(f_p/f_q)), compared in (e, f) form with 2^eta_hat upsilon =
+ * 2^{eta_hat + e_u} f_u, eta_hat = DBL_MAX_EXP - 1, upsilon = 2^{e_u} f_u. */
+static int gs_exceeds(double ea, double fa, double eb, double fb, double ups, int eta_hat)
+{
+    double fab = fa / fb;
+    const int g = ilogb(fab);
+    const long eab = (long)ea - (long)eb + g;
+    fab = scalbn(fab, -g);
+    const int eu = ilogb(ups);
+    const double fu = scalbn(ups, -eu);
+    const long et = (long)eta_hat + eu;
+    return eab > et || (eab == et && fab > fu);
+}
+
+int ora_gs_case(double e1, double f1, double e2, double f2, double ups)
+{
+    if (gs_exceeds(e1, f1, e2, f2, ups, DBL_MAX_EXP - 1)) return 1;
+    if (gs_exceeds(e2, f2, e1, f1, ups, DBL_MAX_EXP - 1)) return 2;
+    return 0;
+}
+
+/* eq. (GS) as Alg. zgsscl / dgsscl order it: x' = 2^-ex x and y' = 2^-ey y
+ * exactly (barring underflow), then per component
+ *   Re y'' = fma(-Re psi, Re x', fma(Im psi, Im x', Re y')),
+ *   Im y'' = fma(-Re psi, Im x', fma(-Im psi, Re x', Im y')),
+ * i.e. y' - psi x', and y <- 2^ey y''.  psi = w fl(fy/fx), one product per
+ * part. */
+double ora_gs(int l, const double *xr, const double *xi, double *yr, double *yi,
+              double ex, double fx, double ey, double fy, double wr, double wi)
+{
+    const double fyx = fy / fx;
+    const double psr = wr * fyx, psi = wi * fyx;
+    const int Ex = (int)ex, Ey = (int)ey;
+    double M = 0.0;
+    for (int i = 0; i < l; ++i) {
+        const double xpr = scalbn(xr[i], -Ex), ypr = scalbn(yr[i], -Ey);
+        if (yi) {
+            const double xpi = scalbn(xi[i], -Ex), ypi = scalbn(yi[i], -Ey);
+            const double nr = scalbn(fma(-psr, xpr, fma(psi, xpi, ypr)), Ey);
+            const double ni = scalbn(fma(-psr, xpi, fma(-psi, xpr, ypi)), Ey);
+            yr[i] = nr;
+            yi[i] = ni;
+            M = fmax(M, fmax(fabs(nr), fabs(ni)));
+        } else {
+            const double nr = scalbn(fma(-psr, xpr, ypr), Ey);
+            yr[i] = nr;
+            M = fmax(M, fabs(nr));
+        }
+    }
+    return M;
+}
+
 /* ------------------------------------------------------------------ */
 /* the driver                                                          */
 /* ------------------------------------------------------------------ */
@@ -405,6 +459,8 @@ int ora_init(ora_svd *st)
     st->k = 0;
     st->T = 0;
     st->last_t = 0;
+    st->GS = 0;
+    st->last_gs = 0;
     st->rescaled = 0;
     return ORA_OK;
 }
@@ -438,19 +494,18 @@ void ora_step(ora_svd *st)
 
     /* tolerance upsilon = fl(eps sqrt m), eps = 2^-53 (eq. tol) */
     const double ups = scalbn(sqrt((double)m), -53);
-    long t = 0, sw = 0;
+    long t = 0, sw = 0, gs = 0;
     double M = 0.0;
     for (int l = 0; l < npairs; ++l) {
         int p, q;
         if (!ora_rr_pair(n, kk, l, &p, &q)) continue;
         const double ep = st->e[p], fp = st->f[p], eq = st->e[q], fq = st->f[q];
-        int transform = 0, pbit;
-        double c = 1.0, C = 0.0, S = 0.0;
+        int transform = 0, pbit, gsc = 0;
+        double c = 1.0, C = 0.0, S = 0.0, zr = 0.0, zi = 0.0;
         if (isinf(ep) || isinf(eq)) {
             /* a zero column: never rotated; the zero column goes last */
             pbit = isinf(ep) && !isinf(eq);
         } else {
-            double zr, zi;
             if (st->comp)
                 ora_dpscl_cs(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
             else
@@ -466,9 +521,33 @@ void ora_step(ora_svd *st)
             else
                 zp = ora_evd2_real(a11, a22, a21r, &c, &C, &l1, &l2, ORA_EVD_SCALED);
             pbit = zp & 1;
+            /* a pair to be transformed whose norms differ by more than
+             * 2^eta_hat upsilon is orthogonalised by Gram-Schmidt instead
+             * (Alg. zvjsvd, eq. GScond); the larger column stays in place
+             * (first), so the permutation is the transposition exactly when
+             * the larger one is g_q */
+            if (transform && !st->nogs) {
+                gsc = ora_gs_case(ep, fp, eq, fq, ups);
+                if (gsc) pbit = (gsc == 2);
+            }
         }
         if (st->nosort) pbit = 0;
-        if (transform) {
+        if (transform && gsc) {
+            ++t;
+            ++gs;
+            double Mg;
+            if (gsc == 1)   /* g_q <- g_q - conj(a21') (f_q/f_p) ... , eq. (GS) */
+                Mg = ora_gs(m, COLR(st, p), COLI(st, p), COLR(st, q), COLI(st, q), ep, fp, eq, fq, zr, -zi);
+            else            /* g_p <- g_p - a21' (f_p/f_q) ..., roles reversed */
+                Mg = ora_gs(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, zr, zi);
+            if (pbit) ora_swap(m, COLR(st, p), COLI(st, p), COLR(st, q), COLI(st, q));
+            /* Gram-Schmidt replaces the rotation of G only: V still takes the
+             * Jacobi rotation of the pair (Alg. zvjsvd applies zjrotf to V
+             * either way), which agrees with the Gram-Schmidt update of V to
+             * first order and keeps V unitary */
+            (void)ora_rot(n, VCOLR(st, p), VCOLI(st, p), VCOLR(st, q), VCOLI(st, q), c, C, S, pbit);
+            M = fmax(M, Mg);
+        } else if (transform) {
             ++t;
             const double Mg = ora_rot(m, COLR(st, p), COLI(st, p), COLR(st, q), COLI(st, q), c, C, S, pbit);
             (void)ora_rot(n, VCOLR(st, p), VCOLI(st, p), VCOLR(st, q), VCOLI(st, q), c, C, S, pbit);
@@ -487,6 +566,8 @@ void ora_step(ora_svd *st)
     st->last_t = t;
     st->SW += sw;
     st->last_sw = sw;
+    st->GS += gs;
+    st->last_gs = gs;
     st->Mt = fmax(st->Mt, M);
     st->k++;
 }
@@ -556,6 +637,7 @@ int ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
     st.Vr = Vr; st.Vi = Vi; st.ldv = ldv;
     st.nosort = (flags & ORA_NO_PERMUTE) != 0;
     st.comp = (flags & ORA_COMPENSATED) != 0;
+    st.nogs = (flags & ORA_NO_GS) != 0;
     if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1) return ORA_EINVAL;
     st.e = (double *)malloc(sizeof(double) * (size_t)n);
     st.f = (double *)malloc(sizeof(double) * (size_t)n);
@@ -623,7 +705,7 @@ int ora_init_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
 
 void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                   double *Vr, double *Vi, size_t ldv, double *e, double *f,
-                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, unsigned flags)
+                  int *s, double *Mt, long k, long *t, long *sw, long *gs, int *rescaled, unsigned flags)
 {
     ora_svd st;
     fill(&st, m, n, Gr, Gi, ldg, Vr, Vi, ldv, e, f);
@@ -632,11 +714,13 @@ void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
     st.k = k;
     st.nosort = (flags & ORA_NO_PERMUTE) != 0;
     st.comp = (flags & ORA_COMPENSATED) != 0;
+    st.nogs = (flags & ORA_NO_GS) != 0;
     ora_step(&st);
     *s = st.s;
     *Mt = st.Mt;
     *t = st.last_t;
     *sw = st.last_sw;
+    *gs = st.last_gs;
     *rescaled = st.rescaled;
 }
 

@@ -120,10 +120,24 @@ typedef struct {
     int  rescaled;                 /* number of step-start downscalings */
     int  nosort;                   /* apply U instead of U P (ignore the EVD's permutation) */
     int  comp;                     /* scaled dot-products with compensated summation */
+    int  nogs;                     /* always rotate (no Gram-Schmidt replacement, eq. GScond) */
+    long GS;                       /* Gram-Schmidt transformations in the current sweep */
+    long last_gs;                  /* Gram-Schmidt transformations of the last step */
 } ora_svd;
 
 #define ORA_NO_PERMUTE 1u
 #define ORA_COMPENSATED 2u      /* Alg. zdpsclcs / ddpsclcs instead of zdpscl */
+#define ORA_NO_GS 4u            /* rotate even where eq. (GScond) calls for Gram-Schmidt */
+
+/* eq. (GScond) on the norms (e1,f1) = ||g_p||, (e2,f2) = ||g_q|| of a pair
+ * that is to be transformed: 1 if ||g_p|| > 2^eta_hat upsilon ||g_q||, 2 if
+ * ||g_q|| > 2^eta_hat upsilon ||g_p||, 0 otherwise (rotate). */
+int ora_gs_case(double e1, double f1, double e2, double f2, double ups);
+/* Alg. zgsscl / dgsscl (eq. GS): y <- (y 2^-ey - psi x 2^-ex) 2^ey with
+ * psi = (wr + i wi) (fy/fx); x is left unchanged.  Returns the max-norm of
+ * the new y. */
+double ora_gs(int l, const double *xr, const double *xi, double *yr, double *yi,
+              double ex, double fx, double ey, double fy, double wr, double wi);
 
 /* ---- single precision SVD (Sect. SM8; constants in ora_ssvd.c) ---- */
 float ora_s_hypot(float x, float y);
@@ -136,12 +150,16 @@ void ora_s_dpscl(int m, const float *qr, const float *qi, const float *pr, const
 void ora_s_gram(float zr, float zi, float e1, float f1, float e2, float f2,
                 float *a11, float *a22, float *a21r, float *a21i);
 float ora_s_rot(int l, float *xpr, float *xpi, float *xqr, float *xqi, float c, float C, float S, int swap);
+/* eq. (GScond) / eq. (GS) in single precision (eta_hat = FLT_MAX_EXP - 1) */
+int ora_s_gs_case(float e1, float f1, float e2, float f2, float ups);
+float ora_s_gs(int l, const float *xr, const float *xi, float *yr, float *yi,
+               float ex, float fx, float ey, float fy, float wr, float wi);
 int ora_sgesvj(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
                float *sv_e, float *sv_f, int max_sweeps, int *sweeps, long *steps, unsigned flags);
 int ora_s_init_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
                    float *e, float *f, int *s, float *Mt);
 void ora_s_step_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float *Vi, size_t ldv,
-                    float *e, float *f, int *s, float *Mt, long k, long *t, long *sw, int *rescaled,
+                    float *e, float *f, int *s, float *Mt, long k, long *t, long *sw, long *gs, int *rescaled,
                     unsigned flags);
 
 #define ORA_OK 0
@@ -172,7 +190,7 @@ int  ora_init_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                   int *s, double *Mt);
 void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                   double *Vr, double *Vi, size_t ldv, double *e, double *f,
-                  int *s, double *Mt, long k, long *t, long *sw, int *rescaled, unsigned flags);
+                  int *s, double *Mt, long k, long *t, long *sw, long *gs, int *rescaled, unsigned flags);
 void ora_finalize_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                       double *Vr, double *Vi, size_t ldv, double *e, double *f,
                       int s, double *sv_e, double *sv_f);
