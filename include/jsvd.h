@@ -54,6 +54,10 @@ enum {
 #define JSVD_COMPENSATED 2u /* scaled dot-products with compensated summation
                                (Sect. SM2.2, Alg. zdpsclcs / ddpsclcs) instead of
                                Alg. zdpscl */
+#define JSVD_NO_GS 4u       /* always rotate: no Gram-Schmidt replacement for pairs
+                               whose norms differ by more than 2^eta_hat upsilon
+                               (eq. GScond; by default such a pair is orthogonalised
+                               by eq. GS, Sect. 3.5.1) */
 
 /* flags of jsvd_evd2_batched */
 #define JSVD_EVD_SCALED  1u /* return lambda' = 2^zeta lambda (not backscaled), Sect. 2.3 */
@@ -128,6 +132,8 @@ typedef struct {
     int32_t status;       /* JSVD_OK or the load error */
     int64_t last_sweep_T;     /* transformations in the last completed sweep */
     int64_t last_sweep_swaps; /* swaps without transformation in the last completed sweep */
+    int64_t gs;               /* Gram-Schmidt steps in the current sweep so far (counted in T) */
+    int64_t last_sweep_gs;    /* Gram-Schmidt steps in the last completed sweep */
 } jsvd_info;
 
 /* Allocate a state for an m x n real (is_complex = 0) or complex problem.
@@ -147,8 +153,12 @@ int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_
  * (Alg. zdpscl), the convergence test (Alg. cvg) and scaled Gram matrix
  * (Alg. Gram), the 2x2 EVD (Listing 1), and the rotation or swap of the G
  * and V column pairs (Alg. zjrot), with the step-start rescaling check of
- * Sect. 3.2.  Step index, M~ and the counters stay on the device; launches
- * only. */
+ * Sect. 3.2.  A pair to be transformed whose norms differ by more than
+ * 2^eta_hat upsilon (eq. GScond) takes the Gram-Schmidt step of eq. (GS) on
+ * G instead (the smaller column orthogonalised against the larger, which
+ * stays or moves to the first place), while V still takes the pair's
+ * rotation; JSVD_NO_GS turns this off.  Step index, M~ and the counters stay
+ * on the device; launches only. */
 int jsvd_step(jsvd_state st, void *stream);
 
 /* K steps followed by the end-of-sweep bookkeeping; launches only. */
@@ -181,6 +191,11 @@ int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu,
  * 1024; 0 = automatic).  Results do not depend on it (bit-identical). */
 int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
 
+/* Set the iteration flags of a state (JSVD_NO_PERMUTE, JSVD_COMPENSATED,
+ * JSVD_NO_GS; default none).  They apply from the next step on.  Returns
+ * JSVD_EINVAL for unknown flags. */
+int jsvd_state_set_flags(jsvd_state st, unsigned flags);
+
 /* Single precision state (Sect. SM8: the method in the precision of the
  * datatype, with that precision's range constants): G, V and the norms are
  * float arrays and every operation of the step is an IEEE single operation;
@@ -189,7 +204,8 @@ int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
  * FLT_MAX, the Gram scaling with FLT_MAX_EXP - 1 and the single precision EVD
  * (Sect. 2.4.1).  The compensated dot-products are not offered.
  * jsvd_step, jsvd_sweep, jsvd_state_query (M~ as a double holding the float
- * value), jsvd_state_set_launch, jsvd_state_set_flags (JSVD_NO_PERMUTE only)
+ * value), jsvd_state_set_launch, jsvd_state_set_flags (JSVD_NO_PERMUTE and
+ * JSVD_NO_GS; eta_hat = FLT_MAX_EXP - 1 in eq. GScond)
  * and jsvd_state_destroy take either kind of state; the calls below take a
  * single precision state and the double calls above reject one
  * (JSVD_EINVAL), and the other way round.  Arguments as for the double
@@ -242,7 +258,7 @@ int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg,
 
 /* The whole SVD in single precision (Sect. SM8; the step of
  * jsvd_state_create_f32): the same interface on float arrays, sv_e holding
- * the exponents as floats.  flags: JSVD_NO_PERMUTE only. */
+ * the exponents as floats.  flags: JSVD_NO_PERMUTE, JSVD_NO_GS. */
 int jsvd_gesvj_f32(int m, int n, float *G_re, float *G_im, size_t ldg,
                    float *V_re, float *V_im, size_t ldv,
                    float *sv_e, float *sv_f, float *sv, int max_sweeps, int *sweeps,
@@ -276,7 +292,7 @@ typedef struct {
     int max_sweeps;          /* per request (<= 0: 128) */
     int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
     unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_NO_PERMUTE,
-                                JSVD_COMPENSATED) */
+                                JSVD_COMPENSATED, JSVD_NO_GS) */
 } jsvd_serve_config;
 
 typedef struct {

@@ -22,7 +22,7 @@ import os as _os
 
 __all__ = [
     "lib", "JsvdError", "fortran_empty", "to_device_fortran", "evd2_batched", "State", "gesvj",
-    "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "COMPENSATED",
+    "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "COMPENSATED", "NO_GS",
     "dot_scaled_batched", "evd2_batched_f32",
 ]
 
@@ -33,6 +33,7 @@ OK, NOT_CONVERGED, EINVAL, ENONFINITE, EZERO, ENOMEM, EDEVICE, EAGAIN, ENOTFOUND
 EVD_SCALED, EVD_SINFORM = 1, 2
 NO_PERMUTE = 1
 COMPENSATED = 2
+NO_GS = 4
 
 _lib = None
 
@@ -48,7 +49,8 @@ class _Info(_ct.Structure):
     _fields_ = [("steps", _ct.c_int64), ("sweeps", _ct.c_int64), ("T", _ct.c_int64),
                 ("last_t", _ct.c_int64), ("swaps", _ct.c_int64), ("s", _ct.c_int32),
                 ("rescaled", _ct.c_int32), ("Mt", _ct.c_double), ("converged", _ct.c_int32),
-                ("status", _ct.c_int32), ("last_sweep_T", _ct.c_int64), ("last_sweep_swaps", _ct.c_int64)]
+                ("status", _ct.c_int32), ("last_sweep_T", _ct.c_int64), ("last_sweep_swaps", _ct.c_int64),
+                ("gs", _ct.c_int64), ("last_sweep_gs", _ct.c_int64)]
 
 
 class ServeConfig(_ct.Structure):

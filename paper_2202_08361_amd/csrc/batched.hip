@@ -40,6 +40,7 @@ struct BatchCtl {
     int count;
     int max_sweeps;
     int nosort;
+    int nogs;
 };
 
 struct BatchSmem {
@@ -118,7 +119,7 @@ __device__ __forceinline__ Norm wave_colnorm(const double *xr, const double *xi,
 }
 
 template <bool CPLX, int R, bool COMP>
-__device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSmem &sm)
+__device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nogs, BatchSmem &sm)
 {
     const int m = it.m, n = it.n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -203,7 +204,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSm
                             if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
                         }
                 }
-                const PairDecision dc = pair_core<CPLX, 64, R, COMP>(xr, xi, it.ups, nosort, (double *)nullptr,
+                const PairDecision dc = pair_core<CPLX, 64, R, COMP>(xr, xi, it.ups, nosort, nogs, (double *)nullptr,
                                                                      (double *)nullptr, (double *)nullptr);
                 const int pbit = dc.pbit;
                 double *const Dp_r = pbit ? Gqr : Gpr;
@@ -211,7 +212,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSm
                 double *const Dp_i = pbit ? Gqi : Gpi;
                 double *const Dq_i = pbit ? Gpi : Gqi;
                 if (dc.transform) {
-                    Mw = fmax(Mw, rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S));
+                    Mw = fmax(Mw, transform_regs<CPLX, R>(xr, xi, dc));
                     ++tw;
                 }
                 if (dc.transform || pbit || rescale) {
@@ -263,7 +264,9 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, BatchSm
                     }
                 }
             }
-            // step end: fold the wavefronts' counts and max (exact, order-free)
+            // step end: fold the wavefronts' counts and max (exact, order-free);
+            // the max-norm first over the lanes of each wavefront
+            Mw = wave_max(Mw);
             if (lane == 0) {
                 sm.wM[wv] = Mw;
                 sm.wt[wv] = tw;
@@ -421,14 +424,14 @@ __global__ __launch_bounds__(kBT) void batched_kernel(BatchItem *items, const in
         if (idx >= count) return;
         BatchItem it = items[order[idx]];
         switch ((it.cplx ? 100 : 0) + it.R) {
-        case 1: svd_workgroup<false, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 2: svd_workgroup<false, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 4: svd_workgroup<false, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 8: svd_workgroup<false, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 101: svd_workgroup<true, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 102: svd_workgroup<true, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 104: svd_workgroup<true, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
-        case 108: svd_workgroup<true, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, sm); break;
+        case 1: svd_workgroup<false, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 2: svd_workgroup<false, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 4: svd_workgroup<false, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 8: svd_workgroup<false, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 101: svd_workgroup<true, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 102: svd_workgroup<true, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 104: svd_workgroup<true, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
+        case 108: svd_workgroup<true, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
         default: break;
         }
         if (threadIdx.x == 0) {
@@ -524,6 +527,7 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     ctl.count = cnt;
     ctl.max_sweeps = max_sweeps;
     ctl.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+    ctl.nogs = (flags & JSVD_NO_GS) ? 1 : 0;
     memcpy(h + oCtl, &ctl, sizeof(ctl));
     char *dm = (char *)bl->dmem;
     int dev = 0, ncu = 256;
@@ -572,7 +576,7 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
     if (count < 0) return JSVD_EINVAL;
     if (count == 0) return JSVD_OK;
     if (!m || !n || !G_re || !ldg || !V_re || !ldv || !sv_e || !sv_f || !status) return JSVD_EINVAL;
-    if (flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED)) return JSVD_EINVAL;
+    if (flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
     for (int i = 0; i < count; ++i) {
         const int c = is_complex ? is_complex[i] : 0;
         if (n[i] < 1 || m[i] < n[i] || !G_re[i] || !V_re[i] || !sv_e[i] || !sv_f[i] || ldg[i] < (size_t)m[i] ||

@@ -158,6 +158,7 @@ static void fill_desc(SvdDescT<T> &d, int m, int n, int cplx, char *b, const Sta
     d.cplx = cplx;
     d.nosort = 0;
     d.comp = 0;
+    d.nogs = 0;
     d.Gr = (T *)(b + L.oG);
     d.Gi = cplx ? d.Gr + (size_t)L.ldg * n : nullptr;
     d.ldg = L.ldg;
@@ -328,19 +329,22 @@ extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
     return JSVD_OK;
 }
 
-static constexpr unsigned kIterFlags = JSVD_NO_PERMUTE | JSVD_COMPENSATED;
+static constexpr unsigned kIterFlags = JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS;
+static constexpr unsigned kIterFlagsF32 = JSVD_NO_PERMUTE | JSVD_NO_GS;
 
 // the iteration flags a state accepts (the compensated dot-products are
 // double precision only)
-static unsigned iter_flags_of(jsvd_state st) { return st->fp32 ? JSVD_NO_PERMUTE : kIterFlags; }
+static unsigned iter_flags_of(jsvd_state st) { return st->fp32 ? kIterFlagsF32 : kIterFlags; }
 
 static void apply_flags(jsvd_state st, unsigned flags)
 {
     st->flags = flags;
     const int nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
     const int comp = (flags & JSVD_COMPENSATED) ? 1 : 0;
+    const int nogs = (flags & JSVD_NO_GS) ? 1 : 0;
     st->d.nosort = st->df.nosort = nosort;
     st->d.comp = st->df.comp = comp;
+    st->d.nogs = st->df.nogs = nogs;
 }
 
 extern "C" int jsvd_state_set_flags(jsvd_state st, unsigned flags)
@@ -505,6 +509,8 @@ extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
     out->status = h.status;
     out->last_sweep_T = h.T_prev;
     out->last_sweep_swaps = h.SW_prev;
+    out->gs = h.GS;
+    out->last_sweep_gs = h.GS_prev;
     return JSVD_OK;
 }
 
@@ -643,7 +649,7 @@ static int gesvj_t(int m, int n, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im,
     if (n < 1 || m < n || !G_re || !V_re || !sv_e || !sv_f || ldg < (size_t)m || ldv < (size_t)n)
         return JSVD_EINVAL;
     if ((G_im == nullptr) != (V_im == nullptr)) return JSVD_EINVAL;
-    if (flags & ~(F32 ? (unsigned)JSVD_NO_PERMUTE : kIterFlags)) return JSVD_EINVAL;
+    if (flags & ~(F32 ? kIterFlagsF32 : kIterFlags)) return JSVD_EINVAL;
     jsvd_state st = nullptr;
     int rc = state_create(m, n, G_im != nullptr, F32, &st);
     if (rc != JSVD_OK) return rc;

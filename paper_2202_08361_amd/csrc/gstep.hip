@@ -27,13 +27,14 @@ constexpr int kPW = 256;   // threads per pivot pair of the G kernel
 
 // Workgroups of the G kernel resident per compute unit: two (at most 256
 // VGPRs), one with the compensated dot-products (more registers), and four
-// (at most 128 VGPRs) for single precision pairs of up to 8192 real / 4096
-// complex rows, which fit there without spilling.
+// (at most 128 VGPRs) for real single precision pairs of up to 8192 rows,
+// which fit there without spilling.  (Complex single precision pairs measured
+// the same with two or four.)
 template <typename T, bool CPLX, int R, bool COMP>
 constexpr int gpair_wgs_per_cu()
 {
     if (COMP) return 1;
-    if (sizeof(T) == sizeof(float) && R <= (CPLX ? 16 : 32)) return 4;
+    if (sizeof(T) == sizeof(float) && !CPLX && R <= 32) return 4;
     return 2;
 }
 
@@ -103,17 +104,18 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
                     if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
                 }
         }
-        const PairDecisionT<T> dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, red, red + 4 * W, mxs);
+        const PairDecisionT<T> dc =
+            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, red, red + 4 * W, mxs);
         const int pbit = dc.pbit;
         T *const Dp_r = pbit ? Gqr : Gpr;
         T *const Dq_r = pbit ? Gpr : Gqr;
         T *const Dp_i = pbit ? Gqi : Gpi;
         T *const Dq_i = pbit ? Gpi : Gqi;
         if (dc.transform) {
-            T mm[1] = {rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S)};
+            T mm[1] = {transform_regs<CPLX, R>(xr, xi, dc)};
             group_max<W, 1>(mm, mxs + 2 * (W / 64));
             pp.mx = mm[0];
-            pp.flag = 1 | (pbit ? 2 : 0);
+            pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
             pp.c = dc.c;
             pp.C = dc.C;
             pp.S = dc.S;
@@ -210,16 +212,17 @@ template <typename T>
 __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs)
 {
     __shared__ double smx[4];
-    __shared__ unsigned long long scnt[8];
+    __shared__ unsigned long long scnt[12];
     DevScalars *sc = d.sc;
     const int t = threadIdx.x;
     double mx = 0.0;
-    unsigned long long tc = 0, swc = 0;
+    unsigned long long tc = 0, swc = 0, gsc = 0;
     for (int l = t; l < npairs; l += 256) {
         const int fl = prm[l].flag;
         if (fl & 1) {
             mx = fmax(mx, prm[l].mx);
             ++tc;
+            if (fl & 4) ++gsc;
         } else if (fl & 2) {
             ++swc;
         }
@@ -229,20 +232,23 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
     for (int h = 32; h >= 1; h >>= 1) {
         tc += __shfl_xor(tc, h, 64);
         swc += __shfl_xor(swc, h, 64);
+        gsc += __shfl_xor(gsc, h, 64);
     }
     if ((t & 63) == 0) {
         smx[t >> 6] = mx;
         scnt[t >> 6] = tc;
         scnt[4 + (t >> 6)] = swc;
+        scnt[8 + (t >> 6)] = gsc;
     }
     __syncthreads();
     if (t == 0) {
         double M = smx[0];
-        unsigned long long tt = scnt[0], sw = scnt[4];
+        unsigned long long tt = scnt[0], sw = scnt[4], gg = scnt[8];
         for (int w = 1; w < 4; ++w) {
             M = fmax(M, smx[w]);
             tt += scnt[w];
             sw += scnt[4 + w];
+            gg += scnt[8 + w];
         }
         const T Mt = (T)bits2d(sc->Mt_bits);
         const bool rescale = (d.cplx ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt) < 0;
@@ -251,6 +257,7 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
         sc->Mt_bits = d2bits((double)fmax(Mt2, (T)M));
         sc->T += (long long)tt;
         sc->SW += (long long)sw;
+        sc->GS += (long long)gg;
         sc->last_t = (long long)tt;
         if (rescale) {
             sc->s += sp;

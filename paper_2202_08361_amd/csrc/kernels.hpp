@@ -23,6 +23,7 @@ struct DevScalars {
     unsigned long long M_step;    // max-norm of the transformed columns of this step (bits)
     unsigned long long t_step;    // transformations in this step
     unsigned long long sw_step;   // swaps without transformation in this step
+    unsigned long long gs_step;   // Gram-Schmidt transformations in this step
     unsigned long long done;      // workgroups finished in this step
     long long k;                  // global step counter
     long long T;                  // transformations in the current sweep
@@ -32,6 +33,8 @@ struct DevScalars {
     long long C;                  // sweeps that found a transformation or a swap
     long long T_prev;             // transformations of the last completed sweep
     long long SW_prev;            // swaps without transformation of the last completed sweep
+    long long GS;                 // Gram-Schmidt transformations in the current sweep (counted in T)
+    long long GS_prev;            // Gram-Schmidt transformations of the last completed sweep
     int s;                        // effective scaling exponent
     int rescaled;                 // step-start downscalings
     int converged;                // a sweep without transformation and swap was seen
@@ -50,6 +53,7 @@ struct SvdDescT {
     int cplx;
     int nosort;            // ignore the permutation of the EVD during the iteration
     int comp;              // compensated scaled dot-products (Alg. zdpsclcs / ddpsclcs; double only)
+    int nogs;              // always rotate (no Gram-Schmidt replacement, eq. GScond)
     T *Gr, *Gi;            // working iteration matrix
     long long ldg;
     T *Vr, *Vi;            // accumulated right transformations
@@ -68,7 +72,8 @@ struct PairParam {
     double c, C, S;   // cos phi, e^{i alpha} tan phi
     double mx;        // max |component| of the rotated G columns (0 if not rotated)
     int p, q;         // the pair
-    int flag;         // bit 0: rotate, bit 1: swap the columns (permutation P)
+    int flag;         // bit 0: transform (rotation of V, counted), bit 1: swap the columns
+                      // (permutation P), bit 2: G took the Gram-Schmidt step of eq. (GS)
     int pad;
 };
 

@@ -321,6 +321,54 @@ __device__ __forceinline__ void gram_scaled(T zr, T zi, int e1, T f1, int e2, T 
     *a21i = scal2(zi, sA);
 }
 
+// eq. (GScond) for norms ||g_a|| = 2^ea fa and ||g_b|| = 2^eb fb: is
+// ||g_a|| > 2^eta_hat upsilon ||g_b||?  Decided on the normalised quotient of
+// eq. (efpq), 2^{ea - eb + g} F(fl(fa/fb)) with g = getexp(fl(fa/fb)), against
+// 2^{eta_hat} upsilon = 2^{eta_hat + eu} fu in (e, f) form (exact comparisons).
+template <typename T>
+__device__ __forceinline__ bool gs_exceeds(int ea, T fa, int eb, T fb, T ups)
+{
+    T q = fa / fb;
+    const int g = getexp(q);
+    const int eab = ea - eb + g;
+    q = scal2(q, -g);
+    const int eu = getexp(ups);
+    const T fu = scal2(ups, -eu);
+    const int et = SvdFp<T>::gram_emax + eu;
+    return eab > et || (eab == et && q > fu);
+}
+
+// eq. (GS) on a register column pair (Alg. zgsscl / dgsscl order): column D
+// <- (x_D 2^-eD - psi x_S 2^-eS) 2^eD with psi = (wr + i wi) fl(fD/fS),
+// column S unchanged.  Per component, with x' = 2^-eS x_S, y' = 2^-eD x_D:
+// Re = fma(-Re psi, Re x', fma(Im psi, Im x', Re y')), Im = fma(-Re psi,
+// Im x', fma(-Im psi, Re x', Im y')).  Returns the thread's max-norm of the
+// new column D.
+template <bool CPLX, int R, int S, int D, typename T>
+__device__ __forceinline__ T gs_regs(T (&xr)[2][R], T (&xi)[2][R], int eS, T fS, int eD, T fD, T wr, T wi)
+{
+    const T fds = fD / fS;
+    const T pr = wr * fds, pi = wi * fds;
+    T Mx = T(0);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const T sr = scal2(xr[S][j], -eS), dr = scal2(xr[D][j], -eD);
+        if (CPLX) {
+            const T si = scal2(xi[S][j], -eS), di = scal2(xi[D][j], -eD);
+            const T nr = scal2(fma(-pr, sr, fma(pi, si, dr)), eD);
+            const T ni = scal2(fma(-pr, si, fma(-pi, sr, di)), eD);
+            xr[D][j] = nr;
+            xi[D][j] = ni;
+            Mx = fmax(Mx, fmax(fabs(nr), fabs(ni)));
+        } else {
+            const T nr = scal2(fma(-pr, sr, dr), eD);
+            xr[D][j] = nr;
+            Mx = fmax(Mx, fabs(nr));
+        }
+    }
+    return Mx;
+}
+
 // The scaled dot-product of the pair without its final division, \hat z =
 // (g_q 2^-e_q)^* (g_p 2^-e_p), in the canonical lane order (h[0] = Re,
 // h[1] = Im): Alg. zdpscl (fma per lane), or with COMP Alg. zdpsclcs /
@@ -416,20 +464,25 @@ struct PairDecisionT {
     NormT<T> np, nq;   // the column norms (e, f) before the transformation
     bool transform;
     int pbit;          // the permutation of the EVD (0 when ignored)
+    int gs;            // 0: rotate; 1: Gram-Schmidt of g_q against g_p; 2: of g_p against g_q
     T c, C, S;
+    T zr, zi;          // a21'
 };
 using PairDecision = PairDecisionT<double>;
 
 // Norms (Sect. 3.2), scaled dot-product (Alg. zdpscl, or zdpsclcs /
 // ddpsclcs with COMP), convergence test (Alg. cvg), scaled Gram matrix
 // (Alg. Gram) and 2x2 EVD (Listing 1) of the pair (xr/xi[0] = column p,
-// [1] = column q; rows t + W j, zeros beyond m).  Scratch: red_norm (4 W
-// values), red_dot (2 W values, 8 W with COMP), mxs (2 W/64 values);
-// unused for W = 64.  Every thread returns the same decision.  All of it in
-// the precision T, with that precision's constants.
+// [1] = column q; rows t + W j, zeros beyond m).  A pair to be transformed
+// whose norms differ by more than 2^eta_hat upsilon is marked for the
+// Gram-Schmidt replacement of eq. (GScond) unless nogs; its permutation is
+// then the transposition exactly when g_q is the larger column.  Scratch:
+// red_norm (4 W values), red_dot (2 W values, 8 W with COMP), mxs (2 W/64
+// values); unused for W = 64.  Every thread returns the same decision.  All of
+// it in the precision T, with that precision's constants.
 template <bool CPLX, int W, int R, bool COMP = false, typename T>
 __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const T (&xi)[2][R], T ups, int nosort,
-                                                      T *red_norm, T *red_dot, T *mxs)
+                                                      int nogs, T *red_norm, T *red_dot, T *mxs)
 {
     using LS = LaneShape<W, R>;
     constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
@@ -477,9 +530,12 @@ __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const
     o.np.zero = zp_;
     o.nq.zero = zq_;
     o.transform = false;
+    o.gs = 0;
     o.c = T(1);
     o.C = T(0);
     o.S = T(0);
+    o.zr = T(0);
+    o.zi = T(0);
     if (zp_ || zq_) {
         // a zero column is never rotated; it goes after the other one
         o.pbit = (zp_ && !zq_) ? 1 : 0;
@@ -498,10 +554,26 @@ __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const
         o.C = e.C;
         o.S = e.S;
         o.pbit = e.p;
+        o.zr = zr;
+        o.zi = zi;
+        if (o.transform && !nogs) {
+            if (gs_exceeds(o.np.e, o.np.f, o.nq.e, o.nq.f, ups))
+                o.gs = 1;
+            else if (gs_exceeds(o.nq.e, o.nq.f, o.np.e, o.np.f, ups))
+                o.gs = 2;
+            if (o.gs) o.pbit = (o.gs == 2) ? 1 : 0;
+        }
     }
     if (nosort) o.pbit = 0;
     return o;
 }
+
+// The transformation of a register pair that pair_core decided on: the
+// rotation of Alg. zjrot or the Gram-Schmidt step of eq. (GS) (g_q against
+// g_p with conj(a21'), or g_p against g_q with a21').  Returns the thread's
+// max-norm of the changed column(s).
+template <bool CPLX, int R, typename T>
+__device__ __forceinline__ T transform_regs(T (&xr)[2][R], T (&xi)[2][R], const PairDecisionT<T> &dc);
 
 // Rotation of a register pair (Alg. zjrot, eq. transf with the complex fma
 // of eq. zfma): xr/xi[0] <- x_p', [1] <- x_q'; returns the thread's max-norm.
@@ -527,6 +599,16 @@ __device__ __forceinline__ T rot_regs(T (&xr)[2][R], T (&xi)[2][R], T c, T C, T 
         }
     }
     return Mx;
+}
+
+template <bool CPLX, int R, typename T>
+__device__ __forceinline__ T transform_regs(T (&xr)[2][R], T (&xi)[2][R], const PairDecisionT<T> &dc)
+{
+    if (dc.gs == 1)
+        return gs_regs<CPLX, R, 0, 1>(xr, xi, dc.np.e, dc.np.f, dc.nq.e, dc.nq.f, dc.zr, -dc.zi);
+    if (dc.gs == 2)
+        return gs_regs<CPLX, R, 1, 0>(xr, xi, dc.nq.e, dc.nq.f, dc.np.e, dc.np.f, dc.zr, dc.zi);
+    return rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S);
 }
 
 } // namespace jsvd

@@ -54,7 +54,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
     T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
 
     bool transform = false;
-    int pbit = 0;
+    int pbit = 0, gs = 0;
     T Mblk = T(0);
 
     if (!valid) {
@@ -88,18 +88,21 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
                 }
         }
 
-        const PairDecisionT<T> dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, sm.norm, sm.dot, sm.mx1);
+        const PairDecisionT<T> dc =
+            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, sm.norm, sm.dot, sm.mx1);
+        gs = dc.gs;
         transform = dc.transform;
         pbit = dc.pbit;
         const NormT<T> np_ = dc.np, nq_ = dc.nq;
 
-        // ---- rotation (Alg. zjrot) or swap of the G pair, then of the V pair
+        // ---- rotation (Alg. zjrot) or Gram-Schmidt step (eq. GS) or swap of
+        // the G pair, then the rotation or swap of the V pair
         T *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
         T *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
         T *const Dp_i = pbit ? Gqi : Gpi;
         T *const Dq_i = pbit ? Gpi : Gqi;
         if (transform) {
-            const T Mx = rot_regs<CPLX, R>(xr, xi, dc.c, dc.C, dc.S);
+            const T Mx = transform_regs<CPLX, R>(xr, xi, dc);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
@@ -196,6 +199,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
         if (transform) {
             atomicMax(&sc->M_step, d2bits((double)Mblk));
             atomicAdd(&sc->t_step, 1ull);
+            if (gs) atomicAdd(&sc->gs_step, 1ull);
         } else if (pbit) {
             atomicAdd(&sc->sw_step, 1ull);
         }
@@ -210,6 +214,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
             const long long sw = (long long)atomicExch(&sc->sw_step, 0ull);
             sc->T += tt;
             sc->SW += sw;
+            sc->GS += (long long)atomicExch(&sc->gs_step, 0ull);
             sc->last_t = tt;
             if (rescale) {
                 sc->s += sp;
@@ -307,8 +312,10 @@ __global__ void sweep_end_kernel(DevScalars *sc)
     }
     sc->T_prev = sc->T;
     sc->SW_prev = sc->SW;
+    sc->GS_prev = sc->GS;
     sc->T = 0;
     sc->SW = 0;
+    sc->GS = 0;
 }
 
 hipError_t launch_sweep_end(DevScalars *sc, hipStream_t s)
@@ -346,6 +353,7 @@ __global__ void init_scalars_kernel(SvdDescT<T> d, const unsigned long long *max
     sc->M_step = 0;
     sc->t_step = 0;
     sc->sw_step = 0;
+    sc->gs_step = 0;
     sc->done = 0;
     sc->k = 0;
     sc->T = 0;
@@ -355,6 +363,8 @@ __global__ void init_scalars_kernel(SvdDescT<T> d, const unsigned long long *max
     sc->C = 0;
     sc->T_prev = 0;
     sc->SW_prev = 0;
+    sc->GS = 0;
+    sc->GS_prev = 0;
     sc->rescaled = 0;
     sc->converged = 0;
     sc->max_sweeps = max_sweeps;

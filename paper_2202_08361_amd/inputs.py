@@ -304,3 +304,32 @@ def serve_matrix(m: int, n: int, kappa: float, cplx: bool, g: np.random.Generato
     """One serving request: cheap random orthonormal factors (QR of a Gaussian)."""
     sig = sigma_logspace(n, 1.0 / kappa)
     return svd_matrix(m, n, sig, g, cplx=cplx, extended=False) + (sig,)
+
+
+# ------------------------------------------------------------------ extreme norm ratios
+def sm9_matrix(hi: int = 1023, lo: int = -51, n: int = 16, dtype=np.float64, phases_seed: int | None = None):
+    """The test matrix of Sect. SM9: G_ij = 2^(hi - (j-1) - |i-j|) for
+    j <= n/2, 2^(lo - (j-1) - |i-j|) beyond (1-based indices); hi = eta_hat,
+    lo = lg upsilon make the two column groups' norms differ by far more than
+    2^eta_hat upsilon.  With phases_seed, complex: every entry times
+    e^{i theta}, theta uniform (returns (re, im) then), else (G, None)."""
+    G = np.zeros((n, n), order="F")
+    for i in range(1, n + 1):
+        for j in range(1, n + 1):
+            G[i - 1, j - 1] = 2.0 ** ((hi if j <= n // 2 else lo) - (j - 1) - abs(i - j))
+    if phases_seed is None:
+        return G.astype(dtype), None
+    g = rng(CFG_PLAIN_LARGE, 4000 + phases_seed)
+    th = g.uniform(0, 2 * np.pi, size=(n, n))
+    return (np.asfortranarray((G * np.cos(th)).astype(dtype)), np.asfortranarray((G * np.sin(th)).astype(dtype)))
+
+
+def split_scale_columns(m: int, n: int, g: np.random.Generator, cplx: bool, shift: int):
+    """Gaussian columns (random_columns) with the second half of the columns
+    scaled by 2^-shift: every pair across the halves has a norm ratio of about
+    2^shift."""
+    Ar, Ai = random_columns(m, n, g, cplx)
+    Ar[:, n // 2:] = np.ldexp(Ar[:, n // 2:], -shift)
+    if cplx:
+        Ai[:, n // 2:] = np.ldexp(Ai[:, n // 2:], -shift)
+    return Ar, Ai

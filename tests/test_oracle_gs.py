@@ -249,16 +249,6 @@ def test_gs_step_forward_reversed(ora):
         assert sr.step() == 1 and sr.last_gs == 0
 
 
-def _sm9(hi, lo, n=16, dtype=np.float64):
-    """The test matrix of Sect. SM9: G_ij = 2^(hi - (j-1) - |i-j|) for j <= n/2
-    and 2^(lo - (j-1) - |i-j|) beyond (1-based), hi = eta_hat, lo = lg upsilon."""
-    G = np.zeros((n, n), order="F", dtype=dtype)
-    for i in range(1, n + 1):
-        for j in range(1, n + 1):
-            G[i - 1, j - 1] = 2.0 ** ((hi if j <= n // 2 else lo) - (j - 1) - abs(i - j))
-    return G
-
-
 @pytest.mark.parametrize("single", [False, True])
 def test_sm9_matrix(ora, single):
     """Sect. SM9 (16 x 16, upsilon = 2^-51; single precision: 2^-22 and
@@ -269,7 +259,7 @@ def test_sm9_matrix(ora, single):
     without it the iteration never stops: 128 sweeps and no convergence."""
     n = 16
     eps = EPS_F if single else EPS
-    G = _sm9(127, -22, dtype=np.float32) if single else _sm9(1023, -51)
+    G = inputs.sm9_matrix(127, -22, dtype=np.float32)[0] if single else inputs.sm9_matrix(1023, -51)[0]
     run = ora.sgesvj if single else ora.gesvj
     St = ora.SState if single else ora.State
     st = St(G)
@@ -303,7 +293,7 @@ def test_sm9_matrix(ora, single):
 def test_sm9_complex_equals_real(ora, single):
     """The SM9 matrix as complex data with zero imaginary parts takes the
     complex Gram-Schmidt path and gives the real results bit for bit."""
-    G = _sm9(127, -22, dtype=np.float32) if single else _sm9(1023, -51)
+    G = inputs.sm9_matrix(127, -22, dtype=np.float32)[0] if single else inputs.sm9_matrix(1023, -51)[0]
     run = ora.sgesvj if single else ora.gesvj
     rr = run(G)
     rc = run(G, np.zeros_like(G))
