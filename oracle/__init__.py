@@ -86,6 +86,10 @@ def lib():
         L.ora_step_ext.argtypes = [i, i, _dp, _dp, sz, _dp, _dp, sz, _dp, _dp, _ct.POINTER(i), _dp,
                                    _ct.c_long, _ct.POINTER(_ct.c_long), _ct.POINTER(_ct.c_long),
                                    _ct.POINTER(_ct.c_long), _ct.POINTER(i), _ct.c_uint]
+        L.ora_nrmf.restype = i
+        L.ora_nrmf.argtypes = [i, _dp, _dp, i, _dp, _dp, _dp, _dp]
+        L.ora_nrmf_lanes.restype = i
+        L.ora_nrmf_lanes.argtypes = [i, _dp, _dp, i, _dp, _dp]
         L.ora_gs_case.restype = i
         L.ora_gs_case.argtypes = [d, d, d, d, d]
         L.ora_gs.restype = d
@@ -460,3 +464,26 @@ def sgesvj(G_re, G_im=None, max_sweeps=128, flags=0):
 def sv_values(sv_e, sv_f):
     """sigma_j = 2^e_j f_j as float64 (may overflow or underflow)."""
     return _np.ldexp(sv_f, _np.where(_np.isinf(sv_e), -2000, sv_e).astype(_np.int64))
+
+
+# ---------------------------------------------------------------- Alg. rnF
+def nrmf(xr, xi=None, lanes=1024):
+    """Alg. rnF with `lanes` lanes: dict(e2, f2, e, f) with ||x||^2 = 2^e2 f2 and
+    ||x|| = 2^e f (integral e as floats, -inf for a zero array)."""
+    xr = _np.ascontiguousarray(xr, dtype=_np.float64)
+    xi = None if xi is None else _np.ascontiguousarray(xi, dtype=_np.float64)
+    o = [_ct.c_double() for _ in range(4)]
+    st = lib().ora_nrmf(xr.shape[0], _p(xr), _p(xi), lanes, *o)
+    if st != OK:
+        raise ValueError("ora_nrmf: invalid arguments")
+    return dict(e2=o[0].value, f2=o[1].value, e=o[2].value, f=o[3].value)
+
+
+def nrmf_lanes(xr, xi=None, lanes=1024):
+    """The unsorted lane partial sums (e, f) of ||x||^2 of Alg. rnF."""
+    xr = _np.ascontiguousarray(xr, dtype=_np.float64)
+    xi = None if xi is None else _np.ascontiguousarray(xi, dtype=_np.float64)
+    le, lf = _np.empty(lanes), _np.empty(lanes)
+    if lib().ora_nrmf_lanes(xr.shape[0], _p(xr), _p(xi), lanes, _p(le), _p(lf)) != OK:
+        raise ValueError("ora_nrmf_lanes: invalid arguments")
+    return le, lf

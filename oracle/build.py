@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["ora_evd2.c", "ora_sevd2.c", "ora_svd.c", "ora_ssvd.c"]
+SOURCES = ["ora_evd2.c", "ora_sevd2.c", "ora_svd.c", "ora_ssvd.c", "ora_nrmf.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only", "-frounding-math",
           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-D_GNU_SOURCE"]

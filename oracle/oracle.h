@@ -195,7 +195,15 @@ void ora_finalize_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
                       double *Vr, double *Vi, size_t ldv, double *e, double *f,
                       int s, double *sv_e, double *sv_f);
 
+/* ---- non-overflowing Frobenius norm with a widened exponent (Sect. SM6, Alg. rnF) ---- */
+/* The s lane partial sums (e, f) of ||x||^2 (s a power of two), unsorted. */
+int ora_nrmf_lanes(int m, const double *xr, const double *xi, int s, double *le, double *lf);
+/* ||x||^2 = 2^e2 f2 and ||x|| = 2^e f (e2, e integral doubles, -inf for x = 0). */
+int ora_nrmf(int m, const double *xr, const double *xi, int s, double *e2, double *f2, double *e, double *f);
+
+
 #ifdef __cplusplus
 }
 #endif
+
 #endif
