@@ -200,6 +200,35 @@ def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0, fp32
                 frac=byts / t / 1e9 / HBM_PEAK_GBS)
 
 
+def nrmf_rate(torch, J, inputs, m, n, cplx, K=10, lanes=1024):
+    """Alg. rnF over every column of an m x n matrix (Gaussian columns): time
+    per launch with HIP events on the launch stream, algorithmic bytes = the
+    matrix read once plus 32 bytes written per column."""
+    import ctypes
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 99 + int(cplx))
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    dr = J.to_device_fortran(Ar)
+    di = J.to_device_fortran(Ai) if cplx else None
+    outs = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    st = torch.cuda.current_stream()
+    args = [n, m, ctypes.c_void_p(dr.data_ptr()), ctypes.c_void_p(di.data_ptr()) if cplx else None, m, lanes] + \
+        [ctypes.c_void_p(o.data_ptr()) for o in outs] + [ctypes.c_void_p(st.cuda_stream)]
+    L = J.lib()
+    for _ in range(2):
+        assert L.jsvd_nrmf_batched(*args) == 0
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for a, b in evs:
+        a.record(st)
+        L.jsvd_nrmf_batched(*args)
+        b.record(st)
+    torch.cuda.synchronize()
+    t = sum(a.elapsed_time(b) for a, b in evs) / K * 1e-3
+    byts = 8.0 * (2 if cplx else 1) * m * n + 32.0 * n
+    return dict(m=m, n=n, complex=bool(cplx), lanes=lanes, us_per_launch=t * 1e6, algorithmic_bytes=byts,
+                achieved_GBs=byts / t / 1e9, frac=byts / t / 1e9 / HBM_PEAK_GBS)
+
+
 def sweep_time(torch, J, inputs, m, n, cplx, fp32=False):
     """One whole sweep (graph of K steps) of the large plain workloads on a fresh state."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 88 + int(cplx))
@@ -453,6 +482,11 @@ def main():
             nm = f"step_{'c' if c else 'r'}{m}x{n}_f32"
             log(f"[bench] {nm}")
             extra[nm] = step_roofline(torch, J, inputs, m, n, c, fp32=True)
+            log(f"[bench]   {extra[nm]}")
+        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
+            nm = f"nrmf_{'c' if c else 'r'}{m}x{n}"
+            log(f"[bench] {nm}: Alg. rnF norms of every column")
+            extra[nm] = nrmf_rate(torch, J, inputs, m, n, c)
             log(f"[bench]   {extra[nm]}")
         for nm, fl in (("svd_real256_permute_f32", 0), ("svd_real256_nopermute_f32", J.NO_PERMUTE)):
             log(f"[bench] {nm}")

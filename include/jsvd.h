@@ -243,6 +243,25 @@ int jsvd_dot_scaled_batched(int npairs, int m, const double *Q_re, const double 
                             double *z_re, double *z_im, unsigned flags, void *stream);
 
 /* ----------------------------------------------------------------------
+ * Batched non-overflowing Frobenius norms with a widened exponent range
+ * (Sect. SM6, Alg. rnF): for each column j < ncols of X (m rows, column-major,
+ * leading dimension ld >= m; complex columns split, X_im NULL for real data),
+ *   ||x_j||^2 = 2^{e2[j]} f2[j] and ||x_j|| = 2^{e[j]} f[j], 1 <= f < 2,
+ * with e2, e integral doubles (-inf for a zero column, then f = 1) that may
+ * exceed the exponent range of double, so no finite input overflows or
+ * underflows to zero.  Steps: lanes (a power of two, 1 ... 1024) partial
+ * sums, lane L taking the elements L, L + lanes, ... in order (complex: real
+ * part, then imaginary part), each updated as fma(|x|, |x|, r) in (e, f) form
+ * (Sect. SM6.2); the partial sums sorted by (e, f) (eq. vsort) and added
+ * pairwise (eqs. 1red, redj); the square root of Sect. SM6.1.  Results depend
+ * on `lanes` only (1024: the lane vector of the step's own sums).  e2 and f2
+ * may be NULL.  Elements must be finite.  Device arrays of the caller;
+ * launches only.
+ * ---------------------------------------------------------------------- */
+int jsvd_nrmf_batched(int ncols, int m, const double *X_re, const double *X_im, size_t ld, int lanes,
+                      double *e2, double *f2, double *e, double *f, void *stream);
+
+/* ----------------------------------------------------------------------
  * The whole SVD (Alg. zvjsvd with round-robin pairs): G = U Sigma V^*.
  * G (m x n, ldg >= m) is overwritten by U; V (n x n, ldv >= n) receives V;
  * sv_e/sv_f (n) receive sigma_j = 2^{sv_e[j]} sv_f[j] in descending order;

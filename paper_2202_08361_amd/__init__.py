@@ -23,7 +23,7 @@ import os as _os
 __all__ = [
     "lib", "JsvdError", "fortran_empty", "to_device_fortran", "evd2_batched", "State", "gesvj",
     "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "COMPENSATED", "NO_GS",
-    "dot_scaled_batched", "evd2_batched_f32",
+    "dot_scaled_batched", "evd2_batched_f32", "nrmf_batched",
 ]
 
 _HERE = _os.path.dirname(_os.path.abspath(__file__))
@@ -101,6 +101,8 @@ def lib():
         L.jsvd_state_restore_f32.argtypes = [vp, vp, vp, sz, vp, vp, sz, _ct.c_int32, d, _ct.c_int64, vp]
         L.jsvd_state_finalize_f32.restype = i
         L.jsvd_state_finalize_f32.argtypes = [vp, vp, vp, sz, vp, vp, sz, vp, vp, vp, vp]
+        L.jsvd_nrmf_batched.restype = i
+        L.jsvd_nrmf_batched.argtypes = [i, i, vp, vp, sz, i, vp, vp, vp, vp, vp]
         L.jsvd_gesvj_f32.restype = i
         L.jsvd_gesvj_f32.argtypes = [i, i, vp, vp, sz, vp, vp, sz, vp, vp, vp, i, _ct.POINTER(i), u, vp]
         L.jsvd_state_destroy.restype = None
@@ -262,6 +264,21 @@ def dot_scaled_batched(Q_re, P_re, eq, fq, ep, fp, Q_im=None, P_im=None, flags=0
                                          _ptr(eq), _ptr(fq), _ptr(ep), _ptr(fp), _ptr(z_re), _ptr(z_im),
                                          flags, _stream(stream)), "jsvd_dot_scaled_batched")
     return z_re, z_im
+
+
+def nrmf_batched(X_re, X_im=None, lanes=1024, stream=None):
+    """Widened-exponent Frobenius norms of the columns of an (m, ncols)
+    column-major float64 CUDA tensor (Alg. rnF, jsvd_nrmf_batched).  Returns
+    (e2, f2, e, f): ||x_j||^2 = 2^e2 f2, ||x_j|| = 2^e f, float64 tensors."""
+    torch = _torch()
+    m, ncols = X_re.shape
+    ld = _mat(X_re, m, ncols, "X_re")
+    if X_im is not None and _mat(X_im, m, ncols, "X_im") != ld:
+        raise ValueError("X_re and X_im need the same leading dimension")
+    out = [torch.empty(ncols, dtype=torch.float64, device=X_re.device) for _ in range(4)]
+    _check(lib().jsvd_nrmf_batched(ncols, m, _ptr(X_re), _ptr(X_im), ld, lanes, *[_ptr(o) for o in out],
+                                   _stream(stream)), "jsvd_nrmf_batched")
+    return tuple(out)
 
 
 def evd2_batched_f32(a11, a22, a21_re, a21_im=None, flags=0, out=None, with_lambda=True, with_zp=True,

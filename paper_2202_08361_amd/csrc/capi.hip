@@ -696,6 +696,19 @@ extern "C" int jsvd_dot_scaled_batched(int npairs, int m, const double *Q_re, co
 }
 
 // ---------------------------------------------------------------------------
+// batched widened-exponent Frobenius norms
+extern "C" int jsvd_nrmf_batched(int ncols, int m, const double *X_re, const double *X_im, size_t ld, int lanes,
+                                 double *e2, double *f2, double *e, double *f, void *stream)
+{
+    if (ncols < 0 || m < 0 || lanes < 1 || lanes > 1024 || (lanes & (lanes - 1))) return JSVD_EINVAL;
+    if (ncols == 0) return JSVD_OK;
+    if (!X_re || !e || !f || ld < (size_t)(m > 0 ? m : 1)) return JSVD_EINVAL;
+    if (m > 0 && (size_t)ncols * ld > ((size_t)1 << 40)) return JSVD_EINVAL;
+    HIPCHK(launch_nrmf(ncols, m, X_re, X_im, (long long)ld, lanes, e2, f2, e, f, (hipStream_t)stream));
+    return JSVD_OK;
+}
+
+// ---------------------------------------------------------------------------
 // layout helpers
 extern "C" int jsvd_split(int m, int n, const double *Z, size_t ldz, double *X_re, double *X_im, size_t ldx,
                           void *stream)

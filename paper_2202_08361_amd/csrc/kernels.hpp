@@ -93,6 +93,11 @@ hipError_t launch_dot(int npairs, int m, const double *Qr, const double *Qi, con
                       long long ld, const double *eq, const double *fq, const double *ep, const double *fp,
                       double *zr, double *zi, bool comp, hipStream_t s);
 
+// batched widened-exponent Frobenius norms (nrmf.hip, Alg. rnF): one
+// workgroup per column; lanes a power of two <= 1024
+hipError_t launch_nrmf(int ncols, int m, const double *Xr, const double *Xi, long long ld, int lanes, double *e2,
+                       double *f2, double *e, double *f, hipStream_t s);
+
 // initialisation: M~_0 into *maxbits (zeroed by the caller), then
 // G <- 2^{s_0} A copied into the workspace and V <- I
 template <typename T>

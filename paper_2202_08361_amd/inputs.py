@@ -333,3 +333,32 @@ def split_scale_columns(m: int, n: int, g: np.random.Generator, cplx: bool, shif
     if cplx:
         Ai[:, n // 2:] = np.ldexp(Ai[:, n // 2:], -shift)
     return Ar, Ai
+
+
+# ------------------------------------------------------------------ Frobenius norm inputs
+def random_bit_vector(g: np.random.Generator, m: int, xi: int) -> np.ndarray:
+    """Sect. SM6.4: every element from 64 random bits (each bit 0 or 1 with
+    equal probability), kept when finite with magnitude in [0, 2^xi], then
+    its absolute value."""
+    out = np.empty(0)
+    while out.size < m:
+        b = g.integers(0, 1 << 63, 2 * m, dtype=np.int64).view(np.float64)
+        b = np.abs(b[np.isfinite(b)])
+        out = np.concatenate([out, b[b <= np.ldexp(1.0, xi)]])
+    return out[:m]
+
+
+def wide_columns(m: int, n: int, g: np.random.Generator, cplx: bool = False, zero_frac: float = 0.02):
+    """Columns over the whole double range: sign 2^E U[1, 2), E uniform in
+    [-1074, 1023] per element (subnormals included), a fraction of zeros, and
+    one column in eight entirely zero."""
+    def part():
+        E = g.integers(-1074, 1024, size=(m, n))
+        x = np.ldexp(g.uniform(1.0, 2.0, size=(m, n)), E) * np.where(g.random((m, n)) < 0.5, -1.0, 1.0)
+        x[g.random((m, n)) < zero_frac] = 0.0
+        if n >= 8:
+            x[:, ::8] = 0.0
+        return np.asfortranarray(x)
+    Ar = part()
+    Ai = part() if cplx else None
+    return Ar, Ai

@@ -146,17 +146,6 @@ def test_no_underflow_subnormals(ora):
             assert rel <= (math.ceil(m / s) + math.log2(s) + 3) * EPS, (trial, s, float(rel))
 
 
-def _sm64_vector(g, m, xi):
-    """Sect. SM6.4: every element from 64 random bits, kept when its magnitude
-    is in [0, 2^xi] (and finite), absolute values."""
-    out = np.empty(0)
-    while out.size < m:
-        b = g.integers(0, 1 << 63, 2 * m, dtype=np.int64).view(np.float64)
-        b = np.abs(b[np.isfinite(b)])
-        out = np.concatenate([out, b[b <= math.ldexp(1.0, xi)]])
-    return out[:m]
-
-
 @pytest.mark.parametrize("xi", [0, 1008])
 def test_sm64_vectors(ora, xi):
     """The random-bit vectors of Sect. SM6.4: relative error of ||x|| within
@@ -165,7 +154,7 @@ def test_sm64_vectors(ora, xi):
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 5006 + xi)
     for trial in range(6):
         m = int(g.integers(1000, 20000))
-        x = _sm64_vector(g, m, xi)
+        x = inputs.random_bit_vector(g, m, xi)
         with mpmath.workprec(2400):
             exact = mpmath.sqrt(mpmath.fsum(mpmath.mpf(v) ** 2 for v in sorted(x)))
         if xi == 1008:
