@@ -72,6 +72,39 @@ def trace_summary(db):
     return "\n".join(out)
 
 
+def counters_table(fetch_db, write_db, calib_mib):
+    """Per kernel: the mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of one
+    counter run each, and the HBM bytes per dispatch after scaling each
+    counter by what it reads for the plain device copy of calib_mib MiB."""
+    q = "select kernel_name, value from counters_collection order by dispatch_id"
+    fetch, write = _rocpd_rows(fetch_db, q), _rocpd_rows(write_db, q)
+    moved = calib_mib * 1024.0
+
+    def per_kernel(rows):
+        acc = {}
+        for nm, v in rows:
+            acc.setdefault(nm, []).append(v)
+        return acc
+    fk, wk = per_kernel(fetch), per_kernel(write)
+    cf = [v for nm, vs in fk.items() if "copyBuffer" in nm for v in vs]
+    cw = [v for nm, vs in wk.items() if "copyBuffer" in nm for v in vs]
+    if not cf or not cw:
+        raise SystemExit("no plain copy in the counter databases (run with --calib-copy)")
+    # the calibration copy is the largest plain copy of the run
+    cf, cw = [max(cf)], [max(cw)]
+    f_scale, w_scale = moved / cf[-1], moved / cw[-1]
+    out = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB per dispatch |", "|---|---|---|---|---|"]
+    for nm in sorted(fk, key=lambda n: -sum(fk[n]) * f_scale - sum(wk.get(n, [0.0])) * w_scale):
+        if "copyBuffer" in nm or nm not in wk:
+            continue
+        f = sum(fk[nm]) / len(fk[nm])
+        w = sum(wk[nm]) / len(wk[nm])
+        out.append(f"| `{nm[:100]}` | {len(fk[nm])} | {f:.1f} | {w:.1f} | {(f * f_scale + w * w_scale) * 1024 / 1e6:.3f} |")
+    out.append(f"\nCalibration: the plain device copy of {calib_mib} MiB reads as FETCH_SIZE {cf[-1]:.1f} KiB and "
+               f"WRITE_SIZE {cw[-1]:.1f} KiB; scale factors {f_scale:.4f} and {w_scale:.4f}.")
+    return "\n".join(out)
+
+
 def traffic_from(fetch_db, write_db, calib_mib, r=1 << 26):
     """HBM bytes per launch of the EVD kernels from one FETCH_SIZE and one
     WRITE_SIZE run (KiB per dispatch), each scaled by what the same counter
@@ -366,6 +399,41 @@ def svd_plain(torch, J, inputs, flags, fp32=False):
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
+def cpu_oracle_svd(inputs, sweeps_256=None):
+    """Context: the oracle (sequential C, one host thread) on the SVD
+    workloads: one sweep of the 256 x 256 real SVD (scaled by the sweep count
+    of the GPU run, which the oracle shares bit for bit), and two steps each of
+    the real 8192 x 2048 and complex 4096 x 4096 workloads, extrapolated to one
+    sweep (K steps)."""
+    import oracle
+    res = {}
+    A, _ = inputs.plain_real_256()
+    st = oracle.State(A)
+    st.init()
+    t0 = time.perf_counter()
+    for _ in range(oracle.rr_steps(256)):
+        st.step()
+    sw = time.perf_counter() - t0
+    res["svd_real256_sweep_s"] = round(sw, 3)
+    if sweeps_256:
+        res["svd_real256_s_extrapolated"] = round(sw * sweeps_256, 2)
+    for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
+        g = inputs.rng(inputs.CFG_PLAIN_LARGE, 77 + int(c))
+        Ar, Ai = inputs.random_columns(m, n, g, c)
+        st = oracle.State(Ar, Ai)
+        st.init()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            st.step()
+        dt = (time.perf_counter() - t0) / 2
+        K = n - 1 if n % 2 == 0 else n
+        res[f"step_{'c' if c else 'r'}{m}x{n}_s"] = round(dt, 4)
+        res[f"sweep_{'c' if c else 'r'}{m}x{n}_s_extrapolated"] = round(dt * K, 1)
+    res["cores"] = 1
+    res["kind"] = "oracle"
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -387,12 +455,20 @@ def main():
                          "(a reference for hardware byte counters)")
     ap.add_argument("--trace-summary", metavar="DB",
                     help="print the kernel table of a rocprofv3 --kernel-trace --stats database and exit")
+    ap.add_argument("--only", default="",
+                    help="comma-separated name prefixes: run only the secondary lines whose names start with one")
+    ap.add_argument("--counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="print per-kernel HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE databases of runs "
+                         "made with --calib-copy, and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="derive the EVD kernels' HBM bytes per launch from FETCH_SIZE / WRITE_SIZE "
                          "databases of runs made with --calib-copy, write profiles/evd2_traffic.json, exit")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
+        return
+    if args.counters:
+        print(counters_table(args.counters[0], args.counters[1], args.calib_copy or 512))
         return
     if args.traffic_from:
         rec, md = traffic_from(args.traffic_from[0], args.traffic_from[1], args.calib_copy or 512)
@@ -466,54 +542,48 @@ def main():
     torch.cuda.empty_cache()
     extra = {}
     if not args.no_extra:
-        log(f"[bench] single precision batched EVD, r = 2^{args.log2r}")
-        extra["evd_f32"] = evd_f32(torch, J, inputs, r, K, W)
-        log(f"[bench]   {extra['evd_f32']}")
-        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
-            log(f"[bench] Jacobi step {m}x{n} {'complex' if c else 'real'}")
-            extra[f"step_{'c' if c else 'r'}{m}x{n}"] = step_roofline(torch, J, inputs, m, n, c)
-            log(f"[bench]   {extra[f'step_{chr(99) if c else chr(114)}{m}x{n}']}")
-        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
-            nm = f"step_{'c' if c else 'r'}{m}x{n}_compensated"
-            log(f"[bench] {nm}")
-            extra[nm] = step_roofline(torch, J, inputs, m, n, c, flags=J.COMPENSATED)
-            log(f"[bench]   {extra[nm]}")
-        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
-            nm = f"step_{'c' if c else 'r'}{m}x{n}_f32"
-            log(f"[bench] {nm}")
-            extra[nm] = step_roofline(torch, J, inputs, m, n, c, fp32=True)
-            log(f"[bench]   {extra[nm]}")
-        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
-            nm = f"nrmf_{'c' if c else 'r'}{m}x{n}"
-            log(f"[bench] {nm}: Alg. rnF norms of every column")
-            extra[nm] = nrmf_rate(torch, J, inputs, m, n, c)
-            log(f"[bench]   {extra[nm]}")
+        prefixes = [x for x in args.only.split(",") if x]
+        tasks = [("evd_f32", lambda: evd_f32(torch, J, inputs, r, K, W))]
+        big = ((8192, 2048, False), (4096, 4096, True))
+
+        def tag(m, n, c):
+            return f"{'c' if c else 'r'}{m}x{n}"
+        for (m, n, c) in big:
+            tasks.append((f"step_{tag(m, n, c)}", lambda m=m, n=n, c=c: step_roofline(torch, J, inputs, m, n, c)))
+        for (m, n, c) in big:
+            tasks.append((f"step_{tag(m, n, c)}_compensated",
+                          lambda m=m, n=n, c=c: step_roofline(torch, J, inputs, m, n, c, flags=J.COMPENSATED)))
+        for (m, n, c) in big:
+            tasks.append((f"step_{tag(m, n, c)}_f32",
+                          lambda m=m, n=n, c=c: step_roofline(torch, J, inputs, m, n, c, fp32=True)))
+        for (m, n, c) in big:
+            tasks.append((f"nrmf_{tag(m, n, c)}", lambda m=m, n=n, c=c: nrmf_rate(torch, J, inputs, m, n, c)))
         for nm, fl in (("svd_real256_permute_f32", 0), ("svd_real256_nopermute_f32", J.NO_PERMUTE)):
-            log(f"[bench] {nm}")
-            extra[nm] = svd_plain(torch, J, inputs, fl, fp32=True)
-            log(f"[bench]   {extra[nm]}")
+            tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl, fp32=True)))
         for nm, fl in (("svd_real256_permute", 0), ("svd_real256_nopermute", J.NO_PERMUTE),
                        ("svd_real256_permute_compensated", J.COMPENSATED),
                        ("svd_real256_nopermute_compensated", J.NO_PERMUTE | J.COMPENSATED)):
-            log(f"[bench] {nm}")
-            extra[nm] = svd_plain(torch, J, inputs, fl)
-            log(f"[bench]   {extra[nm]}")
-        for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
+            tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl)))
+        for (m, n, c) in big:
             for fp32 in (False, True):
-                nm = f"sweep_{'c' if c else 'r'}{m}x{n}" + ("_f32" if fp32 else "")
-                log(f"[bench] {nm}")
-                extra[nm] = sweep_time(torch, J, inputs, m, n, c, fp32=fp32)
-                log(f"[bench]   {extra[nm]}")
+                tasks.append((f"sweep_{tag(m, n, c)}" + ("_f32" if fp32 else ""),
+                              lambda m=m, n=n, c=c, fp32=fp32: sweep_time(torch, J, inputs, m, n, c, fp32=fp32)))
         if not args.no_batched:
             for nm, fl in (("batched_permute", 0), ("batched_nopermute", J.NO_PERMUTE)):
-                log(f"[bench] {nm}: first {args.batched} matrices of the 10,000-matrix workload")
-                extra[nm] = batched_vs_plain(torch, J, inputs, args.batched, args.batched_plain, fl)
-                log(f"[bench]   {extra[nm]}")
+                tasks.append((nm, lambda fl=fl: batched_vs_plain(torch, J, inputs, args.batched, args.batched_plain,
+                                                                 fl)))
         if not args.no_serve:
-            log(f"[bench] serving: Poisson {args.serve_rate}/s for {args.serve_seconds} s")
-            extra["serving"] = serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
-                                           args.serve_pool, J.NO_PERMUTE)
-            log(f"[bench]   {extra['serving']}")
+            tasks.append(("serving", lambda: serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
+                                                         args.serve_pool, J.NO_PERMUTE)))
+        if not args.no_cpu:
+            tasks.append(("cpu_oracle_svd", lambda: cpu_oracle_svd(
+                inputs, extra.get("svd_real256_permute", {}).get("sweeps"))))
+        for nm, fn in tasks:
+            if prefixes and not any(nm.startswith(x) for x in prefixes):
+                continue
+            log(f"[bench] {nm}")
+            extra[nm] = fn()
+            log(f"[bench]   {extra[nm]}")
     line = {
         "metric": "batched 2x2 EVDs/s",
         "value": round(value, 1),

@@ -210,3 +210,30 @@ def test_sweep_graph_bitwise(ora, m, n, cplx):
         _check_state(ost, st.save(), f"sweep {sweep} m={m} n={n} cplx={cplx}")
         assert q["last_sweep_T"] == T and q["last_sweep_swaps"] == SW
         assert q["steps"] == ost.k
+
+
+def test_streams_identical(ora):
+    """The SVD and single steps on a side stream give the bits of the default
+    stream (and of the oracle): the library runs on the stream it is given."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 900)
+    sig = inputs.sigma_logspace(40, 1e-5)
+    Ar, Ai = inputs.svd_matrix(700, 40, sig, g, cplx=True)
+    ro = ora.gesvj(Ar, Ai)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        dAr, dAi = J().to_device_fortran(Ar), J().to_device_fortran(Ai)
+        rg = J().gesvj(dAr, dAi, stream=side)
+        side.synchronize()
+    _check_svd(ro, rg)
+    st = J().State(700, 40, True)
+    ost = ora.State(Ar, Ai)
+    ost.init()
+    with torch.cuda.stream(side):
+        st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai), stream=side)
+        for _ in range(5):
+            st.step(stream=side)
+            ost.step()
+        side.synchronize()
+        sv = st.save(stream=side)
+        side.synchronize()
+    _check_state(ost, sv, "side stream")
