@@ -158,7 +158,12 @@ int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_
  * G instead (the smaller column orthogonalised against the larger, which
  * stays or moves to the first place), while V still takes the pair's
  * rotation; JSVD_NO_GS turns this off.  Step index, M~ and the counters stay
- * on the device; launches only. */
+ * on the device; launches only.  For columns of more than 256 rows (and no
+ * forced workgroup size) the V rotations of up to 32 consecutive steps are
+ * applied together (a row of V never mixes with another row, so the result
+ * is the same bit for bit): V is brought up to date whenever it is read
+ * (jsvd_state_save, jsvd_state_finalize, the end of jsvd_sweep and of
+ * jsvd_gesvj) or the fused small-column kernel takes over. */
 int jsvd_step(jsvd_state st, void *stream);
 
 /* K steps followed by the end-of-sweep bookkeeping; launches only. */

@@ -112,7 +112,7 @@ extern "C" int jsvd_evd2_batched_f32(size_t r, const float *a11, const float *a2
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct StateLayout {
-    long long ldg, ldv;
+    long long ldg, ldv, vstride;
     size_t oG, oV, oE, oF, oR, oS, oM, oP, total;
 };
 
@@ -132,7 +132,9 @@ static StateLayout state_layout(int m, int n, int cplx, size_t es)
     L.oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
     L.oS = off; off = align_up(off + sizeof(DevScalars));
     L.oM = off; off = align_up(off + sizeof(unsigned long long));
-    L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)((n + 1) / 2 + 1));
+    // the outcome log: kVlogSteps slots of the step's pair outcomes
+    L.vstride = round_up((long long)(n + 1) / 2, 4LL);
+    L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)L.vstride * kVlogSteps);
     L.total = off;
     return L;
 }
@@ -199,6 +201,11 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
         return JSVD_ENOMEM;
     }
     st->mem_bytes = L.total;
+    if (vacc_prepare(st->cplx, fp32) != hipSuccess) {
+        (void)hipFree(st->mem);
+        delete st;
+        return JSVD_EDEVICE;
+    }
     if (hipHostMalloc((void **)&st->host, 512, hipHostMallocDefault) != hipSuccess) {
         (void)hipFree(st->mem);
         delete st;
@@ -213,7 +220,10 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
     st->sc = (DevScalars *)(b + L.oS);
     st->rank = (int *)(b + L.oR);
     st->maxbits = (unsigned long long *)(b + L.oM);
-    st->prm = (PairParam *)(b + L.oP);
+    st->vlog = (PairParam *)(b + L.oP);
+    st->vlog_stride = L.vstride;
+    st->vlog_n = 0;
+    st->v_layout = V_EITHER;
     *out = st;
     return JSVD_OK;
 }
@@ -285,6 +295,9 @@ static int load_async_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg,
     HIPCHK(launch_zero_u64(st->maxbits, s));
     HIPCHK(launch_maxabs(d, G_re, G_im, (long long)ldg, st->maxbits, s));
     HIPCHK(launch_init_scale(d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
+    // V = I: the same in either layout, nothing logged
+    st->vlog_n = 0;
+    st->v_layout = V_EITHER;
     return JSVD_OK;
 }
 
@@ -362,18 +375,58 @@ static int state_threads(jsvd_state st)
 }
 
 // one step: for long columns (and no forced workgroup size) the G kernel and
-// the V kernel, otherwise the fused one-workgroup-per-pair kernel
+// the fold, with V updated from the outcome log (deferred), otherwise the
+// fused one-workgroup-per-pair kernel
 static bool uses_gpair(jsvd_state st)
 {
-    return st->threads == 0 && gpair_rows(st->m, st->cplx, st->fp32 != 0) != 0 && st->m > 256;
+    return st->threads == 0 && gpair_rows(st->m, st->cplx, st->fp32 != 0) != 0 && st->m > 256 &&
+           vacc_supported(st->n, st->cplx, st->fp32 != 0);
 }
 
+// apply the logged steps to V (row-major while anything is logged)
+template <typename T>
+static hipError_t flush_vlog_t(jsvd_state st, hipStream_t s)
+{
+    if (st->vlog_n == 0) return hipSuccess;
+    const int nsteps = st->vlog_n;
+    st->vlog_n = 0;
+    return launch_vacc(desc_of<T>(st), st->vlog, st->vlog_stride, nsteps, s);
+}
+
+static hipError_t flush_vlog(jsvd_state st, hipStream_t s)
+{
+    return st->fp32 ? flush_vlog_t<float>(st, s) : flush_vlog_t<double>(st, s);
+}
+
+// V in the layout `want` (V_COLS or V_ROWS) with every logged step applied
+// once it is column-major
+static hipError_t set_v_layout(jsvd_state st, int want, hipStream_t s)
+{
+    if (st->v_layout == V_EITHER || st->v_layout == want) {
+        st->v_layout = want;
+        return want == V_COLS ? flush_vlog(st, s) : hipSuccess;
+    }
+    hipError_t e = flush_vlog(st, s);
+    if (e != hipSuccess) return e;
+    e = st->fp32 ? launch_vtrans(st->df, s) : launch_vtrans(st->d, s);
+    if (e != hipSuccess) return e;
+    st->v_layout = want;
+    return hipSuccess;
+}
+
+static int path_layout(jsvd_state st) { return uses_gpair(st) ? V_ROWS : V_COLS; }
+
+// one step on a state whose V is in the path's layout: on the large-column
+// path the outcomes go to the next log slot and a full log is applied to V
 template <typename T>
 static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s)
 {
     const SvdDescT<T> &d = desc_of<T>(st);
-    if (uses_gpair(st)) return launch_gpair(d, st->prm, s);
-    return launch_step(d, state_threads(st), s);
+    if (!uses_gpair(st)) return launch_step(d, state_threads(st), s);
+    const hipError_t e = launch_gpair(d, st->vlog + (size_t)st->vlog_n * st->vlog_stride, s);
+    if (e != hipSuccess) return e;
+    if (++st->vlog_n == kVlogSteps) return flush_vlog_t<T>(st, s);
+    return hipSuccess;
 }
 
 static hipError_t launch_one_step(jsvd_state st, hipStream_t s)
@@ -384,18 +437,23 @@ static hipError_t launch_one_step(jsvd_state st, hipStream_t s)
 extern "C" int jsvd_step(jsvd_state st, void *stream)
 {
     if (!st) return JSVD_EINVAL;
-    HIPCHK(launch_one_step(st, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(set_v_layout(st, path_layout(st), s));
+    HIPCHK(launch_one_step(st, s));
     return JSVD_OK;
 }
 
 static int sweep_steps(int n) { return n + (n & 1) - 1; }
 
-// Capture the K steps of a sweep and the end-of-sweep bookkeeping.
+// Capture the K steps of a sweep, the update of V from the steps still
+// logged, and the end-of-sweep bookkeeping.  The log is empty when the
+// capture starts and when the graph ends.
 static int capture_sweep(jsvd_state st, hipStream_t cs)
 {
     const int K = sweep_steps(st->n);
     for (int k = 0; k < K; ++k)
         if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
+    if (flush_vlog(st, cs) != hipSuccess) return JSVD_EDEVICE;
     return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
 }
 
@@ -420,6 +478,7 @@ static int build_graph(jsvd_state st)
             rc = JSVD_EDEVICE;
         } else {
             rc = capture_sweep(st, cs);
+            st->vlog_n = 0;
             // a failed capture still has to be ended
             if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == JSVD_OK) rc = JSVD_EDEVICE;
         }
@@ -441,6 +500,9 @@ static int build_graph(jsvd_state st)
 extern "C" int jsvd_sweep(jsvd_state st, void *stream)
 {
     if (!st) return JSVD_EINVAL;
+    // V in the path's layout and the log empty, as the captured sweep expects
+    HIPCHK(set_v_layout(st, path_layout(st), (hipStream_t)stream));
+    HIPCHK(flush_vlog(st, (hipStream_t)stream));
     const int rc = build_graph(st);
     if (rc != JSVD_OK) return rc;
     HIPCHK(hipGraphLaunch(st->graph, (hipStream_t)stream));
@@ -463,6 +525,7 @@ static int finish_async_t(jsvd_state st, bool converged, T *U_re, T *U_im, size_
 {
     if (!is_prec<T>(st)) return JSVD_EINVAL;
     const SvdDescT<T> &d = desc_of<T>(st);
+    HIPCHK(set_v_layout(st, V_COLS, s));
     if (converged) {
         HIPCHK(launch_colnorms_raw(d, s));
         HIPCHK(launch_rank(d, st->rank, s));
@@ -529,6 +592,7 @@ static int save_t(jsvd_state st, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im,
         if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, (const T *)d.Gi, d.ldg, G_im, (long long)ldg, s));
     }
     if (V_re) {
+        HIPCHK(set_v_layout(st, V_COLS, s));
         HIPCHK(launch_copy2d(d.n, d.n, (const T *)d.Vr, d.ldv, V_re, (long long)ldv, s));
         if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, (const T *)d.Vi, d.ldv, V_im, (long long)ldv, s));
     }
@@ -571,6 +635,9 @@ static int restore_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, co
     if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, G_im, (long long)ldg, d.Gi, d.ldg, s));
     HIPCHK(launch_copy2d(d.n, d.n, V_re, (long long)ldv, d.Vr, d.ldv, s));
     if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, V_im, (long long)ldv, d.Vi, d.ldv, s));
+    // the restored V replaces the logged steps too
+    st->vlog_n = 0;
+    st->v_layout = V_COLS;
     DevScalars h;
     memset(&h, 0, sizeof(h));
     h.Mt_bits = dbits(Mt);

@@ -1,18 +1,23 @@
 // gstep.hip -- the parallel Jacobi step for large columns (arXiv:2202.08361,
 // Alg. zvjsvd phases; the same arithmetic, bit for bit, as step.hip).
 //
-// Two kernels per step:
+// Per step:
 //
 // * gpair_kernel: one workgroup per pivot pair.  The G column pair is read
 //   once into registers; norms, scaled dot-product (Alg. zdpscl),
 //   convergence test (Alg. cvg), Gram matrix (Alg. Gram), 2x2 EVD
 //   (Listing 1) and rotation (Alg. zjrot) run on it there, and it is written
 //   once.  Two workgroups per compute unit overlap one pair's reductions and
-//   EVD with the other's memory traffic.
-// * vrot_kernel: a fully occupied streaming kernel that applies the step's
-//   rotations and swaps to the V column pairs; its first workgroup also folds
-//   the step into the device scalars (M~, counts, s, k) from the per-pair
-//   outcomes, so no workgroup of either kernel needs an atomic.
+//   EVD with the other's memory traffic.  The pair's outcome (rotation,
+//   permutation, max-norm) goes to the step's slot of an outcome log.
+// * fold_kernel: one workgroup folds the step into the device scalars (M~,
+//   counts, s, k) from the outcomes, so no workgroup needs an atomic.
+//
+// V is not touched per step.  Its rows never mix, so the rotations of up to
+// a log's worth of consecutive steps are applied to it in one pass
+// (vacc_kernel), on a row-major V staged row by row in LDS: every element
+// gets the same operations in the same order as with a per-step update,
+// while V crosses HBM once per flush instead of once per step.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -50,7 +55,17 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
     __shared__ T red[(COMP ? 12 : 6) * W];
     __shared__ T mxs[4 * (W / 64)];
     DevScalars *sc = d.sc;
-    if (*(volatile int *)&sc->stop) return;
+    if (*(volatile int *)&sc->stop) {
+        // a stopped iteration: the step does nothing, and its log slot says so
+        if (threadIdx.x == 0) {
+            PairParam z;
+            z.c = 1.0;
+            z.C = z.S = z.mx = 0.0;
+            z.p = z.q = z.flag = z.pad = 0;
+            prm[blockIdx.x] = z;
+        }
+        return;
+    }
     const long long k = *(volatile long long *)&sc->k;
     const T Mt = (T)bits2d(*(volatile unsigned long long *)&sc->Mt_bits);
     const int m = d.m, n = d.n;
@@ -148,60 +163,6 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
 }
 
 
-// rotation or swap of one V column pair, rows of row block blockIdx.y (the
-// parameters, kept as doubles in prm, convert back to T exactly)
-template <bool CPLX, typename T>
-__device__ __forceinline__ void vrot_pair(const SvdDescT<T> &d, const PairParam &pp)
-{
-    const int n = d.n;
-    const int i0 = blockIdx.y * 512 + threadIdx.x;
-    T *const Vpr = d.Vr + (size_t)pp.p * d.ldv;
-    T *const Vqr = d.Vr + (size_t)pp.q * d.ldv;
-    T *const Vpi = CPLX ? d.Vi + (size_t)pp.p * d.ldv : nullptr;
-    T *const Vqi = CPLX ? d.Vi + (size_t)pp.q * d.ldv : nullptr;
-    const bool swap = (pp.flag & 2) != 0;
-    T *const Ep_r = swap ? Vqr : Vpr;
-    T *const Eq_r = swap ? Vpr : Vqr;
-    T *const Ep_i = swap ? Vqi : Vpi;
-    T *const Eq_i = swap ? Vpi : Vqi;
-    const T c = (T)pp.c, C = (T)pp.C, S = (T)pp.S;
-    T pr[2], qr[2], pi[2] = {T(0), T(0)}, qi[2] = {T(0), T(0)};
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int i = i0 + 256 * u;
-        const bool in = i < n;
-        pr[u] = in ? Vpr[i] : T(0);
-        qr[u] = in ? Vqr[i] : T(0);
-        if (CPLX) {
-            pi[u] = in ? Vpi[i] : T(0);
-            qi[u] = in ? Vqi[i] : T(0);
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-        const int i = i0 + 256 * u;
-        if (i >= n) continue;
-        if (pp.flag & 1) {
-            if (CPLX) {
-                Ep_r[i] = fma(qr[u], C, fma(-qi[u], S, pr[u])) * c;
-                Ep_i[i] = fma(qr[u], S, fma(qi[u], C, pi[u])) * c;
-                Eq_r[i] = fma(pr[u], -C, fma(-pi[u], S, qr[u])) * c;
-                Eq_i[i] = fma(pr[u], S, fma(pi[u], -C, qi[u])) * c;
-            } else {
-                Ep_r[i] = fma(qr[u], C, pr[u]) * c;
-                Eq_r[i] = fma(pr[u], -C, qr[u]) * c;
-            }
-        } else {
-            Vpr[i] = qr[u];
-            Vqr[i] = pr[u];
-            if (CPLX) {
-                Vpi[i] = qi[u];
-                Vqi[i] = pi[u];
-            }
-        }
-    }
-}
-
 // End of step (Alg. zvjsvd): from the outcomes of all pairs, M~_{k+1} =
 // max(2^{s_[k]} M~_k, M) with M the max-norm of the rotated columns, the
 // counts of rotations and of swaps, the scaling exponent and the step index.
@@ -267,17 +228,147 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
     }
 }
 
-// V column pairs: rotate (flag & 1) and/or swap (flag & 2) with the step's
-// parameters; 2 rows per thread, grid (pairs, row blocks).  Workgroup (0, 0)
-// also folds the step into the device scalars (every G column of the step is
-// final once this kernel runs).
-template <bool CPLX, typename T>
-__global__ __launch_bounds__(256) void vrot_kernel(SvdDescT<T> d, const PairParam *prm)
+// the fold of one step as a kernel of its own: the G kernel's workgroups do
+// not see each other's outcomes before that launch has ended
+template <typename T>
+__global__ __launch_bounds__(256) void fold_kernel(SvdDescT<T> d, const PairParam *prm)
 {
     if (*(volatile int *)&d.sc->stop) return;
-    const PairParam pp = prm[blockIdx.x];
-    if (pp.flag != 0) vrot_pair<CPLX>(d, pp);
-    if (blockIdx.x == 0 && blockIdx.y == 0) fold_step(d, prm, (d.n + (d.n & 1)) / 2);
+    fold_step(d, prm, (d.n + (d.n & 1)) / 2);
+}
+
+// outcomes of this thread's pairs l = t + W u in one step (only what V needs)
+template <int PPT, typename T>
+struct VaccPairs {
+    T c[PPT], C[PPT], S[PPT];
+    int p[PPT], q[PPT], f[PPT];
+};
+
+template <int PPT, typename T>
+__device__ __forceinline__ void vacc_load(VaccPairs<PPT, T> &o, const PairParam *pl, int np, int t, int W, bool live)
+{
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const int l = t + W * u;
+        o.f[u] = 0;
+        if (live && l < np) {
+            const PairParam P = pl[l];
+            o.f[u] = P.flag;
+            o.p[u] = P.p;
+            o.q[u] = P.q;
+            o.c[u] = (T)P.c;
+            o.C[u] = (T)P.C;
+            o.S[u] = (T)P.S;
+        }
+    }
+}
+
+// Deferred V update: nsteps logged steps (step j's outcomes at plog + j
+// stride) applied to B rows of the row-major V (row i at Vr + i ldv) per
+// workgroup, staged in LDS as sm[(plane B + r) n + column].  Within a step
+// the pairs are disjoint, so each thread updates its pairs' two columns in
+// all staged rows, with the per-element formulas of the column update: a
+// rotation (flag & 1; the swap of the permutation, flag & 2, exchanges the
+// destination columns), or a plain exchange.  One barrier per step.  The
+// next step's outcomes are loaded while the current step is applied.
+template <bool CPLX, int PPT, typename T>
+__global__ __launch_bounds__(1024) void vacc_kernel(SvdDescT<T> d, const PairParam *plog, long long stride,
+                                                    int nsteps, int B)
+{
+    if (*(volatile int *)&d.sc->stop) return;
+    extern __shared__ __align__(16) unsigned char vacc_lds[];
+    T *const sm = (T *)vacc_lds;
+    const int n = d.n, t = threadIdx.x, W = blockDim.x;
+    const int np = (n + 1) / 2;
+    const int row0 = blockIdx.x * B;
+    const int nb = min(B, n - row0);
+    for (int r = 0; r < nb; ++r) {
+        const T *vr = d.Vr + (size_t)(row0 + r) * d.ldv;
+        const T *vi = CPLX ? d.Vi + (size_t)(row0 + r) * d.ldv : nullptr;
+        for (int j = t; j < n; j += W) {
+            sm[r * n + j] = vr[j];
+            if (CPLX) sm[(B + r) * n + j] = vi[j];
+        }
+    }
+    VaccPairs<PPT, T> cur, nxt;
+    vacc_load<PPT, T>(cur, plog, np, t, W, true);
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        vacc_load<PPT, T>(nxt, plog + (size_t)(s + 1) * stride, np, t, W, s + 1 < nsteps);
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const int f = cur.f[u];
+            if (f == 0) continue;
+            const int p = cur.p[u], q = cur.q[u];
+            const int ep = (f & 2) ? q : p, eq = (f & 2) ? p : q;
+            const T c = cur.c[u], C = cur.C[u], S = cur.S[u];
+            for (int r = 0; r < nb; ++r) {
+                T *const R = sm + r * n;
+                T *const I = sm + (B + r) * n;
+                const T pr = R[p], qr = R[q];
+                if (CPLX) {
+                    const T pi = I[p], qi = I[q];
+                    if (f & 1) {
+                        R[ep] = fma(qr, C, fma(-qi, S, pr)) * c;
+                        I[ep] = fma(qr, S, fma(qi, C, pi)) * c;
+                        R[eq] = fma(pr, -C, fma(-pi, S, qr)) * c;
+                        I[eq] = fma(pr, S, fma(pi, -C, qi)) * c;
+                    } else {
+                        R[p] = qr;
+                        R[q] = pr;
+                        I[p] = qi;
+                        I[q] = pi;
+                    }
+                } else if (f & 1) {
+                    R[ep] = fma(qr, C, pr) * c;
+                    R[eq] = fma(pr, -C, qr) * c;
+                } else {
+                    R[p] = qr;
+                    R[q] = pr;
+                }
+            }
+        }
+        lds_barrier();
+        cur = nxt;
+    }
+    for (int r = 0; r < nb; ++r) {
+        T *const vr = d.Vr + (size_t)(row0 + r) * d.ldv;
+        T *const vi = CPLX ? d.Vi + (size_t)(row0 + r) * d.ldv : nullptr;
+        for (int j = t; j < n; j += W) {
+            vr[j] = sm[r * n + j];
+            if (CPLX) vi[j] = sm[(B + r) * n + j];
+        }
+    }
+}
+
+// In-place transpose of the n x n matrix V (each plane): switches V between
+// the column-major layout (the fused step kernel, the caller) and the
+// row-major one of the deferred update.  32 x 32 tiles; workgroup (bj, bi,
+// plane) with bi <= bj exchanges tile (bi, bj) with the transpose of tile
+// (bj, bi), a diagonal tile with its own transpose.
+template <typename T>
+__global__ __launch_bounds__(256) void vtrans_kernel(T *Vr, T *Vi, int n, long long ld)
+{
+    const int bi = blockIdx.y, bj = blockIdx.x;
+    if (bi > bj) return;
+    T *const P = blockIdx.z ? Vi : Vr;
+    __shared__ T ta[32][33], tb[32][33];
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    // ta[c][r] = X(32 bi + r, 32 bj + c), tb[c][r] = X(32 bj + r, 32 bi + c); X(i, j) at P[i + j ld]
+    for (int c = ty; c < 32; c += 8) {
+        const int i = bi * 32 + tx, j = bj * 32 + c;
+        if (i < n && j < n) ta[c][tx] = P[i + (size_t)j * ld];
+        const int i2 = bj * 32 + tx, j2 = bi * 32 + c;
+        if (bi != bj && i2 < n && j2 < n) tb[c][tx] = P[i2 + (size_t)j2 * ld];
+    }
+    __syncthreads();
+    // X'(32 bj + r, 32 bi + c) = X(32 bi + c, 32 bj + r) = ta[r][c], and the mirror from tb
+    for (int c = ty; c < 32; c += 8) {
+        const int i = bj * 32 + tx, j = bi * 32 + c;
+        if (i < n && j < n) P[i + (size_t)j * ld] = ta[tx][c];
+        const int i2 = bi * 32 + tx, j2 = bj * 32 + c;
+        if (bi != bj && i2 < n && j2 < n) P[i2 + (size_t)j2 * ld] = tb[tx][c];
+    }
 }
 
 // rows per thread of the G kernel for m rows (0 = not supported): a column
@@ -322,30 +413,105 @@ static hipError_t launch_gpair_t(const SvdDescT<T> &d, PairParam *prm, int R, hi
 }
 
 template <typename T>
-hipError_t launch_vrot(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s)
-{
-    const int npairs = (d.n + (d.n & 1)) / 2;
-    dim3 vgrid(npairs, (d.n + 511) / 512);
-    if (d.cplx)
-        hipLaunchKernelGGL((vrot_kernel<true, T>), vgrid, dim3(256), 0, s, d, prm);
-    else
-        hipLaunchKernelGGL((vrot_kernel<false, T>), vgrid, dim3(256), 0, s, d, prm);
-    return hipGetLastError();
-}
-
-template <typename T>
 hipError_t launch_gpair(const SvdDescT<T> &d, PairParam *prm, hipStream_t s)
 {
     const int R = gpair_rows(d.m, d.cplx, sizeof(T) == sizeof(float));
     if (R == 0) return hipErrorInvalidValue;
     const hipError_t e = d.cplx ? launch_gpair_t<true>(d, prm, R, s) : launch_gpair_t<false>(d, prm, R, s);
     if (e != hipSuccess) return e;
-    return launch_vrot(d, prm, s);
+    hipLaunchKernelGGL((fold_kernel<T>), dim3(1), dim3(256), 0, s, d, prm);
+    return hipGetLastError();
 }
 
-template hipError_t launch_vrot<double>(const SvdDescT<double> &, const PairParam *, hipStream_t);
-template hipError_t launch_vrot<float>(const SvdDescT<float> &, const PairParam *, hipStream_t);
+// the LDS the deferred update may take (more than the default 64 KiB needs
+// the kernel attribute, set by vacc_prepare on the current device)
+constexpr int kVaccMaxLds = 128 << 10;
+
+// rows of V per workgroup of the deferred update: 64 KiB of LDS (two
+// workgroups per compute unit) when that holds at least two rows, else
+// 128 KiB; 0 when a row does not fit
+static int vacc_rows(int n, int cplx, size_t es)
+{
+    const size_t row = es * (size_t)n * (cplx ? 2 : 1);
+    int B = (int)((size_t)(64 << 10) / row);
+    if (B < 2) B = (int)((size_t)kVaccMaxLds / row);
+    return B < n ? B : n;
+}
+
+int vacc_supported(int n, int cplx, bool fp32)
+{
+    return vacc_rows(n, cplx, fp32 ? sizeof(float) : sizeof(double)) >= 1;
+}
+
+template <bool CPLX, int PPT, typename T>
+static hipError_t vacc_allow_lds()
+{
+    return hipFuncSetAttribute((const void *)vacc_kernel<CPLX, PPT, T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kVaccMaxLds);
+}
+
+template <bool CPLX, typename T>
+static hipError_t vacc_prepare_t()
+{
+    hipError_t e = vacc_allow_lds<CPLX, 1, T>();
+    if (e == hipSuccess) e = vacc_allow_lds<CPLX, 2, T>();
+    if (e == hipSuccess) e = vacc_allow_lds<CPLX, 4, T>();
+    if constexpr (!CPLX && sizeof(T) == sizeof(float))
+        if (e == hipSuccess) e = vacc_allow_lds<CPLX, 8, T>();
+    return e;
+}
+
+hipError_t vacc_prepare(int cplx, bool fp32)
+{
+    if (fp32) return cplx ? vacc_prepare_t<true, float>() : vacc_prepare_t<false, float>();
+    return cplx ? vacc_prepare_t<true, double>() : vacc_prepare_t<false, double>();
+}
+
+template <bool CPLX, int PPT, typename T>
+static hipError_t launch_vacc_k(const SvdDescT<T> &d, const PairParam *plog, long long stride, int nsteps, int B,
+                                int W, hipStream_t s)
+{
+    const size_t lds = sizeof(T) * (size_t)B * d.n * (CPLX ? 2 : 1);
+    if (lds > (size_t)kVaccMaxLds) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((vacc_kernel<CPLX, PPT, T>), dim3((d.n + B - 1) / B), dim3(W), lds, s, d, plog, stride, nsteps,
+                       B);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vacc(const SvdDescT<T> &d, const PairParam *plog, long long stride, int nsteps, hipStream_t s)
+{
+    if (nsteps <= 0) return hipSuccess;
+    const int B = vacc_rows(d.n, d.cplx, sizeof(T));
+    if (B < 1) return hipErrorInvalidValue;
+    const int np = (d.n + 1) / 2;
+    const int W = np >= 1024 ? 1024 : ((np + 63) / 64) * 64;
+    const int ppt = (np + W - 1) / W;
+#define JSVD_VA(P)                                                                                                 \
+    if (ppt <= P)                                                                                                  \
+        return d.cplx ? launch_vacc_k<true, P, T>(d, plog, stride, nsteps, B, W, s)                                \
+                      : launch_vacc_k<false, P, T>(d, plog, stride, nsteps, B, W, s);
+    JSVD_VA(1) JSVD_VA(2) JSVD_VA(4)
+#undef JSVD_VA
+    // more than 4096 pairs: real single precision columns only (n <= m <= 16384)
+    if constexpr (sizeof(T) == sizeof(float))
+        if (ppt <= 8 && !d.cplx) return launch_vacc_k<false, 8, T>(d, plog, stride, nsteps, B, W, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_vtrans(const SvdDescT<T> &d, hipStream_t s)
+{
+    const int nt = (d.n + 31) / 32;
+    hipLaunchKernelGGL((vtrans_kernel<T>), dim3(nt, nt, d.cplx ? 2 : 1), dim3(256), 0, s, d.Vr, d.Vi, d.n, d.ldv);
+    return hipGetLastError();
+}
+
 template hipError_t launch_gpair<double>(const SvdDescT<double> &, PairParam *, hipStream_t);
 template hipError_t launch_gpair<float>(const SvdDescT<float> &, PairParam *, hipStream_t);
+template hipError_t launch_vacc<double>(const SvdDescT<double> &, const PairParam *, long long, int, hipStream_t);
+template hipError_t launch_vacc<float>(const SvdDescT<float> &, const PairParam *, long long, int, hipStream_t);
+template hipError_t launch_vtrans<double>(const SvdDescT<double> &, hipStream_t);
+template hipError_t launch_vtrans<float>(const SvdDescT<float> &, hipStream_t);
 
 } // namespace jsvd

@@ -66,8 +66,8 @@ struct SvdDescT {
 using SvdDesc = SvdDescT<double>;
 using SvdDescF = SvdDescT<float>;
 
-// outcome of one pivot pair, written by the G kernels for the V kernel and
-// for the end-of-step fold
+// outcome of one pivot pair, written by the G kernels for the end-of-step
+// fold and the (deferred) V update
 struct PairParam {
     double c, C, S;   // cos phi, e^{i alpha} tan phi
     double mx;        // max |component| of the rotated G columns (0 if not rotated)
@@ -78,13 +78,20 @@ struct PairParam {
 };
 
 // step for large columns (gstep.hip): rows per thread of the G kernel for m
-// (0 = not supported); the V kernel (applies the rotations in prm and folds
-// the step into the device scalars); the G kernel followed by the V kernel
+// (0 = not supported); one step on G (the G kernel, its outcomes into prm,
+// then the fold into the device scalars; V untouched); the deferred V
+// update applying nsteps logged steps (step j's outcomes at plog + j stride)
+// to the row-major V; the in-place transpose of V between its column-major
+// and row-major layouts
 int gpair_rows(int m, int cplx, bool fp32 = false);
-template <typename T>
-hipError_t launch_vrot(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s);
+int vacc_supported(int n, int cplx, bool fp32);
+hipError_t vacc_prepare(int cplx, bool fp32);   // once per state, on its device, outside graph capture
 template <typename T>
 hipError_t launch_gpair(const SvdDescT<T> &d, PairParam *prm, hipStream_t s);
+template <typename T>
+hipError_t launch_vacc(const SvdDescT<T> &d, const PairParam *plog, long long stride, int nsteps, hipStream_t s);
+template <typename T>
+hipError_t launch_vtrans(const SvdDescT<T> &d, hipStream_t s);
 
 // batched scaled dot-products (dot.hip): rows per thread for m (0 = not
 // supported) and the launch (one workgroup per column pair)

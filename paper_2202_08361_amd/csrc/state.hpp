@@ -23,7 +23,10 @@ struct jsvd_state_s {
     jsvd::DevScalars *sc;  // the device scalars (either descriptor's sc)
     int *rank;
     unsigned long long *maxbits;
-    jsvd::PairParam *prm;
+    jsvd::PairParam *vlog;   // outcome log of the large-column steps: kVlogSteps slots of vlog_stride
+    long long vlog_stride;
+    int vlog_n;              // logged steps not yet applied to V
+    int v_layout;            // V_COLS, V_ROWS, or V_EITHER (V = I after a load)
     jsvd::DevScalars *host;  // pinned staging for the scalars
     hipGraphExec_t graph;
     hipGraph_t graph_def;
@@ -33,6 +36,15 @@ struct jsvd_state_s {
 };
 
 namespace jsvd {
+
+// Steps of the outcome log: V is updated once per this many large-column
+// steps, and whenever it is read.
+constexpr int kVlogSteps = 32;
+
+// Layouts of the n x n V workspace: column-major (the fused step kernel and
+// every output), row-major (the deferred update of the large-column steps),
+// or either (V = I).
+enum { V_COLS = 0, V_ROWS = 1, V_EITHER = 2 };
 
 // Bytes of device memory a state for this problem allocates (fp32: the
 // single precision state).

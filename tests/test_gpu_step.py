@@ -190,9 +190,9 @@ def test_step_full_size(ora, m, n, cplx):
 
 @pytest.mark.parametrize("m,n,cplx", [(1500, 21, True), (700, 32, False), (3000, 9, False)])
 def test_sweep_graph_bitwise(ora, m, n, cplx):
-    """Whole sweeps through the captured sweep graph (the pipelined kernels, the
-    V kernel of step j beside the G kernel of step j+1) equal K oracle steps,
-    with the sweep's transformation and swap counts."""
+    """Whole sweeps through the captured sweep graph (G kernel and fold per
+    step, V updated from the outcome log) equal K oracle steps, with the
+    sweep's transformation and swap counts."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 800 + m)
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
     ost = ora.State(Ar, Ai)
