@@ -204,33 +204,42 @@ def evd_f32(torch, J, inputs, r, K, W):
     return res
 
 
-def step_roofline(torch, J, inputs, m, n, cplx, nsteps=20, warm=2, flags=0, fp32=False):
-    """Time the Jacobi step on a freshly loaded state (every pair transforms);
-    fp32: the single precision state on the same columns rounded to float."""
+VLOG_STEPS = 32   # steps of the outcome log: V is updated once per this many large-column steps
+
+
+def step_roofline(torch, J, inputs, m, n, cplx, flags=0, fp32=False):
+    """Time the Jacobi step on a freshly loaded state (every pair transforms):
+    one outcome log's worth of steps (VLOG_STEPS) after a first log as warm-up,
+    so that the timed block holds exactly one update of V; fp32: the single
+    precision state on the same columns rounded to float."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 77 + int(cplx))
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
     dt = torch.float32 if fp32 else torch.float64
     st = J.State(m, n, cplx, fp32=fp32)
     st.set_flags(flags)
     st.load(J.to_device_fortran(Ar, dtype=dt), J.to_device_fortran(Ai, dtype=dt) if cplx else None)
-    for _ in range(warm):
+    for _ in range(VLOG_STEPS):
         st.step()
+    T0 = st.query()["T"]
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nsteps)]
-    for s, e in evs:
-        s.record()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(VLOG_STEPS):
         st.step()
-        e.record()
+    b.record()
     torch.cuda.synchronize()
     q = st.query()
-    t = sum(s.elapsed_time(e) for s, e in evs) / nsteps * 1e-3
+    t = a.elapsed_time(b) * 1e-3 / VLOG_STEPS
     c = 2 if cplx else 1
-    # each element of the transformed G and V column pairs read once and written once
-    byts = 2.0 * (4 if fp32 else 8) * c * n * (m + n) * (q["last_t"] / (n // 2))
+    es = 4 if fp32 else 8
+    tr = (q["T"] - T0) / VLOG_STEPS
+    # per step: the transformed G column pairs read and written once; V read
+    # and written once per outcome log
+    byts = 2.0 * es * c * m * n * (tr / (n // 2)) + 2.0 * es * c * n * n / VLOG_STEPS
     st.close()
     return dict(m=m, n=n, complex=bool(cplx), dtype="f32" if fp32 else "f64", us_per_step=t * 1e6,
-                transformed=q["last_t"], pairs=n // 2, algorithmic_bytes=byts, achieved_GBs=byts / t / 1e9,
-                frac=byts / t / 1e9 / HBM_PEAK_GBS)
+                transformed_per_step=tr, pairs=n // 2, v_update_every=VLOG_STEPS, algorithmic_bytes=byts,
+                achieved_GBs=byts / t / 1e9, frac=byts / t / 1e9 / HBM_PEAK_GBS)
 
 
 def nrmf_rate(torch, J, inputs, m, n, cplx, K=10, lanes=1024):

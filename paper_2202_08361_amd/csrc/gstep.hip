@@ -61,7 +61,7 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
             PairParam z;
             z.c = 1.0;
             z.C = z.S = z.mx = 0.0;
-            z.p = z.q = z.flag = z.pad = 0;
+            z.pq = z.flag = 0;
             prm[blockIdx.x] = z;
         }
         return;
@@ -81,8 +81,7 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
     T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
     T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
     PairParam pp;
-    pp.p = p;
-    pp.q = q;
+    pp.pq = p | (q << 16);
     pp.flag = 0;
     pp.c = 1.0;
     pp.C = 0.0;
@@ -166,26 +165,58 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
 // End of step (Alg. zvjsvd): from the outcomes of all pairs, M~_{k+1} =
 // max(2^{s_[k]} M~_k, M) with M the max-norm of the rotated columns, the
 // counts of rotations and of swaps, the scaling exponent and the step index.
-// One workgroup of 256 threads; max and integer sums are exact, so the order
+// One workgroup of kFoldW threads; max and integer sums are exact, so the order
 // does not matter.  The max-norms are values of the working precision T held
 // as doubles, so the max and the rescaling below are those of T.
+constexpr int kFoldW = 1024;   // threads of the fold kernel
+
 template <typename T>
 __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs)
 {
-    __shared__ double smx[4];
-    __shared__ unsigned long long scnt[12];
+    constexpr int NW = kFoldW / 64;
+    __shared__ double smx[NW];
+    __shared__ unsigned long long scnt[3 * NW];
     DevScalars *sc = d.sc;
     const int t = threadIdx.x;
+    // the scalars the fold updates, loaded (by thread 0) beside the outcomes
+    unsigned long long Mt_bits = 0;
+    long long T0 = 0, SW0 = 0, GS0 = 0, k0 = 0;
+    int s0 = 0, resc0 = 0;
+    if (t == 0) {
+        Mt_bits = sc->Mt_bits;
+        T0 = sc->T;
+        SW0 = sc->SW;
+        GS0 = sc->GS;
+        k0 = sc->k;
+        s0 = sc->s;
+        resc0 = sc->rescaled;
+    }
     double mx = 0.0;
     unsigned long long tc = 0, swc = 0, gsc = 0;
-    for (int l = t; l < npairs; l += 256) {
-        const int fl = prm[l].flag;
-        if (fl & 1) {
-            mx = fmax(mx, prm[l].mx);
-            ++tc;
-            if (fl & 4) ++gsc;
-        } else if (fl & 2) {
-            ++swc;
+    // four outcomes per thread in flight at once (the log was written by
+    // other compute units: each load goes past this one's L2)
+    for (int l0 = 0; l0 < npairs; l0 += 4 * kFoldW) {
+        int fl[4];
+        double m4[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            // unconditional loads (an index past the end reads entry 0, masked)
+            const int l = l0 + t + kFoldW * u;
+            const int lc = l < npairs ? l : 0;
+            const int f = prm[lc].flag;
+            const double mv = prm[lc].mx;
+            fl[u] = l < npairs ? f : 0;
+            m4[u] = mv;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (fl[u] & 1) {
+                mx = fmax(mx, m4[u]);
+                ++tc;
+                if (fl[u] & 4) ++gsc;
+            } else if (fl[u] & 2) {
+                ++swc;
+            }
         }
     }
     mx = wave_max(mx);
@@ -198,40 +229,40 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
     if ((t & 63) == 0) {
         smx[t >> 6] = mx;
         scnt[t >> 6] = tc;
-        scnt[4 + (t >> 6)] = swc;
-        scnt[8 + (t >> 6)] = gsc;
+        scnt[NW + (t >> 6)] = swc;
+        scnt[2 * NW + (t >> 6)] = gsc;
     }
     __syncthreads();
     if (t == 0) {
         double M = smx[0];
-        unsigned long long tt = scnt[0], sw = scnt[4], gg = scnt[8];
-        for (int w = 1; w < 4; ++w) {
+        unsigned long long tt = scnt[0], sw = scnt[NW], gg = scnt[2 * NW];
+        for (int w = 1; w < NW; ++w) {
             M = fmax(M, smx[w]);
             tt += scnt[w];
-            sw += scnt[4 + w];
-            gg += scnt[8 + w];
+            sw += scnt[NW + w];
+            gg += scnt[2 * NW + w];
         }
-        const T Mt = (T)bits2d(sc->Mt_bits);
+        const T Mt = (T)bits2d(Mt_bits);
         const bool rescale = (d.cplx ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt) < 0;
         const int sp = rescale ? (d.lgbound - getexp(Mt) - 1) : 0;
         const T Mt2 = rescale ? scal2(Mt, sp) : Mt;
         sc->Mt_bits = d2bits((double)fmax(Mt2, (T)M));
-        sc->T += (long long)tt;
-        sc->SW += (long long)sw;
-        sc->GS += (long long)gg;
+        sc->T = T0 + (long long)tt;
+        sc->SW = SW0 + (long long)sw;
+        sc->GS = GS0 + (long long)gg;
         sc->last_t = (long long)tt;
         if (rescale) {
-            sc->s += sp;
-            sc->rescaled += 1;
+            sc->s = s0 + sp;
+            sc->rescaled = resc0 + 1;
         }
-        sc->k += 1;
+        sc->k = k0 + 1;
     }
 }
 
 // the fold of one step as a kernel of its own: the G kernel's workgroups do
 // not see each other's outcomes before that launch has ended
 template <typename T>
-__global__ __launch_bounds__(256) void fold_kernel(SvdDescT<T> d, const PairParam *prm)
+__global__ __launch_bounds__(kFoldW) void fold_kernel(SvdDescT<T> d, const PairParam *prm)
 {
     if (*(volatile int *)&d.sc->stop) return;
     fold_step(d, prm, (d.n + (d.n & 1)) / 2);
@@ -244,22 +275,23 @@ struct VaccPairs {
     int p[PPT], q[PPT], f[PPT];
 };
 
-template <int PPT, typename T>
-__device__ __forceinline__ void vacc_load(VaccPairs<PPT, T> &o, const PairParam *pl, int np, int t, int W, bool live)
+// The loads are unconditional (a pair beyond the step's count reads the
+// slot's first entry and is masked out), so that every step issues the same
+// loads and the compiler can wait for the previous step's only.
+template <bool CPLX, int PPT, typename T>
+__device__ __forceinline__ void vacc_load(VaccPairs<PPT, T> &o, const PairParam *pl, int np, int t, int W)
 {
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         const int l = t + W * u;
-        o.f[u] = 0;
-        if (live && l < np) {
-            const PairParam P = pl[l];
-            o.f[u] = P.flag;
-            o.p[u] = P.p;
-            o.q[u] = P.q;
-            o.c[u] = (T)P.c;
-            o.C[u] = (T)P.C;
-            o.S[u] = (T)P.S;
-        }
+        const PairParam *P = pl + (l < np ? l : 0);
+        const int pq = P->pq, f = P->flag;
+        o.f[u] = l < np ? f : 0;
+        o.p[u] = pq & 0xFFFF;
+        o.q[u] = pq >> 16;
+        o.c[u] = (T)P->c;
+        o.C[u] = (T)P->C;
+        o.S[u] = CPLX ? (T)P->S : T(0);
     }
 }
 
@@ -276,6 +308,7 @@ __global__ __launch_bounds__(1024) void vacc_kernel(SvdDescT<T> d, const PairPar
                                                     int nsteps, int B)
 {
     if (*(volatile int *)&d.sc->stop) return;
+    constexpr int RB = PPT >= 4 ? 1 : 2;   // staged rows updated together
     extern __shared__ __align__(16) unsigned char vacc_lds[];
     T *const sm = (T *)vacc_lds;
     const int n = d.n, t = threadIdx.x, W = blockDim.x;
@@ -291,42 +324,63 @@ __global__ __launch_bounds__(1024) void vacc_kernel(SvdDescT<T> d, const PairPar
         }
     }
     VaccPairs<PPT, T> cur, nxt;
-    vacc_load<PPT, T>(cur, plog, np, t, W, true);
+    vacc_load<CPLX, PPT, T>(cur, plog, np, t, W);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
-        vacc_load<PPT, T>(nxt, plog + (size_t)(s + 1) * stride, np, t, W, s + 1 < nsteps);
+        // the next step's outcomes (the last step reloads its own, unused)
+        vacc_load<CPLX, PPT, T>(nxt, plog + (size_t)(s + 1 < nsteps ? s + 1 : s) * stride, np, t, W);
+        // RB rows at a time: first every value the thread's pairs need from
+        // them (the pairs of a step are disjoint, so none of these loads
+        // depends on a store of the step), then the updates
+        for (int r0 = 0; r0 < nb; r0 += RB) {
+            T a[PPT][RB][4];   // p, q (real parts), then p, q (imaginary parts)
 #pragma unroll
-        for (int u = 0; u < PPT; ++u) {
-            const int f = cur.f[u];
-            if (f == 0) continue;
-            const int p = cur.p[u], q = cur.q[u];
-            const int ep = (f & 2) ? q : p, eq = (f & 2) ? p : q;
-            const T c = cur.c[u], C = cur.C[u], S = cur.S[u];
-            for (int r = 0; r < nb; ++r) {
-                T *const R = sm + r * n;
-                T *const I = sm + (B + r) * n;
-                const T pr = R[p], qr = R[q];
-                if (CPLX) {
-                    const T pi = I[p], qi = I[q];
-                    if (f & 1) {
-                        R[ep] = fma(qr, C, fma(-qi, S, pr)) * c;
-                        I[ep] = fma(qr, S, fma(qi, C, pi)) * c;
-                        R[eq] = fma(pr, -C, fma(-pi, S, qr)) * c;
-                        I[eq] = fma(pr, S, fma(pi, -C, qi)) * c;
+            for (int u = 0; u < PPT; ++u)
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) {
+                    if (cur.f[u] == 0 || r0 + rr >= nb) continue;
+                    const T *const R = sm + (r0 + rr) * n;
+                    a[u][rr][0] = R[cur.p[u]];
+                    a[u][rr][1] = R[cur.q[u]];
+                    if (CPLX) {
+                        const T *const I = sm + (B + r0 + rr) * n;
+                        a[u][rr][2] = I[cur.p[u]];
+                        a[u][rr][3] = I[cur.q[u]];
+                    }
+                }
+#pragma unroll
+            for (int u = 0; u < PPT; ++u)
+#pragma unroll
+                for (int rr = 0; rr < RB; ++rr) {
+                    const int f = cur.f[u];
+                    if (f == 0 || r0 + rr >= nb) continue;
+                    const int p = cur.p[u], q = cur.q[u];
+                    const int ep = (f & 2) ? q : p, eq = (f & 2) ? p : q;
+                    const T c = cur.c[u], C = cur.C[u], S = cur.S[u];
+                    const T pr = a[u][rr][0], qr = a[u][rr][1];
+                    T *const R = sm + (r0 + rr) * n;
+                    if (CPLX) {
+                        const T pi = a[u][rr][2], qi = a[u][rr][3];
+                        T *const I = sm + (B + r0 + rr) * n;
+                        if (f & 1) {
+                            R[ep] = fma(qr, C, fma(-qi, S, pr)) * c;
+                            I[ep] = fma(qr, S, fma(qi, C, pi)) * c;
+                            R[eq] = fma(pr, -C, fma(-pi, S, qr)) * c;
+                            I[eq] = fma(pr, S, fma(pi, -C, qi)) * c;
+                        } else {
+                            R[p] = qr;
+                            R[q] = pr;
+                            I[p] = qi;
+                            I[q] = pi;
+                        }
+                    } else if (f & 1) {
+                        R[ep] = fma(qr, C, pr) * c;
+                        R[eq] = fma(pr, -C, qr) * c;
                     } else {
                         R[p] = qr;
                         R[q] = pr;
-                        I[p] = qi;
-                        I[q] = pi;
                     }
-                } else if (f & 1) {
-                    R[ep] = fma(qr, C, pr) * c;
-                    R[eq] = fma(pr, -C, qr) * c;
-                } else {
-                    R[p] = qr;
-                    R[q] = pr;
                 }
-            }
         }
         lds_barrier();
         cur = nxt;
@@ -419,7 +473,7 @@ hipError_t launch_gpair(const SvdDescT<T> &d, PairParam *prm, hipStream_t s)
     if (R == 0) return hipErrorInvalidValue;
     const hipError_t e = d.cplx ? launch_gpair_t<true>(d, prm, R, s) : launch_gpair_t<false>(d, prm, R, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((fold_kernel<T>), dim3(1), dim3(256), 0, s, d, prm);
+    hipLaunchKernelGGL((fold_kernel<T>), dim3(1), dim3(kFoldW), 0, s, d, prm);
     return hipGetLastError();
 }
 
@@ -453,10 +507,12 @@ static hipError_t vacc_allow_lds()
 template <bool CPLX, typename T>
 static hipError_t vacc_prepare_t()
 {
+    constexpr bool F32 = sizeof(T) == sizeof(float);
     hipError_t e = vacc_allow_lds<CPLX, 1, T>();
     if (e == hipSuccess) e = vacc_allow_lds<CPLX, 2, T>();
-    if (e == hipSuccess) e = vacc_allow_lds<CPLX, 4, T>();
-    if constexpr (!CPLX && sizeof(T) == sizeof(float))
+    if constexpr (!CPLX || F32)
+        if (e == hipSuccess) e = vacc_allow_lds<CPLX, 4, T>();
+    if constexpr (!CPLX && F32)
         if (e == hipSuccess) e = vacc_allow_lds<CPLX, 8, T>();
     return e;
 }
@@ -487,15 +543,21 @@ hipError_t launch_vacc(const SvdDescT<T> &d, const PairParam *plog, long long st
     const int np = (d.n + 1) / 2;
     const int W = np >= 1024 ? 1024 : ((np + 63) / 64) * 64;
     const int ppt = (np + W - 1) / W;
-#define JSVD_VA(P)                                                                                                 \
-    if (ppt <= P)                                                                                                  \
-        return d.cplx ? launch_vacc_k<true, P, T>(d, plog, stride, nsteps, B, W, s)                                \
-                      : launch_vacc_k<false, P, T>(d, plog, stride, nsteps, B, W, s);
-    JSVD_VA(1) JSVD_VA(2) JSVD_VA(4)
-#undef JSVD_VA
-    // more than 4096 pairs: real single precision columns only (n <= m <= 16384)
-    if constexpr (sizeof(T) == sizeof(float))
-        if (ppt <= 8 && !d.cplx) return launch_vacc_k<false, 8, T>(d, plog, stride, nsteps, B, W, s);
+    // pairs per thread: n <= m rows, and m is at most 8192 (real) / 4096
+    // (complex) rows in double precision, twice that in single precision
+    constexpr bool F32 = sizeof(T) == sizeof(float);
+    if (d.cplx) {
+        if (ppt <= 1) return launch_vacc_k<true, 1, T>(d, plog, stride, nsteps, B, W, s);
+        if (ppt <= 2) return launch_vacc_k<true, 2, T>(d, plog, stride, nsteps, B, W, s);
+        if constexpr (F32)
+            if (ppt <= 4) return launch_vacc_k<true, 4, T>(d, plog, stride, nsteps, B, W, s);
+    } else {
+        if (ppt <= 1) return launch_vacc_k<false, 1, T>(d, plog, stride, nsteps, B, W, s);
+        if (ppt <= 2) return launch_vacc_k<false, 2, T>(d, plog, stride, nsteps, B, W, s);
+        if (ppt <= 4) return launch_vacc_k<false, 4, T>(d, plog, stride, nsteps, B, W, s);
+        if constexpr (F32)
+            if (ppt <= 8) return launch_vacc_k<false, 8, T>(d, plog, stride, nsteps, B, W, s);
+    }
     return hipErrorInvalidValue;
 }
 

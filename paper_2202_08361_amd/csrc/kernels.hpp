@@ -67,14 +67,14 @@ using SvdDesc = SvdDescT<double>;
 using SvdDescF = SvdDescT<float>;
 
 // outcome of one pivot pair, written by the G kernels for the end-of-step
-// fold and the (deferred) V update
+// fold and the (deferred) V update; what the V update reads comes first
+// (32 bytes)
 struct PairParam {
     double c, C, S;   // cos phi, e^{i alpha} tan phi
-    double mx;        // max |component| of the rotated G columns (0 if not rotated)
-    int p, q;         // the pair
+    int pq;           // the pair: p | q << 16
     int flag;         // bit 0: transform (rotation of V, counted), bit 1: swap the columns
                       // (permutation P), bit 2: G took the Gram-Schmidt step of eq. (GS)
-    int pad;
+    double mx;        // max |component| of the rotated G columns (0 if not rotated)
 };
 
 // step for large columns (gstep.hip): rows per thread of the G kernel for m
