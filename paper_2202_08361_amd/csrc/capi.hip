@@ -113,7 +113,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct StateLayout {
     long long ldg, ldv, vstride;
-    size_t oG, oV, oE, oF, oR, oS, oM, oP, total;
+    size_t oG, oV, oE, oF, oR, oS, oM, oP, oX, oH, total;
 };
 
 // es: bytes per element of the working precision
@@ -135,6 +135,8 @@ static StateLayout state_layout(int m, int n, int cplx, size_t es)
     // the outcome log: kVlogSteps slots of the step's pair outcomes
     L.vstride = round_up((long long)(n + 1) / 2, 4LL);
     L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)L.vstride * kVlogSteps);
+    L.oH = off; off = align_up(off + sizeof(StepHdr) * (size_t)kVlogSteps);
+    L.oX = off; off = align_up(off + sizeof(unsigned long long) * (size_t)kVlogSteps);
     L.total = off;
     return L;
 }
@@ -221,8 +223,11 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
     st->rank = (int *)(b + L.oR);
     st->maxbits = (unsigned long long *)(b + L.oM);
     st->vlog = (PairParam *)(b + L.oP);
+    st->vhdr = (StepHdr *)(b + L.oH);
+    st->vkey = (unsigned long long *)(b + L.oX);
     st->vlog_stride = L.vstride;
     st->vlog_n = 0;
+    st->vlast = -1;
     st->v_layout = V_EITHER;
     *out = st;
     return JSVD_OK;
@@ -295,8 +300,11 @@ static int load_async_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg,
     HIPCHK(launch_zero_u64(st->maxbits, s));
     HIPCHK(launch_maxabs(d, G_re, G_im, (long long)ldg, st->maxbits, s));
     HIPCHK(launch_init_scale(d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
-    // V = I: the same in either layout, nothing logged
+    // V = I: the same in either layout, nothing logged, the scalars current,
+    // no step keys (k starts again from 0)
+    HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSteps, s));
     st->vlog_n = 0;
+    st->vlast = -1;
     st->v_layout = V_EITHER;
     return JSVD_OK;
 }
@@ -416,15 +424,46 @@ static hipError_t set_v_layout(jsvd_state st, int want, hipStream_t s)
 
 static int path_layout(jsvd_state st) { return uses_gpair(st) ? V_ROWS : V_COLS; }
 
+static StepSlot slot_of(jsvd_state st, int j)
+{
+    StepSlot z;
+    z.prm = st->vlog + (size_t)j * st->vlog_stride;
+    z.hdr = st->vhdr + j;
+    z.mxkey = st->vkey + j;
+    return z;
+}
+
+// the device scalars up to date: the fold of the last large-column step,
+// which the next such step would otherwise do
+static hipError_t settle(jsvd_state st, hipStream_t s)
+{
+    if (st->vlast < 0) return hipSuccess;
+    const PairParam *prm = slot_of(st, st->vlast).prm;
+    st->vlast = -1;
+    return st->fp32 ? launch_fold(st->df, prm, s) : launch_fold(st->d, prm, s);
+}
+
 // one step on a state whose V is in the path's layout: on the large-column
-// path the outcomes go to the next log slot and a full log is applied to V
+// path the step continues from the previous one's slot (if its fold is
+// still due), its outcomes go to the next slot, and a full log is applied
+// to V; the fused kernel needs the scalars current
 template <typename T>
 static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s)
 {
     const SvdDescT<T> &d = desc_of<T>(st);
-    if (!uses_gpair(st)) return launch_step(d, state_threads(st), s);
-    const hipError_t e = launch_gpair(d, st->vlog + (size_t)st->vlog_n * st->vlog_stride, s);
+    if (!uses_gpair(st)) {
+        const hipError_t e = settle(st, s);
+        if (e != hipSuccess) return e;
+        return launch_step(d, state_threads(st), s);
+    }
+    StepSlot prev;
+    prev.prm = nullptr;
+    prev.hdr = nullptr;
+    prev.mxkey = nullptr;
+    if (st->vlast >= 0) prev = slot_of(st, st->vlast);
+    const hipError_t e = launch_gpair(d, slot_of(st, st->vlog_n), prev, s);
     if (e != hipSuccess) return e;
+    st->vlast = st->vlog_n;
     if (++st->vlog_n == kVlogSteps) return flush_vlog_t<T>(st, s);
     return hipSuccess;
 }
@@ -453,7 +492,7 @@ static int capture_sweep(jsvd_state st, hipStream_t cs)
     const int K = sweep_steps(st->n);
     for (int k = 0; k < K; ++k)
         if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
-    if (flush_vlog(st, cs) != hipSuccess) return JSVD_EDEVICE;
+    if (flush_vlog(st, cs) != hipSuccess || settle(st, cs) != hipSuccess) return JSVD_EDEVICE;
     return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
 }
 
@@ -479,6 +518,7 @@ static int build_graph(jsvd_state st)
         } else {
             rc = capture_sweep(st, cs);
             st->vlog_n = 0;
+            st->vlast = -1;
             // a failed capture still has to be ended
             if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == JSVD_OK) rc = JSVD_EDEVICE;
         }
@@ -500,9 +540,11 @@ static int build_graph(jsvd_state st)
 extern "C" int jsvd_sweep(jsvd_state st, void *stream)
 {
     if (!st) return JSVD_EINVAL;
-    // V in the path's layout and the log empty, as the captured sweep expects
+    // V in the path's layout, the log empty and the scalars current, as the
+    // captured sweep expects
     HIPCHK(set_v_layout(st, path_layout(st), (hipStream_t)stream));
     HIPCHK(flush_vlog(st, (hipStream_t)stream));
+    HIPCHK(settle(st, (hipStream_t)stream));
     const int rc = build_graph(st);
     if (rc != JSVD_OK) return rc;
     HIPCHK(hipGraphLaunch(st->graph, (hipStream_t)stream));
@@ -526,6 +568,7 @@ static int finish_async_t(jsvd_state st, bool converged, T *U_re, T *U_im, size_
     if (!is_prec<T>(st)) return JSVD_EINVAL;
     const SvdDescT<T> &d = desc_of<T>(st);
     HIPCHK(set_v_layout(st, V_COLS, s));
+    HIPCHK(settle(st, s));
     if (converged) {
         HIPCHK(launch_colnorms_raw(d, s));
         HIPCHK(launch_rank(d, st->rank, s));
@@ -557,6 +600,7 @@ int jsvd::state_finish_async(jsvd_state st, bool converged, float *U_re, float *
 extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
 {
     if (!st || !out) return JSVD_EINVAL;
+    HIPCHK(settle(st, (hipStream_t)stream));
     const int rc = pull_scalars(st, (hipStream_t)stream);
     if (rc != JSVD_OK) return rc;
     const DevScalars &h = *st->host;
@@ -598,6 +642,7 @@ static int save_t(jsvd_state st, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im,
     }
     if (e) HIPCHK(hipMemcpyAsync(e, d.e, sizeof(T) * d.n, hipMemcpyDeviceToDevice, s));
     if (f) HIPCHK(hipMemcpyAsync(f, d.f, sizeof(T) * d.n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(settle(st, s));
     const int rc = pull_scalars(st, s);
     if (rc != JSVD_OK) return rc;
     if (s_out) *s_out = st->host->s;
@@ -635,8 +680,11 @@ static int restore_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, co
     if (st->cplx) HIPCHK(launch_copy2d(d.m, d.n, G_im, (long long)ldg, d.Gi, d.ldg, s));
     HIPCHK(launch_copy2d(d.n, d.n, V_re, (long long)ldv, d.Vr, d.ldv, s));
     if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, V_im, (long long)ldv, d.Vi, d.ldv, s));
-    // the restored V replaces the logged steps too
+    // the restored V and scalars replace the logged steps too (and k may
+    // go back: no step keys)
+    HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSteps, s));
     st->vlog_n = 0;
+    st->vlast = -1;
     st->v_layout = V_COLS;
     DevScalars h;
     memset(&h, 0, sizeof(h));

@@ -10,8 +10,10 @@
 //   once.  Two workgroups per compute unit overlap one pair's reductions and
 //   EVD with the other's memory traffic.  The pair's outcome (rotation,
 //   permutation, max-norm) goes to the step's slot of an outcome log.
-// * fold_kernel: one workgroup folds the step into the device scalars (M~,
-//   counts, s, k) from the outcomes, so no workgroup needs an atomic.
+// * the fold of a step into the device scalars (M~, counts, s, k): done at
+//   the start of the next such step (its workgroups derive k and M~ from the
+//   logged step, its workgroup 0 updates the scalars), or by fold_kernel
+//   when the scalars are read; no workgroup needs an atomic.
 //
 // V is not touched per step.  Its rows never mix, so the rotations of up to
 // a log's worth of consecutive steps are applied to it in one pass
@@ -43,137 +45,18 @@ constexpr int gpair_wgs_per_cu()
     return 2;
 }
 
-// G part of the step: one workgroup of W = 256 threads per pivot pair, the
-// pair held in registers from its load to its store.  Several workgroups
-// share a compute unit, so one computes (reductions, EVD) while the others
-// wait on their loads or stores.  The outcome of the pair (rotation,
-// permutation, max-norm of the rotated columns) goes to prm.
-template <bool CPLX, int W, int R, bool COMP, typename T>
-__global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)) void gpair_kernel(SvdDescT<T> d,
-                                                                                                      PairParam *prm)
-{
-    __shared__ T red[(COMP ? 12 : 6) * W];
-    __shared__ T mxs[4 * (W / 64)];
-    DevScalars *sc = d.sc;
-    if (*(volatile int *)&sc->stop) {
-        // a stopped iteration: the step does nothing, and its log slot says so
-        if (threadIdx.x == 0) {
-            PairParam z;
-            z.c = 1.0;
-            z.C = z.S = z.mx = 0.0;
-            z.pq = z.flag = 0;
-            prm[blockIdx.x] = z;
-        }
-        return;
-    }
-    const long long k = *(volatile long long *)&sc->k;
-    const T Mt = (T)bits2d(*(volatile unsigned long long *)&sc->Mt_bits);
-    const int m = d.m, n = d.n;
-    const int t = threadIdx.x;
-    const int l = blockIdx.x;
-    const int sr = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt);
-    const bool rescale = sr < 0;
-    const int sp = rescale ? (d.lgbound - getexp(Mt) - 1) : 0;
-    int p, q;
-    const bool valid = rr_pair(n, k, l, &p, &q);
-    T *const Gpr = d.Gr + (size_t)p * d.ldg;
-    T *const Gqr = d.Gr + (size_t)q * d.ldg;
-    T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
-    T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
-    PairParam pp;
-    pp.pq = p | (q << 16);
-    pp.flag = 0;
-    pp.c = 1.0;
-    pp.C = 0.0;
-    pp.S = 0.0;
-    pp.mx = 0.0;
-    if (!valid) {
-        // the column sitting out (odd n): only the rescaling applies
-        if (rescale) {
-            for (int i = t; i < m; i += W) {
-                Gpr[i] = scal2(Gpr[i], sp);
-                if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
-            }
-        }
-        if (t == 0) prm[l] = pp;
-    } else {
-        T xr[2][R], xi[2][R];
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int i = t + W * j;
-            const bool in = i < m;
-            xr[0][j] = in ? Gpr[i] : T(0);
-            xr[1][j] = in ? Gqr[i] : T(0);
-            if (CPLX) {
-                xi[0][j] = in ? Gpi[i] : T(0);
-                xi[1][j] = in ? Gqi[i] : T(0);
-            }
-        }
-        if (rescale) {
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    xr[c][j] = scal2(xr[c][j], sp);
-                    if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
-                }
-        }
-        const PairDecisionT<T> dc =
-            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, red, red + 4 * W, mxs);
-        const int pbit = dc.pbit;
-        T *const Dp_r = pbit ? Gqr : Gpr;
-        T *const Dq_r = pbit ? Gpr : Gqr;
-        T *const Dp_i = pbit ? Gqi : Gpi;
-        T *const Dq_i = pbit ? Gpi : Gqi;
-        if (dc.transform) {
-            T mm[1] = {transform_regs<CPLX, R>(xr, xi, dc)};
-            group_max<W, 1>(mm, mxs + 2 * (W / 64));
-            pp.mx = mm[0];
-            pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
-            pp.c = dc.c;
-            pp.C = dc.C;
-            pp.S = dc.S;
-        } else if (pbit) {
-            pp.flag = 2;
-        }
-        if (dc.transform || pbit || rescale) {
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int i = t + W * j;
-                if (i < m) {
-                    Dp_r[i] = xr[0][j];
-                    Dq_r[i] = xr[1][j];
-                    if (CPLX) {
-                        Dp_i[i] = xi[0][j];
-                        Dq_i[i] = xi[1][j];
-                    }
-                }
-            }
-        }
-        if (t == 0) {
-            prm[l] = pp;
-            const int dp = pbit ? q : p, dq = pbit ? p : q;
-            d.e[dp] = dc.np.zero ? T(-INFINITY) : (T)dc.np.e;
-            d.f[dp] = dc.np.zero ? T(1) : dc.np.f;
-            d.e[dq] = dc.nq.zero ? T(-INFINITY) : (T)dc.nq.e;
-            d.f[dq] = dc.nq.zero ? T(1) : dc.nq.f;
-        }
-    }
-}
-
-
 // End of step (Alg. zvjsvd): from the outcomes of all pairs, M~_{k+1} =
 // max(2^{s_[k]} M~_k, M) with M the max-norm of the rotated columns, the
 // counts of rotations and of swaps, the scaling exponent and the step index.
-// One workgroup of kFoldW threads; max and integer sums are exact, so the order
+// One workgroup of FW threads; max and integer sums are exact, so the order
 // does not matter.  The max-norms are values of the working precision T held
 // as doubles, so the max and the rescaling below are those of T.
 constexpr int kFoldW = 1024;   // threads of the fold kernel
 
-template <typename T>
-__device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs)
+template <int FW, typename T>
+__device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs)
 {
-    constexpr int NW = kFoldW / 64;
+    constexpr int NW = FW / 64;
     __shared__ double smx[NW];
     __shared__ unsigned long long scnt[3 * NW];
     DevScalars *sc = d.sc;
@@ -195,13 +78,13 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
     unsigned long long tc = 0, swc = 0, gsc = 0;
     // four outcomes per thread in flight at once (the log was written by
     // other compute units: each load goes past this one's L2)
-    for (int l0 = 0; l0 < npairs; l0 += 4 * kFoldW) {
+    for (int l0 = 0; l0 < npairs; l0 += 4 * FW) {
         int fl[4];
         double m4[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             // unconditional loads (an index past the end reads entry 0, masked)
-            const int l = l0 + t + kFoldW * u;
+            const int l = l0 + t + FW * u;
             const int lc = l < npairs ? l : 0;
             const int f = prm[lc].flag;
             const double mv = prm[lc].mx;
@@ -246,7 +129,8 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
         const bool rescale = (d.cplx ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt) < 0;
         const int sp = rescale ? (d.lgbound - getexp(Mt) - 1) : 0;
         const T Mt2 = rescale ? scal2(Mt, sp) : Mt;
-        sc->Mt_bits = d2bits((double)fmax(Mt2, (T)M));
+        Mt_bits = d2bits((double)fmax(Mt2, (T)M));
+        sc->Mt_bits = Mt_bits;
         sc->T = T0 + (long long)tt;
         sc->SW = SW0 + (long long)sw;
         sc->GS = GS0 + (long long)gg;
@@ -257,7 +141,181 @@ __device__ void fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs
         }
         sc->k = k0 + 1;
     }
+    return Mt_bits;   // the new M~ in thread 0
 }
+
+// The max-norm of a step's rotated columns enters the next step's
+// rescaling check only through its exponent.  Every workgroup that rotates
+// adds the key (k << 12) | (floor(lg mx) + 1075) to its step's slot with an
+// atomic max (exact and order-free); a key of an earlier step (smaller k, or
+// the zero a load leaves) means that no pair was rotated in step k.
+constexpr int kNoExp = -(1 << 20);
+
+__device__ __forceinline__ void step_max_add(unsigned long long *key, long long k, int e)
+{
+    const unsigned long long v = ((unsigned long long)k << 12) | (unsigned long long)(e + 1075);
+    (void)__hip_atomic_fetch_max(key, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int step_max_exp(unsigned long long key, long long k)
+{
+    return (key >> 12) == (unsigned long long)k ? (int)(key & 0xFFF) - 1075 : kNoExp;
+}
+
+// G part of the step: one workgroup of W = 256 threads per pivot pair, the
+// pair held in registers from its load to its store.  Several workgroups
+// share a compute unit, so one computes (reductions, EVD) while the others
+// wait on their loads or stores.  The outcome of the pair (rotation,
+// permutation, max-norm of the rotated columns) goes to the log slot.
+//
+// The step index and M~ come from the device scalars, or, after another
+// step of this kind (prev.prm set), from that step: k + 1, and floor(lg M~)
+// = max(floor(lg 2^{s_[k]} M~_k), floor(lg M)) from its header and its
+// max-norm key, while workgroup 0 folds that step into the device scalars
+// (fold_step: the exact M~ and the counts).  So no kernel runs between two
+// steps.
+template <bool CPLX, int W, int R, bool COMP, typename T>
+__global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)) void gpair_kernel(SvdDescT<T> d,
+                                                                                                      StepSlot slot,
+                                                                                                      StepSlot prev)
+{
+    __shared__ T red[(COMP ? 12 : 6) * W];
+    __shared__ T mxs[4 * (W / 64)];
+    DevScalars *sc = d.sc;
+    PairParam *const prm = slot.prm;
+    const int t = threadIdx.x;
+    const int l = blockIdx.x;
+    if (*(volatile int *)&sc->stop) {
+        // a stopped iteration: the step does nothing, and its log slot says so
+        if (t == 0) {
+            PairParam z;
+            z.c = 1.0;
+            z.C = z.S = z.mx = 0.0;
+            z.pq = z.flag = 0;
+            prm[l] = z;
+        }
+        return;
+    }
+    const int m = d.m, n = d.n;
+    const int npairs = (n + 1) / 2;
+    const long long k = prev.prm ? prev.hdr->k + 1 : *(volatile long long *)&sc->k;
+    const unsigned long long pkey = prev.prm ? *prev.mxkey : 0ull;
+    int p, q;
+    const bool valid = rr_pair(n, k, l, &p, &q);
+    T *const Gpr = d.Gr + (size_t)p * d.ldg;
+    T *const Gqr = d.Gr + (size_t)q * d.ldg;
+    T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
+    T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
+    T xr[2][R], xi[2][R];
+    if (valid) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + W * j;
+            const bool in = i < m;
+            xr[0][j] = in ? Gpr[i] : T(0);
+            xr[1][j] = in ? Gqr[i] : T(0);
+            if (CPLX) {
+                xi[0][j] = in ? Gpi[i] : T(0);
+                xi[1][j] = in ? Gqi[i] : T(0);
+            }
+        }
+    }
+    // floor(lg M~) of this step, which is all the rescaling check needs
+    int eMt;
+    if (prev.prm) {
+        const T Mp = (T)bits2d(prev.hdr->Mt_bits);
+        const bool rp = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mp) < 0;
+        const T Mp2 = rp ? scal2(Mp, d.lgbound - getexp(Mp) - 1) : Mp;
+        eMt = max(getexp(Mp2), step_max_exp(pkey, k - 1));
+        // the previous step's fold: the exact M~ of this step, the counts
+        if (l == 0) {
+            const unsigned long long Mt_bits = fold_step<W, T>(d, prev.prm, npairs);
+            if (t == 0) {
+                slot.hdr->k = k;
+                slot.hdr->Mt_bits = Mt_bits;
+            }
+        }
+    } else {
+        const unsigned long long Mt_bits = *(volatile unsigned long long *)&sc->Mt_bits;
+        eMt = getexp((T)bits2d(Mt_bits));
+        if (l == 0 && t == 0) {
+            slot.hdr->k = k;
+            slot.hdr->Mt_bits = Mt_bits;
+        }
+    }
+    const int sr = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - eMt;
+    const bool rescale = sr < 0;
+    const int sp = rescale ? (d.lgbound - eMt - 1) : 0;
+    PairParam pp;
+    pp.pq = p | (q << 16);
+    pp.flag = 0;
+    pp.c = 1.0;
+    pp.C = 0.0;
+    pp.S = 0.0;
+    pp.mx = 0.0;
+    if (!valid) {
+        // the column sitting out (odd n): only the rescaling applies
+        if (rescale) {
+            for (int i = t; i < m; i += W) {
+                Gpr[i] = scal2(Gpr[i], sp);
+                if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
+            }
+        }
+        if (t == 0) prm[l] = pp;
+    } else {
+        if (rescale) {
+#pragma unroll
+            for (int j = 0; j < R; ++j)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    xr[c][j] = scal2(xr[c][j], sp);
+                    if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
+                }
+        }
+        const PairDecisionT<T> dc =
+            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, red, red + 4 * W, mxs);
+        const int pbit = dc.pbit;
+        T *const Dp_r = pbit ? Gqr : Gpr;
+        T *const Dq_r = pbit ? Gpr : Gqr;
+        T *const Dp_i = pbit ? Gqi : Gpi;
+        T *const Dq_i = pbit ? Gpi : Gqi;
+        if (dc.transform) {
+            T mm[1] = {transform_regs<CPLX, R>(xr, xi, dc)};
+            group_max<W, 1>(mm, mxs + 2 * (W / 64));
+            pp.mx = mm[0];
+            pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
+            pp.c = dc.c;
+            pp.C = dc.C;
+            pp.S = dc.S;
+        } else if (pbit) {
+            pp.flag = 2;
+        }
+        if (dc.transform || pbit || rescale) {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int i = t + W * j;
+                if (i < m) {
+                    Dp_r[i] = xr[0][j];
+                    Dq_r[i] = xr[1][j];
+                    if (CPLX) {
+                        Dp_i[i] = xi[0][j];
+                        Dq_i[i] = xi[1][j];
+                    }
+                }
+            }
+        }
+        if (t == 0) {
+            prm[l] = pp;
+            if ((pp.flag & 1) && pp.mx > 0.0) step_max_add(slot.mxkey, k, getexp((T)pp.mx));
+            const int dp = pbit ? q : p, dq = pbit ? p : q;
+            d.e[dp] = dc.np.zero ? T(-INFINITY) : (T)dc.np.e;
+            d.f[dp] = dc.np.zero ? T(1) : dc.np.f;
+            d.e[dq] = dc.nq.zero ? T(-INFINITY) : (T)dc.nq.e;
+            d.f[dq] = dc.nq.zero ? T(1) : dc.nq.f;
+        }
+    }
+}
+
 
 // the fold of one step as a kernel of its own: the G kernel's workgroups do
 // not see each other's outcomes before that launch has ended
@@ -265,7 +323,7 @@ template <typename T>
 __global__ __launch_bounds__(kFoldW) void fold_kernel(SvdDescT<T> d, const PairParam *prm)
 {
     if (*(volatile int *)&d.sc->stop) return;
-    fold_step(d, prm, (d.n + (d.n & 1)) / 2);
+    (void)fold_step<kFoldW, T>(d, prm, (d.n + (d.n & 1)) / 2);
 }
 
 // outcomes of this thread's pairs l = t + W u in one step (only what V needs)
@@ -439,7 +497,7 @@ int gpair_rows(int m, int cplx, bool fp32)
 }
 
 template <bool CPLX, typename T>
-static hipError_t launch_gpair_t(const SvdDescT<T> &d, PairParam *prm, int R, hipStream_t s)
+static hipError_t launch_gpair_t(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, int R, hipStream_t s)
 {
     constexpr bool F32 = sizeof(T) == sizeof(float);
     const int npairs = (d.n + (d.n & 1)) / 2;
@@ -452,11 +510,12 @@ static hipError_t launch_gpair_t(const SvdDescT<T> &d, PairParam *prm, int R, hi
             if constexpr (!F32) {                                                                               \
                 if (d.comp) {                                                                                   \
                     hipLaunchKernelGGL((gpair_kernel<CPLX, kPW, r, true, T>), dim3(npairs), dim3(kPW), 0, s, d, \
-                                       prm);                                                                    \
+                                       slot, prev);                                                             \
                     return hipGetLastError();                                                                   \
                 }                                                                                               \
             }                                                                                                   \
-            hipLaunchKernelGGL((gpair_kernel<CPLX, kPW, r, false, T>), dim3(npairs), dim3(kPW), 0, s, d, prm);  \
+            hipLaunchKernelGGL((gpair_kernel<CPLX, kPW, r, false, T>), dim3(npairs), dim3(kPW), 0, s, d, slot,  \
+                               prev);                                                                           \
             return hipGetLastError();                                                                           \
         }                                                                                                       \
         break;
@@ -467,12 +526,16 @@ static hipError_t launch_gpair_t(const SvdDescT<T> &d, PairParam *prm, int R, hi
 }
 
 template <typename T>
-hipError_t launch_gpair(const SvdDescT<T> &d, PairParam *prm, hipStream_t s)
+hipError_t launch_gpair(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, hipStream_t s)
 {
     const int R = gpair_rows(d.m, d.cplx, sizeof(T) == sizeof(float));
     if (R == 0) return hipErrorInvalidValue;
-    const hipError_t e = d.cplx ? launch_gpair_t<true>(d, prm, R, s) : launch_gpair_t<false>(d, prm, R, s);
-    if (e != hipSuccess) return e;
+    return d.cplx ? launch_gpair_t<true>(d, slot, prev, R, s) : launch_gpair_t<false>(d, slot, prev, R, s);
+}
+
+template <typename T>
+hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s)
+{
     hipLaunchKernelGGL((fold_kernel<T>), dim3(1), dim3(kFoldW), 0, s, d, prm);
     return hipGetLastError();
 }
@@ -569,8 +632,10 @@ hipError_t launch_vtrans(const SvdDescT<T> &d, hipStream_t s)
     return hipGetLastError();
 }
 
-template hipError_t launch_gpair<double>(const SvdDescT<double> &, PairParam *, hipStream_t);
-template hipError_t launch_gpair<float>(const SvdDescT<float> &, PairParam *, hipStream_t);
+template hipError_t launch_gpair<double>(const SvdDescT<double> &, StepSlot, StepSlot, hipStream_t);
+template hipError_t launch_gpair<float>(const SvdDescT<float> &, StepSlot, StepSlot, hipStream_t);
+template hipError_t launch_fold<double>(const SvdDescT<double> &, const PairParam *, hipStream_t);
+template hipError_t launch_fold<float>(const SvdDescT<float> &, const PairParam *, hipStream_t);
 template hipError_t launch_vacc<double>(const SvdDescT<double> &, const PairParam *, long long, int, hipStream_t);
 template hipError_t launch_vacc<float>(const SvdDescT<float> &, const PairParam *, long long, int, hipStream_t);
 template hipError_t launch_vtrans<double>(const SvdDescT<double> &, hipStream_t);

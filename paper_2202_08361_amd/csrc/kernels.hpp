@@ -77,17 +77,37 @@ struct PairParam {
     double mx;        // max |component| of the rotated G columns (0 if not rotated)
 };
 
+// index and M~ of a large-column step, for the step after it
+struct StepHdr {
+    long long k;
+    unsigned long long Mt_bits;
+};
+
+// one slot of the outcome log of the large-column steps: the pair outcomes,
+// the step header, and the key of the max-norm of its rotated columns
+// ((k << 12) | (floor(lg M) + 1075), an atomic max over the workgroups)
+struct StepSlot {
+    PairParam *prm;
+    StepHdr *hdr;
+    unsigned long long *mxkey;
+};
+
 // step for large columns (gstep.hip): rows per thread of the G kernel for m
-// (0 = not supported); one step on G (the G kernel, its outcomes into prm,
-// then the fold into the device scalars; V untouched); the deferred V
-// update applying nsteps logged steps (step j's outcomes at plog + j stride)
-// to the row-major V; the in-place transpose of V between its column-major
-// and row-major layouts
+// (0 = not supported); one step on G into a log slot (V untouched).  With a
+// previous slot (prev.prm != nullptr) the step starts from that step's
+// outcomes, whose fold into the device scalars is then also done; without,
+// from the device scalars as they are.  launch_fold folds a slot's step
+// into the device scalars (for the last step before they are read).  The
+// deferred V update applies nsteps logged steps (step j's outcomes at plog +
+// j stride) to the row-major V; the in-place transpose switches V between
+// its column-major and row-major layouts.
 int gpair_rows(int m, int cplx, bool fp32 = false);
 int vacc_supported(int n, int cplx, bool fp32);
 hipError_t vacc_prepare(int cplx, bool fp32);   // once per state, on its device, outside graph capture
 template <typename T>
-hipError_t launch_gpair(const SvdDescT<T> &d, PairParam *prm, hipStream_t s);
+hipError_t launch_gpair(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, hipStream_t s);
+template <typename T>
+hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s);
 template <typename T>
 hipError_t launch_vacc(const SvdDescT<T> &d, const PairParam *plog, long long stride, int nsteps, hipStream_t s);
 template <typename T>

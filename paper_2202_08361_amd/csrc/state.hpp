@@ -24,8 +24,11 @@ struct jsvd_state_s {
     int *rank;
     unsigned long long *maxbits;
     jsvd::PairParam *vlog;   // outcome log of the large-column steps: kVlogSteps slots of vlog_stride
+    jsvd::StepHdr *vhdr;     // the header of each slot
+    unsigned long long *vkey;  // the max-norm key of each slot (zeroed by a load or restore)
     long long vlog_stride;
     int vlog_n;              // logged steps not yet applied to V
+    int vlast;               // slot of the last step when its fold is still due, else -1
     int v_layout;            // V_COLS, V_ROWS, or V_EITHER (V = I after a load)
     jsvd::DevScalars *host;  // pinned staging for the scalars
     hipGraphExec_t graph;

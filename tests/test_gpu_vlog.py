@@ -186,3 +186,49 @@ def test_gesvj_large_column_path(ora, single, m, n, cplx):
     assert ro["status"] == rg["status"] == 0 and ro["sweeps"] == rg["sweeps"]
     for k in ("U_re", "V_re", "sv_e", "sv_f") + (("U_im", "V_im") if cplx else ()):
         assert _bits_equal(_host(rg[k]), ro[k]), k
+
+
+@pytest.mark.parametrize("single", [False, True])
+@pytest.mark.parametrize("cplx", [False, True])
+def test_rescale_inside_a_chain(ora, single, cplx):
+    """Sect. 3.2 on the large-column path: G restored with its largest
+    components just below the downscaling threshold, so that a later step of
+    an unbroken chain (whose step index and M~ come from the previous step's
+    log slot and max-norm key, not from the device scalars) is the one that
+    downscales.  Six steps, then every bit against the oracle, the
+    downscaling count included."""
+    m, n = 320, 16
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 2900 + 2 * int(cplx) + int(single))
+    top = (124 if cplx else 126) if single else (1020 if cplx else 1022)
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    dt = np.float32 if single else np.float64
+    # the largest component at 0.98 of 2^(top+1): floor(lg M~) = top, no
+    # downscaling yet; a rotation that grows it by 2 % crosses the threshold
+    raw = max(np.max(np.abs(Ar)), np.max(np.abs(Ai)) if cplx else 0.0)
+    scale = 0.98 * np.ldexp(1.0, top + 1) / raw
+    Gr = np.asfortranarray((Ar * scale).astype(dt))
+    Gi = np.asfortranarray((Ai * scale).astype(dt)) if cplx else None
+    mt = float(max(np.max(np.abs(Gr)), np.max(np.abs(Gi)) if cplx else 0.0))
+    assert np.isfinite(mt) and np.frexp(mt)[1] - 1 <= top
+    ost = (ora.SState if single else ora.State)(Gr, Gi)
+    assert ost.init() == ora.OK
+    ost.Gr[:] = Gr
+    if cplx:
+        ost.Gi[:] = Gi
+    ost.Vr[:] = np.eye(n, dtype=dt)
+    if cplx:
+        ost.Vi[:] = 0
+    ost.s, ost.Mt, ost.k = 0, mt, 0
+    st = J().State(m, n, cplx, fp32=single)
+    eye = np.asfortranarray(np.eye(n, dtype=dt))
+    st.restore(_dev(Gr), _dev(Gi), _dev(eye), _dev(np.zeros_like(eye)) if cplx else None, 0, mt, 0)
+    seen = []
+    for _ in range(6):
+        ost.step()
+        st.step()
+        seen.append(ost.rescaled)
+    # the first step does not downscale; one of the chained steps does
+    assert seen[0] == 0 and seen[-1] >= 1, seen
+    q = st.query()
+    assert q["rescaled"] == ost.rescaled
+    _check(ost, st.save(), "after six steps")
