@@ -232,3 +232,38 @@ def test_rescale_inside_a_chain(ora, single, cplx):
     q = st.query()
     assert q["rescaled"] == ost.rescaled
     _check(ost, st.save(), "after six steps")
+
+
+@pytest.mark.parametrize("m,n,cplx", [(4096, 4096, True), (8192, 2048, False)])
+def test_full_size_sweep_properties(m, n, cplx):
+    """One whole sweep of the large workloads through the captured sweep graph
+    (K steps, the V update applied 128 / 64 times, V transposed back for the
+    read): properties that hold at any size, since the oracle would need half
+    an hour for this sweep.  V stays unitary, ||V^H V - I||_max <= 1e-12, and
+    G = 2^s A V to 1e-12 relative in the Frobenius norm (every rotation is
+    applied to G and V alike; the error is a few eps per rotation)."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 88 + int(cplx))
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    st = J().State(m, n, cplx)
+    assert st.load(_dev(Ar), _dev(Ai)) == 0
+    st.sweep()
+    q = st.query()
+    assert q["sweeps"] == 1 and q["steps"] == n - 1 and q["last_sweep_T"] > 0
+    sv = st.save()
+    torch.cuda.synchronize()
+    dev = sv["G_re"].device
+    if cplx:
+        G = torch.complex(sv["G_re"], sv["G_im"])
+        V = torch.complex(sv["V_re"], sv["V_im"])
+        A = torch.complex(torch.from_numpy(np.ascontiguousarray(Ar)), torch.from_numpy(np.ascontiguousarray(Ai))).to(dev)
+    else:
+        G, V = sv["G_re"], sv["V_re"]
+        A = torch.from_numpy(np.ascontiguousarray(Ar)).to(dev)
+    G, V = G.contiguous(), V.contiguous()
+    eye = torch.eye(n, dtype=V.dtype, device=dev)
+    orth = (V.conj().transpose(0, 1).contiguous() @ V - eye).abs().max().item()
+    assert orth <= 1e-12, orth
+    # G carries the scaling 2^s (s near 1000 here): compare 2^-s G (exact) with A V
+    Gs = G * (2.0 ** -sv["s"])
+    res = torch.linalg.norm(Gs - A @ V).item() / torch.linalg.norm(A).item()
+    assert res <= 1e-12, res
