@@ -408,12 +408,52 @@ def svd_plain(torch, J, inputs, flags, fp32=False):
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
-def cpu_oracle_svd(inputs, sweeps_256=None):
+def svd_large(torch, J, inputs, cplx, flags):
+    """The whole plain SVD of a large workload: complex 4096 x 4096 (sigma
+    geometric from 1 to 1e-12) or real 8192 x 2048 (sigma log-spaced in
+    [1e-8, 1]), A = U diag(sigma) V^* with Haar factors (built on the host
+    first, not timed).  Wall time of jsvd_gesvj on the resident input (HIP
+    events), sweeps, and the sigma error against the prescribed values: the
+    rounding of A to double moves sigma_i by up to about eps sigma_max, so the
+    relative error is given for sigma_i >= 1e-6 sigma_max and the absolute
+    error relative to sigma_max for all.  Run without the EVD's permutation:
+    with it, the round-robin iteration needs far more sweeps as n grows (more
+    than 128 at these sizes)."""
+    import numpy as np
+    t0 = time.perf_counter()
+    if cplx:
+        Ar, Ai, sig = inputs.plain_complex_4096()
+        m = n = 4096
+    else:
+        (Ar, sig), Ai = inputs.plain_real_tall(), None
+        m, n = Ar.shape
+    gen_s = time.perf_counter() - t0
+    dAr = J.to_device_fortran(Ar)
+    dAi = J.to_device_fortran(Ai) if cplx else None
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    r = J.gesvj(dAr, dAi, flags=flags)
+    b.record()
+    torch.cuda.synchronize()
+    t = a.elapsed_time(b) * 1e-3
+    sv = r["sv"].cpu().numpy()
+    big = sig >= 1e-6 * sig[0]
+    K = n - 1 if n % 2 == 0 else n
+    return {"m": m, "n": n, "complex": bool(cplx), "flags": flags, "status": r["status"], "sweeps": r["sweeps"],
+            "s": round(t, 3),
+            "ms_per_sweep": round(t * 1e3 / max(r["sweeps"], 1), 2), "steps": r["sweeps"] * K,
+            "max_rel_sigma_err_sigma_above_1e-6": float(np.max(np.abs(sv[big] - sig[big]) / sig[big])),
+            "max_abs_sigma_err_over_sigma_max": float(np.max(np.abs(sv - sig)) / sig[0]),
+            "input_generation_s": round(gen_s, 1)}
+
+
+def cpu_oracle_svd(inputs, sweeps_256=None, sweeps_large=None):
     """Context: the oracle (sequential C, one host thread) on the SVD
     workloads: one sweep of the 256 x 256 real SVD (scaled by the sweep count
     of the GPU run, which the oracle shares bit for bit), and two steps each of
     the real 8192 x 2048 and complex 4096 x 4096 workloads, extrapolated to one
-    sweep (K steps)."""
+    sweep (K steps) and to the whole SVD with the GPU run's sweep count."""
     import oracle
     res = {}
     A, _ = inputs.plain_real_256()
@@ -437,7 +477,10 @@ def cpu_oracle_svd(inputs, sweeps_256=None):
         dt = (time.perf_counter() - t0) / 2
         K = n - 1 if n % 2 == 0 else n
         res[f"step_{'c' if c else 'r'}{m}x{n}_s"] = round(dt, 4)
-        res[f"sweep_{'c' if c else 'r'}{m}x{n}_s_extrapolated"] = round(dt * K, 1)
+        tg = f"{'c' if c else 'r'}{m}x{n}"
+        res[f"sweep_{tg}_s_extrapolated"] = round(dt * K, 1)
+        if sweeps_large and sweeps_large.get(tg):
+            res[f"svd_{tg}_nopermute_h_extrapolated"] = round(dt * K * sweeps_large[tg] / 3600.0, 1)
     res["cores"] = 1
     res["kind"] = "oracle"
     return res
@@ -577,6 +620,8 @@ def main():
             for fp32 in (False, True):
                 tasks.append((f"sweep_{tag(m, n, c)}" + ("_f32" if fp32 else ""),
                               lambda m=m, n=n, c=c, fp32=fp32: sweep_time(torch, J, inputs, m, n, c, fp32=fp32)))
+        for (m, n, c) in big:
+            tasks.append((f"svd_{tag(m, n, c)}_nopermute", lambda c=c: svd_large(torch, J, inputs, c, J.NO_PERMUTE)))
         if not args.no_batched:
             for nm, fl in (("batched_permute", 0), ("batched_nopermute", J.NO_PERMUTE)):
                 tasks.append((nm, lambda fl=fl: batched_vs_plain(torch, J, inputs, args.batched, args.batched_plain,
@@ -586,7 +631,8 @@ def main():
                                                          args.serve_pool, J.NO_PERMUTE)))
         if not args.no_cpu:
             tasks.append(("cpu_oracle_svd", lambda: cpu_oracle_svd(
-                inputs, extra.get("svd_real256_permute", {}).get("sweeps"))))
+                inputs, extra.get("svd_real256_permute", {}).get("sweeps"),
+                {tg: extra.get(f"svd_{tg}_nopermute", {}).get("sweeps") for tg in ("r8192x2048", "c4096x4096")})))
         for nm, fn in tasks:
             if prefixes and not any(nm.startswith(x) for x in prefixes):
                 continue
