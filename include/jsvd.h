@@ -289,17 +289,40 @@ int jsvd_gesvj_f32(int m, int n, float *G_re, float *G_im, size_t ldg,
                    unsigned flags, void *stream);
 
 /* ----------------------------------------------------------------------
- * Many independent SVDs of uneven sizes in one persistent launch.  Arrays
- * of `count` host pointers / sizes describe the problems; every matrix
- * pointer is a device pointer.  Matrix i follows jsvd_gesvj exactly (same
- * results, bit for bit).  status[i] and sweeps[i] (host arrays) receive the
- * per-matrix outcome.  Synchronises.
+ * Many independent SVDs of uneven sizes in persistent launches, one per
+ * class of matrices (real or complex; rows up to 64, 128, 256 or 512).
+ * Arrays of `count` host pointers / sizes describe the problems; every
+ * matrix pointer is a device pointer.  Matrix i follows jsvd_gesvj exactly
+ * (same results, bit for bit, whatever the launch shape).  status[i] and
+ * sweeps[i] (host arrays) receive the per-matrix outcome.  Matrices of more
+ * than 512 rows or columns take the plain path one by one.  Synchronises.
  * ---------------------------------------------------------------------- */
 int jsvd_gesvj_batched(int count, const int *m, const int *n, const int *is_complex,
                        double *const *G_re, double *const *G_im, const size_t *ldg,
                        double *const *V_re, double *const *V_im, const size_t *ldv,
                        double *const *sv_e, double *const *sv_f,
                        int max_sweeps, int *sweeps, int *status, unsigned flags, void *stream);
+
+/* Launch shape of the batched SVD: the threads per matrix (one wavefront per
+ * pivot pair at a time) of each class are chosen by measurement, once per
+ * process and device: one sweep of up to 1024 random matrices of the class's
+ * median shape for each of 128, 256 and 512 threads, the fastest kept.
+ * jsvd_gesvj_batched measures the classes of its matrices that are not
+ * measured yet; jsvd_batched_tune does it ahead of time for a list of shapes
+ * (host arrays; is_complex may be NULL; flags as for the batched call, of
+ * which JSVD_COMPENSATED selects the compensated kernels).  Synchronises.  The
+ * results do not depend on the launch shape. */
+int jsvd_batched_tune(int count, const int *m, const int *n, const int *is_complex, unsigned flags,
+                      void *stream);
+/* Force the threads per matrix for every class (128, 256 or 512; 0 = the
+ * measured choice, the default).  A process-wide setting.  JSVD_EINVAL for
+ * other values. */
+int jsvd_batched_set_launch(int threads_per_matrix);
+/* The threads per matrix a batched call would use now for an m x n matrix:
+ * the forced value, else the measured one, else 256 (not measured yet);
+ * 0 when the shape is not batched (more than 512 rows or columns), JSVD_EINVAL
+ * for n < 1 or m < n. */
+int jsvd_batched_launch_of(int m, int n, int is_complex, unsigned flags);
 
 /* ----------------------------------------------------------------------
  * Serving: continuous batching of SVD requests under an HBM budget.

@@ -132,6 +132,12 @@ def lib():
         L.jsvd_gesvj.argtypes = [i, i, vp, vp, sz, vp, vp, sz, vp, vp, vp, i, _ct.POINTER(i), u, vp]
         L.jsvd_gesvj_batched.restype = i
         L.jsvd_gesvj_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, u, vp]
+        L.jsvd_batched_tune.restype = i
+        L.jsvd_batched_tune.argtypes = [i, vp, vp, vp, u, vp]
+        L.jsvd_batched_set_launch.restype = i
+        L.jsvd_batched_set_launch.argtypes = [i]
+        L.jsvd_batched_launch_of.restype = i
+        L.jsvd_batched_launch_of.argtypes = [i, i, i, u]
         L.jsvd_serve_create.restype = i
         L.jsvd_serve_create.argtypes = [_ct.POINTER(ServeConfig), _ct.POINTER(vp)]
         L.jsvd_serve_submit.restype = i
@@ -466,6 +472,31 @@ def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None):
         res[idx]["status"] = status[idx]
         res[idx]["sweeps"] = sweeps[idx]
     return res
+
+
+def batched_tune(shapes, flags=0, stream=None):
+    """Measure the batched launch shape (threads per matrix) of the classes of
+    these (m, n, is_complex) shapes (jsvd_batched_tune)."""
+    cnt = len(shapes)
+    I = _ct.c_int * max(cnt, 1)
+    m_a, n_a, c_a = I(), I(), I()
+    for idx, (m, n, c) in enumerate(shapes):
+        m_a[idx], n_a[idx], c_a[idx] = m, n, int(bool(c))
+    _check(lib().jsvd_batched_tune(cnt, m_a, n_a, c_a, flags, _stream(stream)), "jsvd_batched_tune")
+
+
+def batched_set_launch(threads_per_matrix):
+    """Force the batched threads per matrix (128, 256, 512; 0 = measured)."""
+    _check(lib().jsvd_batched_set_launch(threads_per_matrix), "jsvd_batched_set_launch")
+
+
+def batched_launch_of(m, n, cplx=False, flags=0):
+    """Threads per matrix a batched call would use now for an m x n matrix
+    (0: not a batched shape)."""
+    r = lib().jsvd_batched_launch_of(m, n, int(bool(cplx)), flags)
+    if r < 0:
+        _check(r, "jsvd_batched_launch_of")
+    return r
 
 
 # ---------------------------------------------------------------------------- serving

@@ -24,6 +24,14 @@ int batch_rows(int m, int n, int cplx);
 BatchItem make_batch_item(int m, int n, int cplx, double *Gr, double *Gi, size_t ldg, double *Vr, double *Vi,
                           size_t ldv, double *sv_e, double *sv_f);
 
+// The launch shape per class (real or complex, rows per lane): threads per
+// matrix, measured once per process and device for the classes of these
+// items (batch_tune), forced for all (batch_set_threads, 0 = measured), and
+// the current choice for one shape (0: not a batched shape).
+void batch_tune(const BatchItem *items, int count, unsigned flags, hipStream_t s);
+int batch_set_threads(int threads);
+int batch_threads_of(int m, int n, int cplx, unsigned flags);
+
 struct BatchLaunch;
 // Enqueue one persistent launch over the items (all batch_rows() != 0) and the
 // copy of their outcomes to pinned host memory; nullptr on failure.

@@ -1,16 +1,22 @@
-// batched.hip -- many independent SVDs of uneven sizes in one persistent
-// launch (the batched form of Alg. zvjsvd, arXiv:2202.08361).
+// batched.hip -- many independent SVDs of uneven sizes in persistent
+// launches (the batched form of Alg. zvjsvd, arXiv:2202.08361).
 //
-// One workgroup of 512 threads (8 wavefronts) owns one matrix at a time and
-// runs its whole SVD: initial scaling, sweeps of round-robin steps, the
-// convergence test and the finalisation.  Within a step each wavefront takes
-// pivot pairs (one pair per wavefront at a time, the same canonical sums as
-// every other launch shape, so each matrix's result is bit-for-bit the one
-// jsvd_gesvj gives); a workgroup barrier separates the steps, so no step ever
-// needs the host or a grid-wide synchronisation.  Workgroups pull matrices
-// from an atomic queue ordered by decreasing cost (longest first), which
-// balances the uneven sizes.  G and V are iterated in place in the caller's
+// One workgroup of NT threads owns one matrix at a time and runs its whole
+// SVD: initial scaling, sweeps of round-robin steps, the convergence test and
+// the finalisation.  Within a step each wavefront takes pivot pairs (one pair
+// per wavefront at a time, the same canonical sums as every other launch
+// shape, so each matrix's result is bit-for-bit the one jsvd_gesvj gives); a
+// workgroup barrier separates the steps, so no step ever needs the host or a
+// grid-wide synchronisation.  G and V are iterated in place in the caller's
 // buffers; the final sort is an in-place cycle permutation through LDS.
+//
+// The matrices are grouped by class (real or complex, rows per lane R): each
+// class runs as its own kernel instance, with registers and LDS sized for its
+// largest matrix, so that small matrices run at high occupancy.  Per class a
+// persistent grid (as many workgroups as fit on the GPU) pulls matrices from
+// an atomic queue ordered by decreasing cost, which balances the uneven
+// sizes.  The workgroup size of a class is chosen by measurement (batch_tune)
+// and cached for the process.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -18,6 +24,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -29,8 +36,6 @@
 
 namespace jsvd {
 
-constexpr int kBT = 512;           // threads per workgroup
-constexpr int kBWaves = kBT / 64;  // wavefronts per workgroup
 constexpr int kBMaxN = 512;        // largest n of the batched kernel
 constexpr int kBMaxRowsR = 512;    // largest m (real)
 constexpr int kBMaxRowsC = 512;    // largest m (complex)
@@ -43,17 +48,23 @@ struct BatchCtl {
     int nogs;
 };
 
+// LDS of a workgroup of NT threads on matrices of class R (n <= m <= 64 R)
+template <int R, int NT>
 struct BatchSmem {
-    double e[kBMaxN], f[kBMaxN];
-    int rank[kBMaxN], inv[kBMaxN];
-    double tmp[2 * (kBMaxRowsR + kBMaxN)];
-    double wM[kBWaves];
-    unsigned long long wt[kBWaves], wsw[kBWaves];
-    double red[kBWaves];
+    static constexpr int MM = 64 * R;
+    static constexpr int NN = MM < kBMaxN ? MM : kBMaxN;
+    static constexpr int NW = NT / 64;
+    double e[NN], f[NN];
+    int rank[NN], inv[NN];
+    double tmp[2 * (MM + NN)];
+    double wM[NW];
+    unsigned long long wt[NW], wsw[NW];
+    double red[NW];
     int item;
 };
 
 // block-wide max of a non-negative value (exact)
+template <int NW>
 __device__ __forceinline__ double block_max(double x, double *red)
 {
     x = wave_max(x);
@@ -61,7 +72,7 @@ __device__ __forceinline__ double block_max(double x, double *red)
     __syncthreads();
     double r = red[0];
 #pragma unroll
-    for (int w = 1; w < kBWaves; ++w) r = fmax(r, red[w]);
+    for (int w = 1; w < NW; ++w) r = fmax(r, red[w]);
     __syncthreads();
     return r;
 }
@@ -118,9 +129,10 @@ __device__ __forceinline__ Norm wave_colnorm(const double *xr, const double *xi,
     return o;
 }
 
-template <bool CPLX, int R, bool COMP>
-__device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nogs, BatchSmem &sm)
+template <bool CPLX, int R, bool COMP, int NT>
+__device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nogs, BatchSmem<R, NT> &sm)
 {
+    constexpr int kBT = NT, kBWaves = NT / 64;
     const int m = it.m, n = it.n;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const long long ldg = it.ldg, ldv = it.ldv;
@@ -136,7 +148,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
             mx = fmax(mx, fmin(fabs(Gr[(size_t)j * ldg + i]), INFINITY));
             if (CPLX) mx = fmax(mx, fmin(fabs(Gi[(size_t)j * ldg + i]), INFINITY));
         }
-    const double M0 = block_max(mx, sm.red);
+    const double M0 = block_max<kBWaves>(mx, sm.red);
     if (!(M0 <= 1.79769313486231570815e308) || M0 == 0.0) {
         if (tid == 0) {
             it.status = (M0 == 0.0) ? JSVD_EZERO : JSVD_ENONFINITE;
@@ -411,10 +423,11 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
     }
 }
 
-template <bool COMP>
-__global__ __launch_bounds__(kBT) void batched_kernel(BatchItem *items, const int *order, BatchCtl *ctl)
+// the matrices of one class (CPLX, R), NT threads per matrix
+template <bool COMP, bool CPLX, int R, int NT>
+__global__ __launch_bounds__(NT) void batched_kernel(BatchItem *items, const int *order, BatchCtl *ctl)
 {
-    __shared__ BatchSmem sm;
+    __shared__ BatchSmem<R, NT> sm;
     const int count = ctl->count;
     for (;;) {
         if (threadIdx.x == 0) sm.item = (int)atomicAdd(&ctl->next, 1u);
@@ -423,17 +436,7 @@ __global__ __launch_bounds__(kBT) void batched_kernel(BatchItem *items, const in
         __syncthreads();
         if (idx >= count) return;
         BatchItem it = items[order[idx]];
-        switch ((it.cplx ? 100 : 0) + it.R) {
-        case 1: svd_workgroup<false, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 2: svd_workgroup<false, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 4: svd_workgroup<false, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 8: svd_workgroup<false, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 101: svd_workgroup<true, 1, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 102: svd_workgroup<true, 2, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 104: svd_workgroup<true, 4, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        case 108: svd_workgroup<true, 8, COMP>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm); break;
-        default: break;
-        }
+        svd_workgroup<CPLX, R, COMP, NT>(it, ctl->max_sweeps, ctl->nosort, ctl->nogs, sm);
         if (threadIdx.x == 0) {
             items[order[idx]].status = it.status;
             items[order[idx]].sweeps = it.sweeps;
@@ -484,32 +487,264 @@ BatchItem make_batch_item(int m, int n, int cplx, double *Gr, double *Gi, size_t
     return it;
 }
 
+// ---------------------------------------------------------------------------
+// classes, launch shapes and the autotuner
+
+constexpr int kNumNT = 3;
+constexpr int kNTs[kNumNT] = {128, 256, 512};   // threads per matrix tried
+
+static int class_index(int cplx, int R)
+{
+    const int r = R <= 1 ? 0 : R <= 2 ? 1 : R <= 4 ? 2 : 3;
+    return (cplx ? 4 : 0) + r;
+}
+
+template <bool COMP, bool CPLX, int R, int NT>
+static hipError_t launch_class_t(BatchItem *items, const int *order, BatchCtl *ctl, int count, int ncu, hipStream_t s)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)batched_kernel<COMP, CPLX, R, NT>, NT, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    const int grid = std::min(count, per_cu * ncu);
+    hipLaunchKernelGGL((batched_kernel<COMP, CPLX, R, NT>), dim3(grid), dim3(NT), 0, s, items, order, ctl);
+    return hipGetLastError();
+}
+
+template <bool COMP, bool CPLX, int R>
+static hipError_t launch_class_r(int NT, BatchItem *items, const int *order, BatchCtl *ctl, int count, int ncu,
+                                 hipStream_t s)
+{
+    switch (NT) {
+    case 128: return launch_class_t<COMP, CPLX, R, 128>(items, order, ctl, count, ncu, s);
+    case 256: return launch_class_t<COMP, CPLX, R, 256>(items, order, ctl, count, ncu, s);
+    case 512: return launch_class_t<COMP, CPLX, R, 512>(items, order, ctl, count, ncu, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <bool COMP, bool CPLX>
+static hipError_t launch_class_c(int R, int NT, BatchItem *items, const int *order, BatchCtl *ctl, int count, int ncu,
+                                 hipStream_t s)
+{
+    switch (R) {
+    case 1: return launch_class_r<COMP, CPLX, 1>(NT, items, order, ctl, count, ncu, s);
+    case 2: return launch_class_r<COMP, CPLX, 2>(NT, items, order, ctl, count, ncu, s);
+    case 4: return launch_class_r<COMP, CPLX, 4>(NT, items, order, ctl, count, ncu, s);
+    case 8: return launch_class_r<COMP, CPLX, 8>(NT, items, order, ctl, count, ncu, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// one persistent launch over the `count` matrices of class (cplx, R) listed
+// (longest first) in order
+static hipError_t launch_class(bool comp, int cplx, int R, int NT, BatchItem *items, const int *order, BatchCtl *ctl,
+                               int count, int ncu, hipStream_t s)
+{
+    if (comp)
+        return cplx ? launch_class_c<true, true>(R, NT, items, order, ctl, count, ncu, s)
+                    : launch_class_c<true, false>(R, NT, items, order, ctl, count, ncu, s);
+    return cplx ? launch_class_c<false, true>(R, NT, items, order, ctl, count, ncu, s)
+                : launch_class_c<false, false>(R, NT, items, order, ctl, count, ncu, s);
+}
+
+// the tuner's results: threads per matrix per (device, compensated, class);
+// 0 = not measured yet.  A forced value (jsvd_batched_set_launch) overrides.
+constexpr int kMaxDev = 64;
+static std::mutex g_tune_mu;
+static int g_tuned[kMaxDev][2][8];
+static int g_forced_nt = 0;
+
+// fill a sample matrix with values in [-1, 1) from a counter hash
+__global__ void batch_fill_kernel(double *x, size_t count, unsigned long long seed)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        unsigned long long z = seed + 0x9E3779B97F4A7C15ull * (i + 1);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        x[i] = (double)(z >> 11) * 0x1p-52 - 1.0;
+    }
+}
+
+// Measure the threads per matrix of one class: one sweep of up to 1024
+// sample matrices of the class's median shape (random entries), per
+// candidate, after a warm-up; the fastest wins.  Returns 0 on failure.
+static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, hipStream_t s)
+{
+    const int c = cplx ? 2 : 1;
+    const size_t per = (size_t)c * ((size_t)m * n + (size_t)n * n) + 2 * (size_t)n;
+    size_t S = std::min<size_t>(1024, std::max<size_t>(1, ((size_t)1 << 30) / (per * sizeof(double))));
+    const size_t bytes = S * per * sizeof(double) + 4096 + S * (sizeof(BatchItem) + sizeof(int));
+    char *mem = nullptr;
+    if (hipMalloc(&mem, bytes) != hipSuccess) return 0;
+    double *base = (double *)mem;
+    std::vector<BatchItem> items(S);
+    std::vector<int> order(S);
+    for (size_t i = 0; i < S; ++i) {
+        double *G = base + i * per;
+        double *V = G + (size_t)c * m * n;
+        double *e = V + (size_t)c * n * n;
+        items[i] = make_batch_item(m, n, cplx, G, cplx ? G + (size_t)m * n : nullptr, m, V,
+                                   cplx ? V + (size_t)n * n : nullptr, n, e, e + n);
+        order[i] = (int)i;
+    }
+    char *tail = mem + S * per * sizeof(double);
+    BatchItem *ditems = (BatchItem *)tail;
+    int *dorder = (int *)(tail + S * sizeof(BatchItem));
+    BatchCtl *dctl = (BatchCtl *)(((uintptr_t)(dorder + S) + 255) & ~(uintptr_t)255);
+    hipEvent_t a = nullptr, b = nullptr;
+    int best = 0;
+    float best_ms = 0.f;
+    bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+              hipMemcpyAsync(dorder, order.data(), sizeof(int) * S, hipMemcpyHostToDevice, s) == hipSuccess;
+    for (int ci = 0; ok && ci < kNumNT; ++ci) {
+        const int NT = kNTs[ci];
+        for (int rep = 0; ok && rep < 2; ++rep) {
+            // fresh random G (the SVD works in place) and fresh queue
+            hipLaunchKernelGGL(batch_fill_kernel, dim3(1024), dim3(256), 0, s, base, S * per, 1234567ull);
+            BatchCtl ctl;
+            ctl.next = 0;
+            ctl.count = (int)S;
+            ctl.max_sweeps = 1;
+            ctl.nosort = 0;
+            ctl.nogs = 0;
+            ok = hipGetLastError() == hipSuccess &&
+                 hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * S, hipMemcpyHostToDevice, s) == hipSuccess &&
+                 hipMemcpyAsync(dctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s) == hipSuccess &&
+                 hipEventRecord(a, s) == hipSuccess &&
+                 launch_class(comp, cplx, R, NT, ditems, dorder, dctl, (int)S, ncu, s) == hipSuccess &&
+                 hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+            float ms = 0.f;
+            if (ok && rep == 1 && hipEventElapsedTime(&ms, a, b) == hipSuccess && (best == 0 || ms < best_ms)) {
+                best = NT;
+                best_ms = ms;
+            }
+        }
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(mem);
+    return ok ? best : 0;
+}
+
+static int current_device_ncu(int *dev)
+{
+    int ncu = 256;
+    *dev = 0;
+    (void)hipGetDevice(dev);
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, *dev) != hipSuccess || ncu <= 0) ncu = 256;
+    return ncu;
+}
+
+// threads per matrix for a class: forced, else measured (once per process
+// and device), else 256
+static int class_threads(bool comp, int cplx, int R, int m, int n, hipStream_t s, bool measure)
+{
+    int dev = 0;
+    const int ncu = current_device_ncu(&dev);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_forced_nt) return g_forced_nt;
+    if (dev < 0 || dev >= kMaxDev) return 256;
+    int &t = g_tuned[dev][comp ? 1 : 0][class_index(cplx, R)];
+    if (t == 0 && measure) t = measure_class(comp, cplx, R, m, n, ncu, s);
+    return t ? t : 256;
+}
+
+void batch_tune(const BatchItem *items, int cnt, unsigned flags, hipStream_t s)
+{
+    const bool comp = (flags & JSVD_COMPENSATED) != 0;
+    // the median shape of each class present
+    std::vector<std::pair<double, int>> by[8];
+    for (int i = 0; i < cnt; ++i)
+        by[class_index(items[i].cplx, items[i].R)].push_back({(double)items[i].n * items[i].n * items[i].m, i});
+    for (int k = 0; k < 8; ++k) {
+        if (by[k].empty()) continue;
+        std::sort(by[k].begin(), by[k].end());
+        const BatchItem &it = items[by[k][by[k].size() / 2].second];
+        (void)class_threads(comp, it.cplx, it.R, it.m, it.n, s, true);
+    }
+}
+
+int batch_threads_of(int m, int n, int cplx, unsigned flags)
+{
+    const int R = batch_rows(m, n, cplx);
+    if (!R) return 0;
+    return class_threads((flags & JSVD_COMPENSATED) != 0, cplx, R, m, n, nullptr, false);
+}
+
+int batch_set_threads(int nt)
+{
+    if (nt != 0 && nt != 128 && nt != 256 && nt != 512) return JSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_forced_nt = nt;
+    return JSVD_OK;
+}
+
 struct BatchLaunch {
     void *dmem;
     BatchItem *host;   // pinned; results land here
     int count;
 };
 
+// Streams of the classes (created once per device, default priority): the
+// classes of a batch run side by side, forked from the caller's stream and
+// joined back into it, so that one class's longest matrices overlap the
+// others' instead of adding up.
+static std::mutex g_stream_mu;
+static hipStream_t g_class_streams[kMaxDev][8];
+
+static bool class_streams(int dev, hipStream_t *out)
+{
+    if (dev < 0 || dev >= kMaxDev) return false;
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    for (int k = 0; k < 8; ++k) {
+        if (!g_class_streams[dev][k] &&
+            hipStreamCreateWithFlags(&g_class_streams[dev][k], hipStreamNonBlocking) != hipSuccess) {
+            g_class_streams[dev][k] = nullptr;
+            return false;
+        }
+        out[k] = g_class_streams[dev][k];
+    }
+    return true;
+}
+
 BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsigned flags, hipStream_t s)
 {
     if (cnt <= 0) return nullptr;
+    const bool comp = (flags & JSVD_COMPENSATED) != 0;
+    batch_tune(items, cnt, flags, s);
     BatchLaunch *bl = new (std::nothrow) BatchLaunch;
     if (!bl) return nullptr;
     bl->count = cnt;
     bl->dmem = nullptr;
     bl->host = nullptr;
-    // longest first: cost ~ c n^2 (m + n) per sweep
+    // per class, longest first: cost ~ c n^2 (m + n) per sweep
+    auto cost = [&](int i) {
+        return (items[i].cplx ? 2.0 : 1.0) * items[i].n * (double)items[i].n * (items[i].m + items[i].n);
+    };
     std::vector<int> order(cnt);
     for (int i = 0; i < cnt; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-        const double ca = (items[a].cplx ? 2.0 : 1.0) * items[a].n * (double)items[a].n * (items[a].m + items[a].n);
-        const double cb = (items[b].cplx ? 2.0 : 1.0) * items[b].n * (double)items[b].n * (items[b].m + items[b].n);
-        return ca > cb;
+        const int ka = class_index(items[a].cplx, items[a].R), kb = class_index(items[b].cplx, items[b].R);
+        if (ka != kb) return ka > kb;   // complex before real, larger R first
+        return cost(a) > cost(b);
     });
+    int first[9], ncls = 0, cls_of[8];
+    for (int i = 0; i < cnt; ++i) {
+        const int k = class_index(items[order[i]].cplx, items[order[i]].R);
+        if (ncls == 0 || cls_of[ncls - 1] != k) {
+            cls_of[ncls] = k;
+            first[ncls++] = i;
+        }
+    }
+    first[ncls] = cnt;
     const size_t oItems = 0;
     const size_t oOrder = (sizeof(BatchItem) * cnt + 255) & ~(size_t)255;
     const size_t oCtl = oOrder + ((sizeof(int) * cnt + 255) & ~(size_t)255);
-    const size_t bytes = oCtl + 256;
+    const size_t bytes = oCtl + 256 * (size_t)ncls;
     if (hipMalloc(&bl->dmem, bytes) != hipSuccess) {
         delete bl;
         return nullptr;
@@ -522,31 +757,52 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     char *h = (char *)bl->host;
     memcpy(h + oItems, items, sizeof(BatchItem) * cnt);
     memcpy(h + oOrder, order.data(), sizeof(int) * cnt);
-    BatchCtl ctl;
-    ctl.next = 0;
-    ctl.count = cnt;
-    ctl.max_sweeps = max_sweeps;
-    ctl.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
-    ctl.nogs = (flags & JSVD_NO_GS) ? 1 : 0;
-    memcpy(h + oCtl, &ctl, sizeof(ctl));
-    char *dm = (char *)bl->dmem;
-    int dev = 0, ncu = 256;
-    (void)hipGetDevice(&dev);
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) ncu = 256;
-    bool ok = hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
-    if (ok) {
-        const int grid = std::min(cnt, 2 * ncu);
-        if (flags & JSVD_COMPENSATED)
-            hipLaunchKernelGGL(batched_kernel<true>, dim3(grid), dim3(kBT), 0, s, (BatchItem *)(dm + oItems),
-                               (const int *)(dm + oOrder), (BatchCtl *)(dm + oCtl));
-        else
-            hipLaunchKernelGGL(batched_kernel<false>, dim3(grid), dim3(kBT), 0, s, (BatchItem *)(dm + oItems),
-                               (const int *)(dm + oOrder), (BatchCtl *)(dm + oCtl));
-        ok = hipGetLastError() == hipSuccess &&
-             hipMemcpyAsync(bl->host, dm, sizeof(BatchItem) * cnt, hipMemcpyDeviceToHost, s) == hipSuccess;
+    for (int c = 0; c < ncls; ++c) {
+        BatchCtl ctl;
+        ctl.next = 0;
+        ctl.count = first[c + 1] - first[c];
+        ctl.max_sweeps = max_sweeps;
+        ctl.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+        ctl.nogs = (flags & JSVD_NO_GS) ? 1 : 0;
+        memcpy(h + oCtl + 256 * (size_t)c, &ctl, sizeof(ctl));
     }
+    char *dm = (char *)bl->dmem;
+    int dev = 0;
+    const int ncu = current_device_ncu(&dev);
+    bool ok = hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    // one class on the caller's stream, several side by side on the class streams
+    hipStream_t cs[8];
+    hipEvent_t fork = nullptr, join[8] = {};
+    const bool side = ncls > 1 && class_streams(dev, cs);
+    if (side) {
+        ok = ok && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
+             hipEventRecord(fork, s) == hipSuccess;
+    }
+    for (int c = 0; ok && c < ncls; ++c) {
+        const BatchItem &it0 = items[order[first[c]]];
+        const int NT = class_threads(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
+        hipStream_t ls = s;
+        if (side) {
+            ls = cs[c];
+            ok = hipStreamWaitEvent(ls, fork, 0) == hipSuccess;
+        }
+        ok = ok && launch_class(comp, it0.cplx, it0.R, NT, (BatchItem *)(dm + oItems),
+                                (const int *)(dm + oOrder) + first[c], (BatchCtl *)(dm + oCtl + 256 * (size_t)c),
+                                first[c + 1] - first[c], ncu, ls) == hipSuccess;
+        if (side && ok) {
+            ok = hipEventCreateWithFlags(&join[c], hipEventDisableTiming) == hipSuccess &&
+                 hipEventRecord(join[c], ls) == hipSuccess && hipStreamWaitEvent(s, join[c], 0) == hipSuccess;
+        }
+    }
+    if (fork) (void)hipEventDestroy(fork);
+    for (int c = 0; c < 8; ++c)
+        if (join[c]) (void)hipEventDestroy(join[c]);
+    ok = ok && hipMemcpyAsync(bl->host, dm, sizeof(BatchItem) * cnt, hipMemcpyDeviceToHost, s) == hipSuccess;
     if (!ok) {
+        // nothing may still use the buffers when they are freed
         (void)hipStreamSynchronize(s);
+        if (side)
+            for (int c = 0; c < ncls; ++c) (void)hipStreamSynchronize(cs[c]);
         batch_release(bl);
         return nullptr;
     }
@@ -566,6 +822,31 @@ void batch_release(BatchLaunch *bl)
 } // namespace jsvd
 
 using namespace jsvd;
+
+extern "C" int jsvd_batched_tune(int count, const int *m, const int *n, const int *is_complex, unsigned flags,
+                                 void *stream)
+{
+    if (count < 0 || (count > 0 && (!m || !n))) return JSVD_EINVAL;
+    if (flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
+    std::vector<BatchItem> items;
+    for (int i = 0; i < count; ++i) {
+        const int c = is_complex ? (is_complex[i] != 0) : 0;
+        if (n[i] < 1 || m[i] < n[i]) return JSVD_EINVAL;
+        if (!batch_rows(m[i], n[i], c)) continue;
+        items.push_back(make_batch_item(m[i], n[i], c, nullptr, nullptr, (size_t)m[i], nullptr, nullptr, (size_t)n[i],
+                                        nullptr, nullptr));
+    }
+    if (!items.empty()) batch_tune(items.data(), (int)items.size(), flags, (hipStream_t)stream);
+    return hipStreamSynchronize((hipStream_t)stream) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
+}
+
+extern "C" int jsvd_batched_set_launch(int threads_per_matrix) { return batch_set_threads(threads_per_matrix); }
+
+extern "C" int jsvd_batched_launch_of(int m, int n, int is_complex, unsigned flags)
+{
+    if (n < 1 || m < n) return JSVD_EINVAL;
+    return batch_threads_of(m, n, is_complex != 0, flags);
+}
 
 extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const int *is_complex,
                                   double *const *G_re, double *const *G_im, const size_t *ldg,

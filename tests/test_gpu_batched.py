@@ -98,3 +98,39 @@ def test_batched_workload_sample():
         sv = np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))
         big = sig >= 1e-6 * sig[0]
         assert np.max(np.abs(sv[big] - sig[big]) / sig[big]) < 1e-9
+
+
+def test_batched_launch_shapes_identical():
+    """Every forced launch shape (128, 256, 512 threads per matrix) gives the
+    same bits for every class (real and complex, rows up to 64 ... 512), the
+    plain path's, and the measured choice is one of them."""
+    shapes = [(16, 16, False, 1e2), (60, 33, True, 1e4), (100, 70, False, 1e5), (128, 128, True, 1e3),
+              (250, 130, False, 1e6), (256, 200, True, 1e2), (300, 257, False, 1e5), (511, 256, True, 1e8),
+              (512, 300, False, 1e4)]
+    host = _mats(shapes, 4)
+    ref = None
+    try:
+        for nt in (128, 256, 512):
+            J().batched_set_launch(nt)
+            for (m, n, c, _) in shapes:
+                assert J().batched_launch_of(m, n, c) == nt
+            res = _check_batch(host) if nt == 256 else None
+            if res is None:
+                dev = [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host]
+                res = J().gesvj_batched(dev)
+                torch.cuda.synchronize()
+            cur = [[r[k] for k in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f")] + [r["sweeps"]] for r in res]
+            if ref is not None:
+                for a, b in zip(cur, ref):
+                    assert a[-1] == b[-1]
+                    for x, y in zip(a[:-1], b[:-1]):
+                        assert _same(x, y)
+            ref = cur
+    finally:
+        J().batched_set_launch(0)
+    J().batched_tune([(m, n, c) for (m, n, c, _) in shapes])
+    for (m, n, c, _) in shapes:
+        assert J().batched_launch_of(m, n, c) in (128, 256, 512)
+    assert J().batched_launch_of(700, 100, False) == 0
+    with pytest.raises(Exception):
+        J().batched_set_launch(100)
