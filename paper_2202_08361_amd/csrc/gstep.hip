@@ -11,9 +11,11 @@
 //   EVD with the other's memory traffic.  The pair's outcome (rotation,
 //   permutation, max-norm) goes to the step's slot of an outcome log.
 // * the fold of a step into the device scalars (M~, counts, s, k): done at
-//   the start of the next such step (its workgroups derive k and M~ from the
-//   logged step, its workgroup 0 updates the scalars), or by fold_kernel
-//   when the scalars are read; no workgroup needs an atomic.
+//   the start of the next such step (its workgroups derive k and the exponent
+//   of M~ from the logged step, its workgroup 0 updates the scalars), or by
+//   fold_kernel when the scalars are read.  The only atomic is one relaxed
+//   max per rotating workgroup into the step's max-norm key; no workgroup
+//   waits on another.
 //
 // V is not touched per step.  Its rows never mix, so the rotations of up to
 // a log's worth of consecutive steps are applied to it in one pass
