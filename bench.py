@@ -72,7 +72,37 @@ def trace_summary(db):
     return "\n".join(out)
 
 
-def counters_table(fetch_db, write_db, calib_mib):
+def last_call_table(db, pattern):
+    """The dispatches of the last call into kernels whose names contain
+    `pattern`: the last group of such dispatches that overlap in time (the
+    classes of one batched call run on concurrent streams; the tuner's
+    measurement launches before it run one after another)."""
+    rows = _rocpd_rows(db, "select name, start, end, grid_x, workgroup_x, vgpr_count, accum_vgpr_count, "
+                           "lds_size from kernels order by start")
+    rows = [r for r in rows if pattern in r[0]]
+    if not rows:
+        raise SystemExit(f"no dispatch of a kernel matching {pattern!r}")
+    groups, end = [], None
+    for r in rows:
+        if end is None or r[1] >= end:
+            groups.append([])
+            end = r[2]
+        groups[-1].append(r)
+        end = max(end, r[2])
+    last = groups[-1]
+    t0 = min(r[1] for r in last)
+    span = (max(r[2] for r in last) - t0) / 1e3
+    out = [f"Last call: {len(last)} dispatches on concurrent streams, span {span:.1f} us "
+           f"(first start to last end).", "",
+           "| kernel | workgroups | threads | VGPRs (arch + acc) | LDS B | start us | duration us |",
+           "|---|---|---|---|---|---|---|"]
+    for nm, st, en, gx, wx, vg, ag, lds in last:
+        out.append(f"| `{nm[:90]}` | {gx // max(wx, 1)} | {wx} | {vg} + {ag} | {lds} | {(st - t0) / 1e3:.1f} | "
+                   f"{(en - st) / 1e3:.1f} |")
+    return "\n".join(out)
+
+
+def counters_table(fetch_db, write_db, calib_mib, last_of=None):
     """Per kernel: the mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of one
     counter run each, and the HBM bytes per dispatch after scaling each
     counter by what it reads for the plain device copy of calib_mib MiB."""
@@ -86,6 +116,12 @@ def counters_table(fetch_db, write_db, calib_mib):
             acc.setdefault(nm, []).append(v)
         return acc
     fk, wk = per_kernel(fetch), per_kernel(write)
+    if last_of:
+        # only the last dispatch of each matching kernel (that of the timed call)
+        for acc in (fk, wk):
+            for nm in acc:
+                if last_of in nm:
+                    acc[nm] = acc[nm][-1:]
     cf = [v for nm, vs in fk.items() if "copyBuffer" in nm for v in vs]
     cw = [v for nm, vs in wk.items() if "copyBuffer" in nm for v in vs]
     if not cf or not cw:
@@ -293,16 +329,37 @@ def sweep_time(torch, J, inputs, m, n, cplx, fp32=False):
                 us_per_step=s.elapsed_time(e) * 1e3 / K, transformations_in_sweep=q["last_sweep_T"], swaps_in_sweep=q["last_sweep_swaps"])
 
 
+_batched_cache = {}
+
+
+def batched_inputs(inputs, count):
+    """The first `count` matrices of the batched workload with their prescribed
+    singular values, kept for the runs that follow.  Every matrix has its own
+    seeded stream, so they are generated in parallel host threads, each with a
+    one-thread BLAS (the products then round the same at any worker count)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    if _batched_cache.get("count", -1) >= count:
+        return _batched_cache["mats"][:count], _batched_cache["sigs"][:count]
+    m, n, kappa = inputs.batched_shapes(10000)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    out = []
+    with threadpool_limits(1), ThreadPoolExecutor(workers) as ex:
+        for c0 in range(0, count, 1000):
+            ids = range(c0, min(count, c0 + 1000))
+            out += list(ex.map(lambda i: inputs.batched_matrix(i, int(m[i]), int(n[i]), float(kappa[i])), ids))
+            log(f"[bench]   generated {len(out)} of {count} matrices ({time.perf_counter() - t0:.1f} s)")
+    _batched_cache.update(count=count, mats=[a for a, _ in out], sigs=[sg for _, sg in out])
+    return _batched_cache["mats"], _batched_cache["sigs"]
+
+
 def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
     """The first `count` matrices of the batched workload in one call, and the
     first `plain_count` of them one by one through jsvd_gesvj."""
     import numpy as np
     m, n, kappa = inputs.batched_shapes(10000)
-    mats, sigs = [], []
-    for i in range(count):
-        A, sig = inputs.batched_matrix(i, int(m[i]), int(n[i]), float(kappa[i]))
-        mats.append(A)
-        sigs.append(sig)
+    mats, sigs = batched_inputs(inputs, count)
     dev = [(J.to_device_fortran(A), None) for A in mats]
     # the launch shape of each class present is measured once, before timing
     shapes = [(int(m[i]), int(n[i]), False) for i in range(count)]
@@ -508,7 +565,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched", type=int, default=500)
+    ap.add_argument("--batched", type=int, default=500, help="matrices of the batched workload (at most 10000)")
     ap.add_argument("--batched-plain", type=int, default=25)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
@@ -524,15 +581,21 @@ def main():
     ap.add_argument("--counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="print per-kernel HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE databases of runs "
                          "made with --calib-copy, and exit")
+    ap.add_argument("--last-call", metavar="PATTERN",
+                    help="with --trace-summary: also list the dispatches of the last call into kernels matching "
+                         "PATTERN; with --counters: count only the last dispatch of each such kernel")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="derive the EVD kernels' HBM bytes per launch from FETCH_SIZE / WRITE_SIZE "
                          "databases of runs made with --calib-copy, write profiles/evd2_traffic.json, exit")
     args = ap.parse_args()
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
+        if args.last_call:
+            print()
+            print(last_call_table(args.trace_summary, args.last_call))
         return
     if args.counters:
-        print(counters_table(args.counters[0], args.counters[1], args.calib_copy or 512))
+        print(counters_table(args.counters[0], args.counters[1], args.calib_copy or 512, args.last_call))
         return
     if args.traffic_from:
         rec, md = traffic_from(args.traffic_from[0], args.traffic_from[1], args.calib_copy or 512)
