@@ -404,7 +404,10 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
 
 def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32, budget=64 << 30,
                 slots=16, drain_limit=120.0):
-    """Poisson arrivals replayed from a pre-generated pool of request matrices."""
+    """Poisson arrivals replayed from a pre-generated pool of request matrices.
+    Beside the server's figures: the time the plain path (jsvd_gesvj, one
+    request after another) would need for the same completed requests, from
+    one timed solve of each pool matrix."""
     import numpy as np
     t_arr, cplx, m, n, kappa = inputs.serve_stream(rate, duration)
     g = inputs.rng(inputs.CFG_SERVE, 12345)
@@ -415,7 +418,7 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
         pool.append((J.to_device_fortran(Ar), None if Ai is None else J.to_device_fortran(Ai)))
     torch.cuda.synchronize()
     srv = J.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=max_queue, flags=flags)
-    outstanding, rejected, submitted = {}, 0, 0
+    outstanding, rejected, submitted, done = {}, 0, 0, []
     t0 = time.perf_counter()
     for i, ta in enumerate(t_arr):
         while time.perf_counter() - t0 < ta:
@@ -436,11 +439,11 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
             rejected += 1
             continue
         submitted += 1
-        outstanding[t] = (gr, gi)
+        outstanding[t] = (gr, gi, int(pidx[i]))
         if i % 64 == 0:
             for tk in [tk for tk in outstanding if srv.poll(tk)[0]]:
                 srv.wait(tk)
-                outstanding.pop(tk)
+                done.append(outstanding.pop(tk)[2])
     t_end_arrivals = time.perf_counter() - t0
     deadline = time.perf_counter() + drain_limit
     for tk in list(outstanding):
@@ -448,18 +451,35 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
             time.sleep(0.001)
         if srv.poll(tk)[0]:
             srv.wait(tk)
-            outstanding.pop(tk)
+            done.append(outstanding.pop(tk)[2])
     wall = time.perf_counter() - t0
     st = srv.stats()
     unfinished = len(outstanding)
     if unfinished == 0:
         srv.close()
+    # the plain path on the same requests: each pool matrix used once, timed
+    solo = {}
+    for kq in sorted(set(done)):
+        Gr, Gi = pool[kq]
+        gr = J.fortran_empty(*Gr.shape)
+        gr.copy_(Gr)
+        gi = None
+        if Gi is not None:
+            gi = J.fortran_empty(*Gi.shape)
+            gi.copy_(Gi)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        J.gesvj(gr, gi, flags=flags, overwrite=True)
+        torch.cuda.synchronize()
+        solo[kq] = time.perf_counter() - ts
+    plain_s = sum(solo[kq] for kq in done)
     return dict(offered_rate=rate, arrival_window_s=duration, offered=len(t_arr), submitted=submitted,
                 rejected_backpressure=rejected, completed=st["completed"], unfinished_at_limit=unfinished,
                 wall_s=wall, arrivals_s=t_end_arrivals, svds_per_s=st["completed"] / wall,
                 p50_latency_ms=st["p50_ns"] / 1e6, p99_latency_ms=st["p99_ns"] / 1e6,
                 p50_queue_ms=st["p50_queue_ns"] / 1e6, p99_queue_ms=st["p99_queue_ns"] / 1e6,
-                pool=pool_size, max_queue=max_queue, slots=slots, flags=flags)
+                pool=pool_size, max_queue=max_queue, slots=slots, flags=flags,
+                plain_same_requests_s=plain_s, served_vs_plain=(plain_s / wall) if wall > 0 else None)
 
 
 def svd_plain(torch, J, inputs, flags, fp32=False):
@@ -565,7 +585,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched", type=int, default=500, help="matrices of the batched workload (at most 10000)")
+    ap.add_argument("--batched", type=int, default=10000, help="matrices of the batched workload (at most 10000)")
     ap.add_argument("--batched-plain", type=int, default=25)
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
