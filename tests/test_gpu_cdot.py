@@ -129,7 +129,8 @@ def _check_state(ost, sv, tag):
 
 
 @pytest.mark.parametrize("m,n,cplx,threads", [(70, 24, True, 0), (100, 37, False, 0), (300, 40, False, 256),
-                                               (1500, 64, False, 0), (2100, 20, True, 0), (900, 31, True, 512)])
+                                               (1500, 64, False, 0), (2100, 20, True, 0), (4200, 12, False, 0),
+                                               (900, 31, True, 512)])
 def test_step_compensated_bitwise(ora, m, n, cplx, threads):
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 960 + m)
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
