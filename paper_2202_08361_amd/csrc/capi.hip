@@ -113,7 +113,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct StateLayout {
     long long ldg, ldv, vstride;
-    size_t oG, oV, oE, oF, oR, oS, oM, oP, oX, oH, total;
+    size_t oG, oV, oE, oF, oR, oS, oM, oP, oQ, oX, oH, total;
 };
 
 // es: bytes per element of the working precision
@@ -135,6 +135,7 @@ static StateLayout state_layout(int m, int n, int cplx, size_t es)
     // the outcome log: kVlogSteps slots of the step's pair outcomes
     L.vstride = round_up((long long)(n + 1) / 2, 4LL);
     L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)L.vstride * kVlogSteps);
+    L.oQ = off; off = align_up(off + sizeof(double) * (size_t)L.vstride * kVlogSteps);
     L.oH = off; off = align_up(off + sizeof(StepHdr) * (size_t)kVlogSteps);
     L.oX = off; off = align_up(off + sizeof(unsigned long long) * (size_t)kVlogSteps);
     L.total = off;
@@ -223,6 +224,7 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
     st->rank = (int *)(b + L.oR);
     st->maxbits = (unsigned long long *)(b + L.oM);
     st->vlog = (PairParam *)(b + L.oP);
+    st->vmx = (double *)(b + L.oQ);
     st->vhdr = (StepHdr *)(b + L.oH);
     st->vkey = (unsigned long long *)(b + L.oX);
     st->vlog_stride = L.vstride;
@@ -428,6 +430,7 @@ static StepSlot slot_of(jsvd_state st, int j)
 {
     StepSlot z;
     z.prm = st->vlog + (size_t)j * st->vlog_stride;
+    z.mx = st->vmx + (size_t)j * st->vlog_stride;
     z.hdr = st->vhdr + j;
     z.mxkey = st->vkey + j;
     return z;
@@ -438,9 +441,9 @@ static StepSlot slot_of(jsvd_state st, int j)
 static hipError_t settle(jsvd_state st, hipStream_t s)
 {
     if (st->vlast < 0) return hipSuccess;
-    const PairParam *prm = slot_of(st, st->vlast).prm;
+    const StepSlot z = slot_of(st, st->vlast);
     st->vlast = -1;
-    return st->fp32 ? launch_fold(st->df, prm, s) : launch_fold(st->d, prm, s);
+    return st->fp32 ? launch_fold(st->df, z.prm, z.mx, s) : launch_fold(st->d, z.prm, z.mx, s);
 }
 
 // one step on a state whose V is in the path's layout: on the large-column
@@ -458,6 +461,7 @@ static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s)
     }
     StepSlot prev;
     prev.prm = nullptr;
+    prev.mx = nullptr;
     prev.hdr = nullptr;
     prev.mxkey = nullptr;
     if (st->vlast >= 0) prev = slot_of(st, st->vlast);

@@ -56,7 +56,7 @@ constexpr int gpair_wgs_per_cu()
 constexpr int kFoldW = 1024;   // threads of the fold kernel
 
 template <int FW, typename T>
-__device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *prm, int npairs)
+__device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *prm, const double *pmx, int npairs)
 {
     constexpr int NW = FW / 64;
     __shared__ double smx[NW];
@@ -89,7 +89,7 @@ __device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *p
             const int l = l0 + t + FW * u;
             const int lc = l < npairs ? l : 0;
             const int f = prm[lc].flag;
-            const double mv = prm[lc].mx;
+            const double mv = pmx[lc];
             fl[u] = l < npairs ? f : 0;
             m4[u] = mv;
         }
@@ -192,9 +192,10 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
         if (t == 0) {
             PairParam z;
             z.c = 1.0;
-            z.C = z.S = z.mx = 0.0;
+            z.C = z.S = 0.0;
             z.pq = z.flag = 0;
             prm[l] = z;
+            slot.mx[l] = 0.0;
         }
         return;
     }
@@ -231,7 +232,7 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
         eMt = max(getexp(Mp2), step_max_exp(pkey, k - 1));
         // the previous step's fold: the exact M~ of this step, the counts
         if (l == 0) {
-            const unsigned long long Mt_bits = fold_step<W, T>(d, prev.prm, npairs);
+            const unsigned long long Mt_bits = fold_step<W, T>(d, prev.prm, prev.mx, npairs);
             if (t == 0) {
                 slot.hdr->k = k;
                 slot.hdr->Mt_bits = Mt_bits;
@@ -254,7 +255,7 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
     pp.c = 1.0;
     pp.C = 0.0;
     pp.S = 0.0;
-    pp.mx = 0.0;
+    double pmx = 0.0;
     if (!valid) {
         // the column sitting out (odd n): only the rescaling applies
         if (rescale) {
@@ -263,7 +264,10 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
                 if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
             }
         }
-        if (t == 0) prm[l] = pp;
+        if (t == 0) {
+            prm[l] = pp;
+            slot.mx[l] = pmx;
+        }
     } else {
         if (rescale) {
 #pragma unroll
@@ -284,7 +288,7 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
         if (dc.transform) {
             T mm[1] = {transform_regs<CPLX, R>(xr, xi, dc)};
             group_max<W, 1>(mm, mxs + 2 * (W / 64));
-            pp.mx = mm[0];
+            pmx = mm[0];
             pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
             pp.c = dc.c;
             pp.C = dc.C;
@@ -308,7 +312,8 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
         }
         if (t == 0) {
             prm[l] = pp;
-            if ((pp.flag & 1) && pp.mx > 0.0) step_max_add(slot.mxkey, k, getexp((T)pp.mx));
+            slot.mx[l] = pmx;
+            if ((pp.flag & 1) && pmx > 0.0) step_max_add(slot.mxkey, k, getexp((T)pmx));
             const int dp = pbit ? q : p, dq = pbit ? p : q;
             d.e[dp] = dc.np.zero ? T(-INFINITY) : (T)dc.np.e;
             d.f[dp] = dc.np.zero ? T(1) : dc.np.f;
@@ -322,10 +327,10 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
 // the fold of one step as a kernel of its own: the G kernel's workgroups do
 // not see each other's outcomes before that launch has ended
 template <typename T>
-__global__ __launch_bounds__(kFoldW) void fold_kernel(SvdDescT<T> d, const PairParam *prm)
+__global__ __launch_bounds__(kFoldW) void fold_kernel(SvdDescT<T> d, const PairParam *prm, const double *pmx)
 {
     if (*(volatile int *)&d.sc->stop) return;
-    (void)fold_step<kFoldW, T>(d, prm, (d.n + (d.n & 1)) / 2);
+    (void)fold_step<kFoldW, T>(d, prm, pmx, (d.n + (d.n & 1)) / 2);
 }
 
 // outcomes of this thread's pairs l = t + W u in one step (only what V needs)
@@ -344,14 +349,16 @@ __device__ __forceinline__ void vacc_load(VaccPairs<PPT, T> &o, const PairParam 
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         const int l = t + W * u;
-        const PairParam *P = pl + (l < np ? l : 0);
-        const int pq = P->pq, f = P->flag;
+        // the 32-byte outcome as two 16-byte loads: (c, C), (S, pq, flag)
+        const uint4 *const P = reinterpret_cast<const uint4 *>(pl + (l < np ? l : 0));
+        const uint4 a = P[0], b = P[1];
+        const int pq = (int)b.z, f = (int)b.w;
         o.f[u] = l < np ? f : 0;
         o.p[u] = pq & 0xFFFF;
         o.q[u] = pq >> 16;
-        o.c[u] = (T)P->c;
-        o.C[u] = (T)P->C;
-        o.S[u] = CPLX ? (T)P->S : T(0);
+        o.c[u] = (T)__hiloint2double((int)a.y, (int)a.x);
+        o.C[u] = (T)__hiloint2double((int)a.w, (int)a.z);
+        o.S[u] = CPLX ? (T)__hiloint2double((int)b.y, (int)b.x) : T(0);
     }
 }
 
@@ -536,9 +543,9 @@ hipError_t launch_gpair(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, hipS
 }
 
 template <typename T>
-hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s)
+hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, const double *mx, hipStream_t s)
 {
-    hipLaunchKernelGGL((fold_kernel<T>), dim3(1), dim3(kFoldW), 0, s, d, prm);
+    hipLaunchKernelGGL((fold_kernel<T>), dim3(1), dim3(kFoldW), 0, s, d, prm, mx);
     return hipGetLastError();
 }
 
@@ -636,8 +643,8 @@ hipError_t launch_vtrans(const SvdDescT<T> &d, hipStream_t s)
 
 template hipError_t launch_gpair<double>(const SvdDescT<double> &, StepSlot, StepSlot, hipStream_t);
 template hipError_t launch_gpair<float>(const SvdDescT<float> &, StepSlot, StepSlot, hipStream_t);
-template hipError_t launch_fold<double>(const SvdDescT<double> &, const PairParam *, hipStream_t);
-template hipError_t launch_fold<float>(const SvdDescT<float> &, const PairParam *, hipStream_t);
+template hipError_t launch_fold<double>(const SvdDescT<double> &, const PairParam *, const double *, hipStream_t);
+template hipError_t launch_fold<float>(const SvdDescT<float> &, const PairParam *, const double *, hipStream_t);
 template hipError_t launch_vacc<double>(const SvdDescT<double> &, const PairParam *, long long, int, hipStream_t);
 template hipError_t launch_vacc<float>(const SvdDescT<float> &, const PairParam *, long long, int, hipStream_t);
 template hipError_t launch_vtrans<double>(const SvdDescT<double> &, hipStream_t);

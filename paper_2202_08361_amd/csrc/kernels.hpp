@@ -67,15 +67,16 @@ using SvdDesc = SvdDescT<double>;
 using SvdDescF = SvdDescT<float>;
 
 // outcome of one pivot pair, written by the G kernels for the end-of-step
-// fold and the (deferred) V update; what the V update reads comes first
-// (32 bytes)
-struct PairParam {
+// fold and the (deferred) V update: 32 bytes, read by the V update as two
+// 16-byte loads (the max-norm of the rotated columns, which only the fold
+// reads, is kept beside, in the slot's mx array)
+struct alignas(16) PairParam {
     double c, C, S;   // cos phi, e^{i alpha} tan phi
     int pq;           // the pair: p | q << 16
     int flag;         // bit 0: transform (rotation of V, counted), bit 1: swap the columns
                       // (permutation P), bit 2: G took the Gram-Schmidt step of eq. (GS)
-    double mx;        // max |component| of the rotated G columns (0 if not rotated)
 };
+static_assert(sizeof(PairParam) == 32, "PairParam is two 16-byte loads");
 
 // index and M~ of a large-column step, for the step after it
 struct StepHdr {
@@ -84,10 +85,12 @@ struct StepHdr {
 };
 
 // one slot of the outcome log of the large-column steps: the pair outcomes,
+// the max |component| of each pair's rotated columns (0 if not rotated),
 // the step header, and the key of the max-norm of its rotated columns
 // ((k << 12) | (floor(lg M) + 1075), an atomic max over the workgroups)
 struct StepSlot {
     PairParam *prm;
+    double *mx;
     StepHdr *hdr;
     unsigned long long *mxkey;
 };
@@ -107,7 +110,7 @@ hipError_t vacc_prepare(int cplx, bool fp32);   // once per state, on its device
 template <typename T>
 hipError_t launch_gpair(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, hipStream_t s);
 template <typename T>
-hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, hipStream_t s);
+hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, const double *mx, hipStream_t s);
 template <typename T>
 hipError_t launch_vacc(const SvdDescT<T> &d, const PairParam *plog, long long stride, int nsteps, hipStream_t s);
 template <typename T>

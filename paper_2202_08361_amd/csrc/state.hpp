@@ -23,6 +23,7 @@ struct jsvd_state_s {
     jsvd::DevScalars *sc;  // the device scalars (either descriptor's sc)
     int *rank;
     unsigned long long *maxbits;
+    double *vmx;             // the slots' max-norms of the rotated columns (vlog_stride each)
     jsvd::PairParam *vlog;   // outcome log of the large-column steps: kVlogSteps slots of vlog_stride
     jsvd::StepHdr *vhdr;     // the header of each slot
     unsigned long long *vkey;  // the max-norm key of each slot (zeroed by a load or restore)
