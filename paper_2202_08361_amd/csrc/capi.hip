@@ -11,6 +11,7 @@
 #include <limits>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "../../include/jsvd.h"
 #include "kernels.hpp"
@@ -132,12 +133,12 @@ static StateLayout state_layout(int m, int n, int cplx, size_t es)
     L.oR = off; off = align_up(off + sizeof(int) * (size_t)(n + 1));
     L.oS = off; off = align_up(off + sizeof(DevScalars));
     L.oM = off; off = align_up(off + sizeof(unsigned long long));
-    // the outcome log: kVlogSteps slots of the step's pair outcomes
+    // the outcome log: kVlogSlots slots of the step's pair outcomes
     L.vstride = round_up((long long)(n + 1) / 2, 4LL);
-    L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)L.vstride * kVlogSteps);
-    L.oQ = off; off = align_up(off + sizeof(double) * (size_t)L.vstride * kVlogSteps);
-    L.oH = off; off = align_up(off + sizeof(StepHdr) * (size_t)kVlogSteps);
-    L.oX = off; off = align_up(off + sizeof(unsigned long long) * (size_t)kVlogSteps);
+    L.oP = off; off = align_up(off + sizeof(PairParam) * (size_t)L.vstride * kVlogSlots);
+    L.oQ = off; off = align_up(off + sizeof(double) * (size_t)L.vstride * kVlogSlots);
+    L.oH = off; off = align_up(off + sizeof(StepHdr) * (size_t)kVlogSlots);
+    L.oX = off; off = align_up(off + sizeof(unsigned long long) * (size_t)kVlogSlots);
     L.total = off;
     return L;
 }
@@ -229,6 +230,7 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
     st->vkey = (unsigned long long *)(b + L.oX);
     st->vlog_stride = L.vstride;
     st->vlog_n = 0;
+    st->vbase = 0;
     st->vlast = -1;
     st->v_layout = V_EITHER;
     *out = st;
@@ -304,7 +306,7 @@ static int load_async_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg,
     HIPCHK(launch_init_scale(d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
     // V = I: the same in either layout, nothing logged, the scalars current,
     // no step keys (k starts again from 0)
-    HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSteps, s));
+    HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSlots, s));
     st->vlog_n = 0;
     st->vlast = -1;
     st->v_layout = V_EITHER;
@@ -400,7 +402,7 @@ static hipError_t flush_vlog_t(jsvd_state st, hipStream_t s)
     if (st->vlog_n == 0) return hipSuccess;
     const int nsteps = st->vlog_n;
     st->vlog_n = 0;
-    return launch_vacc(desc_of<T>(st), st->vlog, st->vlog_stride, nsteps, s);
+    return launch_vacc(desc_of<T>(st), st->vlog + (size_t)st->vbase * st->vlog_stride, st->vlog_stride, nsteps, s);
 }
 
 static hipError_t flush_vlog(jsvd_state st, hipStream_t s)
@@ -451,7 +453,7 @@ static hipError_t settle(jsvd_state st, hipStream_t s)
 // still due), its outcomes go to the next slot, and a full log is applied
 // to V; the fused kernel needs the scalars current
 template <typename T>
-static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s)
+static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s, bool defer = false)
 {
     const SvdDescT<T> &d = desc_of<T>(st);
     if (!uses_gpair(st)) {
@@ -465,10 +467,11 @@ static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s)
     prev.hdr = nullptr;
     prev.mxkey = nullptr;
     if (st->vlast >= 0) prev = slot_of(st, st->vlast);
-    const hipError_t e = launch_gpair(d, slot_of(st, st->vlog_n), prev, s);
+    const int j = st->vbase + st->vlog_n;
+    const hipError_t e = launch_gpair(d, slot_of(st, j), prev, s);
     if (e != hipSuccess) return e;
-    st->vlast = st->vlog_n;
-    if (++st->vlog_n == kVlogSteps) return flush_vlog_t<T>(st, s);
+    st->vlast = j;
+    if (++st->vlog_n == kVlogSteps && !defer) return flush_vlog_t<T>(st, s);
     return hipSuccess;
 }
 
@@ -490,13 +493,58 @@ static int sweep_steps(int n) { return n + (n & 1) - 1; }
 
 // Capture the K steps of a sweep, the update of V from the steps still
 // logged, and the end-of-sweep bookkeeping.  The log is empty when the
-// capture starts and when the graph ends.
-static int capture_sweep(jsvd_state st, hipStream_t cs)
+// capture starts and when the graph ends.  On the large-column path each
+// full half of the log is applied to V on a second stream (vs), beside the
+// steps that fill the other half: a step only waits for the update of the
+// half it is about to overwrite, issued a half earlier, and the sweep's end
+// waits for the last update.  The events made here (evs) live until the
+// capture has ended.
+static int capture_sweep(jsvd_state st, hipStream_t cs, hipStream_t vs, std::vector<hipEvent_t> &evs)
 {
     const int K = sweep_steps(st->n);
-    for (int k = 0; k < K; ++k)
-        if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
-    if (flush_vlog(st, cs) != hipSuccess || settle(st, cs) != hipSuccess) return JSVD_EDEVICE;
+    if (!uses_gpair(st)) {
+        for (int k = 0; k < K; ++k)
+            if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
+        if (flush_vlog(st, cs) != hipSuccess || settle(st, cs) != hipSuccess) return JSVD_EDEVICE;
+        return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
+    }
+    auto event = [&](hipEvent_t *e) {
+        *e = nullptr;
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return false;
+        evs.push_back(*e);
+        return true;
+    };
+    // the logged steps of the current half, applied on vs after what cs has issued
+    bool forked = false;
+    auto update_on_vs = [&](hipEvent_t *done) {
+        hipEvent_t f;
+        if (!event(&f) || hipEventRecord(f, cs) != hipSuccess || hipStreamWaitEvent(vs, f, 0) != hipSuccess)
+            return false;
+        forked = true;
+        if (flush_vlog(st, vs) != hipSuccess) return false;
+        return done == nullptr || (event(done) && hipEventRecord(*done, vs) == hipSuccess);
+    };
+    hipEvent_t done[2] = {nullptr, nullptr};
+    for (int k = 0; k < K; ++k) {
+        const hipError_t e = st->fp32 ? launch_one_step_t<float>(st, cs, true) : launch_one_step_t<double>(st, cs, true);
+        if (e != hipSuccess) return JSVD_EDEVICE;
+        if (st->vlog_n < kVlogSteps) continue;
+        if (!update_on_vs(&done[st->vbase / kVlogSteps])) return JSVD_EDEVICE;
+        st->vbase = kVlogSteps - st->vbase;
+        hipEvent_t &w = done[st->vbase / kVlogSteps];
+        if (w) {
+            if (hipStreamWaitEvent(cs, w, 0) != hipSuccess) return JSVD_EDEVICE;
+            w = nullptr;
+        }
+    }
+    if (st->vlog_n > 0 && !update_on_vs(nullptr)) return JSVD_EDEVICE;
+    st->vbase = 0;
+    if (forked) {
+        hipEvent_t j;
+        if (!event(&j) || hipEventRecord(j, vs) != hipSuccess || hipStreamWaitEvent(cs, j, 0) != hipSuccess)
+            return JSVD_EDEVICE;
+    }
+    if (settle(st, cs) != hipSuccess) return JSVD_EDEVICE;
     return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
 }
 
@@ -512,21 +560,27 @@ static int build_graph(jsvd_state st)
         (void)hipGraphDestroy(st->graph_def);
         st->graph_def = nullptr;
     }
-    hipStream_t cs = nullptr;
+    hipStream_t cs = nullptr, vs = nullptr;
+    std::vector<hipEvent_t> evs;
     int rc = JSVD_OK;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) rc = JSVD_EDEVICE;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&vs, hipStreamNonBlocking) != hipSuccess)
+        rc = JSVD_EDEVICE;
     hipGraph_t g = nullptr;
     if (rc == JSVD_OK) {
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = JSVD_EDEVICE;
         } else {
-            rc = capture_sweep(st, cs);
+            rc = capture_sweep(st, cs, vs, evs);
             st->vlog_n = 0;
+            st->vbase = 0;
             st->vlast = -1;
             // a failed capture still has to be ended
             if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == JSVD_OK) rc = JSVD_EDEVICE;
         }
     }
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    if (vs) (void)hipStreamDestroy(vs);
     if (cs) (void)hipStreamDestroy(cs);
     if (rc == JSVD_OK && (!g || hipGraphInstantiate(&st->graph, g, nullptr, nullptr, 0) != hipSuccess))
         rc = JSVD_EDEVICE;
@@ -686,7 +740,7 @@ static int restore_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, co
     if (st->cplx) HIPCHK(launch_copy2d(d.n, d.n, V_im, (long long)ldv, d.Vi, d.ldv, s));
     // the restored V and scalars replace the logged steps too (and k may
     // go back: no step keys)
-    HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSteps, s));
+    HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSlots, s));
     st->vlog_n = 0;
     st->vlast = -1;
     st->v_layout = V_COLS;

@@ -24,11 +24,12 @@ struct jsvd_state_s {
     int *rank;
     unsigned long long *maxbits;
     double *vmx;             // the slots' max-norms of the rotated columns (vlog_stride each)
-    jsvd::PairParam *vlog;   // outcome log of the large-column steps: kVlogSteps slots of vlog_stride
+    jsvd::PairParam *vlog;   // outcome log of the large-column steps: kVlogSlots slots of vlog_stride
     jsvd::StepHdr *vhdr;     // the header of each slot
     unsigned long long *vkey;  // the max-norm key of each slot (zeroed by a load or restore)
     long long vlog_stride;
-    int vlog_n;              // logged steps not yet applied to V
+    int vlog_n;              // logged steps not yet applied to V (slots vbase ...)
+    int vbase;               // first slot of the half of the log being filled (0 outside a captured sweep)
     int vlast;               // slot of the last step when its fold is still due, else -1
     int v_layout;            // V_COLS, V_ROWS, or V_EITHER (V = I after a load)
     jsvd::DevScalars *host;  // pinned staging for the scalars
@@ -44,6 +45,9 @@ namespace jsvd {
 // Steps of the outcome log: V is updated once per this many large-column
 // steps, and whenever it is read.
 constexpr int kVlogSteps = 32;
+// Slots of the log: two halves, so that a captured sweep can update V from
+// one half on a second stream while its steps fill the other.
+constexpr int kVlogSlots = 2 * kVlogSteps;
 
 // Layouts of the n x n V workspace: column-major (the fused step kernel and
 // every output), row-major (the deferred update of the large-column steps),
