@@ -403,7 +403,7 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
 
 
 def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32, budget=64 << 30,
-                slots=16, drain_limit=120.0):
+                slots=16, drain_limit=120.0, max_large=0):
     """Poisson arrivals replayed from a pre-generated pool of request matrices.
     Beside the server's figures: the time the plain path (jsvd_gesvj, one
     request after another) would need for the same completed requests, from
@@ -416,8 +416,10 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
     for k in range(pool_size):
         Ar, Ai, sig = inputs.serve_matrix(int(m[k]), int(n[k]), float(kappa[k]), bool(cplx[k]), g)
         pool.append((J.to_device_fortran(Ar), None if Ai is None else J.to_device_fortran(Ai)))
+    # the batched launch shapes of the pool's small requests, measured up front
+    J.batched_tune([(int(m[k]), int(n[k]), bool(cplx[k])) for k in range(pool_size)], flags=flags)
     torch.cuda.synchronize()
-    srv = J.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=max_queue, flags=flags)
+    srv = J.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=max_queue, flags=flags, max_large=max_large)
     outstanding, rejected, submitted, done = {}, 0, 0, []
     t0 = time.perf_counter()
     for i, ta in enumerate(t_arr):
@@ -478,7 +480,7 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
                 wall_s=wall, arrivals_s=t_end_arrivals, svds_per_s=st["completed"] / wall,
                 p50_latency_ms=st["p50_ns"] / 1e6, p99_latency_ms=st["p99_ns"] / 1e6,
                 p50_queue_ms=st["p50_queue_ns"] / 1e6, p99_queue_ms=st["p99_queue_ns"] / 1e6,
-                pool=pool_size, max_queue=max_queue, slots=slots, flags=flags,
+                pool=pool_size, max_queue=max_queue, slots=slots, flags=flags, max_large=max_large,
                 plain_same_requests_s=plain_s, served_vs_plain=(plain_s / wall) if wall > 0 else None)
 
 
@@ -591,6 +593,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=3.0)
     ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-max-large", type=int, default=0,
+                    help="large requests on the device at once (0: the library's default)")
     ap.add_argument("--calib-copy", type=int, default=0,
                     help="MiB copied once by a plain device copy before the timed region "
                          "(a reference for hardware byte counters)")
@@ -723,7 +727,8 @@ def main():
                                                                  fl)))
         if not args.no_serve:
             tasks.append(("serving", lambda: serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
-                                                         args.serve_pool, J.NO_PERMUTE)))
+                                                         args.serve_pool, J.NO_PERMUTE,
+                                                         max_large=args.serve_max_large)))
         if not args.no_cpu:
             tasks.append(("cpu_oracle_svd", lambda: cpu_oracle_svd(
                 inputs, extra.get("svd_real256_permute", {}).get("sweeps"),

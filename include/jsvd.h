@@ -329,7 +329,14 @@ int jsvd_batched_launch_of(int m, int n, int is_complex, unsigned flags);
  * Requests are admitted as slots and device memory free up; admitted
  * requests advance concurrently on the device, sweep by sweep, with their
  * iteration state device-resident.  Buffers stay caller-owned and must stay
- * valid until the ticket completes.
+ * valid until the ticket completes, and complete (the server's streams do
+ * not order after the caller's) when submitted.  Large requests (beyond the
+ * batched kernel's m, n <= 512) each advance on their own state, at most
+ * max_large at once.  Small requests run in batched launches when at least
+ * 32 of them wait, with the launch shapes measured in this process
+ * (jsvd_batched_tune), else the default; with fewer waiting, each runs on
+ * its own state like a large one, which finishes it sooner.  The server
+ * itself measures nothing, so as not to stall the requests in flight.
  * ---------------------------------------------------------------------- */
 typedef struct jsvd_server_s *jsvd_server;
 
@@ -340,6 +347,10 @@ typedef struct {
     int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
     unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_NO_PERMUTE,
                                 JSVD_COMPENSATED, JSVD_NO_GS) */
+    int max_large;           /* large requests (beyond the batched kernel's m, n <= 512, each
+                                advanced sweep by sweep on its own state) on the device at once
+                                (<= 0: 2); while that many are active, queued small requests
+                                are admitted past a large one at the head of the queue */
 } jsvd_serve_config;
 
 typedef struct {

@@ -55,7 +55,8 @@ class _Info(_ct.Structure):
 
 class ServeConfig(_ct.Structure):
     _fields_ = [("hbm_budget_bytes", _ct.c_size_t), ("max_slots", _ct.c_int),
-                ("max_sweeps", _ct.c_int), ("max_queue", _ct.c_int), ("flags", _ct.c_uint)]
+                ("max_sweeps", _ct.c_int), ("max_queue", _ct.c_int), ("flags", _ct.c_uint),
+                ("max_large", _ct.c_int)]
 
 
 class Request(_ct.Structure):
@@ -503,15 +504,19 @@ def batched_launch_of(m, n, cplx=False, flags=0):
 class Server:
     """Continuous-batching SVD server (jsvd_serve_*)."""
 
-    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_sweeps=0, max_queue=0, flags=0):
-        cfg = ServeConfig(hbm_budget_bytes, max_slots, max_sweeps, max_queue, flags)
+    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, max_sweeps=0, max_queue=0, flags=0, max_large=0):
+        cfg = ServeConfig(hbm_budget_bytes, max_slots, max_sweeps, max_queue, flags, max_large)
         h = _ct.c_void_p()
         _check(lib().jsvd_serve_create(_ct.byref(cfg), _ct.byref(h)), "jsvd_serve_create")
         self._h = h
         self._keep = {}
 
     def submit(self, G_re, G_im=None, tag=0):
+        """Submit G (overwritten by U); returns a ticket, or None when the queue
+        is full.  The server's streams do not order after the caller's, so
+        the caller's current stream is waited for first: G must be complete."""
         torch = _torch()
+        torch.cuda.current_stream().synchronize()
         m, n = G_re.shape
         ld = _mat(G_re, m, n, "G_re")
         Vr = fortran_empty(n, n)

@@ -34,8 +34,12 @@ int batch_threads_of(int m, int n, int cplx, unsigned flags);
 
 struct BatchLaunch;
 // Enqueue one persistent launch over the items (all batch_rows() != 0) and the
-// copy of their outcomes to pinned host memory; nullptr on failure.
-BatchLaunch *batch_launch(const BatchItem *items, int count, int max_sweeps, unsigned flags, hipStream_t s);
+// copy of their outcomes to pinned host memory; nullptr on failure.  With
+// tune, classes whose launch shape has not been measured in this process
+// are measured first (which synchronises the stream); without, they take the
+// default shape.
+BatchLaunch *batch_launch(const BatchItem *items, int count, int max_sweeps, unsigned flags, hipStream_t s,
+                          bool tune = true);
 // The outcomes (valid once the stream has passed the launch), then release.
 const BatchItem *batch_results(const BatchLaunch *bl);
 void batch_release(BatchLaunch *bl);

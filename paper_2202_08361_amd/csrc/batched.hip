@@ -711,11 +711,11 @@ static bool class_streams(int dev, hipStream_t *out)
     return true;
 }
 
-BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsigned flags, hipStream_t s)
+BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsigned flags, hipStream_t s, bool tune)
 {
     if (cnt <= 0) return nullptr;
     const bool comp = (flags & JSVD_COMPENSATED) != 0;
-    batch_tune(items, cnt, flags, s);
+    if (tune) batch_tune(items, cnt, flags, s);
     BatchLaunch *bl = new (std::nothrow) BatchLaunch;
     if (!bl) return nullptr;
     bl->count = cnt;

@@ -6,9 +6,12 @@
 // on the device:
 //
 // * small requests (the batched kernel's tile: m, n <= 512) are admitted in
-//   groups; a group is one persistent batched launch (one workgroup per
-//   matrix, the whole SVD on the device, in place in the caller's buffers)
-//   on the slot's stream;
+//   groups while enough of them wait; a group is one persistent batched
+//   launch (one workgroup per matrix, the whole SVD on the device, in place
+//   in the caller's buffers) on the slot's stream.  One workgroup per matrix
+//   spends little of the GPU per matrix but is slow for each one, so with
+//   few small requests waiting they are admitted one by one, like large
+//   ones;
 // * larger requests get a device-resident jsvd_state on their slot's stream
 //   and advance one graph-launched sweep at a time; after each sweep the
 //   device's convergence flags are staged to pinned memory and checked by the
@@ -16,7 +19,12 @@
 //   is enqueued.
 //
 // Slots run on separate streams, so admitted requests overlap on the device
-// while new ones are admitted as slots and memory free up.  Every request's
+// while new ones are admitted as slots and memory free up.  Freeing device
+// memory waits for the whole device, so nothing is freed while work is in
+// flight if it can be helped: a finished large request's state (with its
+// captured sweep) is kept for the next request of its shape, within the HBM
+// budget, and a finished group's launch record is released once the device
+// is idle.  Every request's
 // result is exactly the one jsvd_gesvj computes for it alone (the kernels
 // are the same and their arithmetic does not depend on what else runs).
 #include <hip/hip_runtime.h>
@@ -65,9 +73,18 @@ struct Slot {
     BatchLaunch *bl = nullptr;
     std::vector<uint64_t> group;
     size_t footprint = 0;
+    bool heavy = false;   // a large request (counted against max_large)
 };
 
 constexpr int kMaxGroup = 512;
+// small requests waiting before they are admitted as a batched group
+constexpr int kGroupMin = 32;
+// large requests on the device at once unless configured: one such request
+// already spreads its steps over the whole GPU, a second one fills the gaps
+// between them; more only compete for the caches
+constexpr int kDefaultLarge = 2;
+constexpr int kMaxIdleStates = 8;    // finished states kept for reuse
+constexpr int kMaxHeldLaunches = 64;  // finished group launches kept before a release
 
 size_t footprint_of(const jsvd_request &r, bool small)
 {
@@ -89,12 +106,62 @@ struct jsvd_server_s {
     std::vector<Slot> slots;
     size_t hbm_in_use = 0;
     int active = 0;
+    int active_large = 0;
     bool stopping = false;
     std::thread worker;
     uint64_t submitted = 0, completed = 0, rejected = 0;
     std::vector<double> lat_ns, qlat_ns;
     Clock::time_point t_create;
+    // worker thread only: states of finished large requests (oldest first),
+    // their bytes, and finished group launches not yet released
+    std::vector<jsvd_state> idle;
+    size_t idle_bytes = 0;
+    std::vector<BatchLaunch *> held;
 };
+
+// a kept state of this shape, or a new one; kept states are freed (oldest
+// first) while they would push the server past its budget
+static int take_state(jsvd_server sv, const jsvd_request &r, jsvd_state *out)
+{
+    for (size_t i = 0; i < sv->idle.size(); ++i) {
+        jsvd_state st = sv->idle[i];
+        if (st->m == r.m && st->n == r.n && st->cplx == (r.is_complex != 0) && !st->fp32) {
+            sv->idle.erase(sv->idle.begin() + (long)i);
+            sv->idle_bytes -= st->mem_bytes;
+            *out = st;
+            return JSVD_OK;
+        }
+    }
+    size_t in_use;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        in_use = sv->hbm_in_use;
+    }
+    while (!sv->idle.empty() && in_use + sv->idle_bytes > sv->cfg.hbm_budget_bytes) {
+        sv->idle_bytes -= sv->idle.front()->mem_bytes;
+        jsvd_state_destroy(sv->idle.front());
+        sv->idle.erase(sv->idle.begin());
+    }
+    return jsvd_state_create(r.m, r.n, r.is_complex, out);
+}
+
+// a finished request's state: kept for reuse, or freed
+static void put_state(jsvd_server sv, jsvd_state st)
+{
+    if ((int)sv->idle.size() >= kMaxIdleStates) {
+        sv->idle_bytes -= sv->idle.front()->mem_bytes;
+        jsvd_state_destroy(sv->idle.front());
+        sv->idle.erase(sv->idle.begin());
+    }
+    sv->idle.push_back(st);
+    sv->idle_bytes += st->mem_bytes;
+}
+
+static void release_held(jsvd_server sv)
+{
+    for (BatchLaunch *bl : sv->held) batch_release(bl);
+    sv->held.clear();
+}
 
 static double percentile(std::vector<double> v, double p)
 {
@@ -120,6 +187,8 @@ static void complete_locked(jsvd_server sv, uint64_t id, int status, int sweeps)
 
 static void free_slot_locked(jsvd_server sv, Slot &s)
 {
+    if (s.kind == SLOT_BIG && s.heavy) sv->active_large--;
+    s.heavy = false;
     sv->hbm_in_use -= s.footprint;
     s.footprint = 0;
     s.kind = SLOT_FREE;
@@ -140,7 +209,7 @@ static bool service_slot(jsvd_server sv, Slot &s)
         std::lock_guard<std::mutex> lk(sv->mu);
         for (size_t i = 0; i < s.group.size(); ++i)
             complete_locked(sv, s.group[i], res ? res[i].status : JSVD_EDEVICE, res ? res[i].sweeps : 0);
-        batch_release(s.bl);
+        sv->held.push_back(s.bl);   // its results are read; released with the others
         s.bl = nullptr;
         free_slot_locked(sv, s);
         sv->cv_done.notify_all();
@@ -178,7 +247,8 @@ static bool service_slot(jsvd_server sv, Slot &s)
     }
     if (done_status == kRunning) return true;
     (void)hipStreamSynchronize(s.stream);
-    jsvd_state_destroy(s.st);
+    if (done_status == JSVD_EDEVICE) jsvd_state_destroy(s.st);
+    else put_state(sv, s.st);
     s.st = nullptr;
     std::lock_guard<std::mutex> lk(sv->mu);
     complete_locked(sv, s.ticket, done_status, done_sweeps);
@@ -191,7 +261,8 @@ static bool service_slot(jsvd_server sv, Slot &s)
 static bool admit(jsvd_server sv)
 {
     std::vector<uint64_t> group;
-    uint64_t big = 0;
+    uint64_t big = 0;   // a request admitted alone (large, or small with few waiting)
+    bool heavy = false;
     size_t fp_total = 0;
     int slot_idx = -1;
     {
@@ -204,21 +275,46 @@ static bool admit(jsvd_server sv)
             }
         if (slot_idx < 0) return false;
         const size_t budget = sv->cfg.hbm_budget_bytes;
+        const int large_cap = sv->cfg.max_large > 0 ? sv->cfg.max_large : kDefaultLarge;
         Ticket &front = sv->tickets[sv->queue.front()];
-        if (!front.small) {
+        int waiting_small = 0;
+        for (uint64_t id : sv->queue)
+            if (sv->tickets[id].small && ++waiting_small >= kGroupMin) break;
+        const bool cap_reached = sv->active_large >= large_cap;
+        if (!front.small && !cap_reached) {
+            // a large request, alone on its own state
             if (sv->hbm_in_use + front.footprint > budget && sv->active > 0) return false;
             big = sv->queue.front();
             sv->queue.pop_front();
             fp_total = front.footprint;
+            heavy = true;
+        } else if (waiting_small < kGroupMin) {
+            // few small requests: the first of them alone on its own state
+            auto q = sv->queue.begin();
+            while (q != sv->queue.end() && !sv->tickets[*q].small) ++q;
+            if (q == sv->queue.end()) return false;
+            const jsvd_request &r = sv->tickets[*q].req;
+            const size_t fp = state_bytes(r.m, r.n, r.is_complex);
+            if (sv->hbm_in_use + fp > budget && sv->active > 0) return false;
+            big = *q;
+            sv->queue.erase(q);
+            fp_total = fp;
         } else {
-            // continuous batching: the run of small requests at the head of the queue
-            while (!sv->queue.empty() && (int)group.size() < kMaxGroup) {
-                Ticket &t = sv->tickets[sv->queue.front()];
-                if (!t.small) break;
+            // continuous batching: the run of small requests at the head of the
+            // queue; with a large request at the head that has to wait for one
+            // of the large ones on the device, the small requests queued behind it
+            const bool past_large = !front.small;
+            for (auto q = sv->queue.begin(); q != sv->queue.end() && (int)group.size() < kMaxGroup;) {
+                Ticket &t = sv->tickets[*q];
+                if (!t.small) {
+                    if (!past_large) break;
+                    ++q;
+                    continue;
+                }
                 if (sv->hbm_in_use + fp_total + t.footprint > budget && (sv->active > 0 || !group.empty())) break;
                 fp_total += t.footprint;
-                group.push_back(sv->queue.front());
-                sv->queue.pop_front();
+                group.push_back(*q);
+                q = sv->queue.erase(q);
             }
             if (group.empty()) return false;
         }
@@ -237,6 +333,8 @@ static bool admit(jsvd_server sv)
         }
         Slot &s = sv->slots[slot_idx];
         s.kind = big ? SLOT_BIG : SLOT_GROUP;
+        s.heavy = heavy;
+        if (heavy) sv->active_large++;
         s.footprint = fp_total;
         s.ticket = big;
         s.group = group;
@@ -252,7 +350,7 @@ static bool admit(jsvd_server sv)
             std::lock_guard<std::mutex> lk(sv->mu);
             r = sv->tickets[big].req;
         }
-        rc = jsvd_state_create(r.m, r.n, r.is_complex, &s.st);
+        rc = take_state(sv, r, &s.st);
         if (rc == JSVD_OK) {
             s.st->max_sweeps = sv->cfg.max_sweeps > 0 ? sv->cfg.max_sweeps : 128;
             rc = state_set_flags(s.st, sv->cfg.flags);
@@ -273,7 +371,9 @@ static bool admit(jsvd_server sv)
             }
         }
         const int ms = sv->cfg.max_sweeps > 0 ? sv->cfg.max_sweeps : 128;
-        s.bl = batch_launch(items.data(), (int)items.size(), ms, sv->cfg.flags, s.stream);
+        // no measurement of launch shapes here: it would stall the worker, and
+        // with it every request in flight (jsvd_batched_tune does it up front)
+        s.bl = batch_launch(items.data(), (int)items.size(), ms, sv->cfg.flags, s.stream, false);
         if (!s.bl || hipEventRecord(s.ev, s.stream) != hipSuccess) rc = JSVD_EDEVICE;
     }
     if (rc != JSVD_OK) {
@@ -303,6 +403,14 @@ static void worker_main(jsvd_server sv)
         bool progressed = false;
         for (Slot &s : sv->slots) progressed |= service_slot(sv, s);
         while (admit(sv)) progressed = true;
+        if (!sv->held.empty()) {
+            bool idle_now;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                idle_now = sv->active == 0;
+            }
+            if (idle_now || (int)sv->held.size() >= kMaxHeldLaunches) release_held(sv);
+        }
         std::unique_lock<std::mutex> lk(sv->mu);
         if (sv->stopping && sv->queue.empty() && sv->active == 0) break;
         if (!progressed) {
@@ -451,6 +559,9 @@ extern "C" int jsvd_serve_destroy(jsvd_server sv)
     }
     sv->cv_work.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
+    release_held(sv);
+    for (jsvd_state st : sv->idle) jsvd_state_destroy(st);
+    sv->idle.clear();
     for (Slot &s : sv->slots) {
         if (s.stream) (void)hipStreamDestroy(s.stream);
         if (s.ev) (void)hipEventDestroy(s.ev);
