@@ -63,6 +63,30 @@ def test_serve_mix_equals_alone():
         _same(r, _alone(Ar, Ai))
 
 
+def test_serve_groups_past_a_waiting_large_request():
+    # two slots, one large request at a time: the first large request runs,
+    # the second waits at the head of the queue, and the 40 small requests
+    # behind it (at least 32 waiting) are admitted past it as a batched group
+    g = inputs.rng(inputs.CFG_SERVE, 830)
+    shapes = [(700, 600, False, 1e5), (640, 513, True, 1e3)]
+    for i in range(40):
+        n = int(g.integers(8, 65))
+        shapes.append((int(g.integers(n, 2 * n + 1)), n, bool(i % 3 == 0), 10.0 ** float(g.uniform(1, 6))))
+    pool = _pool(shapes, 2)
+    srv = J().Server(hbm_budget_bytes=4 << 30, max_slots=2, max_large=1)
+    tickets = []
+    for (Ar, Ai) in pool:
+        t = srv.submit(J().to_device_fortran(Ar), None if Ai is None else J().to_device_fortran(Ai))
+        assert t is not None
+        tickets.append(t)
+    results = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(tickets)
+    for (Ar, Ai), r in zip(pool, results):
+        _same(r, _alone(Ar, Ai))
+
+
 def test_serve_small_budget_and_backpressure():
     pool = _pool([(200, 150, False, 1e4), (600, 520, False, 1e3), (50, 40, True, 1e2)], 2)
     # a budget that holds one large request at a time: everything still completes
