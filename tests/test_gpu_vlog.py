@@ -267,3 +267,30 @@ def test_full_size_sweep_properties(m, n, cplx):
     Gs = G * (2.0 ** -sv["s"])
     res = torch.linalg.norm(Gs - A @ V).item() / torch.linalg.norm(A).item()
     assert res <= 1e-12, res
+
+
+def test_full_size_svd_real_workload():
+    """The whole SVD of the real 8192 x 2048 workload as the benchmark times it
+    (A = U diag(sigma) V^T with Haar factors, sigma log-spaced in [1e-8, 1],
+    no permutation): it converges; the relative sigma error is at most 1e-10
+    for sigma >= 1e-6 sigma_max (kappa <= 1e6, where that tolerance applies;
+    rounding A to double already moves sigma_i by about eps sigma_max); the
+    residual ||A - U diag(sigma) V^T||_F is at most 64 n eps ||A||_F; V is
+    orthogonal within the same 64 n eps (max element of V^T V - I: the 42
+    sweeps' rotations accumulate a few eps each, against 1e-12 after one
+    sweep)."""
+    Ar, sig = inputs.plain_real_tall()
+    m, n = Ar.shape
+    A = _dev(Ar)
+    r = J().gesvj(A, None, flags=J().NO_PERMUTE)
+    assert r["status"] == 0, r["status"]
+    sv = r["sv"].cpu().numpy()
+    big = sig >= 1e-6 * sig[0]
+    rel = float(np.max(np.abs(sv[big] - sig[big]) / sig[big]))
+    assert rel <= 1e-10, rel
+    U, V, s = r["U_re"], r["V_re"], r["sv"]
+    res = (torch.linalg.norm(A - (U * s) @ V.transpose(0, 1).contiguous()) / torch.linalg.norm(A)).item()
+    assert res <= 64 * n * np.finfo(np.float64).eps, res
+    eye = torch.eye(n, dtype=V.dtype, device=V.device)
+    orth = (V.transpose(0, 1).contiguous() @ V - eye).abs().max().item()
+    assert orth <= 64 * n * np.finfo(np.float64).eps, orth
