@@ -269,28 +269,40 @@ def test_full_size_sweep_properties(m, n, cplx):
     assert res <= 1e-12, res
 
 
-def test_full_size_svd_real_workload():
-    """The whole SVD of the real 8192 x 2048 workload as the benchmark times it
-    (A = U diag(sigma) V^T with Haar factors, sigma log-spaced in [1e-8, 1],
-    no permutation): it converges; the relative sigma error is at most 1e-10
+@pytest.mark.parametrize("cplx", [False, True])
+def test_full_size_svd_workloads(cplx):
+    """The whole SVD of the large workloads as the benchmark times them, no
+    permutation: real 8192 x 2048 (A = U diag(sigma) V^T with Haar factors,
+    sigma log-spaced in [1e-8, 1]) and complex 4096 x 4096 (sigma geometric
+    from 1 to 1e-12).  It converges; the relative sigma error is at most 1e-10
     for sigma >= 1e-6 sigma_max (kappa <= 1e6, where that tolerance applies;
     rounding A to double already moves sigma_i by about eps sigma_max); the
-    residual ||A - U diag(sigma) V^T||_F is at most 64 n eps ||A||_F; V is
-    orthogonal within the same 64 n eps (max element of V^T V - I: the 42
+    residual ||A - U diag(sigma) V^*||_F is at most 64 n eps ||A||_F; V is
+    unitary within the same 64 n eps (max element of V^* V - I: the 42 / 62
     sweeps' rotations accumulate a few eps each, against 1e-12 after one
     sweep)."""
-    Ar, sig = inputs.plain_real_tall()
+    if cplx:
+        Ar, Ai, sig = inputs.plain_complex_4096()
+    else:
+        (Ar, sig), Ai = inputs.plain_real_tall(), None
     m, n = Ar.shape
-    A = _dev(Ar)
-    r = J().gesvj(A, None, flags=J().NO_PERMUTE)
+    r = J().gesvj(_dev(Ar), _dev(Ai), flags=J().NO_PERMUTE)
     assert r["status"] == 0, r["status"]
     sv = r["sv"].cpu().numpy()
     big = sig >= 1e-6 * sig[0]
     rel = float(np.max(np.abs(sv[big] - sig[big]) / sig[big]))
     assert rel <= 1e-10, rel
-    U, V, s = r["U_re"], r["V_re"], r["sv"]
-    res = (torch.linalg.norm(A - (U * s) @ V.transpose(0, 1).contiguous()) / torch.linalg.norm(A)).item()
-    assert res <= 64 * n * np.finfo(np.float64).eps, res
+    s = r["sv"]
+    if cplx:
+        A = torch.complex(_dev(Ar), _dev(Ai))
+        U = torch.complex(r["U_re"], r["U_im"])
+        V = torch.complex(r["V_re"], r["V_im"])
+    else:
+        A, U, V = _dev(Ar), r["U_re"], r["V_re"]
+    tol = 64 * n * np.finfo(np.float64).eps
+    Vh = V.conj().transpose(0, 1).contiguous()
+    res = (torch.linalg.norm(A - (U * s) @ Vh) / torch.linalg.norm(A)).item()
+    assert res <= tol, res
     eye = torch.eye(n, dtype=V.dtype, device=V.device)
-    orth = (V.transpose(0, 1).contiguous() @ V - eye).abs().max().item()
-    assert orth <= 64 * n * np.finfo(np.float64).eps, orth
+    orth = (Vh @ V - eye).abs().max().item()
+    assert orth <= tol, orth
