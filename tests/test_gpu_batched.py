@@ -134,3 +134,47 @@ def test_batched_launch_shapes_identical():
     assert J().batched_launch_of(700, 100, False) == 0
     with pytest.raises(Exception):
         J().batched_set_launch(100)
+
+
+def _workload(count):
+    """The first `count` matrices of the batched workload with their prescribed
+    singular values, generated in parallel host threads (one-thread BLAS)."""
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    m, n, kappa = inputs.batched_shapes(10000)
+    with threadpool_limits(1), ThreadPoolExecutor(16) as ex:
+        return list(ex.map(lambda i: inputs.batched_matrix(i, int(m[i]), int(n[i]), float(kappa[i])),
+                           range(count)))
+
+
+@pytest.mark.parametrize("nopermute", [False, True])
+def test_batched_full_workload(nopermute):
+    """All 10,000 matrices of the batched workload (n ~ U{16..256}, m ~ U{n..2n},
+    kappa log-uniform in [1e2, 1e8]) in one call, as the benchmark times it:
+    every matrix converges, with sigma to 1e-10 relative for sigma >= 1e-6
+    sigma_max (kappa <= 1e6, where that tolerance applies); on 16 of them
+    the residual ||A - U diag(sigma) V^T||_F and ||V^T V - I||_max are within
+    64 n eps (||A||_F for the residual)."""
+    flags = J().NO_PERMUTE if nopermute else 0
+    work = _workload(10000)
+    dev = [(J().to_device_fortran(A), None) for A, _ in work]
+    res = J().gesvj_batched(dev, flags=flags)
+    worst = 0.0
+    for (A, sig), r in zip(work, res):
+        assert r["status"] == 0
+        sv = np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))
+        big = sig >= 1e-6 * sig[0]
+        worst = max(worst, float(np.max(np.abs(sv[big] - sig[big]) / sig[big])))
+    assert worst <= 1e-10, worst
+    eps = np.finfo(np.float64).eps
+    for i in range(0, 10000, 625):
+        A, _ = work[i]
+        r = res[i]
+        n = A.shape[1]
+        s = torch.from_numpy(np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))).to("cuda")
+        U, V = r["U_re"], r["V_re"]
+        Ad = J().to_device_fortran(A)
+        Vt = V.transpose(0, 1).contiguous()
+        assert (torch.linalg.norm(Ad - (U * s) @ Vt) / torch.linalg.norm(Ad)).item() <= 64 * n * eps
+        eye = torch.eye(n, dtype=V.dtype, device=V.device)
+        assert (Vt @ V - eye).abs().max().item() <= 64 * n * eps
