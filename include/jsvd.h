@@ -166,7 +166,12 @@ int jsvd_state_load(jsvd_state st, const double *G_re, const double *G_im, size_
  * jsvd_gesvj) or the fused small-column kernel takes over. */
 int jsvd_step(jsvd_state st, void *stream);
 
-/* K steps followed by the end-of-sweep bookkeeping; launches only. */
+/* K steps followed by the end-of-sweep bookkeeping; launches only (one
+ * graph, captured once per state and launch configuration).  For columns of
+ * more than 256 rows the graph applies each 32 steps' V rotations on a second
+ * stream of the library's, beside the steps that follow, and joins it back
+ * before its end: to the caller the sweep is ordered on `stream` like any
+ * other launch. */
 int jsvd_sweep(jsvd_state st, void *stream);
 
 /* Read the scalars of the state.  Synchronises. */
