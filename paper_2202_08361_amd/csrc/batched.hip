@@ -770,7 +770,9 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     int dev = 0;
     const int ncu = current_device_ncu(&dev);
     bool ok = hipMemcpyAsync(dm, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
-    // one class on the caller's stream, several side by side on the class streams
+    // the first class on the caller's stream, the others side by side on
+    // class streams forked from it (one stream fewer to share the process's
+    // hardware queues)
     hipStream_t cs[8];
     hipEvent_t fork = nullptr, join[8] = {};
     const bool side = ncls > 1 && class_streams(dev, cs);
@@ -782,14 +784,14 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
         const BatchItem &it0 = items[order[first[c]]];
         const int NT = class_threads(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
         hipStream_t ls = s;
-        if (side) {
-            ls = cs[c];
+        if (side && c > 0) {
+            ls = cs[c - 1];
             ok = hipStreamWaitEvent(ls, fork, 0) == hipSuccess;
         }
         ok = ok && launch_class(comp, it0.cplx, it0.R, NT, (BatchItem *)(dm + oItems),
                                 (const int *)(dm + oOrder) + first[c], (BatchCtl *)(dm + oCtl + 256 * (size_t)c),
                                 first[c + 1] - first[c], ncu, ls) == hipSuccess;
-        if (side && ok) {
+        if (side && c > 0 && ok) {
             ok = hipEventCreateWithFlags(&join[c], hipEventDisableTiming) == hipSuccess &&
                  hipEventRecord(join[c], ls) == hipSuccess && hipStreamWaitEvent(s, join[c], 0) == hipSuccess;
         }
