@@ -507,9 +507,7 @@ def svd_large(torch, J, inputs, cplx, flags):
     events), sweeps, and the sigma error against the prescribed values: the
     rounding of A to double moves sigma_i by up to about eps sigma_max, so the
     relative error is given for sigma_i >= 1e-6 sigma_max and the absolute
-    error relative to sigma_max for all.  Run without the EVD's permutation:
-    with it, the round-robin iteration needs far more sweeps as n grows (more
-    than 128 at these sizes)."""
+    error relative to sigma_max for all.  Default flags (no permutation)."""
     import numpy as np
     t0 = time.perf_counter()
     if cplx:
@@ -571,7 +569,7 @@ def cpu_oracle_svd(inputs, sweeps_256=None, sweeps_large=None):
         tg = f"{'c' if c else 'r'}{m}x{n}"
         res[f"sweep_{tg}_s_extrapolated"] = round(dt * K, 1)
         if sweeps_large and sweeps_large.get(tg):
-            res[f"svd_{tg}_nopermute_h_extrapolated"] = round(dt * K * sweeps_large[tg] / 3600.0, 1)
+            res[f"svd_{tg}_h_extrapolated"] = round(dt * K * sweeps_large[tg] / 3600.0, 1)
     res["cores"] = 1
     res["kind"] = "oracle"
     return res
@@ -709,30 +707,30 @@ def main():
                           lambda m=m, n=n, c=c: step_roofline(torch, J, inputs, m, n, c, fp32=True)))
         for (m, n, c) in big:
             tasks.append((f"nrmf_{tag(m, n, c)}", lambda m=m, n=n, c=c: nrmf_rate(torch, J, inputs, m, n, c)))
-        for nm, fl in (("svd_real256_permute_f32", 0), ("svd_real256_nopermute_f32", J.NO_PERMUTE)):
+        for nm, fl in (("svd_real256_f32", 0), ("svd_real256_permute_f32", J.PERMUTE)):
             tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl, fp32=True)))
-        for nm, fl in (("svd_real256_permute", 0), ("svd_real256_nopermute", J.NO_PERMUTE),
-                       ("svd_real256_permute_compensated", J.COMPENSATED),
-                       ("svd_real256_nopermute_compensated", J.NO_PERMUTE | J.COMPENSATED)):
+        for nm, fl in (("svd_real256", 0), ("svd_real256_permute", J.PERMUTE),
+                       ("svd_real256_compensated", J.COMPENSATED),
+                       ("svd_real256_permute_compensated", J.PERMUTE | J.COMPENSATED)):
             tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl)))
         for (m, n, c) in big:
             for fp32 in (False, True):
                 tasks.append((f"sweep_{tag(m, n, c)}" + ("_f32" if fp32 else ""),
                               lambda m=m, n=n, c=c, fp32=fp32: sweep_time(torch, J, inputs, m, n, c, fp32=fp32)))
         for (m, n, c) in big:
-            tasks.append((f"svd_{tag(m, n, c)}_nopermute", lambda c=c: svd_large(torch, J, inputs, c, J.NO_PERMUTE)))
+            tasks.append((f"svd_{tag(m, n, c)}", lambda c=c: svd_large(torch, J, inputs, c, 0)))
         if not args.no_batched:
-            for nm, fl in (("batched_permute", 0), ("batched_nopermute", J.NO_PERMUTE)):
+            for nm, fl in (("batched", 0), ("batched_permute", J.PERMUTE)):
                 tasks.append((nm, lambda fl=fl: batched_vs_plain(torch, J, inputs, args.batched, args.batched_plain,
                                                                  fl)))
         if not args.no_serve:
             tasks.append(("serving", lambda: serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
-                                                         args.serve_pool, J.NO_PERMUTE,
+                                                         args.serve_pool, 0,
                                                          max_large=args.serve_max_large)))
         if not args.no_cpu:
             tasks.append(("cpu_oracle_svd", lambda: cpu_oracle_svd(
-                inputs, extra.get("svd_real256_permute", {}).get("sweeps"),
-                {tg: extra.get(f"svd_{tg}_nopermute", {}).get("sweeps") for tg in ("r8192x2048", "c4096x4096")})))
+                inputs, extra.get("svd_real256", {}).get("sweeps"),
+                {tg: extra.get(f"svd_{tg}", {}).get("sweeps") for tg in ("r8192x2048", "c4096x4096")})))
         for nm, fn in tasks:
             if prefixes and not any(nm.startswith(x) for x in prefixes):
                 continue

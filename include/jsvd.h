@@ -48,9 +48,9 @@ enum {
 };
 
 /* flags of jsvd_gesvj / jsvd_gesvj_batched / jsvd_state_set_flags / serving */
-#define JSVD_NO_PERMUTE 1u  /* apply U instead of U P during the iteration (no column
-                               sorting by the EVD's permutation, Sect. 2); the final
-                               sort still orders the output */
+#define JSVD_NO_PERMUTE 1u  /* apply U, not U P, during the iteration: the default,
+                               named for explicitness; the final sort orders the
+                               output either way */
 #define JSVD_COMPENSATED 2u /* scaled dot-products with compensated summation
                                (Sect. SM2.2, Alg. zdpsclcs / ddpsclcs) instead of
                                Alg. zdpscl */
@@ -58,6 +58,13 @@ enum {
                                whose norms differ by more than 2^eta_hat upsilon
                                (eq. GScond; by default such a pair is orthogonalised
                                by eq. GS, Sect. 3.5.1) */
+#define JSVD_PERMUTE 8u     /* apply U P: the EVD's permutation P keeps each pivot pair
+                               sorted by norm, larger column first (Sect. 2, optional
+                               there).  Off by default: with round-robin pairs a swapped
+                               column takes over its partner's remaining pairings of the
+                               sweep, so a sweep stops meeting every column pair and
+                               the iteration needs about twice the sweeps, more as n
+                               grows.  Invalid together with JSVD_NO_PERMUTE. */
 
 /* flags of jsvd_evd2_batched */
 #define JSVD_EVD_SCALED  1u /* return lambda' = 2^zeta lambda (not backscaled), Sect. 2.3 */
@@ -201,9 +208,10 @@ int jsvd_state_finalize(jsvd_state st, double *U_re, double *U_im, size_t ldu,
  * 1024; 0 = automatic).  Results do not depend on it (bit-identical). */
 int jsvd_state_set_launch(jsvd_state st, int threads_per_pair);
 
-/* Set the iteration flags of a state (JSVD_NO_PERMUTE, JSVD_COMPENSATED,
- * JSVD_NO_GS; default none).  They apply from the next step on.  Returns
- * JSVD_EINVAL for unknown flags. */
+/* Set the iteration flags of a state (JSVD_PERMUTE or JSVD_NO_PERMUTE,
+ * JSVD_COMPENSATED, JSVD_NO_GS; default none).  They apply from the next step
+ * on.  Returns JSVD_EINVAL for unknown flags and for JSVD_PERMUTE together
+ * with JSVD_NO_PERMUTE. */
 int jsvd_state_set_flags(jsvd_state st, unsigned flags);
 
 /* Single precision state (Sect. SM8: the method in the precision of the
@@ -214,8 +222,8 @@ int jsvd_state_set_flags(jsvd_state st, unsigned flags);
  * FLT_MAX, the Gram scaling with FLT_MAX_EXP - 1 and the single precision EVD
  * (Sect. 2.4.1).  The compensated dot-products are not offered.
  * jsvd_step, jsvd_sweep, jsvd_state_query (M~ as a double holding the float
- * value), jsvd_state_set_launch, jsvd_state_set_flags (JSVD_NO_PERMUTE and
- * JSVD_NO_GS; eta_hat = FLT_MAX_EXP - 1 in eq. GScond)
+ * value), jsvd_state_set_launch, jsvd_state_set_flags (JSVD_PERMUTE,
+ * JSVD_NO_PERMUTE and JSVD_NO_GS; eta_hat = FLT_MAX_EXP - 1 in eq. GScond)
  * and jsvd_state_destroy take either kind of state; the calls below take a
  * single precision state and the double calls above reject one
  * (JSVD_EINVAL), and the other way round.  Arguments as for the double
@@ -287,7 +295,7 @@ int jsvd_gesvj(int m, int n, double *G_re, double *G_im, size_t ldg,
 
 /* The whole SVD in single precision (Sect. SM8; the step of
  * jsvd_state_create_f32): the same interface on float arrays, sv_e holding
- * the exponents as floats.  flags: JSVD_NO_PERMUTE, JSVD_NO_GS. */
+ * the exponents as floats.  flags: JSVD_PERMUTE or JSVD_NO_PERMUTE, JSVD_NO_GS. */
 int jsvd_gesvj_f32(int m, int n, float *G_re, float *G_im, size_t ldg,
                    float *V_re, float *V_im, size_t ldv,
                    float *sv_e, float *sv_f, float *sv, int max_sweeps, int *sweeps,
@@ -350,8 +358,8 @@ typedef struct {
     int max_slots;           /* requests on the device at once */
     int max_sweeps;          /* per request (<= 0: 128) */
     int max_queue;           /* waiting requests before submit returns JSVD_EAGAIN (<= 0: unbounded) */
-    unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_NO_PERMUTE,
-                                JSVD_COMPENSATED, JSVD_NO_GS) */
+    unsigned flags;          /* jsvd_gesvj flags applied to every request (JSVD_PERMUTE or
+                                JSVD_NO_PERMUTE, JSVD_COMPENSATED, JSVD_NO_GS) */
     int max_large;           /* large requests (beyond the batched kernel's m, n <= 512, each
                                 advanced sweep by sweep on its own state) on the device at once
                                 (<= 0: 2); while that many are active, queued small requests

@@ -19,9 +19,10 @@ _lib = None
 
 OK, NOT_CONVERGED, EINVAL, ENONFINITE, EZERO = 0, 1, -1, -2, -3
 EVD_SCALED, EVD_SINFORM = 1, 2
-NO_PERMUTE = 1
+NO_PERMUTE = 1      # the default: U, not U P (named for explicitness)
 COMPENSATED = 2
 NO_GS = 4
+PERMUTE = 8         # apply the EVD's sorting permutation P during the iteration
 LANES = 1024
 
 _dp = _ct.POINTER(_ct.c_double)
@@ -308,8 +309,8 @@ def s_gs(xr, xi, yr, yi, ex, fx, ey, fy, wr, wi):
 class State:
     """Oracle SVD state on host numpy arrays (column-major)."""
 
-    def __init__(self, G_re, G_im=None, nosort=False, compensated=False, nogs=False):
-        self.nosort = bool(nosort)
+    def __init__(self, G_re, G_im=None, permute=False, compensated=False, nogs=False):
+        self.permute = bool(permute)
         self.compensated = bool(compensated)
         self.nogs = bool(nogs)
         self.m, self.n = G_re.shape
@@ -341,7 +342,7 @@ class State:
     def step(self):
         s, Mt = _ct.c_int(self.s), _ct.c_double(self.Mt)
         t, sw, gs_, r = _ct.c_long(), _ct.c_long(), _ct.c_long(), _ct.c_int()
-        flags = ((NO_PERMUTE if self.nosort else 0) | (COMPENSATED if self.compensated else 0) |
+        flags = ((PERMUTE if self.permute else 0) | (COMPENSATED if self.compensated else 0) |
                  (NO_GS if self.nogs else 0))
         lib().ora_step_ext(*self._args(), s, Mt, self.k, t, sw, gs_, r, flags)
         self.s, self.Mt, self.last_t, self.last_sw = s.value, Mt.value, t.value, sw.value
@@ -404,8 +405,8 @@ def s_s_square(Mt, m, cplx):
 class SState:
     """Single precision oracle SVD state on host float32 arrays (column-major)."""
 
-    def __init__(self, G_re, G_im=None, nosort=False, nogs=False):
-        self.nosort = bool(nosort)
+    def __init__(self, G_re, G_im=None, permute=False, nogs=False):
+        self.permute = bool(permute)
         self.nogs = bool(nogs)
         self.m, self.n = G_re.shape
         self.cplx = G_im is not None
@@ -436,7 +437,7 @@ class SState:
     def step(self):
         s, Mt = _ct.c_int(self.s), _ct.c_float(self.Mt)
         t, sw, gs_, r = _ct.c_long(), _ct.c_long(), _ct.c_long(), _ct.c_int()
-        flags = (NO_PERMUTE if self.nosort else 0) | (NO_GS if self.nogs else 0)
+        flags = (PERMUTE if self.permute else 0) | (NO_GS if self.nogs else 0)
         lib().ora_s_step_ext(*self._args(), s, Mt, self.k, t, sw, gs_, r, flags)
         self.s, self.Mt, self.last_t, self.last_sw = s.value, _np.float32(Mt.value), t.value, sw.value
         self.last_gs = gs_.value

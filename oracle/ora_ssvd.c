@@ -475,9 +475,11 @@ int ora_sgesvj(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, float 
     st.m = m; st.n = n; st.cplx = (Gi != NULL);
     st.Gr = Gr; st.Gi = Gi; st.ldg = ldg;
     st.Vr = Vr; st.Vi = Vi; st.ldv = ldv;
-    st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.nosort = (flags & ORA_PERMUTE) == 0;
     st.nogs = (flags & ORA_NO_GS) != 0;
-    if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1 || (flags & ~(ORA_NO_PERMUTE | ORA_NO_GS)))
+    if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1 ||
+        (flags & ~(ORA_NO_PERMUTE | ORA_PERMUTE | ORA_NO_GS)) ||
+        ((flags & ORA_PERMUTE) && (flags & ORA_NO_PERMUTE)))
         return ORA_EINVAL;
     st.e = (float *)malloc(sizeof(float) * (size_t)n);
     st.f = (float *)malloc(sizeof(float) * (size_t)n);
@@ -546,7 +548,7 @@ void ora_s_step_ext(int m, int n, float *Gr, float *Gi, size_t ldg, float *Vr, f
     st.s = *s;
     st.Mt = *Mt;
     st.k = k;
-    st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.nosort = (flags & ORA_PERMUTE) == 0;
     st.nogs = (flags & ORA_NO_GS) != 0;
     s_step(&st);
     *s = st.s;

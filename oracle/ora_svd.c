@@ -635,10 +635,13 @@ int ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
     st.m = m; st.n = n; st.cplx = (Gi != NULL);
     st.Gr = Gr; st.Gi = Gi; st.ldg = ldg;
     st.Vr = Vr; st.Vi = Vi; st.ldv = ldv;
-    st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.nosort = (flags & ORA_PERMUTE) == 0;
     st.comp = (flags & ORA_COMPENSATED) != 0;
     st.nogs = (flags & ORA_NO_GS) != 0;
-    if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1) return ORA_EINVAL;
+    if (n < 1 || m < n || !sv_e || !sv_f || max_sweeps < 1 ||
+        (flags & ~(ORA_NO_PERMUTE | ORA_PERMUTE | ORA_COMPENSATED | ORA_NO_GS)) ||
+        ((flags & ORA_PERMUTE) && (flags & ORA_NO_PERMUTE)))
+        return ORA_EINVAL;
     st.e = (double *)malloc(sizeof(double) * (size_t)n);
     st.f = (double *)malloc(sizeof(double) * (size_t)n);
     int status = ora_init(&st);
@@ -712,7 +715,7 @@ void ora_step_ext(int m, int n, double *Gr, double *Gi, size_t ldg,
     st.s = *s;
     st.Mt = *Mt;
     st.k = k;
-    st.nosort = (flags & ORA_NO_PERMUTE) != 0;
+    st.nosort = (flags & ORA_PERMUTE) == 0;
     st.comp = (flags & ORA_COMPENSATED) != 0;
     st.nogs = (flags & ORA_NO_GS) != 0;
     ora_step(&st);

@@ -118,14 +118,21 @@ typedef struct {
     long SW;                       /* swaps without transformation in the current sweep */
     long last_sw;                  /* swaps without transformation in the last step */
     int  rescaled;                 /* number of step-start downscalings */
-    int  nosort;                   /* apply U instead of U P (ignore the EVD's permutation) */
+    int  nosort;                   /* apply U instead of U P (the default; ORA_PERMUTE clears it) */
     int  comp;                     /* scaled dot-products with compensated summation */
     int  nogs;                     /* always rotate (no Gram-Schmidt replacement, eq. GScond) */
     long GS;                       /* Gram-Schmidt transformations in the current sweep */
     long last_gs;                  /* Gram-Schmidt transformations of the last step */
 } ora_svd;
 
+/* The EVD's permutation P (Sect. 2: the pivot columns are multiplied by U P
+ * instead of U when they are also to be kept sorted by norm) is optional in
+ * the paper.  With round-robin pairs it is off by default: a column swapped
+ * by P takes over the other column's remaining partners of the sweep, so a
+ * sweep no longer meets every pair of columns.  ORA_PERMUTE applies it;
+ * ORA_NO_PERMUTE names the default explicitly; both together are invalid. */
 #define ORA_NO_PERMUTE 1u
+#define ORA_PERMUTE 8u
 #define ORA_COMPENSATED 2u      /* Alg. zdpsclcs / ddpsclcs instead of zdpscl */
 #define ORA_NO_GS 4u            /* rotate even where eq. (GScond) calls for Gram-Schmidt */
 

@@ -22,7 +22,7 @@ import os as _os
 
 __all__ = [
     "lib", "JsvdError", "fortran_empty", "to_device_fortran", "evd2_batched", "State", "gesvj",
-    "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "COMPENSATED", "NO_GS",
+    "gesvj_batched", "Server", "split", "merge", "EVD_SCALED", "EVD_SINFORM", "NO_PERMUTE", "PERMUTE", "COMPENSATED", "NO_GS",
     "dot_scaled_batched", "evd2_batched_f32", "nrmf_batched",
 ]
 
@@ -34,6 +34,7 @@ EVD_SCALED, EVD_SINFORM = 1, 2
 NO_PERMUTE = 1
 COMPENSATED = 2
 NO_GS = 4
+PERMUTE = 8
 
 _lib = None
 

@@ -608,7 +608,7 @@ static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, hipS
             ctl.next = 0;
             ctl.count = (int)S;
             ctl.max_sweeps = 1;
-            ctl.nosort = 0;
+            ctl.nosort = 1;
             ctl.nogs = 0;
             ok = hipGetLastError() == hipSuccess &&
                  hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * S, hipMemcpyHostToDevice, s) == hipSuccess &&
@@ -762,7 +762,7 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
         ctl.next = 0;
         ctl.count = first[c + 1] - first[c];
         ctl.max_sweeps = max_sweeps;
-        ctl.nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+        ctl.nosort = iter_nosort(flags);
         ctl.nogs = (flags & JSVD_NO_GS) ? 1 : 0;
         memcpy(h + oCtl + 256 * (size_t)c, &ctl, sizeof(ctl));
     }
@@ -829,7 +829,7 @@ extern "C" int jsvd_batched_tune(int count, const int *m, const int *n, const in
                                  void *stream)
 {
     if (count < 0 || (count > 0 && (!m || !n))) return JSVD_EINVAL;
-    if (flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
+    if (!iter_flags_valid(flags, JSVD_NO_PERMUTE | JSVD_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
     std::vector<BatchItem> items;
     for (int i = 0; i < count; ++i) {
         const int c = is_complex ? (is_complex[i] != 0) : 0;
@@ -859,7 +859,7 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
     if (count < 0) return JSVD_EINVAL;
     if (count == 0) return JSVD_OK;
     if (!m || !n || !G_re || !ldg || !V_re || !ldv || !sv_e || !sv_f || !status) return JSVD_EINVAL;
-    if (flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
+    if (!iter_flags_valid(flags, JSVD_NO_PERMUTE | JSVD_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
     for (int i = 0; i < count; ++i) {
         const int c = is_complex ? is_complex[i] : 0;
         if (n[i] < 1 || m[i] < n[i] || !G_re[i] || !V_re[i] || !sv_e[i] || !sv_f[i] || ldg[i] < (size_t)m[i] ||

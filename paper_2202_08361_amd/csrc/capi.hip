@@ -162,7 +162,7 @@ static void fill_desc(SvdDescT<T> &d, int m, int n, int cplx, char *b, const Sta
     d.m = m;
     d.n = n;
     d.cplx = cplx;
-    d.nosort = 0;
+    d.nosort = 1;
     d.comp = 0;
     d.nogs = 0;
     d.Gr = (T *)(b + L.oG);
@@ -354,8 +354,8 @@ extern "C" int jsvd_state_set_launch(jsvd_state st, int threads_per_pair)
     return JSVD_OK;
 }
 
-static constexpr unsigned kIterFlags = JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS;
-static constexpr unsigned kIterFlagsF32 = JSVD_NO_PERMUTE | JSVD_NO_GS;
+static constexpr unsigned kIterFlags = JSVD_NO_PERMUTE | JSVD_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS;
+static constexpr unsigned kIterFlagsF32 = JSVD_NO_PERMUTE | JSVD_PERMUTE | JSVD_NO_GS;
 
 // the iteration flags a state accepts (the compensated dot-products are
 // double precision only)
@@ -364,7 +364,7 @@ static unsigned iter_flags_of(jsvd_state st) { return st->fp32 ? kIterFlagsF32 :
 static void apply_flags(jsvd_state st, unsigned flags)
 {
     st->flags = flags;
-    const int nosort = (flags & JSVD_NO_PERMUTE) ? 1 : 0;
+    const int nosort = iter_nosort(flags);
     const int comp = (flags & JSVD_COMPENSATED) ? 1 : 0;
     const int nogs = (flags & JSVD_NO_GS) ? 1 : 0;
     st->d.nosort = st->df.nosort = nosort;
@@ -374,7 +374,7 @@ static void apply_flags(jsvd_state st, unsigned flags)
 
 extern "C" int jsvd_state_set_flags(jsvd_state st, unsigned flags)
 {
-    if (!st || (flags & ~iter_flags_of(st))) return JSVD_EINVAL;
+    if (!st || !iter_flags_valid(flags, iter_flags_of(st))) return JSVD_EINVAL;
     apply_flags(st, flags);
     return JSVD_OK;
 }
@@ -822,7 +822,7 @@ static int gesvj_t(int m, int n, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im,
     if (n < 1 || m < n || !G_re || !V_re || !sv_e || !sv_f || ldg < (size_t)m || ldv < (size_t)n)
         return JSVD_EINVAL;
     if ((G_im == nullptr) != (V_im == nullptr)) return JSVD_EINVAL;
-    if (flags & ~(F32 ? kIterFlagsF32 : kIterFlags)) return JSVD_EINVAL;
+    if (!iter_flags_valid(flags, F32 ? kIterFlagsF32 : kIterFlags)) return JSVD_EINVAL;
     jsvd_state st = nullptr;
     int rc = state_create(m, n, G_im != nullptr, F32, &st);
     if (rc != JSVD_OK) return rc;

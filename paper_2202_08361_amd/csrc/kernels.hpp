@@ -5,7 +5,19 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/jsvd.h"
+
 namespace jsvd {
+
+// Iteration flags: only the bits in `allowed`, and not both JSVD_PERMUTE and
+// JSVD_NO_PERMUTE.
+inline bool iter_flags_valid(unsigned flags, unsigned allowed)
+{
+    return (flags & ~allowed) == 0 && !((flags & JSVD_PERMUTE) && (flags & JSVD_NO_PERMUTE));
+}
+
+// 1 (apply U, the default) unless the EVD's sorting permutation is asked for.
+inline int iter_nosort(unsigned flags) { return (flags & JSVD_PERMUTE) ? 0 : 1; }
 
 hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const double *ar,
                        const double *ai, double *cs, double *cr, double *ci, double *l1,
@@ -51,7 +63,7 @@ template <typename T>
 struct SvdDescT {
     int m, n;
     int cplx;
-    int nosort;            // ignore the permutation of the EVD during the iteration
+    int nosort;            // ignore the permutation of the EVD during the iteration (the default)
     int comp;              // compensated scaled dot-products (Alg. zdpsclcs / ddpsclcs; double only)
     int nogs;              // always rotate (no Gram-Schmidt replacement, eq. GScond)
     T *Gr, *Gi;            // working iteration matrix

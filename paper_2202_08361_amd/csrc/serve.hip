@@ -429,7 +429,7 @@ extern "C" int jsvd_serve_create(const jsvd_serve_config *cfg, jsvd_server *out)
     if (!out) return JSVD_EINVAL;
     *out = nullptr;
     if (!cfg || cfg->max_slots < 1 || cfg->max_slots > 1024 || cfg->hbm_budget_bytes == 0 ||
-        (cfg->flags & ~(JSVD_NO_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)))
+        !iter_flags_valid(cfg->flags, JSVD_NO_PERMUTE | JSVD_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS))
         return JSVD_EINVAL;
     jsvd_server sv = new (std::nothrow) jsvd_server_s;
     if (!sv) return JSVD_ENOMEM;

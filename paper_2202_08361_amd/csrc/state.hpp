@@ -36,7 +36,7 @@ struct jsvd_state_s {
     hipGraphExec_t graph;
     hipGraph_t graph_def;
     int graph_threads;
-    unsigned flags;          // JSVD_NO_PERMUTE | JSVD_COMPENSATED of the iteration
+    unsigned flags;          // iteration flags (JSVD_PERMUTE, JSVD_COMPENSATED, JSVD_NO_GS)
     unsigned graph_flags;    // flags the captured sweep was built with
 };
 
@@ -58,7 +58,7 @@ enum { V_COLS = 0, V_ROWS = 1, V_EITHER = 2 };
 // single precision state).
 size_t state_bytes(int m, int n, int cplx, bool fp32 = false);
 
-// Set the iteration flags (JSVD_NO_PERMUTE | JSVD_COMPENSATED) of a state.
+// Set the iteration flags (JSVD_PERMUTE, JSVD_COMPENSATED, JSVD_NO_GS) of a state.
 int state_set_flags(jsvd_state st, unsigned flags);
 
 // Enqueue the load of G (M~_0, s_0, G_1 = 2^{s_0} G, V_1 = I); a non-finite or

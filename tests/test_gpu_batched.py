@@ -79,7 +79,7 @@ def test_batched_failures_and_limits():
     assert res[3]["status"] == J().ENONFINITE and res[4]["status"] == J().EZERO
     assert res[0]["status"] == J().OK
     _check_batch(host[:3], max_sweeps=1)
-    _check_batch(host[:3], flags=J().NO_PERMUTE)
+    _check_batch(host[:3], flags=J().PERMUTE)
 
 
 def test_batched_workload_sample():
@@ -147,15 +147,15 @@ def _workload(count):
                            range(count)))
 
 
-@pytest.mark.parametrize("nopermute", [False, True])
-def test_batched_full_workload(nopermute):
+@pytest.mark.parametrize("permute", [False, True])
+def test_batched_full_workload(permute):
     """All 10,000 matrices of the batched workload (n ~ U{16..256}, m ~ U{n..2n},
     kappa log-uniform in [1e2, 1e8]) in one call, as the benchmark times it:
     every matrix converges, with sigma to 1e-10 relative for sigma >= 1e-6
     sigma_max (kappa <= 1e6, where that tolerance applies); on 16 of them
     the residual ||A - U diag(sigma) V^T||_F and ||V^T V - I||_max are within
     64 n eps (||A||_F for the residual)."""
-    flags = J().NO_PERMUTE if nopermute else 0
+    flags = J().PERMUTE if permute else 0
     work = _workload(10000)
     dev = [(J().to_device_fortran(A), None) for A, _ in work]
     res = J().gesvj_batched(dev, flags=flags)

@@ -162,7 +162,7 @@ def test_gesvj_compensated_bitwise(ora, m, n, cplx, kappa):
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 970 + m)
     sig = inputs.sigma_logspace(n, 1.0 / kappa)
     Ar, Ai = inputs.svd_matrix(m, n, sig, g, cplx=cplx)
-    for flags in (J().COMPENSATED, J().COMPENSATED | J().NO_PERMUTE):
+    for flags in (J().COMPENSATED, J().COMPENSATED | J().PERMUTE):
         ro = ora.gesvj(Ar, Ai, flags=flags)
         rg = J().gesvj(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None, flags=flags)
         assert rg["status"] == ro["status"] and rg["sweeps"] == ro["sweeps"], (flags, rg["sweeps"], ro["sweeps"])

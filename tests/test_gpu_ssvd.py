@@ -68,15 +68,15 @@ def _check_state(ost, sv, tag):
     assert sv["k"] == ost.k, tag + " k"
 
 
-def _pair_run(ora, m, n, cplx, steps, seed, threads=0, check_every=1, nosort=False):
+def _pair_run(ora, m, n, cplx, steps, seed, threads=0, check_every=1, permute=False):
     Ar, Ai = _columns(m, n, cplx, seed)
-    ost = ora.SState(Ar, Ai, nosort=nosort)
+    ost = ora.SState(Ar, Ai, permute=permute)
     assert ost.init() == ora.OK
     st = J().State(m, n, cplx, fp32=True)
     if threads:
         st.set_launch(threads)
-    if nosort:
-        st.set_flags(J().NO_PERMUTE)
+    if permute:
+        st.set_flags(J().PERMUTE)
     assert st.load(_dev32(Ar), _dev32(Ai)) == 0
     _check_state(ost, st.save(), f"load m={m} n={n}")
     for k in range(steps):
@@ -103,8 +103,8 @@ def test_sstep_bitwise(ora, m, n, cplx):
     _pair_run(ora, m, n, cplx, steps=min(2 * K + 1, 40), seed=m + n, check_every=1 if n <= 64 else 7)
 
 
-def test_sstep_no_permute(ora):
-    _pair_run(ora, 600, 30, True, steps=35, seed=11, nosort=True, check_every=5)
+def test_sstep_permute(ora):
+    _pair_run(ora, 600, 30, True, steps=35, seed=11, permute=True, check_every=5)
 
 
 @pytest.mark.parametrize("cplx,m", [(False, 500), (True, 500), (False, 3000), (True, 3000)])
@@ -156,7 +156,7 @@ def _check_svd(ro, rg):
         assert _bits_equal(_host(rg["U_im"]), ro["U_im"]) and _bits_equal(_host(rg["V_im"]), ro["V_im"])
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 8])
 def test_sgesvj_plain_real_256(ora, flags):
     """The plain real 256 x 256 workload rounded to float: the whole single
     precision SVD bit for bit, sigma within 32 eps kappa of the singular

@@ -44,14 +44,16 @@ def _check_state(ost, sv, tag):
     assert sv["k"] == ost.k, tag + " k"
 
 
-def _pair_run(ora, m, n, cplx, steps, seed, threads=0, check_every=1):
+def _pair_run(ora, m, n, cplx, steps, seed, threads=0, check_every=1, permute=False):
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 300 + seed)
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
-    ost = ora.State(Ar, Ai)
+    ost = ora.State(Ar, Ai, permute=permute)
     assert ost.init() == ora.OK
     st = J().State(m, n, cplx)
     if threads:
         st.set_launch(threads)
+    if permute:
+        st.set_flags(J().PERMUTE)
     dAr = J().to_device_fortran(Ar)
     dAi = J().to_device_fortran(Ai) if cplx else None
     assert st.load(dAr, dAi) == 0
@@ -72,11 +74,14 @@ def _pair_run(ora, m, n, cplx, steps, seed, threads=0, check_every=1):
     (16, 16, False), (70, 24, True), (100, 37, False), (256, 256, False), (97, 33, True),
     (1500, 64, False), (2100, 20, True), (4096, 8, False), (5000, 12, True), (9000, 6, False),
 ])
-def test_step_bitwise(ora, m, n, cplx):
+@pytest.mark.parametrize("permute", [False, True])
+def test_step_bitwise(ora, m, n, cplx, permute):
     """Every step, every bit: G, V, (e, f), M~, s and t against the oracle
-    (chains of the 1024-lane accumulation from m > 1024, ragged tails, odd n)."""
+    (chains of the 1024-lane accumulation from m > 1024, ragged tails, odd n),
+    with U (the default) and with the sorting permutation U P."""
     K = ora.rr_steps(n)
-    _pair_run(ora, m, n, cplx, steps=min(2 * K + 1, 40), seed=m + n, check_every=1 if n <= 64 else 7)
+    _pair_run(ora, m, n, cplx, steps=min(2 * K + 1, 40), seed=m + n, check_every=1 if n <= 64 else 7,
+              permute=permute)
 
 
 @pytest.mark.parametrize("cplx,m", [(False, 500), (True, 500), (False, 3000), (True, 3000)])
@@ -129,7 +134,7 @@ def _check_svd(ro, rg):
         assert _bits_equal(_host(rg["U_im"]), ro["U_im"]) and _bits_equal(_host(rg["V_im"]), ro["V_im"])
 
 
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 8])
 def test_gesvj_plain_real_256(ora, flags):
     """The plain real 256 x 256 workload (sigma log-spaced in [1e-6, 1]): the
     whole SVD bit-for-bit, and max relative sigma error <= 1e-10."""

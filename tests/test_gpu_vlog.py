@@ -271,8 +271,8 @@ def test_full_size_sweep_properties(m, n, cplx):
 
 @pytest.mark.parametrize("cplx", [False, True])
 def test_full_size_svd_workloads(cplx):
-    """The whole SVD of the large workloads as the benchmark times them, no
-    permutation: real 8192 x 2048 (A = U diag(sigma) V^T with Haar factors,
+    """The whole SVD of the large workloads as the benchmark times them, with
+    the default flags (no permutation): real 8192 x 2048 (A = U diag(sigma) V^T with Haar factors,
     sigma log-spaced in [1e-8, 1]) and complex 4096 x 4096 (sigma geometric
     from 1 to 1e-12).  It converges; the relative sigma error is at most 1e-10
     for sigma >= 1e-6 sigma_max (kappa <= 1e6, where that tolerance applies;
@@ -286,7 +286,7 @@ def test_full_size_svd_workloads(cplx):
     else:
         (Ar, sig), Ai = inputs.plain_real_tall(), None
     m, n = Ar.shape
-    r = J().gesvj(_dev(Ar), _dev(Ai), flags=J().NO_PERMUTE)
+    r = J().gesvj(_dev(Ar), _dev(Ai))
     assert r["status"] == 0, r["status"]
     sv = r["sv"].cpu().numpy()
     big = sig >= 1e-6 * sig[0]

@@ -218,15 +218,16 @@ def test_gs_step_forward_reversed(ora):
     transformation, and it is the Gram-Schmidt step; the larger column is
     first and unchanged, the smaller one is orthogonal to it; putting the
     columns in the other order gives the same G bit for bit (real data),
-    and V stays orthogonal.  With NO_PERMUTE the reversed order keeps the
-    smaller column first; with NO_GS the pair is rotated instead."""
+    and V stays orthogonal, all with the sorting permutation.  Without it
+    (the default) the reversed order keeps the smaller column first; with
+    NO_GS the pair is rotated instead."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 3007)
     for trial in range(20):
         m = int(g.integers(2, 600))
         A = _two_columns(g, m, 1000, float(g.uniform(-0.9, 0.9)))
         B = np.asfortranarray(A[:, ::-1])
-        sa = ora.State(A)
-        sb = ora.State(B)
+        sa = ora.State(A, permute=True)
+        sb = ora.State(B, permute=True)
         assert sa.init() == ora.OK and sb.init() == ora.OK
         big = sa.Gr[:, 0].copy()
         assert sa.step() == 1 and sa.last_gs == 1
@@ -238,7 +239,7 @@ def test_gs_step_forward_reversed(ora):
         assert abs(np.dot(a, b)) / (np.linalg.norm(a) * np.linalg.norm(b)) <= 1e-13
         for st in (sa, sb):
             assert np.linalg.norm(st.Vr.T @ st.Vr - np.eye(2)) <= 4 * EPS
-        sn = ora.State(B, nosort=True)
+        sn = ora.State(B)
         sn.init()
         small_before = sn.Gr[:, 0].copy()
         sn.step()
@@ -308,8 +309,8 @@ def test_gs_step_complex_orders(ora, single):
     """Complex pairs (random phases) with a norm ratio beyond 2^eta_hat
     upsilon (2^1000; single precision 2^120) in both column orders: one step
     takes the Gram-Schmidt step (a21' conjugated in the forward order, as it
-    is in the reversed one), leaving the larger column first and unchanged
-    and the two columns orthogonal."""
+    is in the reversed one), leaving the larger column first (with the
+    sorting permutation) and unchanged, and the two columns orthogonal."""
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 3008 + int(single))
     mp.dps = 40
     eps = EPS_F if single else EPS
@@ -323,7 +324,7 @@ def test_gs_step_complex_orders(ora, single):
             cols = (P, Q) if order == 0 else (Q, P)
             Ar = np.asfortranarray(np.stack([c.real for c in cols], axis=1).astype(dt))
             Ai = np.asfortranarray(np.stack([c.imag for c in cols], axis=1).astype(dt))
-            st = ora.SState(Ar, Ai) if single else ora.State(Ar, Ai)
+            st = ora.SState(Ar, Ai, permute=True) if single else ora.State(Ar, Ai, permute=True)
             assert st.init() == ora.OK
             big = (st.Gr[:, order].copy(), st.Gi[:, order].copy())
             assert st.step() == 1 and st.last_gs == 1

@@ -164,7 +164,7 @@ def _sv(res):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
-@pytest.mark.parametrize("flags", [0, 1])
+@pytest.mark.parametrize("flags", [0, 8])
 def test_s_gesvj_accuracy(ora, cplx, flags):
     """Haar factors, kappa = 1e3, rounded once to float: the singular values
     within 32 eps kappa of those of the rounded matrix (computed in double),

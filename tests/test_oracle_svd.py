@@ -415,20 +415,55 @@ def test_orthogonal_columns_no_rotation(ora):
         assert st.step() == 0 and st.last_sw == 0
 
 
-def test_no_permute_option(ora):
-    """Without the permutation of the EVD the iteration still converges to the
-    same singular values (sorted at the end); no column is ever swapped."""
+def test_permute_option(ora):
+    """With and without the EVD's sorting permutation the iteration converges
+    to the same singular values (sorted at the end).  Without it (the default,
+    also named by NO_PERMUTE) no column is ever swapped; asking for both is
+    invalid."""
     A, sig = inputs.plain_real_256()
     A = np.asfortranarray(A[:96, :64])
-    r0 = ora.gesvj(A)
-    r1 = ora.gesvj(A, flags=ora.NO_PERMUTE)
+    r0 = ora.gesvj(A, flags=ora.PERMUTE)
+    r1 = ora.gesvj(A)
+    r2 = ora.gesvj(A, flags=ora.NO_PERMUTE)
     assert r0["status"] == ora.OK and r1["status"] == ora.OK
     assert np.max(np.abs(_sv(r0) - _sv(r1)) / _sv(r0)) < 1e-12
-    st = ora.State(A, nosort=True)
+    for k in ("U_re", "V_re", "sv_e", "sv_f"):
+        assert np.array_equal(r1[k].view(np.int64), r2[k].view(np.int64))
+    assert r1["sweeps"] == r2["sweeps"]
+    assert ora.gesvj(A, flags=ora.PERMUTE | ora.NO_PERMUTE)["status"] == ora.EINVAL
+    st = ora.State(A)
     st.init()
     for _ in range(3 * ora.rr_steps(64)):
         st.step()
         assert st.last_sw == 0
+
+
+def _sweep_coverage(ora, n, swaps):
+    """Column pairs that meet in one round-robin sweep when the contents of
+    the (step, pair) positions in `swaps` are exchanged after their step."""
+    at = list(range(n))                        # content held at each position
+    met = set()
+    for k in range(ora.rr_steps(n)):
+        for l in range((n + (n & 1)) // 2):
+            ok, p, q = ora.rr_pair(n, k, l)
+            if not ok:
+                continue
+            met.add(frozenset((at[p], at[q])))
+            if (k, l) in swaps:
+                at[p], at[q] = at[q], at[p]
+    return met
+
+
+@pytest.mark.parametrize("n", [8, 9, 64, 255])
+def test_permutation_breaks_sweep_coverage(ora, n):
+    """Why the permutation is off by default with round-robin pairs: the
+    circle method meets every pair of columns once per sweep only while the
+    columns stay where they are.  One exchange of a pair's columns after step
+    1 already leaves pairs unmet in that sweep (and meets others twice)."""
+    allpairs = n * (n - 1) // 2
+    assert len(_sweep_coverage(ora, n, set())) == allpairs
+    assert len(_sweep_coverage(ora, n, {(1, 1)})) < allpairs
+    assert len(_sweep_coverage(ora, n, {(2, 1)})) < allpairs
 
 
 @pytest.mark.parametrize("flags", [0, 2])
