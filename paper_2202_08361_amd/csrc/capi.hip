@@ -448,26 +448,36 @@ static hipError_t settle(jsvd_state st, hipStream_t s)
     return st->fp32 ? launch_fold(st->df, z.prm, z.mx, s) : launch_fold(st->d, z.prm, z.mx, s);
 }
 
-// one step on a state whose V is in the path's layout: on the large-column
-// path the step continues from the previous one's slot (if its fold is
-// still due), its outcomes go to the next slot, and a full log is applied
-// to V; the fused kernel needs the scalars current
+// one step on a state whose V is in the path's layout.  Each step continues
+// from the previous one's slot (if its fold is still due) and logs its
+// outcomes to a slot of its own.  On the large-column path that is the next
+// slot of the outcome log, and a full log is applied to V; the fused kernel
+// (V rotated in the step, no V update pending) alternates between slots 0
+// and 1.
 template <typename T>
 static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s, bool defer = false)
 {
     const SvdDescT<T> &d = desc_of<T>(st);
-    if (!uses_gpair(st)) {
-        const hipError_t e = settle(st, s);
-        if (e != hipSuccess) return e;
-        return launch_step(d, state_threads(st), s);
-    }
     StepSlot prev;
     prev.prm = nullptr;
     prev.mx = nullptr;
     prev.hdr = nullptr;
     prev.mxkey = nullptr;
-    if (st->vlast >= 0) prev = slot_of(st, st->vlast);
+    if (!uses_gpair(st)) {
+        if (st->vlast >= 0) prev = slot_of(st, st->vlast);
+        const int jf = st->vlast == 0 ? 1 : 0;
+        const hipError_t e = launch_step(d, state_threads(st), slot_of(st, jf), prev, s);
+        if (e != hipSuccess) return e;
+        st->vlast = jf;
+        return hipSuccess;
+    }
     const int j = st->vbase + st->vlog_n;
+    if (st->vlast == j) {
+        // the last step was a fused one logged in the slot this step fills
+        const hipError_t e = settle(st, s);
+        if (e != hipSuccess) return e;
+    }
+    if (st->vlast >= 0) prev = slot_of(st, st->vlast);
     const hipError_t e = launch_gpair(d, slot_of(st, j), prev, s);
     if (e != hipSuccess) return e;
     st->vlast = j;

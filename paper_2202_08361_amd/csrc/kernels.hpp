@@ -32,11 +32,6 @@ hipError_t launch_sevd2(size_t r, const float *a11, const float *a22, const floa
 // Device-resident scalars of one SVD (updated only by kernels).
 struct DevScalars {
     unsigned long long Mt_bits;   // M~_k as the bit pattern of a non-negative double
-    unsigned long long M_step;    // max-norm of the transformed columns of this step (bits)
-    unsigned long long t_step;    // transformations in this step
-    unsigned long long sw_step;   // swaps without transformation in this step
-    unsigned long long gs_step;   // Gram-Schmidt transformations in this step
-    unsigned long long done;      // workgroups finished in this step
     long long k;                  // global step counter
     long long T;                  // transformations in the current sweep
     long long SW;                 // swaps without transformation in the current sweep
@@ -149,9 +144,13 @@ template <typename T>
 hipError_t launch_init_scale(const SvdDescT<T> &d, const T *Ar, const T *Ai, long long lda,
                              const unsigned long long *maxbits, int max_sweeps, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
-// one parallel step; threads = 0 picks automatically
+// one parallel step of the fused kernel (G and V in one workgroup per pair);
+// threads = 0 picks automatically.  Its outcomes go to the log slot `slot`;
+// with a previous slot (prev.prm != nullptr) the step starts from that
+// step's outcomes and also folds them into the device scalars, as the
+// large-column step does.
 template <typename T>
-hipError_t launch_step(const SvdDescT<T> &d, int threads, hipStream_t s);
+hipError_t launch_step(const SvdDescT<T> &d, int threads, StepSlot slot, StepSlot prev, hipStream_t s);
 int step_max_rows(int cplx, int W);
 int step_auto_threads(int m, int n);
 // end-of-sweep bookkeeping (1 thread)

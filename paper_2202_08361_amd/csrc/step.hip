@@ -8,10 +8,11 @@
 // Mapping: one workgroup of W threads per pivot pair; the column pair lives
 // in registers between the phases, so a step reads and writes each column of
 // G and V once (16 c n (m + n) bytes per fully transformed step, c = 1 real,
-// 2 complex).  The step index, M~ and the counters live on the device; the
-// last workgroup to finish a step (an atomic ticket) folds the per-step
-// results into them, so consecutive steps need no host involvement and can
-// be captured in a graph.
+// 2 complex).  The step index, M~ and the counters live on the device.  Each
+// workgroup logs its pair's outcome; the next step (its workgroup 0), or a
+// fold kernel before the scalars are read, folds a step into them
+// (fold.hpp), so consecutive steps need no host involvement, no workgroup
+// waits on another, and the steps can be captured in a graph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -19,6 +20,7 @@
 #include "evd2_core.hpp"
 #include "kernels.hpp"
 #include "pair.hpp"
+#include "fold.hpp"
 
 namespace jsvd {
 
@@ -31,42 +33,46 @@ struct StepSmem {
 };
 
 template <bool CPLX, int W, int R, bool COMP, typename T>
-__global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
+__global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d, StepSlot slot, StepSlot prev)
 {
     __shared__ StepSmem<W, COMP, T> sm;
     DevScalars *sc = d.sc;
-    if (*(volatile int *)&sc->stop) return;
-    const long long k = *(volatile long long *)&sc->k;
-    const T Mt = (T)bits2d(*(volatile unsigned long long *)&sc->Mt_bits);
-    const int m = d.m, n = d.n;
+    PairParam *const prm = slot.prm;
     const int t = threadIdx.x;
+    const int l = blockIdx.x;
+    if (*(volatile int *)&sc->stop) {
+        // a stopped iteration: the step does nothing, and its log slot says so
+        if (t == 0) {
+            PairParam z;
+            z.c = 1.0;
+            z.C = z.S = 0.0;
+            z.pq = z.flag = 0;
+            prm[l] = z;
+            slot.mx[l] = 0.0;
+        }
+        return;
+    }
+    const int m = d.m, n = d.n;
+    const int npairs = (n + 1) / 2;
+    const long long k = prev.prm ? prev.hdr->k + 1 : *(volatile long long *)&sc->k;
+    const unsigned long long pkey = prev.prm ? *prev.mxkey : 0ull;
     int p, q;
-    const bool valid = rr_pair(n, k, (int)blockIdx.x, &p, &q);
-
-    // step-start rescaling check, Sect. 3.2: s_(k) < 0 => scale by 2^{s_[k]}
-    const int sr = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt);
-    const bool rescale = sr < 0;
-    const int sp = rescale ? (d.lgbound - getexp(Mt) - 1) : 0;
+    const bool valid = rr_pair(n, k, l, &p, &q);
 
     T *const Gpr = d.Gr + (size_t)p * d.ldg;
     T *const Gqr = d.Gr + (size_t)q * d.ldg;
     T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
     T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
+    T *const Vpr = d.Vr + (size_t)p * d.ldv;
+    T *const Vqr = d.Vr + (size_t)q * d.ldv;
+    T *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
+    T *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
 
-    bool transform = false;
-    int pbit = 0, gs = 0;
-    T Mblk = T(0);
-
-    if (!valid) {
-        // the column sitting out this step (odd n): only the rescaling applies
-        if (rescale) {
-            for (int i = t; i < m; i += W) {
-                Gpr[i] = scal2(Gpr[i], sp);
-                if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
-            }
-        }
-    } else {
-        T xr[2][R], xi[2][R];
+    // the G pair and (short columns) the V pair, loaded before anything
+    // else: the loads of V do not depend on the pair's outcome
+    constexpr bool kVEarly = R <= 4 && W <= 256;
+    T xr[2][R], xi[2][R], vr[2][R], vi[2][R];
+    if (valid) {
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int i = t + W * j;
@@ -78,52 +84,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
                 xi[1][j] = in ? Gqi[i] : T(0);
             }
         }
-        if (rescale) {
-#pragma unroll
-            for (int j = 0; j < R; ++j)
-#pragma unroll
-                for (int c = 0; c < 2; ++c) {
-                    xr[c][j] = scal2(xr[c][j], sp);
-                    if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
-                }
-        }
-
-        const PairDecisionT<T> dc =
-            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, sm.norm, sm.dot, sm.mx1);
-        gs = dc.gs;
-        transform = dc.transform;
-        pbit = dc.pbit;
-        const NormT<T> np_ = dc.np, nq_ = dc.nq;
-
-        // ---- rotation (Alg. zjrot) or Gram-Schmidt step (eq. GS) or swap of
-        // the G pair, then the rotation or swap of the V pair
-        T *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
-        T *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
-        T *const Dp_i = pbit ? Gqi : Gpi;
-        T *const Dq_i = pbit ? Gpi : Gqi;
-        if (transform) {
-            const T Mx = transform_regs<CPLX, R>(xr, xi, dc);
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int i = t + W * j;
-                if (i < m) {
-                    Dp_r[i] = xr[0][j];
-                    Dq_r[i] = xr[1][j];
-                    if (CPLX) {
-                        Dp_i[i] = xi[0][j];
-                        Dq_i[i] = xi[1][j];
-                    }
-                }
-            }
-            T *const Vpr = d.Vr + (size_t)p * d.ldv;
-            T *const Vqr = d.Vr + (size_t)q * d.ldv;
-            T *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
-            T *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
-            T *const Ep_r = pbit ? Vqr : Vpr;
-            T *const Eq_r = pbit ? Vpr : Vqr;
-            T *const Ep_i = pbit ? Vqi : Vpi;
-            T *const Eq_i = pbit ? Vpi : Vqi;
-            T vr[2][R], vi[2][R];
+        if constexpr (kVEarly) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
@@ -135,46 +96,168 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
                     vi[1][j] = in ? Vqi[i] : T(0);
                 }
             }
-            (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
+        }
+    }
+
+    // floor(lg M~) of this step, which is all the rescaling check needs:
+    // after another step whose fold is due, from its slot (and workgroup 0
+    // does that fold), else from the device scalars
+    int eMt;
+    if (prev.prm) {
+        const T Mp = (T)bits2d(prev.hdr->Mt_bits);
+        const bool rp = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mp) < 0;
+        const T Mp2 = rp ? scal2(Mp, d.lgbound - getexp(Mp) - 1) : Mp;
+        eMt = max(getexp(Mp2), step_max_exp(pkey, k - 1));
+        if (l == 0) {
+            const unsigned long long Mt_bits = fold_step<W, T>(d, prev.prm, prev.mx, npairs);
+            if (t == 0) {
+                slot.hdr->k = k;
+                slot.hdr->Mt_bits = Mt_bits;
+            }
+        }
+    } else {
+        const unsigned long long Mt_bits = *(volatile unsigned long long *)&sc->Mt_bits;
+        eMt = getexp((T)bits2d(Mt_bits));
+        if (l == 0 && t == 0) {
+            slot.hdr->k = k;
+            slot.hdr->Mt_bits = Mt_bits;
+        }
+    }
+
+    // step-start rescaling check, Sect. 3.2: s_(k) < 0 => scale by 2^{s_[k]}
+    const int sr = (CPLX ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - eMt;
+    const bool rescale = sr < 0;
+    const int sp = rescale ? (d.lgbound - eMt - 1) : 0;
+
+    PairParam pp;
+    pp.pq = p | (q << 16);
+    pp.flag = 0;
+    pp.c = 1.0;
+    pp.C = 0.0;
+    pp.S = 0.0;
+    T Mblk = T(0);
+
+    if (!valid) {
+        // the column sitting out this step (odd n): only the rescaling applies
+        if (rescale) {
+            for (int i = t; i < m; i += W) {
+                Gpr[i] = scal2(Gpr[i], sp);
+                if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
+            }
+        }
+        if (t == 0) {
+            prm[l] = pp;
+            slot.mx[l] = 0.0;
+        }
+        return;
+    }
+    if (rescale) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                xr[c][j] = scal2(xr[c][j], sp);
+                if (CPLX) xi[c][j] = scal2(xi[c][j], sp);
+            }
+    }
+
+    const PairDecisionT<T> dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, sm.norm, sm.dot, sm.mx1);
+    const bool transform = dc.transform;
+    const int pbit = dc.pbit;
+    const NormT<T> np_ = dc.np, nq_ = dc.nq;
+
+    // ---- rotation (Alg. zjrot) or Gram-Schmidt step (eq. GS) or swap of
+    // the G pair, then the rotation or swap of the V pair
+    T *const Dp_r = pbit ? Gqr : Gpr;   // destination of x_p'
+    T *const Dq_r = pbit ? Gpr : Gqr;   // destination of x_q'
+    T *const Dp_i = pbit ? Gqi : Gpi;
+    T *const Dq_i = pbit ? Gpi : Gqi;
+    T *const Ep_r = pbit ? Vqr : Vpr;
+    T *const Eq_r = pbit ? Vpr : Vqr;
+    T *const Ep_i = pbit ? Vqi : Vpi;
+    T *const Eq_i = pbit ? Vpi : Vqi;
+    if (transform) {
+        const T Mx = transform_regs<CPLX, R>(xr, xi, dc);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + W * j;
+            if (i < m) {
+                Dp_r[i] = xr[0][j];
+                Dq_r[i] = xr[1][j];
+                if (CPLX) {
+                    Dp_i[i] = xi[0][j];
+                    Dq_i[i] = xi[1][j];
+                }
+            }
+        }
+        if constexpr (!kVEarly) {
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 const int i = t + W * j;
-                if (i < n) {
-                    Ep_r[i] = vr[0][j];
-                    Eq_r[i] = vr[1][j];
-                    if (CPLX) {
-                        Ep_i[i] = vi[0][j];
-                        Eq_i[i] = vi[1][j];
-                    }
+                const bool in = i < n;
+                vr[0][j] = in ? Vpr[i] : T(0);
+                vr[1][j] = in ? Vqr[i] : T(0);
+                if (CPLX) {
+                    vi[0][j] = in ? Vpi[i] : T(0);
+                    vi[1][j] = in ? Vqi[i] : T(0);
                 }
             }
-            T mm[1] = {Mx};
-            group_max<W, 1>(mm, sm.mx2);
-            Mblk = mm[0];
-        } else if (pbit || rescale) {
-            // swap (or only store the rescaled columns)
+        }
+        (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const int i = t + W * j;
-                if (i < m) {
-                    Dp_r[i] = xr[0][j];
-                    Dq_r[i] = xr[1][j];
-                    if (CPLX) {
-                        Dp_i[i] = xi[0][j];
-                        Dq_i[i] = xi[1][j];
-                    }
+        for (int j = 0; j < R; ++j) {
+            const int i = t + W * j;
+            if (i < n) {
+                Ep_r[i] = vr[0][j];
+                Eq_r[i] = vr[1][j];
+                if (CPLX) {
+                    Ep_i[i] = vi[0][j];
+                    Eq_i[i] = vi[1][j];
                 }
             }
-            if (pbit) {
-                T *const Vpr = d.Vr + (size_t)p * d.ldv;
-                T *const Vqr = d.Vr + (size_t)q * d.ldv;
+        }
+        T mm[1] = {Mx};
+        group_max<W, 1>(mm, sm.mx2);
+        Mblk = mm[0];
+        pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
+        pp.c = dc.c;
+        pp.C = dc.C;
+        pp.S = dc.S;
+    } else if (pbit || rescale) {
+        // swap (or only store the rescaled columns)
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = t + W * j;
+            if (i < m) {
+                Dp_r[i] = xr[0][j];
+                Dq_r[i] = xr[1][j];
+                if (CPLX) {
+                    Dp_i[i] = xi[0][j];
+                    Dq_i[i] = xi[1][j];
+                }
+            }
+        }
+        if (pbit) {
+            pp.flag = 2;
+            if constexpr (kVEarly) {
+#pragma unroll
+                for (int j = 0; j < R; ++j) {
+                    const int i = t + W * j;
+                    if (i < n) {
+                        Vpr[i] = vr[1][j];
+                        Vqr[i] = vr[0][j];
+                        if (CPLX) {
+                            Vpi[i] = vi[1][j];
+                            Vqi[i] = vi[0][j];
+                        }
+                    }
+                }
+            } else {
                 for (int i = t; i < n; i += W) {
                     const T a = Vpr[i], b = Vqr[i];
                     Vpr[i] = b;
                     Vqr[i] = a;
                     if (CPLX) {
-                        T *const Vpi = d.Vi + (size_t)p * d.ldv;
-                        T *const Vqi = d.Vi + (size_t)q * d.ldv;
                         const T ai = Vpi[i], bi = Vqi[i];
                         Vpi[i] = bi;
                         Vqi[i] = ai;
@@ -182,48 +265,20 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
                 }
             }
         }
-        if (t == 0) {
-            const T ep = np_.zero ? T(-INFINITY) : (T)np_.e;
-            const T eq = nq_.zero ? T(-INFINITY) : (T)nq_.e;
-            const int dp = pbit ? q : p, dq = pbit ? p : q;
-            d.e[dp] = ep;
-            d.f[dp] = np_.zero ? T(1) : np_.f;
-            d.e[dq] = eq;
-            d.f[dq] = nq_.zero ? T(1) : nq_.f;
-        }
     }
-
-    // ---- end of step: the last workgroup folds the step into the scalars
-    if constexpr (W > 64) __syncthreads();
+    // ---- the pair's outcome for the fold of this step (done by the next
+    // step or a fold kernel), and its norms
     if (t == 0) {
-        if (transform) {
-            atomicMax(&sc->M_step, d2bits((double)Mblk));
-            atomicAdd(&sc->t_step, 1ull);
-            if (gs) atomicAdd(&sc->gs_step, 1ull);
-        } else if (pbit) {
-            atomicAdd(&sc->sw_step, 1ull);
-        }
-        __threadfence();
-        const unsigned long long prev = atomicAdd(&sc->done, 1ull);
-        if (prev == (unsigned long long)gridDim.x - 1) {
-            __threadfence();
-            const T Mt2 = rescale ? scal2(Mt, sp) : Mt;
-            const T Ms = (T)bits2d(atomicExch(&sc->M_step, 0ull));
-            sc->Mt_bits = d2bits((double)fmax(Mt2, Ms));
-            const long long tt = (long long)atomicExch(&sc->t_step, 0ull);
-            const long long sw = (long long)atomicExch(&sc->sw_step, 0ull);
-            sc->T += tt;
-            sc->SW += sw;
-            sc->GS += (long long)atomicExch(&sc->gs_step, 0ull);
-            sc->last_t = tt;
-            if (rescale) {
-                sc->s += sp;
-                sc->rescaled += 1;
-            }
-            atomicExch(&sc->done, 0ull);
-            sc->k = k + 1;
-            __threadfence();
-        }
+        prm[l] = pp;
+        slot.mx[l] = (double)Mblk;
+        if (transform && Mblk > T(0)) step_max_add(slot.mxkey, k, getexp(Mblk));
+        const T ep = np_.zero ? T(-INFINITY) : (T)np_.e;
+        const T eq = nq_.zero ? T(-INFINITY) : (T)nq_.e;
+        const int dp = pbit ? q : p, dq = pbit ? p : q;
+        d.e[dp] = ep;
+        d.f[dp] = np_.zero ? T(1) : np_.f;
+        d.e[dq] = eq;
+        d.f[dq] = nq_.zero ? T(1) : nq_.f;
     }
 }
 
@@ -231,31 +286,31 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d)
 // dispatch over (complex, W, R, compensated dot-products; these exist in
 // double precision only)
 template <bool CPLX, int W, int R, typename T>
-static hipError_t launch_step_t(const SvdDescT<T> &d, hipStream_t s)
+static hipError_t launch_step_t(const SvdDescT<T> &d, const StepSlot &slot, const StepSlot &prev, hipStream_t s)
 {
     const int N = d.n + (d.n & 1);
     const unsigned blocks = (unsigned)(N / 2);
     if (d.comp) {
         if constexpr (sizeof(T) == sizeof(double))
-            hipLaunchKernelGGL((step_kernel<CPLX, W, R, true, T>), dim3(blocks), dim3(W), 0, s, d);
+            hipLaunchKernelGGL((step_kernel<CPLX, W, R, true, T>), dim3(blocks), dim3(W), 0, s, d, slot, prev);
         else
             return hipErrorInvalidValue;
     } else {
-        hipLaunchKernelGGL((step_kernel<CPLX, W, R, false, T>), dim3(blocks), dim3(W), 0, s, d);
+        hipLaunchKernelGGL((step_kernel<CPLX, W, R, false, T>), dim3(blocks), dim3(W), 0, s, d, slot, prev);
     }
     return hipGetLastError();
 }
 
 template <bool CPLX, int W, typename T>
-static hipError_t launch_step_w(const SvdDescT<T> &d, hipStream_t s)
+static hipError_t launch_step_w(const SvdDescT<T> &d, const StepSlot &slot, const StepSlot &prev, hipStream_t s)
 {
     const int R = (d.m + W - 1) / W;
-    if (R <= 1) return launch_step_t<CPLX, W, 1>(d, s);
-    if (R <= 2) return launch_step_t<CPLX, W, 2>(d, s);
-    if (R <= 4) return launch_step_t<CPLX, W, 4>(d, s);
-    if (R <= 8) return launch_step_t<CPLX, W, 8>(d, s);
+    if (R <= 1) return launch_step_t<CPLX, W, 1>(d, slot, prev, s);
+    if (R <= 2) return launch_step_t<CPLX, W, 2>(d, slot, prev, s);
+    if (R <= 4) return launch_step_t<CPLX, W, 4>(d, slot, prev, s);
+    if (R <= 8) return launch_step_t<CPLX, W, 8>(d, slot, prev, s);
     if constexpr (!CPLX && W == 1024)
-        if (R <= 16) return launch_step_t<CPLX, W, 16>(d, s);
+        if (R <= 16) return launch_step_t<CPLX, W, 16>(d, slot, prev, s);
     return hipErrorInvalidValue;
 }
 
@@ -272,25 +327,25 @@ int step_auto_threads(int m, int n)
 }
 
 template <typename T>
-hipError_t launch_step(const SvdDescT<T> &d, int threads, hipStream_t s)
+hipError_t launch_step(const SvdDescT<T> &d, int threads, StepSlot slot, StepSlot prev, hipStream_t s)
 {
     if (threads <= 0) threads = step_auto_threads(d.m, d.n);
     if (d.m > step_max_rows(d.cplx, threads)) return hipErrorInvalidValue;
     if (d.cplx) {
         switch (threads) {
-        case 64: return launch_step_w<true, 64>(d, s);
-        case 128: return launch_step_w<true, 128>(d, s);
-        case 256: return launch_step_w<true, 256>(d, s);
-        case 512: return launch_step_w<true, 512>(d, s);
-        case 1024: return launch_step_w<true, 1024>(d, s);
+        case 64: return launch_step_w<true, 64>(d, slot, prev, s);
+        case 128: return launch_step_w<true, 128>(d, slot, prev, s);
+        case 256: return launch_step_w<true, 256>(d, slot, prev, s);
+        case 512: return launch_step_w<true, 512>(d, slot, prev, s);
+        case 1024: return launch_step_w<true, 1024>(d, slot, prev, s);
         }
     } else {
         switch (threads) {
-        case 64: return launch_step_w<false, 64>(d, s);
-        case 128: return launch_step_w<false, 128>(d, s);
-        case 256: return launch_step_w<false, 256>(d, s);
-        case 512: return launch_step_w<false, 512>(d, s);
-        case 1024: return launch_step_w<false, 1024>(d, s);
+        case 64: return launch_step_w<false, 64>(d, slot, prev, s);
+        case 128: return launch_step_w<false, 128>(d, slot, prev, s);
+        case 256: return launch_step_w<false, 256>(d, slot, prev, s);
+        case 512: return launch_step_w<false, 512>(d, slot, prev, s);
+        case 1024: return launch_step_w<false, 1024>(d, slot, prev, s);
         }
     }
     return hipErrorInvalidValue;
@@ -350,11 +405,6 @@ __global__ void init_scalars_kernel(SvdDescT<T> d, const unsigned long long *max
     const T M0 = (T)bits2d(*maxbits);
     DevScalars *sc = d.sc;
     sc->Mt_bits = 0;
-    sc->M_step = 0;
-    sc->t_step = 0;
-    sc->sw_step = 0;
-    sc->gs_step = 0;
-    sc->done = 0;
     sc->k = 0;
     sc->T = 0;
     sc->SW = 0;
@@ -641,7 +691,7 @@ hipError_t launch_merge(int m, int n, const double *Xr, const double *Xi, long l
                                          hipStream_t);                                                            \
     template hipError_t launch_init_scale<T>(const SvdDescT<T> &, const T *, const T *, long long,                  \
                                              const unsigned long long *, int, hipStream_t);                       \
-    template hipError_t launch_step<T>(const SvdDescT<T> &, int, hipStream_t);                                     \
+    template hipError_t launch_step<T>(const SvdDescT<T> &, int, StepSlot, StepSlot, hipStream_t);                 \
     template hipError_t launch_colnorms_raw<T>(const SvdDescT<T> &, hipStream_t);                                  \
     template hipError_t launch_rank<T>(const SvdDescT<T> &, int *, hipStream_t);                                   \
     template hipError_t launch_final_write<T>(const SvdDescT<T> &, const int *, T *, T *, long long, T *, T *,      \

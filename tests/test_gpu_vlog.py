@@ -188,16 +188,19 @@ def test_gesvj_large_column_path(ora, single, m, n, cplx):
         assert _bits_equal(_host(rg[k]), ro[k]), k
 
 
+@pytest.mark.parametrize("m,permute", [(320, True), (100, False)])
 @pytest.mark.parametrize("single", [False, True])
 @pytest.mark.parametrize("cplx", [False, True])
-def test_rescale_inside_a_chain(ora, single, cplx):
-    """Sect. 3.2 on the large-column path: G restored with its largest
-    components just below the downscaling threshold, so that a later step of
-    an unbroken chain (whose step index and M~ come from the previous step's
-    log slot and max-norm key, not from the device scalars) is the one that
-    downscales.  Six steps, then every bit against the oracle, the
-    downscaling count included."""
-    m, n = 320, 16
+def test_rescale_inside_a_chain(ora, single, cplx, m, permute):
+    """Sect. 3.2 on the large-column path (320 rows) and the fused kernel
+    (100 rows): G restored with its largest components just below the
+    downscaling threshold, so that a later step of an unbroken chain (whose
+    step index and M~ come from the previous step's log slot and max-norm
+    key, not from the device scalars) is the one that downscales.  Six steps,
+    then every bit against the oracle, the downscaling count included.  (With
+    or without the sorting permutation: the trajectory on which one of the
+    first six steps downscales in every case.)"""
+    n = 16
     g = inputs.rng(inputs.CFG_PLAIN_LARGE, 2900 + 2 * int(cplx) + int(single))
     top = (124 if cplx else 126) if single else (1020 if cplx else 1022)
     Ar, Ai = inputs.random_columns(m, n, g, cplx)
@@ -210,7 +213,7 @@ def test_rescale_inside_a_chain(ora, single, cplx):
     Gi = np.asfortranarray((Ai * scale).astype(dt)) if cplx else None
     mt = float(max(np.max(np.abs(Gr)), np.max(np.abs(Gi)) if cplx else 0.0))
     assert np.isfinite(mt) and np.frexp(mt)[1] - 1 <= top
-    ost = (ora.SState if single else ora.State)(Gr, Gi)
+    ost = (ora.SState if single else ora.State)(Gr, Gi, permute=permute)
     assert ost.init() == ora.OK
     ost.Gr[:] = Gr
     if cplx:
@@ -220,6 +223,8 @@ def test_rescale_inside_a_chain(ora, single, cplx):
         ost.Vi[:] = 0
     ost.s, ost.Mt, ost.k = 0, mt, 0
     st = J().State(m, n, cplx, fp32=single)
+    if permute:
+        st.set_flags(J().PERMUTE)
     eye = np.asfortranarray(np.eye(n, dtype=dt))
     st.restore(_dev(Gr), _dev(Gi), _dev(eye), _dev(np.zeros_like(eye)) if cplx else None, 0, mt, 0)
     seen = []
