@@ -32,6 +32,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def host_cpu():
+    """The host's CPU model and thread counts (for the oracle baselines)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return dict(cpu_model=model, host_threads=os.cpu_count(), usable_threads=usable)
+
+
 def measured_traffic(kind):
     """HBM bytes per launch of the EVD kernel from the committed hardware-counter
     record (FETCH_SIZE/WRITE_SIZE scaled by a plain copy), or None when the
@@ -207,6 +225,44 @@ def evd_workload(torch, J, inputs, r, K, W):
     return wall, dur, dev
 
 
+def evd_ceiling(torch, J, dev, r, K):
+    """The memory-system ceiling of the EVD kernels on this device: the same
+    streams moved without arithmetic (jsvd_evd2_stream_ceiling, same launch
+    shape and access hints), and a plain device copy of the complex EVD's
+    bytes (half read, half written), each timed with HIP events over K
+    launches after one warm-up."""
+    res = {}
+    for cplx, nb in ((False, EVD_BYTES_REAL), (True, EVD_BYTES_CPLX)):
+        ins, out, _ = dev[cplx]
+        J.evd2_stream_ceiling(*ins, out=out)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+        for a, b in evs:
+            a.record()
+            J.evd2_stream_ceiling(*ins, out=out)
+            b.record()
+        torch.cuda.synchronize()
+        t = sum(a.elapsed_time(b) for a, b in evs) / K * 1e-3
+        res["stream_complex" if cplx else "stream_real"] = dict(avg_launch_ms=round(t * 1e3, 4),
+                                                               GBs=round(nb * r / t / 1e9, 1))
+    half = EVD_BYTES_CPLX * r // 2
+    src = torch.empty(half // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    for a, b in evs:
+        a.record()
+        dst.copy_(src)
+        b.record()
+    torch.cuda.synchronize()
+    t = sum(a.elapsed_time(b) for a, b in evs) / K * 1e-3
+    res["plain_copy"] = dict(bytes=2 * half, avg_launch_ms=round(t * 1e3, 4), GBs=round(2 * half / t / 1e9, 1))
+    del src, dst
+    torch.cuda.empty_cache()
+    return res
+
+
 EVD_BYTES_REAL_F32 = 32      # 3 x 4 in, 4 x 4 out, 4 zp
 EVD_BYTES_CPLX_F32 = 40      # 4 x 4 in, 5 x 4 out, 4 zp
 
@@ -269,13 +325,23 @@ def step_roofline(torch, J, inputs, m, n, cplx, flags=0, fp32=False):
     c = 2 if cplx else 1
     es = 4 if fp32 else 8
     tr = (q["T"] - T0) / VLOG_STEPS
-    # per step: the transformed G column pairs read and written once; V read
-    # and written once per outcome log
-    byts = 2.0 * es * c * m * n * (tr / (n // 2)) + 2.0 * es * c * n * n / VLOG_STEPS
+    # (i) the per-step unit of the step's definition: every transformed pair's
+    # G and V columns read and written once, 16 c n (m + n) bytes in double
+    # precision when all n/2 pairs transform
+    frac_tr = tr / (n // 2)
+    b_step = 2.0 * es * c * n * (m + n) * frac_tr
+    # (ii) what this implementation moves: the transformed G column pairs read
+    # and written once per step, V read and written once per outcome log
+    b_deferred = 2.0 * es * c * m * n * frac_tr + 2.0 * es * c * n * n / VLOG_STEPS
     st.close()
     return dict(m=m, n=n, complex=bool(cplx), dtype="f32" if fp32 else "f64", us_per_step=t * 1e6,
-                transformed_per_step=tr, pairs=n // 2, v_update_every=VLOG_STEPS, algorithmic_bytes=byts,
-                achieved_GBs=byts / t / 1e9, frac=byts / t / 1e9 / HBM_PEAK_GBS)
+                transformed_per_step=tr, pairs=n // 2, v_update_every=VLOG_STEPS,
+                bytes_per_step_g_and_v=b_step, GBs_g_and_v=b_step / t / 1e9,
+                frac_g_and_v=b_step / t / 1e9 / HBM_PEAK_GBS,
+                bytes_per_step_deferred_v=b_deferred, achieved_GBs=b_deferred / t / 1e9,
+                frac=b_deferred / t / 1e9 / HBM_PEAK_GBS,
+                frac_unit="deferred V: G pairs read+written per step, V read+written once per "
+                          f"{VLOG_STEPS} steps (frac_g_and_v: G and V every step)")
 
 
 def nrmf_rate(torch, J, inputs, m, n, cplx, K=10, lanes=1024):
@@ -354,9 +420,24 @@ def batched_inputs(inputs, count):
     return _batched_cache["mats"], _batched_cache["sigs"]
 
 
+def _svd_bytes(m, n, sweeps, transformations, c=1):
+    """Algorithmic bytes of one SVD in double precision: (upper) every pair of
+    every step transforms, 16 c n (m + n) bytes per step over the sweeps and
+    the final sweep that finds nothing to do; (moved) both G columns of every
+    pair read in every step, and the transformed pairs' G columns written and
+    V columns read and written."""
+    K = n - 1 if n % 2 == 0 else n
+    upper = 16.0 * c * n * (m + n) * K * (sweeps + 1)
+    moved = 16.0 * c * m * (n // 2) * K * (sweeps + 1) + transformations * (16.0 * c * m + 32.0 * c * n)
+    return upper, moved
+
+
 def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
-    """The first `count` matrices of the batched workload in one call, and the
-    first `plain_count` of them one by one through jsvd_gesvj."""
+    """The first `count` matrices of the batched workload in one call, and a
+    sample of `plain_count` of them (stratified by n: every k-th in the order
+    of n) one by one through jsvd_gesvj.  Both are priced by the same bytes
+    (_svd_bytes, from the batched call's per-matrix sweeps and
+    transformation counts, which the plain path shares bit for bit)."""
     import numpy as np
     m, n, kappa = inputs.batched_shapes(10000)
     mats, sigs = batched_inputs(inputs, count)
@@ -378,70 +459,140 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
     res = J.gesvj_batched(dev, flags=flags)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
-    errs, byts, sweeps = [], 0.0, []
+    errs, up, mv, sweeps = [], np.zeros(count), np.zeros(count), []
     for i, r in enumerate(res):
         sv = np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))
         big = sigs[i] >= 1e-6 * sigs[i][0]
         errs.append(float(np.max(np.abs(sv[big] - sigs[i][big]) / sigs[i][big])))
-        K = n[i] - 1 if n[i] % 2 == 0 else n[i]
-        byts += 16.0 * n[i] * (m[i] + n[i]) * K * (r["sweeps"] + 1)
+        up[i], mv[i] = _svd_bytes(int(m[i]), int(n[i]), r["sweeps"], r["transformations"])
         sweeps.append(r["sweeps"])
-    dev2 = [J.to_device_fortran(A) for A in mats[:plain_count]]
+    del dev, res
+    _batched_cache["bytes_upper_%d" % flags] = up
+    # the plain sample: every k-th matrix in the order of n
+    by_n = np.argsort(n[:count], kind="stable")
+    k = max(1, count // plain_count)
+    sample = [int(i) for i in by_n[k // 2::k][:plain_count]]
+    dev2 = [J.to_device_fortran(mats[i]) for i in sample]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for A in dev2:
         J.gesvj(A, flags=flags, overwrite=True)
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
+    ps = len(sample)
+    bu, bm = up.sum(), mv.sum()
+    pu, pm = up[sample].sum(), mv[sample].sum()
     return dict(count=count, batched_s=tb, batched_svds_per_s=count / tb,
-                plain_count=plain_count, plain_s=tp, plain_svds_per_s=plain_count / tp,
-                speedup=(count / tb) / (plain_count / tp), max_rel_sigma_err=max(errs),
+                plain_count=ps, plain_sample="every %d-th matrix in the order of n (n from %d to %d)"
+                % (k, int(n[sample[0]]), int(n[sample[-1]])),
+                plain_s=tp, plain_svds_per_s=ps / tp,
+                speedup=(count / tb) / (ps / tp), max_rel_sigma_err=max(errs),
                 mean_sweeps=float(np.mean(sweeps)), max_sweeps=int(max(sweeps)),
-                algorithmic_bytes_upper=byts, algorithmic_GBs_upper=byts / tb / 1e9,
+                bytes_unit="upper: 16 n (m + n) per step (every pair transforms), over sweeps + 1; "
+                           "moved: G pairs read every step + transformed pairs' G written and V read+written",
+                batched_bytes_upper=float(bu), batched_GBs_upper=float(bu / tb / 1e9),
+                batched_frac_upper=float(bu / tb / 1e9 / HBM_PEAK_GBS),
+                batched_bytes_moved=float(bm), batched_GBs_moved=float(bm / tb / 1e9),
+                batched_frac_moved=float(bm / tb / 1e9 / HBM_PEAK_GBS),
+                plain_GBs_upper=float(pu / tp / 1e9), plain_frac_upper=float(pu / tp / 1e9 / HBM_PEAK_GBS),
+                plain_GBs_moved=float(pm / tp / 1e9), plain_frac_moved=float(pm / tp / 1e9 / HBM_PEAK_GBS),
                 threads_per_matrix=dict(sorted(launch.items())), tune_s=round(tune_s, 3),
                 bit_identical_to_plain="tested (tests/test_gpu_batched.py)")
 
 
-def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32, budget=64 << 30,
-                slots=16, drain_limit=120.0, max_large=0):
-    """Poisson arrivals replayed from a pre-generated pool of request matrices.
-    Beside the server's figures: the time the plain path (jsvd_gesvj, one
-    request after another) would need for the same completed requests, from
-    one timed solve of each pool matrix."""
+_serve_cache = {}
+
+
+def serve_pool(torch, J, inputs, pool_size, flags):
+    """The request pool of the serving workload: the shapes of the first
+    `pool_size` requests of the stream (70 % real, n log-uniform in
+    [32, 2048], m uniform in [n, 2n], kappa log-uniform in [1e2, 1e10]), each
+    matrix from its own seeded stream, generated in parallel host threads
+    (one-thread BLAS each), then moved to the device.  Beside each: the plain
+    path's time for it alone (jsvd_gesvj on a fresh copy, after one warm-up
+    solve of the pool's first matrix), and the batched launch shapes of the
+    pool's small requests, measured up front."""
     import numpy as np
-    t_arr, cplx, m, n, kappa = inputs.serve_stream(rate, duration)
-    g = inputs.rng(inputs.CFG_SERVE, 12345)
-    pidx = np.arange(len(t_arr)) % pool_size
-    pool = []
-    for k in range(pool_size):
-        Ar, Ai, sig = inputs.serve_matrix(int(m[k]), int(n[k]), float(kappa[k]), bool(cplx[k]), g)
-        pool.append((J.to_device_fortran(Ar), None if Ai is None else J.to_device_fortran(Ai)))
-    # the batched launch shapes of the pool's small requests, measured up front
-    J.batched_tune([(int(m[k]), int(n[k]), bool(cplx[k])) for k in range(pool_size)], flags=flags)
-    torch.cuda.synchronize()
-    srv = J.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=max_queue, flags=flags, max_large=max_large)
-    outstanding, rejected, submitted, done = {}, 0, 0, []
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    key = (pool_size, flags)
+    if _serve_cache.get("key") == key:
+        return _serve_cache
+    _, cplx, m, n, kappa = inputs.serve_stream(2000.0, 60.0)
     t0 = time.perf_counter()
-    for i, ta in enumerate(t_arr):
-        while time.perf_counter() - t0 < ta:
-            time.sleep(0.0002)
-        st = srv.stats()
-        if st["queue_depth"] >= max_queue:
-            rejected += 1
-            continue
-        Gr, Gi = pool[pidx[i]]
+
+    def make(k):
+        g = inputs.rng(inputs.CFG_SERVE, 50000 + k)
+        Ar, Ai, _ = inputs.serve_matrix(int(m[k]), int(n[k]), float(kappa[k]), bool(cplx[k]), g)
+        return Ar, Ai
+    with threadpool_limits(1), ThreadPoolExecutor(max(1, min(16, os.cpu_count() or 1))) as ex:
+        host = list(ex.map(make, range(pool_size)))
+    gen_s = time.perf_counter() - t0
+    pool = [(J.to_device_fortran(Ar), None if Ai is None else J.to_device_fortran(Ai)) for Ar, Ai in host]
+    del host
+    J.batched_tune([(int(m[k]), int(n[k]), bool(cplx[k])) for k in range(pool_size)], flags=flags)
+
+    def fresh(k):
+        Gr, Gi = pool[k]
         gr = J.fortran_empty(*Gr.shape)
         gr.copy_(Gr)
         gi = None
         if Gi is not None:
             gi = J.fortran_empty(*Gi.shape)
             gi.copy_(Gi)
+        return gr, gi
+    gr, gi = fresh(0)
+    J.gesvj(gr, gi, flags=flags, overwrite=True)
+    solo = []
+    for k in range(pool_size):
+        gr, gi = fresh(k)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        J.gesvj(gr, gi, flags=flags, overwrite=True)
+        torch.cuda.synchronize()
+        solo.append(time.perf_counter() - ts)
+    small = [int(m[k]) <= 512 and int(n[k]) <= 512 for k in range(pool_size)]
+    _serve_cache.update(key=key, pool=pool, fresh=fresh, solo=solo, gen_s=gen_s, small=small,
+                        shapes=[(int(m[k]), int(n[k]), bool(cplx[k])) for k in range(pool_size)])
+    log(f"[bench]   serving pool: {pool_size} requests generated in {gen_s:.1f} s; plain path "
+        f"{sum(solo):.2f} s for all of them")
+    return _serve_cache
+
+
+def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32, budget=64 << 30,
+                slots=16, drain_limit=120.0, max_large=0):
+    """Poisson arrivals at `rate` for `duration` seconds, each request a fresh
+    device copy of a pool matrix (serve_pool) submitted to the server when
+    its queue holds fewer than max_queue requests (else rejected: 0 means
+    no limit).  Beside the server's figures: the plain path's time for the
+    same completed requests one after another (the sum of their pool
+    matrices' solo times)."""
+    import numpy as np
+    P = serve_pool(torch, J, inputs, pool_size, flags)
+    t_arr = inputs.serve_stream(rate, duration)[0]
+    srv = J.Server(hbm_budget_bytes=budget, max_slots=slots, max_queue=max_queue, flags=flags, max_large=max_large)
+    outstanding, rejected, submitted, done = {}, 0, 0, []
+    t0 = time.perf_counter()
+    next_log = 15.0
+    for i, ta in enumerate(t_arr):
+        while time.perf_counter() - t0 < ta:
+            time.sleep(0.0002)
+        if ta >= next_log:
+            q, a, _ = srv.load()
+            log(f"[bench]   serving {rate:g}/s: t = {ta:.0f} s, submitted {submitted}, completed {len(done)}, "
+                f"rejected {rejected}, queued {q}, active {a}")
+            next_log += 15.0
+        if max_queue > 0 and srv.load()[0] >= max_queue:
+            rejected += 1
+            continue
+        k = i % pool_size
+        gr, gi = P["fresh"](k)
         t = srv.submit(gr, gi)
         if t is None:
             rejected += 1
             continue
         submitted += 1
-        outstanding[t] = (gr, gi, int(pidx[i]))
+        outstanding[t] = (gr, gi, k)
         if i % 64 == 0:
             for tk in [tk for tk in outstanding if srv.poll(tk)[0]]:
                 srv.wait(tk)
@@ -459,28 +610,16 @@ def serving_run(torch, J, inputs, rate, duration, pool_size, flags, max_queue=32
     unfinished = len(outstanding)
     if unfinished == 0:
         srv.close()
-    # the plain path on the same requests: each pool matrix used once, timed
-    solo = {}
-    for kq in sorted(set(done)):
-        Gr, Gi = pool[kq]
-        gr = J.fortran_empty(*Gr.shape)
-        gr.copy_(Gr)
-        gi = None
-        if Gi is not None:
-            gi = J.fortran_empty(*Gi.shape)
-            gi.copy_(Gi)
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        J.gesvj(gr, gi, flags=flags, overwrite=True)
-        torch.cuda.synchronize()
-        solo[kq] = time.perf_counter() - ts
-    plain_s = sum(solo[kq] for kq in done)
+    plain_s = sum(P["solo"][k] for k in done)
     return dict(offered_rate=rate, arrival_window_s=duration, offered=len(t_arr), submitted=submitted,
                 rejected_backpressure=rejected, completed=st["completed"], unfinished_at_limit=unfinished,
                 wall_s=wall, arrivals_s=t_end_arrivals, svds_per_s=st["completed"] / wall,
                 p50_latency_ms=st["p50_ns"] / 1e6, p99_latency_ms=st["p99_ns"] / 1e6,
                 p50_queue_ms=st["p50_queue_ns"] / 1e6, p99_queue_ms=st["p99_queue_ns"] / 1e6,
-                pool=pool_size, max_queue=max_queue, slots=slots, flags=flags, max_large=max_large,
+                p50_service_ms=st["p50_service_ns"] / 1e6, p99_service_ms=st["p99_service_ns"] / 1e6,
+                completed_small=sum(1 for k in done if P["small"][k]),
+                pool=pool_size, pool_generation_s=round(P["gen_s"], 1), max_queue=max_queue, slots=slots,
+                flags=flags, max_large=max_large,
                 plain_same_requests_s=plain_s, served_vs_plain=(plain_s / wall) if wall > 0 else None)
 
 
@@ -537,24 +676,41 @@ def svd_large(torch, J, inputs, cplx, flags):
             "input_generation_s": round(gen_s, 1)}
 
 
-def cpu_oracle_svd(inputs, sweeps_256=None, sweeps_large=None):
-    """Context: the oracle (sequential C, one host thread) on the SVD
-    workloads: one sweep of the 256 x 256 real SVD (scaled by the sweep count
-    of the GPU run, which the oracle shares bit for bit), and two steps each of
-    the real 8192 x 2048 and complex 4096 x 4096 workloads, extrapolated to one
-    sweep (K steps) and to the whole SVD with the GPU run's sweep count."""
+def cpu_oracle_svd(inputs, sweeps_256=None, sweeps_large=None, c4_sample=96):
+    """Context: the oracle (C, on the host) on the SVD workloads:
+    - the whole 256 x 256 real SVD with the step's loops over pairs on every
+      host thread, and one sweep of it on one thread;
+    - two steps each of the real 8192 x 2048 and complex 4096 x 4096
+      workloads on one thread, extrapolated to one sweep (K steps) and to the
+      whole SVD with the GPU run's sweep count (the oracle's iteration is the
+      same, bit for bit);
+    - a sample of the batched workload (every k-th matrix in the order of n),
+      one oracle SVD per host thread at a time, extrapolated to the whole
+      batch by the ratio of its algorithmic bytes (16 n (m + n) per step over
+      the sweeps the GPU run took) to the sample's."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
-    res = {}
+    nth = oracle.omp_max_threads()
+    res = dict(kind="oracle", threads=nth, **host_cpu())
     A, _ = inputs.plain_real_256()
+    oracle.set_step_threads(nth)
+    try:
+        t0 = time.perf_counter()
+        r = oracle.gesvj(A)
+        res["svd_real256_s"] = round(time.perf_counter() - t0, 3)
+        res["svd_real256_sweeps"] = r["sweeps"]
+    finally:
+        oracle.set_step_threads(1)
     st = oracle.State(A)
     st.init()
     t0 = time.perf_counter()
     for _ in range(oracle.rr_steps(256)):
         st.step()
     sw = time.perf_counter() - t0
-    res["svd_real256_sweep_s"] = round(sw, 3)
+    res["svd_real256_sweep_1thread_s"] = round(sw, 3)
     if sweeps_256:
-        res["svd_real256_s_extrapolated"] = round(sw * sweeps_256, 2)
+        res["svd_real256_1thread_s_extrapolated"] = round(sw * sweeps_256, 2)
     for (m, n, c) in ((8192, 2048, False), (4096, 4096, True)):
         g = inputs.rng(inputs.CFG_PLAIN_LARGE, 77 + int(c))
         Ar, Ai = inputs.random_columns(m, n, g, c)
@@ -565,13 +721,28 @@ def cpu_oracle_svd(inputs, sweeps_256=None, sweeps_large=None):
             st.step()
         dt = (time.perf_counter() - t0) / 2
         K = n - 1 if n % 2 == 0 else n
-        res[f"step_{'c' if c else 'r'}{m}x{n}_s"] = round(dt, 4)
         tg = f"{'c' if c else 'r'}{m}x{n}"
-        res[f"sweep_{tg}_s_extrapolated"] = round(dt * K, 1)
+        res[f"step_{tg}_1thread_s"] = round(dt, 4)
+        res[f"sweep_{tg}_1thread_s_extrapolated"] = round(dt * K, 1)
         if sweeps_large and sweeps_large.get(tg):
-            res[f"svd_{tg}_h_extrapolated"] = round(dt * K * sweeps_large[tg] / 3600.0, 1)
-    res["cores"] = 1
-    res["kind"] = "oracle"
+            res[f"svd_{tg}_1thread_h_extrapolated"] = round(dt * K * sweeps_large[tg] / 3600.0, 1)
+    cost = _batched_cache.get("bytes_upper_0")
+    if cost is not None and c4_sample > 0:
+        count = len(cost)
+        mm, nn, _ = inputs.batched_shapes(10000)
+        mats, _ = batched_inputs(inputs, count)
+        by_n = np.argsort(nn[:count], kind="stable")
+        k = max(1, count // c4_sample)
+        sample = [int(i) for i in by_n[k // 2::k][:c4_sample]]
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(nth) as ex:
+            outs = list(ex.map(lambda i: oracle.gesvj(mats[i])["status"], sample))
+        dt = time.perf_counter() - t0
+        factor = float(cost.sum() / cost[sample].sum())
+        res["batched_sample"] = dict(matrices=len(sample), every=k, all_converged=all(o == 0 for o in outs),
+                                     wall_s=round(dt, 2), threads=nth, extrapolation_factor=round(factor, 2),
+                                     whole_batch_s_extrapolated=round(dt * factor, 1),
+                                     svds_per_s_extrapolated=round(count / (dt * factor), 2))
     return res
 
 
@@ -586,11 +757,17 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched", type=int, default=10000, help="matrices of the batched workload (at most 10000)")
-    ap.add_argument("--batched-plain", type=int, default=25)
+    ap.add_argument("--batched-plain", type=int, default=200,
+                    help="matrices of the plain-path sample, stratified by n")
+    ap.add_argument("--oracle-batched-sample", type=int, default=96,
+                    help="matrices of the batched workload the CPU oracle solves (stratified by n)")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
-    ap.add_argument("--serve-pool", type=int, default=16)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
+    ap.add_argument("--serve-pool", type=int, default=64)
+    ap.add_argument("--serve-sustained-rate", type=float, default=3.0,
+                    help="a second serving line at this rate with no queue limit (0: skip)")
+    ap.add_argument("--serve-sustained-seconds", type=float, default=30.0)
     ap.add_argument("--serve-max-large", type=int, default=0,
                     help="large requests on the device at once (0: the library's default)")
     ap.add_argument("--calib-copy", type=int, default=0,
@@ -657,6 +834,8 @@ def main():
     ach_r = EVD_BYTES_REAL * r / dur[False] / 1e9
     log(f"[bench] EVD: {value:.4g} EVD/s, {ms_per_step:.3f} ms/step; complex kernel {dur[True]*1e3:.3f} ms "
         f"({ach_c:.0f} GB/s), real kernel {dur[False]*1e3:.3f} ms ({ach_r:.0f} GB/s)")
+    ceil = evd_ceiling(torch, J, dev, r, K)
+    log(f"[bench] EVD ceiling: {ceil}")
     tr_c, tr_r = (measured_traffic("complex"), measured_traffic("real")) if r == 1 << 26 else (None, None)
     roofline = dict(bound="hbm", kernel=evd_kernel_name(r, True), achieved=round(ach_c, 1),
                     peak=HBM_PEAK_GBS, unit="GB/s", frac=round(ach_c / HBM_PEAK_GBS, 4),
@@ -666,7 +845,9 @@ def main():
                                      frac=round(ach_r / HBM_PEAK_GBS, 4),
                                      traffic=None if tr_r is None else round(tr_r / 1e9, 4),
                                      bytes_per_launch=EVD_BYTES_REAL * r,
-                                     avg_launch_ms=round(dur[False] * 1e3, 4)))
+                                     avg_launch_ms=round(dur[False] * 1e3, 4)),
+                    ceiling=dict(ceil, frac_of_stream_ceiling=round(ach_c / ceil["stream_complex"]["GBs"], 4),
+                                 note="the same streams moved without arithmetic, and a plain copy"))
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -685,7 +866,7 @@ def main():
         cpu = dict(value=round(2 * ns * passes / ct, 1), unit="EVD/s", cores=nth, kind="oracle",
                    sample=f"{passes} passes over the first 2^{ns.bit_length() - 1} real + "
                           f"2^{ns.bit_length() - 1} complex matrices of the workload, OpenMP over matrices, "
-                          f"{ct:.1f} s")
+                          f"{ct:.1f} s", **host_cpu())
         log(f"[bench] cpu oracle: {cpu['value']:.4g} EVD/s on {nth} threads ({ct:.1f} s)")
     del dev
     torch.cuda.empty_cache()
@@ -727,10 +908,15 @@ def main():
             tasks.append(("serving", lambda: serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
                                                          args.serve_pool, 0,
                                                          max_large=args.serve_max_large)))
+            if args.serve_sustained_rate > 0:
+                tasks.append(("serving_sustained", lambda: serving_run(
+                    torch, J, inputs, args.serve_sustained_rate, args.serve_sustained_seconds, args.serve_pool, 0,
+                    max_queue=0, max_large=args.serve_max_large)))
         if not args.no_cpu:
             tasks.append(("cpu_oracle_svd", lambda: cpu_oracle_svd(
                 inputs, extra.get("svd_real256", {}).get("sweeps"),
-                {tg: extra.get(f"svd_{tg}", {}).get("sweeps") for tg in ("r8192x2048", "c4096x4096")})))
+                {tg: extra.get(f"svd_{tg}", {}).get("sweeps") for tg in ("r8192x2048", "c4096x4096")},
+                c4_sample=args.oracle_batched_sample)))
         for nm, fn in tasks:
             if prefixes and not any(nm.startswith(x) for x in prefixes):
                 continue

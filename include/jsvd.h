@@ -102,6 +102,18 @@ int jsvd_evd2_batched(size_t r, const double *a11, const double *a22,
                       double *lambda1, double *lambda2, int32_t *zp,
                       unsigned flags, void *stream);
 
+/* Measurement aid: moves exactly the bytes jsvd_evd2_batched moves for a
+ * batch of r (the same input streams read, the same output streams written,
+ * the same launch shape and access hints as its kernel for batches of 2^22
+ * and more) without its arithmetic: every output is a copy of an input.  Its
+ * throughput is the memory-system ceiling of the batched EVD on the device.
+ * All pointers as for jsvd_evd2_batched, but lambda1, lambda2 and zp are
+ * required; the outputs carry no meaning.  Async on `stream`. */
+int jsvd_evd2_stream_ceiling(size_t r, const double *a11, const double *a22,
+                             const double *a21_re, const double *a21_im,
+                             double *cos_phi, double *ctan_re, double *ctan_im,
+                             double *lambda1, double *lambda2, int32_t *zp, void *stream);
+
 /* Single precision variant (Sect. 2.4.1: nu = FLT_MAX, fl(sqrt nu) =
  * 1.844674297E+19, FLT_TRUE_MIN, eta = FLT_MAX_EXP - 4): the same interface
  * on float arrays.  Results are bit-for-bit those of the serial algorithm
@@ -307,14 +319,18 @@ int jsvd_gesvj_f32(int m, int n, float *G_re, float *G_im, size_t ldg,
  * Arrays of `count` host pointers / sizes describe the problems; every
  * matrix pointer is a device pointer.  Matrix i follows jsvd_gesvj exactly
  * (same results, bit for bit, whatever the launch shape).  status[i] and
- * sweeps[i] (host arrays) receive the per-matrix outcome.  Matrices of more
- * than 512 rows or columns take the plain path one by one.  Synchronises.
+ * sweeps[i] (host arrays; sweeps may be NULL) receive the per-matrix
+ * outcome; transformations[i] (host array, may be NULL) the number of pairs
+ * transformed over the whole iteration, -1 for a matrix that took the plain
+ * path.  Matrices of more than 512 rows or columns take the plain path one
+ * by one.  Synchronises.
  * ---------------------------------------------------------------------- */
 int jsvd_gesvj_batched(int count, const int *m, const int *n, const int *is_complex,
                        double *const *G_re, double *const *G_im, const size_t *ldg,
                        double *const *V_re, double *const *V_im, const size_t *ldv,
                        double *const *sv_e, double *const *sv_f,
-                       int max_sweeps, int *sweeps, int *status, unsigned flags, void *stream);
+                       int max_sweeps, int *sweeps, int *status, int64_t *transformations,
+                       unsigned flags, void *stream);
 
 /* Launch shape of the batched SVD: the threads per matrix (one wavefront per
  * pivot pair at a time) of each class are chosen by measurement, once per
@@ -381,6 +397,7 @@ typedef struct {
     double svds_per_s;           /* completions per second since creation */
     int queue_depth, active;
     size_t hbm_in_use;
+    double p50_service_ns, p99_service_ns; /* admission-to-completion */
 } jsvd_serve_stats;
 
 int jsvd_serve_create(const jsvd_serve_config *cfg, jsvd_server *out);
@@ -389,7 +406,13 @@ int jsvd_serve_submit(jsvd_server sv, const jsvd_request *req, uint64_t *ticket)
 /* *done = 1 once finished; *status is its jsvd_gesvj status, *sweeps its C. */
 int jsvd_serve_poll(jsvd_server sv, uint64_t ticket, int *done, int *status, int *sweeps);
 int jsvd_serve_wait(jsvd_server sv, uint64_t ticket, int *status, int *sweeps);
+/* Counters, rates and latency percentiles since creation (the name differs
+ * from the struct's, which C does not allow to share it).  Takes a copy of
+ * every recorded latency: O(completed) per call. */
 int jsvd_serve_stats_get(jsvd_server sv, jsvd_serve_stats *out);
+/* The server's load now, without the percentiles: cheap enough to call
+ * before every submission.  Each output pointer may be NULL. */
+int jsvd_serve_load(jsvd_server sv, int *queue_depth, int *active, size_t *hbm_in_use);
 /* Waits for every admitted request, then frees the server. */
 int jsvd_serve_destroy(jsvd_server sv);
 

@@ -53,6 +53,8 @@ def lib():
         L.ora_sevd2_batch.restype = None
         L.ora_sevd2_batch.argtypes = [sz, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _fp, _ip, _ct.c_uint, i]
         L.ora_omp_max_threads.restype = i
+        L.ora_set_step_threads.restype = None
+        L.ora_set_step_threads.argtypes = [i]
         L.ora_hypot.restype = d
         L.ora_hypot.argtypes = [d, d]
         L.ora_getexp.restype = i
@@ -208,6 +210,12 @@ def sevd2_batch(a11, a22, a21r, a21i=None, flags=0, nthreads=0):
 
 def omp_max_threads():
     return lib().ora_omp_max_threads()
+
+
+def set_step_threads(nthreads):
+    """Threads of the oracle step's loops over pairs (1: sequential, the
+    default; results do not depend on it)."""
+    lib().ora_set_step_threads(int(nthreads))
 
 
 # ---------------------------------------------------------------- helpers

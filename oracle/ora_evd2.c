@@ -4,16 +4,21 @@
  *
  * TEST INFRASTRUCTURE ONLY (see oracle.h).
  *
- * The complex routine follows the serial algorithm of Sect. 2.3.1 (Listing 1)
- * of arXiv:2202.08361 step by step: the scaling exponent of eq. (z) with
- * eta' = DBL_MAX_EXP - 3, the exact power-of-two scaling, the polar form of
- * eq. (zpolar) with the naive hypot of eq. (hypot), the clamped tan(2 phi) of
- * eq. (tan2), tan(phi) of eq. (jactan), the secant form of eq. (jacsec) and
- * the eigenvalues of eq. (lamsec).  The real routine is the specialisation
- * of Alg. d8jac2 (Sect. SM2.1): e^{i alpha} = sign(a21).
+ * Written from the equations of Sect. 2 of arXiv:2202.08361, each in a
+ * routine of its own:
+ *   eq. (z)                     the scaling exponent zeta = min_c (eta -
+ *                               floor(lg|c|)), eta = floor(lg(nu/8)),
+ *                               lg 0 read as lg of the smallest subnormal;
+ *   eqs. (hypot), (zpolar)      |a21'| and e^{i alpha} = cos + i sin;
+ *   eqs. (tan2), (jactan),      tan(2 phi) clamped by fl(sqrt(nu)), tan(phi),
+ *   (jacsec)                    sec^2, sec and cos(phi);
+ *   eq. (lamsec)                the eigenvalues of A' = 2^zeta A.
+ * The real case takes e^{i alpha} = sign(a21) = +-1 (eq. alpha, with
+ * sign(+-0) = +-1).
  *
  * Build with -ffp-contract=off: every operation below is one IEEE-754
- * double operation, rounded to nearest-even, fma() written out explicitly.
+ * double operation, rounded to nearest-even, fma() written out where an
+ * equation has one.
  */
 #include <float.h>
 #include <math.h>
@@ -24,123 +29,121 @@
 #endif
 #include "oracle.h"
 
-/* fl(sqrt(nu)), the clamp of tan(2 phi) in eq. (tan2) */
+/* fl(sqrt(nu)) for nu = DBL_MAX: the bound on |tan(2 phi)| of eq. (tan2) */
 static const double ORA_SQRT_NU = 1.34078079299425956E+154;
 
-/* zeta_c = eta' - (exponent of |c|, zero treated as the smallest subnormal),
- * with eta' = DBL_MAX_EXP - 3 = 1021 and frexp's exponent being
- * floor(lg|c|) + 1. */
-static int zeta_of(double c)
+/* eq. (z) for one component c: eta - floor(lg|c|) with eta = floor(lg(nu/8))
+ * = DBL_MAX_EXP - 4; frexp returns floor(lg|c|) + 1 and nothing useful for
+ * zero, so zero is replaced by the smallest subnormal */
+static int ora_zeta_part(double c)
 {
-    int ex;
-    (void)frexp(fmax(fabs(c), DBL_TRUE_MIN), &ex);
-    return (DBL_MAX_EXP - 3) - ex;
+    int e;
+    (void)frexp(fmax(fabs(c), DBL_TRUE_MIN), &e);
+    return (DBL_MAX_EXP - 4) - (e - 1);
 }
 
-static double flip_sign_by(double x, double s)
+/* eq. (z): the minimum over the k components */
+static int ora_zeta(const double *comp, int k)
 {
-    /* x with its sign bit XOR-ed with the sign bit of s */
-    uint64_t ux, us;
-    memcpy(&ux, &x, 8);
-    memcpy(&us, &s, 8);
-    ux ^= (us & 0x8000000000000000ull);
-    memcpy(&x, &ux, 8);
-    return x;
+    int z = ora_zeta_part(comp[0]);
+    for (int i = 1; i < k; ++i) {
+        const int zi = ora_zeta_part(comp[i]);
+        if (zi < z) z = zi;
+    }
+    return z;
+}
+
+/* eqs. (hypot), (zpolar): x + iy = r (cos + i sin).  r is the naive hypot
+ * M sqrt(q^2 + 1) with q = m/M (0/0 read as 0); the cosine is clamped to 1
+ * and takes the sign of x; the sine divides by r, kept from zero by the
+ * smallest subnormal. */
+static void ora_polar(double x, double y, double *r, double *cosv, double *sinv)
+{
+    const double m = fmin(fabs(x), fabs(y));
+    const double M = fmax(fabs(x), fabs(y));
+    const double q = fmax(m / M, 0.0);
+    *r = sqrt(fma(q, q, 1.0)) * M;
+    *cosv = copysign(fmin(fabs(x) / *r, 1.0), x);
+    *sinv = y / fmax(*r, DBL_TRUE_MIN);
+}
+
+/* eqs. (tan2), (jactan), (jacsec): the rotation from 2|a21'| and
+ * a = a11' - a22' */
+typedef struct {
+    double tan_phi, sec2_phi, sec_phi, cos_phi;
+} ora_jrot;
+
+static ora_jrot ora_rotation(double two_abs21, double a)
+{
+    ora_jrot g;
+    const double tan_2phi = copysign(fmin(fmax(two_abs21 / fabs(a), 0.0), ORA_SQRT_NU), a);
+    g.tan_phi = tan_2phi / (1.0 + sqrt(fma(tan_2phi, tan_2phi, 1.0)));
+    g.sec2_phi = fma(g.tan_phi, g.tan_phi, 1.0);
+    g.sec_phi = sqrt(g.sec2_phi);
+    g.cos_phi = 1.0 / g.sec_phi;
+    return g;
+}
+
+/* eq. (lamsec): ((y tan + o) tan + x) / sec^2.  lambda_1 takes
+ * (x, y, o) = (a11', a22', 2|a21'|) and lambda_2 (a22', a11', -2|a21'|). */
+static double ora_lamsec(double x, double y, double o, const ora_jrot *g)
+{
+    return fma(g->tan_phi, fma(y, g->tan_phi, o), x) / g->sec2_phi;
+}
+
+/* the outputs common to both cases; returns (zeta' << 1) | p */
+static int ora_finish(double a11s, double a22s, double two_abs21, const ora_jrot *g, int zeta,
+                      double *l1, double *l2, unsigned flags)
+{
+    const double lam1 = ora_lamsec(a11s, a22s, two_abs21, g);
+    const double lam2 = ora_lamsec(a22s, a11s, -two_abs21, g);
+    const int zeta_back = -zeta;
+    const int scaled = (flags & ORA_EVD_SCALED) != 0;
+    if (l1) *l1 = scaled ? lam1 : scalbn(lam1, zeta_back);
+    if (l2) *l2 = scaled ? lam2 : scalbn(lam2, zeta_back);
+    return (int)(((unsigned)zeta_back << 1) | (unsigned)(lam1 < lam2));
 }
 
 int ora_evd2_cplx(double a11, double a22, double a21r, double a21i,
                   double *cs, double *ctr, double *cti, double *l1, double *l2,
                   unsigned flags)
 {
-    /* scaling exponent: the minimum over the four components (eq. z) */
-    const int z11 = zeta_of(a11), z22 = zeta_of(a22);
-    const int zr = zeta_of(a21r), zi = zeta_of(a21i);
-    const int zR = (z11 <= z22) ? z11 : z22;
-    const int zC = (zr <= zi) ? zr : zi;
-    const int zeta = (zR <= zC) ? zR : zC;
-    const int zeta_b = -zeta;
-
-    /* A' = 2^zeta A, exact unless a component is pushed below the normal range */
-    const double br = scalbn(a21r, zeta), bi = scalbn(a21i, zeta);
-    const double b11 = scalbn(a11, zeta), b22 = scalbn(a22, zeta);
-
-    /* polar form |a21'| e^{i alpha} with the naive hypot */
-    const double abr = fabs(br), abi = fabs(bi);
-    const double am = fmin(abr, abi), aM = fmax(abr, abi);
-    const double mM = fmax(am / aM, 0.0);
-    const double ab = sqrt(fma(mM, mM, 1.0)) * aM;
-    const double ca = copysign(fmin(abr / ab, 1.0), br);
-    const double sa = bi / fmax(ab, DBL_TRUE_MIN);
-
-    /* the Jacobi rotation */
-    const double o = ab * 2.0;
-    const double a = b11 - b22;
-    const double t2 = copysign(fmin(fmax(o / fabs(a), 0.0), ORA_SQRT_NU), a);
-    const double t = t2 / (1.0 + sqrt(fma(t2, t2, 1.0)));
-    const double sec2 = fma(t, t, 1.0);
-    const double sec = sqrt(sec2);
-    const double c = 1.0 / sec;
-    double C = ca * t;
-    double S = sa * t;
+    const double comp[4] = {a11, a22, a21r, a21i};
+    const int zeta = ora_zeta(comp, 4);
+    /* A' = 2^zeta A */
+    const double a11s = scalbn(a11, zeta), a22s = scalbn(a22, zeta);
+    double r, cos_alpha, sin_alpha;
+    ora_polar(scalbn(a21r, zeta), scalbn(a21i, zeta), &r, &cos_alpha, &sin_alpha);
+    const double two_abs21 = r * 2.0;
+    const ora_jrot g = ora_rotation(two_abs21, a11s - a22s);
+    /* e^{i alpha} tan(phi), or e^{i alpha} sin(phi) = e^{i alpha} tan(phi) / sec(phi) */
+    double re = cos_alpha * g.tan_phi, im = sin_alpha * g.tan_phi;
     if (flags & ORA_EVD_SINFORM) {
-        C = C / sec;
-        S = S / sec;
+        re = re / g.sec_phi;
+        im = im / g.sec_phi;
     }
-
-    /* eigenvalues of A' */
-    const double lp1 = fma(t, fma(b22, t, o), b11) / sec2;
-    const double lp2 = fma(t, fma(b11, t, -o), b22) / sec2;
-
-    if (cs) *cs = c;
-    if (ctr) *ctr = C;
-    if (cti) *cti = S;
-    if (flags & ORA_EVD_SCALED) {
-        if (l1) *l1 = lp1;
-        if (l2) *l2 = lp2;
-    } else {
-        if (l1) *l1 = scalbn(lp1, zeta_b);
-        if (l2) *l2 = scalbn(lp2, zeta_b);
-    }
-    return (int)(((unsigned)zeta_b << 1) | (unsigned)(lp1 < lp2));
+    if (cs) *cs = g.cos_phi;
+    if (ctr) *ctr = re;
+    if (cti) *cti = im;
+    return ora_finish(a11s, a22s, two_abs21, &g, zeta, l1, l2, flags);
 }
 
 int ora_evd2_real(double a11, double a22, double a21,
                   double *cs, double *tn, double *l1, double *l2, unsigned flags)
 {
-    const int z11 = zeta_of(a11), z22 = zeta_of(a22), z21 = zeta_of(a21);
-    const int zR = (z11 <= z22) ? z11 : z22;
-    const int zeta = (zR <= z21) ? zR : z21;
-    const int zeta_b = -zeta;
-
-    const double b21 = scalbn(a21, zeta);
-    const double b11 = scalbn(a11, zeta), b22 = scalbn(a22, zeta);
-
-    const double ab = fabs(b21);
-    const double o = ab * 2.0;
-    const double a = b11 - b22;
-    const double t2 = copysign(fmin(fmax(o / fabs(a), 0.0), ORA_SQRT_NU), a);
-    const double t = t2 / (1.0 + sqrt(fma(t2, t2, 1.0)));
-    const double sec2 = fma(t, t, 1.0);
-    const double sec = sqrt(sec2);
-    const double c = 1.0 / sec;
-    /* e^{i alpha} tan(phi) = sign(a21) tan(phi): the sign bits multiply */
-    double T = flip_sign_by(t, b21);
+    const double comp[3] = {a11, a22, a21};
+    const int zeta = ora_zeta(comp, 3);
+    const double a11s = scalbn(a11, zeta), a22s = scalbn(a22, zeta);
+    const double a21s = scalbn(a21, zeta);
+    const double two_abs21 = fabs(a21s) * 2.0;
+    const ora_jrot g = ora_rotation(two_abs21, a11s - a22s);
+    /* e^{i alpha} = sign(a21) = +-1: multiplying by it is exact */
+    double v = g.tan_phi * copysign(1.0, a21s);
     if (flags & ORA_EVD_SINFORM)
-        T = T / sec;
-
-    const double lp1 = fma(t, fma(b22, t, o), b11) / sec2;
-    const double lp2 = fma(t, fma(b11, t, -o), b22) / sec2;
-
-    if (cs) *cs = c;
-    if (tn) *tn = T;
-    if (flags & ORA_EVD_SCALED) {
-        if (l1) *l1 = lp1;
-        if (l2) *l2 = lp2;
-    } else {
-        if (l1) *l1 = scalbn(lp1, zeta_b);
-        if (l2) *l2 = scalbn(lp2, zeta_b);
-    }
-    return (int)(((unsigned)zeta_b << 1) | (unsigned)(lp1 < lp2));
+        v = v / g.sec_phi;
+    if (cs) *cs = g.cos_phi;
+    if (tn) *tn = v;
+    return ora_finish(a11s, a22s, two_abs21, &g, zeta, l1, l2, flags);
 }
 
 void ora_evd2_batch(size_t r, const double *a11, const double *a22,

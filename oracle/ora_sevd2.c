@@ -7,12 +7,12 @@
  *
  * The paper converts its double precision routines to single precision by
  * redefining nu = FLT_MAX, fl(sqrt(nu)) = 1.844674297E+19, the smallest
- * subnormal FLT_TRUE_MIN and eta = FLT_MAX_EXP - 4 (Sect. 2.4.1), so
- * eta' = eta + 1 = FLT_MAX_EXP - 3 = 125 in the frexp form of Listing 1.
- * The steps are those of ora_evd2.c, every one of them a single precision
- * IEEE-754 operation rounded to nearest-even (build with -ffp-contract=off;
- * on x86-64 float arithmetic is evaluated in float, FLT_EVAL_METHOD = 0;
- * every constant below is a float constant so nothing is promoted).
+ * subnormal FLT_TRUE_MIN and eta = FLT_MAX_EXP - 4 (Sect. 2.4.1).  The
+ * equations are evaluated as in ora_evd2.c, every operation a single
+ * precision IEEE-754 operation rounded to nearest-even (build with
+ * -ffp-contract=off; on x86-64 float arithmetic is evaluated in float,
+ * FLT_EVAL_METHOD = 0; every constant below is a float constant so nothing
+ * is promoted).
  */
 #include <float.h>
 #include <math.h>
@@ -27,111 +27,111 @@
 #error "the single precision oracle needs float arithmetic evaluated in float"
 #endif
 
-/* fl(sqrt(FLT_MAX)) = 0x1.fffffep+63 */
+/* fl(sqrt(FLT_MAX)) = 0x1.fffffep+63, the bound on |tan(2 phi)| of eq. (tan2) */
 static const float ORA_SQRT_NU_F = 1.844674297E+19f;
 
-/* zeta_c = eta' - (frexp exponent of max(|c|, FLT_TRUE_MIN)), eta' = 125 */
-static int zeta_of_f(float c)
+/* eq. (z) for one component: eta - floor(lg|c|), eta = floor(lg(FLT_MAX/8))
+ * = FLT_MAX_EXP - 4, zero replaced by the smallest subnormal */
+static int ora_s_zeta_part(float c)
 {
-    int ex;
-    (void)frexpf(fmaxf(fabsf(c), FLT_TRUE_MIN), &ex);
-    return (FLT_MAX_EXP - 3) - ex;
+    int e;
+    (void)frexpf(fmaxf(fabsf(c), FLT_TRUE_MIN), &e);
+    return (FLT_MAX_EXP - 4) - (e - 1);
 }
 
-static float flip_sign_by_f(float x, float s)
+/* eq. (z): the minimum over the k components */
+static int ora_s_zeta(const float *comp, int k)
 {
-    uint32_t ux, us;
-    memcpy(&ux, &x, 4);
-    memcpy(&us, &s, 4);
-    ux ^= (us & 0x80000000u);
-    memcpy(&x, &ux, 4);
-    return x;
+    int z = ora_s_zeta_part(comp[0]);
+    for (int i = 1; i < k; ++i) {
+        const int zi = ora_s_zeta_part(comp[i]);
+        if (zi < z) z = zi;
+    }
+    return z;
+}
+
+/* eqs. (hypot), (zpolar) in single precision: x + iy = r (cos + i sin) */
+static void ora_s_polar(float x, float y, float *r, float *cosv, float *sinv)
+{
+    const float m = fminf(fabsf(x), fabsf(y));
+    const float M = fmaxf(fabsf(x), fabsf(y));
+    const float q = fmaxf(m / M, 0.0f);
+    *r = sqrtf(fmaf(q, q, 1.0f)) * M;
+    *cosv = copysignf(fminf(fabsf(x) / *r, 1.0f), x);
+    *sinv = y / fmaxf(*r, FLT_TRUE_MIN);
+}
+
+/* eqs. (tan2), (jactan), (jacsec) */
+typedef struct {
+    float tan_phi, sec2_phi, sec_phi, cos_phi;
+} ora_s_jrot;
+
+static ora_s_jrot ora_s_rotation(float two_abs21, float a)
+{
+    ora_s_jrot g;
+    const float tan_2phi = copysignf(fminf(fmaxf(two_abs21 / fabsf(a), 0.0f), ORA_SQRT_NU_F), a);
+    g.tan_phi = tan_2phi / (1.0f + sqrtf(fmaf(tan_2phi, tan_2phi, 1.0f)));
+    g.sec2_phi = fmaf(g.tan_phi, g.tan_phi, 1.0f);
+    g.sec_phi = sqrtf(g.sec2_phi);
+    g.cos_phi = 1.0f / g.sec_phi;
+    return g;
+}
+
+/* eq. (lamsec): ((y tan + o) tan + x) / sec^2 */
+static float ora_s_lamsec(float x, float y, float o, const ora_s_jrot *g)
+{
+    return fmaf(g->tan_phi, fmaf(y, g->tan_phi, o), x) / g->sec2_phi;
+}
+
+static int ora_s_finish(float a11s, float a22s, float two_abs21, const ora_s_jrot *g, int zeta,
+                        float *l1, float *l2, unsigned flags)
+{
+    const float lam1 = ora_s_lamsec(a11s, a22s, two_abs21, g);
+    const float lam2 = ora_s_lamsec(a22s, a11s, -two_abs21, g);
+    const int zeta_back = -zeta;
+    const int scaled = (flags & ORA_EVD_SCALED) != 0;
+    if (l1) *l1 = scaled ? lam1 : scalbnf(lam1, zeta_back);
+    if (l2) *l2 = scaled ? lam2 : scalbnf(lam2, zeta_back);
+    return (int)(((unsigned)zeta_back << 1) | (unsigned)(lam1 < lam2));
 }
 
 int ora_sevd2_cplx(float a11, float a22, float a21r, float a21i,
                    float *cs, float *ctr, float *cti, float *l1, float *l2, unsigned flags)
 {
-    const int z11 = zeta_of_f(a11), z22 = zeta_of_f(a22);
-    const int zr = zeta_of_f(a21r), zi = zeta_of_f(a21i);
-    const int zR = (z11 <= z22) ? z11 : z22;
-    const int zC = (zr <= zi) ? zr : zi;
-    const int zeta = (zR <= zC) ? zR : zC;
-    const int zeta_b = -zeta;
-
-    const float br = scalbnf(a21r, zeta), bi = scalbnf(a21i, zeta);
-    const float b11 = scalbnf(a11, zeta), b22 = scalbnf(a22, zeta);
-
-    const float abr = fabsf(br), abi = fabsf(bi);
-    const float am = fminf(abr, abi), aM = fmaxf(abr, abi);
-    const float mM = fmaxf(am / aM, 0.0f);
-    const float ab = sqrtf(fmaf(mM, mM, 1.0f)) * aM;
-    const float ca = copysignf(fminf(abr / ab, 1.0f), br);
-    const float sa = bi / fmaxf(ab, FLT_TRUE_MIN);
-
-    const float o = ab * 2.0f;
-    const float a = b11 - b22;
-    const float t2 = copysignf(fminf(fmaxf(o / fabsf(a), 0.0f), ORA_SQRT_NU_F), a);
-    const float t = t2 / (1.0f + sqrtf(fmaf(t2, t2, 1.0f)));
-    const float sec2 = fmaf(t, t, 1.0f);
-    const float sec = sqrtf(sec2);
-    const float c = 1.0f / sec;
-    float C = ca * t;
-    float S = sa * t;
+    const float comp[4] = {a11, a22, a21r, a21i};
+    const int zeta = ora_s_zeta(comp, 4);
+    const float a11s = scalbnf(a11, zeta), a22s = scalbnf(a22, zeta);
+    float r, cos_alpha, sin_alpha;
+    ora_s_polar(scalbnf(a21r, zeta), scalbnf(a21i, zeta), &r, &cos_alpha, &sin_alpha);
+    const float two_abs21 = r * 2.0f;
+    const ora_s_jrot g = ora_s_rotation(two_abs21, a11s - a22s);
+    float re = cos_alpha * g.tan_phi, im = sin_alpha * g.tan_phi;
     if (flags & ORA_EVD_SINFORM) {
-        C = C / sec;
-        S = S / sec;
+        re = re / g.sec_phi;
+        im = im / g.sec_phi;
     }
-    const float lp1 = fmaf(t, fmaf(b22, t, o), b11) / sec2;
-    const float lp2 = fmaf(t, fmaf(b11, t, -o), b22) / sec2;
-
-    if (cs) *cs = c;
-    if (ctr) *ctr = C;
-    if (cti) *cti = S;
-    if (flags & ORA_EVD_SCALED) {
-        if (l1) *l1 = lp1;
-        if (l2) *l2 = lp2;
-    } else {
-        if (l1) *l1 = scalbnf(lp1, zeta_b);
-        if (l2) *l2 = scalbnf(lp2, zeta_b);
-    }
-    return (int)(((unsigned)zeta_b << 1) | (unsigned)(lp1 < lp2));
+    if (cs) *cs = g.cos_phi;
+    if (ctr) *ctr = re;
+    if (cti) *cti = im;
+    return ora_s_finish(a11s, a22s, two_abs21, &g, zeta, l1, l2, flags);
 }
 
 int ora_sevd2_real(float a11, float a22, float a21,
                    float *cs, float *tn, float *l1, float *l2, unsigned flags)
 {
-    const int z11 = zeta_of_f(a11), z22 = zeta_of_f(a22), z21 = zeta_of_f(a21);
-    const int zR = (z11 <= z22) ? z11 : z22;
-    const int zeta = (zR <= z21) ? zR : z21;
-    const int zeta_b = -zeta;
-
-    const float b21 = scalbnf(a21, zeta);
-    const float b11 = scalbnf(a11, zeta), b22 = scalbnf(a22, zeta);
-
-    const float ab = fabsf(b21);
-    const float o = ab * 2.0f;
-    const float a = b11 - b22;
-    const float t2 = copysignf(fminf(fmaxf(o / fabsf(a), 0.0f), ORA_SQRT_NU_F), a);
-    const float t = t2 / (1.0f + sqrtf(fmaf(t2, t2, 1.0f)));
-    const float sec2 = fmaf(t, t, 1.0f);
-    const float sec = sqrtf(sec2);
-    const float c = 1.0f / sec;
-    float T = flip_sign_by_f(t, b21);
+    const float comp[3] = {a11, a22, a21};
+    const int zeta = ora_s_zeta(comp, 3);
+    const float a11s = scalbnf(a11, zeta), a22s = scalbnf(a22, zeta);
+    const float a21s = scalbnf(a21, zeta);
+    const float two_abs21 = fabsf(a21s) * 2.0f;
+    const ora_s_jrot g = ora_s_rotation(two_abs21, a11s - a22s);
+    /* e^{i alpha} = sign(a21) = +-1 (eq. alpha): an exact product */
+    float v = g.tan_phi * copysignf(1.0f, a21s);
     if (flags & ORA_EVD_SINFORM)
-        T = T / sec;
-    const float lp1 = fmaf(t, fmaf(b22, t, o), b11) / sec2;
-    const float lp2 = fmaf(t, fmaf(b11, t, -o), b22) / sec2;
-
-    if (cs) *cs = c;
-    if (tn) *tn = T;
-    if (flags & ORA_EVD_SCALED) {
-        if (l1) *l1 = lp1;
-        if (l2) *l2 = lp2;
-    } else {
-        if (l1) *l1 = scalbnf(lp1, zeta_b);
-        if (l2) *l2 = scalbnf(lp2, zeta_b);
-    }
-    return (int)(((unsigned)zeta_b << 1) | (unsigned)(lp1 < lp2));
+        v = v / g.sec_phi;
+    if (cs) *cs = g.cos_phi;
+    if (tn) *tn = v;
+    return ora_s_finish(a11s, a22s, two_abs21, &g, zeta, l1, l2, flags);
 }
 
 void ora_sevd2_batch(size_t r, const float *a11, const float *a22,

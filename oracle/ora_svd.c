@@ -465,6 +465,14 @@ int ora_init(ora_svd *st)
     return ORA_OK;
 }
 
+/* Threads of ora_step's loops over the pairs of a step (1: sequential, the
+ * default).  The pairs of a step are disjoint and the step's counts and its
+ * max-norm are an integer sum and an exact max, so the result does not
+ * depend on the thread count. */
+static int g_step_threads = 1;
+
+void ora_set_step_threads(int nthreads) { g_step_threads = nthreads > 1 ? nthreads : 1; }
+
 void ora_step(ora_svd *st)
 {
     const int m = st->m, n = st->n, cplx = st->cplx;
@@ -485,6 +493,9 @@ void ora_step(ora_svd *st)
     }
 
     /* column norms of every column taking part in this step */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(g_step_threads) if (g_step_threads > 1)
+#endif
     for (int l = 0; l < npairs; ++l) {
         int p, q;
         if (!ora_rr_pair(n, kk, l, &p, &q)) continue;
@@ -496,6 +507,10 @@ void ora_step(ora_svd *st)
     const double ups = scalbn(sqrt((double)m), -53);
     long t = 0, sw = 0, gs = 0;
     double M = 0.0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(g_step_threads) if (g_step_threads > 1) \
+    reduction(+ : t, sw, gs) reduction(max : M)
+#endif
     for (int l = 0; l < npairs; ++l) {
         int p, q;
         if (!ora_rr_pair(n, kk, l, &p, &q)) continue;

@@ -186,6 +186,9 @@ void ora_finalize(ora_svd *st, double *sv_e, double *sv_f);
  * the number of sweeps before the one that found nothing to do.  A sweep
  * converges when it neither transformed nor swapped a pair: a swap moves
  * columns, so a sweep that swapped did not meet every column pair. */
+/* threads of the loops over a step's pairs (default 1); results do not
+ * depend on it */
+void ora_set_step_threads(int nthreads);
 int  ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
                double *Vr, double *Vi, size_t ldv,
                double *sv_e, double *sv_f, int max_sweeps, int *sweeps, long *steps,

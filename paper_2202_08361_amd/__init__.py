@@ -71,7 +71,8 @@ class ServeStats(_ct.Structure):
     _fields_ = [("submitted", _ct.c_uint64), ("completed", _ct.c_uint64), ("rejected", _ct.c_uint64),
                 ("p50_ns", _ct.c_double), ("p99_ns", _ct.c_double), ("p50_queue_ns", _ct.c_double),
                 ("p99_queue_ns", _ct.c_double), ("svds_per_s", _ct.c_double),
-                ("queue_depth", _ct.c_int), ("active", _ct.c_int), ("hbm_in_use", _ct.c_size_t)]
+                ("queue_depth", _ct.c_int), ("active", _ct.c_int), ("hbm_in_use", _ct.c_size_t),
+                ("p50_service_ns", _ct.c_double), ("p99_service_ns", _ct.c_double)]
 
 
 def lib():
@@ -90,6 +91,8 @@ def lib():
         L.jsvd_evd2_batched.argtypes = [sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u, vp]
         L.jsvd_evd2_batched_f32.restype = i
         L.jsvd_evd2_batched_f32.argtypes = [sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, u, vp]
+        L.jsvd_evd2_stream_ceiling.restype = i
+        L.jsvd_evd2_stream_ceiling.argtypes = [sz, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.jsvd_state_create.restype = i
         L.jsvd_state_create.argtypes = [i, i, i, _ct.POINTER(vp)]
         L.jsvd_state_create_f32.restype = i
@@ -133,7 +136,7 @@ def lib():
         L.jsvd_gesvj.restype = i
         L.jsvd_gesvj.argtypes = [i, i, vp, vp, sz, vp, vp, sz, vp, vp, vp, i, _ct.POINTER(i), u, vp]
         L.jsvd_gesvj_batched.restype = i
-        L.jsvd_gesvj_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, u, vp]
+        L.jsvd_gesvj_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, vp, u, vp]
         L.jsvd_batched_tune.restype = i
         L.jsvd_batched_tune.argtypes = [i, vp, vp, vp, u, vp]
         L.jsvd_batched_set_launch.restype = i
@@ -150,6 +153,8 @@ def lib():
         L.jsvd_serve_wait.argtypes = [vp, _ct.c_uint64, _ct.POINTER(i), _ct.POINTER(i)]
         L.jsvd_serve_stats_get.restype = i
         L.jsvd_serve_stats_get.argtypes = [vp, _ct.POINTER(ServeStats)]
+        L.jsvd_serve_load.restype = i
+        L.jsvd_serve_load.argtypes = [vp, _ct.POINTER(i), _ct.POINTER(i), _ct.POINTER(sz)]
         L.jsvd_serve_destroy.restype = i
         L.jsvd_serve_destroy.argtypes = [vp]
         L.jsvd_split.restype = i
@@ -252,6 +257,17 @@ def evd2_batched(a11, a22, a21_re, a21_im=None, flags=0, out=None, with_lambda=T
                                  _ptr(out.get("lambda2")), _ptr(out.get("zp")), flags, _stream(stream))
     _check(st, "jsvd_evd2_batched")
     return out
+
+
+def evd2_stream_ceiling(a11, a22, a21_re, a21_im, out, stream=None):
+    """jsvd_evd2_stream_ceiling: the batched EVD's streams moved without its
+    arithmetic, into the output tensors of an evd2_batched call (with lambda
+    and zp).  A measurement aid; the outputs carry no meaning."""
+    r = a11.numel()
+    _check(lib().jsvd_evd2_stream_ceiling(r, _ptr(a11), _ptr(a22), _ptr(a21_re), _ptr(a21_im), _ptr(out["cos"]),
+                                          _ptr(out["ctan_re"]), _ptr(out.get("ctan_im")), _ptr(out["lambda1"]),
+                                          _ptr(out["lambda2"]), _ptr(out["zp"]), _stream(stream)),
+           "jsvd_evd2_stream_ceiling")
 
 
 def dot_scaled_batched(Q_re, P_re, eq, fq, ep, fp, Q_im=None, P_im=None, flags=0, stream=None):
@@ -466,13 +482,14 @@ def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None):
         se[idx], sf[idx] = e.data_ptr(), f.data_ptr()
         lg[idx], lv[idx] = ld, n
         res.append(dict(U_re=Gr, U_im=Gi, V_re=Vr, V_im=Vi, sv_e=e, sv_f=f))
-    sweeps, status = I(), I()
+    sweeps, status, trans = I(), I(), (_ct.c_int64 * cnt)()
     st = lib().jsvd_gesvj_batched(cnt, m_a, n_a, c_a, gr, gi, lg, vr, vi, lv, se, sf, max_sweeps, sweeps, status,
-                                  flags, _stream(stream))
+                                  trans, flags, _stream(stream))
     _check(st, "jsvd_gesvj_batched", allow=(OK, NOT_CONVERGED, ENONFINITE, EZERO))
     for idx in range(cnt):
         res[idx]["status"] = status[idx]
         res[idx]["sweeps"] = sweeps[idx]
+        res[idx]["transformations"] = trans[idx]
     return res
 
 
@@ -551,6 +568,13 @@ class Server:
         st = ServeStats()
         _check(lib().jsvd_serve_stats_get(self._h, _ct.byref(st)), "jsvd_serve_stats_get")
         return {f: getattr(st, f) for f, _ in ServeStats._fields_}
+
+    def load(self):
+        """(queue_depth, active, hbm_in_use) now, without the latency
+        percentiles of stats() (jsvd_serve_load)."""
+        q, a, h = _ct.c_int(), _ct.c_int(), _ct.c_size_t()
+        _check(lib().jsvd_serve_load(self._h, _ct.byref(q), _ct.byref(a), _ct.byref(h)), "jsvd_serve_load")
+        return q.value, a.value, h.value
 
     def close(self):
         if getattr(self, "_h", None):

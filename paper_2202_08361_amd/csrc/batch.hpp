@@ -17,6 +17,7 @@ struct BatchItem {
     int lgbound;
     double ups;
     int status, sweeps;
+    long long transformations;   // pairs transformed over the whole iteration
 };
 
 // rows-per-lane class of the batched kernel for an m x n matrix (0: too large)
@@ -40,8 +41,11 @@ struct BatchLaunch;
 // default shape.
 BatchLaunch *batch_launch(const BatchItem *items, int count, int max_sweeps, unsigned flags, hipStream_t s,
                           bool tune = true);
-// The outcomes (valid once the stream has passed the launch), then release.
+// The outcomes (valid once the stream has passed the launch); batch_done
+// hands the launch's class streams back for other launches once the stream
+// has passed it; release (which also does that) frees the rest.
 const BatchItem *batch_results(const BatchLaunch *bl);
+void batch_done(BatchLaunch *bl);
 void batch_release(BatchLaunch *bl);
 
 } // namespace jsvd

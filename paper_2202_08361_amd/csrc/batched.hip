@@ -153,6 +153,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
         if (tid == 0) {
             it.status = (M0 == 0.0) ? JSVD_EZERO : JSVD_ENONFINITE;
             it.sweeps = 0;
+            it.transformations = 0;
         }
         return;
     }
@@ -173,7 +174,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
     const int N = n + (n & 1), K = N - 1, npairs = N / 2;
     int C = 0;
     bool converged = false;
-    long long k = 0;
+    long long k = 0, Tall = 0;
     for (;;) {
         long long T = 0, SW = 0;
         for (int kk = 0; kk < K; ++kk, ++k) {
@@ -302,6 +303,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
             T += (long long)ts;
             SW += (long long)sws;
         }
+        Tall += T;
         if (T == 0 && SW == 0) {
             converged = true;
             break;
@@ -328,6 +330,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
         if (tid == 0) {
             it.status = JSVD_NOT_CONVERGED;
             it.sweeps = C;
+            it.transformations = Tall;
         }
         return;
     }
@@ -420,6 +423,7 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
     if (tid == 0) {
         it.status = JSVD_OK;
         it.sweeps = C;
+        it.transformations = Tall;
     }
 }
 
@@ -440,6 +444,7 @@ __global__ __launch_bounds__(NT) void batched_kernel(BatchItem *items, const int
         if (threadIdx.x == 0) {
             items[order[idx]].status = it.status;
             items[order[idx]].sweeps = it.sweeps;
+            items[order[idx]].transformations = it.transformations;
         }
         __syncthreads();
     }
@@ -687,28 +692,50 @@ struct BatchLaunch {
     void *dmem;
     BatchItem *host;   // pinned; results land here
     int count;
+    int dev;
+    int nside;         // class streams checked out of the pool for this launch
+    hipStream_t side[8];
 };
 
-// Streams of the classes (created once per device, default priority): the
-// classes of a batch run side by side, forked from the caller's stream and
-// joined back into it, so that one class's longest matrices overlap the
-// others' instead of adding up.
+// Streams of the classes (default priority): the classes of a batch run side
+// by side, forked from the caller's stream and joined back into it, so that
+// one class's longest matrices overlap the others' instead of adding up.
+// Each launch checks its side streams out of a per-device pool and returns
+// them once it has completed, so launches in flight at the same time (two
+// callers, or two group slots of a server) never queue one's classes behind
+// the other's persistent kernels on a shared stream.
 static std::mutex g_stream_mu;
-static hipStream_t g_class_streams[kMaxDev][8];
+static std::vector<hipStream_t> g_stream_pool[kMaxDev];
 
-static bool class_streams(int dev, hipStream_t *out)
+static bool take_streams(int dev, int k, hipStream_t *out)
 {
     if (dev < 0 || dev >= kMaxDev) return false;
     std::lock_guard<std::mutex> lk(g_stream_mu);
-    for (int k = 0; k < 8; ++k) {
-        if (!g_class_streams[dev][k] &&
-            hipStreamCreateWithFlags(&g_class_streams[dev][k], hipStreamNonBlocking) != hipSuccess) {
-            g_class_streams[dev][k] = nullptr;
+    std::vector<hipStream_t> &pool = g_stream_pool[dev];
+    int got = 0;
+    while (got < k && !pool.empty()) {
+        out[got++] = pool.back();
+        pool.pop_back();
+    }
+    while (got < k) {
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            for (int i = 0; i < got; ++i) pool.push_back(out[i]);
             return false;
         }
-        out[k] = g_class_streams[dev][k];
+        out[got++] = st;
     }
     return true;
+}
+
+// the launch has completed (its side streams were joined into the caller's
+// stream, which has passed the join): its streams go back to the pool
+void batch_done(BatchLaunch *bl)
+{
+    if (!bl || bl->nside == 0) return;
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    for (int i = 0; i < bl->nside; ++i) g_stream_pool[bl->dev].push_back(bl->side[i]);
+    bl->nside = 0;
 }
 
 BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsigned flags, hipStream_t s, bool tune)
@@ -721,6 +748,8 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     bl->count = cnt;
     bl->dmem = nullptr;
     bl->host = nullptr;
+    bl->dev = 0;
+    bl->nside = 0;
     // per class, longest first: cost ~ c n^2 (m + n) per sweep
     auto cost = [&](int i) {
         return (items[i].cplx ? 2.0 : 1.0) * items[i].n * (double)items[i].n * (items[i].m + items[i].n);
@@ -773,9 +802,11 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     // the first class on the caller's stream, the others side by side on
     // class streams forked from it (one stream fewer to share the process's
     // hardware queues)
-    hipStream_t cs[8];
+    hipStream_t *cs = bl->side;
     hipEvent_t fork = nullptr, join[8] = {};
-    const bool side = ncls > 1 && class_streams(dev, cs);
+    bl->dev = dev;
+    const bool side = ncls > 1 && take_streams(dev, ncls - 1, cs);
+    if (side) bl->nside = ncls - 1;
     if (side) {
         ok = ok && hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess &&
              hipEventRecord(fork, s) == hipSuccess;
@@ -803,8 +834,7 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     if (!ok) {
         // nothing may still use the buffers when they are freed
         (void)hipStreamSynchronize(s);
-        if (side)
-            for (int c = 0; c < ncls; ++c) (void)hipStreamSynchronize(cs[c]);
+        for (int c = 0; c < bl->nside; ++c) (void)hipStreamSynchronize(cs[c]);
         batch_release(bl);
         return nullptr;
     }
@@ -816,6 +846,7 @@ const BatchItem *batch_results(const BatchLaunch *bl) { return bl->host; }
 void batch_release(BatchLaunch *bl)
 {
     if (!bl) return;
+    batch_done(bl);
     if (bl->dmem) (void)hipFree(bl->dmem);
     if (bl->host) (void)hipHostFree(bl->host);
     delete bl;
@@ -854,7 +885,7 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
                                   double *const *G_re, double *const *G_im, const size_t *ldg,
                                   double *const *V_re, double *const *V_im, const size_t *ldv,
                                   double *const *sv_e, double *const *sv_f, int max_sweeps, int *sweeps,
-                                  int *status, unsigned flags, void *stream)
+                                  int *status, int64_t *transformations, unsigned flags, void *stream)
 {
     if (count < 0) return JSVD_EINVAL;
     if (count == 0) return JSVD_OK;
@@ -896,6 +927,7 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
             const BatchItem &it = res[item_of[i]];
             status[i] = it.status;
             if (sweeps) sweeps[i] = it.sweeps;
+            if (transformations) transformations[i] = it.transformations;
             if (it.status < 0 && rc_all == JSVD_OK) rc_all = it.status;
         }
         batch_release(bl);
@@ -909,6 +941,7 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
                                   flags, stream);
         status[i] = rc;
         if (sweeps) sweeps[i] = sw;
+        if (transformations) transformations[i] = -1;   // not counted on the plain path
         if (rc < 0 && rc_all == JSVD_OK) rc_all = rc;
     }
     return rc_all;

@@ -93,6 +93,20 @@ extern "C" int jsvd_evd2_batched(size_t r, const double *a11, const double *a22,
     return JSVD_OK;
 }
 
+extern "C" int jsvd_evd2_stream_ceiling(size_t r, const double *a11, const double *a22, const double *a21_re,
+                                        const double *a21_im, double *cos_phi, double *ctan_re, double *ctan_im,
+                                        double *lambda1, double *lambda2, int32_t *zp, void *stream)
+{
+    if (r == 0) return JSVD_OK;
+    if (!a11 || !a22 || !a21_re || !cos_phi || !ctan_re || !lambda1 || !lambda2 || !zp) return JSVD_EINVAL;
+    if ((a21_im == nullptr) != (ctan_im == nullptr)) return JSVD_EINVAL;
+    if (r > (size_t)1 << 40) return JSVD_EINVAL;
+    if (launch_evd2_stream(r, a11, a22, a21_re, a21_im, cos_phi, ctan_re, ctan_im, lambda1, lambda2, zp,
+                           (hipStream_t)stream) != hipSuccess)
+        return JSVD_EDEVICE;
+    return JSVD_OK;
+}
+
 extern "C" int jsvd_evd2_batched_f32(size_t r, const float *a11, const float *a22, const float *a21_re,
                                      const float *a21_im, float *cos_phi, float *ctan_re, float *ctan_im,
                                      float *lambda1, float *lambda2, int32_t *zp, unsigned flags, void *stream)

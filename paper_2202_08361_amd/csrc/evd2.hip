@@ -44,11 +44,11 @@ __device__ __forceinline__ void evd2_one(const Evd2Args &A, size_t i)
     __builtin_nontemporal_store(o.c, A.cs + i);
     __builtin_nontemporal_store(o.C, A.cr + i);
     if (CPLX) __builtin_nontemporal_store(o.S, A.ci + i);
-    const double L1 = SCALED ? o.l1 : scal2(o.l1, o.zeta_b);
-    const double L2 = SCALED ? o.l2 : scal2(o.l2, o.zeta_b);
+    const double L1 = SCALED ? o.l1 : scal2(o.l1, o.unscale);
+    const double L2 = SCALED ? o.l2 : scal2(o.l2, o.unscale);
     if (A.l1) __builtin_nontemporal_store(L1, A.l1 + i);
     if (A.l2) __builtin_nontemporal_store(L2, A.l2 + i);
-    if (A.zp) __builtin_nontemporal_store(pack_zp(o.zeta_b, o.p), A.zp + i);
+    if (A.zp) __builtin_nontemporal_store(pack_zp(o.unscale, o.p), A.zp + i);
 }
 
 template <bool CPLX, bool SINFORM, bool SCALED>
@@ -84,15 +84,15 @@ __global__ __launch_bounds__(256) void evd2_kernel_v2(Evd2Args A)
     __builtin_nontemporal_store(d2v{o0.C, o1.C}, (d2v *)(A.cr + i));
     if (CPLX) __builtin_nontemporal_store(d2v{o0.S, o1.S}, (d2v *)(A.ci + i));
     if (A.l1) {
-        const d2v L = SCALED ? d2v{o0.l1, o1.l1} : d2v{scal2(o0.l1, o0.zeta_b), scal2(o1.l1, o1.zeta_b)};
+        const d2v L = SCALED ? d2v{o0.l1, o1.l1} : d2v{scal2(o0.l1, o0.unscale), scal2(o1.l1, o1.unscale)};
         __builtin_nontemporal_store(L, (d2v *)(A.l1 + i));
     }
     if (A.l2) {
-        const d2v L = SCALED ? d2v{o0.l2, o1.l2} : d2v{scal2(o0.l2, o0.zeta_b), scal2(o1.l2, o1.zeta_b)};
+        const d2v L = SCALED ? d2v{o0.l2, o1.l2} : d2v{scal2(o0.l2, o0.unscale), scal2(o1.l2, o1.unscale)};
         __builtin_nontemporal_store(L, (d2v *)(A.l2 + i));
     }
     if (A.zp)
-        __builtin_nontemporal_store(i2v{pack_zp(o0.zeta_b, o0.p), pack_zp(o1.zeta_b, o1.p)},
+        __builtin_nontemporal_store(i2v{pack_zp(o0.unscale, o0.p), pack_zp(o1.unscale, o1.p)},
                                     (i2v *)(A.zp + i));
 }
 
@@ -120,9 +120,9 @@ __device__ __forceinline__ void sevd2_one(const SEvd2Args &A, size_t i)
     __builtin_nontemporal_store(o.c, A.cs + i);
     __builtin_nontemporal_store(o.C, A.cr + i);
     if (CPLX) __builtin_nontemporal_store(o.S, A.ci + i);
-    if (A.l1) __builtin_nontemporal_store(SCALED ? o.l1 : __builtin_amdgcn_ldexpf(o.l1, o.zeta_b), A.l1 + i);
-    if (A.l2) __builtin_nontemporal_store(SCALED ? o.l2 : __builtin_amdgcn_ldexpf(o.l2, o.zeta_b), A.l2 + i);
-    if (A.zp) __builtin_nontemporal_store(pack_zp(o.zeta_b, o.p), A.zp + i);
+    if (A.l1) __builtin_nontemporal_store(SCALED ? o.l1 : __builtin_amdgcn_ldexpf(o.l1, o.unscale), A.l1 + i);
+    if (A.l2) __builtin_nontemporal_store(SCALED ? o.l2 : __builtin_amdgcn_ldexpf(o.l2, o.unscale), A.l2 + i);
+    if (A.zp) __builtin_nontemporal_store(pack_zp(o.unscale, o.p), A.zp + i);
 }
 
 template <bool CPLX, bool SINFORM, bool SCALED, int V>
@@ -153,9 +153,9 @@ __global__ __launch_bounds__(256) void sevd2_kernel(SEvd2Args A)
             c[u] = o.c;
             C[u] = o.C;
             S[u] = o.S;
-            L1[u] = SCALED ? o.l1 : __builtin_amdgcn_ldexpf(o.l1, o.zeta_b);
-            L2[u] = SCALED ? o.l2 : __builtin_amdgcn_ldexpf(o.l2, o.zeta_b);
-            z[u] = pack_zp(o.zeta_b, o.p);
+            L1[u] = SCALED ? o.l1 : __builtin_amdgcn_ldexpf(o.l1, o.unscale);
+            L2[u] = SCALED ? o.l2 : __builtin_amdgcn_ldexpf(o.l2, o.unscale);
+            z[u] = pack_zp(o.unscale, o.p);
         }
         __builtin_nontemporal_store(c, (fv *)(A.cs + i));
         __builtin_nontemporal_store(C, (fv *)(A.cr + i));
@@ -250,6 +250,45 @@ hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const dou
     if (sinf)
         return scaled ? launch_t<false, true, true>(A, vec2, s) : launch_t<false, true, false>(A, vec2, s);
     return scaled ? launch_t<false, false, true>(A, vec2, s) : launch_t<false, false, false>(A, vec2, s);
+}
+
+// ---------------------------------------------------------------------------
+// The memory-system ceiling of the EVD kernels: the same streams read and
+// written with the same launch shapes and access hints, every output a copy
+// of an input (no arithmetic).  A measurement aid for the roofline of
+// jsvd_evd2_batched.
+template <bool CPLX>
+__device__ __forceinline__ void stream_one(const Evd2Args &A, size_t i)
+{
+    const double a11 = __builtin_nontemporal_load(A.a11 + i);
+    const double a22 = __builtin_nontemporal_load(A.a22 + i);
+    const double ar = __builtin_nontemporal_load(A.ar + i);
+    __builtin_nontemporal_store(a11, A.cs + i);
+    __builtin_nontemporal_store(a22, A.cr + i);
+    if (CPLX) __builtin_nontemporal_store(__builtin_nontemporal_load(A.ai + i), A.ci + i);
+    __builtin_nontemporal_store(ar, A.l1 + i);
+    __builtin_nontemporal_store(a11, A.l2 + i);
+    __builtin_nontemporal_store((int32_t)(__double_as_longlong(a22) >> 32), A.zp + i);
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(256) void evd2_stream_kernel_v1(Evd2Args A)
+{
+    const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < A.r) stream_one<CPLX>(A, i);
+}
+
+hipError_t launch_evd2_stream(size_t r, const double *a11, const double *a22, const double *ar, const double *ai,
+                              double *cs, double *cr, double *ci, double *l1, double *l2, int32_t *zp, hipStream_t s)
+{
+    if (r == 0) return hipSuccess;
+    Evd2Args A{r, a11, a22, ar, ai, cs, cr, ci, l1, l2, zp};
+    const unsigned blocks = (unsigned)((r + 255) / 256);
+    if (ai)
+        hipLaunchKernelGGL((evd2_stream_kernel_v1<true>), dim3(blocks), dim3(256), 0, s, A);
+    else
+        hipLaunchKernelGGL((evd2_stream_kernel_v1<false>), dim3(blocks), dim3(256), 0, s, A);
+    return hipGetLastError();
 }
 
 } // namespace jsvd

@@ -19,6 +19,11 @@ inline bool iter_flags_valid(unsigned flags, unsigned allowed)
 // 1 (apply U, the default) unless the EVD's sorting permutation is asked for.
 inline int iter_nosort(unsigned flags) { return (flags & JSVD_PERMUTE) ? 0 : 1; }
 
+// the EVD's streams moved without arithmetic (the memory ceiling of launch_evd2
+// at batches of 2^22 and more)
+hipError_t launch_evd2_stream(size_t r, const double *a11, const double *a22, const double *ar, const double *ai,
+                              double *cs, double *cr, double *ci, double *l1, double *l2, int32_t *zp,
+                              hipStream_t s);
 hipError_t launch_evd2(size_t r, const double *a11, const double *a22, const double *ar,
                        const double *ai, double *cs, double *cr, double *ci, double *l1,
                        double *l2, int32_t *zp, unsigned flags, hipStream_t s);

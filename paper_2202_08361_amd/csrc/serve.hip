@@ -110,7 +110,7 @@ struct jsvd_server_s {
     bool stopping = false;
     std::thread worker;
     uint64_t submitted = 0, completed = 0, rejected = 0;
-    std::vector<double> lat_ns, qlat_ns;
+    std::vector<double> lat_ns, qlat_ns, svc_ns;
     Clock::time_point t_create;
     // worker thread only: states of finished large requests (oldest first),
     // their bytes, and finished group launches not yet released
@@ -163,7 +163,7 @@ static void release_held(jsvd_server sv)
     sv->held.clear();
 }
 
-static double percentile(std::vector<double> v, double p)
+static double percentile(std::vector<double> &v, double p)
 {
     if (v.empty()) return 0.0;
     const size_t k = std::min(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5));
@@ -182,6 +182,7 @@ static void complete_locked(jsvd_server sv, uint64_t id, int status, int sweeps)
     t.sweeps = sweeps;
     const auto now = Clock::now();
     sv->lat_ns.push_back((double)std::chrono::duration_cast<std::chrono::nanoseconds>(now - t.t_submit).count());
+    sv->svc_ns.push_back((double)std::chrono::duration_cast<std::chrono::nanoseconds>(now - t.t_admit).count());
     sv->completed++;
 }
 
@@ -209,6 +210,7 @@ static bool service_slot(jsvd_server sv, Slot &s)
         std::lock_guard<std::mutex> lk(sv->mu);
         for (size_t i = 0; i < s.group.size(); ++i)
             complete_locked(sv, s.group[i], res ? res[i].status : JSVD_EDEVICE, res ? res[i].sweeps : 0);
+        if (q == hipSuccess) batch_done(s.bl);   // its class streams serve other launches now
         sv->held.push_back(s.bl);   // its results are read; released with the others
         s.bl = nullptr;
         free_slot_locked(sv, s);
@@ -532,21 +534,41 @@ extern "C" int jsvd_serve_wait(jsvd_server sv, uint64_t ticket, int *status, int
 extern "C" int jsvd_serve_stats_get(jsvd_server sv, jsvd_serve_stats *out)
 {
     if (!sv || !out) return JSVD_EINVAL;
-    std::lock_guard<std::mutex> lk(sv->mu);
+    std::vector<double> lat, qlat, svc;
     memset(out, 0, sizeof(*out));
-    out->submitted = sv->submitted;
-    out->completed = sv->completed;
-    out->rejected = sv->rejected;
-    out->p50_ns = percentile(sv->lat_ns, 0.50);
-    out->p99_ns = percentile(sv->lat_ns, 0.99);
-    out->p50_queue_ns = percentile(sv->qlat_ns, 0.50);
-    out->p99_queue_ns = percentile(sv->qlat_ns, 0.99);
+    {
+        // copy under the lock; the percentiles are taken outside it, so the
+        // worker is held up only for the copy
+        std::lock_guard<std::mutex> lk(sv->mu);
+        lat = sv->lat_ns;
+        qlat = sv->qlat_ns;
+        svc = sv->svc_ns;
+        out->submitted = sv->submitted;
+        out->completed = sv->completed;
+        out->rejected = sv->rejected;
+        out->queue_depth = (int)sv->queue.size();
+        out->active = sv->active;
+        out->hbm_in_use = sv->hbm_in_use;
+    }
+    out->p50_ns = percentile(lat, 0.50);
+    out->p99_ns = percentile(lat, 0.99);
+    out->p50_queue_ns = percentile(qlat, 0.50);
+    out->p99_queue_ns = percentile(qlat, 0.99);
+    out->p50_service_ns = percentile(svc, 0.50);
+    out->p99_service_ns = percentile(svc, 0.99);
     const double secs =
         std::chrono::duration_cast<std::chrono::duration<double>>(Clock::now() - sv->t_create).count();
-    out->svds_per_s = secs > 0 ? (double)sv->completed / secs : 0.0;
-    out->queue_depth = (int)sv->queue.size();
-    out->active = sv->active;
-    out->hbm_in_use = sv->hbm_in_use;
+    out->svds_per_s = secs > 0 ? (double)out->completed / secs : 0.0;
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_serve_load(jsvd_server sv, int *queue_depth, int *active, size_t *hbm_in_use)
+{
+    if (!sv) return JSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (queue_depth) *queue_depth = (int)sv->queue.size();
+    if (active) *active = sv->active;
+    if (hbm_in_use) *hbm_in_use = sv->hbm_in_use;
     return JSVD_OK;
 }
 

@@ -178,3 +178,34 @@ def test_batched_full_workload(permute):
         assert (torch.linalg.norm(Ad - (U * s) @ Vt) / torch.linalg.norm(Ad)).item() <= 64 * n * eps
         eye = torch.eye(n, dtype=V.dtype, device=V.device)
         assert (Vt @ V - eye).abs().max().item() <= 64 * n * eps
+
+
+def test_batched_transformation_counts():
+    """transformations[i] of the batched call is the number of pairs the
+    iteration transformed: the sum over the sweeps of the plain path's
+    per-sweep count (the iterations are the same, bit for bit); -1 for a
+    matrix that took the plain path."""
+    shapes = [(60, 40, False, 1e4), (100, 100, True, 1e6), (257, 128, False, 1e8), (700, 64, False, 1e3)]
+    host = _mats(shapes, 7)
+    dev = [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host]
+    res = J().gesvj_batched(dev)
+    torch.cuda.synchronize()
+    for (Ar, Ai), r in zip(host, res):
+        m, n = Ar.shape
+        if m > 512:
+            assert r["transformations"] == -1
+            continue
+        st = J().State(m, n, Ai is not None)
+        st.load(J().to_device_fortran(Ar), None if Ai is None else J().to_device_fortran(Ai))
+        total, sweeps = 0, 0
+        while True:
+            st.sweep()
+            q = st.query()
+            total += q["last_sweep_T"]
+            sweeps += 1
+            if q["converged"]:
+                break
+            assert sweeps <= 128
+        st.close()
+        assert r["status"] == 0 and r["transformations"] == total, (Ar.shape, r["transformations"], total)
+        assert total > 0

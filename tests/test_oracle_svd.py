@@ -599,3 +599,23 @@ def test_zero_column(ora):
     assert np.isinf(r["sv_e"][-1]) and r["sv_e"][-1] < 0
     assert np.all(np.isfinite(r["U_re"])) and np.all(r["U_re"][:, -1] == 0)
     assert np.all(np.isfinite(r["sv_e"][:-1]))
+
+
+@pytest.mark.parametrize("cplx,flags", [(False, 0), (True, 2), (False, 8)])
+def test_step_threads_do_not_change_results(ora, cplx, flags):
+    """The pairs of a step are disjoint and the step's counts and max-norm are
+    an integer sum and an exact max: running the step's loops over pairs on
+    several threads gives the same bits as one thread."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, 4321 + int(cplx))
+    sig = inputs.sigma_logspace(41, 1e-5)
+    Ar, Ai = inputs.svd_matrix(70, 41, sig, g, cplx=cplx)
+    out = {}
+    try:
+        for th in (1, 4):
+            ora.set_step_threads(th)
+            out[th] = ora.gesvj(Ar, Ai if cplx else None, flags=flags)
+    finally:
+        ora.set_step_threads(1)
+    assert out[1]["sweeps"] == out[4]["sweeps"] and out[1]["status"] == out[4]["status"] == 0
+    for k in ("U_re", "V_re", "sv_e", "sv_f") + (("U_im", "V_im") if cplx else ()):
+        assert np.array_equal(out[1][k].view(np.int64), out[4][k].view(np.int64)), k
