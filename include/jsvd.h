@@ -332,6 +332,29 @@ int jsvd_gesvj_batched(int count, const int *m, const int *n, const int *is_comp
                        int max_sweeps, int *sweeps, int *status, int64_t *transformations,
                        unsigned flags, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): jsvd_gesvj_batched without any
+ * allocation.  The same arguments and the same per-matrix results, bit
+ * for bit, with these limits:
+ * - at most 8192 matrices per call (JSVD_EINVAL beyond);
+ * - every matrix must be a batched shape (at most 512 rows and columns):
+ *   JSVD_EINVAL otherwise, since the plain path allocates a state;
+ * - launch shapes are the ones measured earlier in the process
+ *   (jsvd_batched_tune, or a jsvd_gesvj_batched call), else the default; this
+ *   call measures nothing;
+ * - the classes run one after another on `stream`.
+ * The launch records (930 KiB: per-matrix records, the processing
+ * order and the classes' work-queue counters, rewritten on every call) sit
+ * in a file-scope device array that each GPU the library runs on holds until
+ * the process ends.  Calls in one process are serialised by a lock, so they
+ * never overlap on the array.  Synchronises. */
+int jsvd_gesvj_batched_noalloc(int count, const int *m, const int *n, const int *is_complex,
+                               double *const *G_re, double *const *G_im, const size_t *ldg,
+                               double *const *V_re, double *const *V_im, const size_t *ldv,
+                               double *const *sv_e, double *const *sv_f,
+                               int max_sweeps, int *sweeps, int *status, int64_t *transformations,
+                               unsigned flags, void *stream);
+
 /* Launch shape of the batched SVD: the threads per matrix (one wavefront per
  * pivot pair at a time) of each class are chosen by measurement, once per
  * process and device: one sweep of up to 1024 random matrices of the class's

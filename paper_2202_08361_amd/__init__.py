@@ -137,6 +137,9 @@ def lib():
         L.jsvd_gesvj.argtypes = [i, i, vp, vp, sz, vp, vp, sz, vp, vp, vp, i, _ct.POINTER(i), u, vp]
         L.jsvd_gesvj_batched.restype = i
         L.jsvd_gesvj_batched.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, vp, u, vp]
+        L.jsvd_gesvj_batched_noalloc.restype = i
+        L.jsvd_gesvj_batched_noalloc.argtypes = [i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, i, vp, vp, vp, u,
+                                                 vp]
         L.jsvd_batched_tune.restype = i
         L.jsvd_batched_tune.argtypes = [i, vp, vp, vp, u, vp]
         L.jsvd_batched_set_launch.restype = i
@@ -455,9 +458,11 @@ def gesvj(G_re, G_im=None, max_sweeps=0, flags=0, overwrite=False, stream=None):
                 sv_f=sv_f, sv=sv)
 
 
-def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None):
+def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None, noalloc=False):
     """Many SVDs in one call.  ``mats`` is a list of (G_re, G_im|None) column-major
-    device tensors, overwritten by U.  Returns a list of dicts like :func:`gesvj`."""
+    device tensors, overwritten by U.  Returns a list of dicts like :func:`gesvj`.
+    noalloc: the library allocates no device memory for the call
+    (jsvd_gesvj_batched_noalloc: at most 8192 matrices, each at most 512 x 512)."""
     torch = _torch()
     cnt = len(mats)
     I = _ct.c_int * cnt
@@ -483,9 +488,11 @@ def gesvj_batched(mats, max_sweeps=0, flags=0, stream=None):
         lg[idx], lv[idx] = ld, n
         res.append(dict(U_re=Gr, U_im=Gi, V_re=Vr, V_im=Vi, sv_e=e, sv_f=f))
     sweeps, status, trans = I(), I(), (_ct.c_int64 * cnt)()
-    st = lib().jsvd_gesvj_batched(cnt, m_a, n_a, c_a, gr, gi, lg, vr, vi, lv, se, sf, max_sweeps, sweeps, status,
-                                  trans, flags, _stream(stream))
-    _check(st, "jsvd_gesvj_batched", allow=(OK, NOT_CONVERGED, ENONFINITE, EZERO))
+    fn = lib().jsvd_gesvj_batched_noalloc if noalloc else lib().jsvd_gesvj_batched
+    st = fn(cnt, m_a, n_a, c_a, gr, gi, lg, vr, vi, lv, se, sf, max_sweeps, sweeps, status, trans, flags,
+            _stream(stream))
+    _check(st, "jsvd_gesvj_batched_noalloc" if noalloc else "jsvd_gesvj_batched",
+           allow=(OK, NOT_CONVERGED, ENONFINITE, EZERO))
     for idx in range(cnt):
         res[idx]["status"] = status[idx]
         res[idx]["sweeps"] = sweeps[idx]

@@ -48,4 +48,11 @@ const BatchItem *batch_results(const BatchLaunch *bl);
 void batch_done(BatchLaunch *bl);
 void batch_release(BatchLaunch *bl);
 
+// The allocation-free variant: the items (all batched shapes, at most
+// kNoAllocMaxCount) run class after class on stream s with the launch
+// records in a file-scope device array; status and sweeps come back in the
+// items.  Synchronises.  Calls in one process are serialised by a lock.
+constexpr int kNoAllocMaxCount = 8192;
+int batch_run_noalloc(BatchItem *items, int count, int max_sweeps, unsigned flags, hipStream_t s);
+
 } // namespace jsvd

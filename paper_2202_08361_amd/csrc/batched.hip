@@ -852,6 +852,111 @@ void batch_release(BatchLaunch *bl)
     delete bl;
 }
 
+// ---------------------------------------------------------------------------
+// The allocation-free batched call: its per-matrix records, the processing
+// order and the classes' work-queue counters live in a file-scope device
+// array instead of a hipMalloc'ed buffer, staged through file-scope host
+// arrays.  Its address is looked up once per device (the array's name is a
+// host-side stand-in, not a device address).
+
+constexpr size_t kNaItemsOff = 0;
+constexpr size_t kNaOrderOff = (sizeof(BatchItem) * kNoAllocMaxCount + 255) & ~(size_t)255;
+constexpr size_t kNaCtlOff = kNaOrderOff + ((sizeof(int) * kNoAllocMaxCount + 255) & ~(size_t)255);
+constexpr size_t kNoAllocBytes = kNaCtlOff + 256 * 8;
+static_assert(kNoAllocBytes <= 930 * 1024, "the size the header states");
+
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+static std::mutex g_na_mu;                 // one call at a time in the process
+static char *g_na_dev[kMaxDev];            // the array's address on each device
+alignas(256) static char g_na_host[kNoAllocBytes];
+
+// the device address of `scratch` on the current device (looked up on the
+// first call on that device); nullptr on failure.  Caller holds g_na_mu.
+static char *noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDev) return nullptr;
+    if (!g_na_dev[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_na_dev[dev] = (char *)ptr;
+    }
+    return g_na_dev[dev];
+}
+
+// Run the items (all batched shapes, count <= kNoAllocMaxCount) class by
+// class on stream s, without allocating; their status and sweeps come back
+// in items.  Synchronises.
+int batch_run_noalloc(BatchItem *items, int cnt, int max_sweeps, unsigned flags, hipStream_t s)
+{
+    if (cnt < 0 || cnt > kNoAllocMaxCount) return JSVD_EINVAL;
+    if (cnt == 0) return JSVD_OK;
+    const bool comp = (flags & JSVD_COMPENSATED) != 0;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    int dev = 0;
+    const int ncu = current_device_ncu(&dev);
+    char *dm = noalloc_scratch(dev);
+    if (!dm) return JSVD_EDEVICE;
+    BatchItem *hitems = (BatchItem *)(g_na_host + kNaItemsOff);
+    int *horder = (int *)(g_na_host + kNaOrderOff);
+    memcpy(hitems, items, sizeof(BatchItem) * cnt);
+    // per class (complex first, more rows first), longest first; ties by index
+    auto cost = [&](int i) {
+        return (hitems[i].cplx ? 2.0 : 1.0) * hitems[i].n * (double)hitems[i].n * (hitems[i].m + hitems[i].n);
+    };
+    for (int i = 0; i < cnt; ++i) horder[i] = i;
+    std::sort(horder, horder + cnt, [&](int a, int b) {
+        const int ka = class_index(hitems[a].cplx, hitems[a].R), kb = class_index(hitems[b].cplx, hitems[b].R);
+        if (ka != kb) return ka > kb;
+        const double ca = cost(a), cb = cost(b);
+        if (ca != cb) return ca > cb;
+        return a < b;
+    });
+    int first[9], ncls = 0, cls_of[8];
+    for (int i = 0; i < cnt; ++i) {
+        const int k = class_index(hitems[horder[i]].cplx, hitems[horder[i]].R);
+        if (ncls == 0 || cls_of[ncls - 1] != k) {
+            cls_of[ncls] = k;
+            first[ncls++] = i;
+        }
+    }
+    first[ncls] = cnt;
+    for (int c = 0; c < ncls; ++c) {
+        BatchCtl ctl;
+        memset(&ctl, 0, sizeof(ctl));
+        ctl.next = 0;   // the class's work queue starts at zero on every call
+        ctl.count = first[c + 1] - first[c];
+        ctl.max_sweeps = max_sweeps;
+        ctl.nosort = iter_nosort(flags);
+        ctl.nogs = (flags & JSVD_NO_GS) ? 1 : 0;
+        memcpy(g_na_host + kNaCtlOff + 256 * (size_t)c, &ctl, sizeof(ctl));
+    }
+    bool ok = hipMemcpyAsync(dm + kNaItemsOff, hitems, sizeof(BatchItem) * cnt, hipMemcpyHostToDevice, s) ==
+                  hipSuccess &&
+              hipMemcpyAsync(dm + kNaOrderOff, horder, sizeof(int) * cnt, hipMemcpyHostToDevice, s) == hipSuccess &&
+              hipMemcpyAsync(dm + kNaCtlOff, g_na_host + kNaCtlOff, 256 * (size_t)ncls, hipMemcpyHostToDevice, s) ==
+                  hipSuccess;
+    // the classes one after another on the caller's stream (no class streams:
+    // creating one may allocate)
+    for (int c = 0; ok && c < ncls; ++c) {
+        const BatchItem &it0 = hitems[horder[first[c]]];
+        const int NT = class_threads(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
+        ok = launch_class(comp, it0.cplx, it0.R, NT, (BatchItem *)(dm + kNaItemsOff),
+                          (const int *)(dm + kNaOrderOff) + first[c], (BatchCtl *)(dm + kNaCtlOff + 256 * (size_t)c),
+                          first[c + 1] - first[c], ncu, s) == hipSuccess;
+    }
+    ok = ok && hipMemcpyAsync(hitems, dm + kNaItemsOff, sizeof(BatchItem) * cnt, hipMemcpyDeviceToHost, s) ==
+                   hipSuccess;
+    ok = (hipStreamSynchronize(s) == hipSuccess) && ok;
+    if (!ok) return JSVD_EDEVICE;
+    for (int i = 0; i < cnt; ++i) {
+        items[i].status = hitems[i].status;
+        items[i].sweeps = hitems[i].sweeps;
+        items[i].transformations = hitems[i].transformations;
+    }
+    return JSVD_OK;
+}
+
 } // namespace jsvd
 
 using namespace jsvd;
@@ -943,6 +1048,47 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
         if (sweeps) sweeps[i] = sw;
         if (transformations) transformations[i] = -1;   // not counted on the plain path
         if (rc < 0 && rc_all == JSVD_OK) rc_all = rc;
+    }
+    return rc_all;
+}
+
+extern "C" int jsvd_gesvj_batched_noalloc(int count, const int *m, const int *n, const int *is_complex,
+                                          double *const *G_re, double *const *G_im, const size_t *ldg,
+                                          double *const *V_re, double *const *V_im, const size_t *ldv,
+                                          double *const *sv_e, double *const *sv_f, int max_sweeps, int *sweeps,
+                                          int *status, int64_t *transformations, unsigned flags, void *stream)
+{
+    if (count < 0 || count > kNoAllocMaxCount) return JSVD_EINVAL;
+    if (count == 0) return JSVD_OK;
+    if (!m || !n || !G_re || !ldg || !V_re || !ldv || !sv_e || !sv_f || !status) return JSVD_EINVAL;
+    if (!iter_flags_valid(flags, JSVD_NO_PERMUTE | JSVD_PERMUTE | JSVD_COMPENSATED | JSVD_NO_GS)) return JSVD_EINVAL;
+    for (int i = 0; i < count; ++i) {
+        const int c = is_complex ? is_complex[i] : 0;
+        if (n[i] < 1 || m[i] < n[i] || !G_re[i] || !V_re[i] || !sv_e[i] || !sv_f[i] || ldg[i] < (size_t)m[i] ||
+            ldv[i] < (size_t)n[i])
+            return JSVD_EINVAL;
+        if (c && (!G_im || !V_im || !G_im[i] || !V_im[i])) return JSVD_EINVAL;
+        // only the batched kernel's shapes: the plain path would allocate a state
+        if (!batch_rows(m[i], n[i], c != 0)) return JSVD_EINVAL;
+    }
+    if (max_sweeps <= 0) max_sweeps = 128;
+    // the records are built in a file-scope array too (no heap allocation)
+    static BatchItem items[kNoAllocMaxCount];
+    static std::mutex items_mu;
+    std::lock_guard<std::mutex> lk(items_mu);
+    for (int i = 0; i < count; ++i) {
+        const int c = is_complex ? (is_complex[i] != 0) : 0;
+        items[i] = make_batch_item(m[i], n[i], c, G_re[i], c ? G_im[i] : nullptr, ldg[i], V_re[i],
+                                   c ? V_im[i] : nullptr, ldv[i], sv_e[i], sv_f[i]);
+    }
+    const int rc = batch_run_noalloc(items, count, max_sweeps, flags, (hipStream_t)stream);
+    if (rc != JSVD_OK) return rc;
+    int rc_all = JSVD_OK;
+    for (int i = 0; i < count; ++i) {
+        status[i] = items[i].status;
+        if (sweeps) sweeps[i] = items[i].sweeps;
+        if (transformations) transformations[i] = items[i].transformations;
+        if (items[i].status < 0 && rc_all == JSVD_OK) rc_all = items[i].status;
     }
     return rc_all;
 }
