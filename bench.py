@@ -638,6 +638,36 @@ def svd_plain(torch, J, inputs, flags, fp32=False):
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
+def svd_plain_sweeps(torch, J, inputs, persistent):
+    """The 256 x 256 workload through the state API (load, jsvd_state_iterate,
+    finalize), with persistent sweeps or with step-by-step sweeps (a zero
+    wait budget turns persistent sweeps off): the A/B of the two sweep forms
+    on the same iteration (the same bits, tested)."""
+    import numpy as np
+    A, sig = inputs.plain_real_256()
+    dA = J.to_device_fortran(A)
+    best, q = None, None
+    for rep in range(3):
+        st = J.State(256, 256, False)
+        if not persistent:
+            st.set_loop_wait(0.0)
+        st.load(dA)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.iterate()
+        r = st.finalize()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        q = st.query()
+        st.close()
+        best = dt if best is None else min(best, dt)
+    sv = r["sv"].cpu().numpy()
+    K = 255
+    return dict(ms=best * 1e3, sweeps=q["sweeps"], persistent_sweeps=q["loop_sweeps"], redone=q["loop_redos"],
+                us_per_step=best * 1e6 / ((q["sweeps"] + 1) * K),
+                max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
+
+
 def svd_large(torch, J, inputs, cplx, flags):
     """The whole plain SVD of a large workload: complex 4096 x 4096 (sigma
     geometric from 1 to 1e-12) or real 8192 x 2048 (sigma log-spaced in
@@ -894,6 +924,8 @@ def main():
                        ("svd_real256_compensated", J.COMPENSATED),
                        ("svd_real256_permute_compensated", J.PERMUTE | J.COMPENSATED)):
             tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl)))
+        for nm, pers in (("svd_real256_persistent_sweeps", True), ("svd_real256_stepwise_sweeps", False)):
+            tasks.append((nm, lambda pers=pers: svd_plain_sweeps(torch, J, inputs, pers)))
         for (m, n, c) in big:
             for fp32 in (False, True):
                 tasks.append((f"sweep_{tag(m, n, c)}" + ("_f32" if fp32 else ""),

@@ -153,6 +153,8 @@ typedef struct {
     int64_t last_sweep_swaps; /* swaps without transformation in the last completed sweep */
     int64_t gs;               /* Gram-Schmidt steps in the current sweep so far (counted in T) */
     int64_t last_sweep_gs;    /* Gram-Schmidt steps in the last completed sweep */
+    int64_t loop_sweeps;      /* sweeps since the load that ran as one persistent launch */
+    int64_t loop_redos;       /* persistent sweeps that gave up and were redone step by step */
 } jsvd_info;
 
 /* Allocate a state for an m x n real (is_complex = 0) or complex problem.
@@ -192,6 +194,25 @@ int jsvd_step(jsvd_state st, void *stream);
  * before its end: to the caller the sweep is ordered on `stream` like any
  * other launch. */
 int jsvd_sweep(jsvd_state st, void *stream);
+
+/* Sweeps until the state stops (converged, or the sweep limit), one
+ * graph-launched sweep at a time with a synchronisation after each (the
+ * device decides convergence): the iteration of jsvd_gesvj on a loaded
+ * state.  For columns of at most 256 rows (automatic launch shape) a sweep
+ * runs as one persistent launch whenever the device has found that the
+ * rescaling check of Sect. 3.2 cannot fire in it (max(M~, (1 + 32 eps K)
+ * ||G||_F) below the threshold): one workgroup per pair slot, each pair of
+ * step k + 1 starting as soon as its two columns are out of step k.  The
+ * result is the same, bit for bit, as K steps.  Such a sweep needs its
+ * workgroups resident together; one that waits too long for a column gives
+ * up and is redone step by step from a copy taken before it.
+ * jsvd_state_query reports both counts.  Synchronises. */
+int jsvd_state_iterate(jsvd_state st, void *stream);
+/* How long (wall clock, seconds) a workgroup of a persistent sweep of
+ * jsvd_state_iterate / jsvd_gesvj waits for one column before the sweep
+ * gives up and is redone step by step (default 0.25; at most 60).  0 turns
+ * persistent sweeps off for the state.  JSVD_EINVAL outside [0, 60]. */
+int jsvd_state_set_loop_wait(jsvd_state st, double seconds);
 
 /* Read the scalars of the state.  Synchronises. */
 int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream);

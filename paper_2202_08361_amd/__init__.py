@@ -51,7 +51,8 @@ class _Info(_ct.Structure):
                 ("last_t", _ct.c_int64), ("swaps", _ct.c_int64), ("s", _ct.c_int32),
                 ("rescaled", _ct.c_int32), ("Mt", _ct.c_double), ("converged", _ct.c_int32),
                 ("status", _ct.c_int32), ("last_sweep_T", _ct.c_int64), ("last_sweep_swaps", _ct.c_int64),
-                ("gs", _ct.c_int64), ("last_sweep_gs", _ct.c_int64)]
+                ("gs", _ct.c_int64), ("last_sweep_gs", _ct.c_int64), ("loop_sweeps", _ct.c_int64),
+                ("loop_redos", _ct.c_int64)]
 
 
 class ServeConfig(_ct.Structure):
@@ -118,6 +119,10 @@ def lib():
         L.jsvd_step.argtypes = [vp, vp]
         L.jsvd_sweep.restype = i
         L.jsvd_sweep.argtypes = [vp, vp]
+        L.jsvd_state_iterate.restype = i
+        L.jsvd_state_iterate.argtypes = [vp, vp]
+        L.jsvd_state_set_loop_wait.restype = i
+        L.jsvd_state_set_loop_wait.argtypes = [vp, d]
         L.jsvd_state_query.restype = i
         L.jsvd_state_query.argtypes = [vp, _ct.POINTER(_Info), vp]
         L.jsvd_state_save.restype = i
@@ -380,6 +385,15 @@ class State:
 
     def sweep(self, stream=None):
         _check(lib().jsvd_sweep(self._h, _stream(stream)), "jsvd_sweep")
+
+    def iterate(self, stream=None):
+        """Sweeps until the state stops (jsvd_state_iterate; synchronises)."""
+        _check(lib().jsvd_state_iterate(self._h, _stream(stream)), "jsvd_state_iterate")
+
+    def set_loop_wait(self, seconds):
+        """Wait budget of a persistent sweep's workgroup for one column
+        (jsvd_state_set_loop_wait; 0 turns persistent sweeps off)."""
+        _check(lib().jsvd_state_set_loop_wait(self._h, float(seconds)), "jsvd_state_set_loop_wait")
 
     def query(self, stream=None):
         info = _Info()

@@ -128,8 +128,13 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct StateLayout {
     long long ldg, ldv, vstride;
-    size_t oG, oV, oE, oF, oR, oS, oM, oP, oQ, oX, oH, total;
+    size_t oG, oV, oE, oF, oR, oS, oM, oP, oQ, oX, oH;
+    size_t oLV, oLA, oLC, oLB, oLZ;   // persistent sweeps (m <= 256): flags, folds, sums, abort, snapshot
+    size_t total;
 };
+
+// states whose sweeps may run as one persistent launch
+static bool loop_candidate_shape(int m) { return m <= 256; }
 
 // es: bytes per element of the working precision
 static StateLayout state_layout(int m, int n, int cplx, size_t es)
@@ -153,6 +158,16 @@ static StateLayout state_layout(int m, int n, int cplx, size_t es)
     L.oQ = off; off = align_up(off + sizeof(double) * (size_t)L.vstride * kVlogSlots);
     L.oH = off; off = align_up(off + sizeof(StepHdr) * (size_t)kVlogSlots);
     L.oX = off; off = align_up(off + sizeof(unsigned long long) * (size_t)kVlogSlots);
+    L.oLV = L.oLA = L.oLC = L.oLB = L.oLZ = 0;
+    if (loop_candidate_shape(m)) {
+        const size_t npairs = (size_t)(n + 1) / 2;
+        L.oLV = off; off = align_up(off + sizeof(unsigned long long) * (size_t)n);
+        L.oLA = off; off = align_up(off + sizeof(LoopAcc) * npairs);
+        L.oLC = off; off = align_up(off + sizeof(double) * (size_t)n);
+        L.oLB = off; off = align_up(off + sizeof(unsigned));
+        // the snapshot: G, V, e and f, one contiguous block from oG to oR
+        L.oLZ = off; off = align_up(off + (L.oR - L.oG));
+    }
     L.total = off;
     return L;
 }
@@ -247,6 +262,32 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
     st->vbase = 0;
     st->vlast = -1;
     st->v_layout = V_EITHER;
+    // the device scalars start from zero (loop_epoch included)
+    if (hipMemset(st->sc, 0, sizeof(DevScalars)) != hipSuccess) {
+        jsvd_state_destroy(st);
+        return JSVD_EDEVICE;
+    }
+    if (loop_candidate_shape(m)) {
+        st->loop_cand = 1;
+        st->loop.ver = (unsigned long long *)(b + L.oLV);
+        st->loop.acc = (LoopAcc *)(b + L.oLA);
+        st->loop.abort = (unsigned *)(b + L.oLB);
+        st->colsq = (double *)(b + L.oLC);
+        st->snap = b + L.oLZ;
+        st->snap_bytes = L.oR - L.oG;
+        // a wait for one column may take 0.25 s (wall clock) before the sweep gives up
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, st->device) != hipSuccess || khz <= 0)
+            khz = 100000;
+        st->loop.budget = (unsigned long long)khz * 250ull;
+        // column flags of epoch 0, a lowered abort flag and scalars of epoch 0
+        // (outside any graph)
+        if (hipMemset(b + L.oLV, 0, L.oLC - L.oLV) != hipSuccess || hipMemset(b + L.oLB, 0, 256) != hipSuccess ||
+            hipDeviceSynchronize() != hipSuccess) {
+            jsvd_state_destroy(st);
+            return JSVD_EDEVICE;
+        }
+    }
     *out = st;
     return JSVD_OK;
 }
@@ -266,6 +307,8 @@ extern "C" void jsvd_state_destroy(jsvd_state st)
     if (!st) return;
     if (st->graph) (void)hipGraphExecDestroy(st->graph);
     if (st->graph_def) (void)hipGraphDestroy(st->graph_def);
+    if (st->loop_graph) (void)hipGraphExecDestroy(st->loop_graph);
+    if (st->loop_graph_def) (void)hipGraphDestroy(st->loop_graph_def);
     if (st->mem) (void)hipFree(st->mem);
     if (st->host) (void)hipHostFree(st->host);
     delete st;
@@ -318,6 +361,8 @@ static int load_async_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg,
     HIPCHK(launch_zero_u64(st->maxbits, s));
     HIPCHK(launch_maxabs(d, G_re, G_im, (long long)ldg, st->maxbits, s));
     HIPCHK(launch_init_scale(d, G_re, G_im, (long long)ldg, st->maxbits, st->max_sweeps, s));
+    // whether the first sweep may run as one persistent launch
+    if (st->loop_cand) HIPCHK(launch_loop_check(d, st->colsq, s));
     // V = I: the same in either layout, nothing logged, the scalars current,
     // no step keys (k starts again from 0)
     HIPCHK(hipMemsetAsync(st->vkey, 0, sizeof(unsigned long long) * kVlogSlots, s));
@@ -515,6 +560,63 @@ extern "C" int jsvd_step(jsvd_state st, void *stream)
 
 static int sweep_steps(int n) { return n + (n & 1) - 1; }
 
+static hipError_t loop_check(jsvd_state st, hipStream_t s)
+{
+    return st->fp32 ? launch_loop_check(st->df, st->colsq, s) : launch_loop_check(st->d, st->colsq, s);
+}
+
+// The sweep of this state may run as one persistent launch: a state with
+// the loop's workspace on the one-wavefront-per-pair path (automatic launch
+// shape) whose pair slots are all resident at once.
+static bool loop_usable(jsvd_state st)
+{
+    if (!st->loop_cand || st->threads != 0 || uses_gpair(st) || st->loop.budget == 0) return false;
+    return st->fp32 ? loop_fits(st->df, st->ncu) : loop_fits(st->d, st->ncu);
+}
+
+// Capture a persistent sweep: the snapshot of G, V, e and f it can be redone
+// from, the sweep with its fold, the check for the sweep after it, and the
+// end-of-sweep bookkeeping (which skips a sweep that gave up).
+static int build_loop_graph(jsvd_state st)
+{
+    if (st->loop_graph && st->loop_graph_flags == st->flags && st->loop_graph_budget == st->loop.budget) return JSVD_OK;
+    if (st->loop_graph) {
+        (void)hipGraphExecDestroy(st->loop_graph);
+        st->loop_graph = nullptr;
+    }
+    if (st->loop_graph_def) {
+        (void)hipGraphDestroy(st->loop_graph_def);
+        st->loop_graph_def = nullptr;
+    }
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return JSVD_EDEVICE;
+    int rc = JSVD_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        rc = JSVD_EDEVICE;
+    } else {
+        char *gbase = st->fp32 ? (char *)st->df.Gr : (char *)st->d.Gr;
+        if (hipMemcpyAsync(st->snap, gbase, st->snap_bytes, hipMemcpyDeviceToDevice, cs) != hipSuccess ||
+            (st->fp32 ? launch_loop_sweep(st->df, st->loop, cs) : launch_loop_sweep(st->d, st->loop, cs)) !=
+                hipSuccess ||
+            loop_check(st, cs) != hipSuccess || launch_sweep_end(st->sc, cs) != hipSuccess)
+            rc = JSVD_EDEVICE;
+        if (hipStreamEndCapture(cs, &g) != hipSuccess && rc == JSVD_OK) rc = JSVD_EDEVICE;
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc == JSVD_OK && (!g || hipGraphInstantiate(&st->loop_graph, g, nullptr, nullptr, 0) != hipSuccess))
+        rc = JSVD_EDEVICE;
+    if (rc != JSVD_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        st->loop_graph = nullptr;
+        return rc;
+    }
+    st->loop_graph_def = g;
+    st->loop_graph_flags = st->flags;
+    st->loop_graph_budget = st->loop.budget;
+    return JSVD_OK;
+}
+
 // Capture the K steps of a sweep, the update of V from the steps still
 // logged, and the end-of-sweep bookkeeping.  The log is empty when the
 // capture starts and when the graph ends.  On the large-column path each
@@ -530,6 +632,8 @@ static int capture_sweep(jsvd_state st, hipStream_t cs, hipStream_t vs, std::vec
         for (int k = 0; k < K; ++k)
             if (launch_one_step(st, cs) != hipSuccess) return JSVD_EDEVICE;
         if (flush_vlog(st, cs) != hipSuccess || settle(st, cs) != hipSuccess) return JSVD_EDEVICE;
+        // whether the next sweep may run as one persistent launch
+        if (st->loop_cand && loop_check(st, cs) != hipSuccess) return JSVD_EDEVICE;
         return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
     }
     auto event = [&](hipEvent_t *e) {
@@ -700,6 +804,8 @@ extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
     out->last_sweep_swaps = h.SW_prev;
     out->gs = h.GS;
     out->last_sweep_gs = h.GS_prev;
+    out->loop_sweeps = h.loop_sweeps;
+    out->loop_redos = st->loop_redos;
     return JSVD_OK;
 }
 
@@ -768,6 +874,9 @@ static int restore_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, co
     st->vlog_n = 0;
     st->vlast = -1;
     st->v_layout = V_COLS;
+    // the pushed scalars start the persistent sweeps' flag epochs again at 0,
+    // so the flags are cleared with them
+    if (st->loop_cand) HIPCHK(hipMemsetAsync(st->loop.ver, 0, sizeof(unsigned long long) * (size_t)st->n, s));
     DevScalars h;
     memset(&h, 0, sizeof(h));
     h.Mt_bits = dbits(Mt);
@@ -816,19 +925,71 @@ extern "C" int jsvd_state_finalize_f32(jsvd_state st, float *U_re, float *U_im, 
 
 // ---------------------------------------------------------------------------
 // the whole SVD
+// Sweeps on a loaded state until it stops (converged, or the sweep limit),
+// one graph launch per sweep, synchronising after each: the device decides
+// convergence.  Where the device has found that no rescaling can happen in
+// the next sweep, the sweep runs as one persistent launch (loop.hip); one
+// that gives up is redone step by step from the snapshot taken before it.
+static int iterate(jsvd_state st, hipStream_t s)
+{
+    const bool loop = loop_usable(st);
+    HIPCHK(set_v_layout(st, path_layout(st), s));
+    HIPCHK(flush_vlog(st, s));
+    HIPCHK(settle(st, s));
+    HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    while (!st->host->stop) {
+        const bool as_loop = loop && st->host->loop_ok;
+        if (as_loop) {
+            const int rc = build_loop_graph(st);
+            if (rc != JSVD_OK) return rc;
+            HIPCHK(hipGraphLaunch(st->loop_graph, s));
+            HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        } else {
+            const int rc = state_sweep_async(st, s);
+            if (rc != JSVD_OK) return rc;
+        }
+        HIPCHK(hipStreamSynchronize(s));
+        if (as_loop && st->host->loop_redo) {
+            char *gbase = st->fp32 ? (char *)st->df.Gr : (char *)st->d.Gr;
+            HIPCHK(hipMemcpyAsync(gbase, st->snap, st->snap_bytes, hipMemcpyDeviceToDevice, s));
+            HIPCHK(launch_loop_clear(st->sc, s));
+            const int rc = state_sweep_async(st, s);
+            if (rc != JSVD_OK) return rc;
+            HIPCHK(hipStreamSynchronize(s));
+            st->loop_redos++;
+        }
+    }
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_set_loop_wait(jsvd_state st, double seconds)
+{
+    if (!st || !(seconds >= 0.0 && seconds <= 60.0)) return JSVD_EINVAL;
+    if (!st->loop_cand) return JSVD_OK;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, st->device) != hipSuccess || khz <= 0)
+        khz = 100000;
+    const double ticks = seconds * 1e3 * khz;
+    // a positive wait of less than one tick still allows persistent sweeps
+    st->loop.budget = seconds == 0.0 ? 0ull : (ticks < 1.0 ? 1ull : (unsigned long long)ticks);
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_iterate(jsvd_state st, void *stream)
+{
+    if (!st) return JSVD_EINVAL;
+    return iterate(st, (hipStream_t)stream);
+}
+
 template <typename T>
 static int gesvj_on_state(jsvd_state st, T *G_re, T *G_im, size_t ldg, T *V_re, T *V_im, size_t ldv, T *sv_e,
                           T *sv_f, T *sv, int *sweeps, hipStream_t s)
 {
     int rc = load_async_t<T>(st, G_re, G_im, ldg, s);
     if (rc != JSVD_OK) return rc;
-    // one graph-launched sweep at a time; the device decides convergence
-    for (;;) {
-        rc = state_sweep_async(st, s);
-        if (rc != JSVD_OK) return rc;
-        HIPCHK(hipStreamSynchronize(s));
-        if (st->host->stop) break;
-    }
+    rc = iterate(st, s);
+    if (rc != JSVD_OK) return rc;
     const DevScalars h = *st->host;
     if (sweeps) *sweeps = (int)h.C;
     if (h.status != 0) return h.status;

@@ -53,6 +53,10 @@ struct DevScalars {
     int stop;                     // set when converged or the sweep limit is reached
     int max_sweeps;
     int status;                   // init status: 0, or -2 (non-finite), -3 (zero)
+    int loop_ok;                  // the next sweep may run as one persistent launch (loop.hip)
+    int loop_epoch;               // persistent sweeps launched (tags the column flags)
+    int loop_redo;                // the last persistent sweep gave up: redo it step by step
+    long long loop_sweeps;        // sweeps completed as persistent launches
 };
 
 // Problem description shared by the SVD kernels, for the working precision T
@@ -160,6 +164,32 @@ int step_max_rows(int cplx, int W);
 int step_auto_threads(int m, int n);
 // end-of-sweep bookkeeping (1 thread)
 hipError_t launch_sweep_end(DevScalars *sc, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// a whole sweep in one persistent launch (loop.hip), for m <= 256
+struct LoopAcc {                  // one workgroup's share of the sweep's fold
+    long long t, sw, gs, tlast;   // transformations, swaps, Gram-Schmidt steps, transformations of the last step
+    double M;                     // max-norm of the transformed columns
+    int done;                     // steps completed (K unless the launch gave up)
+    int pad;
+};
+struct LoopArgs {
+    unsigned long long *ver;      // per column: (epoch << 32) | the step offset it is ready for
+    LoopAcc *acc;                 // per workgroup
+    unsigned *abort;              // raised by a workgroup whose wait ran out of budget
+    unsigned long long budget;    // wall-clock ticks a workgroup may wait for one column
+};
+// the persistent sweep applies to this state (m <= 256, every pair slot resident at once)
+template <typename T>
+bool loop_fits(const SvdDescT<T> &d, int ncu);
+// the persistent sweep and its fold into the device scalars
+template <typename T>
+hipError_t launch_loop_sweep(const SvdDescT<T> &d, const LoopArgs &a, hipStream_t s);
+// loop_ok for the next sweep: no rescaling can happen in it (column sums of
+// squares into colsq, n doubles)
+template <typename T>
+hipError_t launch_loop_check(const SvdDescT<T> &d, double *colsq, hipStream_t s);
+hipError_t launch_loop_clear(DevScalars *sc, hipStream_t s);
 // finalisation: norms of all columns into d.e/d.f, their descending ranks,
 // then U = G diag(2^-e)/f and V permuted into the caller's buffers
 template <typename T>

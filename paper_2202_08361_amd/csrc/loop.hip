@@ -1,0 +1,435 @@
+// loop.hip -- a whole sweep of the one-sided Jacobi SVD (Alg. zvjsvd: K
+// round-robin steps) in one persistent launch, for states on the
+// one-wavefront-per-pair path (m <= 256).
+//
+// One workgroup per pair slot l (n/2 of them, all resident at once) runs the
+// K steps of the sweep.  In the circle method a column of step k + 1 comes
+// from slot l - 1, l or l + 1 of step k, so there is no need for a barrier
+// between steps: each column carries a flag, the step it is ready for, and a
+// workgroup starts its pair of step k as soon as both of its columns are
+// ready (agent-scope acquire), then publishes them for step k + 1
+// (agent-scope release).  The pair's arithmetic is that of the fused step
+// kernel (pair_core, transform_regs, rot_regs), so the sweep gives the same
+// bits as K steps.
+//
+// What a step needs from all pairs of the step before is M~, for the
+// rescaling check of Sect. 3.2.  The launch is used only when no rescaling
+// can happen in the sweep: every component of G stays below ||G||_F, the
+// rotations change ||G||_F by a factor within 1 + 16 eps per step, and a
+// bound B >= (1 + 32 eps K) ||G_k0||_F is computed before the sweep
+// (frob_cols_kernel, loop_check_kernel).  If max(M~_k0, B) < 2^(round + 1)
+// then M~ stays below the threshold for the whole sweep and every check
+// says "no rescaling", exactly as the steps would decide it.  Otherwise
+// the caller runs the sweep step by step.
+//
+// Every wait is bounded (a wall-clock budget); a workgroup that runs out of
+// it raises an abort flag that every other one sees, so the launch always
+// ends.  The counts and the max-norm are kept per workgroup and folded once
+// at the end (loop_fold_kernel): integer sums and an exact max, so the
+// order does not matter.  An aborted sweep is marked for a redo from the
+// snapshot taken before it.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "evd2_core.hpp"
+#include "kernels.hpp"
+#include "pair.hpp"
+
+namespace jsvd {
+
+// wait until column c is ready for step offset `want` (flag >= want), then
+// acquire; false on abort or when the budget runs out
+__device__ __forceinline__ bool loop_wait(const LoopArgs &a, int c, unsigned long long want)
+{
+    unsigned long long v = __hip_atomic_load(a.ver + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v < want) {
+        const unsigned long long t0 = wall_clock64();
+        for (unsigned it = 1;; ++it) {
+            __builtin_amdgcn_s_sleep(2);
+            v = __hip_atomic_load(a.ver + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v >= want) break;
+            if (wall_clock64() - t0 >= a.budget) {
+                __hip_atomic_store(a.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                return false;
+            }
+            if ((it & 7) == 0 && __hip_atomic_load(a.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+                return false;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+// a store that is coherent at agent scope (relaxed atomic)
+template <typename T>
+__device__ __forceinline__ void coherent_store(T *p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// publish columns p and q (q < 0: p only) as ready for step offset `val`,
+// after everything this wavefront wrote before
+__device__ __forceinline__ void loop_publish(const LoopArgs &a, int p, int q, unsigned long long val)
+{
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(a.ver + p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (q >= 0) __hip_atomic_store(a.ver + q, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <bool CPLX, int R, bool COMP, typename T>
+__global__ __launch_bounds__(64) void loop_kernel(SvdDescT<T> d, LoopArgs a)
+{
+    constexpr int W = 64;
+    const int t = threadIdx.x;
+    const int l = blockIdx.x;
+    DevScalars *sc = d.sc;
+    LoopAcc acc;
+    acc.t = acc.sw = acc.gs = acc.tlast = 0;
+    acc.M = 0.0;
+    acc.done = 0;
+    // the scalars do not change during the launch: every workgroup reads the same
+    if (sc->stop) {
+        if (t == 0) a.acc[l] = acc;
+        return;
+    }
+    const int m = d.m, n = d.n;
+    const int N = n + (n & 1), K = N - 1;
+    const long long k0 = sc->k;
+    const unsigned long long epoch = (unsigned long long)(unsigned)sc->loop_epoch << 32;
+    T Mrun = T(0);
+    int steps = 0;
+    for (int j = 0; j < K; ++j) {
+        const long long k = k0 + j;
+        int p, q;
+        const bool valid = rr_pair(n, k, l, &p, &q);
+        // the columns of step offset 0 are current from the launch boundary
+        if (j > 0 && (!loop_wait(a, p, epoch | (unsigned)j) || (valid && !loop_wait(a, q, epoch | (unsigned)j))))
+            break;
+        if (!valid) {
+            // the column sitting out this step (odd n): nothing to compute
+            loop_publish(a, p, -1, epoch | (unsigned)(j + 1));
+            ++steps;
+            continue;
+        }
+        T *const Gpr = d.Gr + (size_t)p * d.ldg;
+        T *const Gqr = d.Gr + (size_t)q * d.ldg;
+        T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
+        T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
+        T *const Vpr = d.Vr + (size_t)p * d.ldv;
+        T *const Vqr = d.Vr + (size_t)q * d.ldv;
+        T *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
+        T *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
+        T xr[2][R], xi[2][R], vr[2][R], vi[2][R];
+#pragma unroll
+        for (int jj = 0; jj < R; ++jj) {
+            const int i = t + W * jj;
+            const bool in = i < m, inv = i < n;
+            xr[0][jj] = in ? Gpr[i] : T(0);
+            xr[1][jj] = in ? Gqr[i] : T(0);
+            vr[0][jj] = inv ? Vpr[i] : T(0);
+            vr[1][jj] = inv ? Vqr[i] : T(0);
+            if (CPLX) {
+                xi[0][jj] = in ? Gpi[i] : T(0);
+                xi[1][jj] = in ? Gqi[i] : T(0);
+                vi[0][jj] = inv ? Vpi[i] : T(0);
+                vi[1][jj] = inv ? Vqi[i] : T(0);
+            }
+        }
+        // no rescaling in this sweep (checked before the launch)
+        const PairDecisionT<T> dc =
+            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, (T *)nullptr, (T *)nullptr, (T *)nullptr);
+        const int pbit = dc.pbit;
+        T *const Dp_r = pbit ? Gqr : Gpr;
+        T *const Dq_r = pbit ? Gpr : Gqr;
+        T *const Dp_i = pbit ? Gqi : Gpi;
+        T *const Dq_i = pbit ? Gpi : Gqi;
+        T *const Ep_r = pbit ? Vqr : Vpr;
+        T *const Eq_r = pbit ? Vpr : Vqr;
+        T *const Ep_i = pbit ? Vqi : Vpi;
+        T *const Eq_i = pbit ? Vpi : Vqi;
+        if (dc.transform) {
+            T Mx = transform_regs<CPLX, R>(xr, xi, dc);
+            (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
+            Mx = wave_max(Mx);
+            Mrun = fmax(Mrun, Mx);
+            ++acc.t;
+            if (dc.gs) ++acc.gs;
+            if (j == K - 1) acc.tlast = 1;
+        } else if (pbit) {
+            ++acc.sw;
+        }
+        if (dc.transform || pbit) {
+            // agent-coherent stores: the release below then has fewer dirty
+            // L2 lines to write back (measured 6.9 -> 5.5 us per 256 x 256
+            // real step); ordering still comes from the release / acquire
+#pragma unroll
+            for (int jj = 0; jj < R; ++jj) {
+                const int i = t + W * jj;
+                if (i < m) {
+                    coherent_store(Dp_r + i, xr[0][jj]);
+                    coherent_store(Dq_r + i, xr[1][jj]);
+                    if (CPLX) {
+                        coherent_store(Dp_i + i, xi[0][jj]);
+                        coherent_store(Dq_i + i, xi[1][jj]);
+                    }
+                }
+                if (i < n) {
+                    coherent_store(Ep_r + i, vr[0][jj]);
+                    coherent_store(Eq_r + i, vr[1][jj]);
+                    if (CPLX) {
+                        coherent_store(Ep_i + i, vi[0][jj]);
+                        coherent_store(Eq_i + i, vi[1][jj]);
+                    }
+                }
+            }
+        }
+        if (t == 0) {
+            const NormT<T> np_ = dc.np, nq_ = dc.nq;
+            const int dp = pbit ? q : p, dq = pbit ? p : q;
+            d.e[dp] = np_.zero ? T(-INFINITY) : (T)np_.e;
+            d.f[dp] = np_.zero ? T(1) : np_.f;
+            d.e[dq] = nq_.zero ? T(-INFINITY) : (T)nq_.e;
+            d.f[dq] = nq_.zero ? T(1) : nq_.f;
+        }
+        loop_publish(a, p, q, epoch | (unsigned)(j + 1));
+        ++steps;
+    }
+    if (t == 0) {
+        acc.M = (double)Mrun;
+        acc.done = steps;
+        a.acc[l] = acc;
+    }
+}
+
+// The end of a persistent sweep: the counts and the max-norm of all
+// workgroups folded into the device scalars as the K step folds would have
+// done it (no rescaling happened), the step index advanced by K, the flag
+// epoch advanced.  An aborted sweep (some workgroup ran out of its wait
+// budget) changes no scalar but the redo mark.  One workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs a, int npairs, int K)
+{
+    __shared__ double sM[4];
+    __shared__ long long sc4[4][5];
+    DevScalars *sc = d.sc;
+    if (sc->stop) return;
+    const int t = threadIdx.x;
+    double M = 0.0;
+    long long tt = 0, sw = 0, gg = 0, tl = 0, short_ = 0;
+    for (int l = t; l < npairs; l += 256) {
+        const LoopAcc x = a.acc[l];
+        M = fmax(M, x.M);
+        tt += x.t;
+        sw += x.sw;
+        gg += x.gs;
+        tl += x.tlast;
+        short_ += (x.done != K) ? 1 : 0;
+    }
+    M = wave_max(M);
+#pragma unroll
+    for (int h = 32; h >= 1; h >>= 1) {
+        tt += __shfl_xor(tt, h, 64);
+        sw += __shfl_xor(sw, h, 64);
+        gg += __shfl_xor(gg, h, 64);
+        tl += __shfl_xor(tl, h, 64);
+        short_ += __shfl_xor(short_, h, 64);
+    }
+    if ((t & 63) == 0) {
+        sM[t >> 6] = M;
+        sc4[t >> 6][0] = tt;
+        sc4[t >> 6][1] = sw;
+        sc4[t >> 6][2] = gg;
+        sc4[t >> 6][3] = tl;
+        sc4[t >> 6][4] = short_;
+    }
+    __syncthreads();
+    if (t != 0) return;
+    for (int w = 1; w < 4; ++w) {
+        sM[0] = fmax(sM[0], sM[w]);
+        for (int c = 0; c < 5; ++c) sc4[0][c] += sc4[w][c];
+    }
+    const bool aborted = *a.abort != 0 || sc4[0][4] != 0;
+    *a.abort = 0;
+    sc->loop_epoch += 1;
+    if (aborted) {
+        sc->loop_redo = 1;
+        return;
+    }
+    const T Mt = (T)bits2d(sc->Mt_bits);
+    sc->Mt_bits = d2bits((double)fmax(Mt, (T)sM[0]));
+    sc->T += sc4[0][0];
+    sc->SW += sc4[0][1];
+    sc->GS += sc4[0][2];
+    sc->last_t = sc4[0][3];
+    sc->k += K;
+    sc->loop_sweeps += 1;
+}
+
+// Per column j: sum_i (g_ij 2^-E)^2 (both parts of a complex column), with
+// E = floor(lg M~): every component is at most M~, so each term is below 4.
+// One wavefront per column, lanes over rows, a fixed tree (the sum is used
+// as a bound only).
+template <bool CPLX, typename T>
+__global__ __launch_bounds__(64) void frob_cols_kernel(SvdDescT<T> d, double *colsq)
+{
+    const int j = blockIdx.x, t = threadIdx.x;
+    const double Mt = bits2d(d.sc->Mt_bits);
+    const int E = Mt > 0.0 ? getexp(Mt) : 0;
+    const T *gr = d.Gr + (size_t)j * d.ldg;
+    const T *gi = CPLX ? d.Gi + (size_t)j * d.ldg : nullptr;
+    double s = 0.0;
+    for (int i = t; i < d.m; i += 64) {
+        const double x = scal2((double)gr[i], -E);
+        s = fma(x, x, s);
+        if (CPLX) {
+            const double y = scal2((double)gi[i], -E);
+            s = fma(y, y, s);
+        }
+    }
+    s = wave_tree_sum(s);
+    if (t == 0) colsq[j] = s;
+}
+
+// loop_ok: max(M~, B) < 2^(round + 1) with B an upper bound of
+// (1 + 32 eps K) ||G||_F (rounding of the sums covered by the factors below,
+// underflowed squares by an absolute term).  One workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void loop_check_kernel(SvdDescT<T> d, const double *colsq)
+{
+    __shared__ double part[4];
+    DevScalars *sc = d.sc;
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int j = t; j < d.n; j += 256) s += colsq[j];
+    s = wave_tree_sum(s);
+    if ((t & 63) == 0) part[t >> 6] = s;
+    __syncthreads();
+    if (t != 0) return;
+    const double tot = ((part[0] + part[1]) + (part[2] + part[3])) * (1.0 + 0x1p-30) +
+                       (double)d.m * d.n * (d.cplx ? 2.0 : 1.0) * 0x1p-1000;
+    const double Mt = bits2d(sc->Mt_bits);
+    const int E = Mt > 0.0 ? getexp(Mt) : 0;
+    // ||G||_F grows by at most a factor 1 + 16 eps per step (the rotation
+    // with the computed parameters, Lemmas l:rt and l:ct, and the rounding
+    // of cos phi); over the K steps of a sweep by at most 1 + 32 eps K
+    const int K = d.n + (d.n & 1) - 1;
+    const double eps = sizeof(T) == sizeof(double) ? 0x1p-53 : 0x1p-24;
+    const double F = 1.0 + 32.0 * eps * K + 0x1p-30;
+    const double B = scal2(sqrt(tot) * F, E);
+    const double top = fmax(Mt, B);
+    // the check of Sect. 3.2 rescales iff floor(lg M~) > round, i.e. M~ >= 2^(round + 1)
+    const int round = d.cplx ? SvdFp<T>::round_cplx : SvdFp<T>::round_real;
+    sc->loop_ok = top < scal2(1.0, round + 1) ? 1 : 0;
+}
+
+__global__ void loop_clear_kernel(DevScalars *sc)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) sc->loop_redo = 0;
+}
+
+// ---------------------------------------------------------------------------
+template <bool CPLX, int R, bool COMP, typename T>
+static const void *loop_fn()
+{
+    return (const void *)loop_kernel<CPLX, R, COMP, T>;
+}
+
+template <typename T>
+static const void *loop_fn_of(const SvdDescT<T> &d, int R)
+{
+    if constexpr (sizeof(T) == sizeof(double)) {
+        if (d.comp) {
+            if (d.cplx)
+                return R <= 1 ? loop_fn<true, 1, true, T>() : R <= 2 ? loop_fn<true, 2, true, T>() : loop_fn<true, 4, true, T>();
+            return R <= 1 ? loop_fn<false, 1, true, T>() : R <= 2 ? loop_fn<false, 2, true, T>() : loop_fn<false, 4, true, T>();
+        }
+    } else {
+        if (d.comp) return nullptr;
+    }
+    if (d.cplx)
+        return R <= 1 ? loop_fn<true, 1, false, T>() : R <= 2 ? loop_fn<true, 2, false, T>() : loop_fn<true, 4, false, T>();
+    return R <= 1 ? loop_fn<false, 1, false, T>() : R <= 2 ? loop_fn<false, 2, false, T>() : loop_fn<false, 4, false, T>();
+}
+
+static int loop_rows(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 4; }
+
+template <typename T>
+bool loop_fits(const SvdDescT<T> &d, int ncu)
+{
+    if (d.m > 256) return false;
+    const void *fn = loop_fn_of(d, loop_rows(d.m));
+    if (!fn) return false;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1) return false;
+    const int npairs = (d.n + (d.n & 1)) / 2;
+    return (long long)per_cu * ncu >= npairs;
+}
+
+template <bool CPLX, int R, bool COMP, typename T>
+static void launch_loop_t(const SvdDescT<T> &d, const LoopArgs &a, int npairs, hipStream_t s)
+{
+    hipLaunchKernelGGL((loop_kernel<CPLX, R, COMP, T>), dim3(npairs), dim3(64), 0, s, d, a);
+}
+
+template <bool CPLX, bool COMP, typename T>
+static void launch_loop_r(const SvdDescT<T> &d, const LoopArgs &a, int npairs, hipStream_t s)
+{
+    const int R = loop_rows(d.m);
+    if (R <= 1) launch_loop_t<CPLX, 1, COMP, T>(d, a, npairs, s);
+    else if (R <= 2) launch_loop_t<CPLX, 2, COMP, T>(d, a, npairs, s);
+    else launch_loop_t<CPLX, 4, COMP, T>(d, a, npairs, s);
+}
+
+template <typename T>
+hipError_t launch_loop_sweep(const SvdDescT<T> &d, const LoopArgs &a, hipStream_t s)
+{
+    const int N = d.n + (d.n & 1), npairs = N / 2, K = N - 1;
+    if (d.m > 256) return hipErrorInvalidValue;
+    if (d.comp) {
+        if constexpr (sizeof(T) == sizeof(double)) {
+            if (d.cplx) launch_loop_r<true, true, T>(d, a, npairs, s);
+            else launch_loop_r<false, true, T>(d, a, npairs, s);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else {
+        if (d.cplx) launch_loop_r<true, false, T>(d, a, npairs, s);
+        else launch_loop_r<false, false, T>(d, a, npairs, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((loop_fold_kernel<T>), dim3(1), dim3(256), 0, s, d, a, npairs, K);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_loop_check(const SvdDescT<T> &d, double *colsq, hipStream_t s)
+{
+    if (d.cplx)
+        hipLaunchKernelGGL((frob_cols_kernel<true, T>), dim3(d.n), dim3(64), 0, s, d, colsq);
+    else
+        hipLaunchKernelGGL((frob_cols_kernel<false, T>), dim3(d.n), dim3(64), 0, s, d, colsq);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((loop_check_kernel<T>), dim3(1), dim3(256), 0, s, d, (const double *)colsq);
+    return hipGetLastError();
+}
+
+hipError_t launch_loop_clear(DevScalars *sc, hipStream_t s)
+{
+    hipLaunchKernelGGL(loop_clear_kernel, dim3(1), dim3(64), 0, s, sc);
+    return hipGetLastError();
+}
+
+template bool loop_fits<double>(const SvdDescT<double> &, int);
+template bool loop_fits<float>(const SvdDescT<float> &, int);
+template hipError_t launch_loop_sweep<double>(const SvdDescT<double> &, const LoopArgs &, hipStream_t);
+template hipError_t launch_loop_sweep<float>(const SvdDescT<float> &, const LoopArgs &, hipStream_t);
+template hipError_t launch_loop_check<double>(const SvdDescT<double> &, double *, hipStream_t);
+template hipError_t launch_loop_check<float>(const SvdDescT<float> &, double *, hipStream_t);
+
+} // namespace jsvd

@@ -38,6 +38,17 @@ struct jsvd_state_s {
     int graph_threads;
     unsigned flags;          // iteration flags (JSVD_PERMUTE, JSVD_COMPENSATED, JSVD_NO_GS)
     unsigned graph_flags;    // flags the captured sweep was built with
+    // whole sweeps as one persistent launch (loop.hip; states with m <= 256)
+    int loop_cand;           // the state has the loop's workspace (m <= 256)
+    jsvd::LoopArgs loop;     // column flags, per-workgroup folds, abort flag, wait budget
+    double *colsq;           // per-column sums of squares of the bound check
+    char *snap;              // G, V, e, f as they were before the last persistent sweep
+    size_t snap_bytes;
+    hipGraphExec_t loop_graph;
+    hipGraph_t loop_graph_def;
+    unsigned loop_graph_flags;
+    unsigned long long loop_graph_budget;
+    long long loop_redos;    // persistent sweeps that gave up and were redone step by step
 };
 
 namespace jsvd {

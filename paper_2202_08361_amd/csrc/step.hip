@@ -356,7 +356,8 @@ hipError_t launch_step(const SvdDescT<T> &d, int threads, StepSlot slot, StepSlo
 __global__ void sweep_end_kernel(DevScalars *sc)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    if (sc->stop) return;
+    // a persistent sweep that gave up is redone step by step; it does not count
+    if (sc->stop || sc->loop_redo) return;
     sc->sweeps += 1;
     if (sc->T == 0 && sc->SW == 0) {
         sc->converged = 1;
@@ -418,6 +419,11 @@ __global__ void init_scalars_kernel(SvdDescT<T> d, const unsigned long long *max
     sc->rescaled = 0;
     sc->converged = 0;
     sc->max_sweeps = max_sweeps;
+    // (loop_epoch keeps counting across loads: it tags the column flags of
+    // the persistent sweeps, which are never cleared)
+    sc->loop_ok = 0;
+    sc->loop_redo = 0;
+    sc->loop_sweeps = 0;
     if (!(M0 < T(INFINITY)) || M0 == T(0)) {
         sc->status = (M0 == T(0)) ? -3 : -2;
         sc->stop = 1;
