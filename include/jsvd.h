@@ -157,8 +157,13 @@ typedef struct {
     int64_t loop_redos;       /* persistent sweeps that gave up and were redone step by step */
 } jsvd_info;
 
-/* Allocate a state for an m x n real (is_complex = 0) or complex problem.
- * Returns JSVD_EINVAL for m < n, n < 1, JSVD_ENOMEM when out of memory. */
+/* Allocate a state for an m x n real (is_complex = 0) or complex problem,
+ * m <= 2^24.  Columns of more than 16384 (real) / 8192 (complex) rows, which
+ * no workgroup holds in registers, are streamed from memory by the step: the
+ * pair is read three times (max, sums of squares, dot-product) and read and
+ * written once, with the same sums in the same lane order, so the results
+ * are the same bits as the oracle's.  Returns JSVD_EINVAL for m < n, n < 1,
+ * m > 2^24, JSVD_ENOMEM when out of memory. */
 int jsvd_state_create(int m, int n, int is_complex, jsvd_state *out);
 void jsvd_state_destroy(jsvd_state st);
 

@@ -212,7 +212,7 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
     if (!out) return JSVD_EINVAL;
     *out = nullptr;
     if (n < 1 || m < n) return JSVD_EINVAL;
-    if (m > step_max_rows(is_complex != 0, 1024)) return JSVD_EINVAL;
+    if (m > state_max_rows()) return JSVD_EINVAL;
     jsvd_state st = new (std::nothrow) jsvd_state_s;
     if (!st) return JSVD_ENOMEM;
     memset(st, 0, sizeof(*st));

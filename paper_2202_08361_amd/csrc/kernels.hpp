@@ -161,6 +161,11 @@ hipError_t launch_zero_u64(unsigned long long *p, hipStream_t s);
 template <typename T>
 hipError_t launch_step(const SvdDescT<T> &d, int threads, StepSlot slot, StepSlot prev, hipStream_t s);
 int step_max_rows(int cplx, int W);
+// rows of a state: beyond step_max_rows(cplx, 1024) the step streams the
+// pair from memory (sstep.hip)
+int state_max_rows();
+template <typename T>
+hipError_t launch_stream_step(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, hipStream_t s);
 int step_auto_threads(int m, int n);
 // end-of-sweep bookkeeping (1 thread)
 hipError_t launch_sweep_end(DevScalars *sc, hipStream_t s);

@@ -470,6 +470,55 @@ struct PairDecisionT {
 };
 using PairDecision = PairDecisionT<double>;
 
+// The decision for a pair from its norms (zero flags set) and, when neither
+// column is zero, the scaled dot-product without its final division (h):
+// a21' (Alg. zdpscl's division), the convergence test (Alg. cvg), the
+// scaled Gram matrix (Alg. Gram), its EVD, and the Gram-Schmidt choice of
+// eq. (GScond).  Every thread computes the same decision.
+template <bool CPLX, typename T>
+__device__ __forceinline__ PairDecisionT<T> pair_decide(const NormT<T> &np, const NormT<T> &nq, const T (&h)[2], T ups,
+                                                       int nosort, int nogs)
+{
+    PairDecisionT<T> o;
+    o.np = np;
+    o.nq = nq;
+    o.transform = false;
+    o.gs = 0;
+    o.c = T(1);
+    o.C = T(0);
+    o.S = T(0);
+    o.zr = T(0);
+    o.zi = T(0);
+    if (np.zero || nq.zero) {
+        // a zero column is never rotated; it goes after the other one
+        o.pbit = (np.zero && !nq.zero) ? 1 : 0;
+    } else {
+        const T dd = o.nq.f * o.np.f;
+        const T zr = h[0] / dd;
+        const T zi = CPLX ? h[1] / dd : T(0);
+        const T az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
+        o.transform = ups <= az;
+        T a11, a22, a21r, a21i;
+        gram_scaled(zr, zi, o.np.e, o.np.f, o.nq.e, o.nq.f, &a11, &a22, &a21r, &a21i);
+        const Evd2OutT<T> e = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
+        o.c = e.c;
+        o.C = e.C;
+        o.S = e.S;
+        o.pbit = e.p;
+        o.zr = zr;
+        o.zi = zi;
+        if (o.transform && !nogs) {
+            if (gs_exceeds(o.np.e, o.np.f, o.nq.e, o.nq.f, ups))
+                o.gs = 1;
+            else if (gs_exceeds(o.nq.e, o.nq.f, o.np.e, o.np.f, ups))
+                o.gs = 2;
+            if (o.gs) o.pbit = (o.gs == 2) ? 1 : 0;
+        }
+    }
+    if (nosort) o.pbit = 0;
+    return o;
+}
+
 // Norms (Sect. 3.2), scaled dot-product (Alg. zdpscl, or zdpsclcs /
 // ddpsclcs with COMP), convergence test (Alg. cvg), scaled Gram matrix
 // (Alg. Gram) and 2x2 EVD (Listing 1) of the pair (xr/xi[0] = column p,
@@ -486,7 +535,6 @@ __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const
 {
     using LS = LaneShape<W, R>;
     constexpr int V = LS::V, NL = LS::NL, CH = LS::CH;
-    PairDecisionT<T> o;
     T mx[2] = {T(0), T(0)};
 #pragma unroll
     for (int j = 0; j < R; ++j)
@@ -525,47 +573,13 @@ __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
     group_tree_sum<W, NQ>(s, red_norm);
-    o.np = norm_from_sums(Ep, s[0], CPLX ? s[2] : T(0), CPLX);
-    o.nq = norm_from_sums(Eq, s[1], CPLX ? s[3] : T(0), CPLX);
-    o.np.zero = zp_;
-    o.nq.zero = zq_;
-    o.transform = false;
-    o.gs = 0;
-    o.c = T(1);
-    o.C = T(0);
-    o.S = T(0);
-    o.zr = T(0);
-    o.zi = T(0);
-    if (zp_ || zq_) {
-        // a zero column is never rotated; it goes after the other one
-        o.pbit = (zp_ && !zq_) ? 1 : 0;
-    } else {
-        T h[2];
-        pair_dot<CPLX, W, R, COMP>(xr, xi, o.np.e, o.nq.e, h, red_dot);
-        const T dd = o.nq.f * o.np.f;
-        const T zr = h[0] / dd;
-        const T zi = CPLX ? h[1] / dd : T(0);
-        const T az = CPLX ? hypot_naive(zr, zi) : fabs(zr);
-        o.transform = ups <= az;
-        T a11, a22, a21r, a21i;
-        gram_scaled(zr, zi, o.np.e, o.np.f, o.nq.e, o.nq.f, &a11, &a22, &a21r, &a21i);
-        const Evd2OutT<T> e = CPLX ? evd2_cplx<false>(a11, a22, a21r, a21i) : evd2_real<false>(a11, a22, a21r);
-        o.c = e.c;
-        o.C = e.C;
-        o.S = e.S;
-        o.pbit = e.p;
-        o.zr = zr;
-        o.zi = zi;
-        if (o.transform && !nogs) {
-            if (gs_exceeds(o.np.e, o.np.f, o.nq.e, o.nq.f, ups))
-                o.gs = 1;
-            else if (gs_exceeds(o.nq.e, o.nq.f, o.np.e, o.np.f, ups))
-                o.gs = 2;
-            if (o.gs) o.pbit = (o.gs == 2) ? 1 : 0;
-        }
-    }
-    if (nosort) o.pbit = 0;
-    return o;
+    NormT<T> np = norm_from_sums(Ep, s[0], CPLX ? s[2] : T(0), CPLX);
+    NormT<T> nq = norm_from_sums(Eq, s[1], CPLX ? s[3] : T(0), CPLX);
+    np.zero = zp_;
+    nq.zero = zq_;
+    T h[2] = {T(0), T(0)};
+    if (!zp_ && !zq_) pair_dot<CPLX, W, R, COMP>(xr, xi, np.e, nq.e, h, red_dot);
+    return pair_decide<CPLX>(np, nq, h, ups, nosort, nogs);
 }
 
 // The transformation of a register pair that pair_core decided on: the

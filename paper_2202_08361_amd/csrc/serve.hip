@@ -476,7 +476,7 @@ extern "C" int jsvd_serve_submit(jsvd_server sv, const jsvd_request *req, uint64
         return JSVD_EINVAL;
     if (r.is_complex && (!r.G_im || !r.V_im)) return JSVD_EINVAL;
     const bool small = batch_rows(r.m, r.n, r.is_complex != 0) != 0;
-    if (!small && r.m > step_max_rows(r.is_complex != 0, 1024)) return JSVD_EINVAL;
+    if (!small && r.m > state_max_rows()) return JSVD_EINVAL;
     const size_t fp = footprint_of(r, small);
     if (fp > sv->cfg.hbm_budget_bytes) return JSVD_EINVAL;   // could never be admitted
     std::lock_guard<std::mutex> lk(sv->mu);

@@ -317,6 +317,8 @@ static hipError_t launch_step_w(const SvdDescT<T> &d, const StepSlot &slot, cons
 // largest supported m for a workgroup size
 int step_max_rows(int cplx, int W) { return W * ((!cplx && W == 1024) ? 16 : 8); }
 
+int state_max_rows() { return 1 << 24; }
+
 int step_auto_threads(int m, int n)
 {
     (void)n;
@@ -329,6 +331,9 @@ int step_auto_threads(int m, int n)
 template <typename T>
 hipError_t launch_step(const SvdDescT<T> &d, int threads, StepSlot slot, StepSlot prev, hipStream_t s)
 {
+    // columns longer than the register tile of the largest workgroup: the
+    // pair is streamed from memory (sstep.hip)
+    if (d.m > step_max_rows(d.cplx, 1024)) return launch_stream_step(d, slot, prev, s);
     if (threads <= 0) threads = step_auto_threads(d.m, d.n);
     if (d.m > step_max_rows(d.cplx, threads)) return hipErrorInvalidValue;
     if (d.cplx) {

@@ -47,11 +47,11 @@ def test_host_only_calls():
     h = ctypes.c_void_p()
     assert L.jsvd_state_create(3, 5, 0, ctypes.byref(h)) == J.EINVAL      # m < n
     assert L.jsvd_state_create(5, 0, 0, ctypes.byref(h)) == J.EINVAL      # n < 1
-    assert L.jsvd_state_create(20000, 5, 1, ctypes.byref(h)) == J.EINVAL  # beyond the register tile
+    assert L.jsvd_state_create((1 << 24) + 1, 5, 1, ctypes.byref(h)) == J.EINVAL  # beyond 2^24 rows
     assert L.jsvd_evd2_batched(10, None, None, None, None, None, None, None, None, None, None, 0, None) == J.EINVAL
     assert L.jsvd_gesvj(3, 4, None, None, 3, None, None, 4, None, None, None, 0, None, 0, None) == J.EINVAL
     assert L.jsvd_state_create_f32(3, 5, 0, ctypes.byref(h)) == J.EINVAL  # m < n
-    assert L.jsvd_state_create_f32(20000, 5, 0, ctypes.byref(h)) == J.EINVAL
+    assert L.jsvd_state_create_f32((1 << 24) + 1, 5, 0, ctypes.byref(h)) == J.EINVAL
     assert L.jsvd_gesvj_f32(3, 4, None, None, 3, None, None, 4, None, None, None, 0, None, 0, None) == J.EINVAL
     # the compensated dot-products are double precision only (rejected before any device call)
     p = ctypes.c_void_p(256)
