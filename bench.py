@@ -140,12 +140,11 @@ def counters_table(fetch_db, write_db, calib_mib, last_of=None):
             for nm in acc:
                 if last_of in nm:
                     acc[nm] = acc[nm][-1:]
-    cf = [v for nm, vs in fk.items() if "copyBuffer" in nm for v in vs]
-    cw = [v for nm, vs in wk.items() if "copyBuffer" in nm for v in vs]
+    # the calibration copy is the run's first plain device copy
+    cf = [v for nm, v in fetch if "copyBuffer" in nm][:1]
+    cw = [v for nm, v in write if "copyBuffer" in nm][:1]
     if not cf or not cw:
         raise SystemExit("no plain copy in the counter databases (run with --calib-copy)")
-    # the calibration copy is the largest plain copy of the run
-    cf, cw = [max(cf)], [max(cw)]
     f_scale, w_scale = moved / cf[-1], moved / cw[-1]
     out = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled MB per dispatch |", "|---|---|---|---|---|"]
     for nm in sorted(fk, key=lambda n: -sum(fk[n]) * f_scale - sum(wk.get(n, [0.0])) * w_scale):
@@ -168,13 +167,16 @@ def traffic_from(fetch_db, write_db, calib_mib, r=1 << 26):
     fetch, write = _rocpd_rows(fetch_db, q), _rocpd_rows(write_db, q)
     moved = calib_mib * 1024.0   # KiB read and written by the copy
 
-    def pick(rows, key):
+    def pick(rows, key, first=False):
         vals = [v for (nm, g, v) in rows if key in nm]
         if not vals:
             raise SystemExit(f"no dispatch of {key} in the counter database")
-        return vals[-1]
-    f_scale = moved / pick(fetch, "copyBuffer")
-    w_scale = moved / pick(write, "copyBuffer")
+        return vals[0] if first else vals[-1]
+    # the calibration copy is the run's first plain device copy (it runs
+    # before anything else; later copies, such as the stream-ceiling
+    # reference, have other sizes)
+    f_scale = moved / pick(fetch, "copyBuffer", first=True)
+    w_scale = moved / pick(write, "copyBuffer", first=True)
     csrc = os.path.join(ROOT, "paper_2202_08361_amd", "csrc")
     src = open(os.path.join(csrc, "evd2.hip"), "rb").read() + open(os.path.join(csrc, "evd2_core.hpp"), "rb").read()
     rec = dict(kernel_sources_sha256=hashlib.sha256(src).hexdigest(), fetch_scale=f_scale, write_scale=w_scale,
@@ -187,7 +189,7 @@ def traffic_from(fetch_db, write_db, calib_mib, r=1 << 26):
         rec[kind] = dict(kernel=name, fetch_kib=fk, write_kib=wk, bytes=byts)
         md.append(f"| `{name}` | {fk:.1f} | {wk:.1f} | {byts:.4g} | {alg * r:.4g} |")
     md.append(f"\nCalibration: the plain device copy of {calib_mib} MiB reads as FETCH_SIZE "
-              f"{pick(fetch, 'copyBuffer'):.1f} KiB and WRITE_SIZE {pick(write, 'copyBuffer'):.1f} KiB; "
+              f"{pick(fetch, 'copyBuffer', True):.1f} KiB and WRITE_SIZE {pick(write, 'copyBuffer', True):.1f} KiB; "
               f"scale factors {f_scale:.4f} and {w_scale:.4f}.")
     return rec, "\n".join(md)
 
@@ -299,7 +301,7 @@ def evd_f32(torch, J, inputs, r, K, W):
 VLOG_STEPS = 32   # steps of the outcome log: V is updated once per this many large-column steps
 
 
-def step_roofline(torch, J, inputs, m, n, cplx, flags=0, fp32=False):
+def step_roofline(torch, J, inputs, m, n, cplx, flags=0, fp32=False, streamed=False):
     """Time the Jacobi step on a freshly loaded state (every pair transforms):
     one outcome log's worth of steps (VLOG_STEPS) after a first log as warm-up,
     so that the timed block holds exactly one update of V; fp32: the single
@@ -334,6 +336,14 @@ def step_roofline(torch, J, inputs, m, n, cplx, flags=0, fp32=False):
     # and written once per step, V read and written once per outcome log
     b_deferred = 2.0 * es * c * m * n * frac_tr + 2.0 * es * c * n * n / VLOG_STEPS
     st.close()
+    if streamed:
+        # columns longer than the register tile: each pair streamed from
+        # memory, G and V pairs updated in the same launch every step
+        return dict(m=m, n=n, complex=bool(cplx), dtype="f32" if fp32 else "f64", us_per_step=t * 1e6,
+                    transformed_per_step=tr, pairs=n // 2, bytes_per_step=b_step, achieved_GBs=b_step / t / 1e9,
+                    frac=b_step / t / 1e9 / HBM_PEAK_GBS,
+                    frac_unit="G and V pairs of every transformed pair read and written once per step "
+                              "(the kernel reads the G pair three more times for its sums)")
     return dict(m=m, n=n, complex=bool(cplx), dtype="f32" if fp32 else "f64", us_per_step=t * 1e6,
                 transformed_per_step=tr, pairs=n // 2, v_update_every=VLOG_STEPS,
                 bytes_per_step_g_and_v=b_step, GBs_g_and_v=b_step / t / 1e9,
@@ -916,6 +926,10 @@ def main():
         for (m, n, c) in big:
             tasks.append((f"step_{tag(m, n, c)}_f32",
                           lambda m=m, n=n, c=c: step_roofline(torch, J, inputs, m, n, c, fp32=True)))
+        # columns beyond the register tile (the streamed step)
+        for (m, n, c) in ((65536, 512, False), (32768, 512, True)):
+            tasks.append((f"step_{tag(m, n, c)}_streamed",
+                          lambda m=m, n=n, c=c: step_roofline(torch, J, inputs, m, n, c, streamed=True)))
         for (m, n, c) in big:
             tasks.append((f"nrmf_{tag(m, n, c)}", lambda m=m, n=n, c=c: nrmf_rate(torch, J, inputs, m, n, c)))
         for nm, fl in (("svd_real256_f32", 0), ("svd_real256_permute_f32", J.PERMUTE)):
