@@ -43,7 +43,7 @@ constexpr int kPW = 256;   // threads per pivot pair of the G kernel
 template <typename T, bool CPLX, int R, bool COMP>
 constexpr int gpair_wgs_per_cu()
 {
-    if (COMP) return 1;
+    if (COMP) return 2;
     if (sizeof(T) == sizeof(float) && !CPLX && R <= 32) return 4;
     return 2;
 }

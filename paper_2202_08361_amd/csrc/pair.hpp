@@ -236,6 +236,17 @@ __device__ __noinline__ double mul_rd_slow(double a, double b, double p)
     return -scal2((fr > 0.0 || lo > 0.0) ? f + 1.0 : f, -1074);
 }
 
+// RD(a b) by the fma test alone, and whether that test holds: the product's
+// magnitude is in [2^-960, max], or an operand is zero
+__device__ __forceinline__ double mul_rd_fast(double a, double b, bool &odd)
+{
+    const double p = a * b;
+    const double ap = fabs(p);
+    const double e = fma(a, b, -p);
+    odd |= !(ap >= 0x1p-960 && ap <= 1.79769313486231570815e308) && a != 0.0 && b != 0.0;
+    return e < 0.0 ? __longlong_as_double(__double_as_longlong(p) + (p > 0.0 ? -1 : 1)) : p;
+}
+
 __device__ __forceinline__ double mul_rd(double a, double b)
 {
     const double p = a * b;
@@ -268,6 +279,39 @@ __device__ __forceinline__ void cs_term(double x, double y, double &s, double &t
     const double c2 = fma(x, y, -c);
     two_sum(s, c + t, s, t);
     two_sum(s2, c2 + t2, s2, t2);
+}
+
+__device__ __forceinline__ void cs_term_fast(double x, double y, double &s, double &t, double &s2, double &t2,
+                                             bool &odd)
+{
+    const double c = mul_rd_fast(x, y, odd);
+    const double c2 = fma(x, y, -c);
+    two_sum(s, c + t, s, t);
+    two_sum(s2, c2 + t2, s2, t2);
+}
+
+// The compensated sums of one thread's NL lanes from its n rows in x
+// (x[0..3][j]: Re g_p, Re g_q, Im g_p, Im g_q of the thread's row j, lane j
+// mod V, in the row order of the lane), with the exact RD(x y): the rare
+// pass for products outside the fma test's range.  Out of line and over
+// memory, so that the register-resident first pass keeps its registers.
+template <bool CPLX>
+__device__ __noinline__ void cs_lanes_exact(const double *x, int n, int V, int NL, int ep, int eq, double *out)
+{
+    constexpr int NS = CPLX ? 2 : 1;
+    for (int i = 0; i < NS * 4 * NL; ++i) out[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const int v = j % V;
+        double *a0 = out + v, *a1 = out + (NS - 1) * 4 * NL + v;
+        const double gpr = scal2(x[j], -ep), gqr = scal2(x[n + j], -eq);
+        cs_term(gpr, gqr, a0[0], a0[NL], a0[2 * NL], a0[3 * NL]);
+        if (CPLX) {
+            const double gpi = scal2(x[2 * n + j], -ep), gqi = scal2(x[3 * n + j], -eq);
+            cs_term(gpi, gqi, a0[0], a0[NL], a0[2 * NL], a0[3 * NL]);
+            cs_term(gqr, gpi, a1[0], a1[NL], a1[2 * NL], a1[3 * NL]);
+            cs_term(-gqi, gpr, a1[0], a1[NL], a1[2 * NL], a1[3 * NL]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -426,6 +470,7 @@ __device__ __forceinline__ void pair_dot(const T (&xr)[2][R], const T (&xi)[2][R
             for (int u = 0; u < 4; ++u)
 #pragma unroll
                 for (int v = 0; v < NL; ++v) a[st][u][v] = 0.0;
+        bool odd = false;
 #pragma unroll
         for (int ch = 0; ch < CH; ++ch)
 #pragma unroll
@@ -433,15 +478,36 @@ __device__ __forceinline__ void pair_dot(const T (&xr)[2][R], const T (&xi)[2][R
                 const int j = ch * V + v;
                 if (j < R) {
                     const double gpr = scal2(xr[0][j], -ep), gqr = scal2(xr[1][j], -eq);
-                    cs_term(gpr, gqr, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v]);
+                    cs_term_fast(gpr, gqr, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v], odd);
                     if (CPLX) {
                         const double gpi = scal2(xi[0][j], -ep), gqi = scal2(xi[1][j], -eq);
-                        cs_term(gpi, gqi, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v]);
-                        cs_term(gqr, gpi, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v], a[NS - 1][3][v]);
-                        cs_term(-gqi, gpr, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v], a[NS - 1][3][v]);
+                        cs_term_fast(gpi, gqi, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v], odd);
+                        cs_term_fast(gqr, gpi, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v],
+                                     a[NS - 1][3][v], odd);
+                        cs_term_fast(-gqi, gpr, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v],
+                                     a[NS - 1][3][v], odd);
                     }
                 }
             }
+        if (odd) {
+            // a product outside the fma test's range: this thread's lanes
+            // again with the exact RD(x y), out of line
+            double x[4 * R], out[NS * 4 * NL];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                x[j] = xr[0][j];
+                x[R + j] = xr[1][j];
+                x[2 * R + j] = CPLX ? xi[0][j] : 0.0;
+                x[3 * R + j] = CPLX ? xi[1][j] : 0.0;
+            }
+            cs_lanes_exact<CPLX>(x, R, V, NL, ep, eq, out);
+#pragma unroll
+            for (int st = 0; st < NS; ++st)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < NL; ++v) a[st][u][v] = out[(st * 4 + u) * NL + v];
+        }
         double g[4 * NS];
 #pragma unroll
         for (int st = 0; st < NS; ++st)

@@ -156,6 +156,57 @@ def test_step_compensated_bitwise(ora, m, n, cplx, threads):
     _check_state(ost, st.save(), "sweep after set_flags(0)")
 
 
+def _graded(m, n, cplx, seed, span=1100.0):
+    """Rows scaled from 1 down to 2^-span: once the columns are scaled by their
+    norms, the products of the lower rows fall below 2^-960, into the
+    subnormal range and below it, where the rounded-down product is not
+    given by the fma test."""
+    g = inputs.rng(inputs.CFG_PLAIN_LARGE, seed)
+    Ar, Ai = inputs.random_columns(m, n, g, cplx)
+    sc = np.ldexp(1.0, -np.round(np.linspace(0.0, span, m)).astype(int))[:, None]
+    Ar = np.asfortranarray(Ar * sc)
+    Ai = np.asfortranarray(Ai * sc) if cplx else None
+    return Ar, Ai
+
+
+@pytest.mark.parametrize("m,n,cplx,threads", [(200, 40, True, 0), (1500, 32, False, 0), (2100, 20, True, 0),
+                                               (5000, 12, True, 0), (9000, 10, False, 0), (700, 16, True, 1024)])
+def test_step_compensated_graded_rows(ora, m, n, cplx, threads):
+    """Products outside the fma test's range in every pair: each kernel's
+    exact second pass over such a thread's rows, after every step."""
+    Ar, Ai = _graded(m, n, cplx, 990 + m)
+    ost = ora.State(Ar, Ai, compensated=True)
+    assert ost.init() == ora.OK
+    st = J().State(m, n, cplx)
+    st.set_flags(J().COMPENSATED)
+    if threads:
+        st.set_launch(threads)
+    assert st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None) == 0
+    for k in range(ora.rr_steps(n) + 2):
+        ost.step()
+        st.step()
+        _check_state(ost, st.save(), f"step {k} m={m} n={n} cplx={cplx}")
+
+
+@pytest.mark.parametrize("m,n,cplx", [(120, 90, True), (400, 64, False)])
+def test_gesvj_compensated_graded_rows(ora, m, n, cplx):
+    """Whole SVDs of graded matrices: persistent sweeps (m <= 256) or the
+    large-column steps, and the batched kernel, against the oracle."""
+    Ar, Ai = _graded(m, n, cplx, 995 + m, span=1000.0)
+    flags = J().COMPENSATED
+    ro = ora.gesvj(Ar, Ai, flags=flags)
+    rg = J().gesvj(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None, flags=flags)
+    rb = J().gesvj_batched([(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None)],
+                           flags=flags)[0]
+    torch.cuda.synchronize()
+    for r in (rg, rb):
+        assert r["status"] == ro["status"] and r["sweeps"] == ro["sweeps"], (r["sweeps"], ro["sweeps"])
+        for key in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+            if ro[key] is None:
+                continue
+            assert np.array_equal(_bits(r[key].cpu().numpy()), _bits(ro[key])), key
+
+
 @pytest.mark.parametrize("m,n,cplx,kappa", [(60, 33, True, 1e4), (129, 128, False, 1e8), (1100, 40, False, 1e3),
                                               (600, 48, True, 1e6)])
 def test_gesvj_compensated_bitwise(ora, m, n, cplx, kappa):
