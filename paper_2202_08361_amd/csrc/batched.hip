@@ -24,8 +24,10 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/jsvd.h"
@@ -33,6 +35,7 @@
 #include "batch.hpp"
 #include "kernels.hpp"
 #include "pair.hpp"
+#include "state.hpp"
 
 namespace jsvd {
 
@@ -728,13 +731,18 @@ static bool take_streams(int dev, int k, hipStream_t *out)
     return true;
 }
 
+static void give_streams(int dev, int k, const hipStream_t *st)
+{
+    std::lock_guard<std::mutex> lk(g_stream_mu);
+    for (int i = 0; i < k; ++i) g_stream_pool[dev].push_back(st[i]);
+}
+
 // the launch has completed (its side streams were joined into the caller's
 // stream, which has passed the join): its streams go back to the pool
 void batch_done(BatchLaunch *bl)
 {
     if (!bl || bl->nside == 0) return;
-    std::lock_guard<std::mutex> lk(g_stream_mu);
-    for (int i = 0; i < bl->nside; ++i) g_stream_pool[bl->dev].push_back(bl->side[i]);
+    give_streams(bl->dev, bl->nside, bl->side);
     bl->nside = 0;
 }
 
@@ -961,6 +969,176 @@ int batch_run_noalloc(BatchItem *items, int cnt, int max_sweeps, unsigned flags,
 
 using namespace jsvd;
 
+namespace {
+
+// Matrices of a batch outside the batched kernel's tile (more than 512 rows):
+// each on a state of its own, up to kPlainRuns of them at once on streams of
+// the pool, side by side with the batched launch on the caller's stream.  A
+// sweep is enqueued as soon as the previous one is seen done (one sweep is a
+// captured graph of K steps, and every step spreads its pairs over the whole
+// GPU; a second and third matrix fill the gaps between one's steps and
+// sweeps).  Each matrix goes through the same load, sweeps and finalisation
+// as jsvd_gesvj, so its result is the same bits.
+constexpr int kPlainRuns = 4;
+
+struct PlainRun {
+    jsvd_state st = nullptr;
+    hipEvent_t ev = nullptr;
+    int idx = -1;        // matrix of the batch, -1 = free
+    int finishing = 0;   // 0 sweeping, 1 converged output enqueued, 2 output after the sweep limit
+};
+
+struct PlainBatch {
+    const int *m, *n, *is_complex;
+    double *const *G_re, *const *G_im;
+    const size_t *ldg;
+    double *const *V_re, *const *V_im;
+    const size_t *ldv;
+    double *const *sv_e, *const *sv_f;
+    int max_sweeps;
+    unsigned flags;
+    int *sweeps, *status;
+    int64_t *transformations;
+};
+
+// start matrix i on run r (its stream waits for `ready`, the caller's inputs)
+int plain_start(const PlainBatch &b, int i, PlainRun &r, hipStream_t st, hipEvent_t ready)
+{
+    const int c = b.is_complex ? (b.is_complex[i] != 0) : 0;
+    r.idx = i;
+    r.finishing = 0;
+    int rc = jsvd_state_create(b.m[i], b.n[i], c, &r.st);
+    if (rc != JSVD_OK) return rc;
+    r.st->max_sweeps = b.max_sweeps;
+    rc = state_set_flags(r.st, b.flags);
+    if (rc == JSVD_OK && hipStreamWaitEvent(st, ready, 0) != hipSuccess) rc = JSVD_EDEVICE;
+    if (rc == JSVD_OK) rc = state_load_async(r.st, b.G_re[i], c ? b.G_im[i] : nullptr, b.ldg[i], st);
+    if (rc == JSVD_OK) rc = state_sweep_async(r.st, st);
+    if (rc == JSVD_OK && hipEventRecord(r.ev, st) != hipSuccess) rc = JSVD_EDEVICE;
+    return rc;
+}
+
+// advance run r if its stream has passed the last recorded point; returns
+// whether anything happened, and sets *done_status once the matrix is done
+bool plain_service(const PlainBatch &b, PlainRun &r, hipStream_t st, int *done_status, int *done_sweeps)
+{
+    constexpr int kRunning = 1 << 20;
+    *done_status = kRunning;
+    const hipError_t q = hipEventQuery(r.ev);
+    if (q == hipErrorNotReady) return false;
+    const int i = r.idx;
+    const int c = b.is_complex ? (b.is_complex[i] != 0) : 0;
+    if (q != hipSuccess) {
+        *done_status = JSVD_EDEVICE;
+    } else if (!r.finishing) {
+        const DevScalars &h = state_staged(r.st);
+        *done_sweeps = (int)h.C;
+        if (!h.stop) {
+            if (state_sweep_async(r.st, st) != JSVD_OK || hipEventRecord(r.ev, st) != hipSuccess)
+                *done_status = JSVD_EDEVICE;
+        } else if (h.status != 0) {
+            *done_status = h.status;
+        } else {
+            r.finishing = h.converged ? 1 : 2;
+            if (state_finish_async(r.st, h.converged != 0, b.G_re[i], c ? b.G_im[i] : nullptr, b.ldg[i], b.V_re[i],
+                                   c ? b.V_im[i] : nullptr, b.ldv[i], b.sv_e[i], b.sv_f[i], (double *)nullptr,
+                                   st) != JSVD_OK ||
+                hipEventRecord(r.ev, st) != hipSuccess)
+                *done_status = JSVD_EDEVICE;
+        }
+    } else {
+        *done_status = r.finishing == 1 ? JSVD_OK : JSVD_NOT_CONVERGED;
+        *done_sweeps = (int)state_staged(r.st).C;
+    }
+    return true;
+}
+
+// every matrix of `list`, at most kPlainRuns at once and at most half the
+// free device memory in states (one at a time beyond that); blocks until all
+// are done; returns the first negative status
+int plain_concurrent(const PlainBatch &b, const std::vector<int> &list, hipStream_t caller)
+{
+    if (list.empty()) return JSVD_OK;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return JSVD_EDEVICE;
+    const int k = std::min<int>(kPlainRuns, (int)list.size());
+    hipStream_t streams[kPlainRuns];
+    if (!take_streams(dev, k, streams)) return JSVD_EDEVICE;
+    PlainRun runs[kPlainRuns];
+    hipEvent_t ready = nullptr;
+    bool ok = hipEventCreateWithFlags(&ready, hipEventDisableTiming) == hipSuccess &&
+              hipEventRecord(ready, caller) == hipSuccess;
+    for (int j = 0; j < k && ok; ++j)
+        ok = hipEventCreateWithFlags(&runs[j].ev, hipEventDisableTiming) == hipSuccess;
+    size_t free_b = 0, total_b = 0;
+    if (ok && hipMemGetInfo(&free_b, &total_b) != hipSuccess) ok = false;
+    const size_t budget = free_b / 2;
+    int rc_all = JSVD_OK;
+    size_t next = 0, in_use = 0;
+    int active = 0;
+    auto finish = [&](PlainRun &r, hipStream_t st, int status, int sw) {
+        (void)hipStreamSynchronize(st);
+        in_use -= state_bytes(r.st->m, r.st->n, r.st->cplx);
+        jsvd_state_destroy(r.st);
+        r.st = nullptr;
+        b.status[r.idx] = status;
+        if (b.sweeps) b.sweeps[r.idx] = sw;
+        if (b.transformations) b.transformations[r.idx] = -1;   // not counted on this path
+        if (status < 0 && rc_all == JSVD_OK) rc_all = status;
+        r.idx = -1;
+        --active;
+    };
+    if (!ok) {
+        for (int i : list) b.status[i] = JSVD_EDEVICE;
+        rc_all = JSVD_EDEVICE;
+        next = list.size();
+    }
+    while (next < list.size() || active > 0) {
+        bool progressed = false;
+        for (int j = 0; j < k; ++j) {
+            PlainRun &r = runs[j];
+            if (r.idx < 0) {
+                if (next >= list.size()) continue;
+                const int i = list[next];
+                const size_t fp = state_bytes(b.m[i], b.n[i], b.is_complex ? (b.is_complex[i] != 0) : 0);
+                if (active > 0 && in_use + fp > budget) continue;
+                ++next;
+                ++active;
+                progressed = true;
+                const int rc = plain_start(b, i, r, streams[j], ready);
+                if (r.st) in_use += fp;
+                if (rc != JSVD_OK) {
+                    if (r.st) {
+                        finish(r, streams[j], rc, 0);
+                    } else {
+                        b.status[i] = rc;
+                        if (b.sweeps) b.sweeps[i] = 0;
+                        if (b.transformations) b.transformations[i] = -1;
+                        if (rc < 0 && rc_all == JSVD_OK) rc_all = rc;
+                        r.idx = -1;
+                        --active;
+                    }
+                }
+                continue;
+            }
+            int st_done = 0, sw = 0;
+            if (!plain_service(b, r, streams[j], &st_done, &sw)) continue;
+            progressed = true;
+            if (st_done != (1 << 20)) finish(r, streams[j], st_done, sw);
+        }
+        if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    for (int j = 0; j < k; ++j) {
+        (void)hipStreamSynchronize(streams[j]);
+        if (runs[j].ev) (void)hipEventDestroy(runs[j].ev);
+    }
+    if (ready) (void)hipEventDestroy(ready);
+    give_streams(dev, k, streams);
+    return rc_all;
+}
+
+} // namespace
+
 extern "C" int jsvd_batched_tune(int count, const int *m, const int *n, const int *is_complex, unsigned flags,
                                  void *stream)
 {
@@ -1019,9 +1197,16 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
                                         c ? V_im[i] : nullptr, ldv[i], sv_e[i], sv_f[i]));
     }
     int rc_all = JSVD_OK;
+    BatchLaunch *bl = nullptr;
     if (!items.empty()) {
-        BatchLaunch *bl = batch_launch(items.data(), (int)items.size(), max_sweeps, flags, s);
+        bl = batch_launch(items.data(), (int)items.size(), max_sweeps, flags, s);
         if (!bl) return JSVD_EDEVICE;
+    }
+    // matrices outside the batched kernel's tile, beside the batched launch
+    const PlainBatch pb{m, n, is_complex, G_re, G_im, ldg, V_re, V_im, ldv, sv_e, sv_f, max_sweeps, flags,
+                        sweeps, status, transformations};
+    rc_all = plain_concurrent(pb, plain, s);
+    if (bl) {
         if (hipStreamSynchronize(s) != hipSuccess) {
             batch_release(bl);
             return JSVD_EDEVICE;
@@ -1036,18 +1221,6 @@ extern "C" int jsvd_gesvj_batched(int count, const int *m, const int *n, const i
             if (it.status < 0 && rc_all == JSVD_OK) rc_all = it.status;
         }
         batch_release(bl);
-    }
-    // matrices outside the batched kernel's tile: the plain path, one by one
-    for (int i : plain) {
-        const int c = is_complex ? is_complex[i] : 0;
-        int sw = 0;
-        const int rc = jsvd_gesvj(m[i], n[i], G_re[i], c ? G_im[i] : nullptr, ldg[i], V_re[i],
-                                  c ? V_im[i] : nullptr, ldv[i], sv_e[i], sv_f[i], nullptr, max_sweeps, &sw,
-                                  flags, stream);
-        status[i] = rc;
-        if (sweeps) sweeps[i] = sw;
-        if (transformations) transformations[i] = -1;   // not counted on the plain path
-        if (rc < 0 && rc_all == JSVD_OK) rc_all = rc;
     }
     return rc_all;
 }

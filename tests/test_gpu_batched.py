@@ -57,6 +57,27 @@ def test_batched_mixed_shapes():
     _check_batch(_mats(shapes, 1))
 
 
+def test_batched_tall_members_side_by_side():
+    """More matrices outside the tile than the batch runs at once (their own
+    states, up to four side by side with the batched launch): each still
+    the plain path's bits, including a non-finite one, a zero one and the
+    sweep limit."""
+    shapes = [(520, 300, False, 1e4), (1500, 200, True, 1e6), (40, 33, True, 1e4), (2048, 64, False, 1e8),
+              (600, 600, False, 1e2), (513, 17, True, 1e3), (900, 450, False, 1e5), (100, 100, False, 1e6),
+              (1100, 2, False, 10.0)]
+    host = _mats(shapes, 4)
+    bad = host[3][0].copy(order="F")
+    bad[7, 9] = np.inf
+    host.append((bad, None))
+    host.append((np.zeros((700, 5), order="F"), None))
+    res = _check_batch(host)
+    assert res[-2]["status"] == J().ENONFINITE and res[-1]["status"] == J().EZERO
+    assert all(r["status"] == 0 for r in res[:-2])
+    assert all(r["transformations"] == -1 for r, (A, _) in zip(res, host) if A.shape[0] > 512)
+    _check_batch(host[:7], max_sweeps=2)
+    _check_batch(host[:7], flags=J().PERMUTE | J().COMPENSATED)
+
+
 def test_batched_vs_oracle():
     import oracle
     host = _mats([(60, 33, True, 1e4), (90, 90, False, 1e6)], 2)
