@@ -451,24 +451,37 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
     import numpy as np
     m, n, kappa = inputs.batched_shapes(10000)
     mats, sigs = batched_inputs(inputs, count)
-    dev = [(J.to_device_fortran(A), None) for A in mats]
-    # the launch shape of each class present is measured once, before timing
     shapes = [(int(m[i]), int(n[i]), False) for i in range(count)]
-    t0 = time.perf_counter()
-    J.batched_tune(shapes, flags=flags)
-    tune_s = time.perf_counter() - t0
-    launch = {}
-    for (mm, nn, _) in shapes:
-        rows = 64
-        while rows < mm:
-            rows *= 2
-        launch[f"rows<={rows}"] = J.batched_launch_of(mm, nn, False, flags)
-    J.gesvj_batched([(J.to_device_fortran(mats[0]), None)], flags=flags)   # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = J.gesvj_batched(dev, flags=flags)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+
+    def run(tuning):
+        # the schedule of each class present is measured once, before timing,
+        # among the candidates `tuning` allows
+        J.batched_set_tuning(tuning)
+        t0 = time.perf_counter()
+        J.batched_tune(shapes, flags=flags)
+        tune_s = time.perf_counter() - t0
+        sched = {}
+        for (mm, nn, _) in shapes:
+            rows = 64
+            while rows < mm:
+                rows *= 2
+            t, d, w = J.batched_schedule_of(mm, nn, False, flags)
+            sched[f"rows<={rows}"] = dict(threads=t, dense=d, workgroups_per_cu=w)
+        dev = [(J.to_device_fortran(A), None) for A in mats]
+        J.gesvj_batched([(J.to_device_fortran(mats[0]), None)], flags=flags)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = J.gesvj_batched(dev, flags=flags)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, res, sched, tune_s
+    # A: threads per matrix alone (default instance, full grid); B: the
+    # widened schedule (dense instances, workgroups per CU); same bits
+    ta, res_a, sched_a, _ = run(0)
+    tb, res, launch, tune_s = run(J.TUNE_DENSE | J.TUNE_WGS)
+    same = all(a["sweeps"] == b["sweeps"] and bool(torch.equal(a["sv_f"], b["sv_f"])) and
+               bool(torch.equal(a["sv_e"], b["sv_e"])) and bool(torch.equal(a["V_re"], b["V_re"]))
+               for a, b in zip(res_a, res))
+    del res_a
     errs, up, mv, sweeps = [], np.zeros(count), np.zeros(count), []
     for i, r in enumerate(res):
         sv = np.ldexp(r["sv_f"].cpu().numpy(), r["sv_e"].cpu().numpy().astype(int))
@@ -476,7 +489,7 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
         errs.append(float(np.max(np.abs(sv[big] - sigs[i][big]) / sigs[i][big])))
         up[i], mv[i] = _svd_bytes(int(m[i]), int(n[i]), r["sweeps"], r["transformations"])
         sweeps.append(r["sweeps"])
-    del dev, res
+    del res
     _batched_cache["bytes_upper_%d" % flags] = up
     # the plain sample: every k-th matrix in the order of n
     by_n = np.argsort(n[:count], kind="stable")
@@ -506,7 +519,9 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
                 batched_frac_moved=float(bm / tb / 1e9 / HBM_PEAK_GBS),
                 plain_GBs_upper=float(pu / tp / 1e9), plain_frac_upper=float(pu / tp / 1e9 / HBM_PEAK_GBS),
                 plain_GBs_moved=float(pm / tp / 1e9), plain_frac_moved=float(pm / tp / 1e9 / HBM_PEAK_GBS),
-                threads_per_matrix=dict(sorted(launch.items())), tune_s=round(tune_s, 3),
+                schedule=dict(sorted(launch.items())), tune_s=round(tune_s, 3),
+                threads_only_schedule=dict(sorted(sched_a.items())), threads_only_s=ta,
+                threads_only_svds_per_s=count / ta, schedule_gain=ta / tb, schedules_same_bits=same,
                 bit_identical_to_plain="tested (tests/test_gpu_batched.py)")
 
 

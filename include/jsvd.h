@@ -381,21 +381,48 @@ int jsvd_gesvj_batched_noalloc(int count, const int *m, const int *n, const int 
                                int max_sweeps, int *sweeps, int *status, int64_t *transformations,
                                unsigned flags, void *stream);
 
-/* Launch shape of the batched SVD: the threads per matrix (one wavefront per
- * pivot pair at a time) of each class are chosen by measurement, once per
- * process and device: one sweep of up to 1024 random matrices of the class's
- * median shape for each of 128, 256 and 512 threads, the fastest kept.
- * jsvd_gesvj_batched measures the classes of its matrices that are not
- * measured yet; jsvd_batched_tune does it ahead of time for a list of shapes
- * (host arrays; is_complex may be NULL; flags as for the batched call, of
- * which JSVD_COMPENSATED selects the compensated kernels).  Synchronises.  The
- * results do not depend on the launch shape. */
+/* Launch schedule of the batched SVD, per class (real or complex; rows per
+ * lane 1, 2, 4 or 8, i.e. at most 64, 128, 256 or 512 rows):
+ *   - threads per matrix (128, 256 or 512; one wavefront per pivot pair at a
+ *     time, so that many pairs of a matrix in flight);
+ *   - the register budget of the kernel instance: the compiler's own, or
+ *     "dense", at most 128 VGPRs (four waves per SIMD, a few spills where
+ *     the default instance needs more);
+ *   - workgroups per CU of the persistent grid (0 = as many as fit; fewer
+ *     keeps fewer matrices in flight, whose columns then stay in the caches).
+ * Chosen by measurement once per process and device: one sweep of up to 1024
+ * random matrices of the class's median shape per candidate schedule, the
+ * fastest kept.  jsvd_gesvj_batched measures the classes of its matrices that
+ * are not measured yet; jsvd_batched_tune does it ahead of time for a list
+ * of shapes (host arrays; is_complex may be NULL; flags as for the batched
+ * call, of which JSVD_COMPENSATED selects the compensated kernels).
+ * Synchronises.  The results do not depend on the schedule. */
 int jsvd_batched_tune(int count, const int *m, const int *n, const int *is_complex, unsigned flags,
                       void *stream);
 /* Force the threads per matrix for every class (128, 256 or 512; 0 = the
- * measured choice, the default).  A process-wide setting.  JSVD_EINVAL for
- * other values. */
+ * measured choice, the default), with the default instance and grid.  A
+ * process-wide setting.  JSVD_EINVAL for other values. */
 int jsvd_batched_set_launch(int threads_per_matrix);
+/* Force a whole schedule for every class: threads per matrix as above (0 =
+ * the measured choice, the other two arguments then ignored), dense 0 or 1,
+ * workgroups per CU 0..64 (0 = as many as fit; more than fit is clamped).
+ * JSVD_EINVAL for other values. */
+int jsvd_batched_set_schedule(int threads_per_matrix, int dense, int workgroups_per_cu);
+/* The candidates the measurement tries besides the three thread counts with
+ * the default instance and a full grid: JSVD_TUNE_DENSE adds the dense
+ * instances (where the default one takes more than 128 registers),
+ * JSVD_TUNE_WGS adds half, 2 and 1 workgroups per CU; both are the default.
+ * Forgets every measured schedule of the process.  JSVD_EINVAL for other
+ * bits. */
+#define JSVD_TUNE_DENSE 1u
+#define JSVD_TUNE_WGS 2u
+int jsvd_batched_set_tuning(unsigned candidates);
+/* The schedule a batched call would use now for an m x n matrix (forced,
+ * else measured, else 256 threads with the default instance and grid);
+ * threads 0 when the shape is not batched.  JSVD_EINVAL for n < 1, m < n or
+ * a NULL output. */
+int jsvd_batched_schedule_of(int m, int n, int is_complex, unsigned flags, int *threads_per_matrix, int *dense,
+                             int *workgroups_per_cu);
 /* The threads per matrix a batched call would use now for an m x n matrix:
  * the forced value, else the measured one, else 256 (not measured yet);
  * 0 when the shape is not batched (more than 512 rows or columns), JSVD_EINVAL

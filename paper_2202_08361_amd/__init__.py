@@ -151,6 +151,12 @@ def lib():
         L.jsvd_batched_set_launch.argtypes = [i]
         L.jsvd_batched_launch_of.restype = i
         L.jsvd_batched_launch_of.argtypes = [i, i, i, u]
+        L.jsvd_batched_set_schedule.restype = i
+        L.jsvd_batched_set_schedule.argtypes = [i, i, i]
+        L.jsvd_batched_set_tuning.restype = i
+        L.jsvd_batched_set_tuning.argtypes = [u]
+        L.jsvd_batched_schedule_of.restype = i
+        L.jsvd_batched_schedule_of.argtypes = [i, i, i, u, _ct.POINTER(i), _ct.POINTER(i), _ct.POINTER(i)]
         L.jsvd_serve_create.restype = i
         L.jsvd_serve_create.argtypes = [_ct.POINTER(ServeConfig), _ct.POINTER(vp)]
         L.jsvd_serve_submit.restype = i
@@ -537,6 +543,30 @@ def batched_launch_of(m, n, cplx=False, flags=0):
     if r < 0:
         _check(r, "jsvd_batched_launch_of")
     return r
+
+
+TUNE_DENSE = 1
+TUNE_WGS = 2
+
+
+def batched_set_schedule(threads_per_matrix, dense=0, workgroups_per_cu=0):
+    """Force the batched schedule of every class (threads 0 = measured)."""
+    _check(lib().jsvd_batched_set_schedule(threads_per_matrix, int(dense), workgroups_per_cu),
+           "jsvd_batched_set_schedule")
+
+
+def batched_set_tuning(candidates=TUNE_DENSE | TUNE_WGS):
+    """The candidate schedules the batched tuner tries (and forget the measured ones)."""
+    _check(lib().jsvd_batched_set_tuning(candidates), "jsvd_batched_set_tuning")
+
+
+def batched_schedule_of(m, n, cplx=False, flags=0):
+    """(threads per matrix, dense, workgroups per CU) a batched call would use
+    now for an m x n matrix (threads 0: not a batched shape)."""
+    t, d, w = _ct.c_int(), _ct.c_int(), _ct.c_int()
+    _check(lib().jsvd_batched_schedule_of(m, n, int(bool(cplx)), flags, _ct.byref(t), _ct.byref(d), _ct.byref(w)),
+           "jsvd_batched_schedule_of")
+    return t.value, d.value, w.value
 
 
 # ---------------------------------------------------------------------------- serving

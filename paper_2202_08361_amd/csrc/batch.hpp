@@ -25,12 +25,24 @@ int batch_rows(int m, int n, int cplx);
 BatchItem make_batch_item(int m, int n, int cplx, double *Gr, double *Gi, size_t ldg, double *Vr, double *Vi,
                           size_t ldv, double *sv_e, double *sv_f);
 
-// The launch shape per class (real or complex, rows per lane): threads per
-// matrix, measured once per process and device for the classes of these
-// items (batch_tune), forced for all (batch_set_threads, 0 = measured), and
-// the current choice for one shape (0: not a batched shape).
+// The launch schedule of a class (real or complex, rows per lane): threads
+// per matrix, the dense (four waves per SIMD) instance or the default one,
+// and workgroups per CU of the persistent grid (0: as many as fit).
+struct BatchSched {
+    int nt;
+    int dense;
+    int wpc;
+};
+
+// Measured once per process and device for the classes of these items
+// (batch_tune) among the candidates batch_set_tuning allows, forced for all
+// (batch_set_sched / batch_set_threads, nt = 0: measured), and the current
+// choice for one shape (nt = 0: not a batched shape).
 void batch_tune(const BatchItem *items, int count, unsigned flags, hipStream_t s);
+int batch_set_sched(int nt, int dense, int wpc);
 int batch_set_threads(int threads);
+int batch_set_tuning(unsigned what);
+BatchSched batch_sched_of(int m, int n, int cplx, unsigned flags);
 int batch_threads_of(int m, int n, int cplx, unsigned flags);
 
 struct BatchLaunch;

@@ -430,9 +430,12 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
     }
 }
 
-// the matrices of one class (CPLX, R), NT threads per matrix
-template <bool COMP, bool CPLX, int R, int NT>
-__global__ __launch_bounds__(NT) void batched_kernel(BatchItem *items, const int *order, BatchCtl *ctl)
+// the matrices of one class (CPLX, R), NT threads per matrix.  DENSE: the
+// instance compiled for four waves per SIMD (at most 128 VGPRs, a few spills
+// in the phases that need more), else the compiler's own register budget.
+template <bool COMP, bool CPLX, int R, int NT, bool DENSE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(DENSE ? 4 : (NT >= 512 ? 2 : 1)))) void
+batched_kernel(BatchItem *items, const int *order, BatchCtl *ctl)
 {
     __shared__ BatchSmem<R, NT> sm;
     const int count = ctl->count;
@@ -496,7 +499,13 @@ BatchItem make_batch_item(int m, int n, int cplx, double *Gr, double *Gi, size_t
 }
 
 // ---------------------------------------------------------------------------
-// classes, launch shapes and the autotuner
+// classes, launch schedules and the autotuner
+//
+// A class's schedule: threads per matrix NT (one pivot pair per wavefront
+// at a time, so NT/64 pairs of a matrix in flight), the register budget of
+// the instance (dense: four waves per SIMD), and the workgroups per CU of the
+// persistent grid (0: as many as fit; fewer keeps fewer matrices in flight,
+// whose columns then stay in the caches).  Every schedule gives the same bits.
 
 constexpr int kNumNT = 3;
 constexpr int kNTs[kNumNT] = {128, 256, 512};   // threads per matrix tried
@@ -507,62 +516,84 @@ static int class_index(int cplx, int R)
     return (cplx ? 4 : 0) + r;
 }
 
-template <bool COMP, bool CPLX, int R, int NT>
-static hipError_t launch_class_t(BatchItem *items, const int *order, BatchCtl *ctl, int count, int ncu, hipStream_t s)
-{
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)batched_kernel<COMP, CPLX, R, NT>, NT, 0) !=
-            hipSuccess ||
-        per_cu < 1)
-        per_cu = 1;
-    const int grid = std::min(count, per_cu * ncu);
-    hipLaunchKernelGGL((batched_kernel<COMP, CPLX, R, NT>), dim3(grid), dim3(NT), 0, s, items, order, ctl);
-    return hipGetLastError();
-}
+// packed schedule: nt | dense << 10 | wpc << 11 (0: none)
+static int sched_pack(const BatchSched &b) { return b.nt | (b.dense ? 1 << 10 : 0) | (b.wpc << 11); }
+static BatchSched sched_unpack(int v) { return BatchSched{v & 1023, (v >> 10) & 1, v >> 11}; }
 
 template <bool COMP, bool CPLX, int R>
-static hipError_t launch_class_r(int NT, BatchItem *items, const int *order, BatchCtl *ctl, int count, int ncu,
-                                 hipStream_t s)
+static const void *class_kernel_r(int NT, bool dense)
 {
     switch (NT) {
-    case 128: return launch_class_t<COMP, CPLX, R, 128>(items, order, ctl, count, ncu, s);
-    case 256: return launch_class_t<COMP, CPLX, R, 256>(items, order, ctl, count, ncu, s);
-    case 512: return launch_class_t<COMP, CPLX, R, 512>(items, order, ctl, count, ncu, s);
-    default: return hipErrorInvalidValue;
+    case 128:
+        return dense ? (const void *)batched_kernel<COMP, CPLX, R, 128, true>
+                     : (const void *)batched_kernel<COMP, CPLX, R, 128, false>;
+    case 256:
+        return dense ? (const void *)batched_kernel<COMP, CPLX, R, 256, true>
+                     : (const void *)batched_kernel<COMP, CPLX, R, 256, false>;
+    case 512:
+        return dense ? (const void *)batched_kernel<COMP, CPLX, R, 512, true>
+                     : (const void *)batched_kernel<COMP, CPLX, R, 512, false>;
+    default: return nullptr;
     }
 }
 
 template <bool COMP, bool CPLX>
-static hipError_t launch_class_c(int R, int NT, BatchItem *items, const int *order, BatchCtl *ctl, int count, int ncu,
-                                 hipStream_t s)
+static const void *class_kernel_c(int R, int NT, bool dense)
 {
     switch (R) {
-    case 1: return launch_class_r<COMP, CPLX, 1>(NT, items, order, ctl, count, ncu, s);
-    case 2: return launch_class_r<COMP, CPLX, 2>(NT, items, order, ctl, count, ncu, s);
-    case 4: return launch_class_r<COMP, CPLX, 4>(NT, items, order, ctl, count, ncu, s);
-    case 8: return launch_class_r<COMP, CPLX, 8>(NT, items, order, ctl, count, ncu, s);
-    default: return hipErrorInvalidValue;
+    case 1: return class_kernel_r<COMP, CPLX, 1>(NT, dense);
+    case 2: return class_kernel_r<COMP, CPLX, 2>(NT, dense);
+    case 4: return class_kernel_r<COMP, CPLX, 4>(NT, dense);
+    case 8: return class_kernel_r<COMP, CPLX, 8>(NT, dense);
+    default: return nullptr;
     }
+}
+
+// the kernel instance of a class and schedule (nullptr: no such instance)
+static const void *class_kernel_of(bool comp, int cplx, int R, int NT, bool dense)
+{
+    if (comp) return cplx ? class_kernel_c<true, true>(R, NT, dense) : class_kernel_c<true, false>(R, NT, dense);
+    return cplx ? class_kernel_c<false, true>(R, NT, dense) : class_kernel_c<false, false>(R, NT, dense);
+}
+
+// workgroups of an instance that fit on one CU (at least 1)
+static int class_per_cu(const void *fn, int NT)
+{
+    int per_cu = 0;
+    if (!fn || hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, NT, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return per_cu;
+}
+
+// registers per lane of an instance (0 if unknown)
+static int class_regs(const void *fn)
+{
+    hipFuncAttributes a;
+    if (!fn || hipFuncGetAttributes(&a, fn) != hipSuccess) return 0;
+    return a.numRegs;
 }
 
 // one persistent launch over the `count` matrices of class (cplx, R) listed
 // (longest first) in order
-static hipError_t launch_class(bool comp, int cplx, int R, int NT, BatchItem *items, const int *order, BatchCtl *ctl,
-                               int count, int ncu, hipStream_t s)
+static hipError_t launch_class(bool comp, int cplx, int R, const BatchSched &sc, BatchItem *items, const int *order,
+                               BatchCtl *ctl, int count, int ncu, hipStream_t s)
 {
-    if (comp)
-        return cplx ? launch_class_c<true, true>(R, NT, items, order, ctl, count, ncu, s)
-                    : launch_class_c<true, false>(R, NT, items, order, ctl, count, ncu, s);
-    return cplx ? launch_class_c<false, true>(R, NT, items, order, ctl, count, ncu, s)
-                : launch_class_c<false, false>(R, NT, items, order, ctl, count, ncu, s);
+    const void *fn = class_kernel_of(comp, cplx, R, sc.nt, sc.dense != 0);
+    if (!fn) return hipErrorInvalidValue;
+    const int per_cu = class_per_cu(fn, sc.nt);
+    const int wpc = sc.wpc > 0 ? std::min(sc.wpc, per_cu) : per_cu;
+    const int grid = std::min(count, wpc * ncu);
+    void *args[] = {(void *)&items, (void *)&order, (void *)&ctl};
+    return hipLaunchKernel(fn, dim3(grid), dim3(sc.nt), args, 0, s);
 }
 
-// the tuner's results: threads per matrix per (device, compensated, class);
-// 0 = not measured yet.  A forced value (jsvd_batched_set_launch) overrides.
+// the tuner's results per (device, compensated, class), packed; 0 = not
+// measured yet.  A forced schedule (jsvd_batched_set_schedule) overrides.
 constexpr int kMaxDev = 64;
 static std::mutex g_tune_mu;
 static int g_tuned[kMaxDev][2][8];
-static int g_forced_nt = 0;
+static int g_forced = 0;
+static unsigned g_tuning = JSVD_TUNE_DENSE | JSVD_TUNE_WGS;
 
 // fill a sample matrix with values in [-1, 1) from a counter hash
 __global__ void batch_fill_kernel(double *x, size_t count, unsigned long long seed)
@@ -579,7 +610,7 @@ __global__ void batch_fill_kernel(double *x, size_t count, unsigned long long se
 // Measure the threads per matrix of one class: one sweep of up to 1024
 // sample matrices of the class's median shape (random entries), per
 // candidate, after a warm-up; the fastest wins.  Returns 0 on failure.
-static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, hipStream_t s)
+static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, unsigned tuning, hipStream_t s)
 {
     const int c = cplx ? 2 : 1;
     const size_t per = (size_t)c * ((size_t)m * n + (size_t)n * n) + 2 * (size_t)n;
@@ -602,13 +633,36 @@ static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, hipS
     BatchItem *ditems = (BatchItem *)tail;
     int *dorder = (int *)(tail + S * sizeof(BatchItem));
     BatchCtl *dctl = (BatchCtl *)(((uintptr_t)(dorder + S) + 255) & ~(uintptr_t)255);
+    // the candidates: every NT; with JSVD_TUNE_DENSE the dense instance where
+    // the default one takes more than 128 registers; with JSVD_TUNE_WGS also
+    // half, 2 and 1 workgroups per CU (each below the most that fit)
+    std::vector<BatchSched> cand;
+    for (int ci = 0; ci < kNumNT; ++ci) {
+        for (int dense = 0; dense < 2; ++dense) {
+            if (dense && (!(tuning & JSVD_TUNE_DENSE) ||
+                          class_regs(class_kernel_of(comp, cplx, R, kNTs[ci], false)) <= 128))
+                continue;
+            const int per_cu = class_per_cu(class_kernel_of(comp, cplx, R, kNTs[ci], dense != 0), kNTs[ci]);
+            BatchSched sc{kNTs[ci], dense, 0};
+            cand.push_back(sc);
+            if (!(tuning & JSVD_TUNE_WGS)) continue;
+            for (int w : {per_cu / 2, 2, 1}) {
+                bool dup = w < 1 || w >= per_cu;
+                for (const BatchSched &o : cand)
+                    dup = dup || (o.nt == sc.nt && o.dense == sc.dense && o.wpc == w);
+                if (dup) continue;
+                sc.wpc = w;
+                cand.push_back(sc);
+            }
+        }
+    }
     hipEvent_t a = nullptr, b = nullptr;
     int best = 0;
     float best_ms = 0.f;
     bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
               hipMemcpyAsync(dorder, order.data(), sizeof(int) * S, hipMemcpyHostToDevice, s) == hipSuccess;
-    for (int ci = 0; ok && ci < kNumNT; ++ci) {
-        const int NT = kNTs[ci];
+    for (size_t ci = 0; ok && ci < cand.size(); ++ci) {
+        const BatchSched &sc = cand[ci];
         for (int rep = 0; ok && rep < 2; ++rep) {
             // fresh random G (the SVD works in place) and fresh queue
             hipLaunchKernelGGL(batch_fill_kernel, dim3(1024), dim3(256), 0, s, base, S * per, 1234567ull);
@@ -622,11 +676,11 @@ static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, hipS
                  hipMemcpyAsync(ditems, items.data(), sizeof(BatchItem) * S, hipMemcpyHostToDevice, s) == hipSuccess &&
                  hipMemcpyAsync(dctl, &ctl, sizeof(ctl), hipMemcpyHostToDevice, s) == hipSuccess &&
                  hipEventRecord(a, s) == hipSuccess &&
-                 launch_class(comp, cplx, R, NT, ditems, dorder, dctl, (int)S, ncu, s) == hipSuccess &&
+                 launch_class(comp, cplx, R, sc, ditems, dorder, dctl, (int)S, ncu, s) == hipSuccess &&
                  hipEventRecord(b, s) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
             float ms = 0.f;
             if (ok && rep == 1 && hipEventElapsedTime(&ms, a, b) == hipSuccess && (best == 0 || ms < best_ms)) {
-                best = NT;
+                best = sched_pack(sc);
                 best_ms = ms;
             }
         }
@@ -647,18 +701,21 @@ static int current_device_ncu(int *dev)
     return ncu;
 }
 
-// threads per matrix for a class: forced, else measured (once per process
-// and device), else 256
-static int class_threads(bool comp, int cplx, int R, int m, int n, hipStream_t s, bool measure)
+// the schedule of a class: forced, else measured (once per process and
+// device), else 256 threads with the default instance and grid
+static BatchSched class_sched(bool comp, int cplx, int R, int m, int n, hipStream_t s, bool measure)
 {
     int dev = 0;
     const int ncu = current_device_ncu(&dev);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (g_forced_nt) return g_forced_nt;
-    if (dev < 0 || dev >= kMaxDev) return 256;
-    int &t = g_tuned[dev][comp ? 1 : 0][class_index(cplx, R)];
-    if (t == 0 && measure) t = measure_class(comp, cplx, R, m, n, ncu, s);
-    return t ? t : 256;
+    if (g_forced) return sched_unpack(g_forced);
+    int v = 0;
+    if (dev >= 0 && dev < kMaxDev) {
+        int &t = g_tuned[dev][comp ? 1 : 0][class_index(cplx, R)];
+        if (t == 0 && measure) t = measure_class(comp, cplx, R, m, n, ncu, g_tuning, s);
+        v = t;
+    }
+    return sched_unpack(v ? v : 256);
 }
 
 void batch_tune(const BatchItem *items, int cnt, unsigned flags, hipStream_t s)
@@ -672,22 +729,36 @@ void batch_tune(const BatchItem *items, int cnt, unsigned flags, hipStream_t s)
         if (by[k].empty()) continue;
         std::sort(by[k].begin(), by[k].end());
         const BatchItem &it = items[by[k][by[k].size() / 2].second];
-        (void)class_threads(comp, it.cplx, it.R, it.m, it.n, s, true);
+        (void)class_sched(comp, it.cplx, it.R, it.m, it.n, s, true);
     }
 }
 
-int batch_threads_of(int m, int n, int cplx, unsigned flags)
+BatchSched batch_sched_of(int m, int n, int cplx, unsigned flags)
 {
     const int R = batch_rows(m, n, cplx);
-    if (!R) return 0;
-    return class_threads((flags & JSVD_COMPENSATED) != 0, cplx, R, m, n, nullptr, false);
+    if (!R) return BatchSched{0, 0, 0};
+    return class_sched((flags & JSVD_COMPENSATED) != 0, cplx, R, m, n, nullptr, false);
 }
 
-int batch_set_threads(int nt)
+int batch_threads_of(int m, int n, int cplx, unsigned flags) { return batch_sched_of(m, n, cplx, flags).nt; }
+
+int batch_set_sched(int nt, int dense, int wpc)
 {
     if (nt != 0 && nt != 128 && nt != 256 && nt != 512) return JSVD_EINVAL;
+    if (dense < 0 || dense > 1 || wpc < 0 || wpc > 64) return JSVD_EINVAL;
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_forced_nt = nt;
+    g_forced = nt ? sched_pack(BatchSched{nt, dense, wpc}) : 0;
+    return JSVD_OK;
+}
+
+int batch_set_threads(int nt) { return batch_set_sched(nt, 0, 0); }
+
+int batch_set_tuning(unsigned what)
+{
+    if (what & ~(unsigned)(JSVD_TUNE_DENSE | JSVD_TUNE_WGS)) return JSVD_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuning = what;
+    memset(g_tuned, 0, sizeof(g_tuned));
     return JSVD_OK;
 }
 
@@ -821,13 +892,13 @@ BatchLaunch *batch_launch(const BatchItem *items, int cnt, int max_sweeps, unsig
     }
     for (int c = 0; ok && c < ncls; ++c) {
         const BatchItem &it0 = items[order[first[c]]];
-        const int NT = class_threads(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
+        const BatchSched sc = class_sched(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
         hipStream_t ls = s;
         if (side && c > 0) {
             ls = cs[c - 1];
             ok = hipStreamWaitEvent(ls, fork, 0) == hipSuccess;
         }
-        ok = ok && launch_class(comp, it0.cplx, it0.R, NT, (BatchItem *)(dm + oItems),
+        ok = ok && launch_class(comp, it0.cplx, it0.R, sc, (BatchItem *)(dm + oItems),
                                 (const int *)(dm + oOrder) + first[c], (BatchCtl *)(dm + oCtl + 256 * (size_t)c),
                                 first[c + 1] - first[c], ncu, ls) == hipSuccess;
         if (side && c > 0 && ok) {
@@ -948,8 +1019,8 @@ int batch_run_noalloc(BatchItem *items, int cnt, int max_sweeps, unsigned flags,
     // creating one may allocate)
     for (int c = 0; ok && c < ncls; ++c) {
         const BatchItem &it0 = hitems[horder[first[c]]];
-        const int NT = class_threads(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
-        ok = launch_class(comp, it0.cplx, it0.R, NT, (BatchItem *)(dm + kNaItemsOff),
+        const BatchSched sc = class_sched(comp, it0.cplx, it0.R, it0.m, it0.n, s, false);
+        ok = launch_class(comp, it0.cplx, it0.R, sc, (BatchItem *)(dm + kNaItemsOff),
                           (const int *)(dm + kNaOrderOff) + first[c], (BatchCtl *)(dm + kNaCtlOff + 256 * (size_t)c),
                           first[c + 1] - first[c], ncu, s) == hipSuccess;
     }
@@ -1157,6 +1228,24 @@ extern "C" int jsvd_batched_tune(int count, const int *m, const int *n, const in
 }
 
 extern "C" int jsvd_batched_set_launch(int threads_per_matrix) { return batch_set_threads(threads_per_matrix); }
+
+extern "C" int jsvd_batched_set_schedule(int threads_per_matrix, int dense, int workgroups_per_cu)
+{
+    return batch_set_sched(threads_per_matrix, dense, workgroups_per_cu);
+}
+
+extern "C" int jsvd_batched_set_tuning(unsigned candidates) { return batch_set_tuning(candidates); }
+
+extern "C" int jsvd_batched_schedule_of(int m, int n, int is_complex, unsigned flags, int *threads_per_matrix,
+                                        int *dense, int *workgroups_per_cu)
+{
+    if (n < 1 || m < n || !threads_per_matrix || !dense || !workgroups_per_cu) return JSVD_EINVAL;
+    const BatchSched b = batch_sched_of(m, n, is_complex != 0, flags);
+    *threads_per_matrix = b.nt;
+    *dense = b.dense;
+    *workgroups_per_cu = b.wpc;
+    return JSVD_OK;
+}
 
 extern "C" int jsvd_batched_launch_of(int m, int n, int is_complex, unsigned flags)
 {

@@ -157,6 +157,46 @@ def test_batched_launch_shapes_identical():
         J().batched_set_launch(100)
 
 
+@pytest.mark.parametrize("flags", [0, 2])
+def test_batched_schedules_identical(flags):
+    """The dense instances and reduced grids (workgroups per CU) give the
+    same bits as the default schedule, plain and compensated; the tuner's
+    choice is reported and one of the candidates."""
+    shapes = [(40, 33, True, 1e4), (100, 70, False, 1e5), (250, 130, False, 1e6), (256, 200, True, 1e2),
+              (511, 256, True, 1e8), (512, 300, False, 1e4), (16, 16, False, 1e2)]
+    host = _mats(shapes, 5)
+    ref = None
+    try:
+        for (nt, dense, wpc) in ((256, 0, 0), (512, 1, 0), (128, 1, 1), (256, 0, 2), (512, 0, 1), (256, 1, 3)):
+            J().batched_set_schedule(nt, dense, wpc)
+            for (m, n, c, _) in shapes:
+                assert J().batched_schedule_of(m, n, c, flags) == (nt, dense, wpc)
+            dev = [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host]
+            res = J().gesvj_batched(dev, flags=flags)
+            torch.cuda.synchronize()
+            assert all(r["status"] == 0 for r in res)
+            cur = [[r[k] for k in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f")] + [r["sweeps"]] for r in res]
+            if ref is not None:
+                for a, b in zip(cur, ref):
+                    assert a[-1] == b[-1]
+                    for x, y in zip(a[:-1], b[:-1]):
+                        assert _same(x, y)
+            ref = cur
+    finally:
+        J().batched_set_schedule(0)
+    J().batched_set_tuning(J().TUNE_DENSE | J().TUNE_WGS)
+    J().batched_tune([(m, n, c) for (m, n, c, _) in shapes], flags=flags)
+    for (m, n, c, _) in shapes:
+        nt, dense, wpc = J().batched_schedule_of(m, n, c, flags)
+        assert nt in (128, 256, 512) and dense in (0, 1) and 0 <= wpc <= 64
+    assert J().batched_schedule_of(700, 100, False) == (0, 0, 0)
+    for bad in ((100, 0, 0), (256, 2, 0), (256, 0, -1), (256, 0, 65)):
+        with pytest.raises(Exception):
+            J().batched_set_schedule(*bad)
+    with pytest.raises(Exception):
+        J().batched_set_tuning(4)
+
+
 def _workload(count):
     """The first `count` matrices of the batched workload with their prescribed
     singular values, generated in parallel host threads (one-thread BLAS)."""
