@@ -236,15 +236,19 @@ __device__ __noinline__ double mul_rd_slow(double a, double b, double p)
     return -scal2((fr > 0.0 || lo > 0.0) ? f + 1.0 : f, -1074);
 }
 
-// RD(a b) by the fma test alone, and whether that test holds: the product's
-// magnitude is in [2^-960, max], or an operand is zero
-__device__ __forceinline__ double mul_rd_fast(double a, double b, bool &odd)
+// The next double below a normal p: p - |p| (2^-53 + 2^-105) rounded to
+// nearest, one fma.  |p| times that factor lies strictly between half and
+// one and a half of the spacing below p (also at powers of two, where that
+// spacing halves), so the nearest double is the next one down.
+__device__ __forceinline__ double next_down_normal(double p) { return fma(-fabs(p), 0x1p-53 + 0x1p-105, p); }
+
+// RD(a b) by the fma test alone: exact when the product's magnitude is in
+// [2^-960, max] or an operand is zero (the caller rules the rest out)
+__device__ __forceinline__ double mul_rd_fast(double a, double b)
 {
     const double p = a * b;
-    const double ap = fabs(p);
     const double e = fma(a, b, -p);
-    odd |= !(ap >= 0x1p-960 && ap <= 1.79769313486231570815e308) && a != 0.0 && b != 0.0;
-    return e < 0.0 ? __longlong_as_double(__double_as_longlong(p) + (p > 0.0 ? -1 : 1)) : p;
+    return e < 0.0 ? next_down_normal(p) : p;
 }
 
 __device__ __forceinline__ double mul_rd(double a, double b)
@@ -253,11 +257,15 @@ __device__ __forceinline__ double mul_rd(double a, double b)
     const double ap = fabs(p);
     if (ap >= 0x1p-960 && ap <= 1.79769313486231570815e308) {
         const double e = fma(a, b, -p);
-        if (e < 0.0) return __longlong_as_double(__double_as_longlong(p) + (p > 0.0 ? -1 : 1));
-        return p;
+        return e < 0.0 ? next_down_normal(p) : p;
     }
     return mul_rd_slow(a, b, p);
 }
+
+// a nonzero operand below 2^-480: only a product with such an operand can
+// fall below 2^-960 (operands scaled by their columns' norm exponents stay
+// below 4 in magnitude, so no product overflows)
+__device__ __forceinline__ bool tiny_operand(double x) { return fabs(x) < 0x1p-480 && x != 0.0; }
 
 // eq. (d2sum): s = fl(a + b), a + b = s + t exactly
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &t)
@@ -281,10 +289,9 @@ __device__ __forceinline__ void cs_term(double x, double y, double &s, double &t
     two_sum(s2, c2 + t2, s2, t2);
 }
 
-__device__ __forceinline__ void cs_term_fast(double x, double y, double &s, double &t, double &s2, double &t2,
-                                             bool &odd)
+__device__ __forceinline__ void cs_term_fast(double x, double y, double &s, double &t, double &s2, double &t2)
 {
-    const double c = mul_rd_fast(x, y, odd);
+    const double c = mul_rd_fast(x, y);
     const double c2 = fma(x, y, -c);
     two_sum(s, c + t, s, t);
     two_sum(s2, c2 + t2, s2, t2);
@@ -478,20 +485,20 @@ __device__ __forceinline__ void pair_dot(const T (&xr)[2][R], const T (&xi)[2][R
                 const int j = ch * V + v;
                 if (j < R) {
                     const double gpr = scal2(xr[0][j], -ep), gqr = scal2(xr[1][j], -eq);
-                    cs_term_fast(gpr, gqr, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v], odd);
+                    odd |= tiny_operand(gpr) || tiny_operand(gqr);
+                    cs_term_fast(gpr, gqr, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v]);
                     if (CPLX) {
                         const double gpi = scal2(xi[0][j], -ep), gqi = scal2(xi[1][j], -eq);
-                        cs_term_fast(gpi, gqi, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v], odd);
-                        cs_term_fast(gqr, gpi, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v],
-                                     a[NS - 1][3][v], odd);
-                        cs_term_fast(-gqi, gpr, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v],
-                                     a[NS - 1][3][v], odd);
+                        odd |= tiny_operand(gpi) || tiny_operand(gqi);
+                        cs_term_fast(gpi, gqi, a[0][0][v], a[0][1][v], a[0][2][v], a[0][3][v]);
+                        cs_term_fast(gqr, gpi, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v], a[NS - 1][3][v]);
+                        cs_term_fast(-gqi, gpr, a[NS - 1][0][v], a[NS - 1][1][v], a[NS - 1][2][v], a[NS - 1][3][v]);
                     }
                 }
             }
         if (odd) {
-            // a product outside the fma test's range: this thread's lanes
-            // again with the exact RD(x y), out of line
+            // a product that may lie outside the fma test's range: this
+            // thread's lanes again with the exact RD(x y), out of line
             double x[4 * R], out[NS * 4 * NL];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
