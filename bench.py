@@ -442,7 +442,7 @@ def _svd_bytes(m, n, sweeps, transformations, c=1):
     return upper, moved
 
 
-def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
+def batched_vs_plain(torch, J, inputs, count, plain_count, flags, ab=True):
     """The first `count` matrices of the batched workload in one call, and a
     sample of `plain_count` of them (stratified by n: every k-th in the order
     of n) one by one through jsvd_gesvj.  Both are priced by the same bytes
@@ -476,11 +476,11 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
         return time.perf_counter() - t0, res, sched, tune_s
     # A: threads per matrix alone (default instance, full grid); B: the
     # widened schedule (dense instances, workgroups per CU); same bits
-    ta, res_a, sched_a, _ = run(0)
+    ta, res_a, sched_a, _ = run(0) if ab else (None, None, None, None)
     tb, res, launch, tune_s = run(J.TUNE_DENSE | J.TUNE_WGS)
-    same = all(a["sweeps"] == b["sweeps"] and bool(torch.equal(a["sv_f"], b["sv_f"])) and
-               bool(torch.equal(a["sv_e"], b["sv_e"])) and bool(torch.equal(a["V_re"], b["V_re"]))
-               for a, b in zip(res_a, res))
+    same = ab and all(a["sweeps"] == b["sweeps"] and bool(torch.equal(a["sv_f"], b["sv_f"])) and
+                      bool(torch.equal(a["sv_e"], b["sv_e"])) and bool(torch.equal(a["V_re"], b["V_re"]))
+                      for a, b in zip(res_a, res))
     del res_a
     errs, up, mv, sweeps = [], np.zeros(count), np.zeros(count), []
     for i, r in enumerate(res):
@@ -520,8 +520,9 @@ def batched_vs_plain(torch, J, inputs, count, plain_count, flags):
                 plain_GBs_upper=float(pu / tp / 1e9), plain_frac_upper=float(pu / tp / 1e9 / HBM_PEAK_GBS),
                 plain_GBs_moved=float(pm / tp / 1e9), plain_frac_moved=float(pm / tp / 1e9 / HBM_PEAK_GBS),
                 schedule=dict(sorted(launch.items())), tune_s=round(tune_s, 3),
-                threads_only_schedule=dict(sorted(sched_a.items())), threads_only_s=ta,
-                threads_only_svds_per_s=count / ta, schedule_gain=ta / tb, schedules_same_bits=same,
+                threads_only_schedule=dict(sorted(sched_a.items())) if ab else None, threads_only_s=ta,
+                threads_only_svds_per_s=count / ta if ab else None, schedule_gain=ta / tb if ab else None,
+                schedules_same_bits=same if ab else None,
                 bit_identical_to_plain="tested (tests/test_gpu_batched.py)")
 
 
@@ -812,6 +813,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched", type=int, default=10000, help="matrices of the batched workload (at most 10000)")
+    ap.add_argument("--no-batched-ab", action="store_true",
+                    help="time the batched workload with the full schedule tuner only, not also with the "
+                         "threads-per-matrix tuner")
     ap.add_argument("--batched-plain", type=int, default=200,
                     help="matrices of the plain-path sample, stratified by n")
     ap.add_argument("--oracle-batched-sample", type=int, default=96,
@@ -831,7 +835,8 @@ def main():
     ap.add_argument("--trace-summary", metavar="DB",
                     help="print the kernel table of a rocprofv3 --kernel-trace --stats database and exit")
     ap.add_argument("--only", default="",
-                    help="comma-separated name prefixes: run only the secondary lines whose names start with one")
+                    help="comma-separated name prefixes: run only the secondary lines whose names start with one "
+                         "(a prefix ending in '=' names one line exactly)")
     ap.add_argument("--counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="print per-kernel HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE databases of runs "
                          "made with --calib-copy, and exit")
@@ -964,7 +969,7 @@ def main():
         if not args.no_batched:
             for nm, fl in (("batched", 0), ("batched_permute", J.PERMUTE)):
                 tasks.append((nm, lambda fl=fl: batched_vs_plain(torch, J, inputs, args.batched, args.batched_plain,
-                                                                 fl)))
+                                                                 fl, ab=not args.no_batched_ab)))
         if not args.no_serve:
             tasks.append(("serving", lambda: serving_run(torch, J, inputs, args.serve_rate, args.serve_seconds,
                                                          args.serve_pool, 0,
@@ -979,7 +984,8 @@ def main():
                 {tg: extra.get(f"svd_{tg}", {}).get("sweeps") for tg in ("r8192x2048", "c4096x4096")},
                 c4_sample=args.oracle_batched_sample)))
         for nm, fn in tasks:
-            if prefixes and not any(nm.startswith(x) for x in prefixes):
+            # a prefix ending in '=' names one line exactly
+            if prefixes and not any(nm == x[:-1] if x.endswith("=") else nm.startswith(x) for x in prefixes):
                 continue
             log(f"[bench] {nm}")
             extra[nm] = fn()

@@ -607,6 +607,35 @@ __global__ void batch_fill_kernel(double *x, size_t count, unsigned long long se
     }
 }
 
+// The candidate schedules of a class: every NT with the default instance and
+// a full grid; with JSVD_TUNE_DENSE the dense instance where the default one
+// takes more than 128 registers; with JSVD_TUNE_WGS also half, 2 and 1
+// workgroups per CU (each below the most that fit).
+static std::vector<BatchSched> class_candidates(bool comp, int cplx, int R, unsigned tuning)
+{
+    std::vector<BatchSched> cand;
+    for (int ci = 0; ci < kNumNT; ++ci) {
+        for (int dense = 0; dense < 2; ++dense) {
+            if (dense && (!(tuning & JSVD_TUNE_DENSE) ||
+                          class_regs(class_kernel_of(comp, cplx, R, kNTs[ci], false)) <= 128))
+                continue;
+            const int per_cu = class_per_cu(class_kernel_of(comp, cplx, R, kNTs[ci], dense != 0), kNTs[ci]);
+            BatchSched sc{kNTs[ci], dense, 0};
+            cand.push_back(sc);
+            if (!(tuning & JSVD_TUNE_WGS)) continue;
+            for (int w : {per_cu / 2, 2, 1}) {
+                bool dup = w < 1 || w >= per_cu;
+                for (const BatchSched &o : cand)
+                    dup = dup || (o.nt == sc.nt && o.dense == sc.dense && o.wpc == w);
+                if (dup) continue;
+                sc.wpc = w;
+                cand.push_back(sc);
+            }
+        }
+    }
+    return cand;
+}
+
 // Measure the threads per matrix of one class: one sweep of up to 1024
 // sample matrices of the class's median shape (random entries), per
 // candidate, after a warm-up; the fastest wins.  Returns 0 on failure.
@@ -633,29 +662,7 @@ static int measure_class(bool comp, int cplx, int R, int m, int n, int ncu, unsi
     BatchItem *ditems = (BatchItem *)tail;
     int *dorder = (int *)(tail + S * sizeof(BatchItem));
     BatchCtl *dctl = (BatchCtl *)(((uintptr_t)(dorder + S) + 255) & ~(uintptr_t)255);
-    // the candidates: every NT; with JSVD_TUNE_DENSE the dense instance where
-    // the default one takes more than 128 registers; with JSVD_TUNE_WGS also
-    // half, 2 and 1 workgroups per CU (each below the most that fit)
-    std::vector<BatchSched> cand;
-    for (int ci = 0; ci < kNumNT; ++ci) {
-        for (int dense = 0; dense < 2; ++dense) {
-            if (dense && (!(tuning & JSVD_TUNE_DENSE) ||
-                          class_regs(class_kernel_of(comp, cplx, R, kNTs[ci], false)) <= 128))
-                continue;
-            const int per_cu = class_per_cu(class_kernel_of(comp, cplx, R, kNTs[ci], dense != 0), kNTs[ci]);
-            BatchSched sc{kNTs[ci], dense, 0};
-            cand.push_back(sc);
-            if (!(tuning & JSVD_TUNE_WGS)) continue;
-            for (int w : {per_cu / 2, 2, 1}) {
-                bool dup = w < 1 || w >= per_cu;
-                for (const BatchSched &o : cand)
-                    dup = dup || (o.nt == sc.nt && o.dense == sc.dense && o.wpc == w);
-                if (dup) continue;
-                sc.wpc = w;
-                cand.push_back(sc);
-            }
-        }
-    }
+    const std::vector<BatchSched> cand = class_candidates(comp, cplx, R, tuning);
     hipEvent_t a = nullptr, b = nullptr;
     int best = 0;
     float best_ms = 0.f;
@@ -701,10 +708,17 @@ static int current_device_ncu(int *dev)
     return ncu;
 }
 
-// the schedule of a class: forced, else measured (once per process and
-// device), else 256 threads with the default instance and grid
+// Trial schedules of the joint refinement (batch_tune), per class, packed (0:
+// none): seen by class_sched on the tuning thread only.
+static thread_local int t_trial[8];
+static thread_local bool t_trial_on = false;
+
+// the schedule of a class: a trial of the joint refinement, forced, else
+// measured (once per process and device), else 256 threads with the default
+// instance and grid
 static BatchSched class_sched(bool comp, int cplx, int R, int m, int n, hipStream_t s, bool measure)
 {
+    if (t_trial_on && t_trial[class_index(cplx, R)]) return sched_unpack(t_trial[class_index(cplx, R)]);
     int dev = 0;
     const int ncu = current_device_ncu(&dev);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -718,19 +732,139 @@ static BatchSched class_sched(bool comp, int cplx, int R, int m, int n, hipStrea
     return sched_unpack(v ? v : 256);
 }
 
+// One sweep of the sample, every class side by side on its own stream as in
+// a real launch, after refilling the sample's G with random entries; the
+// span in milliseconds (negative on failure).
+static float sample_span(const std::vector<BatchItem> &sample, unsigned flags, double *buf, size_t nbuf,
+                         hipEvent_t a, hipEvent_t b, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_fill_kernel, dim3(1024), dim3(256), 0, s, buf, nbuf, 7654321ull);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(a, s) != hipSuccess) return -1.f;
+    BatchLaunch *bl = batch_launch(sample.data(), (int)sample.size(), 1, flags, s, false);
+    if (!bl) return -1.f;
+    float ms = -1.f;
+    if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess)
+        ms = -1.f;
+    (void)hipStreamSynchronize(s);
+    batch_release(bl);
+    return ms;
+}
+
+// Measure the schedules of the classes of these items that are not measured
+// yet.  First each class alone, threads per matrix only (measure_class).
+// Then, when the tuning allows more, a joint refinement: the classes of a
+// batch run side by side and share the compute units, so a class's other
+// candidates are timed on a sample of this batch's own shapes (every class,
+// in the batch's proportions, one sweep), the largest class first, each
+// change kept when it shortens the whole sample's span by more than 1 %.
 void batch_tune(const BatchItem *items, int cnt, unsigned flags, hipStream_t s)
 {
     const bool comp = (flags & JSVD_COMPENSATED) != 0;
-    // the median shape of each class present
-    std::vector<std::pair<double, int>> by[8];
+    int dev = 0;
+    const int ncu = current_device_ncu(&dev);
+    if (dev < 0 || dev >= kMaxDev || cnt <= 0) return;
+    std::vector<int> by[8];
+    double cost[8] = {};
+    for (int i = 0; i < cnt; ++i) {
+        const int k = class_index(items[i].cplx, items[i].R);
+        by[k].push_back(i);
+        cost[k] += (items[i].cplx ? 2.0 : 1.0) * items[i].n * (double)items[i].n * (items[i].m + items[i].n);
+    }
+    std::vector<int> fresh;
+    unsigned tuning = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_forced) return;
+        tuning = g_tuning;
+        for (int k = 0; k < 8; ++k) {
+            if (by[k].empty()) continue;
+            int &t = g_tuned[dev][comp ? 1 : 0][k];
+            if (t) continue;
+            std::vector<std::pair<double, int>> sz;
+            for (int i : by[k]) sz.push_back({(double)items[i].n * items[i].n * items[i].m, i});
+            std::sort(sz.begin(), sz.end());
+            const BatchItem &it = items[sz[sz.size() / 2].second];
+            t = measure_class(comp, it.cplx, it.R, it.m, it.n, ncu, 0, s);
+            if (t) fresh.push_back(k);
+        }
+    }
+    if (fresh.empty() || !(tuning & (JSVD_TUNE_DENSE | JSVD_TUNE_WGS))) return;
+    // the sample: evenly spaced members of each class, in the batch's
+    // proportions, at most 2048 matrices and 512 MiB of G and V
+    double total_bytes = 0.0;
     for (int i = 0; i < cnt; ++i)
-        by[class_index(items[i].cplx, items[i].R)].push_back({(double)items[i].n * items[i].n * items[i].m, i});
+        total_bytes += 8.0 * (items[i].cplx ? 2 : 1) * ((double)items[i].m * items[i].n + (double)items[i].n * items[i].n);
+    const double frac = std::min(1.0, std::min(2048.0 / cnt, (double)(512u << 20) / total_bytes));
+    std::vector<int> pick;
     for (int k = 0; k < 8; ++k) {
         if (by[k].empty()) continue;
-        std::sort(by[k].begin(), by[k].end());
-        const BatchItem &it = items[by[k][by[k].size() / 2].second];
-        (void)class_sched(comp, it.cplx, it.R, it.m, it.n, s, true);
+        const int want = std::max(1, (int)(frac * by[k].size() + 0.5));
+        for (int j = 0; j < want; ++j) pick.push_back(by[k][(size_t)j * by[k].size() / want]);
     }
+    size_t nbuf = 0;
+    for (int i : pick) {
+        const size_t c = items[i].cplx ? 2 : 1;
+        nbuf += c * ((size_t)items[i].m * items[i].n + (size_t)items[i].n * items[i].n) + 2 * (size_t)items[i].n;
+    }
+    double *buf = nullptr;
+    if (hipMalloc(&buf, nbuf * sizeof(double)) != hipSuccess) return;
+    std::vector<BatchItem> sample;
+    size_t off = 0;
+    for (int i : pick) {
+        const int m = items[i].m, n = items[i].n, c = items[i].cplx;
+        double *G = buf + off;
+        double *V = G + (size_t)(c ? 2 : 1) * m * n;
+        double *e = V + (size_t)(c ? 2 : 1) * n * n;
+        sample.push_back(make_batch_item(m, n, c, G, c ? G + (size_t)m * n : nullptr, m, V,
+                                         c ? V + (size_t)n * n : nullptr, n, e, e + n));
+        off += (size_t)(c ? 2 : 1) * ((size_t)m * n + (size_t)n * n) + 2 * (size_t)n;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int k = 0; k < 8; ++k) t_trial[k] = g_tuned[dev][comp ? 1 : 0][k];
+    }
+    t_trial_on = true;
+    auto span = [&]() {
+        float best = -1.f;
+        for (int rep = 0; ok && rep < 2; ++rep) {
+            const float ms = sample_span(sample, flags, buf, nbuf, a, b, s);
+            if (ms < 0.f) ok = false;
+            else if (best < 0.f || ms < best) best = ms;
+        }
+        return best;
+    };
+    (void)span();   // warm-up
+    float best = span();
+    std::sort(fresh.begin(), fresh.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    for (int k : fresh) {
+        if (!ok) break;
+        const BatchItem &it = items[by[k][0]];
+        const int cur = t_trial[k];
+        int keep = cur;
+        for (const BatchSched &sc : class_candidates(comp, it.cplx, it.R, tuning)) {
+            const int v = sched_pack(sc);
+            if (v == cur || !ok) continue;
+            t_trial[k] = v;
+            const float ms = span();
+            if (ok && ms > 0.f && ms < 0.99f * best) {
+                best = ms;
+                keep = v;
+            }
+        }
+        t_trial[k] = keep;
+    }
+    t_trial_on = false;
+    if (ok) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (int k : fresh) g_tuned[dev][comp ? 1 : 0][k] = t_trial[k];
+    }
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
 }
 
 BatchSched batch_sched_of(int m, int n, int cplx, unsigned flags)
