@@ -55,6 +55,14 @@ def lib():
         L.ora_omp_max_threads.restype = i
         L.ora_set_step_threads.restype = None
         L.ora_set_step_threads.argtypes = [i]
+        L.ora_set_exact.restype = None
+        L.ora_set_exact.argtypes = [i]
+        L.ora_get_exact.restype = i
+        L.ora_get_exact.argtypes = []
+        L.ora_colnorm_exact.restype = None
+        L.ora_colnorm_exact.argtypes = [i, _dp, _dp, _dp, _dp]
+        L.ora_dpscl_exact.restype = None
+        L.ora_dpscl_exact.argtypes = [i, _dp, _dp, _dp, _dp, d, d, d, d, _dp, _dp]
         L.ora_hypot.restype = d
         L.ora_hypot.argtypes = [d, d]
         L.ora_getexp.restype = i
@@ -260,6 +268,39 @@ def dpscl(qr, qi, pr, pi, eq, fq, ep, fp):
     pi = None if pi is None else _np.ascontiguousarray(pi, dtype=_np.float64)
     lib().ora_dpscl(qr.shape[0], _p(qr), _p(qi), _p(pr), _p(pi), eq, fq, ep, fp, zr, zi)
     return zr.value, zi.value
+
+
+def colnorm_exact(xr, xi=None):
+    """The exact mode's column norm: binary128 sum of squares, sqrt, rounded once."""
+    e, f = _ct.c_double(), _ct.c_double()
+    xr = _np.ascontiguousarray(xr, dtype=_np.float64)
+    xi = None if xi is None else _np.ascontiguousarray(xi, dtype=_np.float64)
+    lib().ora_colnorm_exact(xr.shape[0], _p(xr), _p(xi), e, f)
+    return e.value, f.value
+
+
+def dpscl_exact(qr, qi, pr, pi, eq, fq, ep, fp):
+    """The exact mode's scaled dot-product: binary128 sum rounded once, then / fl(fq fp)."""
+    zr, zi = _ct.c_double(), _ct.c_double()
+    qr, pr = (_np.ascontiguousarray(a, dtype=_np.float64) for a in (qr, pr))
+    qi = None if qi is None else _np.ascontiguousarray(qi, dtype=_np.float64)
+    pi = None if pi is None else _np.ascontiguousarray(pi, dtype=_np.float64)
+    lib().ora_dpscl_exact(qr.shape[0], _p(qr), _p(qi), _p(pr), _p(pi), eq, fq, ep, fp, zr, zi)
+    return zr.value, zi.value
+
+
+class exact_mode:
+    """Context manager: the iteration (State, gesvj) uses the exact mode's
+    norms and dot-products inside the block."""
+
+    def __enter__(self):
+        self._old = lib().ora_get_exact()
+        lib().ora_set_exact(1)
+        return self
+
+    def __exit__(self, *exc):
+        lib().ora_set_exact(self._old)
+        return False
 
 
 def mul_rd(a, b):

@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["ora_evd2.c", "ora_sevd2.c", "ora_svd.c", "ora_ssvd.c", "ora_nrmf.c"]
+SOURCES = ["ora_evd2.c", "ora_sevd2.c", "ora_svd.c", "ora_ssvd.c", "ora_nrmf.c", "ora_exact.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-finite-math-only", "-frounding-math",
           "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra", "-D_GNU_SOURCE"]
@@ -18,7 +18,7 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fno-finite
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc"] + CFLAGS + ["-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lm"]
+    cmd = ["gcc"] + CFLAGS + ["-o", tmp] + [os.path.join(HERE, s) for s in SOURCES] + ["-lquadmath", "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

@@ -471,6 +471,22 @@ int ora_init(ora_svd *st)
  * depend on the thread count. */
 static int g_step_threads = 1;
 
+/* The oracle's exact mode (ora_exact.c): the iteration takes its column
+ * norms and scaled dot-products from binary128 sums rounded once, instead
+ * of the ordered 1024-lane sums (it supersedes the compensated
+ * dot-product).  Off by default; the GPU path reproduces the ordered mode. */
+static int g_exact = 0;
+void ora_set_exact(int on) { g_exact = on != 0; }
+int ora_get_exact(void) { return g_exact; }
+
+static void norm_of(int m, const double *xr, const double *xi, double *e, double *f)
+{
+    if (g_exact)
+        ora_colnorm_exact(m, xr, xi, e, f);
+    else
+        ora_colnorm(m, xr, xi, e, f);
+}
+
 void ora_set_step_threads(int nthreads) { g_step_threads = nthreads > 1 ? nthreads : 1; }
 
 void ora_step(ora_svd *st)
@@ -499,8 +515,8 @@ void ora_step(ora_svd *st)
     for (int l = 0; l < npairs; ++l) {
         int p, q;
         if (!ora_rr_pair(n, kk, l, &p, &q)) continue;
-        ora_colnorm(m, COLR(st, p), COLI(st, p), &st->e[p], &st->f[p]);
-        ora_colnorm(m, COLR(st, q), COLI(st, q), &st->e[q], &st->f[q]);
+        norm_of(m, COLR(st, p), COLI(st, p), &st->e[p], &st->f[p]);
+        norm_of(m, COLR(st, q), COLI(st, q), &st->e[q], &st->f[q]);
     }
 
     /* tolerance upsilon = fl(eps sqrt m), eps = 2^-53 (eq. tol) */
@@ -521,7 +537,9 @@ void ora_step(ora_svd *st)
             /* a zero column: never rotated; the zero column goes last */
             pbit = isinf(ep) && !isinf(eq);
         } else {
-            if (st->comp)
+            if (g_exact)
+                ora_dpscl_exact(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
+            else if (st->comp)
                 ora_dpscl_cs(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
             else
                 ora_dpscl(m, COLR(st, q), COLI(st, q), COLR(st, p), COLI(st, p), eq, fq, ep, fp, &zr, &zi);
@@ -603,7 +621,7 @@ void ora_finalize(ora_svd *st, double *sv_e, double *sv_f)
     double *tmpv = (double *)malloc(sizeof(double) * (size_t)n * (size_t)n * 2);
     /* U = G diag(2^-e) / f, column by column (Sect. 4.2.1) */
     for (int j = 0; j < n; ++j) {
-        ora_colnorm(m, COLR(st, j), COLI(st, j), &e[j], &f[j]);
+        norm_of(m, COLR(st, j), COLI(st, j), &e[j], &f[j]);
         const int zero = isinf(e[j]);
         const int E = zero ? 0 : (int)e[j];
         for (int i = 0; i < m; ++i) {
@@ -685,7 +703,7 @@ int ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
          * current column norms, backscaled, in column order */
         for (int j = 0; j < n; ++j) {
             double e, f;
-            ora_colnorm(m, Gr + (size_t)j * ldg, Gi ? Gi + (size_t)j * ldg : NULL, &e, &f);
+            norm_of(m, Gr + (size_t)j * ldg, Gi ? Gi + (size_t)j * ldg : NULL, &e, &f);
             sv_e[j] = e - (double)st.s;
             sv_f[j] = f;
         }

@@ -189,6 +189,14 @@ void ora_finalize(ora_svd *st, double *sv_e, double *sv_f);
 /* threads of the loops over a step's pairs (default 1); results do not
  * depend on it */
 void ora_set_step_threads(int nthreads);
+/* The exact mode (ora_exact.c): column norms and scaled dot-products of the
+ * iteration from binary128 sums rounded once to double (superseding the
+ * compensated dot-product); 0 = the ordered 1024-lane mode, the default. */
+void ora_set_exact(int on);
+int ora_get_exact(void);
+void ora_colnorm_exact(int m, const double *xr, const double *xi, double *e, double *f);
+void ora_dpscl_exact(int m, const double *qr, const double *qi, const double *pr, const double *pi,
+                     double eq, double fq, double ep, double fp, double *zr, double *zi);
 int  ora_gesvj(int m, int n, double *Gr, double *Gi, size_t ldg,
                double *Vr, double *Vi, size_t ldv,
                double *sv_e, double *sv_f, int max_sweeps, int *sweeps, long *steps,
