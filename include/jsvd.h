@@ -155,6 +155,9 @@ typedef struct {
     int64_t last_sweep_gs;    /* Gram-Schmidt steps in the last completed sweep */
     int64_t loop_sweeps;      /* sweeps since the load that ran as one persistent launch */
     int64_t loop_redos;       /* persistent sweeps that gave up and were redone step by step */
+    int64_t skipped_pairs;    /* pairs of large-column steps since the load that were not read:
+                                 both columns unchanged since the pair last met, one sweep
+                                 earlier, so its outcome is that meeting's (no change) */
 } jsvd_info;
 
 /* Allocate a state for an m x n real (is_complex = 0) or complex problem,

@@ -52,7 +52,7 @@ class _Info(_ct.Structure):
                 ("rescaled", _ct.c_int32), ("Mt", _ct.c_double), ("converged", _ct.c_int32),
                 ("status", _ct.c_int32), ("last_sweep_T", _ct.c_int64), ("last_sweep_swaps", _ct.c_int64),
                 ("gs", _ct.c_int64), ("last_sweep_gs", _ct.c_int64), ("loop_sweeps", _ct.c_int64),
-                ("loop_redos", _ct.c_int64)]
+                ("loop_redos", _ct.c_int64), ("skipped_pairs", _ct.c_int64)]
 
 
 class ServeConfig(_ct.Structure):

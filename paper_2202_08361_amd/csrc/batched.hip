@@ -58,7 +58,7 @@ struct BatchSmem {
     static constexpr int NN = MM < kBMaxN ? MM : kBMaxN;
     static constexpr int NW = NT / 64;
     double e[NN], f[NN];
-    int rank[NN], inv[NN];
+    int rank[NN], inv[NN];   // the final sort; rank holds each column's last-change step before it
     double tmp[2 * (MM + NN)];
     double wM[NW];
     unsigned long long wt[NW], wsw[NW];
@@ -172,6 +172,9 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
         }
     }
     double Mt = scal2(M0, s);
+    // per column, the step that last changed it (sm.rank, free until the
+    // finalisation): the scaling above counts as a change at step 0
+    for (int j = tid; j < n; j += kBT) sm.rank[j] = 0;
     __syncthreads();
 
     const int N = n + (n & 1), K = N - 1, npairs = N / 2;
@@ -192,13 +195,18 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
                 double *const Gpr = Gr + (size_t)p * ldg;
                 double *const Gpi = CPLX ? Gi + (size_t)p * ldg : nullptr;
                 if (!valid) {
-                    if (rescale)
+                    if (rescale) {
                         for (int i = lane; i < m; i += 64) {
                             Gpr[i] = scal2(Gpr[i], sp);
                             if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
                         }
+                        if (lane == 0) sm.rank[p] = (int)k;
+                    }
                     continue;
                 }
+                // both columns unchanged since the pair last met, one sweep
+                // ago: that meeting's outcome (no change) holds, nothing to read
+                if (!rescale && sm.rank[p] < k - K && sm.rank[q] < k - K) continue;
                 double *const Gqr = Gr + (size_t)q * ldg;
                 double *const Gqi = CPLX ? Gi + (size_t)q * ldg : nullptr;
                 double xr[2][R], xi[2][R];
@@ -243,6 +251,10 @@ __device__ void svd_workgroup(BatchItem &it, int max_sweeps, int nosort, int nog
                                 Dq_i[i] = xi[1][j];
                             }
                         }
+                    }
+                    if (lane == 0) {
+                        sm.rank[p] = (int)k;
+                        sm.rank[q] = (int)k;
                     }
                 }
                 if (dc.transform || pbit) {

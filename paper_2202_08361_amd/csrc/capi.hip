@@ -128,7 +128,7 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct StateLayout {
     long long ldg, ldv, vstride;
-    size_t oG, oV, oE, oF, oR, oS, oM, oP, oQ, oX, oH;
+    size_t oG, oV, oE, oF, oR, oS, oM, oP, oQ, oX, oH, oT;
     size_t oLV, oLA, oLC, oLB, oLZ;   // persistent sweeps (m <= 256): flags, folds, sums, abort, snapshot
     size_t total;
 };
@@ -158,6 +158,8 @@ static StateLayout state_layout(int m, int n, int cplx, size_t es)
     L.oQ = off; off = align_up(off + sizeof(double) * (size_t)L.vstride * kVlogSlots);
     L.oH = off; off = align_up(off + sizeof(StepHdr) * (size_t)kVlogSlots);
     L.oX = off; off = align_up(off + sizeof(unsigned long long) * (size_t)kVlogSlots);
+    // per column, the step that last changed it (large-column steps)
+    L.oT = off; off = align_up(off + sizeof(long long) * (size_t)n);
     L.oLV = L.oLA = L.oLC = L.oLB = L.oLZ = 0;
     if (loop_candidate_shape(m)) {
         const size_t npairs = (size_t)(n + 1) / 2;
@@ -205,6 +207,7 @@ static void fill_desc(SvdDescT<T> &d, int m, int n, int cplx, char *b, const Sta
     d.sc = (DevScalars *)(b + L.oS);
     d.lgbound = lgbound;
     d.ups = ups;
+    d.lastmod = (long long *)(b + L.oT);
 }
 
 static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out)
@@ -369,6 +372,7 @@ static int load_async_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg,
     st->vlog_n = 0;
     st->vlast = -1;
     st->v_layout = V_EITHER;
+    st->lastmod_valid = 0;
     return JSVD_OK;
 }
 
@@ -422,6 +426,8 @@ static unsigned iter_flags_of(jsvd_state st) { return st->fp32 ? kIterFlagsF32 :
 
 static void apply_flags(jsvd_state st, unsigned flags)
 {
+    // a pair's earlier decision holds only under the same flags
+    if (flags != st->flags) st->lastmod_valid = 0;
     st->flags = flags;
     const int nosort = iter_nosort(flags);
     const int comp = (flags & JSVD_COMPENSATED) ? 1 : 0;
@@ -528,6 +534,7 @@ static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s, bool defer = f
         const hipError_t e = launch_step(d, state_threads(st), slot_of(st, jf), prev, s);
         if (e != hipSuccess) return e;
         st->vlast = jf;
+        st->lastmod_valid = 0;   // this kernel changes columns without recording it
         return hipSuccess;
     }
     const int j = st->vbase + st->vlog_n;
@@ -537,6 +544,11 @@ static hipError_t launch_one_step_t(jsvd_state st, hipStream_t s, bool defer = f
         if (e != hipSuccess) return e;
     }
     if (st->vlast >= 0) prev = slot_of(st, st->vlast);
+    if (!st->lastmod_valid) {
+        const hipError_t e = launch_lastmod_reset(d, prev, s);
+        if (e != hipSuccess) return e;
+        st->lastmod_valid = 1;
+    }
     const hipError_t e = launch_gpair(d, slot_of(st, j), prev, s);
     if (e != hipSuccess) return e;
     st->vlast = j;
@@ -731,6 +743,18 @@ extern "C" int jsvd_sweep(jsvd_state st, void *stream)
     HIPCHK(set_v_layout(st, path_layout(st), (hipStream_t)stream));
     HIPCHK(flush_vlog(st, (hipStream_t)stream));
     HIPCHK(settle(st, (hipStream_t)stream));
+    // the last-change steps are reset here, outside the graph: inside it the
+    // reset would run again at every replay and no pair would ever be skipped
+    if (uses_gpair(st) && !st->lastmod_valid) {
+        StepSlot none;
+        none.prm = nullptr;
+        none.mx = nullptr;
+        none.hdr = nullptr;
+        none.mxkey = nullptr;
+        HIPCHK(st->fp32 ? launch_lastmod_reset(st->df, none, (hipStream_t)stream)
+                        : launch_lastmod_reset(st->d, none, (hipStream_t)stream));
+        st->lastmod_valid = 1;
+    }
     const int rc = build_graph(st);
     if (rc != JSVD_OK) return rc;
     HIPCHK(hipGraphLaunch(st->graph, (hipStream_t)stream));
@@ -806,6 +830,7 @@ extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
     out->last_sweep_gs = h.GS_prev;
     out->loop_sweeps = h.loop_sweeps;
     out->loop_redos = st->loop_redos;
+    out->skipped_pairs = h.skipped;
     return JSVD_OK;
 }
 
@@ -874,6 +899,7 @@ static int restore_t(jsvd_state st, const T *G_re, const T *G_im, size_t ldg, co
     st->vlog_n = 0;
     st->vlast = -1;
     st->v_layout = V_COLS;
+    st->lastmod_valid = 0;
     // the pushed scalars start the persistent sweeps' flag epochs again at 0,
     // so the flags are cleared with them
     if (st->loop_cand) HIPCHK(hipMemsetAsync(st->loop.ver, 0, sizeof(unsigned long long) * (size_t)st->n, s));

@@ -29,24 +29,25 @@ __device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *p
 {
     constexpr int NW = FW / 64;
     __shared__ double smx[NW];
-    __shared__ unsigned long long scnt[3 * NW];
+    __shared__ unsigned long long scnt[4 * NW];
     DevScalars *sc = d.sc;
     const int t = threadIdx.x;
     // the scalars the fold updates, loaded (by thread 0) beside the outcomes
     unsigned long long Mt_bits = 0;
-    long long T0 = 0, SW0 = 0, GS0 = 0, k0 = 0;
+    long long T0 = 0, SW0 = 0, GS0 = 0, k0 = 0, SK0 = 0;
     int s0 = 0, resc0 = 0;
     if (t == 0) {
         Mt_bits = sc->Mt_bits;
         T0 = sc->T;
         SW0 = sc->SW;
         GS0 = sc->GS;
+        SK0 = sc->skipped;
         k0 = sc->k;
         s0 = sc->s;
         resc0 = sc->rescaled;
     }
     double mx = 0.0;
-    unsigned long long tc = 0, swc = 0, gsc = 0;
+    unsigned long long tc = 0, swc = 0, gsc = 0, skc = 0;
     // four outcomes per thread in flight at once (the log was written by
     // other compute units: each load goes past this one's L2)
     for (int l0 = 0; l0 < npairs; l0 += 4 * FW) {
@@ -71,6 +72,7 @@ __device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *p
             } else if (fl[u] & 2) {
                 ++swc;
             }
+            if (fl[u] & 8) ++skc;
         }
     }
     mx = wave_max(mx);
@@ -79,22 +81,25 @@ __device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *p
         tc += __shfl_xor(tc, h, 64);
         swc += __shfl_xor(swc, h, 64);
         gsc += __shfl_xor(gsc, h, 64);
+        skc += __shfl_xor(skc, h, 64);
     }
     if ((t & 63) == 0) {
         smx[t >> 6] = mx;
         scnt[t >> 6] = tc;
         scnt[NW + (t >> 6)] = swc;
         scnt[2 * NW + (t >> 6)] = gsc;
+        scnt[3 * NW + (t >> 6)] = skc;
     }
     __syncthreads();
     if (t == 0) {
         double M = smx[0];
-        unsigned long long tt = scnt[0], sw = scnt[NW], gg = scnt[2 * NW];
+        unsigned long long tt = scnt[0], sw = scnt[NW], gg = scnt[2 * NW], sk = scnt[3 * NW];
         for (int w = 1; w < NW; ++w) {
             M = fmax(M, smx[w]);
             tt += scnt[w];
             sw += scnt[NW + w];
             gg += scnt[2 * NW + w];
+            sk += scnt[3 * NW + w];
         }
         const T Mt = (T)bits2d(Mt_bits);
         const bool rescale = (d.cplx ? SvdFp<T>::round_cplx : SvdFp<T>::round_real) - getexp(Mt) < 0;
@@ -105,6 +110,7 @@ __device__ unsigned long long fold_step(const SvdDescT<T> &d, const PairParam *p
         sc->T = T0 + (long long)tt;
         sc->SW = SW0 + (long long)sw;
         sc->GS = GS0 + (long long)gg;
+        sc->skipped = SK0 + (long long)sk;
         sc->last_t = (long long)tt;
         if (rescale) {
             sc->s = s0 + sp;

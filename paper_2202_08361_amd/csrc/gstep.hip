@@ -48,6 +48,24 @@ constexpr int gpair_wgs_per_cu()
     return 2;
 }
 
+// rows t + W j (j < R) of the pair's columns into registers, 0 beyond m
+template <bool CPLX, int W, int R, typename T>
+__device__ __forceinline__ void gpair_load(T (&xr)[2][R], T (&xi)[2][R], const T *Gpr, const T *Gqr, const T *Gpi,
+                                           const T *Gqi, int m, int t)
+{
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = t + W * j;
+        const bool in = i < m;
+        xr[0][j] = in ? Gpr[i] : T(0);
+        xr[1][j] = in ? Gqr[i] : T(0);
+        if (CPLX) {
+            xi[0][j] = in ? Gpi[i] : T(0);
+            xi[1][j] = in ? Gqi[i] : T(0);
+        }
+    }
+}
+
 // G part of the step: one workgroup of W = 256 threads per pivot pair, the
 // pair held in registers from its load to its store.  Several workgroups
 // share a compute unit, so one computes (reductions, EVD) while the others
@@ -93,20 +111,15 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
     T *const Gqr = d.Gr + (size_t)q * d.ldg;
     T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
     T *const Gqi = CPLX ? d.Gi + (size_t)q * d.ldg : nullptr;
+    // A pair whose two columns have not changed since it last met, one sweep
+    // (K steps) earlier: its norms, dot-product and decision are the same bits
+    // as at that meeting, which left both columns as they were (neither
+    // rotated nor swapped them).  It is not read again, unless this step
+    // rescales every column.
+    const long long K = (long long)(n + (n & 1)) - 1;
+    const bool unchanged = valid && d.lastmod[p] < k - K && d.lastmod[q] < k - K;
     T xr[2][R], xi[2][R];
-    if (valid) {
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int i = t + W * j;
-            const bool in = i < m;
-            xr[0][j] = in ? Gpr[i] : T(0);
-            xr[1][j] = in ? Gqr[i] : T(0);
-            if (CPLX) {
-                xi[0][j] = in ? Gpi[i] : T(0);
-                xi[1][j] = in ? Gqi[i] : T(0);
-            }
-        }
-    }
+    if (valid && !unchanged) gpair_load<CPLX, W, R>(xr, xi, Gpr, Gqr, Gpi, Gqi, m, t);
     // floor(lg M~) of this step, which is all the rescaling check needs
     int eMt;
     if (prev.prm) {
@@ -147,12 +160,21 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
                 Gpr[i] = scal2(Gpr[i], sp);
                 if (CPLX) Gpi[i] = scal2(Gpi[i], sp);
             }
+            if (t == 0) d.lastmod[p] = k;
         }
         if (t == 0) {
             prm[l] = pp;
             slot.mx[l] = pmx;
         }
+    } else if (unchanged && !rescale) {
+        // the outcome of the pair's last meeting: nothing to do
+        if (t == 0) {
+            pp.flag = 8;
+            prm[l] = pp;
+            slot.mx[l] = pmx;
+        }
     } else {
+        if (unchanged) gpair_load<CPLX, W, R>(xr, xi, Gpr, Gqr, Gpi, Gqi, m, t);
         if (rescale) {
 #pragma unroll
             for (int j = 0; j < R; ++j)
@@ -193,6 +215,10 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
                     }
                 }
             }
+            if (t == 0) {
+                d.lastmod[p] = k;
+                d.lastmod[q] = k;
+            }
         }
         if (t == 0) {
             prm[l] = pp;
@@ -207,6 +233,24 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
     }
 }
 
+
+// every column's last change := the step about to run
+template <typename T>
+__global__ void lastmod_reset_kernel(SvdDescT<T> d, StepSlot prev)
+{
+    const long long k = prev.prm ? prev.hdr->k + 1 : *(volatile long long *)&d.sc->k;
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d.n; j += gridDim.x * blockDim.x) d.lastmod[j] = k;
+}
+
+template <typename T>
+hipError_t launch_lastmod_reset(const SvdDescT<T> &d, StepSlot prev, hipStream_t s)
+{
+    const int blocks = (d.n + 255) / 256;
+    hipLaunchKernelGGL((lastmod_reset_kernel<T>), dim3(blocks < 64 ? blocks : 64), dim3(256), 0, s, d, prev);
+    return hipGetLastError();
+}
+template hipError_t launch_lastmod_reset<double>(const SvdDescT<double> &, StepSlot, hipStream_t);
+template hipError_t launch_lastmod_reset<float>(const SvdDescT<float> &, StepSlot, hipStream_t);
 
 // the fold of one step as a kernel of its own: the G kernel's workgroups do
 // not see each other's outcomes before that launch has ended
@@ -237,7 +281,9 @@ __device__ __forceinline__ void vacc_load(VaccPairs<PPT, T> &o, const PairParam 
         const uint4 *const P = reinterpret_cast<const uint4 *>(pl + (l < np ? l : 0));
         const uint4 a = P[0], b = P[1];
         const int pq = (int)b.z, f = (int)b.w;
-        o.f[u] = l < np ? f : 0;
+        // rotation or swap only (bit 2 marks a Gram-Schmidt rotation, which V
+        // takes as any other; bit 3 a pair that was not read: no change)
+        o.f[u] = l < np ? (f & 3) : 0;
         o.p[u] = pq & 0xFFFF;
         o.q[u] = pq >> 16;
         o.c[u] = (T)__hiloint2double((int)a.y, (int)a.x);

@@ -57,6 +57,7 @@ struct DevScalars {
     int loop_epoch;               // persistent sweeps launched (tags the column flags)
     int loop_redo;                // the last persistent sweep gave up: redo it step by step
     long long loop_sweeps;        // sweeps completed as persistent launches
+    long long skipped;            // pairs of large-column steps not read: unchanged since they last met
 };
 
 // Problem description shared by the SVD kernels, for the working precision T
@@ -78,6 +79,10 @@ struct SvdDescT {
     DevScalars *sc;
     int lgbound;           // floor(lg(nu/(varsigma m))) of eq. (skn), nu = DBL_MAX or FLT_MAX
     T ups;                 // fl(sqrt(m)) eps, eps = 2^-53 or 2^-24
+    // per column, the step that last changed it (read and kept by the
+    // large-column G kernel only; other steps leave it stale, and the host
+    // resets it before the G kernel runs again)
+    long long *lastmod;
 };
 using SvdDesc = SvdDescT<double>;
 using SvdDescF = SvdDescT<float>;
@@ -90,7 +95,8 @@ struct alignas(16) PairParam {
     double c, C, S;   // cos phi, e^{i alpha} tan phi
     int pq;           // the pair: p | q << 16
     int flag;         // bit 0: transform (rotation of V, counted), bit 1: swap the columns
-                      // (permutation P), bit 2: G took the Gram-Schmidt step of eq. (GS)
+                      // (permutation P), bit 2: G took the Gram-Schmidt step of eq. (GS),
+                      // bit 3: not read, unchanged since its last meeting (counted)
 };
 static_assert(sizeof(PairParam) == 32, "PairParam is two 16-byte loads");
 
@@ -127,6 +133,12 @@ template <typename T>
 hipError_t launch_gpair(const SvdDescT<T> &d, StepSlot slot, StepSlot prev, hipStream_t s);
 template <typename T>
 hipError_t launch_fold(const SvdDescT<T> &d, const PairParam *prm, const double *mx, hipStream_t s);
+// every column's last change set to the step about to run (k from the
+// previous slot when its fold is still due, else from the device scalars):
+// no pair of the large-column steps is skipped before a whole sweep of them
+// has met it
+template <typename T>
+hipError_t launch_lastmod_reset(const SvdDescT<T> &d, StepSlot prev, hipStream_t s);
 template <typename T>
 hipError_t launch_vacc(const SvdDescT<T> &d, const PairParam *plog, long long stride, int nsteps, hipStream_t s);
 template <typename T>

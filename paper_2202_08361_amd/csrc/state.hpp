@@ -49,6 +49,7 @@ struct jsvd_state_s {
     unsigned loop_graph_flags;
     unsigned long long loop_graph_budget;
     long long loop_redos;    // persistent sweeps that gave up and were redone step by step
+    int lastmod_valid;       // the per-column last-change steps are current (only large-column steps ran since their reset)
 };
 
 namespace jsvd {

@@ -429,6 +429,7 @@ __global__ void init_scalars_kernel(SvdDescT<T> d, const unsigned long long *max
     sc->loop_ok = 0;
     sc->loop_redo = 0;
     sc->loop_sweeps = 0;
+    sc->skipped = 0;
     if (!(M0 < T(INFINITY)) || M0 == T(0)) {
         sc->status = (M0 == T(0)) ? -3 : -2;
         sc->stop = 1;
