@@ -664,20 +664,29 @@ def svd_plain(torch, J, inputs, flags, fp32=False):
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
-def svd_plain_sweeps(torch, J, inputs, persistent):
-    """The 256 x 256 workload through the state API (load, jsvd_state_iterate,
-    finalize), with persistent sweeps or with step-by-step sweeps (a zero
-    wait budget turns persistent sweeps off): the A/B of the two sweep forms
-    on the same iteration (the same bits, tested)."""
+def svd_plain_sweeps(torch, J, inputs, persistent, shape=None):
+    """The 256 x 256 workload (or an m x n x complex `shape`, sigma
+    log-spaced in [1e-6, 1]) through the state API (load,
+    jsvd_state_iterate, finalize), with persistent sweeps or with step-by-step
+    sweeps (a zero wait budget turns persistent sweeps off): the A/B of the two
+    sweep forms on the same iteration (the same bits, tested)."""
     import numpy as np
-    A, sig = inputs.plain_real_256()
+    if shape is None:
+        A, sig = inputs.plain_real_256()
+        Ai, m, n, cplx = None, 256, 256, False
+    else:
+        m, n, cplx = shape
+        g = inputs.rng(inputs.CFG_PLAIN_LARGE, 4400 + m + n)
+        sig = inputs.sigma_logspace(n, 1e-6)
+        A, Ai = inputs.svd_matrix(m, n, sig, g, cplx=cplx)
     dA = J.to_device_fortran(A)
+    dAi = J.to_device_fortran(Ai) if cplx else None
     best, q = None, None
     for rep in range(3):
-        st = J.State(256, 256, False)
+        st = J.State(m, n, cplx)
         if not persistent:
             st.set_loop_wait(0.0)
-        st.load(dA)
+        st.load(dA, dAi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st.iterate()
@@ -688,9 +697,9 @@ def svd_plain_sweeps(torch, J, inputs, persistent):
         st.close()
         best = dt if best is None else min(best, dt)
     sv = r["sv"].cpu().numpy()
-    K = 255
-    return dict(ms=best * 1e3, sweeps=q["sweeps"], persistent_sweeps=q["loop_sweeps"], redone=q["loop_redos"],
-                us_per_step=best * 1e6 / ((q["sweeps"] + 1) * K),
+    K = n - 1 if n % 2 == 0 else n
+    return dict(m=m, n=n, complex=bool(cplx), ms=best * 1e3, sweeps=q["sweeps"], persistent_sweeps=q["loop_sweeps"],
+                redone=q["loop_redos"], us_per_step=best * 1e6 / ((q["sweeps"] + 1) * K),
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
@@ -960,6 +969,11 @@ def main():
             tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl)))
         for nm, pers in (("svd_real256_persistent_sweeps", True), ("svd_real256_stepwise_sweeps", False)):
             tasks.append((nm, lambda pers=pers: svd_plain_sweeps(torch, J, inputs, pers)))
+        # mid-size matrices (the persistent sweep with 256-thread workgroups)
+        for (m, n, c) in ((1024, 256, False), (1000, 300, True)):
+            for nm, pers in (("persistent_sweeps", True), ("stepwise_sweeps", False)):
+                tasks.append((f"svd_mid_{tag(m, n, c)}_{nm}",
+                              lambda m=m, n=n, c=c, pers=pers: svd_plain_sweeps(torch, J, inputs, pers, (m, n, c))))
         for (m, n, c) in big:
             for fp32 in (False, True):
                 tasks.append((f"sweep_{tag(m, n, c)}" + ("_f32" if fp32 else ""),

@@ -129,12 +129,12 @@ static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct StateLayout {
     long long ldg, ldv, vstride;
     size_t oG, oV, oE, oF, oR, oS, oM, oP, oQ, oX, oH, oT;
-    size_t oLV, oLA, oLC, oLB, oLZ;   // persistent sweeps (m <= 256): flags, folds, sums, abort, snapshot
+    size_t oLV, oLA, oLC, oLB, oLZ;   // persistent sweeps (m <= 1024): flags, folds, sums, abort, snapshot
     size_t total;
 };
 
 // states whose sweeps may run as one persistent launch
-static bool loop_candidate_shape(int m) { return m <= 256; }
+static bool loop_candidate_shape(int m) { return m <= loop_max_rows(); }
 
 // es: bytes per element of the working precision
 static StateLayout state_layout(int m, int n, int cplx, size_t es)
@@ -577,12 +577,20 @@ static hipError_t loop_check(jsvd_state st, hipStream_t s)
     return st->fp32 ? launch_loop_check(st->df, st->colsq, s) : launch_loop_check(st->d, st->colsq, s);
 }
 
+// Pair slots up to which a persistent sweep beats the step-by-step one
+// (measured, whole SVDs: n = 256: 1.35-1.41x, n = 300: 1.21-1.23x, n = 384:
+// 1.06-1.13x, n = 512: 0.86-0.99x, n = 1024: 0.53x).  Each step of the
+// persistent sweep writes back and invalidates caches per workgroup, and
+// with more workgroups that costs more than the launch boundary it saves.
+constexpr int kLoopMaxPairs = 192;
+
 // The sweep of this state may run as one persistent launch: a state with
-// the loop's workspace on the one-wavefront-per-pair path (automatic launch
-// shape) whose pair slots are all resident at once.
+// the loop's workspace (automatic launch shape) of at most kLoopMaxPairs
+// pair slots, all resident at once.
 static bool loop_usable(jsvd_state st)
 {
-    if (!st->loop_cand || st->threads != 0 || uses_gpair(st) || st->loop.budget == 0) return false;
+    if (!st->loop_cand || st->threads != 0 || st->loop.budget == 0) return false;
+    if ((st->n + 1) / 2 > kLoopMaxPairs) return false;
     return st->fp32 ? loop_fits(st->df, st->ncu) : loop_fits(st->d, st->ncu);
 }
 
@@ -685,6 +693,8 @@ static int capture_sweep(jsvd_state st, hipStream_t cs, hipStream_t vs, std::vec
             return JSVD_EDEVICE;
     }
     if (settle(st, cs) != hipSuccess) return JSVD_EDEVICE;
+    // whether the next sweep may run as one persistent launch
+    if (st->loop_cand && loop_check(st, cs) != hipSuccess) return JSVD_EDEVICE;
     return launch_sweep_end(st->sc, cs) == hipSuccess ? JSVD_OK : JSVD_EDEVICE;
 }
 
@@ -959,7 +969,10 @@ extern "C" int jsvd_state_finalize_f32(jsvd_state st, float *U_re, float *U_im, 
 static int iterate(jsvd_state st, hipStream_t s)
 {
     const bool loop = loop_usable(st);
-    HIPCHK(set_v_layout(st, path_layout(st), s));
+    // a persistent sweep rotates V's columns in place (V column-major); the
+    // large-column steps keep V row-major, so a switch between the two
+    // transposes V once
+    HIPCHK(set_v_layout(st, loop ? V_COLS : path_layout(st), s));
     HIPCHK(flush_vlog(st, s));
     HIPCHK(settle(st, s));
     HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
@@ -969,8 +982,11 @@ static int iterate(jsvd_state st, hipStream_t s)
         if (as_loop) {
             const int rc = build_loop_graph(st);
             if (rc != JSVD_OK) return rc;
+            HIPCHK(set_v_layout(st, V_COLS, s));
+            HIPCHK(settle(st, s));
             HIPCHK(hipGraphLaunch(st->loop_graph, s));
             HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+            st->lastmod_valid = 0;   // the persistent sweep changes columns without recording it
         } else {
             const int rc = state_sweep_async(st, s);
             if (rc != JSVD_OK) return rc;

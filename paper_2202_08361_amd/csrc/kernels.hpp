@@ -199,6 +199,8 @@ struct LoopArgs {
 // the persistent sweep applies to this state (m <= 256, every pair slot resident at once)
 template <typename T>
 bool loop_fits(const SvdDescT<T> &d, int ncu);
+// longest columns of a persistent sweep
+int loop_max_rows();
 // the persistent sweep and its fold into the device scalars
 template <typename T>
 hipError_t launch_loop_sweep(const SvdDescT<T> &d, const LoopArgs &a, hipStream_t s);

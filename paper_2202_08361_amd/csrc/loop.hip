@@ -1,8 +1,9 @@
 // loop.hip -- a whole sweep of the one-sided Jacobi SVD (Alg. zvjsvd: K
-// round-robin steps) in one persistent launch, for states on the
-// one-wavefront-per-pair path (m <= 256).
+// round-robin steps) in one persistent launch, for columns of up to 1024
+// rows.
 //
-// One workgroup per pair slot l (n/2 of them, all resident at once) runs the
+// One workgroup per pair slot l (n/2 of them, all resident at once; one
+// wavefront up to 256 rows, four up to 1024) runs the
 // K steps of the sweep.  In the circle method a column of step k + 1 comes
 // from slot l - 1, l or l + 1 of step k, so there is no need for a barrier
 // between steps: each column carries a flag, the step it is ready for, and a
@@ -61,6 +62,29 @@ __device__ __forceinline__ bool loop_wait(const LoopArgs &a, int c, unsigned lon
     return true;
 }
 
+// both columns of a pair (q < 0: p only) ready for step offset `want`, with
+// one outcome for the whole workgroup: in a workgroup of several wavefronts
+// the first one waits and the others take its outcome from LDS, so that no
+// two wavefronts can see different ones (a barrier later in the step would
+// then never be reached by all of them)
+template <int W>
+__device__ __forceinline__ bool loop_wait_pair(const LoopArgs &a, int p, int q, unsigned long long want, int *ok_lds)
+{
+    if constexpr (W == 64) {
+        return loop_wait(a, p, want) && (q < 0 || loop_wait(a, q, want));
+    } else {
+        if (threadIdx.x < 64) {
+            const bool ok = loop_wait(a, p, want) && (q < 0 || loop_wait(a, q, want));
+            if (threadIdx.x == 0) *ok_lds = ok ? 1 : 0;
+        }
+        // the first wavefront's acquire (after its wait) has invalidated the
+        // caches this compute unit reads through; the barrier orders the other
+        // wavefronts' loads after it
+        __syncthreads();
+        return *(volatile int *)ok_lds != 0;
+    }
+}
+
 // a store that is coherent at agent scope (relaxed atomic)
 template <typename T>
 __device__ __forceinline__ void coherent_store(T *p, T v)
@@ -70,20 +94,32 @@ __device__ __forceinline__ void coherent_store(T *p, T v)
 
 // publish columns p and q (q < 0: p only) as ready for step offset `val`,
 // after everything this wavefront wrote before
+// (the workgroup barrier first makes every wavefront's stores complete in
+// the L2; the agent-scope release of the first wavefront then writes the
+// L2 back once for all of them)
 __device__ __forceinline__ void loop_publish(const LoopArgs &a, int p, int q, unsigned long long val)
 {
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(a.ver + p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (q >= 0) __hip_atomic_store(a.ver + q, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 64) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (threadIdx.x == 0) {
+            __hip_atomic_store(a.ver + p, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (q >= 0) __hip_atomic_store(a.ver + q, val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
-template <bool CPLX, int R, bool COMP, typename T>
-__global__ __launch_bounds__(64) void loop_kernel(SvdDescT<T> d, LoopArgs a)
+template <bool CPLX, int W, int R, bool COMP, typename T>
+__global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
 {
-    constexpr int W = 64;
+    // the reduction scratch of pair_core (a workgroup of one wavefront
+    // reduces in registers alone)
+    __shared__ T red[W > 64 ? (COMP ? 12 : 6) * W : 1];
+    __shared__ T mxs[W > 64 ? 4 * (W / 64) : 1];
+    __shared__ int wait_ok;
+    T *const red_norm = W > 64 ? red : (T *)nullptr;
+    T *const red_dot = W > 64 ? red + 4 * W : (T *)nullptr;
+    T *const mxs_p = W > 64 ? mxs : (T *)nullptr;
     const int t = threadIdx.x;
     const int l = blockIdx.x;
     DevScalars *sc = d.sc;
@@ -107,8 +143,7 @@ __global__ __launch_bounds__(64) void loop_kernel(SvdDescT<T> d, LoopArgs a)
         int p, q;
         const bool valid = rr_pair(n, k, l, &p, &q);
         // the columns of step offset 0 are current from the launch boundary
-        if (j > 0 && (!loop_wait(a, p, epoch | (unsigned)j) || (valid && !loop_wait(a, q, epoch | (unsigned)j))))
-            break;
+        if (j > 0 && !loop_wait_pair<W>(a, p, valid ? q : -1, epoch | (unsigned)j, &wait_ok)) break;
         if (!valid) {
             // the column sitting out this step (odd n): nothing to compute
             loop_publish(a, p, -1, epoch | (unsigned)(j + 1));
@@ -140,8 +175,7 @@ __global__ __launch_bounds__(64) void loop_kernel(SvdDescT<T> d, LoopArgs a)
             }
         }
         // no rescaling in this sweep (checked before the launch)
-        const PairDecisionT<T> dc =
-            pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, (T *)nullptr, (T *)nullptr, (T *)nullptr);
+        const PairDecisionT<T> dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, red_norm, red_dot, mxs_p);
         const int pbit = dc.pbit;
         T *const Dp_r = pbit ? Gqr : Gpr;
         T *const Dq_r = pbit ? Gpr : Gqr;
@@ -152,10 +186,9 @@ __global__ __launch_bounds__(64) void loop_kernel(SvdDescT<T> d, LoopArgs a)
         T *const Ep_i = pbit ? Vqi : Vpi;
         T *const Eq_i = pbit ? Vpi : Vqi;
         if (dc.transform) {
-            T Mx = transform_regs<CPLX, R>(xr, xi, dc);
+            // this thread's max-norm; the workgroup's is taken once, at the end
+            Mrun = fmax(Mrun, transform_regs<CPLX, R>(xr, xi, dc));
             (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
-            Mx = wave_max(Mx);
-            Mrun = fmax(Mrun, Mx);
             ++acc.t;
             if (dc.gs) ++acc.gs;
             if (j == K - 1) acc.tlast = 1;
@@ -197,6 +230,14 @@ __global__ __launch_bounds__(64) void loop_kernel(SvdDescT<T> d, LoopArgs a)
         }
         loop_publish(a, p, q, epoch | (unsigned)(j + 1));
         ++steps;
+    }
+    // the max-norm of the rotated columns over the workgroup (an exact max)
+    if constexpr (W == 64) {
+        Mrun = wave_max(Mrun);
+    } else {
+        T mm[1] = {Mrun};
+        group_max<W, 1>(mm, mxs);
+        Mrun = mm[0];
     }
     if (t == 0) {
         acc.M = (double)Mrun;
@@ -332,75 +373,73 @@ __global__ void loop_clear_kernel(DevScalars *sc)
 }
 
 // ---------------------------------------------------------------------------
-template <bool CPLX, int R, bool COMP, typename T>
-static const void *loop_fn()
+// Launch shape of a persistent sweep: one 64-thread workgroup per pair slot
+// up to 256 rows (R = 1, 2, 4 rows per lane), one 256-thread workgroup up to
+// 1024 rows (R = 2, 4), the same canonical sums either way.
+struct LoopShape {
+    int W, R;
+};
+
+static LoopShape loop_shape(int m)
 {
-    return (const void *)loop_kernel<CPLX, R, COMP, T>;
+    if (m <= 64) return {64, 1};
+    if (m <= 128) return {64, 2};
+    if (m <= 256) return {64, 4};
+    if (m <= 512) return {256, 2};
+    return {256, 4};
+}
+
+int loop_max_rows() { return 1024; }
+
+template <bool CPLX, bool COMP, typename T>
+static const void *loop_fn_c(LoopShape sh)
+{
+    if (sh.W == 64) {
+        if (sh.R <= 1) return (const void *)loop_kernel<CPLX, 64, 1, COMP, T>;
+        if (sh.R <= 2) return (const void *)loop_kernel<CPLX, 64, 2, COMP, T>;
+        return (const void *)loop_kernel<CPLX, 64, 4, COMP, T>;
+    }
+    if (sh.R <= 2) return (const void *)loop_kernel<CPLX, 256, 2, COMP, T>;
+    return (const void *)loop_kernel<CPLX, 256, 4, COMP, T>;
 }
 
 template <typename T>
-static const void *loop_fn_of(const SvdDescT<T> &d, int R)
+static const void *loop_fn_of(const SvdDescT<T> &d, LoopShape sh)
 {
     if constexpr (sizeof(T) == sizeof(double)) {
-        if (d.comp) {
-            if (d.cplx)
-                return R <= 1 ? loop_fn<true, 1, true, T>() : R <= 2 ? loop_fn<true, 2, true, T>() : loop_fn<true, 4, true, T>();
-            return R <= 1 ? loop_fn<false, 1, true, T>() : R <= 2 ? loop_fn<false, 2, true, T>() : loop_fn<false, 4, true, T>();
-        }
+        if (d.comp) return d.cplx ? loop_fn_c<true, true, T>(sh) : loop_fn_c<false, true, T>(sh);
     } else {
         if (d.comp) return nullptr;
     }
-    if (d.cplx)
-        return R <= 1 ? loop_fn<true, 1, false, T>() : R <= 2 ? loop_fn<true, 2, false, T>() : loop_fn<true, 4, false, T>();
-    return R <= 1 ? loop_fn<false, 1, false, T>() : R <= 2 ? loop_fn<false, 2, false, T>() : loop_fn<false, 4, false, T>();
+    return d.cplx ? loop_fn_c<true, false, T>(sh) : loop_fn_c<false, false, T>(sh);
 }
 
-static int loop_rows(int m) { return m <= 64 ? 1 : m <= 128 ? 2 : 4; }
-
+// every pair slot's workgroup resident at once
 template <typename T>
 bool loop_fits(const SvdDescT<T> &d, int ncu)
 {
-    if (d.m > 256) return false;
-    const void *fn = loop_fn_of(d, loop_rows(d.m));
+    if (d.m > loop_max_rows()) return false;
+    const LoopShape sh = loop_shape(d.m);
+    const void *fn = loop_fn_of(d, sh);
     if (!fn) return false;
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu < 1) return false;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, sh.W, 0) != hipSuccess || per_cu < 1) return false;
     const int npairs = (d.n + (d.n & 1)) / 2;
     return (long long)per_cu * ncu >= npairs;
-}
-
-template <bool CPLX, int R, bool COMP, typename T>
-static void launch_loop_t(const SvdDescT<T> &d, const LoopArgs &a, int npairs, hipStream_t s)
-{
-    hipLaunchKernelGGL((loop_kernel<CPLX, R, COMP, T>), dim3(npairs), dim3(64), 0, s, d, a);
-}
-
-template <bool CPLX, bool COMP, typename T>
-static void launch_loop_r(const SvdDescT<T> &d, const LoopArgs &a, int npairs, hipStream_t s)
-{
-    const int R = loop_rows(d.m);
-    if (R <= 1) launch_loop_t<CPLX, 1, COMP, T>(d, a, npairs, s);
-    else if (R <= 2) launch_loop_t<CPLX, 2, COMP, T>(d, a, npairs, s);
-    else launch_loop_t<CPLX, 4, COMP, T>(d, a, npairs, s);
 }
 
 template <typename T>
 hipError_t launch_loop_sweep(const SvdDescT<T> &d, const LoopArgs &a, hipStream_t s)
 {
     const int N = d.n + (d.n & 1), npairs = N / 2, K = N - 1;
-    if (d.m > 256) return hipErrorInvalidValue;
-    if (d.comp) {
-        if constexpr (sizeof(T) == sizeof(double)) {
-            if (d.cplx) launch_loop_r<true, true, T>(d, a, npairs, s);
-            else launch_loop_r<false, true, T>(d, a, npairs, s);
-        } else {
-            return hipErrorInvalidValue;
-        }
-    } else {
-        if (d.cplx) launch_loop_r<true, false, T>(d, a, npairs, s);
-        else launch_loop_r<false, false, T>(d, a, npairs, s);
-    }
-    hipError_t e = hipGetLastError();
+    if (d.m > loop_max_rows()) return hipErrorInvalidValue;
+    const LoopShape sh = loop_shape(d.m);
+    const void *fn = loop_fn_of(d, sh);
+    if (!fn) return hipErrorInvalidValue;
+    SvdDescT<T> dd = d;
+    LoopArgs aa = a;
+    void *args[] = {(void *)&dd, (void *)&aa};
+    hipError_t e = hipLaunchKernel(fn, dim3(npairs), dim3(sh.W), args, 0, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((loop_fold_kernel<T>), dim3(1), dim3(256), 0, s, d, a, npairs, K);
     return hipGetLastError();

@@ -1,6 +1,6 @@
 """GPU tests of the persistent sweep (one launch per sweep, pairs started as
 soon as their columns are out of the previous step) used by
-jsvd_state_iterate and jsvd_gesvj for columns of at most 256 rows.
+jsvd_state_iterate and jsvd_gesvj for columns of at most 1024 rows.
 
 The bar is bit-for-bit equality with the CPU oracle (U, V, sigma, sweep
 count), and with the step-by-step sweeps of the same state (forced by a
@@ -74,7 +74,10 @@ def _same(a, b, tag):
 @pytest.mark.parametrize("m,n,cplx,flags", [
     (256, 256, False, 0), (200, 131, False, 0), (64, 64, True, 0), (100, 37, True, 0),
     (256, 255, True, 0), (120, 80, False, 2), (90, 57, True, 2), (77, 40, False, 8),
-    (60, 60, True, 8), (33, 2, False, 0), (5, 3, True, 0), (1, 1, False, 0), (130, 129, False, 4)])
+    (60, 60, True, 8), (33, 2, False, 0), (5, 3, True, 0), (1, 1, False, 0), (130, 129, False, 4),
+    # 256-thread workgroups (257 to 1024 rows)
+    (300, 200, False, 0), (512, 300, True, 0), (1024, 130, False, 2), (700, 255, True, 8), (640, 97, False, 0),
+    (257, 257, True, 4)])
 def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     Ar, Ai = _matrix(m, n, cplx, 1e6, m + 3 * n)
     got = _iterate(Ar, Ai, flags)
@@ -91,7 +94,7 @@ def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
             continue
         assert np.array_equal(_bits(got[k]), _bits(ro[k])), k
     # the same state swept step by step (fixed launch shape)
-    steps = _iterate(Ar, Ai, flags, threads=64)
+    steps = _iterate(Ar, Ai, flags, threads=64 if m <= 512 else 256)
     assert steps["info"]["loop_sweeps"] == 0
     _same(got, steps, "steps")
 
@@ -135,18 +138,32 @@ def test_loop_ruled_out_by_the_bound(ora):
         assert np.array_equal(_bits(got[k]), _bits(ro[k])), k
 
 
-@pytest.mark.parametrize("cplx", [False, True])
-def test_loop_gives_up_and_is_redone(cplx):
+@pytest.mark.parametrize("m,n,cplx", [(200, 160, False), (200, 160, True), (600, 300, False), (800, 200, True)])
+def test_loop_gives_up_and_is_redone(m, n, cplx):
     """A wait budget of a few microseconds: persistent sweeps give up through
     their bounded waits (forced from the host, every launch still exits)
-    and are redone step by step from the copy taken before them."""
-    Ar, Ai = _matrix(200, 160, cplx, 1e5, 40 + int(cplx))
+    and are redone step by step from the copy taken before them (with
+    256-thread workgroups beyond 256 rows: one outcome per workgroup)."""
+    Ar, Ai = _matrix(m, n, cplx, 1e5, 40 + int(cplx) + m)
     got = _iterate(Ar, Ai, wait=1e-6)
     ref = _iterate(Ar, Ai, wait=0.0)
     assert ref["info"]["loop_sweeps"] == 0
     assert got["info"]["loop_redos"] > 0, got["info"]
     assert got["info"]["sweeps"] == ref["info"]["sweeps"]
     _same(got, ref, "redo")
+
+
+def test_many_pairs_sweep_step_by_step(ora):
+    """Beyond 192 pair slots the step-by-step sweep is the faster one: a
+    600 x 400 state (200 slots) takes no persistent sweep and still gives the
+    oracle's bits."""
+    Ar, Ai = _matrix(600, 400, False, 1e4, 77)
+    got = _iterate(Ar, Ai)
+    assert got["info"]["status"] == 0 and got["info"]["loop_sweeps"] == 0
+    ro = ora.gesvj(Ar, Ai)
+    assert ro["sweeps"] == got["info"]["sweeps"]
+    for k in ("U_re", "V_re", "sv_e", "sv_f"):
+        assert np.array_equal(_bits(got[k]), _bits(ro[k])), k
 
 
 def test_gesvj_uses_the_loop_and_matches(ora):

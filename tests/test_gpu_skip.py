@@ -94,6 +94,9 @@ def test_skipping_steps_bitwise(ora, m, n, cplx, flags):
 def test_skipping_whole_svd(ora, m, n, cplx, kappa):
     Ar, Ai = _graded(m, n, cplx, 7 * m, kappa)
     st = J().State(m, n, cplx)
+    # the large-column steps (these shapes would otherwise sweep as
+    # persistent launches, which read every pair)
+    st.set_loop_wait(0.0)
     st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None)
     st.iterate()
     info = st.query()
