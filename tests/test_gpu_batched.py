@@ -78,6 +78,61 @@ def test_batched_tall_members_side_by_side():
     _check_batch(host[:7], flags=J().PERMUTE | J().COMPENSATED)
 
 
+def test_two_batched_calls_overlap():
+    """Two multi-class batches in flight at once (two host threads, two
+    streams): each launch takes its class streams from a pool of its own
+    streams, so neither queues behind the other's persistent kernels. Each
+    batch alone keeps a small part of the GPU busy (one workgroup per matrix)
+    for its whole time, so the two together finish well within the sum of
+    their times alone, with each result the bits of the batch alone."""
+    import threading
+    import time
+    shapes_a = [(100, 60, False, 1e6)] * 16 + [(200, 120, False, 1e6)] * 16 + [(400, 200, False, 1e6)] * 8
+    shapes_b = [(90, 50, True, 1e4)] * 16 + [(230, 100, False, 1e5)] * 16 + [(380, 150, False, 1e5)] * 8
+    host_a, host_b = _mats(shapes_a, 21), _mats(shapes_b, 22)
+
+    def dev(host):
+        return [(J().to_device_fortran(a), None if b is None else J().to_device_fortran(b)) for a, b in host]
+    J().batched_tune([(m, n, c) for (m, n, c, _) in shapes_a + shapes_b])
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+
+    def run(host, stream, out, key):
+        d = dev(host)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            r = J().gesvj_batched(d, stream=stream)
+        stream.synchronize()
+        out[key] = (time.perf_counter() - t0, r)
+    alone = {}
+    run(host_a, streams[0], alone, "a")
+    run(host_b, streams[1], alone, "b")
+    both = {}
+    da, db = dev(host_a), dev(host_b)
+    torch.cuda.synchronize()
+
+    def go(d, stream, key):
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            r = J().gesvj_batched(d, stream=stream)
+        stream.synchronize()
+        both[key] = (t0, time.perf_counter(), r)
+    th = [threading.Thread(target=go, args=(da, streams[0], "a")), threading.Thread(target=go, args=(db, streams[1], "b"))]
+    t0 = time.perf_counter()
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    wall = time.perf_counter() - t0
+    ta, tb = alone["a"][0], alone["b"][0]
+    assert wall < 0.85 * (ta + tb), (wall, ta, tb)
+    for key in ("a", "b"):
+        for x, y in zip(alone[key][1], both[key][2]):
+            assert x["sweeps"] == y["sweeps"]
+            for k in ("U_re", "U_im", "V_re", "V_im", "sv_e", "sv_f"):
+                assert _same(x[k], y[k]), (key, k)
+
+
 def test_batched_vs_oracle():
     import oracle
     host = _mats([(60, 33, True, 1e4), (90, 90, False, 1e6)], 2)
