@@ -106,23 +106,76 @@ __device__ __forceinline__ void lds_barrier()
 }
 
 // ---------------------------------------------------------------------------
-// In-wave halving tree: after the call lane 0 holds x_0 + x_1 + ... in the
-// canonical order (lane i += lane i+h for h = 32, ..., 1); the total is
-// broadcast to every lane.
+// Cross-lane moves of the in-wave trees, on the VALU (no LDS round trip):
+// lane i (i < h) receives lane i + h.  h = 32: v_permlane32_swap (the upper
+// half of the wave into the lower one); h = 16: v_permlane16_swap (odd rows
+// of 16 lanes into even ones); h <= 8: DPP row_shl within each row.  The
+// other lanes receive values the trees do not use.
+template <int H>
+__device__ __forceinline__ unsigned lane_down_u32(unsigned v)
+{
+    if constexpr (H == 32) {
+        return __builtin_amdgcn_permlane32_swap(v, v, false, false)[1];
+    } else if constexpr (H == 16) {
+        return __builtin_amdgcn_permlane16_swap(v, v, false, false)[1];
+    } else {
+        static_assert(H >= 1 && H <= 8, "row shift");
+        return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x100 + H, 0xF, 0xF, false);
+    }
+}
+
+template <int H, typename T>
+__device__ __forceinline__ T lane_down(T x)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __uint_as_float(lane_down_u32<H>(__float_as_uint(x)));
+    } else {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        const unsigned lo = lane_down_u32<H>((unsigned)b), hi = lane_down_u32<H>((unsigned)(b >> 32));
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+}
+
+// lane 0's value in every lane (whatever the exec mask)
+template <typename T>
+__device__ __forceinline__ T lane0(T x)
+{
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    } else {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 0);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 0);
+        return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
+}
+
+// In-wave halving tree: lane 0 ends with x_0 + x_1 + ... in the canonical
+// order (lane i += lane i+h for h = 32, ..., 1); the total is broadcast to
+// every lane.
 template <typename T>
 __device__ __forceinline__ T wave_tree_sum(T x)
 {
-#pragma unroll
-    for (int h = 32; h >= 1; h >>= 1) x = x + __shfl_down(x, h, 64);
-    return __shfl(x, 0, 64);
+    x = x + lane_down<32>(x);
+    x = x + lane_down<16>(x);
+    x = x + lane_down<8>(x);
+    x = x + lane_down<4>(x);
+    x = x + lane_down<2>(x);
+    x = x + lane_down<1>(x);
+    return lane0(x);
 }
 
+// The wave's maximum of non-negative values (exact, so any order), in every lane.
 template <typename T>
 __device__ __forceinline__ T wave_max(T x)
 {
-#pragma unroll
-    for (int h = 32; h >= 1; h >>= 1) x = fmax(x, __shfl_xor(x, h, 64));
-    return x;
+    x = fmax(x, lane_down<32>(x));
+    x = fmax(x, lane_down<16>(x));
+    x = fmax(x, lane_down<8>(x));
+    x = fmax(x, lane_down<4>(x));
+    x = fmax(x, lane_down<2>(x));
+    x = fmax(x, lane_down<1>(x));
+    return lane0(x);
 }
 
 // Group-wide canonical sum of NQ quantities (one value per thread each, the
