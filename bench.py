@@ -664,12 +664,13 @@ def svd_plain(torch, J, inputs, flags, fp32=False):
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
-def svd_plain_sweeps(torch, J, inputs, persistent, shape=None):
+def svd_plain_sweeps(torch, J, inputs, persistent, shape=None, local=True):
     """The 256 x 256 workload (or an m x n x complex `shape`, sigma
     log-spaced in [1e-6, 1]) through the state API (load,
     jsvd_state_iterate, finalize), with persistent sweeps or with step-by-step
     sweeps (a zero wait budget turns persistent sweeps off): the A/B of the two
-    sweep forms on the same iteration (the same bits, tested)."""
+    sweep forms on the same iteration (the same bits, tested).  local=False
+    keeps persistent sweeps out of the L2-local mode."""
     import numpy as np
     if shape is None:
         A, sig = inputs.plain_real_256()
@@ -686,6 +687,8 @@ def svd_plain_sweeps(torch, J, inputs, persistent, shape=None):
         st = J.State(m, n, cplx)
         if not persistent:
             st.set_loop_wait(0.0)
+        if not local:
+            st.set_loop_local(False)
         st.load(dA, dAi)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -699,7 +702,7 @@ def svd_plain_sweeps(torch, J, inputs, persistent, shape=None):
     sv = r["sv"].cpu().numpy()
     K = n - 1 if n % 2 == 0 else n
     return dict(m=m, n=n, complex=bool(cplx), ms=best * 1e3, sweeps=q["sweeps"], persistent_sweeps=q["loop_sweeps"],
-                redone=q["loop_redos"], us_per_step=best * 1e6 / ((q["sweeps"] + 1) * K),
+                l2_local_sweeps=q["local_sweeps"], redone=q["loop_redos"], us_per_step=best * 1e6 / ((q["sweeps"] + 1) * K),
                 max_rel_sigma_err=float(np.max(np.abs(sv - sig) / sig)))
 
 
@@ -969,6 +972,9 @@ def main():
             tasks.append((nm, lambda fl=fl: svd_plain(torch, J, inputs, fl)))
         for nm, pers in (("svd_real256_persistent_sweeps", True), ("svd_real256_stepwise_sweeps", False)):
             tasks.append((nm, lambda pers=pers: svd_plain_sweeps(torch, J, inputs, pers)))
+        # the persistent sweeps spread over the device instead of on one XCC
+        tasks.append(("svd_real256_persistent_spread",
+                      lambda: svd_plain_sweeps(torch, J, inputs, True, local=False)))
         # mid-size matrices (the persistent sweep with 256-thread workgroups)
         for (m, n, c) in ((1024, 256, False), (1000, 300, True)):
             for nm, pers in (("persistent_sweeps", True), ("stepwise_sweeps", False)):

@@ -158,6 +158,8 @@ typedef struct {
     int64_t skipped_pairs;    /* pairs of large-column steps since the load that were not read:
                                  both columns unchanged since the pair last met, one sweep
                                  earlier, so its outcome is that meeting's (no change) */
+    int64_t local_sweeps;     /* persistent sweeps of the state that ran in the L2-local mode
+                                 (jsvd_state_set_loop_local) */
 } jsvd_info;
 
 /* Allocate a state for an m x n real (is_complex = 0) or complex problem,
@@ -221,6 +223,16 @@ int jsvd_state_iterate(jsvd_state st, void *stream);
  * gives up and is redone step by step (default 0.25; at most 60).  0 turns
  * persistent sweeps off for the state.  JSVD_EINVAL outside [0, 60]. */
 int jsvd_state_set_loop_wait(jsvd_state st, double seconds);
+/* Whether persistent sweeps of the state may run in the L2-local mode
+ * (allow = 1, the default) or always spread over the device (0).  In the
+ * L2-local mode, used where every pair slot's workgroup fits on one XCC with
+ * one wavefront per SIMD (columns of at most 256 rows, at most 4 x CUs/8
+ * slots), the workgroups of one XCC take the slots and exchange columns
+ * through its L2 without cache write-back or invalidation; the results are
+ * the same bits.  A sweep in that mode that gives up turns it off for the
+ * state until the next call of this function.  JSVD_EINVAL for another
+ * value of allow. */
+int jsvd_state_set_loop_local(jsvd_state st, int allow);
 
 /* Read the scalars of the state.  Synchronises. */
 int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream);

@@ -52,7 +52,7 @@ class _Info(_ct.Structure):
                 ("rescaled", _ct.c_int32), ("Mt", _ct.c_double), ("converged", _ct.c_int32),
                 ("status", _ct.c_int32), ("last_sweep_T", _ct.c_int64), ("last_sweep_swaps", _ct.c_int64),
                 ("gs", _ct.c_int64), ("last_sweep_gs", _ct.c_int64), ("loop_sweeps", _ct.c_int64),
-                ("loop_redos", _ct.c_int64), ("skipped_pairs", _ct.c_int64)]
+                ("loop_redos", _ct.c_int64), ("skipped_pairs", _ct.c_int64), ("local_sweeps", _ct.c_int64)]
 
 
 class ServeConfig(_ct.Structure):
@@ -123,6 +123,8 @@ def lib():
         L.jsvd_state_iterate.argtypes = [vp, vp]
         L.jsvd_state_set_loop_wait.restype = i
         L.jsvd_state_set_loop_wait.argtypes = [vp, d]
+        L.jsvd_state_set_loop_local.restype = i
+        L.jsvd_state_set_loop_local.argtypes = [vp, i]
         L.jsvd_state_query.restype = i
         L.jsvd_state_query.argtypes = [vp, _ct.POINTER(_Info), vp]
         L.jsvd_state_save.restype = i
@@ -400,6 +402,11 @@ class State:
         """Wait budget of a persistent sweep's workgroup for one column
         (jsvd_state_set_loop_wait; 0 turns persistent sweeps off)."""
         _check(lib().jsvd_state_set_loop_wait(self._h, float(seconds)), "jsvd_state_set_loop_wait")
+
+    def set_loop_local(self, allow):
+        """Allow (True, the default) or forbid the L2-local mode of persistent
+        sweeps (jsvd_state_set_loop_local)."""
+        _check(lib().jsvd_state_set_loop_local(self._h, 1 if allow else 0), "jsvd_state_set_loop_local")
 
     def query(self, stream=None):
         info = _Info()

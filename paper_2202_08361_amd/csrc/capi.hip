@@ -275,6 +275,10 @@ static int state_create(int m, int n, int is_complex, bool fp32, jsvd_state *out
         st->loop.ver = (unsigned long long *)(b + L.oLV);
         st->loop.acc = (LoopAcc *)(b + L.oLA);
         st->loop.abort = (unsigned *)(b + L.oLB);
+        // the slot claims of an L2-local launch, in the abort flag's block
+        st->loop.claim = st->loop.abort + 1;
+        st->loop.local = 0;
+        st->loop_local_allow = 1;
         st->colsq = (double *)(b + L.oLC);
         st->snap = b + L.oLZ;
         st->snap_bytes = L.oR - L.oG;
@@ -594,12 +598,24 @@ static bool loop_usable(jsvd_state st)
     return st->fp32 ? loop_fits(st->df, st->ncu) : loop_fits(st->d, st->ncu);
 }
 
+// The persistent sweep of this state runs in the L2-local mode: allowed, no
+// L2-local sweep of the state has given up, and the slots' workgroups fit on
+// one XCC with one wavefront per SIMD.
+static int loop_local_now(jsvd_state st)
+{
+    if (!st->loop_local_allow || st->loop_local_failed) return 0;
+    return (st->fp32 ? loop_fits_local(st->df, st->ncu) : loop_fits_local(st->d, st->ncu)) ? 1 : 0;
+}
+
 // Capture a persistent sweep: the snapshot of G, V, e and f it can be redone
 // from, the sweep with its fold, the check for the sweep after it, and the
 // end-of-sweep bookkeeping (which skips a sweep that gave up).
 static int build_loop_graph(jsvd_state st)
 {
-    if (st->loop_graph && st->loop_graph_flags == st->flags && st->loop_graph_budget == st->loop.budget) return JSVD_OK;
+    st->loop.local = loop_local_now(st);
+    if (st->loop_graph && st->loop_graph_flags == st->flags && st->loop_graph_budget == st->loop.budget &&
+        st->loop_graph_local == st->loop.local)
+        return JSVD_OK;
     if (st->loop_graph) {
         (void)hipGraphExecDestroy(st->loop_graph);
         st->loop_graph = nullptr;
@@ -634,6 +650,7 @@ static int build_loop_graph(jsvd_state st)
     st->loop_graph_def = g;
     st->loop_graph_flags = st->flags;
     st->loop_graph_budget = st->loop.budget;
+    st->loop_graph_local = st->loop.local;
     return JSVD_OK;
 }
 
@@ -840,6 +857,7 @@ extern "C" int jsvd_state_query(jsvd_state st, jsvd_info *out, void *stream)
     out->last_sweep_gs = h.GS_prev;
     out->loop_sweeps = h.loop_sweeps;
     out->loop_redos = st->loop_redos;
+    out->local_sweeps = st->loop_local_sweeps;
     out->skipped_pairs = h.skipped;
     return JSVD_OK;
 }
@@ -992,6 +1010,14 @@ static int iterate(jsvd_state st, hipStream_t s)
             if (rc != JSVD_OK) return rc;
         }
         HIPCHK(hipStreamSynchronize(s));
+        if (as_loop && st->loop.local) {
+            // an L2-local sweep that gave up (too few of its workgroups on the
+            // XCC, say) is not tried again on this state
+            if (st->host->loop_redo)
+                st->loop_local_failed = 1;
+            else
+                st->loop_local_sweeps++;
+        }
         if (as_loop && st->host->loop_redo) {
             char *gbase = st->fp32 ? (char *)st->df.Gr : (char *)st->d.Gr;
             HIPCHK(hipMemcpyAsync(gbase, st->snap, st->snap_bytes, hipMemcpyDeviceToDevice, s));
@@ -1015,6 +1041,14 @@ extern "C" int jsvd_state_set_loop_wait(jsvd_state st, double seconds)
     const double ticks = seconds * 1e3 * khz;
     // a positive wait of less than one tick still allows persistent sweeps
     st->loop.budget = seconds == 0.0 ? 0ull : (ticks < 1.0 ? 1ull : (unsigned long long)ticks);
+    return JSVD_OK;
+}
+
+extern "C" int jsvd_state_set_loop_local(jsvd_state st, int allow)
+{
+    if (!st || (allow != 0 && allow != 1)) return JSVD_EINVAL;
+    st->loop_local_allow = allow;
+    st->loop_local_failed = 0;
     return JSVD_OK;
 }
 

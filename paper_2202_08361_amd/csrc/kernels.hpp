@@ -195,10 +195,19 @@ struct LoopArgs {
     LoopAcc *acc;                 // per workgroup
     unsigned *abort;              // raised by a workgroup whose wait ran out of budget
     unsigned long long budget;    // wall-clock ticks a workgroup may wait for one column
+    // L2-local mode (nonzero): every pair slot's workgroup on one XCC, columns
+    // and flags exchanged through that XCC's L2 without cache maintenance;
+    // claim[0] counts the slots taken, claim[1] names the XCC (its id + 1)
+    int local;
+    unsigned *claim;
 };
 // the persistent sweep applies to this state (m <= 256, every pair slot resident at once)
 template <typename T>
 bool loop_fits(const SvdDescT<T> &d, int ncu);
+// the sweep may run in the L2-local mode (every slot's workgroup on one XCC,
+// one wavefront per SIMD there)
+template <typename T>
+bool loop_fits_local(const SvdDescT<T> &d, int ncu);
 // longest columns of a persistent sweep
 int loop_max_rows();
 // the persistent sweep and its fold into the device scalars

@@ -48,7 +48,11 @@ struct jsvd_state_s {
     hipGraph_t loop_graph_def;
     unsigned loop_graph_flags;
     unsigned long long loop_graph_budget;
+    int loop_graph_local;    // the captured persistent sweep is an L2-local launch
     long long loop_redos;    // persistent sweeps that gave up and were redone step by step
+    int loop_local_allow;    // persistent sweeps may run in the L2-local mode (default)
+    int loop_local_failed;   // an L2-local sweep gave up: the state keeps the spread mode
+    long long loop_local_sweeps;   // persistent sweeps that ran in the L2-local mode
     int lastmod_valid;       // the per-column last-change steps are current (only large-column steps ran since their reset)
 };
 

@@ -9,7 +9,10 @@ persistent launches (jsvd_state_query's count), a matrix whose Frobenius
 bound rules the persistent sweep out gives the same bits through the
 step-by-step sweeps, and a wait budget so small that every persistent sweep
 gives up (the bounded wait's own exit, forced from the host) is redone step
-by step with the same bits."""
+by step with the same bits.  Where the slots fit on one XCC (64-thread
+workgroups, at most four per compute unit there) the persistent sweeps run
+in the L2-local mode, and give the same bits as the spread mode
+(jsvd_state_set_loop_local(st, 0))."""
 import numpy as np
 import pytest
 
@@ -44,7 +47,7 @@ def _matrix(m, n, cplx, kappa, seed):
     return inputs.svd_matrix(m, n, sig, g, cplx=cplx)
 
 
-def _iterate(Ar, Ai, flags=0, wait=None, threads=0):
+def _iterate(Ar, Ai, flags=0, wait=None, threads=0, local=None):
     m, n = Ar.shape
     st = J().State(m, n, Ai is not None)
     if flags:
@@ -53,6 +56,8 @@ def _iterate(Ar, Ai, flags=0, wait=None, threads=0):
         st.set_launch(threads)
     if wait is not None:
         st.set_loop_wait(wait)
+    if local is not None:
+        st.set_loop_local(local)
     st.load(J().to_device_fortran(Ar), None if Ai is None else J().to_device_fortran(Ai))
     st.iterate()
     q = st.query()
@@ -61,6 +66,13 @@ def _iterate(Ar, Ai, flags=0, wait=None, threads=0):
     st.close()
     out["info"] = q
     return out
+
+
+def _local_fits(m, n):
+    """The L2-local mode applies: 64-thread workgroups (m <= 256), every slot
+    on one of the 8 XCCs with at most four workgroups per compute unit."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    return m <= 256 and ncu % 8 == 0 and (n + 1) // 2 <= 4 * (ncu // 8)
 
 
 def _same(a, b, tag):
@@ -83,8 +95,10 @@ def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     got = _iterate(Ar, Ai, flags)
     info = got["info"]
     assert info["status"] == 0 and info["converged"] == 1
-    # the sweeps ran as persistent launches and none had to be redone
+    # the sweeps ran as persistent launches and none had to be redone; in the
+    # L2-local mode where the slots fit on one XCC
     assert info["loop_sweeps"] == info["sweeps"] + 1 and info["loop_redos"] == 0, info
+    assert info["local_sweeps"] == (info["loop_sweeps"] if _local_fits(m, n) else 0), info
     ora_flags = (ora.COMPENSATED if flags & 2 else 0) | (ora.PERMUTE if flags & 8 else 0) | \
         (ora.NO_GS if flags & 4 else 0)
     ro = ora.gesvj(Ar, Ai, flags=ora_flags)
@@ -97,6 +111,11 @@ def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     steps = _iterate(Ar, Ai, flags, threads=64 if m <= 512 else 256)
     assert steps["info"]["loop_sweeps"] == 0
     _same(got, steps, "steps")
+    if _local_fits(m, n):
+        # the same persistent sweeps spread over the device
+        spread = _iterate(Ar, Ai, flags, local=False)
+        assert spread["info"]["local_sweeps"] == 0 and spread["info"]["loop_sweeps"] == info["loop_sweeps"]
+        _same(got, spread, "spread")
 
 
 def test_loop_single_precision():
@@ -151,6 +170,36 @@ def test_loop_gives_up_and_is_redone(m, n, cplx):
     assert got["info"]["loop_redos"] > 0, got["info"]
     assert got["info"]["sweeps"] == ref["info"]["sweeps"]
     _same(got, ref, "redo")
+
+
+@pytest.mark.parametrize("m,n,cplx", [(256, 256, False), (130, 97, True)])
+def test_local_mode_gives_up_and_turns_off(m, n, cplx):
+    """An L2-local sweep that gives up (a wait budget of a microsecond,
+    forced from the host) is redone step by step and turns the mode off for
+    the state: the later persistent sweeps are spread ones (which give up
+    too, at that budget), and the bits are those of step-by-step sweeps.
+    jsvd_state_set_loop_local(st, 1) turns it on again."""
+    if not _local_fits(m, n):
+        pytest.skip("the slots do not fit on one XCC of this device")
+    Ar, Ai = _matrix(m, n, cplx, 1e5, 900 + m)
+    got = _iterate(Ar, Ai, wait=1e-6)
+    ref = _iterate(Ar, Ai, wait=0.0)
+    assert got["info"]["loop_redos"] > 0 and got["info"]["local_sweeps"] == 0, got["info"]
+    _same(got, ref, "local give-up")
+    st = J().State(m, n, cplx)
+    st.set_loop_wait(1e-6)
+    st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None)
+    st.iterate()
+    st.set_loop_wait(0.25)
+    st.set_loop_local(True)
+    st.load(J().to_device_fortran(Ar), J().to_device_fortran(Ai) if cplx else None)
+    st.iterate()
+    q = st.query()
+    r = st.finalize()
+    torch.cuda.synchronize()
+    st.close()
+    assert q["local_sweeps"] > 0 and q["loop_sweeps"] == q["sweeps"] + 1, q
+    _same(r, ref, "local again")
 
 
 def test_many_pairs_sweep_step_by_step(ora):
