@@ -489,6 +489,9 @@ typedef struct {
     int queue_depth, active;
     size_t hbm_in_use;
     double p50_service_ns, p99_service_ns; /* admission-to-completion */
+    uint64_t persistent_sweeps;  /* sweeps of requests on their own state that ran as one
+                                    persistent launch (while alone on the device) */
+    uint64_t persistent_redos;   /* of those, sweeps that gave up and were redone step by step */
 } jsvd_serve_stats;
 
 int jsvd_serve_create(const jsvd_serve_config *cfg, jsvd_server *out);

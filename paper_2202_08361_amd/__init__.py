@@ -73,7 +73,8 @@ class ServeStats(_ct.Structure):
                 ("p50_ns", _ct.c_double), ("p99_ns", _ct.c_double), ("p50_queue_ns", _ct.c_double),
                 ("p99_queue_ns", _ct.c_double), ("svds_per_s", _ct.c_double),
                 ("queue_depth", _ct.c_int), ("active", _ct.c_int), ("hbm_in_use", _ct.c_size_t),
-                ("p50_service_ns", _ct.c_double), ("p99_service_ns", _ct.c_double)]
+                ("p50_service_ns", _ct.c_double), ("p99_service_ns", _ct.c_double),
+                ("persistent_sweeps", _ct.c_uint64), ("persistent_redos", _ct.c_uint64)]
 
 
 def lib():

@@ -984,49 +984,65 @@ extern "C" int jsvd_state_finalize_f32(jsvd_state st, float *U_re, float *U_im, 
 // convergence.  Where the device has found that no rescaling can happen in
 // the next sweep, the sweep runs as one persistent launch (loop.hip); one
 // that gives up is redone step by step from the snapshot taken before it.
+int jsvd::state_next_sweep_async(jsvd_state st, hipStream_t s, bool allow_persistent, bool *persistent)
+{
+    *persistent = false;
+    if (allow_persistent && loop_usable(st) && st->host->loop_ok) {
+        const int rc = build_loop_graph(st);
+        if (rc != JSVD_OK) return rc;
+        // a persistent sweep rotates V's columns in place (V column-major); the
+        // large-column steps keep V row-major, so a switch between the two
+        // transposes V once
+        HIPCHK(set_v_layout(st, V_COLS, s));
+        HIPCHK(settle(st, s));
+        HIPCHK(hipGraphLaunch(st->loop_graph, s));
+        HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
+        st->lastmod_valid = 0;   // the persistent sweep changes columns without recording it
+        *persistent = true;
+        return JSVD_OK;
+    }
+    return state_sweep_async(st, s);
+}
+
+int jsvd::state_after_persistent_async(jsvd_state st, hipStream_t s, bool *redone)
+{
+    *redone = false;
+    const bool gave_up = st->host->loop_redo != 0;
+    if (st->loop.local) {
+        // an L2-local sweep that gave up (too few of its workgroups on the
+        // XCC, say) is not tried again on this state
+        if (gave_up)
+            st->loop_local_failed = 1;
+        else
+            st->loop_local_sweeps++;
+    }
+    if (!gave_up) return JSVD_OK;
+    char *gbase = st->fp32 ? (char *)st->df.Gr : (char *)st->d.Gr;
+    HIPCHK(hipMemcpyAsync(gbase, st->snap, st->snap_bytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_loop_clear(st->sc, s));
+    const int rc = state_sweep_async(st, s);
+    if (rc != JSVD_OK) return rc;
+    st->loop_redos++;
+    *redone = true;
+    return JSVD_OK;
+}
+
 static int iterate(jsvd_state st, hipStream_t s)
 {
-    const bool loop = loop_usable(st);
-    // a persistent sweep rotates V's columns in place (V column-major); the
-    // large-column steps keep V row-major, so a switch between the two
-    // transposes V once
-    HIPCHK(set_v_layout(st, loop ? V_COLS : path_layout(st), s));
+    HIPCHK(set_v_layout(st, loop_usable(st) ? V_COLS : path_layout(st), s));
     HIPCHK(flush_vlog(st, s));
     HIPCHK(settle(st, s));
     HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     while (!st->host->stop) {
-        const bool as_loop = loop && st->host->loop_ok;
-        if (as_loop) {
-            const int rc = build_loop_graph(st);
-            if (rc != JSVD_OK) return rc;
-            HIPCHK(set_v_layout(st, V_COLS, s));
-            HIPCHK(settle(st, s));
-            HIPCHK(hipGraphLaunch(st->loop_graph, s));
-            HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-            st->lastmod_valid = 0;   // the persistent sweep changes columns without recording it
-        } else {
-            const int rc = state_sweep_async(st, s);
-            if (rc != JSVD_OK) return rc;
-        }
+        bool as_loop = false, redone = false;
+        int rc = state_next_sweep_async(st, s, true, &as_loop);
+        if (rc != JSVD_OK) return rc;
         HIPCHK(hipStreamSynchronize(s));
-        if (as_loop && st->loop.local) {
-            // an L2-local sweep that gave up (too few of its workgroups on the
-            // XCC, say) is not tried again on this state
-            if (st->host->loop_redo)
-                st->loop_local_failed = 1;
-            else
-                st->loop_local_sweeps++;
-        }
-        if (as_loop && st->host->loop_redo) {
-            char *gbase = st->fp32 ? (char *)st->df.Gr : (char *)st->d.Gr;
-            HIPCHK(hipMemcpyAsync(gbase, st->snap, st->snap_bytes, hipMemcpyDeviceToDevice, s));
-            HIPCHK(launch_loop_clear(st->sc, s));
-            const int rc = state_sweep_async(st, s);
-            if (rc != JSVD_OK) return rc;
-            HIPCHK(hipStreamSynchronize(s));
-            st->loop_redos++;
-        }
+        if (!as_loop) continue;
+        rc = state_after_persistent_async(st, s, &redone);
+        if (rc != JSVD_OK) return rc;
+        if (redone) HIPCHK(hipStreamSynchronize(s));
     }
     return JSVD_OK;
 }

@@ -16,7 +16,11 @@
 //   and advance one graph-launched sweep at a time; after each sweep the
 //   device's convergence flags are staged to pinned memory and checked by the
 //   worker without blocking (events), then the next sweep or the finalisation
-//   is enqueued.
+//   is enqueued.  While such a request is the only one on the device, its
+//   sweeps run as persistent launches where jsvd_state_iterate would (a
+//   persistent launch needs all its workgroups resident; next to other
+//   requests' kernels it could wait out its budget), with the same redo of a
+//   sweep that gives up.
 //
 // Slots run on separate streams, so admitted requests overlap on the device
 // while new ones are admitted as slots and memory free up.  Freeing device
@@ -70,6 +74,7 @@ struct Slot {
     jsvd_state st = nullptr;
     uint64_t ticket = 0;
     int finishing = 0;
+    bool persistent = false;   // the sweep in flight is a persistent launch
     BatchLaunch *bl = nullptr;
     std::vector<uint64_t> group;
     size_t footprint = 0;
@@ -110,6 +115,7 @@ struct jsvd_server_s {
     bool stopping = false;
     std::thread worker;
     uint64_t submitted = 0, completed = 0, rejected = 0;
+    uint64_t persistent_sweeps = 0, persistent_redos = 0;
     std::vector<double> lat_ns, qlat_ns, svc_ns;
     Clock::time_point t_create;
     // worker thread only: states of finished large requests (oldest first),
@@ -224,10 +230,34 @@ static bool service_slot(jsvd_server sv, Slot &s)
     if (q != hipSuccess) {
         done_status = JSVD_EDEVICE;
     } else if (!s.finishing) {
-        const DevScalars &h = state_staged(s.st);
-        if (!h.stop) {
-            if (state_sweep_async(s.st, s.stream) != JSVD_OK || hipEventRecord(s.ev, s.stream) != hipSuccess)
+        bool redone = false;
+        if (s.persistent) {
+            // a persistent sweep that gave up is redone step by step first
+            s.persistent = false;
+            if (state_after_persistent_async(s.st, s.stream, &redone) != JSVD_OK ||
+                (redone && hipEventRecord(s.ev, s.stream) != hipSuccess))
                 done_status = JSVD_EDEVICE;
+            if (redone) {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->persistent_redos++;
+            }
+        }
+        const DevScalars &h = state_staged(s.st);
+        if (done_status != kRunning || redone) {
+            // the redo's scalars are read once it has run
+        } else if (!h.stop) {
+            bool alone;
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                alone = sv->active == 1;
+            }
+            if (state_next_sweep_async(s.st, s.stream, alone, &s.persistent) != JSVD_OK ||
+                hipEventRecord(s.ev, s.stream) != hipSuccess)
+                done_status = JSVD_EDEVICE;
+            if (s.persistent) {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                sv->persistent_sweeps++;
+            }
         } else if (h.status != 0) {
             done_status = h.status;
         } else {
@@ -341,6 +371,7 @@ static bool admit(jsvd_server sv)
         s.ticket = big;
         s.group = group;
         s.finishing = 0;
+        s.persistent = false;
         sv->hbm_in_use += fp_total;
         sv->active++;
     }
@@ -549,6 +580,8 @@ extern "C" int jsvd_serve_stats_get(jsvd_server sv, jsvd_serve_stats *out)
         out->queue_depth = (int)sv->queue.size();
         out->active = sv->active;
         out->hbm_in_use = sv->hbm_in_use;
+        out->persistent_sweeps = sv->persistent_sweeps;
+        out->persistent_redos = sv->persistent_redos;
     }
     out->p50_ns = percentile(lat, 0.50);
     out->p99_ns = percentile(lat, 0.99);

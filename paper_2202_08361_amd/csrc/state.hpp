@@ -85,6 +85,16 @@ int state_load_async(jsvd_state st, const float *G_re, const float *G_im, size_t
 // Enqueue one sweep (a graph of K steps and the end-of-sweep bookkeeping)
 // followed by the copy of the scalars into the state's pinned staging area.
 int state_sweep_async(jsvd_state st, hipStream_t s);
+// Enqueue the next sweep as jsvd_state_iterate runs it: where
+// allow_persistent, the state admits it and the staged scalars (those of the
+// sweep before, so not right after a load) say that no rescaling can happen
+// in it, as one persistent launch (*persistent = true), else step by step;
+// then the copy of the scalars.
+int state_next_sweep_async(jsvd_state st, hipStream_t s, bool allow_persistent, bool *persistent);
+// Once a persistent sweep so enqueued has completed (its scalars staged):
+// if it gave up, restore the state from the copy taken before it and
+// enqueue the sweep step by step with the copy of the scalars (*redone).
+int state_after_persistent_async(jsvd_state st, hipStream_t s, bool *redone);
 // The scalars staged by the last state_sweep_async (valid once the stream
 // has passed that point).
 const DevScalars &state_staged(jsvd_state st);

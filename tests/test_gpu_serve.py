@@ -63,6 +63,29 @@ def test_serve_mix_equals_alone():
         _same(r, _alone(Ar, Ai))
 
 
+@pytest.mark.parametrize("shapes", [
+    [(256, 256, False, 1e6)],                       # a small request alone: its own state, L2-local sweeps
+    [(700, 300, True, 1e4), (120, 100, False, 1e3)],   # a mid-size request (spread sweeps), then a small one
+])
+def test_serve_lone_requests_sweep_persistently(shapes):
+    """Requests submitted one at a time, each alone on the device: their
+    sweeps run as persistent launches (the server's count), and each result
+    is bit for bit the one jsvd_gesvj gives."""
+    pool = _pool(shapes, 7)
+    srv = J().Server(hbm_budget_bytes=4 << 30, max_slots=4)
+    results = []
+    for (Ar, Ai) in pool:
+        t = srv.submit(J().to_device_fortran(Ar), None if Ai is None else J().to_device_fortran(Ai))
+        assert t is not None
+        results.append(srv.wait(t))
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(pool)
+    assert st["persistent_sweeps"] > 0 and st["persistent_redos"] == 0, st
+    for (Ar, Ai), r in zip(pool, results):
+        _same(r, _alone(Ar, Ai))
+
+
 def test_serve_groups_past_a_waiting_large_request():
     # two slots, one large request at a time: the first large request runs,
     # the second waits at the head of the queue, and the 40 small requests
