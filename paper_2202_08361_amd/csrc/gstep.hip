@@ -193,7 +193,7 @@ __global__ __launch_bounds__(W, (gpair_wgs_per_cu<T, CPLX, R, COMP>() * W / 256)
         T *const Dq_i = pbit ? Gpi : Gqi;
         if (dc.transform) {
             T mm[1] = {transform_regs<CPLX, R>(xr, xi, dc)};
-            group_max<W, 1>(mm, mxs + 2 * (W / 64));
+            group_max<W, 1, valu_trees<R>()>(mm, mxs + 2 * (W / 64));
             pmx = mm[0];
             pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
             pp.c = dc.c;

@@ -152,10 +152,17 @@ __device__ __forceinline__ T lane0(T x)
 
 // In-wave halving tree: lane 0 ends with x_0 + x_1 + ... in the canonical
 // order (lane i += lane i+h for h = 32, ..., 1); the total is broadcast to
-// every lane.
-template <typename T>
+// every lane.  VALU = false moves the lanes through the LDS crossbar
+// (ds_bpermute) instead: the same sums, slower, but with fewer temporary
+// registers, for kernels at the edge of their register budget.
+template <bool VALU = true, typename T>
 __device__ __forceinline__ T wave_tree_sum(T x)
 {
+    if constexpr (!VALU) {
+#pragma unroll
+        for (int h = 32; h >= 1; h >>= 1) x = x + __shfl_down(x, h, 64);
+        return __shfl(x, 0, 64);
+    }
     x = x + lane_down<32>(x);
     x = x + lane_down<16>(x);
     x = x + lane_down<8>(x);
@@ -166,9 +173,14 @@ __device__ __forceinline__ T wave_tree_sum(T x)
 }
 
 // The wave's maximum of non-negative values (exact, so any order), in every lane.
-template <typename T>
+template <bool VALU = true, typename T>
 __device__ __forceinline__ T wave_max(T x)
 {
+    if constexpr (!VALU) {
+#pragma unroll
+        for (int h = 32; h >= 1; h >>= 1) x = fmax(x, __shfl_xor(x, h, 64));
+        return x;
+    }
     x = fmax(x, lane_down<32>(x));
     x = fmax(x, lane_down<16>(x));
     x = fmax(x, lane_down<8>(x));
@@ -181,13 +193,13 @@ __device__ __forceinline__ T wave_max(T x)
 // Group-wide canonical sum of NQ quantities (one value per thread each, the
 // thread's in-thread tree already applied).  lds must hold NQ * W values and
 // must not be reused by the caller until after the next workgroup barrier.
-template <int W, int NQ, typename T>
+template <int W, int NQ, bool VALU = true, typename T>
 __device__ __forceinline__ void group_tree_sum(T (&v)[NQ], T *lds)
 {
     constexpr int NW = W / 64;
     if constexpr (NW == 1) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) v[q] = wave_tree_sum(v[q]);
+        for (int q = 0; q < NQ; ++q) v[q] = wave_tree_sum<VALU>(v[q]);
     } else {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
@@ -203,18 +215,18 @@ __device__ __forceinline__ void group_tree_sum(T (&v)[NQ], T *lds)
             for (int h = NW / 2; h >= 1; h >>= 1)
 #pragma unroll
                 for (int w = 0; w < h; ++w) x[w] = x[w] + x[w + h];
-            v[q] = wave_tree_sum(x[0]);
+            v[q] = wave_tree_sum<VALU>(x[0]);
         }
     }
 }
 
 // Group-wide max of NQ non-negative quantities (exact, order-free).
-template <int W, int NQ, typename T>
+template <int W, int NQ, bool VALU = true, typename T>
 __device__ __forceinline__ void group_max(T (&v)[NQ], T *lds)
 {
     constexpr int NW = W / 64;
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) v[q] = wave_max(v[q]);
+    for (int q = 0; q < NQ; ++q) v[q] = wave_max<VALU>(v[q]);
     if constexpr (NW > 1) {
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
         if (lane == 0) {
@@ -231,6 +243,14 @@ __device__ __forceinline__ void group_max(T (&v)[NQ], T *lds)
         }
     }
 }
+
+// The cross-lane method of the trees of a pair held at R rows per thread:
+// the VALU moves where registers allow; from 16 rows per thread on (a
+// column pair that fills most of the register file) the LDS permutes, whose
+// fewer temporaries keep the kernel free of spills and at two workgroups
+// per compute unit.
+template <int R>
+constexpr bool valu_trees() { return R < 16; }
 
 // In-thread part of the canonical tree for a thread holding rows j < R:
 // lane v = j mod V (V = S/W virtual lanes per thread), chain position
@@ -517,7 +537,7 @@ __device__ __forceinline__ void pair_dot(const T (&xr)[2][R], const T (&xi)[2][R
         T g[ND];
         g[0] = thread_tree<V>(dr);
         if (CPLX) g[ND - 1] = thread_tree<V>(di);
-        group_tree_sum<W, ND>(g, lds);
+        group_tree_sum<W, ND, valu_trees<R>()>(g, lds);
         h[0] = g[0];
         h[1] = CPLX ? g[ND - 1] : T(0);
     } else {
@@ -573,7 +593,7 @@ __device__ __forceinline__ void pair_dot(const T (&xr)[2][R], const T (&xi)[2][R
         for (int st = 0; st < NS; ++st)
 #pragma unroll
             for (int u = 0; u < 4; ++u) g[4 * st + u] = thread_tree<V>(a[st][u]);
-        group_tree_sum<W, 4 * NS>(g, lds);
+        group_tree_sum<W, 4 * NS, valu_trees<R>()>(g, lds);
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
             double z = g[4 * st + 2] + g[4 * st + 3];
@@ -669,7 +689,7 @@ __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const
             mx[c] = fmax(mx[c], fabs(xr[c][j]));
             if (CPLX) mx[c] = fmax(mx[c], fabs(xi[c][j]));
         }
-    group_max<W, 2>(mx, mxs);
+    group_max<W, 2, valu_trees<R>()>(mx, mxs);
     const bool zp_ = mx[0] == T(0), zq_ = mx[1] == T(0);
     const int Ep = zp_ ? 0 : getexp(mx[0]);
     const int Eq = zq_ ? 0 : getexp(mx[1]);
@@ -698,7 +718,7 @@ __device__ __forceinline__ PairDecisionT<T> pair_core(const T (&xr)[2][R], const
     T s[NQ];
 #pragma unroll
     for (int qq = 0; qq < NQ; ++qq) s[qq] = thread_tree<V>(acc[qq]);
-    group_tree_sum<W, NQ>(s, red_norm);
+    group_tree_sum<W, NQ, valu_trees<R>()>(s, red_norm);
     NormT<T> np = norm_from_sums(Ep, s[0], CPLX ? s[2] : T(0), CPLX);
     NormT<T> nq = norm_from_sums(Eq, s[1], CPLX ? s[3] : T(0), CPLX);
     np.zero = zp_;

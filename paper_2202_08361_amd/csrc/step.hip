@@ -217,7 +217,7 @@ __global__ __launch_bounds__(W) void step_kernel(SvdDescT<T> d, StepSlot slot, S
             }
         }
         T mm[1] = {Mx};
-        group_max<W, 1>(mm, sm.mx2);
+        group_max<W, 1, valu_trees<R>()>(mm, sm.mx2);
         Mblk = mm[0];
         pp.flag = 1 | (pbit ? 2 : 0) | (dc.gs ? 4 : 0);
         pp.c = dc.c;
