@@ -226,9 +226,10 @@ int jsvd_state_set_loop_wait(jsvd_state st, double seconds);
 /* Whether persistent sweeps of the state may run in the L2-local mode
  * (allow = 1, the default) or always spread over the device (0).  In the
  * L2-local mode, used where every pair slot's workgroup fits on one XCC with
- * one wavefront per SIMD (columns of at most 256 rows, at most 4 x CUs/8
- * slots), the workgroups of one XCC take the slots and exchange columns
- * through its L2 without cache write-back or invalidation; the results are
+ * one wavefront per SIMD (n <= 256, columns of at most 1024 real / 512
+ * complex rows, at most 4 x CUs/8 slots), the workgroups of one XCC take the
+ * slots and exchange columns through its L2 without cache write-back or
+ * invalidation; the results are
  * the same bits.  A sweep in that mode that gives up turns it off for the
  * state until the next call of this function.  JSVD_EINVAL for another
  * value of allow. */

@@ -24,7 +24,9 @@
 // the caller runs the sweep step by step.
 //
 // L2-local mode (64-thread workgroups, at most four per compute unit of one
-// XCC): the launch has one workgroup per pair slot on every XCC, and only
+// XCC, n <= 256; columns of up to 1024 real / 512 complex rows at 8 or 16
+// rows per lane, the same canonical sums): the launch has one workgroup per pair slot on every
+// XCC, and only
 // those that land on one XCC (the first one to arrive names it) take the
 // slots; the others end at once.  Those workgroups share one L2, which is
 // then the point of coherence for everything the sweep exchanges: columns
@@ -165,6 +167,10 @@ template <bool CPLX, int W, int R, bool COMP, bool LOCAL, typename T>
 __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
 {
     static_assert(!LOCAL || W == 64, "the L2-local mode has one wavefront per workgroup");
+    // rows of V per thread: V has n <= 256 rows wherever a wavefront holds a
+    // pair slot (64-thread workgroups run for n <= 256 only), so a 64-thread
+    // workgroup with more G rows per lane keeps four of V's
+    constexpr int RV = (W == 64 && R > 4) ? 4 : R;
     // the reduction scratch of pair_core (a workgroup of one wavefront
     // reduces in registers alone)
     __shared__ T red[W > 64 ? (COMP ? 12 : 6) * W : 1];
@@ -223,18 +229,25 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
         T *const Vqr = d.Vr + (size_t)q * d.ldv;
         T *const Vpi = CPLX ? d.Vi + (size_t)p * d.ldv : nullptr;
         T *const Vqi = CPLX ? d.Vi + (size_t)q * d.ldv : nullptr;
-        T xr[2][R], xi[2][R], vr[2][R], vi[2][R];
+        T xr[2][R], xi[2][R], vr[2][RV], vi[2][RV];
 #pragma unroll
         for (int jj = 0; jj < R; ++jj) {
             const int i = t + W * jj;
-            const bool in = i < m, inv = i < n;
+            const bool in = i < m;
             xr[0][jj] = in ? col_load<LOCAL>(Gpr + i) : T(0);
             xr[1][jj] = in ? col_load<LOCAL>(Gqr + i) : T(0);
-            vr[0][jj] = inv ? col_load<LOCAL>(Vpr + i) : T(0);
-            vr[1][jj] = inv ? col_load<LOCAL>(Vqr + i) : T(0);
             if (CPLX) {
                 xi[0][jj] = in ? col_load<LOCAL>(Gpi + i) : T(0);
                 xi[1][jj] = in ? col_load<LOCAL>(Gqi + i) : T(0);
+            }
+        }
+#pragma unroll
+        for (int jj = 0; jj < RV; ++jj) {
+            const int i = t + W * jj;
+            const bool inv = i < n;
+            vr[0][jj] = inv ? col_load<LOCAL>(Vpr + i) : T(0);
+            vr[1][jj] = inv ? col_load<LOCAL>(Vqr + i) : T(0);
+            if (CPLX) {
                 vi[0][jj] = inv ? col_load<LOCAL>(Vpi + i) : T(0);
                 vi[1][jj] = inv ? col_load<LOCAL>(Vqi + i) : T(0);
             }
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
         if (dc.transform) {
             // this thread's max-norm; the workgroup's is taken once, at the end
             Mrun = fmax(Mrun, transform_regs<CPLX, R>(xr, xi, dc));
-            (void)rot_regs<CPLX, R>(vr, vi, dc.c, dc.C, dc.S);
+            (void)rot_regs<CPLX, RV>(vr, vi, dc.c, dc.C, dc.S);
             ++acc.t;
             if (dc.gs) ++acc.gs;
             if (j == K - 1) acc.tlast = 1;
@@ -275,6 +288,10 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
                         col_store<LOCAL>(Dq_i + i, xi[1][jj]);
                     }
                 }
+            }
+#pragma unroll
+            for (int jj = 0; jj < RV; ++jj) {
+                const int i = t + W * jj;
                 if (i < n) {
                     col_store<LOCAL>(Ep_r + i, vr[0][jj]);
                     col_store<LOCAL>(Eq_r + i, vr[1][jj]);
@@ -450,11 +467,14 @@ struct LoopShape {
     int W, R;
 };
 
-static LoopShape loop_shape(int m)
+static LoopShape loop_shape(int m, bool local)
 {
     if (m <= 64) return {64, 1};
     if (m <= 128) return {64, 2};
     if (m <= 256) return {64, 4};
+    // L2-local mode: one wavefront per slot throughout (its XCD has one SIMD
+    // per slot), with more rows per lane
+    if (local) return {64, m <= 512 ? 8 : 16};
     if (m <= 512) return {256, 2};
     return {256, 4};
 }
@@ -468,7 +488,14 @@ static const void *loop_fn_c(LoopShape sh, bool local)
         if (local) {
             if (sh.R <= 1) return (const void *)loop_kernel<CPLX, 64, 1, COMP, true, T>;
             if (sh.R <= 2) return (const void *)loop_kernel<CPLX, 64, 2, COMP, true, T>;
-            return (const void *)loop_kernel<CPLX, 64, 4, COMP, true, T>;
+            if (sh.R <= 4) return (const void *)loop_kernel<CPLX, 64, 4, COMP, true, T>;
+            if (sh.R <= 8) return (const void *)loop_kernel<CPLX, 64, 8, COMP, true, T>;
+            // a complex pair at 16 rows per lane is slower on one wavefront
+            // than spread over four (1000 x 199: 45.5 against 36.9 ms)
+            if constexpr (CPLX)
+                return nullptr;
+            else
+                return (const void *)loop_kernel<CPLX, 64, 16, COMP, true, T>;
         }
         if (sh.R <= 1) return (const void *)loop_kernel<CPLX, 64, 1, COMP, false, T>;
         if (sh.R <= 2) return (const void *)loop_kernel<CPLX, 64, 2, COMP, false, T>;
@@ -498,7 +525,7 @@ template <typename T>
 bool loop_fits(const SvdDescT<T> &d, int ncu)
 {
     if (d.m > loop_max_rows()) return false;
-    const LoopShape sh = loop_shape(d.m);
+    const LoopShape sh = loop_shape(d.m, false);
     const void *fn = loop_fn_of(d, sh, false);
     if (!fn) return false;
     int per_cu = 0;
@@ -513,8 +540,8 @@ bool loop_fits(const SvdDescT<T> &d, int ncu)
 template <typename T>
 bool loop_fits_local(const SvdDescT<T> &d, int ncu)
 {
-    if (d.m > loop_max_rows() || ncu % kXcc != 0) return false;
-    const LoopShape sh = loop_shape(d.m);
+    if (d.m > loop_max_rows() || d.n > 256 || ncu % kXcc != 0) return false;
+    const LoopShape sh = loop_shape(d.m, true);
     if (sh.W != 64) return false;
     const void *fn = loop_fn_of(d, sh, true);
     if (!fn) return false;
@@ -530,7 +557,7 @@ hipError_t launch_loop_sweep(const SvdDescT<T> &d, const LoopArgs &a, hipStream_
 {
     const int N = d.n + (d.n & 1), npairs = N / 2, K = N - 1;
     if (d.m > loop_max_rows()) return hipErrorInvalidValue;
-    const LoopShape sh = loop_shape(d.m);
+    const LoopShape sh = loop_shape(d.m, a.local != 0);
     const void *fn = loop_fn_of(d, sh, a.local != 0);
     if (!fn) return hipErrorInvalidValue;
     SvdDescT<T> dd = d;

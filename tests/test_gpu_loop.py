@@ -68,11 +68,13 @@ def _iterate(Ar, Ai, flags=0, wait=None, threads=0, local=None):
     return out
 
 
-def _local_fits(m, n):
-    """The L2-local mode applies: 64-thread workgroups (m <= 256), every slot
-    on one of the 8 XCCs with at most four workgroups per compute unit."""
+def _local_fits(m, n, cplx=False):
+    """The L2-local mode applies: n <= 256 and columns of at most 1024 real /
+    512 complex rows (one 64-thread workgroup per slot, 1 to 16 rows per
+    lane), every slot on one of the 8 XCCs with at most four workgroups per
+    compute unit."""
     ncu = torch.cuda.get_device_properties(0).multi_processor_count
-    return m <= 256 and ncu % 8 == 0 and (n + 1) // 2 <= 4 * (ncu // 8)
+    return m <= (512 if cplx else 1024) and n <= 256 and ncu % 8 == 0 and (n + 1) // 2 <= 4 * (ncu // 8)
 
 
 def _same(a, b, tag):
@@ -89,7 +91,9 @@ def _same(a, b, tag):
     (60, 60, True, 8), (33, 2, False, 0), (5, 3, True, 0), (1, 1, False, 0), (130, 129, False, 4),
     # 256-thread workgroups (257 to 1024 rows)
     (300, 200, False, 0), (512, 300, True, 0), (1024, 130, False, 2), (700, 255, True, 8), (640, 97, False, 0),
-    (257, 257, True, 4)])
+    (257, 257, True, 4),
+    # one wavefront at 8 and 16 rows per lane (the L2-local mode beyond 256 rows)
+    (512, 256, False, 0), (1000, 199, True, 2), (1024, 256, False, 4), (384, 120, True, 0)])
 def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     Ar, Ai = _matrix(m, n, cplx, 1e6, m + 3 * n)
     got = _iterate(Ar, Ai, flags)
@@ -98,7 +102,7 @@ def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     # the sweeps ran as persistent launches and none had to be redone; in the
     # L2-local mode where the slots fit on one XCC
     assert info["loop_sweeps"] == info["sweeps"] + 1 and info["loop_redos"] == 0, info
-    assert info["local_sweeps"] == (info["loop_sweeps"] if _local_fits(m, n) else 0), info
+    assert info["local_sweeps"] == (info["loop_sweeps"] if _local_fits(m, n, cplx) else 0), info
     ora_flags = (ora.COMPENSATED if flags & 2 else 0) | (ora.PERMUTE if flags & 8 else 0) | \
         (ora.NO_GS if flags & 4 else 0)
     ro = ora.gesvj(Ar, Ai, flags=ora_flags)
@@ -111,7 +115,7 @@ def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     steps = _iterate(Ar, Ai, flags, threads=64 if m <= 512 else 256)
     assert steps["info"]["loop_sweeps"] == 0
     _same(got, steps, "steps")
-    if _local_fits(m, n):
+    if _local_fits(m, n, cplx):
         # the same persistent sweeps spread over the device
         spread = _iterate(Ar, Ai, flags, local=False)
         assert spread["info"]["local_sweeps"] == 0 and spread["info"]["loop_sweeps"] == info["loop_sweeps"]
@@ -179,7 +183,7 @@ def test_local_mode_gives_up_and_turns_off(m, n, cplx):
     the state: the later persistent sweeps are spread ones (which give up
     too, at that budget), and the bits are those of step-by-step sweeps.
     jsvd_state_set_loop_local(st, 1) turns it on again."""
-    if not _local_fits(m, n):
+    if not _local_fits(m, n, cplx):
         pytest.skip("the slots do not fit on one XCC of this device")
     Ar, Ai = _matrix(m, n, cplx, 1e5, 900 + m)
     got = _iterate(Ar, Ai, wait=1e-6)
