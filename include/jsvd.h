@@ -208,10 +208,11 @@ int jsvd_sweep(jsvd_state st, void *stream);
 /* Sweeps until the state stops (converged, or the sweep limit), one
  * graph-launched sweep at a time with a synchronisation after each (the
  * device decides convergence): the iteration of jsvd_gesvj on a loaded
- * state.  For columns of at most 256 rows (automatic launch shape) a sweep
- * runs as one persistent launch whenever the device has found that the
- * rescaling check of Sect. 3.2 cannot fire in it (max(M~, (1 + 32 eps K)
- * ||G||_F) below the threshold): one workgroup per pair slot, each pair of
+ * state.  For columns of at most 1024 rows and at most 192 pair slots
+ * (automatic launch shape) a sweep runs as one persistent launch whenever
+ * the device has found that the rescaling check of Sect. 3.2 cannot fire in
+ * it (max(M~, (1 + 32 eps K) ||G||_F) below the threshold): one workgroup
+ * per pair slot, each pair of
  * step k + 1 starting as soon as its two columns are out of step k.  The
  * result is the same, bit for bit, as K steps.  Such a sweep needs its
  * workgroups resident together; one that waits too long for a column gives
