@@ -762,6 +762,21 @@ static int build_graph(jsvd_state st)
     return JSVD_OK;
 }
 
+// The per-column steps of the last change, reset (every column "changed
+// now") unless they are current: enqueued outside any graph.
+static hipError_t lastmod_ensure(jsvd_state st, hipStream_t s)
+{
+    if (st->lastmod_valid) return hipSuccess;
+    StepSlot none;
+    none.prm = nullptr;
+    none.mx = nullptr;
+    none.hdr = nullptr;
+    none.mxkey = nullptr;
+    const hipError_t e = st->fp32 ? launch_lastmod_reset(st->df, none, s) : launch_lastmod_reset(st->d, none, s);
+    if (e == hipSuccess) st->lastmod_valid = 1;
+    return e;
+}
+
 extern "C" int jsvd_sweep(jsvd_state st, void *stream)
 {
     if (!st) return JSVD_EINVAL;
@@ -772,16 +787,7 @@ extern "C" int jsvd_sweep(jsvd_state st, void *stream)
     HIPCHK(settle(st, (hipStream_t)stream));
     // the last-change steps are reset here, outside the graph: inside it the
     // reset would run again at every replay and no pair would ever be skipped
-    if (uses_gpair(st) && !st->lastmod_valid) {
-        StepSlot none;
-        none.prm = nullptr;
-        none.mx = nullptr;
-        none.hdr = nullptr;
-        none.mxkey = nullptr;
-        HIPCHK(st->fp32 ? launch_lastmod_reset(st->df, none, (hipStream_t)stream)
-                        : launch_lastmod_reset(st->d, none, (hipStream_t)stream));
-        st->lastmod_valid = 1;
-    }
+    if (uses_gpair(st)) HIPCHK(lastmod_ensure(st, (hipStream_t)stream));
     const int rc = build_graph(st);
     if (rc != JSVD_OK) return rc;
     HIPCHK(hipGraphLaunch(st->graph, (hipStream_t)stream));
@@ -995,9 +1001,11 @@ int jsvd::state_next_sweep_async(jsvd_state st, hipStream_t s, bool allow_persis
         // transposes V once
         HIPCHK(set_v_layout(st, V_COLS, s));
         HIPCHK(settle(st, s));
+        // the sweep reads and keeps the last-change steps (outside its graph,
+        // as for the large-column steps)
+        HIPCHK(lastmod_ensure(st, s));
         HIPCHK(hipGraphLaunch(st->loop_graph, s));
         HIPCHK(hipMemcpyAsync(st->host, st->sc, sizeof(DevScalars), hipMemcpyDeviceToHost, s));
-        st->lastmod_valid = 0;   // the persistent sweep changes columns without recording it
         *persistent = true;
         return JSVD_OK;
     }
@@ -1017,6 +1025,8 @@ int jsvd::state_after_persistent_async(jsvd_state st, hipStream_t s, bool *redon
             st->loop_local_sweeps++;
     }
     if (!gave_up) return JSVD_OK;
+    // the sweep that gave up recorded part of its changes: the record starts over
+    st->lastmod_valid = 0;
     char *gbase = st->fp32 ? (char *)st->df.Gr : (char *)st->d.Gr;
     HIPCHK(hipMemcpyAsync(gbase, st->snap, st->snap_bytes, hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_loop_clear(st->sc, s));

@@ -186,6 +186,7 @@ hipError_t launch_sweep_end(DevScalars *sc, hipStream_t s);
 // a whole sweep in one persistent launch (loop.hip), for m <= 256
 struct LoopAcc {                  // one workgroup's share of the sweep's fold
     long long t, sw, gs, tlast;   // transformations, swaps, Gram-Schmidt steps, transformations of the last step
+    long long sk;                 // pairs not read: unchanged since they last met
     double M;                     // max-norm of the transformed columns
     int done;                     // steps completed (K unless the launch gave up)
     int pad;

@@ -39,6 +39,14 @@
 // on the XCC, the waits run out of budget and the sweep is redone step by
 // step like any other that gives up.
 //
+// A pair whose two columns have not changed since it last met, one sweep
+// earlier (the per-column step of the last change, kept up to date by the
+// sweep like the large-column steps keep it), had no transformation and no
+// swap then, and its columns are the same now: its workgroup computes and
+// stores nothing for it and only passes the columns on.  (The columns are
+// loaded anyway, together with the two last-change steps: loading those
+// first would add a memory round trip to every step.)
+//
 // Every wait is bounded (a wall-clock budget); a workgroup that runs out of
 // it raises an abort flag that every other one sees, so the launch always
 // ends.  The counts and the max-norm are kept per workgroup and folded once
@@ -182,7 +190,7 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
     const int t = threadIdx.x;
     DevScalars *sc = d.sc;
     LoopAcc acc;
-    acc.t = acc.sw = acc.gs = acc.tlast = 0;
+    acc.t = acc.sw = acc.gs = acc.tlast = acc.sk = 0;
     acc.M = 0.0;
     acc.done = 0;
     // the scalars do not change during the launch: every workgroup reads the same
@@ -221,6 +229,9 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
             ++steps;
             continue;
         }
+        // the steps of the columns' last changes, loaded beside the columns
+        // (a load before the columns' would add its latency to every step)
+        const long long lm_p = col_load<LOCAL>(d.lastmod + p), lm_q = col_load<LOCAL>(d.lastmod + q);
         T *const Gpr = d.Gr + (size_t)p * d.ldg;
         T *const Gqr = d.Gr + (size_t)q * d.ldg;
         T *const Gpi = CPLX ? d.Gi + (size_t)p * d.ldg : nullptr;
@@ -251,6 +262,14 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
                 vi[0][jj] = inv ? col_load<LOCAL>(Vpi + i) : T(0);
                 vi[1][jj] = inv ? col_load<LOCAL>(Vqi + i) : T(0);
             }
+        }
+        // both columns unchanged since the pair last met (K steps ago, when it
+        // changed neither): the same outcome, no change, so nothing to compute
+        if (lm_p < k - K && lm_q < k - K) {
+            ++acc.sk;
+            loop_publish<LOCAL>(a, p, q, epoch | (unsigned)(j + 1));
+            ++steps;
+            continue;
         }
         // no rescaling in this sweep (checked before the launch)
         const PairDecisionT<T> dc = pair_core<CPLX, W, R, COMP>(xr, xi, d.ups, d.nosort, d.nogs, red_norm, red_dot, mxs_p);
@@ -302,6 +321,12 @@ __global__ __launch_bounds__(W) void loop_kernel(SvdDescT<T> d, LoopArgs a)
                 }
             }
         }
+        if (t == 0 && (dc.transform || pbit)) {
+            // the step of the last change of both columns (read with the
+            // columns by their next owners)
+            col_store<LOCAL>(d.lastmod + p, k);
+            col_store<LOCAL>(d.lastmod + q, k);
+        }
         if (t == 0) {
             const NormT<T> np_ = dc.np, nq_ = dc.nq;
             const int dp = pbit ? q : p, dq = pbit ? p : q;
@@ -337,7 +362,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs a, int npairs, int K)
 {
     __shared__ double sM[4];
-    __shared__ long long sc4[4][5];
+    __shared__ long long sc4[4][6];
     DevScalars *sc = d.sc;
     // the slot claims of an L2-local launch start from zero in the next one
     if (a.local && threadIdx.x == 0) {
@@ -347,7 +372,7 @@ __global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs 
     if (sc->stop) return;
     const int t = threadIdx.x;
     double M = 0.0;
-    long long tt = 0, sw = 0, gg = 0, tl = 0, short_ = 0;
+    long long tt = 0, sw = 0, gg = 0, tl = 0, short_ = 0, sk = 0;
     for (int l = t; l < npairs; l += 256) {
         const LoopAcc x = a.acc[l];
         M = fmax(M, x.M);
@@ -355,6 +380,7 @@ __global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs 
         sw += x.sw;
         gg += x.gs;
         tl += x.tlast;
+        sk += x.sk;
         short_ += (x.done != K) ? 1 : 0;
     }
     M = wave_max(M);
@@ -364,6 +390,7 @@ __global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs 
         sw += __shfl_xor(sw, h, 64);
         gg += __shfl_xor(gg, h, 64);
         tl += __shfl_xor(tl, h, 64);
+        sk += __shfl_xor(sk, h, 64);
         short_ += __shfl_xor(short_, h, 64);
     }
     if ((t & 63) == 0) {
@@ -373,12 +400,13 @@ __global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs 
         sc4[t >> 6][2] = gg;
         sc4[t >> 6][3] = tl;
         sc4[t >> 6][4] = short_;
+        sc4[t >> 6][5] = sk;
     }
     __syncthreads();
     if (t != 0) return;
     for (int w = 1; w < 4; ++w) {
         sM[0] = fmax(sM[0], sM[w]);
-        for (int c = 0; c < 5; ++c) sc4[0][c] += sc4[w][c];
+        for (int c = 0; c < 6; ++c) sc4[0][c] += sc4[w][c];
     }
     const bool aborted = *a.abort != 0 || sc4[0][4] != 0;
     *a.abort = 0;
@@ -393,6 +421,7 @@ __global__ __launch_bounds__(256) void loop_fold_kernel(SvdDescT<T> d, LoopArgs 
     sc->SW += sc4[0][1];
     sc->GS += sc4[0][2];
     sc->last_t = sc4[0][3];
+    sc->skipped += sc4[0][5];
     sc->k += K;
     sc->loop_sweeps += 1;
 }

@@ -53,7 +53,7 @@ struct jsvd_state_s {
     int loop_local_allow;    // persistent sweeps may run in the L2-local mode (default)
     int loop_local_failed;   // an L2-local sweep gave up: the state keeps the spread mode
     long long loop_local_sweeps;   // persistent sweeps that ran in the L2-local mode
-    int lastmod_valid;       // the per-column last-change steps are current (only large-column steps ran since their reset)
+    int lastmod_valid;       // the per-column last-change steps are current (only large-column steps and persistent sweeps ran since their reset)
 };
 
 namespace jsvd {

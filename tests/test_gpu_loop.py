@@ -3,7 +3,9 @@ soon as their columns are out of the previous step) used by
 jsvd_state_iterate and jsvd_gesvj for columns of at most 1024 rows.
 
 The bar is bit-for-bit equality with the CPU oracle (U, V, sigma, sweep
-count), and with the step-by-step sweeps of the same state (forced by a
+count; the oracle reads every pair, the persistent sweep skips those whose
+columns have not changed since they last met), and with the step-by-step
+sweeps of the same state (forced by a
 fixed launch shape, or by a zero wait budget).  Also: the sweeps did run as
 persistent launches (jsvd_state_query's count), a matrix whose Frobenius
 bound rules the persistent sweep out gives the same bits through the
@@ -103,6 +105,9 @@ def test_loop_matches_oracle_and_steps(ora, m, n, cplx, flags):
     # L2-local mode where the slots fit on one XCC
     assert info["loop_sweeps"] == info["sweeps"] + 1 and info["loop_redos"] == 0, info
     assert info["local_sweeps"] == (info["loop_sweeps"] if _local_fits(m, n, cplx) else 0), info
+    # the pairs whose columns had not changed since they last met were not read
+    if n >= 64:
+        assert info["skipped_pairs"] > 0, info
     ora_flags = (ora.COMPENSATED if flags & 2 else 0) | (ora.PERMUTE if flags & 8 else 0) | \
         (ora.NO_GS if flags & 4 else 0)
     ro = ora.gesvj(Ar, Ai, flags=ora_flags)
