@@ -120,6 +120,55 @@ def last_call_table(db, pattern):
     return "\n".join(out)
 
 
+def _union_ns(spans, a, b):
+    """Length of the union of the intervals (start, end), sorted by start,
+    clipped to [a, b)."""
+    tot, cs, ce = 0, None, None
+    for s_, e_ in spans:
+        s_, e_ = max(s_, a), min(e_, b)
+        if e_ <= s_:
+            continue
+        if ce is None or s_ > ce:
+            if ce is not None:
+                tot += ce - cs
+            cs, ce = s_, e_
+        else:
+            ce = max(ce, e_)
+    if ce is not None:
+        tot += ce - cs
+    return tot
+
+
+def busy_table(db, window_s=5.0, families=12):
+    """How busy the device was over a kernel trace: the union of all kernel
+    intervals (any stream) as a fraction of the span from the first start to
+    the last end, overall and per window, and the summed kernel time per
+    kernel family (template arguments dropped; kernels on concurrent
+    streams overlap, so the sum may exceed the span)."""
+    rows = _rocpd_rows(db, "select name, start, end from kernels order by start")
+    if not rows:
+        raise SystemExit("no kernel dispatches in the trace")
+    spans = [(r[1], r[2]) for r in rows]
+    t0, t1 = rows[0][1], max(r[2] for r in rows)
+    out = [f"{len(rows)} dispatches over {(t1 - t0) / 1e9:.2f} s; device busy "
+           f"{_union_ns(spans, t0, t1) / max(t1 - t0, 1):.3f} of it.", "",
+           "| window s | busy |", "|---|---|"]
+    w = int(window_s * 1e9)
+    a = t0
+    while a < t1:
+        b = min(a + w, t1)
+        out.append(f"| {(a - t0) / 1e9:.1f}–{(b - t0) / 1e9:.1f} | {_union_ns(spans, a, b) / (b - a):.3f} |")
+        a = b
+    fam = {}
+    for nm, st, en in rows:
+        key = nm.replace("void ", "").split("<")[0].split("(")[0]
+        fam[key] = fam.get(key, 0) + (en - st)
+    out += ["", "| kernel family | summed time s |", "|---|---|"]
+    for key, v in sorted(fam.items(), key=lambda x: -x[1])[:families]:
+        out.append(f"| `{key}` | {v / 1e9:.2f} |")
+    return "\n".join(out)
+
+
 def counters_table(fetch_db, write_db, calib_mib, last_of=None):
     """Per kernel: the mean FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of one
     counter run each, and the HBM bytes per dispatch after scaling each
@@ -852,6 +901,9 @@ def main():
     ap.add_argument("--counters", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
                     help="print per-kernel HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE databases of runs "
                          "made with --calib-copy, and exit")
+    ap.add_argument("--busy", action="store_true",
+                    help="with --trace-summary: print the device's busy fraction over the trace (the union of "
+                         "all kernel intervals, overall and per 5 s window) and the kernel time per family instead")
     ap.add_argument("--last-call", metavar="PATTERN",
                     help="with --trace-summary: also list the dispatches of the last call into kernels matching "
                          "PATTERN; with --counters: count only the last dispatch of each such kernel")
@@ -859,6 +911,9 @@ def main():
                     help="derive the EVD kernels' HBM bytes per launch from FETCH_SIZE / WRITE_SIZE "
                          "databases of runs made with --calib-copy, write profiles/evd2_traffic.json, exit")
     args = ap.parse_args()
+    if args.trace_summary and args.busy:
+        print(busy_table(args.trace_summary))
+        return
     if args.trace_summary:
         print(trace_summary(args.trace_summary))
         if args.last_call:
