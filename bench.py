@@ -931,7 +931,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the batched EVD and the Jacobi step are single-device "
-              "kernels here (how the path would shard across GPUs is described in DESIGN.md)",
+              "kernels here; sharding them across GPUs is not built",
               file=sys.stderr)
         sys.exit(2)
 
