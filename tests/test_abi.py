@@ -56,6 +56,11 @@ def test_host_only_calls():
     # the compensated dot-products are double precision only (rejected before any device call)
     p = ctypes.c_void_p(256)
     assert L.jsvd_gesvj_f32(8, 4, p, None, 8, p, None, 4, p, p, None, 0, None, J.COMPENSATED, None) == J.EINVAL
+    # the persistent sweep's settings need a state
+    L.jsvd_state_set_loop_local.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.jsvd_state_set_loop_wait.argtypes = [ctypes.c_void_p, ctypes.c_double]
+    assert L.jsvd_state_set_loop_local(None, 1) == J.EINVAL
+    assert L.jsvd_state_set_loop_wait(None, 0.25) == J.EINVAL
 
 
 def test_no_oracle_in_product():
