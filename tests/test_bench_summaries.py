@@ -1,7 +1,9 @@
 """The benchmark's profile summarisers on small synthetic rocprofv3-style
 databases (no GPU): the busy fraction of a kernel trace is the union of the
 kernel intervals, overlaps counted once, per window and overall; the last
-call of a batched launch is the last group of overlapping dispatches."""
+call of a batched launch is the last group of overlapping dispatches; the
+byte counters are scaled by what they read for a plain copy of known size
+(the arithmetic behind the headline's traffic figure)."""
 import os
 import sqlite3
 import sys
@@ -65,3 +67,59 @@ def test_last_call_is_the_last_overlapping_group(tmp_path):
     assert out.startswith("Last call: 3 dispatches")
     assert "span 0.1 us" in out   # 40 .. 120 ns
     assert out.count("| `batched_kernel<") == 3
+
+
+def _counter_db(tmp_path, name, rows):
+    db = str(tmp_path / name)
+    con = sqlite3.connect(db)
+    con.execute("create table counters_collection (dispatch_id integer, kernel_name text, grid_size integer, "
+                "value real)")
+    con.executemany("insert into counters_collection values (?,?,?,?)",
+                    [(i, nm, g, v) for i, (nm, g, v) in enumerate(rows)])
+    con.commit()
+    con.close()
+    return db
+
+
+def test_counters_are_scaled_by_the_calibration_copy(tmp_path):
+    """A copy of 512 MiB that FETCH_SIZE reads as half its bytes (one read per
+    64 B line counted as 32 B, say) and WRITE_SIZE as all of them: FETCH is
+    scaled by 2, WRITE by 1; a kernel's scaled bytes per dispatch are the
+    means of its dispatches, scaled; with last_of only the last dispatch of a
+    matching kernel counts."""
+    mib = 512
+    fetch = [("__amd_rocclr_copyBuffer", 0, mib * 1024 / 2), ("kern_a", 0, 100.0), ("kern_a", 0, 300.0),
+             ("kern_b", 0, 50.0), ("__amd_rocclr_copyBuffer", 0, 1.0)]
+    write = [("__amd_rocclr_copyBuffer", 0, mib * 1024), ("kern_a", 0, 10.0), ("kern_a", 0, 30.0),
+             ("kern_b", 0, 5.0), ("__amd_rocclr_copyBuffer", 0, 2.0)]
+    fdb, wdb = _counter_db(tmp_path, "f.db", fetch), _counter_db(tmp_path, "w.db", write)
+    out = bench.counters_table(fdb, wdb, mib)
+    # kern_a: mean fetch 200 KiB x 2 + mean write 20 KiB x 1 = 420 KiB = 0.430 MB
+    assert "| `kern_a` | 2 | 200.0 | 20.0 | 0.430 |" in out
+    assert "| `kern_b` | 1 | 50.0 | 5.0 | 0.108 |" in out
+    assert "scale factors 2.0000 and 1.0000" in out
+    # only the last dispatch of kern_a: 300 x 2 + 30 = 630 KiB
+    out = bench.counters_table(fdb, wdb, mib, last_of="kern_a")
+    assert "| `kern_a` | 1 | 300.0 | 30.0 | 0.645 |" in out
+
+
+def test_counters_need_the_calibration_copy(tmp_path):
+    rows = [("kern_a", 0, 1.0)]
+    with pytest.raises(SystemExit):
+        bench.counters_table(_counter_db(tmp_path, "f.db", rows), _counter_db(tmp_path, "w.db", rows), 512)
+
+
+def test_evd_traffic_record(tmp_path):
+    """The EVD kernels' bytes per launch: the last dispatch of each kernel,
+    each counter scaled by the first copy; the record names the sources it
+    was taken for."""
+    r = 1 << 26
+    real, cplx = bench.evd_kernel_name(r, False), bench.evd_kernel_name(r, True)
+    fetch = [("__amd_rocclr_copyBuffer", 0, 262144.0), (real, 0, 1.0), (real, 0, 1000.0), (cplx, 0, 2000.0)]
+    write = [("__amd_rocclr_copyBuffer", 0, 524288.0), (real, 0, 1.0), (real, 0, 3000.0), (cplx, 0, 4000.0)]
+    rec, md = bench.traffic_from(_counter_db(tmp_path, "f.db", fetch), _counter_db(tmp_path, "w.db", write), 512, r)
+    assert rec["fetch_scale"] == 2.0 and rec["write_scale"] == 1.0
+    assert rec["real"]["bytes"] == (1000.0 * 2 + 3000.0) * 1024
+    assert rec["complex"]["bytes"] == (2000.0 * 2 + 4000.0) * 1024
+    assert len(rec["kernel_sources_sha256"]) == 64
+    assert real in md and cplx in md
